@@ -1,0 +1,37 @@
+"""Plain FP64 CPU oracle of the space-time FE slab problem and its GMRES-GMG solver.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the C-ABI library and
+its Python binding) imports, links or executes anything in this package; only
+the test-suite, the smoke check and the CPU-baseline leg of the benchmark do.
+
+The oracle follows the paper (Anselmann, Bause, Margenberg, Shamko: "An
+energy-efficient GMRES-Multigrid solver for space-time finite element
+computation of dynamic poro- and thermoelasticity", arXiv:2303.06742):
+
+* ``timedg``   -- right Gauss-Radau rule and dG(k) Lagrange time basis (Sec. 2, Eq:GF, Eq:TimeExp).
+* ``fem``      -- tensor Lagrange elements Q_r^d / Q_{r-1}, the forms Def:ACB, Def:ab.
+* ``problem``  -- Problem 3.1 assembled into the algebraic slab system of Problem 4.1.
+* ``gmg``      -- grid transfers, vertex/cell patches, Def. 4.2 and Alg. 4.1, V-cycle.
+* ``fgmres``   -- flexible (right-preconditioned) restarted GMRES.
+* ``norms``    -- the discrete error norms of Sec. 5.1.
+
+Everything is written for clarity, not speed, in float64 throughout.
+
+What pins it (tests/test_oracle_*.py, all CPU):
+  time rule and matrices  -- Gauss-Radau exactness, known nodes, the (k,k+1)
+                             Pade identity of dG(k)+right Radau, backward Euler;
+  element integrals       -- closed forms (mass, rigid motions, uniaxial strain
+                             energy, divergence, face terms);
+  assembled problem       -- exact reproduction of a solution in the discrete
+                             space (row-wise residual ~1e-16), optimal EOC,
+                             nodal superconvergence 2k+1, energy decay of
+                             Lemma 3.2, symmetry and coercivity (Appendix A);
+  multigrid / Krylov      -- polynomial reproduction of the transfers, the
+                             exact-local-solve invariant of Def:VankaOP, the
+                             averaging identity of Alg. 4.1, one-level V-cycle =
+                             direct solve, agreement with the sparse direct
+                             solve, brute-force minimal residual of FGMRES.
+Parity unpinned: the magnitudes of Table C.1 are not reproduced digit for digit
+(rates agree, values differ by 1.4-7x; recorded, not asserted), and GMRES
+iteration counts and V-cycle output values have no printed reference.
+

@@ -1,0 +1,175 @@
+"""Tensor-product Lagrange elements and the cell/face integrals of the forms.
+
+Paper, Sec. 2 (Def:VhQh, Eq:DefVhQh): V_h = continuous Q_r^d for u and v,
+Q_h = continuous Q_{r-1} for p (Taylor-Hood), on a mesh of axis-parallel
+squares/cubes.  Sec. 3 (Def:ACB, Def:ab) gives the forms
+
+    A_gamma(w, chi) = <C eps(w), eps(chi)> - <C eps(w) n, chi>_G + a_gamma(w, chi)
+    a_gamma(w, chi) = -<w, C eps(chi) n>_G + gamma_a/h_F <w, chi>_G
+    C(chi, q)       = -alpha <div chi, q> + alpha <chi . n, q>_G
+    B_gamma(q, psi) = <K grad q, grad psi> - <K grad q . n, psi>_G + b_gamma(q, psi)
+    b_gamma(q, psi) = -<q, K grad psi . n>_G + gamma_b/h_F <q, psi>_G
+
+with C eps(w) = 2 mu eps(w) + lambda div(w) I (isotropic), G = the Dirichlet
+boundary (all of the boundary here), gamma_a = 5e4 r (r+1), gamma_b = r(r-1)/2
+and, on a boundary face, h_F = |K|_d, the d-dimensional measure of the cell.
+
+Everything here works on one reference cell [0, h]^d: basis functions are
+evaluated at Gauss points and the integrals are sums over those points.  The
+local node order is lexicographic on the (p+1)^d lattice, x fastest; a vector
+basis function (node a, component c) has local index d*a + c.
+"""
+import itertools
+
+import numpy as np
+from numpy.polynomial import legendre as L
+from numpy.polynomial import polynomial as Pw
+
+
+def gauss01(n):
+    """n-point Gauss-Legendre rule on [0, 1]."""
+    x, w = L.leggauss(n)
+    return 0.5 * (x + 1.0), 0.5 * w
+
+
+def lagrange_1d(p):
+    """Coefficients of the degree-p Lagrange polynomials on equispaced nodes of [0, 1]."""
+    nodes = np.linspace(0.0, 1.0, p + 1)
+    out = []
+    for a in range(p + 1):
+        c = Pw.polyfromroots(np.delete(nodes, a)) if p > 0 else np.array([1.0])
+        out.append(c / Pw.polyval(nodes[a], c))
+    return out
+
+
+def basis_1d(p, xi):
+    """(values, derivatives) of the degree-p 1D basis at reference points xi; shape (len(xi), p+1)."""
+    polys = lagrange_1d(p)
+    xi = np.asarray(xi, dtype=float)
+    v = np.stack([Pw.polyval(xi, c) for c in polys], axis=-1)
+    dv = np.stack([Pw.polyval(xi, Pw.polyder(c)) if p > 0 else 0.0 * xi for c in polys], axis=-1)
+    return v, dv
+
+
+def local_lattice(p, d):
+    """Local node multi-indices (ix, iy[, iz]) in lexicographic order, x fastest."""
+    return [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=d)]
+
+
+def scalar_basis(p, d, pts, h):
+    """Values (nq, nloc) and physical gradients (nq, nloc, d) of Q_p on [0,h]^d at reference points pts (nq, d)."""
+    pts = np.atleast_2d(pts)
+    nq = pts.shape[0]
+    lat = local_lattice(p, d)
+    v1 = []
+    dv1 = []
+    for ax in range(d):
+        v, dv = basis_1d(p, pts[:, ax])
+        v1.append(v)
+        dv1.append(dv)
+    val = np.ones((nq, len(lat)))
+    grad = np.ones((nq, len(lat), d))
+    for a, idx in enumerate(lat):
+        for ax in range(d):
+            val[:, a] *= v1[ax][:, idx[ax]]
+            for g in range(d):
+                grad[:, a, g] *= (dv1[ax][:, idx[ax]] / h) if g == ax else v1[ax][:, idx[ax]]
+    return val, grad
+
+
+def cell_rule(n, d, h):
+    """Tensor Gauss rule with n points per axis on [0,h]^d: reference points (nq,d), weights (nq,)."""
+    x, w = gauss01(n)
+    pts = np.array([tuple(reversed(t)) for t in itertools.product(x, repeat=d)])
+    wts = np.array([np.prod(t) for t in itertools.product(w, repeat=d)]) * h ** d
+    return pts, wts
+
+
+def face_rule(n, d, h, axis, side):
+    """Gauss rule on the face {xi_axis = side} of [0,h]^d; returns points, weights, outward normal."""
+    x, w = gauss01(n)
+    pts = []
+    wts = []
+    for t, wt in zip(itertools.product(x, repeat=d - 1), itertools.product(w, repeat=d - 1)):
+        t = list(reversed(t))
+        t.insert(axis, float(side))
+        pts.append(t)
+        wts.append(np.prod(wt))
+    normal = np.zeros(d)
+    normal[axis] = 1.0 if side == 1 else -1.0
+    return np.array(pts), np.array(wts) * h ** (d - 1), normal
+
+
+def vector_fields(val, grad, d):
+    """For vector basis functions (node a, comp c) -> index d*a + c, return
+    values (nq, nv, d) and gradient tensors G[q, i, comp, j] = d_j w_comp."""
+    nq, ns = val.shape
+    nv = d * ns
+    W = np.zeros((nq, nv, d))
+    G = np.zeros((nq, nv, d, d))
+    for a in range(ns):
+        for c in range(d):
+            W[:, d * a + c, c] = val[:, a]
+            G[:, d * a + c, c, :] = grad[:, a, :]
+    return W, G
+
+
+def stress(G, lam, mu):
+    """sigma = 2 mu eps + lambda tr(eps) I for gradient tensors G[..., i, j]."""
+    eps = 0.5 * (G + np.swapaxes(G, -1, -2))
+    tr = np.trace(eps, axis1=-2, axis2=-1)
+    d = G.shape[-1]
+    return 2.0 * mu * eps + lam * tr[..., None, None] * np.eye(d)
+
+
+class CellMatrices:
+    """All cell and boundary-face matrices on the cell [0,h]^d for Q_r^d / Q_{r-1}.
+
+    Matrices are indexed [test, trial].  K-dependent parts are returned for K=1
+    and scaled by the caller with the cell's permeability.
+    """
+
+    def __init__(self, d, r, h, lam, mu, rho, alpha, gamma_a=None, gamma_b=None, nq=None):
+        self.d, self.r, self.h = d, r, h
+        self.gamma_a = 5e4 * r * (r + 1) if gamma_a is None else gamma_a
+        self.gamma_b = 0.5 * r * (r - 1) if gamma_b is None else gamma_b
+        self.hF = h ** d  # boundary face: the measure of its cell
+        nq = r + 1 if nq is None else nq
+        pts, wts = cell_rule(nq, d, h)
+        sv, sg = scalar_basis(r, d, pts, h)
+        pv, pg = scalar_basis(r - 1, d, pts, h)
+        W, G = vector_fields(sv, sg, d)
+        S = stress(G, lam, mu)
+        eps = 0.5 * (G + np.swapaxes(G, -1, -2))
+        div = np.trace(G, axis1=-2, axis2=-1)
+        # mass of the vector space times rho: rho <w, chi>
+        self.Mrho = rho * np.einsum('q,qic,qjc->ij', wts, W, W)
+        # elasticity volume term <C eps(w), eps(chi)>
+        self.Avol = np.einsum('q,qjab,qiab->ij', wts, S, eps)
+        # C(chi, q) volume part; rows = pressure test, cols = vector trial
+        self.Cvol = -alpha * np.einsum('q,qr,qj->rj', wts, pv, div)
+        # <grad q, grad psi> (times K) and <q, psi>
+        self.Bvol = np.einsum('q,qra,qsa->rs', wts, pg, pg)
+        self.Mp = np.einsum('q,qr,qs->rs', wts, pv, pv)
+        # boundary faces: key (axis, side)
+        self.Aface, self.Cface, self.Bface_K, self.Bface_pen = {}, {}, {}, {}
+        for axis in range(d):
+            for side in (0, 1):
+                fp, fw, n = face_rule(nq, d, h, axis, side)
+                sv_, sg_ = scalar_basis(r, d, fp, h)
+                pv_, pg_ = scalar_basis(r - 1, d, fp, h)
+                W_, G_ = vector_fields(sv_, sg_, d)
+                S_ = stress(G_, lam, mu)
+                Sn = np.einsum('qiab,b->qia', S_, n)  # traction sigma(w) n
+                # -<C eps(w) n, chi> - <w, C eps(chi) n> + gamma_a/h_F <w, chi>
+                Af = -np.einsum('q,qja,qia->ij', fw, Sn, W_)
+                Af += -np.einsum('q,qja,qia->ij', fw, W_, Sn)
+                Af += (self.gamma_a / self.hF) * np.einsum('q,qja,qia->ij', fw, W_, W_)
+                self.Aface[(axis, side)] = Af
+                # alpha <chi . n, q>
+                self.Cface[(axis, side)] = alpha * np.einsum('q,qr,qja,a->rj', fw, pv_, W_, n)
+                # -<grad q . n, psi> - <q, grad psi . n>   (times K)
+                gn = np.einsum('qsa,a->qs', pg_, n)
+                self.Bface_K[(axis, side)] = -np.einsum('q,qs,qr->rs', fw, gn, pv_) - np.einsum('q,qs,qr->rs', fw, pv_, gn)
+                # gamma_b/h_F <q, psi>
+                self.Bface_pen[(axis, side)] = (self.gamma_b / self.hF) * np.einsum('q,qs,qr->rs', fw, pv_, pv_)

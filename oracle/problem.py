@@ -1,0 +1,349 @@
+"""Problem 3.1 (numerically integrated I_n-problem, v-form) as the algebraic slab
+system A_n X_n = F_n of Problem 4.1, on the unit square/cube.
+
+Unknown vector (Eq:DefXn): X_n = (V_1, U_1, P_1, ..., V_{k+1}, U_{k+1}, P_{k+1}),
+time node outermost.  Inside one time node: V and U are node-major over the
+lexicographic Q_r lattice (x fastest), components interleaved (d*node + c); P
+is over the lexicographic Q_{r-1} lattice.
+
+Block structure (Problem 3.1 tested with chi_b, rows = (u-eq, v-eq, p-eq),
+columns = (V, U, P); the u-equation multiplied by rho as noted after
+Eq:DefAab):
+
+    A_n = D^t (x) MM + M^t (x) KK,
+
+    MM = [[0, M_rho, 0], [M_rho, 0, 0], [0, 0, c0 M_p]]
+    KK = [[-M_rho, 0, 0], [0, A_gamma, C^T], [-C, 0, B_gamma]]
+
+where (C^T)[i, s] = C(psi_i, xi_s) couples the v-equation to P and the
+p-equation carries -C(v, psi) on V (Problem 3.1, third equation).  The
+right-hand side is
+
+    F_n[b] = (tau/2) w_b S(t_{n,b}) + e_b MM X_{n-1,end}
+
+with S(t) = (0; <f(t), chi> + a_gamma(u_D(t), chi);
+             <g(t), psi> - alpha <v_D(t) . n, psi>_G + b_gamma(p_D(t), psi))
+(Def:LG), f and g computed from the prescribed solution.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+import sympy
+
+from . import fem, timedg
+
+
+class Params:
+    """Material and discretisation parameters (Sec. 1, Eq:HPS; Sec. 3)."""
+
+    def __init__(self, rho=1.0, lam=1.0, mu=1.0, alpha=0.9, c0=0.01, K=1.0, gamma_a=None, gamma_b=None):
+        self.rho, self.lam, self.mu, self.alpha, self.c0 = rho, lam, mu, alpha, c0
+        self.K = K  # scalar, or array of per-cell values (lexicographic, x fastest)
+        self.gamma_a, self.gamma_b = gamma_a, gamma_b
+
+
+def lame_from_young(E, nu):
+    """Lame parameters of an isotropic material from Young's modulus and Poisson's ratio."""
+    return E * nu / ((1 + nu) * (1 - 2 * nu)), E / (2 * (1 + nu))
+
+
+class Mesh:
+    """N^d axis-parallel cells of size h = 1/N on the unit square/cube."""
+
+    def __init__(self, d, N):
+        self.d, self.N, self.h = d, N, 1.0 / N
+        self.ncells = N ** d
+
+    def cell_index(self, c):
+        """Multi-index (cx, cy[, cz]) of cell number c."""
+        out = []
+        for _ in range(self.d):
+            out.append(c % self.N)
+            c //= self.N
+        return tuple(out)
+
+    def lattice_size(self, p):
+        return (p * self.N + 1) ** self.d
+
+    def cell_dofs(self, p):
+        """(ncells, (p+1)^d) global lexicographic Q_p node numbers of each cell's local nodes."""
+        n1 = p * self.N + 1
+        lat = np.array(fem.local_lattice(p, self.d), dtype=np.int64)  # (nloc, d)
+        ci = np.array([self.cell_index(c) for c in range(self.ncells)], dtype=np.int64)  # (nc, d)
+        gi = p * ci[:, None, :] + lat[None, :, :]  # (nc, nloc, d) global lattice multi-index
+        g = np.zeros(gi.shape[:2], dtype=np.int64)
+        for ax in reversed(range(self.d)):
+            g = g * n1 + gi[:, :, ax]
+        return g
+
+    def node_coords(self, p):
+        """Coordinates (n, d) of the Q_p lattice nodes in global lexicographic order."""
+        n1 = p * self.N + 1
+        xs = np.linspace(0.0, 1.0, n1)
+        grids = np.meshgrid(*([xs] * self.d), indexing='ij')
+        # lexicographic with x fastest: index = ix + n1*(iy + n1*iz)
+        return np.stack([g.transpose().reshape(-1) for g in grids], axis=-1)
+
+    def boundary_faces(self):
+        """List of (cell, axis, side) for every cell face on the boundary of the unit cube."""
+        out = []
+        for c in range(self.ncells):
+            ci = self.cell_index(c)
+            for ax in range(self.d):
+                if ci[ax] == 0:
+                    out.append((c, ax, 0))
+                if ci[ax] == self.N - 1:
+                    out.append((c, ax, 1))
+        return out
+
+    def cell_origin(self, c):
+        return np.array(self.cell_index(c), dtype=float) * self.h
+
+
+def vec_dofs(sdofs, d):
+    """Scalar node numbers -> interleaved vector dof numbers d*node + c (local order d*a + c)."""
+    return (d * sdofs[:, :, None] + np.arange(d)[None, None, :]).reshape(sdofs.shape[0], -1)
+
+
+def _scatter(rows_loc, cols_loc, mats, shape):
+    """Sum the dense local matrices mats[c] (indexed [test, trial]) into a sparse matrix."""
+    I = np.repeat(rows_loc[:, :, None], cols_loc.shape[1], axis=2)
+    J = np.repeat(cols_loc[:, None, :], rows_loc.shape[1], axis=1)
+    return sp.coo_matrix((np.asarray(mats).reshape(-1), (I.reshape(-1), J.reshape(-1))), shape=shape).tocsr()
+
+
+class SpaceBlocks:
+    """Spatial matrices M_rho, A_gamma, C, B_gamma, M_p of one mesh level, and MM, KK."""
+
+    def __init__(self, d, N, r, prm):
+        self.d, self.N, self.r, self.prm = d, N, r, prm
+        self.mesh = Mesh(d, N)
+        m = self.mesh
+        self.nQ = m.lattice_size(r)
+        self.nP = m.lattice_size(r - 1)
+        self.nv = d * self.nQ
+        self.ns = 2 * self.nv + self.nP
+        cm = fem.CellMatrices(d, r, m.h, prm.lam, prm.mu, prm.rho, prm.alpha, prm.gamma_a, prm.gamma_b)
+        self.cm = cm
+        Kc = np.broadcast_to(np.asarray(prm.K, dtype=float), (m.ncells,)).copy()
+        self.Kcell = Kc
+        qd = m.cell_dofs(r)
+        pd = m.cell_dofs(r - 1)
+        vd = vec_dofs(qd, d)
+        self.qdofs, self.pdofs, self.vdofs = qd, pd, vd
+        nc = m.ncells
+        rep = lambda M: np.broadcast_to(M, (nc,) + M.shape)
+        self.Mrho = _scatter(vd, vd, rep(cm.Mrho), (self.nv, self.nv))
+        A = _scatter(vd, vd, rep(cm.Avol), (self.nv, self.nv))
+        C = _scatter(pd, vd, rep(cm.Cvol), (self.nP, self.nv))
+        B = _scatter(pd, pd, Kc[:, None, None] * cm.Bvol[None], (self.nP, self.nP))
+        self.Mp = _scatter(pd, pd, rep(cm.Mp), (self.nP, self.nP))
+        faces = m.boundary_faces()
+        if faces:
+            fc = np.array([f[0] for f in faces])
+            Af = np.array([cm.Aface[(f[1], f[2])] for f in faces])
+            Cf = np.array([cm.Cface[(f[1], f[2])] for f in faces])
+            Bf = np.array([Kc[f[0]] * cm.Bface_K[(f[1], f[2])] + cm.Bface_pen[(f[1], f[2])] for f in faces])
+            A = A + _scatter(vd[fc], vd[fc], Af, (self.nv, self.nv))
+            C = C + _scatter(pd[fc], vd[fc], Cf, (self.nP, self.nv))
+            B = B + _scatter(pd[fc], pd[fc], Bf, (self.nP, self.nP))
+        self.A, self.C, self.B = A.tocsr(), C.tocsr(), B.tocsr()
+        Z = None
+        c0 = prm.c0
+        self.MM = sp.bmat([[Z, self.Mrho, Z], [self.Mrho, Z, Z], [Z, Z, c0 * self.Mp]], format='csr')
+        self.KK = sp.bmat([[-self.Mrho, Z, Z], [Z, self.A, self.C.T], [-self.C, Z, self.B]], format='csr')
+
+
+def slab_operator(blocks, k, tau):
+    """A_n = D^t (x) MM + M^t (x) KK (Problem 4.1, Eq:DefAn/Eq:DefAab, v-form)."""
+    Dt, Mt, _, _, _ = timedg.time_matrices(k, tau)
+    return (sp.kron(sp.csr_matrix(Dt), blocks.MM) + sp.kron(sp.csr_matrix(Mt), blocks.KK)).tocsr()
+
+
+class ExactSolution:
+    """A prescribed solution (u, p) given as sympy expressions in x, y[, z], t.
+
+    f = rho u_tt - div(C eps(u)) + alpha grad p and g = c0 p_t + alpha div(u_t)
+    - K lap(p) are derived symbolically (K is a scalar that the caller supplies
+    per cell), so that the discrete problem is consistent with (u, p).
+    """
+
+    def __init__(self, d, u_exprs, p_expr, prm):
+        self.d = d
+        X = sympy.symbols('x y z')[:d]
+        t = sympy.Symbol('t')
+        Ksym = sympy.Symbol('K')
+        u = [sympy.sympify(e) for e in u_exprs]
+        p = sympy.sympify(p_expr)
+        v = [sympy.diff(ui, t) for ui in u]
+        grad_u = [[sympy.diff(u[i], X[j]) for j in range(d)] for i in range(d)]
+        eps = [[(grad_u[i][j] + grad_u[j][i]) / 2 for j in range(d)] for i in range(d)]
+        divu = sum(grad_u[i][i] for i in range(d))
+        sig = [[2 * prm.mu * eps[i][j] + (prm.lam * divu if i == j else 0) for j in range(d)] for i in range(d)]
+        f = [prm.rho * sympy.diff(u[i], t, 2) - sum(sympy.diff(sig[i][j], X[j]) for j in range(d))
+             + prm.alpha * sympy.diff(p, X[i]) for i in range(d)]
+        g = prm.c0 * sympy.diff(p, t) + prm.alpha * sum(sympy.diff(v[i], X[i]) for i in range(d)) \
+            - Ksym * sum(sympy.diff(p, X[i], 2) for i in range(d))
+        args = list(X) + [t]
+        lam = lambda e: sympy.lambdify(args, e, 'numpy')
+        self._u = [lam(e) for e in u]
+        self._v = [lam(e) for e in v]
+        self._p = lam(p)
+        self._gu = [[lam(grad_u[i][j]) for j in range(d)] for i in range(d)]
+        self._gv = [[lam(sympy.diff(v[i], X[j])) for j in range(d)] for i in range(d)]
+        self._gp = [lam(sympy.diff(p, X[j])) for j in range(d)]
+        self._f = [lam(e) for e in f]
+        self._g = sympy.lambdify(args + [Ksym], g, 'numpy')
+
+    @staticmethod
+    def _ev(fn, xs, t):
+        out = fn(*[xs[:, j] for j in range(xs.shape[1])], t)
+        return np.broadcast_to(np.asarray(out, dtype=float), (xs.shape[0],)).copy()
+
+    def u(self, xs, t):
+        return np.stack([self._ev(f, xs, t) for f in self._u], axis=-1)
+
+    def v(self, xs, t):
+        return np.stack([self._ev(f, xs, t) for f in self._v], axis=-1)
+
+    def p(self, xs, t):
+        return self._ev(self._p, xs, t)
+
+    def grad_u(self, xs, t):
+        return np.stack([np.stack([self._ev(f, xs, t) for f in row], axis=-1) for row in self._gu], axis=-2)
+
+    def grad_v(self, xs, t):
+        return np.stack([np.stack([self._ev(f, xs, t) for f in row], axis=-1) for row in self._gv], axis=-2)
+
+    def grad_p(self, xs, t):
+        return np.stack([self._ev(f, xs, t) for f in self._gp], axis=-1)
+
+    def f(self, xs, t):
+        return np.stack([self._ev(fn, xs, t) for fn in self._f], axis=-1)
+
+    def g(self, xs, t, K):
+        out = self._g(*[xs[:, j] for j in range(xs.shape[1])], t, K)
+        return np.broadcast_to(np.asarray(out, dtype=float), (xs.shape[0],)).copy()
+
+
+def interpolate(blocks, sol, t):
+    """Nodal interpolant (V, U, P) of the prescribed solution at time t (one time-node block)."""
+    m = blocks.mesh
+    xq = m.node_coords(blocks.r)
+    xp = m.node_coords(blocks.r - 1)
+    return np.concatenate([sol.v(xq, t).reshape(-1), sol.u(xq, t).reshape(-1), sol.p(xp, t)])
+
+
+def source_vector(blocks, sol, t, nq=None):
+    """S(t) of Def:LG for one time node: (0; <f,chi> + a_gamma(u_D,chi); <g,psi> - alpha<v_D.n,psi>_G + b_gamma(p_D,psi)).
+
+    Volume integrals use (r+2)^d Gauss points, face integrals (r+2)^(d-1).
+    """
+    d, r, m, prm, cm = blocks.d, blocks.r, blocks.mesh, blocks.prm, blocks.cm
+    h = m.h
+    nq = r + 2 if nq is None else nq
+    pts, wts = fem.cell_rule(nq, d, h)
+    sv, _ = fem.scalar_basis(r, d, pts, h)
+    pv, _ = fem.scalar_basis(r - 1, d, pts, h)
+    origins = np.array([m.cell_origin(c) for c in range(m.ncells)])
+    xs = (origins[:, None, :] + h * pts[None, :, :]).reshape(-1, d)
+    fv = sol.f(xs, t).reshape(m.ncells, len(wts), d)
+    Kq = np.repeat(blocks.Kcell, len(wts))
+    gv = sol.g(xs, t, Kq).reshape(m.ncells, len(wts))
+    Fv = np.zeros(blocks.nv)
+    Fp = np.zeros(blocks.nP)
+    np.add.at(Fv, blocks.vdofs, np.einsum('q,qa,cqe->cae', wts, sv, fv).reshape(m.ncells, -1))
+    np.add.at(Fp, blocks.pdofs, np.einsum('q,qr,cq->cr', wts, pv, gv))
+    faces = m.boundary_faces()
+    for axis in range(d):
+        for side in (0, 1):
+            cells = np.array([f[0] for f in faces if f[1] == axis and f[2] == side], dtype=np.int64)
+            if len(cells) == 0:
+                continue
+            fp, fw, n = fem.face_rule(nq, d, h, axis, side)
+            xs = (origins[cells][:, None, :] + h * fp[None, :, :]).reshape(-1, d)
+            nf = len(fw)
+            sv_, sg_ = fem.scalar_basis(r, d, fp, h)
+            pv_, pg_ = fem.scalar_basis(r - 1, d, fp, h)
+            W_, G_ = fem.vector_fields(sv_, sg_, d)
+            Sn = np.einsum('qiab,b->qia', fem.stress(G_, prm.lam, prm.mu), n)
+            uD = sol.u(xs, t).reshape(len(cells), nf, d)
+            vD = sol.v(xs, t).reshape(len(cells), nf, d)
+            pD = sol.p(xs, t).reshape(len(cells), nf)
+            K = blocks.Kcell[cells]
+            # a_gamma(u_D, chi) = -<u_D, C eps(chi) n> + gamma_a/h_F <u_D, chi>
+            av = -np.einsum('q,cqa,qia->ci', fw, uD, Sn) + (cm.gamma_a / cm.hF) * np.einsum('q,cqa,qia->ci', fw, uD, W_)
+            np.add.at(Fv, blocks.vdofs[cells], av)
+            # -alpha <v_D . n, psi> + b_gamma(p_D, psi), b_gamma(q,psi) = -<q, K grad psi . n> + gamma_b/h_F <q, psi>
+            gn = np.einsum('qra,a->qr', pg_, n)
+            bp = -prm.alpha * np.einsum('q,cq,qr->cr', fw, vD @ n, pv_)
+            bp += -K[:, None] * np.einsum('q,cq,qr->cr', fw, pD, gn)
+            bp += (cm.gamma_b / cm.hF) * np.einsum('q,cq,qr->cr', fw, pD, pv_)
+            np.add.at(Fp, blocks.pdofs[cells], bp)
+    return np.concatenate([np.zeros(blocks.nv), Fv, Fp])
+
+
+def slab_rhs(blocks, k, tau, t_start, X_prev_end, sol=None):
+    """F_n of Problem 4.1: (tau/2) w_b S(t_{n,b}) + e_b MM X_{n-1,end}, for b = 1..k+1."""
+    _, _, e, _, w = timedg.time_matrices(k, tau)
+    tn = timedg.slab_nodes(t_start, tau, k)
+    jump = blocks.MM @ X_prev_end
+    parts = []
+    for b in range(k + 1):
+        Fb = e[b] * jump
+        if sol is not None:
+            Fb = Fb + 0.5 * tau * w[b] * source_vector(blocks, sol, tn[b])
+        parts.append(Fb)
+    return np.concatenate(parts)
+
+
+class SlabProblem:
+    """One mesh level with its slab operator; convenience for time marching."""
+
+    def __init__(self, d, N, r, k, tau, prm):
+        self.d, self.N, self.r, self.k, self.tau, self.prm = d, N, r, k, tau, prm
+        self.blocks = SpaceBlocks(d, N, r, prm)
+        self.A = slab_operator(self.blocks, k, tau)
+        self.n = self.A.shape[0]
+        self.ns = self.blocks.ns
+
+    def end_block(self, X):
+        """The block of X at the last Gauss-Radau node, t_n."""
+        return X[self.k * self.ns:(self.k + 1) * self.ns]
+
+    def factor(self):
+        """Sparse LU of the row-equilibrated operator diag(1/max|row|) A_n.
+
+        The Nitsche penalty makes boundary rows ~1e7-1e10 times larger than the
+        mass rows; scaling the rows leaves the solution unchanged and brings
+        the condition number down to O(1e3) on small grids.  Returns a solve
+        function F -> A_n^{-1} F.
+        """
+        Dr = 1.0 / abs(self.A).max(axis=1).toarray().ravel()
+        As = (sp.diags(Dr) @ self.A).tocsc()
+        lu = spla.splu(As, permc_spec='MMD_AT_PLUS_A', diag_pivot_thresh=0.01)
+
+        def solve(F):
+            # the relaxed pivot threshold keeps the fill small; two steps of
+            # iterative refinement recover full accuracy
+            x = lu.solve(Dr * F)
+            for _ in range(2):
+                x = x + lu.solve(Dr * (F - self.A @ x))
+            return x
+        return solve
+
+    def direct_solve(self, F):
+        return self.factor()(F)
+
+    def march(self, sol, t0, nslabs, solver=None):
+        """Time marching with the slab problem; returns the list of slab vectors X_n."""
+        Xend = interpolate(self.blocks, sol, t0)
+        out = []
+        solve = self.factor() if solver is None else solver
+        for n in range(nslabs):
+            ts = t0 + n * self.tau
+            F = slab_rhs(self.blocks, self.k, self.tau, ts, Xend, sol)
+            X = solve(F)
+            out.append(X)
+            Xend = self.end_block(X)
+        return out
