@@ -1,0 +1,158 @@
+/*
+ * stgmg -- space-time geometric-multigrid preconditioned flexible GMRES for the
+ * dG(k) x Q_r^d / Q_{r-1} slab systems of dynamic poro-/thermoelasticity, on one
+ * AMD MI355X (gfx950).
+ *
+ * Method: Anselmann, Bause, Margenberg, Shamko, "An energy-efficient
+ * GMRES-Multigrid solver for space-time finite element computation of dynamic
+ * poro- and thermoelasticity" (arXiv:2303.06742).
+ *   - slab problem: Problem 3.1 (v-form, Eq:DPQ_A0), algebraic form Problem 4.1
+ *     (Eq:ALS_In, Eq:DefAn, Eq:DefAab);
+ *   - solver: flexible GMRES preconditioned by one geometric-multigrid V-cycle
+ *     (Sec. 4), smoother = patchwise Vanka operator (Def:VankaOP, Eq:VankaOP0)
+ *     applied by Algorithm 4.1, direct solve on the coarsest level.
+ *
+ * Vector layout (all vectors are FP64, on the device unless stated otherwise):
+ *   X = (V_1, U_1, P_1, ..., V_{k+1}, U_{k+1}, P_{k+1})      (Eq:DefXn)
+ *   time node outermost; inside a node V and U are node-major over the
+ *   lexicographic Q_r lattice of (r N + 1)^d nodes (x fastest) with the d
+ *   components interleaved (index d*node + c), and P is over the lexicographic
+ *   Q_{r-1} lattice of ((r-1) N + 1)^d nodes.  A residual / right-hand side has
+ *   the same layout with the rows (u-equation, v-equation, p-equation).
+ *   n_s = 2 d (rN+1)^d + ((r-1)N+1)^d values per time node, n = (k+1) n_s.
+ *
+ * Ownership: the library owns handles and all hierarchy memory (operators,
+ * patch inverses, Krylov bases) and frees them in stgmg_destroy.  The caller
+ * owns every vector argument; the library never keeps a pointer past the call.
+ * Device vectors must be 8-byte aligned, hold n doubles and must not alias
+ * each other unless stated.
+ *
+ * Errors: every function returns a status; no C++ exception crosses this
+ * interface.  stgmg_last_error() gives a thread-local text for the last
+ * failure.  A handle may be used by one host thread / stream at a time.
+ */
+#ifndef STGMG_H
+#define STGMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t stgmg_status;
+#define STGMG_OK 0
+#define STGMG_NOT_CONVERGED 1        /* x holds the last iterate */
+#define STGMG_ERR_INVALID_ARG (-1)
+#define STGMG_ERR_UNSUPPORTED (-2)
+#define STGMG_ERR_OOM (-3)
+#define STGMG_ERR_HIP (-4)
+#define STGMG_ERR_SINGULAR_PATCH (-5) /* a patch matrix A_P had a zero pivot */
+#define STGMG_ERR_NONFINITE (-6)      /* NaN/Inf in rhs, x0 or a residual */
+
+#define STGMG_PATCH_CELL 0   /* one patch per cell */
+#define STGMG_PATCH_VERTEX 1 /* one patch per grid vertex: the cells that touch it (Eq:DefPlm) */
+
+#define STGMG_FP64 0 /* patch inverses stored and applied in FP64 */
+#define STGMG_FP32 1 /* patch inverses computed in FP64, stored and applied in FP32 */
+
+typedef struct stgmg_handle stgmg_handle;
+
+/* Problem and solver parameters.  Fine level: coarse_cells << (levels-1) cells
+ * per axis on the unit square/cube; level 0 is solved directly. */
+typedef struct {
+  int32_t dim;           /* 2 or 3 */
+  int32_t coarse_cells;  /* cells per axis on level 0 (>= 1) */
+  int32_t levels;        /* number of levels L+1 >= 1 */
+  int32_t r;             /* displacement degree (Q_r^d); pressure Q_{r-1}; 2 <= r <= 4 */
+  int32_t k;             /* dG(k) in time, 0 <= k <= 3 */
+  int32_t patch;         /* STGMG_PATCH_CELL or STGMG_PATCH_VERTEX */
+  int32_t smoother_prec; /* STGMG_FP64 or STGMG_FP32 */
+  int32_t n_smooth;      /* J_max pre- and post-smoothing sweeps (paper: 4) */
+  double omega;          /* Vanka under-relaxation (paper: 0.7) */
+  double tau;            /* slab length */
+  double rho, lambda, mu, alpha, c0; /* material parameters of Eq:HPS (isotropic C) */
+  double K;              /* permeability K*I when K_cells == NULL */
+  const double* K_cells; /* host, optional: K per fine cell, lexicographic (x fastest);
+                            coarse cells take the mean of their 2^d children. Copied. */
+} stgmg_params;
+
+typedef struct {
+  int32_t iters;         /* FGMRES iterations = V-cycles applied */
+  int32_t restarts;
+  int32_t converged;     /* 1 if ||b - A x|| <= rtol ||b - A x0|| */
+  double res0;           /* ||b - A x0||_2 */
+  double rel_res_true;   /* ||b - A x||_2 / res0, recomputed at exit */
+  double rel_res_est;    /* last Givens estimate */
+  double t_solve_ms;     /* wall time of the solve (device synchronised) */
+} stgmg_info;
+
+/* Build the level hierarchy for Problem 4.1 with the given parameters: level
+ * operators (Eq:DefAab, re-assembled on every level), grid transfers, patch
+ * tables, the patch inverses A_P^{-1} of Def:VankaOP (extracted from the
+ * assembled level matrix and inverted on the GPU) and the coarse inverse.
+ * hip_stream: a hipStream_t (NULL = default stream) on which all later work of
+ * this handle is enqueued.  Returns STGMG_ERR_SINGULAR_PATCH if any A_P is
+ * singular, STGMG_ERR_OOM if device memory runs out. */
+stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_handle** out);
+
+/* Sizes of one level (level = 0..levels-1; -1 = finest): number of unknowns n,
+ * number of patches, stored nonzeros of the level operator, and the device
+ * bytes held by the whole handle. Any output pointer may be NULL. */
+stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, int64_t* n_patches,
+                         int64_t* nnz, int64_t* hbm_bytes);
+
+/* Solve A_n x = rhs (Problem 4.1, Eq:ALS_In) on the finest level with FGMRES
+ * (right preconditioning, restart length `restart`, at most `max_iters`
+ * iterations), one V-cycle per iteration (Sec. 4).  x: in = x0, out = solution.
+ * Stops when ||rhs - A x||_2 <= rtol * ||rhs - A x0||_2, checked on the true
+ * residual.  info may be NULL.  Returns STGMG_NOT_CONVERGED (x = last iterate)
+ * or STGMG_ERR_NONFINITE (x unchanged) when applicable. */
+stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, double rtol,
+                         int32_t restart, int32_t max_iters, stgmg_info* info);
+
+/* y = A_level x (the assembled level operator of Eq:DefAn). level -1 = finest. */
+stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* x_dev, double* y_dev);
+
+/* z = B r: one V-cycle with zero initial guess on the finest level (Sec. 4). */
+stgmg_status stgmg_apply_vcycle(stgmg_handle* h, const double* r_dev, double* z_dev);
+
+/* d <- `sweeps` steps of Algorithm 4.1 on level `level` (>= 1) for A_l d = b,
+ * starting from the given d (Def:VankaOP with the handle's omega). */
+stgmg_status stgmg_smooth(stgmg_handle* h, int32_t level, const double* b_dev, double* d_dev, int32_t sweeps);
+
+/* Grid transfers between level l-1 and l (l >= 1): prolongation by
+ * interpolation, d_fine += P e_coarse, and restriction by the transpose,
+ * b_coarse = P^T r_fine (Sec. 4, list of GMRES-GMG ingredients). */
+stgmg_status stgmg_prolongate_add(stgmg_handle* h, int32_t level, const double* e_coarse_dev, double* d_fine_dev);
+stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine_dev, double* b_coarse_dev);
+
+/* Right-hand side of Problem 3.1 for the slab (t_start, t_start + tau] on the
+ * finest level, for the built-in prescribed solution
+ *   u_i = S(x) sin(t) (every component), p = S(x) cos(t), S = prod_j sin(pi x_j),
+ * whose Dirichlet data vanish on the boundary of the unit square/cube:
+ *   F[b] = tau/2 w_b S(t_{n,b}) + e_b MM x_prev_end          (Def:LG, Problem 3.1)
+ * x_prev_end_dev: the previous slab's values at t_{n-1} (n_s doubles, one time
+ * node block).  rhs_dev: n doubles. */
+stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_prev_end_dev, double* rhs_dev);
+
+/* Nodal interpolant (V, U, P) of the built-in prescribed solution at time t,
+ * n_s doubles (one time-node block), on the finest level. */
+stgmg_status stgmg_interpolate_solution(stgmg_handle* h, double t, double* x_block_dev);
+
+/* Copy the stored inverse of patch `patch` of level `level` (>= 1) to host
+ * memory as a dense row-major FP64 matrix of n_P x n_P (the patch dofs in
+ * increasing global order), and its global dof numbers (n_P int64).
+ * Call with out == NULL to get n_P only.  For tests. */
+stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t patch, int32_t* n_p,
+                                     double* out_host, int64_t* dofs_host);
+
+stgmg_status stgmg_destroy(stgmg_handle* h);
+
+const char* stgmg_status_string(stgmg_status s);
+const char* stgmg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STGMG_H */

@@ -35,3 +35,4 @@ Parity unpinned: the magnitudes of Table C.1 are not reproduced digit for digit
 (rates agree, values differ by 1.4-7x; recorded, not asserted), and GMRES
 iteration counts and V-cycle output values have no printed reference.
 
+"""

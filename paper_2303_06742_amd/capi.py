@@ -1,0 +1,201 @@
+"""ctypes binding of the C ABI in include/stgmg.h (argument marshalling only).
+
+Every computation happens in libstgmg.so (HIP kernels for gfx950).  Device
+vectors are torch tensors on a ROCm device, float64 and contiguous; torch is
+used for device memory and the stream handle only.  If the library is missing
+this module raises at import: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, 'libstgmg.so')
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+STGMG_OK = 0
+STGMG_NOT_CONVERGED = 1
+STGMG_ERR_INVALID_ARG = -1
+STGMG_ERR_UNSUPPORTED = -2
+STGMG_ERR_OOM = -3
+STGMG_ERR_HIP = -4
+STGMG_ERR_SINGULAR_PATCH = -5
+STGMG_ERR_NONFINITE = -6
+PATCH = {'cell': 0, 'vertex': 1}
+PREC = {'fp64': 0, 'fp32': 1}
+
+
+class Params(ctypes.Structure):
+    _fields_ = [('dim', ctypes.c_int32), ('coarse_cells', ctypes.c_int32), ('levels', ctypes.c_int32),
+                ('r', ctypes.c_int32), ('k', ctypes.c_int32), ('patch', ctypes.c_int32),
+                ('smoother_prec', ctypes.c_int32), ('n_smooth', ctypes.c_int32), ('omega', ctypes.c_double),
+                ('tau', ctypes.c_double), ('rho', ctypes.c_double), ('lam', ctypes.c_double),
+                ('mu', ctypes.c_double), ('alpha', ctypes.c_double), ('c0', ctypes.c_double),
+                ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [('iters', ctypes.c_int32), ('restarts', ctypes.c_int32), ('converged', ctypes.c_int32),
+                ('res0', ctypes.c_double), ('rel_res_true', ctypes.c_double), ('rel_res_est', ctypes.c_double),
+                ('t_solve_ms', ctypes.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+_H = ctypes.c_void_p
+_P = ctypes.c_void_p
+_I32, _I64, _D = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_S = ctypes.c_int32
+
+
+def _decl(name, args, res=_S):
+    f = getattr(_lib, name)
+    f.argtypes = args
+    f.restype = res
+    return f
+
+
+stgmg_setup = _decl('stgmg_setup', [ctypes.POINTER(Params), _P, ctypes.POINTER(_H)])
+stgmg_query = _decl('stgmg_query', [_H, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                    ctypes.POINTER(_I64)])
+stgmg_solve = _decl('stgmg_solve', [_H, _P, _P, _D, _I32, _I32, ctypes.POINTER(Info)])
+stgmg_apply_operator = _decl('stgmg_apply_operator', [_H, _I32, _P, _P])
+stgmg_apply_vcycle = _decl('stgmg_apply_vcycle', [_H, _P, _P])
+stgmg_smooth = _decl('stgmg_smooth', [_H, _I32, _P, _P, _I32])
+stgmg_prolongate_add = _decl('stgmg_prolongate_add', [_H, _I32, _P, _P])
+stgmg_restrict = _decl('stgmg_restrict', [_H, _I32, _P, _P])
+stgmg_slab_rhs = _decl('stgmg_slab_rhs', [_H, _D, _P, _P])
+stgmg_interpolate_solution = _decl('stgmg_interpolate_solution', [_H, _D, _P])
+stgmg_get_patch_inverse = _decl('stgmg_get_patch_inverse', [_H, _I32, _I64, ctypes.POINTER(_I32), _P, _P])
+stgmg_destroy = _decl('stgmg_destroy', [_H])
+stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
+stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
+
+EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
+            'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs',
+            'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_destroy', 'stgmg_status_string',
+            'stgmg_last_error']
+
+
+class StgmgError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = stgmg_last_error().decode(errors='replace')
+        super().__init__(f"{where}: {stgmg_status_string(status).decode()} ({status}): {msg}")
+
+
+def check(status, where, allow=(STGMG_OK,)):
+    if status not in allow:
+        raise StgmgError(status, where)
+    return status
+
+
+def _dptr(t, n=None):
+    """Device pointer of a contiguous float64 tensor on a ROCm device, with a size check."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor on the GPU")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} values, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One problem hierarchy (stgmg_setup) and the calls on it."""
+
+    def __init__(self, cfg, precision=None, stream=None):
+        import torch
+        self._torch = torch
+        self.cfg = cfg
+        prec = precision or cfg.precision
+        self._K = cfg.K_cells()
+        if self._K is not None:
+            self._K = np.ascontiguousarray(self._K, dtype=np.float64)
+        p = Params(dim=cfg.dim, coarse_cells=cfg.coarse_cells, levels=cfg.levels, r=cfg.r, k=cfg.k,
+                   patch=PATCH[cfg.patch], smoother_prec=PREC[prec], n_smooth=cfg.n_smooth, omega=cfg.omega,
+                   tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0, K=cfg.K,
+                   K_cells=None if self._K is None else self._K.ctypes.data)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _H()
+        check(stgmg_setup(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), 'stgmg_setup')
+        self.h = h
+        self.levels = cfg.levels
+        self.n = self.query(-1)['n']
+        self.ns = self.n // (cfg.k + 1)
+
+    def query(self, level=-1):
+        n, npch, nnz, b = _I64(), _I64(), _I64(), _I64()
+        check(stgmg_query(self.h, level, ctypes.byref(n), ctypes.byref(npch), ctypes.byref(nnz), ctypes.byref(b)),
+              'stgmg_query')
+        return {'n': n.value, 'patches': npch.value, 'nnz': nnz.value, 'bytes': b.value}
+
+    def empty(self, n=None):
+        return self._torch.zeros(self.n if n is None else n, dtype=self._torch.float64, device='cuda')
+
+    def solve(self, rhs, x, rtol=1e-8, restart=30, max_iters=1000):
+        info = Info()
+        st = stgmg_solve(self.h, _dptr(rhs, self.n), _dptr(x, self.n), rtol, restart, max_iters, ctypes.byref(info))
+        check(st, 'stgmg_solve', allow=(STGMG_OK, STGMG_NOT_CONVERGED))
+        return info.as_dict()
+
+    def apply_operator(self, x, level=-1, y=None):
+        n = self.query(level)['n']
+        y = self.empty(n) if y is None else y
+        check(stgmg_apply_operator(self.h, level, _dptr(x, n), _dptr(y, n)), 'stgmg_apply_operator')
+        return y
+
+    def vcycle(self, r, z=None):
+        z = self.empty() if z is None else z
+        check(stgmg_apply_vcycle(self.h, _dptr(r, self.n), _dptr(z, self.n)), 'stgmg_apply_vcycle')
+        return z
+
+    def smooth(self, level, b, d, sweeps):
+        n = self.query(level)['n']
+        check(stgmg_smooth(self.h, level, _dptr(b, n), _dptr(d, n), sweeps), 'stgmg_smooth')
+        return d
+
+    def prolongate_add(self, level, e, d):
+        check(stgmg_prolongate_add(self.h, level, _dptr(e, self.query(level - 1)['n']),
+                                   _dptr(d, self.query(level)['n'])), 'stgmg_prolongate_add')
+        return d
+
+    def restrict(self, level, r):
+        b = self.empty(self.query(level - 1)['n'])
+        check(stgmg_restrict(self.h, level, _dptr(r, self.query(level)['n']), _dptr(b)), 'stgmg_restrict')
+        return b
+
+    def slab_rhs(self, t_start, x_prev_end, rhs=None):
+        rhs = self.empty() if rhs is None else rhs
+        check(stgmg_slab_rhs(self.h, t_start, _dptr(x_prev_end, self.ns), _dptr(rhs, self.n)), 'stgmg_slab_rhs')
+        return rhs
+
+    def interpolate_solution(self, t):
+        out = self.empty(self.ns)
+        check(stgmg_interpolate_solution(self.h, t, _dptr(out, self.ns)), 'stgmg_interpolate_solution')
+        return out
+
+    def patch_inverse(self, level, patch):
+        npp = _I32()
+        check(stgmg_get_patch_inverse(self.h, level, patch, ctypes.byref(npp), None, None), 'stgmg_get_patch_inverse')
+        out = np.zeros((npp.value, npp.value))
+        dofs = np.zeros(npp.value, dtype=np.int64)
+        check(stgmg_get_patch_inverse(self.h, level, patch, ctypes.byref(npp), out.ctypes.data_as(_P),
+                                      dofs.ctypes.data_as(_P)), 'stgmg_get_patch_inverse')
+        return out, dofs
+
+    def close(self):
+        if getattr(self, 'h', None):
+            stgmg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

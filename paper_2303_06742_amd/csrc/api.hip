@@ -1,0 +1,719 @@
+// C ABI of the space-time GMRES-GMG solver: hierarchy setup, V-cycle with the
+// patchwise Vanka smoother (Def:VankaOP, Algorithm 4.1), flexible GMRES
+// (Sec. 4) and test entry points.  Host code orchestrating the kernels of
+// kernels.hip on the handle's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "host_setup.h"
+#include "kernels.h"
+#include "stgmg.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct ApiError : std::runtime_error {
+  stgmg_status code;
+  ApiError(stgmg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                                  \
+  do {                                                                                                \
+    hipError_t e_ = (expr);                                                                           \
+    if (e_ != hipSuccess) {                                                                           \
+      throw ApiError(e_ == hipErrorOutOfMemory ? STGMG_ERR_OOM : STGMG_ERR_HIP,                       \
+                     std::string(#expr) + ": " + hipGetErrorString(e_));                              \
+    }                                                                                                 \
+  } while (0)
+
+// Owning device array.
+template <class T>
+struct DArr {
+  T* p = nullptr;
+  int64_t n = 0;
+  DArr() = default;
+  DArr(const DArr&) = delete;
+  DArr& operator=(const DArr&) = delete;
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DArr& operator=(DArr&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DArr() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(int64_t count, int64_t* counter) {
+    release();
+    if (count > 0) HIPCHK(hipMalloc(&p, size_t(count) * sizeof(T)));
+    n = count;
+    if (counter) *counter += count * int64_t(sizeof(T));
+  }
+  void upload(const std::vector<T>& h, hipStream_t st, int64_t* counter) {
+    alloc(int64_t(h.size()), counter);
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+};
+
+struct DevCsr {
+  int64_t nrows = 0, nnz = 0;
+  int lanes = 16;
+  DArr<int64_t> ptr;
+  DArr<int32_t> col;
+  DArr<double> val;
+  void upload(const stgmg::Csr& c, hipStream_t st, int64_t* counter) {
+    nrows = c.nrows;
+    nnz = int64_t(c.col.size());
+    ptr.upload(c.ptr, st, counter);
+    col.upload(c.col, st, counter);
+    val.upload(c.val, st, counter);
+    const double avg = nrows ? double(nnz) / double(nrows) : 0.0;
+    lanes = avg < 12 ? 4 : avg < 24 ? 8 : avg < 100 ? 16 : avg < 200 ? 32 : 64;
+  }
+  void apply(hipStream_t st, int mode, const double* x, const double* b, double* y) const {
+    stgmg::k_csr(st, mode, nrows, ptr.p, col.p, val.p, x, b, y, lanes);
+  }
+};
+
+struct LevelDev {
+  int N = 0;
+  int64_t n = 0, ns = 0;
+  DevCsr A;
+  int64_t npatch = 0;
+  int max_np = 0;
+  DArr<int64_t> poff, ioff, tptr, tidx;
+  DArr<int32_t> pdof;
+  DArr<double> inv64, winv, y;
+  DArr<float> inv32;
+  DevCsr P, R;  // prolongation from level-1 and its transpose
+  DArr<double> b, d, r;
+  std::vector<int64_t> poff_h, ioff_h;
+  std::vector<int32_t> pdof_h;
+};
+
+}  // namespace
+
+struct stgmg_handle {
+  stgmg_params prm{};
+  hipStream_t st = nullptr;
+  int L = 0;  // finest level index
+  std::vector<LevelDev> lv;
+  int64_t bytes = 0;
+  // coarse solve
+  int n0 = 0;
+  DArr<double> coarse_inv;
+  // finest level data for the right-hand side
+  stgmg::LevelHost fine_info;  // sizes, Kcell (no matrices)
+  stgmg::Material mat{};
+  stgmg::TimeConsts T;
+  DevCsr MM;
+  DArr<double> e_dev, tmp_ns, src_buf;
+  // FGMRES workspace
+  int m_alloc = 0;
+  DArr<double> V, Z, w, partials, hdev, ydev;
+  double* hhost = nullptr;  // pinned
+  ~stgmg_handle() {
+    if (hhost) (void)hipHostFree(hhost);
+  }
+};
+
+namespace {
+
+using stgmg::LevelHost;
+
+void check_params(const stgmg_params* p) {
+  if (!p) throw ApiError(STGMG_ERR_INVALID_ARG, "params is NULL");
+  if (p->dim != 2 && p->dim != 3) throw ApiError(STGMG_ERR_INVALID_ARG, "dim must be 2 or 3");
+  if (p->coarse_cells < 1 || p->levels < 1 || p->levels > 12)
+    throw ApiError(STGMG_ERR_INVALID_ARG, "coarse_cells >= 1 and 1 <= levels <= 12 required");
+  if (p->r < 2 || p->r > 4) throw ApiError(STGMG_ERR_UNSUPPORTED, "r must be in 2..4");
+  if (p->k < 0 || p->k > 3) throw ApiError(STGMG_ERR_UNSUPPORTED, "k must be in 0..3");
+  if (p->patch != STGMG_PATCH_CELL && p->patch != STGMG_PATCH_VERTEX)
+    throw ApiError(STGMG_ERR_INVALID_ARG, "unknown patch kind");
+  if (p->smoother_prec != STGMG_FP64 && p->smoother_prec != STGMG_FP32)
+    throw ApiError(STGMG_ERR_INVALID_ARG, "unknown smoother precision");
+  if (p->n_smooth < 0 || p->n_smooth > 64) throw ApiError(STGMG_ERR_INVALID_ARG, "n_smooth out of range");
+  if (!(p->tau > 0) || !(p->rho > 0) || !(p->mu > 0) || !(p->c0 > 0) || !(p->alpha >= 0) ||
+      !(p->lambda >= 0) || !(p->omega > 0))
+    throw ApiError(STGMG_ERR_INVALID_ARG, "tau, rho, mu, c0, omega must be > 0; lambda, alpha >= 0");
+  const int64_t Nf = int64_t(p->coarse_cells) << (p->levels - 1);
+  if (Nf > 4096) throw ApiError(STGMG_ERR_UNSUPPORTED, "grid too fine");
+  if (!p->K_cells && !(p->K > 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "K must be > 0");
+}
+
+int host_threads() {
+  unsigned t = std::thread::hardware_concurrency();
+  if (t == 0) t = 4;
+  return int(std::min(t, 32u));
+}
+
+size_t lds_limit() {
+  // dynamic LDS per block used by the inversion kernel; 64 KiB works on every
+  // CDNA part without changing kernel attributes
+  return 64 * 1024;
+}
+
+void vcycle(stgmg_handle* h, int l, const double* b, double* d);
+
+void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool zero_start) {
+  LevelDev& L = h->lv[l];
+  for (int j = 0; j < sweeps; ++j) {
+    const double* r = b;
+    if (!(j == 0 && zero_start)) {
+      L.A.apply(h->st, 1, d, b, L.r.p);
+      r = L.r.p;
+    }
+    if (h->prm.smoother_prec == STGMG_FP32)
+      stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r, L.y.p);
+    else
+      stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r, L.y.p);
+    stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.tidx.p, L.winv.p, L.y.p, d);
+  }
+}
+
+void vcycle(stgmg_handle* h, int l, const double* b, double* d) {
+  if (l == 0) {
+    stgmg::k_dense_gemv_t(h->st, h->n0, h->coarse_inv.p, b, d);
+    return;
+  }
+  LevelDev& L = h->lv[l];
+  LevelDev& C = h->lv[l - 1];
+  const int J = h->prm.n_smooth;
+  stgmg::k_fill_zero(h->st, d, L.n);
+  smooth(h, l, b, d, J, true);
+  L.A.apply(h->st, 1, d, b, L.r.p);
+  L.R.apply(h->st, 0, L.r.p, nullptr, C.b.p);
+  vcycle(h, l - 1, C.b.p, C.d.p);
+  L.P.apply(h->st, 2, C.d.p, nullptr, d);
+  smooth(h, l, b, d, J, false);
+}
+
+// Dense transposed copy of a CSR matrix: W[c * n + r] = A[r][c].
+std::vector<double> dense_transposed(const stgmg::Csr& A) {
+  const int64_t n = A.nrows;
+  std::vector<double> W(size_t(n) * n, 0.0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t p = A.ptr[r]; p < A.ptr[r + 1]; ++p) W[size_t(A.col[p]) * n + r] = A.val[p];
+  return W;
+}
+
+void build(stgmg_handle* h) {
+  const stgmg_params& p = h->prm;
+  const int d = p.dim, L = p.levels - 1;
+  h->L = L;
+  h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
+  h->T = stgmg::make_time_consts(p.k, p.tau);
+  const int nth = host_threads();
+  int64_t* ctr = &h->bytes;
+  // permeability per level: finest from the caller, coarse = mean of the 2^d children
+  std::vector<std::vector<double>> Kl(L + 1);
+  {
+    const int Nf = p.coarse_cells << L;
+    int64_t nc = 1;
+    for (int a = 0; a < d; ++a) nc *= Nf;
+    Kl[L].assign(nc, p.K);
+    if (p.K_cells) {
+      for (int64_t c = 0; c < nc; ++c) {
+        if (!(p.K_cells[c] > 0) || !std::isfinite(p.K_cells[c]))
+          throw ApiError(STGMG_ERR_INVALID_ARG, "K_cells must be finite and > 0");
+        Kl[L][c] = p.K_cells[c];
+      }
+    }
+    for (int l = L - 1; l >= 0; --l) {
+      const int N = p.coarse_cells << l;
+      int64_t ncl = 1;
+      for (int a = 0; a < d; ++a) ncl *= N;
+      Kl[l].assign(ncl, 0.0);
+      const int Nfn = 2 * N;
+      for (int64_t c = 0; c < ncl; ++c) {
+        int cc[3] = {0, 0, 0};
+        int64_t rem = c;
+        for (int a = 0; a < d; ++a) {
+          cc[a] = int(rem % N);
+          rem /= N;
+        }
+        double s = 0.0;
+        for (int ch = 0; ch < (1 << d); ++ch) {
+          int64_t idx = 0;
+          for (int a = d - 1; a >= 0; --a) idx = idx * Nfn + (2 * cc[a] + ((ch >> a) & 1));
+          s += Kl[l + 1][idx];
+        }
+        Kl[l][c] = s / double(1 << d);
+      }
+    }
+  }
+  h->lv.resize(L + 1);
+  LevelHost prev;
+  for (int l = 0; l <= L; ++l) {
+    LevelHost H;
+    stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1, l == L};
+    stgmg::build_level(o, h->mat, Kl[l], H, nth);
+    LevelDev& D = h->lv[l];
+    D.N = H.N;
+    D.n = H.n;
+    D.ns = H.ns;
+    D.A.upload(H.A, h->st, ctr);
+    D.b.alloc(H.n, ctr);
+    D.d.alloc(H.n, ctr);
+    D.r.alloc(H.n, ctr);
+    if (l == 0) {
+      if (H.n > 1400) throw ApiError(STGMG_ERR_UNSUPPORTED, "coarsest level too large for the dense inverse");
+      h->n0 = int(H.n);
+      std::vector<double> W0 = dense_transposed(H.A);
+      DArr<double> Wd;
+      Wd.upload(W0, h->st, nullptr);
+      h->coarse_inv.alloc(H.n * H.n, ctr);
+      std::vector<int64_t> poff0 = {0, H.n}, zero = {0};
+      DArr<int64_t> poffd, woffd;
+      poffd.upload(poff0, h->st, nullptr);
+      woffd.upload(zero, h->st, nullptr);
+      DArr<int32_t> stat;
+      stat.upload(std::vector<int32_t>(1, 0), h->st, nullptr);
+      const int nb = stgmg::gj_panel_width(int(H.n), lds_limit());
+      if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "coarse inverse does not fit in LDS");
+      stgmg::k_gj_invert_f64(h->st, nb, 0, 1, int(H.n), poffd.p, woffd.p, Wd.p, woffd.p, h->coarse_inv.p, stat.p);
+      HIPCHK(hipGetLastError());
+      int32_t s = 0;
+      HIPCHK(hipMemcpyAsync(&s, stat.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      if (s) throw ApiError(STGMG_ERR_SINGULAR_PATCH, "coarse operator is singular");
+    }
+    if (l >= 1) {
+      stgmg::Csr P = stgmg::build_prolongation(prev, H);
+      D.P.upload(P, h->st, ctr);
+      D.R.upload(stgmg::transpose(P, H.n), h->st, ctr);
+      // patches
+      D.npatch = H.npatch;
+      D.poff_h = H.poff;
+      D.pdof_h = H.pdof;
+      D.ioff_h.assign(H.npatch + 1, 0);
+      int max_np = 0;
+      for (int64_t q = 0; q < H.npatch; ++q) {
+        const int64_t np = H.poff[q + 1] - H.poff[q];
+        max_np = std::max<int>(max_np, int(np));
+        D.ioff_h[q + 1] = D.ioff_h[q] + np * np;
+      }
+      D.max_np = max_np;
+      D.poff.upload(H.poff, h->st, ctr);
+      D.pdof.upload(H.pdof, h->st, ctr);
+      D.ioff.upload(D.ioff_h, h->st, ctr);
+      D.tptr.upload(H.tptr, h->st, ctr);
+      D.tidx.upload(H.tidx, h->st, ctr);
+      D.winv.upload(H.winv, h->st, ctr);
+      D.y.alloc(int64_t(H.pdof.size()), ctr);
+      const int64_t tot = D.ioff_h[H.npatch];
+      if (p.smoother_prec == STGMG_FP32)
+        D.inv32.alloc(tot, ctr);
+      else
+        D.inv64.alloc(tot, ctr);
+      // extraction + inversion in batches through a dense work buffer
+      const int nb = stgmg::gj_panel_width(max_np, lds_limit());
+      if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
+      const int64_t stride = int64_t(max_np) * max_np;
+      int64_t batch = std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / (stride * 8)));
+      DArr<double> Wb;
+      Wb.alloc(batch * stride, nullptr);
+      std::vector<int64_t> woff_h(batch);
+      for (int64_t i = 0; i < batch; ++i) woff_h[i] = i * stride;
+      DArr<int64_t> woff;
+      woff.upload(woff_h, h->st, nullptr);
+      DArr<int32_t> stat;
+      stat.upload(std::vector<int32_t>(H.npatch, 0), h->st, nullptr);
+      for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
+        const int64_t cnt = std::min(batch, H.npatch - p0);
+        stgmg::k_fill_zero(h->st, Wb.p, cnt * stride);
+        stgmg::k_patch_extract_t(h->st, p0, cnt, max_np, D.poff.p, D.pdof.p, D.A.ptr.p, D.A.col.p, D.A.val.p, woff.p,
+                                 Wb.p);
+        if (p.smoother_prec == STGMG_FP32)
+          stgmg::k_gj_invert_f32(h->st, nb, p0, cnt, max_np, D.poff.p, woff.p, Wb.p, D.ioff.p, D.inv32.p, stat.p);
+        else
+          stgmg::k_gj_invert_f64(h->st, nb, p0, cnt, max_np, D.poff.p, woff.p, Wb.p, D.ioff.p, D.inv64.p, stat.p);
+        HIPCHK(hipGetLastError());
+      }
+      std::vector<int32_t> st_h(H.npatch);
+      HIPCHK(hipMemcpyAsync(st_h.data(), stat.p, st_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      for (int64_t q = 0; q < H.npatch; ++q)
+        if (st_h[q])
+          throw ApiError(STGMG_ERR_SINGULAR_PATCH,
+                         "patch " + std::to_string(q) + " of level " + std::to_string(l) + " is singular");
+    }
+    if (l == L) {
+      h->MM.upload(H.MM, h->st, ctr);
+      h->fine_info = H;
+      h->fine_info.A = stgmg::Csr();
+      h->fine_info.MM = stgmg::Csr();
+      h->fine_info.pdof.clear();
+      h->fine_info.pdof.shrink_to_fit();
+      h->fine_info.poff.clear();
+      h->fine_info.tptr.clear();
+      h->fine_info.tidx.clear();
+      h->fine_info.winv.clear();
+    }
+    HIPCHK(hipStreamSynchronize(h->st));  // host vectors of H are freed below
+    prev = LevelHost();
+    prev.d = H.d;
+    prev.r = H.r;
+    prev.k = H.k;
+    prev.N = H.N;
+    prev.n1 = H.n1;
+    prev.n1p = H.n1p;
+    prev.nQ = H.nQ;
+    prev.nP = H.nP;
+    prev.nv = H.nv;
+    prev.ns = H.ns;
+    prev.n = H.n;
+  }
+  h->e_dev.upload(h->T.e, h->st, ctr);
+  h->tmp_ns.alloc(h->fine_info.ns, ctr);
+  h->src_buf.alloc(h->fine_info.n, ctr);
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 256 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipStreamSynchronize(h->st));
+}
+
+void ensure_krylov(stgmg_handle* h, int m) {
+  if (h->m_alloc >= m) return;
+  const int64_t n = h->lv[h->L].n;
+  h->V.alloc(int64_t(m + 1) * n, &h->bytes);
+  h->Z.alloc(int64_t(m) * n, &h->bytes);
+  h->w.alloc(n, &h->bytes);
+  h->partials.alloc(int64_t(m + 2) * stgmg::dot_blocks(n), &h->bytes);
+  h->hdev.alloc(2 * (m + 2) + 4, &h->bytes);
+  h->ydev.alloc(m + 1, &h->bytes);
+  h->m_alloc = m;
+}
+
+double device_norm2(stgmg_handle* h, const double* x, int64_t n) {
+  stgmg::k_multi_dot(h->st, x, n, 1, x, n, h->partials.p, h->hdev.p, 0);
+  HIPCHK(hipMemcpyAsync(h->hhost, h->hdev.p, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return h->hhost[0];
+}
+
+stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol, int m, int maxit,
+                      stgmg_info* info) {
+  if (!rhs || !x) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL vector");
+  if (m < 1 || m > 100 || maxit < 1 || !(rtol >= 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "bad solver arguments");
+  auto t0 = std::chrono::steady_clock::now();
+  ensure_krylov(h, m);
+  const int64_t n = h->lv[h->L].n;
+  const DevCsr& A = h->lv[h->L].A;
+  hipStream_t st = h->st;
+  stgmg_info inf{};
+  // r0 = rhs - A x0
+  A.apply(st, 1, x, rhs, h->w.p);
+  const double b0sq = device_norm2(h, h->w.p, n);
+  if (!std::isfinite(b0sq)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite initial residual (rhs or x0)");
+  const double beta0 = std::sqrt(b0sq);
+  inf.res0 = beta0;
+  double beta = beta0;
+  const double target = rtol * beta0;
+  int its = 0;
+  stgmg_status status = STGMG_OK;
+  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  double est = beta0 > 0 ? 1.0 : 0.0;
+  while (beta > target && beta0 > 0) {
+    if (its >= maxit) {
+      status = STGMG_NOT_CONVERGED;
+      break;
+    }
+    // v_0 = r / beta   (h->hdev[0] still holds ||r||^2 from device_norm2)
+    stgmg::k_scale_copy(st, h->w.p, h->hdev.p, h->V.p, n);
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int jd = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->V.p + int64_t(j) * n;
+      double* zj = h->Z.p + int64_t(j) * n;
+      vcycle(h, h->L, vj, zj);
+      A.apply(st, 0, zj, nullptr, h->w.p);
+      // classical Gram-Schmidt, twice (CGS2)
+      double* h1 = h->hdev.p;
+      double* h2 = h->hdev.p + (m + 2);
+      double* hn = h->hdev.p + 2 * (m + 2);
+      stgmg::k_multi_dot(st, h->V.p, n, j + 1, h->w.p, n, h->partials.p, h1, 0);
+      stgmg::k_multi_axpy(st, h->V.p, n, j + 1, h1, -1.0, h->w.p, n);
+      stgmg::k_multi_dot(st, h->V.p, n, j + 1, h->w.p, n, h->partials.p, h2, 0);
+      stgmg::k_multi_axpy(st, h->V.p, n, j + 1, h2, -1.0, h->w.p, n);
+      stgmg::k_multi_dot(st, h->w.p, n, 1, h->w.p, n, h->partials.p, hn, 0);
+      stgmg::k_scale_copy(st, h->w.p, hn, h->V.p + int64_t(j + 1) * n, n);
+      HIPCHK(hipMemcpyAsync(h->hhost, h->hdev.p, (2 * (m + 2) + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h->hhost[i] + h->hhost[m + 2 + i];
+      const double hnn = std::sqrt(h->hhost[2 * (m + 2)]);
+      if (!std::isfinite(hnn)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite value in the Arnoldi process");
+      H[size_t(j + 1) * m + j] = hnn;
+      for (int i = 0; i < j; ++i) {
+        const double a = H[size_t(i) * m + j], b = H[size_t(i + 1) * m + j];
+        H[size_t(i) * m + j] = cs[i] * a + sn[i] * b;
+        H[size_t(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[size_t(j) * m + j], b = H[size_t(j + 1) * m + j];
+      const double den = std::hypot(a, b);
+      cs[j] = den > 0 ? a / den : 1.0;
+      sn[j] = den > 0 ? b / den : 0.0;
+      H[size_t(j) * m + j] = den;
+      H[size_t(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++its;
+      jd = j + 1;
+      est = std::fabs(g[j + 1]) / beta0;
+      if (std::fabs(g[j + 1]) <= target || its >= maxit || hnn == 0.0) break;
+    }
+    // y = H^{-1} g (upper triangular), x += Z y
+    for (int i = jd - 1; i >= 0; --i) {
+      double s = g[i];
+      for (int c = i + 1; c < jd; ++c) s -= H[size_t(i) * m + c] * y[c];
+      y[i] = s / H[size_t(i) * m + i];
+    }
+    HIPCHK(hipMemcpyAsync(h->ydev.p, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
+    stgmg::k_multi_axpy(st, h->Z.p, n, jd, h->ydev.p, 1.0, x, n);
+    A.apply(st, 1, x, rhs, h->w.p);
+    beta = std::sqrt(device_norm2(h, h->w.p, n));
+    if (!std::isfinite(beta)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite residual");
+    if (beta > target) inf.restarts++;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  inf.iters = its;
+  inf.converged = beta <= target ? 1 : 0;
+  if (!inf.converged) status = STGMG_NOT_CONVERGED;
+  if (inf.converged && inf.restarts > 0) inf.restarts--;  // the final check is not a restart
+  inf.rel_res_true = beta0 > 0 ? beta / beta0 : 0.0;
+  inf.rel_res_est = est;
+  inf.t_solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+template <class F>
+stgmg_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const ApiError& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host out of memory";
+    return STGMG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return STGMG_ERR_HIP;
+  }
+}
+
+int level_index(const stgmg_handle* h, int32_t level) {
+  if (level == -1) return h->L;
+  if (level < 0 || level > h->L) throw ApiError(STGMG_ERR_INVALID_ARG, "level out of range");
+  return level;
+}
+
+}  // namespace
+
+extern "C" {
+
+stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_handle** out) {
+  return guarded([&] {
+    if (!out) throw ApiError(STGMG_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    check_params(params);
+    std::unique_ptr<stgmg_handle> h(new stgmg_handle());
+    h->prm = *params;
+    h->prm.K_cells = nullptr;  // copied into the level data, never kept
+    h->st = reinterpret_cast<hipStream_t>(hip_stream);
+    stgmg_params tmp = *params;
+    h->prm = tmp;
+    build(h.get());
+    h->prm.K_cells = nullptr;
+    *out = h.release();
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, int64_t* n_patches, int64_t* nnz,
+                         int64_t* hbm_bytes) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    const int l = level_index(h, level);
+    if (n_dofs) *n_dofs = h->lv[l].n;
+    if (n_patches) *n_patches = h->lv[l].npatch;
+    if (nnz) *nnz = h->lv[l].A.nnz;
+    if (hbm_bytes) *hbm_bytes = h->bytes;
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, double rtol, int32_t restart,
+                         int32_t max_iters, stgmg_info* info) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    return do_solve(h, rhs_dev, x_dev, rtol, restart, max_iters, info);
+  });
+}
+
+stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* x_dev, double* y_dev) {
+  return guarded([&] {
+    if (!h || !x_dev || !y_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    const int l = level_index(h, level);
+    h->lv[l].A.apply(h->st, 0, x_dev, nullptr, y_dev);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_apply_vcycle(stgmg_handle* h, const double* r_dev, double* z_dev) {
+  return guarded([&] {
+    if (!h || !r_dev || !z_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    vcycle(h, h->L, r_dev, z_dev);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_smooth(stgmg_handle* h, int32_t level, const double* b_dev, double* d_dev, int32_t sweeps) {
+  return guarded([&] {
+    if (!h || !b_dev || !d_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    const int l = level_index(h, level);
+    if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level 0 has no smoother");
+    if (sweeps < 0) throw ApiError(STGMG_ERR_INVALID_ARG, "sweeps < 0");
+    smooth(h, l, b_dev, d_dev, sweeps, false);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_prolongate_add(stgmg_handle* h, int32_t level, const double* e_coarse_dev, double* d_fine_dev) {
+  return guarded([&] {
+    if (!h || !e_coarse_dev || !d_fine_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    const int l = level_index(h, level);
+    if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
+    h->lv[l].P.apply(h->st, 2, e_coarse_dev, nullptr, d_fine_dev);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine_dev, double* b_coarse_dev) {
+  return guarded([&] {
+    if (!h || !r_fine_dev || !b_coarse_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    const int l = level_index(h, level);
+    if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
+    h->lv[l].R.apply(h->st, 0, r_fine_dev, nullptr, b_coarse_dev);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_prev_end_dev, double* rhs_dev) {
+  return guarded([&] {
+    if (!h || !x_prev_end_dev || !rhs_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    const auto& F = h->fine_info;
+    const int nt = h->T.k + 1;
+    std::vector<double> src(size_t(nt) * F.ns), one;
+    for (int b = 0; b < nt; ++b) {
+      const double tb = t_start + 0.5 * h->prm.tau * (1.0 + h->T.x[b]);
+      stgmg::source_vector(F, h->mat, tb, one);
+      for (int64_t i = 0; i < F.ns; ++i) src[size_t(b) * F.ns + i] = h->T.mt[b] * one[i];
+    }
+    HIPCHK(hipMemcpyAsync(h->src_buf.p, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    h->MM.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
+    stgmg::k_slab_rhs(h->st, nt, F.ns, h->e_dev.p, h->tmp_ns.p, h->src_buf.p, rhs_dev);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_interpolate_solution(stgmg_handle* h, double t, double* x_block_dev) {
+  return guarded([&] {
+    if (!h || !x_block_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    std::vector<double> v;
+    stgmg::interpolate_solution(h->fine_info, t, v);
+    HIPCHK(hipMemcpyAsync(x_block_dev, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t patch, int32_t* n_p, double* out_host,
+                                     int64_t* dofs_host) {
+  return guarded([&] {
+    if (!h || !n_p) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    const int l = level_index(h, level);
+    if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
+    const LevelDev& D = h->lv[l];
+    if (patch < 0 || patch >= D.npatch) throw ApiError(STGMG_ERR_INVALID_ARG, "patch out of range");
+    const int n = int(D.poff_h[patch + 1] - D.poff_h[patch]);
+    *n_p = n;
+    if (!out_host) return STGMG_OK;
+    std::vector<double> st(size_t(n) * n);
+    if (h->prm.smoother_prec == STGMG_FP32) {
+      std::vector<float> f(size_t(n) * n);
+      HIPCHK(hipMemcpy(f.data(), D.inv32.p + D.ioff_h[patch], f.size() * sizeof(float), hipMemcpyDeviceToHost));
+      for (size_t i = 0; i < f.size(); ++i) st[i] = f[i];
+    } else {
+      HIPCHK(hipMemcpy(st.data(), D.inv64.p + D.ioff_h[patch], st.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * n + a];
+    if (dofs_host)
+      for (int a = 0; a < n; ++a) dofs_host[a] = D.pdof_h[D.poff_h[patch] + a];
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_destroy(stgmg_handle* h) {
+  return guarded([&] {
+    if (h) {
+      (void)hipStreamSynchronize(h->st);
+      delete h;
+    }
+    return STGMG_OK;
+  });
+}
+
+const char* stgmg_status_string(stgmg_status s) {
+  switch (s) {
+    case STGMG_OK: return "ok";
+    case STGMG_NOT_CONVERGED: return "not converged";
+    case STGMG_ERR_INVALID_ARG: return "invalid argument";
+    case STGMG_ERR_UNSUPPORTED: return "unsupported configuration";
+    case STGMG_ERR_OOM: return "out of memory";
+    case STGMG_ERR_HIP: return "HIP error";
+    case STGMG_ERR_SINGULAR_PATCH: return "singular patch matrix";
+    case STGMG_ERR_NONFINITE: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+const char* stgmg_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Host-only test exports of the setup code (no HIP): lets CPU tests compare
+// the C++ assembly, patch tables, transfers and sources with the oracle.
+#include <cstring>
+#include <vector>
+
+#include "host_setup.h"
+
+namespace {
+stgmg::LevelHost g_level;
+stgmg::Csr g_P;
+std::vector<double> g_vec;
+}  // namespace
+
+extern "C" {
+
+// Build one level; returns n (space-time unknowns) or -1 on error.
+long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double tau, double omega, double rho,
+                           double lambda, double mu, double alpha, double c0, const double* Kcell) {
+  try {
+    long long nc = 1;
+    for (int a = 0; a < d; ++a) nc *= N;
+    std::vector<double> K(Kcell, Kcell + nc);
+    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true};
+    stgmg::Material m{rho, lambda, mu, alpha, c0};
+    g_level = stgmg::LevelHost();
+    stgmg::build_level(o, m, K, g_level, 4);
+    return g_level.n;
+  } catch (...) {
+    return -1;
+  }
+}
+
+long long stgmg_host_nnz(int which) {
+  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : g_P;
+  return (long long)c.col.size();
+}
+
+// which: 0 = A, 1 = MM, 2 = last prolongation
+void stgmg_host_csr(int which, long long* ptr, int* col, double* val) {
+  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : g_P;
+  for (size_t i = 0; i < c.ptr.size(); ++i) ptr[i] = c.ptr[i];
+  std::memcpy(col, c.col.data(), c.col.size() * sizeof(int));
+  std::memcpy(val, c.val.data(), c.val.size() * sizeof(double));
+}
+
+long long stgmg_host_npatch(void) { return g_level.npatch; }
+long long stgmg_host_patch_total(void) { return (long long)g_level.pdof.size(); }
+
+void stgmg_host_patches(long long* poff, int* pdof, double* winv) {
+  for (size_t i = 0; i < g_level.poff.size(); ++i) poff[i] = g_level.poff[i];
+  std::memcpy(pdof, g_level.pdof.data(), g_level.pdof.size() * sizeof(int));
+  std::memcpy(winv, g_level.winv.data(), g_level.winv.size() * sizeof(double));
+}
+
+// Prolongation from an N-cell level to the 2N-cell level (both built here).
+long long stgmg_host_prolongation(int d, int r, int k, int Nc) {
+  try {
+    stgmg::LevelHost C, F;
+    std::vector<double> Kc(1, 1.0), Kf(1, 1.0);
+    long long ncc = 1, ncf = 1;
+    for (int a = 0; a < d; ++a) {
+      ncc *= Nc;
+      ncf *= 2 * Nc;
+    }
+    Kc.assign(ncc, 1.0);
+    Kf.assign(ncf, 1.0);
+    stgmg::Material m{1, 1, 1, 1, 1};
+    stgmg::build_level({d, r, k, Nc, 0, 0.1, 0.7, false, false}, m, Kc, C, 4);
+    stgmg::build_level({d, r, k, 2 * Nc, 0, 0.1, 0.7, false, false}, m, Kf, F, 4);
+    g_P = stgmg::build_prolongation(C, F);
+    return (long long)g_P.col.size();
+  } catch (...) {
+    return -1;
+  }
+}
+
+void stgmg_host_time(int k, double tau, double* x, double* w, double* Dt, double* mt, double* e) {
+  stgmg::TimeConsts T = stgmg::make_time_consts(k, tau);
+  for (int i = 0; i <= k; ++i) {
+    x[i] = T.x[i];
+    w[i] = T.w[i];
+    mt[i] = T.mt[i];
+    e[i] = T.e[i];
+  }
+  for (int i = 0; i < (k + 1) * (k + 1); ++i) Dt[i] = T.Dt[i];
+}
+
+// Source vector of the built-in solution at time t for the last built level (n_s values).
+void stgmg_host_source(double t, double rho, double lambda, double mu, double alpha, double c0, double* out) {
+  stgmg::Material m{rho, lambda, mu, alpha, c0};
+  stgmg::source_vector(g_level, m, t, g_vec);
+  std::memcpy(out, g_vec.data(), g_vec.size() * sizeof(double));
+}
+
+void stgmg_host_interpolate(double t, double* out) {
+  stgmg::interpolate_solution(g_level, t, g_vec);
+  std::memcpy(out, g_vec.data(), g_vec.size() * sizeof(double));
+}
+
+}  // extern "C"

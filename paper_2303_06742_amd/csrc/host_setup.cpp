@@ -1,0 +1,930 @@
+// Host construction of the slab operators, patch tables and transfers.
+//
+// Discretisation (paper Sec. 2-4): dG(k) in time with the Lagrange basis at the
+// right Gauss-Radau points (Eq:GF, Eq:TimeExp), Taylor-Hood Q_r^d / Q_{r-1} in
+// space on axis-parallel square/cube cells (Def:VhQh), Nitsche boundary terms
+// (Def:ACB, Def:ab) with gamma_a = 5e4 r(r+1), gamma_b = r(r-1)/2 and
+// h_F = |K|_d on boundary faces.  The slab matrix of Problem 4.1 (v-form of
+// Problem 3.1) is
+//     A_n = D^t (x) MM + M^t (x) KK,
+//     MM = [[0, Mrho, 0], [Mrho, 0, 0], [0, 0, c0 Mp]],
+//     KK = [[-Mrho, 0, 0], [0, A_gamma, C^T], [-C, 0, B_gamma]]
+// with rows (u-eq, v-eq, p-eq) and columns (V, U, P).
+#include "host_setup.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <functional>
+#include <stdexcept>
+#include <thread>
+
+namespace stgmg {
+
+namespace {
+
+// ---------------------------------------------------------------- 1D tools
+double legendre(int n, double x) {
+  if (n == 0) return 1.0;
+  double p0 = 1.0, p1 = x;
+  for (int j = 2; j <= n; ++j) {
+    double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// Gauss-Legendre points/weights on [0,1] by Newton iteration on P_n.
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p = legendre(n, z), pm = legendre(n - 1, z);
+      double dp = n * (z * p - pm) / (z * z - 1.0);
+      double dz = p / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p = legendre(n, z), pm = legendre(n - 1, z);
+    double dp = n * (z * p - pm) / (z * z - 1.0);
+    x[n - 1 - i] = 0.5 * (z + 1.0);
+    w[n - 1 - i] = 0.5 * 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// Degree-p Lagrange basis on the equispaced nodes j/p of [0,1]: values and derivatives at xi.
+void lagrange01(int p, double xi, double* v, double* dv) {
+  for (int a = 0; a <= p; ++a) {
+    double xa = double(a) / p, val = 1.0, der = 0.0;
+    for (int b = 0; b <= p; ++b) {
+      if (b == a) continue;
+      double xb = double(b) / p;
+      // product rule: der = der*(xi-xb)/(xa-xb) + val/(xa-xb)
+      der = der * (xi - xb) / (xa - xb) + val / (xa - xb);
+      val = val * (xi - xb) / (xa - xb);
+    }
+    v[a] = val;
+    if (dv) dv[a] = der;
+  }
+}
+
+// Tensor-product basis of Q_p on [0,h]^d at a reference point: values and physical gradients.
+struct Tab {
+  int nl;
+  std::vector<double> v;  // [nl]
+  std::vector<double> g;  // [nl][3]
+};
+void tabulate(int p, int d, const double* xi, double h, Tab& t) {
+  int n1 = p + 1;
+  t.nl = 1;
+  for (int a = 0; a < d; ++a) t.nl *= n1;
+  t.v.assign(t.nl, 1.0);
+  t.g.assign(size_t(t.nl) * 3, 1.0);
+  double v1[3][8], d1[3][8];
+  for (int ax = 0; ax < d; ++ax) lagrange01(p, xi[ax], v1[ax], d1[ax]);
+  for (int a = 0; a < t.nl; ++a) {
+    int idx[3] = {0, 0, 0}, rem = a;
+    for (int ax = 0; ax < d; ++ax) {
+      idx[ax] = rem % n1;
+      rem /= n1;
+    }
+    for (int ax = 0; ax < d; ++ax) t.v[a] *= v1[ax][idx[ax]];
+    for (int g = 0; g < d; ++g)
+      for (int ax = 0; ax < d; ++ax)
+        t.g[a * 3 + g] *= (g == ax) ? d1[ax][idx[ax]] / h : v1[ax][idx[ax]];
+  }
+}
+
+template <class F>
+void parallel_for(int64_t n, int nthreads, F&& f) {
+  if (nthreads <= 1 || n < 4096) {
+    f(int64_t(0), n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nthreads - 1) / nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    int64_t lo = t * chunk, hi = std::min(n, lo + chunk);
+    if (lo >= hi) break;
+    th.emplace_back([&f, lo, hi] { f(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- time constants
+TimeConsts make_time_consts(int k, double tau) {
+  TimeConsts T;
+  T.k = k;
+  T.tau = tau;
+  int n = k + 1;
+  // right Radau: roots of P_k - P_{k+1}; x = +1 is one of them.  The interior
+  // roots are found by sign changes of (P_k - P_{k+1})/(1-x) and bisection.
+  std::vector<double> xs;
+  if (k > 0) {
+    auto f = [k](double x) { return (legendre(k, x) - legendre(k + 1, x)) / (1.0 - x); };
+    const int M = 20000;
+    double xl = -1.0, fl = f(xl);
+    for (int i = 1; i <= M; ++i) {
+      double xr = -1.0 + 2.0 * i / M * (1.0 - 1e-12), fr = f(xr);
+      if (fl == 0.0) {
+        xs.push_back(xl);
+      } else if ((fl < 0) != (fr < 0)) {
+        double a = xl, b = xr, fa = fl;
+        for (int it = 0; it < 200; ++it) {
+          double m = 0.5 * (a + b), fm = f(m);
+          if ((fm < 0) == (fa < 0)) {
+            a = m;
+            fa = fm;
+          } else {
+            b = m;
+          }
+        }
+        xs.push_back(0.5 * (a + b));
+      }
+      xl = xr;
+      fl = fr;
+    }
+  }
+  if (int(xs.size()) != k) throw std::runtime_error("Gauss-Radau node search failed");
+  xs.push_back(1.0);
+  T.x = xs;
+  T.w.resize(n);
+  // weights of the right Radau rule: 2/n^2 at +1, (1 + x_j) / (n^2 P_{n-1}(x_j)^2) inside
+  for (int j = 0; j < n; ++j) {
+    if (j == n - 1) {
+      T.w[j] = 2.0 / (double(n) * n);
+    } else {
+      double pk = legendre(n - 1, xs[j]);
+      T.w[j] = (1.0 + xs[j]) / (double(n) * n * pk * pk);
+    }
+  }
+  auto chi = [&](int a, double t) {
+    double v = 1.0;
+    for (int b = 0; b < n; ++b)
+      if (b != a) v *= (t - xs[b]) / (xs[a] - xs[b]);
+    return v;
+  };
+  auto dchi = [&](int a, double t) {
+    double s = 0.0;
+    for (int c = 0; c < n; ++c) {
+      if (c == a) continue;
+      double v = 1.0 / (xs[a] - xs[c]);
+      for (int b = 0; b < n; ++b)
+        if (b != a && b != c) v *= (t - xs[b]) / (xs[a] - xs[b]);
+      s += v;
+    }
+    return s;
+  };
+  T.Dt.assign(n * n, 0.0);
+  T.e.resize(n);
+  T.mt.resize(n);
+  for (int b = 0; b < n; ++b) {
+    T.e[b] = chi(b, -1.0);
+    T.mt[b] = 0.5 * tau * T.w[b];
+  }
+  // D^t[b][a] = w_b chi_a'(x_b) + chi_a(-1) chi_b(-1)  (the rule is exact, chi_b(x_m) = delta)
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a < n; ++a) T.Dt[b * n + a] = T.w[b] * dchi(a, xs[b]) + T.e[a] * T.e[b];
+  return T;
+}
+
+// ------------------------------------------------------------- cell matrices
+CellMats make_cell_mats(int d, int r, double h, const Material& m) {
+  CellMats C;
+  C.d = d;
+  C.r = r;
+  int ns = 1, np = 1;
+  for (int a = 0; a < d; ++a) {
+    ns *= (r + 1);
+    np *= r;
+  }
+  C.nls = ns;
+  C.nlv = d * ns;
+  C.nlp = np;
+  C.gamma_a = 5e4 * r * (r + 1);
+  C.gamma_b = 0.5 * r * (r - 1);
+  C.hF = std::pow(h, d);
+  const int nv = C.nlv;
+  C.Mrho.assign(size_t(nv) * nv, 0.0);
+  C.Avol.assign(size_t(nv) * nv, 0.0);
+  C.Cvol.assign(size_t(np) * nv, 0.0);
+  C.Bvol.assign(size_t(np) * np, 0.0);
+  C.Mp.assign(size_t(np) * np, 0.0);
+  std::vector<double> gx, gw;
+  gauss_legendre01(r + 1, gx, gw);
+  const int nq1 = r + 1;
+  int nq = 1;
+  for (int a = 0; a < d; ++a) nq *= nq1;
+  Tab s, p;
+  const double mu = m.mu, lam = m.lambda;
+  for (int q = 0; q < nq; ++q) {
+    double xi[3] = {0, 0, 0}, wq = 1.0;
+    int rem = q;
+    for (int ax = 0; ax < d; ++ax) {
+      xi[ax] = gx[rem % nq1];
+      wq *= gw[rem % nq1] * h;
+      rem /= nq1;
+    }
+    tabulate(r, d, xi, h, s);
+    tabulate(r - 1, d, xi, h, p);
+    for (int b = 0; b < ns; ++b)
+      for (int a = 0; a < ns; ++a) {
+        double mass = wq * s.v[a] * s.v[b];
+        double gg = 0.0;
+        for (int j = 0; j < d; ++j) gg += s.g[a * 3 + j] * s.g[b * 3 + j];
+        for (int e = 0; e < d; ++e) {
+          C.Mrho[size_t(d * b + e) * nv + d * a + e] += m.rho * mass;
+          for (int c = 0; c < d; ++c) {
+            // sigma(phi_a e_c) : eps(phi_b e_e) = mu (delta_ce grad a.grad b + d_e a d_c b) + lam d_c a d_e b
+            double val = mu * ((c == e ? gg : 0.0) + s.g[a * 3 + e] * s.g[b * 3 + c]) +
+                         lam * s.g[a * 3 + c] * s.g[b * 3 + e];
+            C.Avol[size_t(d * b + e) * nv + d * a + c] += wq * val;
+          }
+        }
+      }
+    for (int t = 0; t < np; ++t) {
+      for (int a = 0; a < ns; ++a)
+        for (int c = 0; c < d; ++c) C.Cvol[size_t(t) * nv + d * a + c] += -m.alpha * wq * s.g[a * 3 + c] * p.v[t];
+      for (int u = 0; u < np; ++u) {
+        double gg = 0.0;
+        for (int j = 0; j < d; ++j) gg += p.g[u * 3 + j] * p.g[t * 3 + j];
+        C.Bvol[size_t(t) * np + u] += wq * gg;
+        C.Mp[size_t(t) * np + u] += wq * p.v[u] * p.v[t];
+      }
+    }
+  }
+  // boundary faces
+  int nqf = 1;
+  for (int a = 0; a < d - 1; ++a) nqf *= nq1;
+  for (int axis = 0; axis < d; ++axis)
+    for (int side = 0; side < 2; ++side) {
+      int f = 2 * axis + side;
+      auto& Af = C.Aface[f];
+      auto& Cf = C.Cface[f];
+      auto& BK = C.BfaceK[f];
+      auto& Bp = C.Bpen[f];
+      Af.assign(size_t(nv) * nv, 0.0);
+      Cf.assign(size_t(np) * nv, 0.0);
+      BK.assign(size_t(np) * np, 0.0);
+      Bp.assign(size_t(np) * np, 0.0);
+      double nrm[3] = {0, 0, 0};
+      nrm[axis] = side ? 1.0 : -1.0;
+      for (int q = 0; q < nqf; ++q) {
+        double xi[3] = {0, 0, 0}, wq = 1.0;
+        int rem = q;
+        for (int ax = 0; ax < d; ++ax) {
+          if (ax == axis) {
+            xi[ax] = side ? 1.0 : 0.0;
+            continue;
+          }
+          xi[ax] = gx[rem % nq1];
+          wq *= gw[rem % nq1] * h;
+          rem /= nq1;
+        }
+        tabulate(r, d, xi, h, s);
+        tabulate(r - 1, d, xi, h, p);
+        for (int b = 0; b < ns; ++b)
+          for (int a = 0; a < ns; ++a) {
+            double dna = 0.0, dnb = 0.0;
+            for (int j = 0; j < d; ++j) {
+              dna += s.g[a * 3 + j] * nrm[j];
+              dnb += s.g[b * 3 + j] * nrm[j];
+            }
+            for (int e = 0; e < d; ++e)
+              for (int c = 0; c < d; ++c) {
+                // traction of w = phi_a e_c: (sigma n)_i = mu(delta_ic d_n a + d_i a n_c) + lam d_c a n_i
+                double tw_e = mu * ((e == c ? dna : 0.0) + s.g[a * 3 + e] * nrm[c]) + lam * s.g[a * 3 + c] * nrm[e];
+                double tc_c = mu * ((c == e ? dnb : 0.0) + s.g[b * 3 + c] * nrm[e]) + lam * s.g[b * 3 + e] * nrm[c];
+                double val = -tw_e * s.v[b] - s.v[a] * tc_c;
+                if (c == e) val += C.gamma_a / C.hF * s.v[a] * s.v[b];
+                Af[size_t(d * b + e) * nv + d * a + c] += wq * val;
+              }
+          }
+        for (int t = 0; t < np; ++t) {
+          for (int a = 0; a < ns; ++a)
+            for (int c = 0; c < d; ++c) Cf[size_t(t) * nv + d * a + c] += m.alpha * wq * s.v[a] * nrm[c] * p.v[t];
+          double dnt = 0.0;
+          for (int j = 0; j < d; ++j) dnt += p.g[t * 3 + j] * nrm[j];
+          for (int u = 0; u < np; ++u) {
+            double dnu = 0.0;
+            for (int j = 0; j < d; ++j) dnu += p.g[u * 3 + j] * nrm[j];
+            BK[size_t(t) * np + u] += wq * (-dnu * p.v[t] - p.v[u] * dnt);
+            Bp[size_t(t) * np + u] += wq * C.gamma_b / C.hF * p.v[u] * p.v[t];
+          }
+        }
+      }
+    }
+  return C;
+}
+
+// ------------------------------------------------------------- level assembly
+namespace {
+
+struct Entry {
+  int64_t col;
+  double val;
+};
+
+struct RowBuilder {
+  const BuildOptions* o;
+  const CellMats* cm;
+  const LevelHost* L;
+  const Material* m;
+
+  // cells touching lattice point g (per axis) for a degree-p lattice; local index
+  int cells_axis(int64_t g, int p, int N, int* cells, int* loc) const {
+    int cnt = 0;
+    if (g % p == 0) {
+      int64_t c = g / p;
+      if (c - 1 >= 0) {
+        cells[cnt] = int(c - 1);
+        loc[cnt++] = p;
+      }
+      if (c < N) {
+        cells[cnt] = int(c);
+        loc[cnt++] = 0;
+      }
+    } else {
+      cells[cnt] = int(g / p);
+      loc[cnt++] = int(g % p);
+    }
+    return cnt;
+  }
+
+  // global lattice index of local node a of cell (cx,cy,cz) for degree p
+  int64_t gnode(const int* cc, int a, int p, int64_t n1) const {
+    int d = o->d;
+    int64_t g = 0;
+    int idx[3];
+    int rem = a;
+    for (int ax = 0; ax < d; ++ax) {
+      idx[ax] = rem % (p + 1);
+      rem /= (p + 1);
+    }
+    for (int ax = d - 1; ax >= 0; --ax) g = g * n1 + (int64_t(p) * cc[ax] + idx[ax]);
+    return g;
+  }
+
+  static void sort_merge(std::vector<Entry>& v) {
+    std::sort(v.begin(), v.end(), [](const Entry& a, const Entry& b) { return a.col < b.col; });
+    size_t w = 0;
+    for (size_t i = 0; i < v.size(); ++i) {
+      if (w > 0 && v[w - 1].col == v[i].col)
+        v[w - 1].val += v[i].val;
+      else
+        v[w++] = v[i];
+    }
+    v.resize(w);
+  }
+
+  // Spatial row i of MM and KK (sorted, merged).
+  void row(int64_t i, std::vector<Entry>& mm, std::vector<Entry>& kk) const {
+    mm.clear();
+    kk.clear();
+    const int d = o->d, r = o->r, N = o->N;
+    const int64_t nv = L->nv;
+    const int nlv = cm->nlv, nls = cm->nls, nlp = cm->nlp;
+    if (i < 2 * nv) {
+      const int field = i < nv ? 0 : 1;  // 0: u-equation, 1: v-equation
+      const int64_t iv = i - field * nv;
+      const int64_t node = iv / d;
+      const int comp = int(iv % d);
+      int64_t g[3];
+      int64_t rem = node;
+      for (int ax = 0; ax < d; ++ax) {
+        g[ax] = rem % L->n1;
+        rem /= L->n1;
+      }
+      int cl[3][2], ll[3][2], cn[3];
+      for (int ax = 0; ax < d; ++ax) cn[ax] = cells_axis(g[ax], r, N, cl[ax], ll[ax]);
+      int combos = 1;
+      for (int ax = 0; ax < d; ++ax) combos *= cn[ax];
+      for (int cb = 0; cb < combos; ++cb) {
+        int cc[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, t = cb;
+        for (int ax = 0; ax < d; ++ax) {
+          cc[ax] = cl[ax][t % cn[ax]];
+          lo[ax] = ll[ax][t % cn[ax]];
+          t /= cn[ax];
+        }
+        int a_test = 0;
+        for (int ax = d - 1; ax >= 0; --ax) a_test = a_test * (r + 1) + lo[ax];
+        const int bt = d * a_test + comp;  // local vector test index
+        int64_t cell = 0;
+        for (int ax = d - 1; ax >= 0; --ax) cell = cell * N + cc[ax];
+        const double K = L->Kcell[cell];
+        // boundary faces of this cell
+        int faces[6], nf = 0;
+        for (int ax = 0; ax < d; ++ax) {
+          if (cc[ax] == 0) faces[nf++] = 2 * ax;
+          if (cc[ax] == N - 1) faces[nf++] = 2 * ax + 1;
+        }
+        (void)K;
+        for (int a = 0; a < nls; ++a) {
+          const int64_t gn = gnode(cc, a, r, L->n1);
+          for (int c = 0; c < d; ++c) {
+            const int at = d * a + c;
+            const int64_t gcol = d * gn + c;
+            const double mr = cm->Mrho[size_t(bt) * nlv + at];
+            if (field == 0) {
+              if (mr != 0.0) {
+                mm.push_back({nv + gcol, mr});   // M_rho on U
+                kk.push_back({gcol, -mr});       // -M_rho on V
+              }
+            } else {
+              if (mr != 0.0) mm.push_back({gcol, mr});  // M_rho on V
+              double av = cm->Avol[size_t(bt) * nlv + at];
+              for (int f = 0; f < nf; ++f) av += cm->Aface[faces[f]][size_t(bt) * nlv + at];
+              kk.push_back({nv + gcol, av});  // A_gamma on U
+            }
+          }
+        }
+        if (field == 1) {
+          for (int s = 0; s < nlp; ++s) {
+            // (C^T)[i][s] = C(psi_i, xi_s): stored as Cvol[s][i]
+            double cv = cm->Cvol[size_t(s) * nlv + bt];
+            for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(s) * nlv + bt];
+            kk.push_back({2 * nv + gnode(cc, s, r - 1, L->n1p), cv});
+          }
+        }
+      }
+    } else {
+      const int64_t node = i - 2 * nv;
+      int64_t g[3];
+      int64_t rem = node;
+      for (int ax = 0; ax < d; ++ax) {
+        g[ax] = rem % L->n1p;
+        rem /= L->n1p;
+      }
+      int cl[3][2], ll[3][2], cn[3];
+      for (int ax = 0; ax < d; ++ax) cn[ax] = cells_axis(g[ax], r - 1, N, cl[ax], ll[ax]);
+      int combos = 1;
+      for (int ax = 0; ax < d; ++ax) combos *= cn[ax];
+      for (int cb = 0; cb < combos; ++cb) {
+        int cc[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, t = cb;
+        for (int ax = 0; ax < d; ++ax) {
+          cc[ax] = cl[ax][t % cn[ax]];
+          lo[ax] = ll[ax][t % cn[ax]];
+          t /= cn[ax];
+        }
+        int st = 0;
+        for (int ax = d - 1; ax >= 0; --ax) st = st * r + lo[ax];
+        int64_t cell = 0;
+        for (int ax = d - 1; ax >= 0; --ax) cell = cell * N + cc[ax];
+        const double K = L->Kcell[cell];
+        int faces[6], nf = 0;
+        for (int ax = 0; ax < d; ++ax) {
+          if (cc[ax] == 0) faces[nf++] = 2 * ax;
+          if (cc[ax] == N - 1) faces[nf++] = 2 * ax + 1;
+        }
+        // -C(v, psi_st) on V
+        for (int a = 0; a < nls; ++a) {
+          const int64_t gn = gnode(cc, a, r, L->n1);
+          for (int c = 0; c < d; ++c) {
+            const int at = d * a + c;
+            double cv = cm->Cvol[size_t(st) * nlv + at];
+            for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(st) * nlv + at];
+            kk.push_back({d * gn + c, -cv});
+          }
+        }
+        for (int s = 0; s < nlp; ++s) {
+          const int64_t gp = 2 * nv + gnode(cc, s, r - 1, L->n1p);
+          mm.push_back({gp, m->c0 * cm->Mp[size_t(st) * nlp + s]});
+          double bv = K * cm->Bvol[size_t(st) * nlp + s];
+          for (int f = 0; f < nf; ++f)
+            bv += K * cm->BfaceK[faces[f]][size_t(st) * nlp + s] + cm->Bpen[faces[f]][size_t(st) * nlp + s];
+          kk.push_back({gp, bv});
+        }
+      }
+    }
+    sort_merge(mm);
+    sort_merge(kk);
+  }
+};
+
+}  // namespace
+
+void build_level(const BuildOptions& o, const Material& m, const std::vector<double>& Kcell, LevelHost& L,
+                 int nthreads) {
+  L.d = o.d;
+  L.r = o.r;
+  L.k = o.k;
+  L.N = o.N;
+  const int d = o.d, r = o.r, k = o.k, N = o.N;
+  L.n1 = int64_t(r) * N + 1;
+  L.n1p = int64_t(r - 1) * N + 1;
+  L.nQ = 1;
+  L.nP = 1;
+  for (int a = 0; a < d; ++a) {
+    L.nQ *= L.n1;
+    L.nP *= L.n1p;
+  }
+  L.nv = d * L.nQ;
+  L.ns = 2 * L.nv + L.nP;
+  L.n = (k + 1) * L.ns;
+  L.Kcell = Kcell;
+  const double h = 1.0 / N;
+  CellMats cm = make_cell_mats(d, r, h, m);
+  TimeConsts T = make_time_consts(k, o.tau);
+  RowBuilder rb{&o, &cm, &L, &m};
+  const int64_t ns = L.ns;
+  const int nt = k + 1;
+
+  // pass 1: space-time row lengths
+  std::vector<int64_t> slen(ns);  // length of one space-time row for spatial row i (same for every b)
+  std::vector<int64_t> mmlen(ns);
+  parallel_for(ns, nthreads, [&](int64_t lo, int64_t hi) {
+    std::vector<Entry> mm, kk;
+    for (int64_t i = lo; i < hi; ++i) {
+      rb.row(i, mm, kk);
+      // union of MM and KK columns for the diagonal time block
+      size_t a = 0, b = 0, u = 0;
+      while (a < mm.size() || b < kk.size()) {
+        if (b >= kk.size() || (a < mm.size() && mm[a].col < kk[b].col))
+          ++a;
+        else if (a >= mm.size() || kk[b].col < mm[a].col)
+          ++b;
+        else {
+          ++a;
+          ++b;
+        }
+        ++u;
+      }
+      slen[i] = int64_t(k) * int64_t(mm.size()) + int64_t(u);
+      mmlen[i] = int64_t(mm.size());
+    }
+  });
+  L.A.nrows = L.n;
+  L.A.ncols = L.n;
+  L.A.ptr.assign(L.n + 1, 0);
+  for (int b = 0; b < nt; ++b)
+    for (int64_t i = 0; i < ns; ++i) L.A.ptr[b * ns + i + 1] = slen[i];
+  for (int64_t i = 0; i < L.n; ++i) L.A.ptr[i + 1] += L.A.ptr[i];
+  const int64_t nnz = L.A.ptr[L.n];
+  if (nnz > INT64_C(4000000000)) throw std::runtime_error("level operator too large");
+  L.A.col.resize(nnz);
+  L.A.val.resize(nnz);
+  if (o.need_MM) {
+    L.MM.nrows = ns;
+    L.MM.ncols = ns;
+    L.MM.ptr.assign(ns + 1, 0);
+    for (int64_t i = 0; i < ns; ++i) L.MM.ptr[i + 1] = L.MM.ptr[i] + mmlen[i];
+    L.MM.col.resize(L.MM.ptr[ns]);
+    L.MM.val.resize(L.MM.ptr[ns]);
+  }
+  // pass 2: fill
+  parallel_for(ns, nthreads, [&](int64_t lo, int64_t hi) {
+    std::vector<Entry> mm, kk;
+    for (int64_t i = lo; i < hi; ++i) {
+      rb.row(i, mm, kk);
+      if (o.need_MM) {
+        int64_t p = L.MM.ptr[i];
+        for (auto& e : mm) {
+          L.MM.col[p] = int32_t(e.col);
+          L.MM.val[p++] = e.val;
+        }
+      }
+      for (int b = 0; b < nt; ++b) {
+        int64_t p = L.A.ptr[b * ns + i];
+        for (int a = 0; a < nt; ++a) {
+          const double D = T.Dt[b * nt + a];
+          const int64_t off = int64_t(a) * ns;
+          if (a != b) {
+            for (auto& e : mm) {
+              L.A.col[p] = int32_t(off + e.col);
+              L.A.val[p++] = D * e.val;
+            }
+          } else {
+            const double mt = T.mt[b];
+            size_t x = 0, y = 0;
+            while (x < mm.size() || y < kk.size()) {
+              if (y >= kk.size() || (x < mm.size() && mm[x].col < kk[y].col)) {
+                L.A.col[p] = int32_t(off + mm[x].col);
+                L.A.val[p++] = D * mm[x].val;
+                ++x;
+              } else if (x >= mm.size() || kk[y].col < mm[x].col) {
+                L.A.col[p] = int32_t(off + kk[y].col);
+                L.A.val[p++] = mt * kk[y].val;
+                ++y;
+              } else {
+                L.A.col[p] = int32_t(off + mm[x].col);
+                L.A.val[p++] = D * mm[x].val + mt * kk[y].val;
+                ++x;
+                ++y;
+              }
+            }
+          }
+        }
+      }
+    }
+  });
+
+  if (!o.need_patches) return;
+  // ------------------------------------------------------------ patches
+  // vertex patch at grid vertex v: the cells with c in {v-1, v} (per axis) that exist;
+  // cell patch: the cell itself.  Closure node boxes per axis.
+  const int64_t nverts = o.patch_kind == 1 ? [&] {
+    int64_t t = 1;
+    for (int a = 0; a < d; ++a) t *= (N + 1);
+    return t;
+  }()
+                                           : 0;
+  int64_t ncells = 1;
+  for (int a = 0; a < d; ++a) ncells *= N;
+  L.npatch = o.patch_kind == 1 ? nverts : ncells;
+  auto patch_box = [&](int64_t pidx, int* cmin, int* cmax) {
+    int64_t rem = pidx;
+    const int base = o.patch_kind == 1 ? N + 1 : N;
+    for (int ax = 0; ax < d; ++ax) {
+      int v = int(rem % base);
+      rem /= base;
+      if (o.patch_kind == 1) {
+        cmin[ax] = std::max(v - 1, 0);
+        cmax[ax] = std::min(v, N - 1);
+      } else {
+        cmin[ax] = cmax[ax] = v;
+      }
+    }
+  };
+  L.poff.assign(L.npatch + 1, 0);
+  for (int64_t pi = 0; pi < L.npatch; ++pi) {
+    int cmin[3], cmax[3];
+    patch_box(pi, cmin, cmax);
+    int64_t q = 1, pp = 1;
+    for (int ax = 0; ax < d; ++ax) {
+      q *= int64_t(r) * (cmax[ax] + 1 - cmin[ax]) + 1;
+      pp *= int64_t(r - 1) * (cmax[ax] + 1 - cmin[ax]) + 1;
+    }
+    L.poff[pi + 1] = L.poff[pi] + nt * (2 * d * q + pp);
+  }
+  L.pdof.resize(L.poff[L.npatch]);
+  parallel_for(L.npatch, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t pi = lo; pi < hi; ++pi) {
+      int cmin[3] = {0, 0, 0}, cmax[3] = {0, 0, 0};
+      patch_box(pi, cmin, cmax);
+      int64_t w = L.poff[pi];
+      int lo3[3] = {0, 0, 0}, hi3[3] = {0, 0, 0}, lop[3] = {0, 0, 0}, hip3[3] = {0, 0, 0};
+      for (int ax = 0; ax < 3; ++ax) {
+        if (ax < d) {
+          lo3[ax] = r * cmin[ax];
+          hi3[ax] = r * (cmax[ax] + 1);
+          lop[ax] = (r - 1) * cmin[ax];
+          hip3[ax] = (r - 1) * (cmax[ax] + 1);
+        }
+      }
+      for (int tn = 0; tn < nt; ++tn) {
+        const int64_t off = int64_t(tn) * ns;
+        for (int field = 0; field < 2; ++field)
+          for (int z = lo3[2]; z <= hi3[2]; ++z)
+            for (int y = lo3[1]; y <= hi3[1]; ++y)
+              for (int x = lo3[0]; x <= hi3[0]; ++x) {
+                int64_t node = x + L.n1 * (y + L.n1 * int64_t(z));
+                for (int c = 0; c < d; ++c) L.pdof[w++] = int32_t(off + field * L.nv + d * node + c);
+              }
+        for (int z = lop[2]; z <= hip3[2]; ++z)
+          for (int y = lop[1]; y <= hip3[1]; ++y)
+            for (int x = lop[0]; x <= hip3[0]; ++x)
+              L.pdof[w++] = int32_t(off + 2 * L.nv + x + L.n1p * (y + L.n1p * int64_t(z)));
+      }
+    }
+  });
+  // transposed map and weights (deterministic: patches in increasing order)
+  L.tptr.assign(L.n + 1, 0);
+  for (int64_t t = 0; t < int64_t(L.pdof.size()); ++t) L.tptr[L.pdof[t] + 1]++;
+  for (int64_t i = 0; i < L.n; ++i) L.tptr[i + 1] += L.tptr[i];
+  L.tidx.resize(L.pdof.size());
+  {
+    std::vector<int64_t> fill(L.tptr.begin(), L.tptr.end() - 1);
+    for (int64_t t = 0; t < int64_t(L.pdof.size()); ++t) L.tidx[fill[L.pdof[t]]++] = t;
+  }
+  L.winv.resize(L.n);
+  for (int64_t i = 0; i < L.n; ++i) {
+    int64_t c = L.tptr[i + 1] - L.tptr[i];
+    if (c == 0) throw std::runtime_error("dof not covered by any patch");
+    L.winv[i] = o.omega / double(c);
+  }
+}
+
+// ------------------------------------------------------------- transfers
+namespace {
+// 1D interpolation weights of the coarse Q_p basis at fine lattice point g.
+int interp_weights_1d(int p, int Nc, int64_t g, int64_t* cols, double* w) {
+  int64_t c = g / (2 * p);
+  if (c > Nc - 1) c = Nc - 1;
+  double xi = double(g - 2 * p * c) / (2.0 * p);
+  double v[8];
+  lagrange01(p, xi, v, nullptr);
+  int cnt = 0;
+  for (int a = 0; a <= p; ++a)
+    if (std::fabs(v[a]) > 1e-13) {
+      cols[cnt] = int64_t(p) * c + a;
+      w[cnt++] = v[a];
+    }
+  return cnt;
+}
+}  // namespace
+
+Csr build_prolongation(const LevelHost& C, const LevelHost& F) {
+  const int d = F.d, r = F.r, nt = F.k + 1;
+  Csr P;
+  P.nrows = F.n;
+  P.ncols = C.n;
+  P.ptr.assign(F.n + 1, 0);
+  // rows in order; build row by row
+  std::vector<int64_t> cols;
+  std::vector<double> vals;
+  auto emit_scalar = [&](int p, int64_t fnode, int64_t fn1, int64_t cn1, int64_t base_col, int stride, int comp) {
+    int64_t g[3], rem = fnode;
+    for (int ax = 0; ax < d; ++ax) {
+      g[ax] = rem % fn1;
+      rem /= fn1;
+    }
+    int64_t c1[3][8];
+    double w1[3][8];
+    int n1[3] = {1, 1, 1};
+    for (int ax = 0; ax < d; ++ax) n1[ax] = interp_weights_1d(p, C.N, g[ax], c1[ax], w1[ax]);
+    // columns ascending: z outer, x inner
+    for (int iz = 0; iz < (d > 2 ? n1[2] : 1); ++iz)
+      for (int iy = 0; iy < (d > 1 ? n1[1] : 1); ++iy)
+        for (int ix = 0; ix < n1[0]; ++ix) {
+          int64_t node = c1[0][ix];
+          double w = w1[0][ix];
+          if (d > 1) {
+            node += cn1 * c1[1][iy];
+            w *= w1[1][iy];
+          }
+          if (d > 2) {
+            node += cn1 * cn1 * c1[2][iz];
+            w *= w1[2][iz];
+          }
+          cols.push_back(base_col + stride * node + comp);
+          vals.push_back(w);
+        }
+  };
+  for (int64_t row = 0; row < F.n; ++row) {
+    const int tn = int(row / F.ns);
+    const int64_t s = row % F.ns;
+    const int64_t coff = int64_t(tn) * C.ns;
+    if (s < 2 * F.nv) {
+      const int field = s < F.nv ? 0 : 1;
+      const int64_t iv = s - field * F.nv;
+      emit_scalar(r, iv / d, F.n1, C.n1, coff + field * C.nv, d, int(iv % d));
+    } else {
+      emit_scalar(r - 1, s - 2 * F.nv, F.n1p, C.n1p, coff + 2 * C.nv, 1, 0);
+    }
+    P.ptr[row + 1] = int64_t(cols.size());
+  }
+  P.col.resize(cols.size());
+  for (size_t i = 0; i < cols.size(); ++i) P.col[i] = int32_t(cols[i]);
+  P.val = std::move(vals);
+  (void)nt;
+  return P;
+}
+
+Csr transpose(const Csr& a, int64_t ncols_out) {
+  Csr t;
+  t.nrows = a.ncols;
+  t.ncols = ncols_out;
+  t.ptr.assign(a.ncols + 1, 0);
+  for (auto c : a.col) t.ptr[c + 1]++;
+  for (int64_t i = 0; i < a.ncols; ++i) t.ptr[i + 1] += t.ptr[i];
+  t.col.resize(a.col.size());
+  t.val.resize(a.val.size());
+  std::vector<int64_t> fill(t.ptr.begin(), t.ptr.end() - 1);
+  for (int64_t row = 0; row < a.nrows; ++row)
+    for (int64_t p = a.ptr[row]; p < a.ptr[row + 1]; ++p) {
+      int64_t q = fill[a.col[p]]++;
+      t.col[q] = int32_t(row);
+      t.val[q] = a.val[p];
+    }
+  return t;
+}
+
+// ------------------------------------------------------------- built-in solution
+// u_i = S sin t, v_i = S cos t, p = S cos t, S = prod_j sin(pi x_j).
+// f_i = rho u_tt - div sigma(u) + alpha d_i p
+//     = [-rho S + mu d pi^2 S - (mu + lambda) sum_c d_i d_c S] sin t + alpha d_i S cos t
+// g   = c0 p_t + alpha div v - K lap p = -c0 S sin t + alpha sum_c d_c S cos t + K d pi^2 S cos t
+void source_vector(const LevelHost& L, const Material& m, double t, std::vector<double>& out) {
+  const int d = L.d, r = L.r, N = L.N;
+  const double h = 1.0 / N;
+  out.assign(L.ns, 0.0);
+  std::vector<double> gx, gw;
+  gauss_legendre01(r + 2, gx, gw);
+  const int nq1 = r + 2;
+  int nq = 1;
+  for (int a = 0; a < d; ++a) nq *= nq1;
+  // tabulate once (reference coordinates are identical in every cell)
+  std::vector<Tab> ts(nq), tp(nq);
+  std::vector<double> wq(nq);
+  std::vector<std::array<double, 3>> xq(nq);
+  for (int q = 0; q < nq; ++q) {
+    double xi[3] = {0, 0, 0}, w = 1.0;
+    int rem = q;
+    for (int ax = 0; ax < d; ++ax) {
+      xi[ax] = gx[rem % nq1];
+      w *= gw[rem % nq1] * h;
+      rem /= nq1;
+    }
+    tabulate(r, d, xi, h, ts[q]);
+    tabulate(r - 1, d, xi, h, tp[q]);
+    wq[q] = w;
+    xq[q] = {xi[0], xi[1], xi[2]};
+  }
+  const double st = std::sin(t), ct = std::cos(t), pi = M_PI;
+  int64_t ncells = 1;
+  for (int a = 0; a < d; ++a) ncells *= N;
+  const int nls = ts[0].nl, nlp = tp[0].nl;
+  for (int64_t cell = 0; cell < ncells; ++cell) {
+    int cc[3] = {0, 0, 0};
+    int64_t rem = cell;
+    for (int ax = 0; ax < d; ++ax) {
+      cc[ax] = int(rem % N);
+      rem /= N;
+    }
+    const double K = L.Kcell[cell];
+    for (int q = 0; q < nq; ++q) {
+      double sn[3] = {1, 1, 1}, cs[3] = {0, 0, 0};
+      for (int ax = 0; ax < d; ++ax) {
+        double x = (cc[ax] + xq[q][ax]) * h;
+        sn[ax] = std::sin(pi * x);
+        cs[ax] = std::cos(pi * x);
+      }
+      double S = 1.0, dS[3], ddS[3][3];
+      for (int ax = 0; ax < d; ++ax) S *= sn[ax];
+      for (int i = 0; i < d; ++i) {
+        dS[i] = pi * cs[i];
+        for (int j = 0; j < d; ++j)
+          if (j != i) dS[i] *= sn[j];
+        for (int j = 0; j < d; ++j) {
+          if (i == j) {
+            ddS[i][j] = -pi * pi * S;
+          } else {
+            double v = pi * pi * cs[i] * cs[j];
+            for (int l = 0; l < d; ++l)
+              if (l != i && l != j) v *= sn[l];
+            ddS[i][j] = v;
+          }
+        }
+      }
+      double f[3];
+      for (int i = 0; i < d; ++i) {
+        double sum = 0.0;
+        for (int c = 0; c < d; ++c) sum += ddS[i][c];
+        f[i] = (-m.rho * S + m.mu * d * pi * pi * S - (m.mu + m.lambda) * sum) * st + m.alpha * dS[i] * ct;
+      }
+      double divS = 0.0;
+      for (int c = 0; c < d; ++c) divS += dS[c];
+      const double g = -m.c0 * S * st + m.alpha * divS * ct + K * d * pi * pi * S * ct;
+      for (int a = 0; a < nls; ++a) {
+        int64_t gn = 0;
+        int idx[3], rm = a;
+        for (int ax = 0; ax < d; ++ax) {
+          idx[ax] = rm % (r + 1);
+          rm /= (r + 1);
+        }
+        for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1 + (int64_t(r) * cc[ax] + idx[ax]);
+        for (int c = 0; c < d; ++c) out[L.nv + d * gn + c] += wq[q] * ts[q].v[a] * f[c];
+      }
+      for (int s = 0; s < nlp; ++s) {
+        int64_t gn = 0;
+        int idx[3], rm = s;
+        for (int ax = 0; ax < d; ++ax) {
+          idx[ax] = rm % r;
+          rm /= r;
+        }
+        for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1p + (int64_t(r - 1) * cc[ax] + idx[ax]);
+        out[2 * L.nv + gn] += wq[q] * tp[q].v[s] * g;
+      }
+    }
+  }
+}
+
+void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out) {
+  const int d = L.d;
+  out.assign(L.ns, 0.0);
+  auto S_at = [&](int64_t node, int64_t n1, int p) {
+    double S = 1.0;
+    int64_t rem = node;
+    for (int ax = 0; ax < d; ++ax) {
+      double x = double(rem % n1) / (double(p) * L.N);
+      rem /= n1;
+      S *= std::sin(M_PI * x);
+    }
+    return S;
+  };
+  for (int64_t q = 0; q < L.nQ; ++q) {
+    double S = S_at(q, L.n1, L.r);
+    for (int c = 0; c < d; ++c) {
+      out[d * q + c] = S * std::cos(t);
+      out[L.nv + d * q + c] = S * std::sin(t);
+    }
+  }
+  for (int64_t q = 0; q < L.nP; ++q) out[2 * L.nv + q] = S_at(q, L.n1p, L.r - 1) * std::cos(t);
+}
+
+}  // namespace stgmg

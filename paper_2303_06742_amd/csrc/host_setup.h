@@ -1,0 +1,81 @@
+// Host-side construction of the level hierarchy: time constants, element
+// integrals, space-time operators in CSR, patch tables and grid transfers.
+// Plain C++17, no HIP; the device side only uploads what is built here.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace stgmg {
+
+struct Material {
+  double rho, lambda, mu, alpha, c0;
+};
+
+// dG(k) on one slab: right Gauss-Radau nodes/weights on [-1,1], Lagrange basis
+// at those nodes; Dt[b*(k+1)+a] (row b = test), mt[b] = tau/2 w_b (diagonal
+// M^t), e[b] = chi_b(-1).
+struct TimeConsts {
+  int k = 0;
+  double tau = 0;
+  std::vector<double> x, w, Dt, mt, e;
+};
+TimeConsts make_time_consts(int k, double tau);
+
+// Element and boundary-face matrices of one cell [0,h]^d, indexed [test][trial]
+// row-major.  Vector local index = d*a + c (a = lexicographic local node).
+struct CellMats {
+  int d = 0, r = 0;
+  int nls = 0, nlv = 0, nlp = 0;  // local scalar Q_r, vector, Q_{r-1} counts
+  double gamma_a = 0, gamma_b = 0, hF = 0;
+  std::vector<double> Mrho, Avol, Cvol, Bvol, Mp;  // Cvol: [p-test][v-trial]
+  std::vector<double> Aface[6], Cface[6], BfaceK[6], Bpen[6];  // face = 2*axis + side
+};
+CellMats make_cell_mats(int d, int r, double h, const Material& m);
+
+struct Csr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+struct LevelHost {
+  int d = 0, r = 0, k = 0, N = 0;
+  int64_t n1 = 0, n1p = 0;  // lattice points per axis, Q_r and Q_{r-1}
+  int64_t nQ = 0, nP = 0, nv = 0, ns = 0, n = 0;
+  std::vector<double> Kcell;
+  Csr A;   // space-time operator D^t (x) MM + M^t (x) KK
+  Csr MM;  // spatial MM (finest level only, used for the jump term of the rhs)
+  // patches: dofs of patch p are pdof[poff[p] .. poff[p+1]) in increasing order
+  int64_t npatch = 0;
+  std::vector<int64_t> poff;
+  std::vector<int32_t> pdof;
+  // averaged scatter: entries of dof mu are at positions tidx[tptr[mu]..tptr[mu+1]) of pdof
+  std::vector<int64_t> tptr;
+  std::vector<int64_t> tidx;
+  std::vector<double> winv;  // omega / (number of patches containing mu)
+};
+
+struct BuildOptions {
+  int d, r, k, N;
+  int patch_kind;  // 0 cell, 1 vertex
+  double tau, omega;
+  bool need_patches;
+  bool need_MM;
+};
+
+// Assemble one level.  Kcell: per-cell K (N^d values).
+void build_level(const BuildOptions& o, const Material& m, const std::vector<double>& Kcell, LevelHost& L,
+                 int nthreads);
+
+// Space-time prolongation from the coarse level to the next finer one.
+Csr build_prolongation(const LevelHost& coarse, const LevelHost& fine);
+Csr transpose(const Csr& a, int64_t ncols_out);
+
+// Built-in prescribed solution u_i = S sin t, p = S cos t, S = prod sin(pi x_j):
+// source vector S(t) of one time node (u-eq rows zero), and nodal interpolant.
+void source_vector(const LevelHost& L, const Material& m, double t, std::vector<double>& out);
+void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out);
+
+}  // namespace stgmg

@@ -1,0 +1,41 @@
+// Launch wrappers of the HIP kernels in kernels.hip (all enqueue on `st`).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace stgmg {
+
+// mode 0: y = A x; 1: y = b - A x; 2: y += A x.  lanes = CSR lanes per row (4..64).
+void k_csr(hipStream_t st, int mode, int64_t nrows, const int64_t* ptr, const int32_t* col, const double* val,
+           const double* x, const double* b, double* y, int lanes);
+void k_fill_zero(hipStream_t st, double* a, int64_t n);
+void k_patch_extract_t(hipStream_t st, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                       const int32_t* pdof, const int64_t* ptr, const int32_t* col, const double* val,
+                       const int64_t* woff, double* W);
+size_t gj_lds_bytes(int max_np, int nb);
+int gj_panel_width(int max_np, size_t lds_limit);
+void k_gj_invert_f64(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                     const int64_t* woff, double* W, const int64_t* ooff, double* out, int32_t* status);
+void k_gj_invert_f32(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                     const int64_t* woff, double* W, const int64_t* ooff, float* out, int32_t* status);
+void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+                       const int64_t* ioff, const double* inv, const double* r, double* y);
+void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+                       const int64_t* ioff, const float* inv, const double* r, double* y);
+void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
+                    const double* y, double* d);
+void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* y);
+int dot_blocks(int64_t n);
+// out[v] (+)= V_v . w for v < m (V rows of length n, leading dimension ldv); partials >= m * dot_blocks(n)
+void k_multi_dot(hipStream_t st, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials,
+                 double* out, int accumulate);
+void k_multi_axpy(hipStream_t st, const double* V, int64_t ldv, int m, const double* h, double sign, double* w,
+                  int64_t n);
+void k_scale_copy(hipStream_t st, const double* src, const double* nrm2, double* dst, int64_t n);
+void k_axpby(hipStream_t st, double a, const double* x, double b, const double* y, double* out, int64_t n);
+void k_slab_rhs(hipStream_t st, int nt, int64_t ns, const double* e, const double* mmx, const double* src,
+                double* rhs);
+
+}  // namespace stgmg

@@ -1,0 +1,525 @@
+// HIP kernels for gfx950 (CDNA4, wave64) of the GMRES-GMG slab solver.
+//
+//   csr_residual       r = b - A x  or  y = A x      (level operator, Eq:DefAn)
+//   csr_accumulate     y += A x                       (prolongation, Sec. 4)
+//   patch_extract_t    A_P^T into a dense work buffer (Def:VankaOP, A_P = A[Z_P, Z_P])
+//   gj_invert          blocked Gauss-Jordan inverse with scaled partial pivoting
+//   patch_apply        y_P = A_P^{-1} R_P r           (stored inverses, FP64 or FP32)
+//   vanka_update       d += omega/p * sum_P E_P y_P   (Alg. 4.1, atomics-free pull)
+//   dense_gemv_t       coarse solve with the stored inverse
+//   dot_partials / reduce_partials / multi_axpy / scale_copy: FGMRES BLAS-1, fixed
+//                      reduction order (bitwise reproducible).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace stgmg {
+namespace dev {
+
+constexpr int WAVE = 64;
+
+template <int G>
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+  return v;
+}
+
+// ---------------------------------------------------------------- CSR
+// G lanes per row; BS threads per block.  mode 0: y = A x; mode 1: y = b - A x.
+template <int G, int MODE>
+__global__ void __launch_bounds__(256) csr_kernel(int64_t nrows, const int64_t* __restrict__ ptr,
+                                                  const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                  const double* __restrict__ x, const double* __restrict__ b,
+                                                  double* __restrict__ y) {
+  const int lane = threadIdx.x % G;
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+  if (row >= nrows) return;
+  const int64_t s = ptr[row], e = ptr[row + 1];
+  double acc = 0.0;
+  for (int64_t p = s + lane; p < e; p += G) acc += val[p] * x[col[p]];
+  acc = group_sum<G>(acc);
+  if (lane == 0) {
+    if (MODE == 0) y[row] = acc;
+    if (MODE == 1) y[row] = b[row] - acc;
+    if (MODE == 2) y[row] += acc;
+  }
+}
+
+template <int G, int MODE>
+static void launch_csr(hipStream_t st, int64_t nrows, const int64_t* ptr, const int32_t* col, const double* val,
+                       const double* x, const double* b, double* y) {
+  if (nrows == 0) return;
+  const int bs = 256;
+  const int64_t rows_per_block = bs / G;
+  const int64_t grid = (nrows + rows_per_block - 1) / rows_per_block;
+  hipLaunchKernelGGL((csr_kernel<G, MODE>), dim3(grid), dim3(bs), 0, st, nrows, ptr, col, val, x, b, y);
+}
+
+// ---------------------------------------------------------------- patch extraction
+// One block per patch of the batch: W (row-major n x n) receives A_P^T, i.e.
+// W[mu * n + nu] = A[dof(nu)][dof(mu)].  W must be zero on entry.
+__global__ void __launch_bounds__(256) patch_extract_t_kernel(
+    int64_t p0, const int64_t* __restrict__ poff, const int32_t* __restrict__ pdof, const int64_t* __restrict__ ptr,
+    const int32_t* __restrict__ col, const double* __restrict__ val, const int64_t* __restrict__ woff,
+    double* __restrict__ W) {
+  extern __shared__ int32_t sdof[];
+  const int64_t p = p0 + blockIdx.x;
+  const int64_t o = poff[p];
+  const int n = int(poff[p + 1] - o);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sdof[i] = pdof[o + i];
+  __syncthreads();
+  double* Wp = W + woff[blockIdx.x];
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE, nw = blockDim.x / WAVE;
+  for (int nu = wave; nu < n; nu += nw) {
+    const int64_t g = sdof[nu];
+    for (int64_t q = ptr[g] + lane; q < ptr[g + 1]; q += WAVE) {
+      const int32_t c = col[q];
+      int lo = 0, hi = n - 1;
+      while (lo < hi) {  // first index with sdof >= c
+        int mid = (lo + hi) >> 1;
+        if (sdof[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (sdof[lo] == c) Wp[int64_t(lo) * n + nu] = val[q];
+    }
+  }
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ a, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+    a[i] = 0.0;
+}
+
+// ---------------------------------------------------------------- Gauss-Jordan
+// In-place blocked Gauss-Jordan inversion of the row-major n x n matrix M of
+// this block, with the rows first scaled by powers of two (row equilibration,
+// exact in floating point) and partial pivoting on the scaled matrix.  Panels
+// of NB columns live in LDS; the rest of the matrix is updated by a rank-NB
+// Schur-complement step:  M[:, rest] = [i notin K] M[:, rest] + Pnl[:, K] W,
+// with W = the (swapped) pivot rows of M[:, rest].  The result
+// inv(M) = inv(S M) S, columns un-permuted, is written row-major to out.
+template <typename T, int NB>
+__global__ void __launch_bounds__(256) gj_invert_kernel(int64_t p0, const int64_t* __restrict__ poff,
+                                                        const int64_t* __restrict__ woff, double* __restrict__ W,
+                                                        const int64_t* __restrict__ ooff, T* __restrict__ out,
+                                                        int32_t* __restrict__ status) {
+  extern __shared__ double lds[];
+  const int64_t p = p0 + blockIdx.x;
+  const int n = int(poff[p + 1] - poff[p]);
+  double* M = W + woff[blockIdx.x];
+  double* Pnl = lds;                                   // n * NB
+  double* scl = lds + size_t(n) * NB;                  // n
+  double* red_v = scl + n;                             // 4 waves
+  int* red_i = reinterpret_cast<int*>(red_v + 8);      // 4 waves
+  int* perm = red_i + 8;                               // n
+  int* src = perm + n;                                 // n
+  __shared__ int s_flag;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int wave = tid / WAVE, lane = tid % WAVE, nw = bs / WAVE;
+  if (tid == 0) s_flag = 0;
+  // row equilibration by powers of two
+  for (int i = wave; i < n; i += nw) {
+    double m = 0.0;
+    for (int j = lane; j < n; j += WAVE) m = fmax(m, fabs(M[int64_t(i) * n + j]));
+    for (int off = WAVE / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    const double s = (m > 0.0 && isfinite(m)) ? ldexp(1.0, -ilogb(m)) : 1.0;
+    for (int j = lane; j < n; j += WAVE) M[int64_t(i) * n + j] *= s;
+    if (lane == 0) scl[i] = s;
+  }
+  __syncthreads();
+  for (int k0 = 0; k0 < n; k0 += NB) {
+    const int nb = min(NB, n - k0);
+    for (int t = tid; t < n * nb; t += bs) {
+      const int i = t / nb, c = t % nb;
+      Pnl[i * NB + c] = M[int64_t(i) * n + k0 + c];
+    }
+    __syncthreads();
+    for (int c = 0; c < nb; ++c) {
+      const int k = k0 + c;
+      // pivot search over rows k..n-1 of panel column c (ties: lowest row)
+      double bv = -1.0;
+      int bi = n;
+      for (int i = k + tid; i < n; i += bs) {
+        const double v = fabs(Pnl[i * NB + c]);
+        if (v > bv) {
+          bv = v;
+          bi = i;
+        }
+      }
+      for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        red_v[wave] = bv;
+        red_i[wave] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double v = red_v[0];
+        int ii = red_i[0];
+        for (int w = 1; w < nw; ++w)
+          if (red_v[w] > v || (red_v[w] == v && red_i[w] < ii)) {
+            v = red_v[w];
+            ii = red_i[w];
+          }
+        if (!(v > 0.0) || !isfinite(v) || ii >= n) {
+          s_flag = 1;
+          ii = k;
+        }
+        perm[k] = ii;
+        if (ii != k)
+          for (int cc = 0; cc < nb; ++cc) {
+            const double tmp = Pnl[k * NB + cc];
+            Pnl[k * NB + cc] = Pnl[ii * NB + cc];
+            Pnl[ii * NB + cc] = tmp;
+          }
+        double piv = Pnl[k * NB + c];
+        if (piv == 0.0 || !isfinite(piv)) piv = 1.0;
+        const double rp = 1.0 / piv;
+        Pnl[k * NB + c] = 1.0;
+        for (int cc = 0; cc < nb; ++cc) Pnl[k * NB + cc] *= rp;
+      }
+      __syncthreads();
+      for (int i = tid; i < n; i += bs) {
+        if (i == k) continue;
+        const double f = Pnl[i * NB + c];
+        Pnl[i * NB + c] = 0.0;
+        for (int cc = 0; cc < nb; ++cc) Pnl[i * NB + cc] -= f * Pnl[k * NB + cc];
+      }
+      __syncthreads();
+    }
+    // rest of the matrix: row swaps then the rank-nb update, column-owned by threads
+    for (int j = tid; j < n; j += bs) {
+      if (j >= k0 && j < k0 + nb) continue;
+      double w[NB];
+      for (int c = 0; c < nb; ++c) {
+        const int k = k0 + c, q = perm[k];
+        if (q != k) {
+          const double a = M[int64_t(k) * n + j];
+          M[int64_t(k) * n + j] = M[int64_t(q) * n + j];
+          M[int64_t(q) * n + j] = a;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NB; ++c) w[c] = c < nb ? M[int64_t(k0 + c) * n + j] : 0.0;
+      for (int i = 0; i < n; ++i) {
+        double acc = (i >= k0 && i < k0 + nb) ? 0.0 : M[int64_t(i) * n + j];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc += Pnl[i * NB + c] * w[c];
+        M[int64_t(i) * n + j] = acc;
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < n * nb; t += bs) {
+      const int i = t / nb, c = t % nb;
+      M[int64_t(i) * n + k0 + c] = Pnl[i * NB + c];
+    }
+    __syncthreads();
+  }
+  // column un-permutation: inv(SM) = M * Pi, source column of each output column
+  if (tid == 0) {
+    for (int j = 0; j < n; ++j) src[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+      const int q = perm[k];
+      const int t = src[k];
+      src[k] = src[q];
+      src[q] = t;
+    }
+    if (s_flag) status[p] = 1;
+  }
+  __syncthreads();
+  T* o = out + ooff[p];
+  for (int i = wave; i < n; i += nw)
+    for (int j = lane; j < n; j += WAVE) o[int64_t(i) * n + j] = T(M[int64_t(i) * n + src[j]] * scl[j]);
+}
+
+// ---------------------------------------------------------------- patch apply
+// y_P = A_P^{-1} R_P r for every patch; inverse of patch p stored so that
+// element (i, j) of A_P^{-1} is at inv[ioff[p] + j * n + i].
+template <typename T>
+__global__ void __launch_bounds__(256) patch_apply_kernel(int64_t npatch, const int64_t* __restrict__ poff,
+                                                          const int32_t* __restrict__ pdof,
+                                                          const int64_t* __restrict__ ioff,
+                                                          const T* __restrict__ inv, const double* __restrict__ r,
+                                                          double* __restrict__ y) {
+  extern __shared__ char smem[];
+  T* rl = reinterpret_cast<T*>(smem);
+  const int64_t p = blockIdx.x;
+  const int64_t o = poff[p];
+  const int n = int(poff[p + 1] - o);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) rl[i] = T(r[pdof[o + i]]);
+  __syncthreads();
+  const T* X = inv + ioff[p];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int j = 0;
+    for (; j + 3 < n; j += 4) {
+      a0 += X[int64_t(j) * n + i] * rl[j];
+      a1 += X[int64_t(j + 1) * n + i] * rl[j + 1];
+      a2 += X[int64_t(j + 2) * n + i] * rl[j + 2];
+      a3 += X[int64_t(j + 3) * n + i] * rl[j + 3];
+    }
+    for (; j < n; ++j) a0 += X[int64_t(j) * n + i] * rl[j];
+    y[o + i] = double((a0 + a1) + (a2 + a3));
+  }
+}
+
+// d[mu] += winv[mu] * sum of the patch images of mu, in patch order
+__global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr, const int64_t* __restrict__ tidx,
+                                    const double* __restrict__ winv, const double* __restrict__ y,
+                                    double* __restrict__ d) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t t = tptr[i]; t < tptr[i + 1]; ++t) s += y[tidx[t]];
+  d[i] += winv[i] * s;
+}
+
+// ---------------------------------------------------------------- dense coarse solve
+// y = X b with X stored as Xt row-major (X[i][j] at j*n + i).
+__global__ void __launch_bounds__(256) dense_gemv_t_kernel(int n, const double* __restrict__ Xt,
+                                                           const double* __restrict__ b, double* __restrict__ y) {
+  extern __shared__ double sb[];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sb[j] = b[j];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double a0 = 0, a1 = 0;
+  int j = 0;
+  for (; j + 1 < n; j += 2) {
+    a0 += Xt[int64_t(j) * n + i] * sb[j];
+    a1 += Xt[int64_t(j + 1) * n + i] * sb[j + 1];
+  }
+  if (j < n) a0 += Xt[int64_t(j) * n + i] * sb[j];
+  y[i] = a0 + a1;
+}
+
+// ---------------------------------------------------------------- BLAS-1 (FGMRES)
+// partials[v * nblk + blk] = sum over block blk's chunk of V_v . w
+__global__ void __launch_bounds__(256) dot_partials_kernel(const double* __restrict__ V, int64_t ldv,
+                                                           const double* __restrict__ w, int64_t n, int64_t chunk,
+                                                           double* __restrict__ partials) {
+  __shared__ double red[256 / WAVE];
+  const int v = blockIdx.y;
+  const int64_t lo = int64_t(blockIdx.x) * chunk, hi = min(n, lo + chunk);
+  const double* Vv = V + int64_t(v) * ldv;
+  double acc = 0.0;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += Vv[i] * w[i];
+  for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < int(blockDim.x / WAVE); ++q) s += red[q];
+    partials[int64_t(v) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out[v] = sum_b partials[v * nblk + b] (+ out[v] if accumulate)
+__global__ void __launch_bounds__(256) reduce_partials_kernel(const double* __restrict__ partials, int nblk,
+                                                              double* __restrict__ out, int accumulate) {
+  __shared__ double red[256 / WAVE];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partials[int64_t(v) * nblk + b];
+  for (int off = WAVE / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (threadIdx.x % WAVE == 0) red[threadIdx.x / WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int q = 0; q < int(blockDim.x / WAVE); ++q) s += red[q];
+    out[v] = accumulate ? out[v] + s : s;
+  }
+}
+
+// w += sign * sum_v h[v] V_v
+__global__ void multi_axpy_kernel(const double* __restrict__ V, int64_t ldv, int m, const double* __restrict__ h,
+                                  double sign, double* __restrict__ w, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int v = 0; v < m; ++v) s += h[v] * V[int64_t(v) * ldv + i];
+  w[i] += sign * s;
+}
+
+// dst = src * (1 / sqrt(*nrm2))  (nrm2 = squared norm on the device)
+__global__ void scale_copy_kernel(const double* __restrict__ src, const double* __restrict__ nrm2,
+                                  double* __restrict__ dst, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double nr = sqrt(*nrm2);
+  dst[i] = nr > 0.0 ? src[i] / nr : 0.0;
+}
+
+// out = a*x + b*y elementwise
+__global__ void axpby_kernel(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                             double* __restrict__ out, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+// rhs[b*ns + i] = e_b * mmx[i] + src[b*ns + i]
+__global__ void slab_rhs_kernel(int nt, int64_t ns, const double* __restrict__ e, const double* __restrict__ mmx,
+                                const double* __restrict__ src, double* __restrict__ rhs) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= int64_t(nt) * ns) return;
+  const int b = int(i / ns);
+  rhs[i] = e[b] * mmx[i % ns] + src[i];
+}
+
+}  // namespace dev
+
+// ================================================================= launchers
+static inline int64_t blocks_for(int64_t n, int bs) { return (n + bs - 1) / bs; }
+
+void k_csr(hipStream_t st, int mode, int64_t nrows, const int64_t* ptr, const int32_t* col, const double* val,
+           const double* x, const double* b, double* y, int lanes) {
+#define STGMG_CSR(G)                                                                  \
+  if (mode == 0) dev::launch_csr<G, 0>(st, nrows, ptr, col, val, x, b, y);            \
+  else if (mode == 1) dev::launch_csr<G, 1>(st, nrows, ptr, col, val, x, b, y);       \
+  else dev::launch_csr<G, 2>(st, nrows, ptr, col, val, x, b, y);
+  if (lanes <= 4) {
+    STGMG_CSR(4)
+  } else if (lanes <= 8) {
+    STGMG_CSR(8)
+  } else if (lanes <= 16) {
+    STGMG_CSR(16)
+  } else if (lanes <= 32) {
+    STGMG_CSR(32)
+  } else {
+    STGMG_CSR(64)
+  }
+#undef STGMG_CSR
+}
+
+void k_fill_zero(hipStream_t st, double* a, int64_t n) {
+  if (n == 0) return;
+  int64_t g = blocks_for(n, 256);
+  if (g > 65536) g = 65536;
+  hipLaunchKernelGGL(dev::fill_zero_kernel, dim3(g), dim3(256), 0, st, a, n);
+}
+
+void k_patch_extract_t(hipStream_t st, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                       const int32_t* pdof, const int64_t* ptr, const int32_t* col, const double* val,
+                       const int64_t* woff, double* W) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(dev::patch_extract_t_kernel, dim3(count), dim3(256), size_t(max_np) * sizeof(int32_t), st, p0,
+                     poff, pdof, ptr, col, val, woff, W);
+}
+
+size_t gj_lds_bytes(int max_np, int nb) {
+  return (size_t(max_np) * nb + max_np + 16) * sizeof(double) + 2 * size_t(max_np) * sizeof(int);
+}
+
+int gj_panel_width(int max_np, size_t lds_limit) {
+  for (int nb : {32, 16, 8, 4})
+    if (gj_lds_bytes(max_np, nb) <= lds_limit) return nb;
+  return 0;
+}
+
+template <typename T>
+static void gj_launch(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                      const int64_t* woff, double* W, const int64_t* ooff, T* out, int32_t* status) {
+  const size_t lds = gj_lds_bytes(max_np, nb);
+  switch (nb) {
+    case 32:
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 32>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
+                         out, status);
+      break;
+    case 16:
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 16>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
+                         out, status);
+      break;
+    case 8:
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 8>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
+                         out, status);
+      break;
+    default:
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 4>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
+                         out, status);
+      break;
+  }
+}
+
+void k_gj_invert_f64(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                     const int64_t* woff, double* W, const int64_t* ooff, double* out, int32_t* status) {
+  if (count) gj_launch<double>(st, nb, p0, count, max_np, poff, woff, W, ooff, out, status);
+}
+void k_gj_invert_f32(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
+                     const int64_t* woff, double* W, const int64_t* ooff, float* out, int32_t* status) {
+  if (count) gj_launch<float>(st, nb, p0, count, max_np, poff, woff, W, ooff, out, status);
+}
+
+void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+                       const int64_t* ioff, const double* inv, const double* r, double* y) {
+  if (npatch == 0) return;
+  hipLaunchKernelGGL(dev::patch_apply_kernel<double>, dim3(npatch), dim3(256), size_t(max_np) * sizeof(double), st,
+                     npatch, poff, pdof, ioff, inv, r, y);
+}
+void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+                       const int64_t* ioff, const float* inv, const double* r, double* y) {
+  if (npatch == 0) return;
+  hipLaunchKernelGGL(dev::patch_apply_kernel<float>, dim3(npatch), dim3(256), size_t(max_np) * sizeof(float), st,
+                     npatch, poff, pdof, ioff, inv, r, y);
+}
+
+void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
+                    const double* y, double* d) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(dev::vanka_update_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tptr, tidx, winv, y,
+                     d);
+}
+
+void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* y) {
+  hipLaunchKernelGGL(dev::dense_gemv_t_kernel, dim3(blocks_for(n, 256)), dim3(256), size_t(n) * sizeof(double), st,
+                     n, Xt, b, y);
+}
+
+int dot_blocks(int64_t n) {
+  int64_t b = (n + 8191) / 8192;
+  if (b < 1) b = 1;
+  if (b > 1024) b = 1024;
+  return int(b);
+}
+
+void k_multi_dot(hipStream_t st, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials,
+                 double* out, int accumulate) {
+  const int nblk = dot_blocks(n);
+  const int64_t chunk = (n + nblk - 1) / nblk;
+  hipLaunchKernelGGL(dev::dot_partials_kernel, dim3(nblk, m), dim3(256), 0, st, V, ldv, w, n, chunk, partials);
+  hipLaunchKernelGGL(dev::reduce_partials_kernel, dim3(m), dim3(256), 0, st, partials, nblk, out, accumulate);
+}
+
+void k_multi_axpy(hipStream_t st, const double* V, int64_t ldv, int m, const double* h, double sign, double* w,
+                  int64_t n) {
+  if (n == 0 || m == 0) return;
+  hipLaunchKernelGGL(dev::multi_axpy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, V, ldv, m, h, sign, w, n);
+}
+
+void k_scale_copy(hipStream_t st, const double* src, const double* nrm2, double* dst, int64_t n) {
+  hipLaunchKernelGGL(dev::scale_copy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, nrm2, dst, n);
+}
+
+void k_axpby(hipStream_t st, double a, const double* x, double b, const double* y, double* out, int64_t n) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(dev::axpby_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, a, x, b, y, out, n);
+}
+
+void k_slab_rhs(hipStream_t st, int nt, int64_t ns, const double* e, const double* mmx, const double* src,
+                double* rhs) {
+  hipLaunchKernelGGL(dev::slab_rhs_kernel, dim3(blocks_for(int64_t(nt) * ns, 256)), dim3(256), 0, st, nt, ns, e, mmx,
+                     src, rhs);
+}
+
+}  // namespace stgmg

@@ -1,0 +1,44 @@
+"""ctypes access to the host-only setup library (assembly, patches, transfers)."""
+import ctypes
+import os
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PATH = os.path.join(ROOT, 'paper_2303_06742_amd', 'libstgmg_host.so')
+
+
+def load():
+    if not os.path.exists(PATH):
+        from paper_2303_06742_amd import build
+        build.build_host()
+    lib = ctypes.CDLL(PATH)
+    D, I, LL, P = ctypes.c_double, ctypes.c_int, ctypes.c_longlong, ctypes.c_void_p
+    lib.stgmg_host_build.restype = LL
+    lib.stgmg_host_build.argtypes = [I, I, I, I, I, D, D, D, D, D, D, D, P]
+    lib.stgmg_host_nnz.restype = LL
+    lib.stgmg_host_nnz.argtypes = [I]
+    lib.stgmg_host_csr.argtypes = [I, P, P, P]
+    lib.stgmg_host_npatch.restype = LL
+    lib.stgmg_host_patch_total.restype = LL
+    lib.stgmg_host_patches.argtypes = [P, P, P]
+    lib.stgmg_host_prolongation.restype = LL
+    lib.stgmg_host_prolongation.argtypes = [I, I, I, I]
+    lib.stgmg_host_time.argtypes = [I, D, P, P, P, P, P]
+    lib.stgmg_host_source.argtypes = [D, D, D, D, D, D, P]
+    lib.stgmg_host_interpolate.argtypes = [D, P]
+    return lib
+
+
+def ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def csr(lib, which, nrows):
+    import scipy.sparse as sp
+    nnz = lib.stgmg_host_nnz(which)
+    p = np.zeros(nrows + 1, dtype=np.int64)
+    c = np.zeros(nnz, dtype=np.int32)
+    v = np.zeros(nnz)
+    lib.stgmg_host_csr(which, ptr(p), ptr(c), ptr(v))
+    return sp.csr_matrix((v, c, p), shape=(nrows, nrows if which != 2 else int(c.max()) + 1 if nnz else 0))

@@ -1,0 +1,74 @@
+"""Edge cases and error paths of the C ABI on the GPU."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import CONFIGS, require_gpu, to_dev, to_host
+from paper_2303_06742_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def capi():
+    require_gpu()
+    from paper_2303_06742_amd import capi as c
+    return c
+
+
+def test_invalid_params_rejected():
+    c = capi()
+    p = c.Params(dim=4, coarse_cells=2, levels=2, r=2, k=1, patch=0, smoother_prec=0, n_smooth=4, omega=0.7,
+                 tau=0.01, rho=1, lam=1, mu=1, alpha=0.9, c0=0.01, K=1.0, K_cells=None)
+    h = ctypes.c_void_p()
+    assert c.stgmg_setup(ctypes.byref(p), None, ctypes.byref(h)) == c.STGMG_ERR_INVALID_ARG
+    assert b"dim" in c.stgmg_last_error()
+    p.dim, p.k = 2, 7
+    assert c.stgmg_setup(ctypes.byref(p), None, ctypes.byref(h)) == c.STGMG_ERR_UNSUPPORTED
+    p.k, p.tau = 1, -1.0
+    assert c.stgmg_setup(ctypes.byref(p), None, ctypes.byref(h)) == c.STGMG_ERR_INVALID_ARG
+
+
+def test_solve_edge_cases():
+    c = capi()
+    S = c.Solver(CONFIGS['c1'])
+    n = S.n
+    # zero right-hand side: x stays zero, converged, no iterations
+    x = S.empty()
+    info = S.solve(S.empty(), x)
+    assert info['converged'] == 1 and info['iters'] == 0 and float(x.abs().max()) == 0.0
+    # NaN in the right-hand side
+    F = workloads.random_vector(n, 1)
+    F[5] = np.nan
+    with pytest.raises(c.StgmgError) as e:
+        S.solve(to_dev(F), S.empty())
+    assert e.value.status == c.STGMG_ERR_NONFINITE
+    # iteration cap: not converged, x holds the last iterate
+    F = workloads.random_vector(n, 2)
+    x = S.empty()
+    info = S.solve(to_dev(F), x, rtol=1e-14, max_iters=1)
+    assert info['converged'] == 0 and info['iters'] == 1 and info['rel_res_true'] < 1.0
+    # warm start from the solution converges at once
+    x2 = x.clone()
+    info = S.solve(to_dev(F), x2, rtol=1e-8)
+    info2 = S.solve(to_dev(F), x2, rtol=1e-3)
+    assert info2['iters'] == 0
+    # bad level index and wrong sizes
+    assert c.stgmg_apply_operator(S.h, 9, ctypes.c_void_p(x.data_ptr()),
+                                  ctypes.c_void_p(x.data_ptr())) == c.STGMG_ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        S.solve(to_dev(np.zeros(n + 1)), S.empty())
+    S.close()
+
+
+def test_restart_short_cycles():
+    """Restart length 2: more cycles, same answer to the tolerance."""
+    c = capi()
+    S = c.Solver(CONFIGS['c1'])
+    F = to_dev(workloads.random_vector(S.n, 3))
+    a, b = S.empty(), S.empty()
+    ia = S.solve(F, a, restart=30)
+    ib = S.solve(F, b, restart=2)
+    assert ia['converged'] and ib['converged']
+    d = np.abs(to_host(a) - to_host(b)).max() / np.abs(to_host(a)).max()
+    assert d < 1e-6

@@ -1,0 +1,164 @@
+"""GPU path (libstgmg.so through the C ABI) against the oracle, element by element,
+on shared seeded inputs.  Sizes span several patches/tiles and ragged patch sizes."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import CONFIGS, oracle_hierarchy, require_gpu, to_dev, to_host
+from paper_2303_06742_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+_solvers = {}
+
+
+def solver(key, precision=None):
+    require_gpu()
+    from paper_2303_06742_amd import capi
+    tag = (key, precision)
+    if tag not in _solvers:
+        print(f"[setup] {CONFIGS[key].name} {precision or CONFIGS[key].precision}", flush=True)
+        _solvers[tag] = capi.Solver(CONFIGS[key], precision=precision)
+    return _solvers[tag]
+
+
+def rel_err(a, b, scale=None):
+    s = np.abs(b).max() if scale is None else scale
+    return np.abs(a - b).max() / s
+
+
+KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0']
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_operator(key):
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    for l in range(S.levels):
+        A = H.levels[l].A
+        x = workloads.random_vector(A.shape[0], 100 + l)
+        y = to_host(S.apply_operator(to_dev(x), level=l))
+        ref = A @ x
+        bound = abs(A) @ abs(x)
+        assert np.all(np.abs(y - ref) <= 1e-13 * bound + 1e-300), (key, l)
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_transfers(key):
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    for l in range(1, S.levels):
+        P = H.P[l]
+        r = workloads.random_vector(P.shape[0], 200 + l)
+        e = workloads.random_vector(P.shape[1], 300 + l)
+        b = to_host(S.restrict(l, to_dev(r)))
+        assert rel_err(b, P.T @ r) < 1e-14
+        d0 = workloads.random_vector(P.shape[0], 400 + l)
+        d = to_host(S.prolongate_add(l, to_dev(e), to_dev(d0)))
+        assert rel_err(d, d0 + P @ e) < 1e-14
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_patch_inverses(key):
+    """Sampled stored inverses against LAPACK's inverse of the oracle's A_P, and A_P X = I."""
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    lev = H.levels[-1]
+    npatch = len(lev.patches)
+    for q in sorted(set([0, 1, npatch // 2, npatch - 1])):
+        X, dofs = S.patch_inverse(-1, q)
+        assert np.array_equal(dofs, lev.patches[q])
+        Ap = lev.A[lev.patches[q]][:, lev.patches[q]].toarray()
+        ref = lev.inv[q]
+        # both are backward-stable inverses: compare through the scaled residual
+        res = np.abs(Ap @ X - np.eye(len(dofs))).max()
+        res_ref = np.abs(Ap @ ref - np.eye(len(dofs))).max()
+        assert res < max(1e-9, 100 * res_ref), (q, res, res_ref)
+        y = workloads.random_vector(len(dofs), q)
+        assert rel_err(X @ y, ref @ y) < 1e-9
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_smoother(key):
+    """Algorithm 4.1 sweeps on the finest level from a random iterate."""
+    from oracle import gmg
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    lev = H.levels[-1]
+    b = workloads.random_vector(lev.n, 11)
+    d0 = workloads.random_vector(lev.n, 12)
+    for sweeps in (1, 4):
+        d = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), sweeps))
+        ref = gmg.vanka_smooth(lev, b, d0, sweeps, H.omega)
+        assert rel_err(d, ref) < 1e-10, (key, sweeps, rel_err(d, ref))
+
+
+@pytest.mark.parametrize("key", KEYS + ['one_level'])
+def test_vcycle(key):
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    r = workloads.random_vector(S.n, 21)
+    z = to_host(S.vcycle(to_dev(r)))
+    ref = H.precondition(r)
+    assert rel_err(z, ref) < 1e-10, (key, rel_err(z, ref))
+
+
+@pytest.mark.parametrize("key", KEYS)
+def test_solve_against_oracle(key):
+    """FGMRES-GMG to rtol 1e-8: same iteration count as the oracle's FGMRES-GMG, and the
+    solution agrees with the oracle's direct solve to the accuracy the tolerance allows."""
+    from oracle import fgmres
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    A = H.levels[-1].A
+    F = workloads.random_vector(S.n, 31)
+    x = S.empty()
+    info = S.solve(to_dev(F), x, rtol=1e-8)
+    xs = to_host(x)
+    assert info['converged'] == 1
+    assert np.linalg.norm(F - A @ xs) <= 1e-8 * np.linalg.norm(F) * (1 + 1e-6)
+    xo, oi = fgmres.fgmres(A, F, H.precondition, rtol=1e-8)
+    assert abs(info['iters'] - oi['iters']) <= 1, (info['iters'], oi['iters'])
+    # equal iteration counts: the two iterates agree to the rounding of the V-cycle
+    xg, _ = fgmres.fgmres(A, F, H.precondition, rtol=0.0, fixed_iters=info['iters'])
+    assert rel_err(xs, xg) < 1e-8, rel_err(xs, xg)
+
+
+@pytest.mark.parametrize("key", ['c1', 'c2s'])
+def test_time_marching_rhs(key):
+    """Right-hand side of Problem 3.1 for the built-in prescribed solution, and the
+    nodal interpolant at t0 (initial data)."""
+    from oracle import problem
+    S = solver(key)
+    H = oracle_hierarchy(key)
+    cfg = CONFIGS[key]
+    prob = H.levels[-1].prob
+    sol = problem.ExactSolution(cfg.dim, *workloads.builtin_solution_exprs(cfg.dim), prob.prm)
+    X0 = to_host(S.interpolate_solution(0.0))
+    assert rel_err(X0, problem.interpolate(prob.blocks, sol, 0.0)) < 1e-14
+    Xp = workloads.random_vector(S.ns, 41)
+    F = to_host(S.slab_rhs(0.25, to_dev(Xp)))
+    ref = problem.slab_rhs(prob.blocks, cfg.k, cfg.tau, 0.25, Xp, sol)
+    assert rel_err(F, ref) < 1e-10
+
+
+def test_fp32_smoother_meets_tolerances():
+    """FP32 patch inverses inside FP64 FGMRES: relative residual 1e-8 and solution
+    within 1e-7 of the FP64 solve (relative, max norm)."""
+    S64 = solver('c2s')
+    S32 = solver('c2s', 'fp32')
+    F = workloads.random_vector(S64.n, 51)
+    x64, x32 = S64.empty(), S32.empty()
+    i64 = S64.solve(to_dev(F), x64, rtol=1e-10)
+    i32 = S32.solve(to_dev(F), x32, rtol=1e-10)
+    assert i32['converged'] and i32['rel_res_true'] <= 1e-10
+    assert rel_err(to_host(x32), to_host(x64)) < 1e-7
+    assert i32['iters'] <= i64['iters'] + 2
+
+
+def test_deterministic():
+    S = solver('c2s')
+    F = to_dev(workloads.random_vector(S.n, 61))
+    a, b = S.empty(), S.empty()
+    S.solve(F, a)
+    S.solve(F, b)
+    assert np.array_equal(to_host(a), to_host(b))

@@ -1,0 +1,106 @@
+"""The C++ host setup (assembly, patch tables, transfers, sources) against the
+oracle, entry by entry, on the CPU.  The two are independent implementations."""
+import numpy as np
+import pytest
+
+from oracle import gmg, problem, timedg
+from tests import hostlib
+from paper_2303_06742_amd import workloads
+
+LIB = hostlib.load()
+
+
+def build(d, N, r, k, kind, prm, tau=0.01, omega=0.7):
+    K = np.broadcast_to(np.asarray(prm.K, dtype=float), (N ** d,)).copy()
+    n = LIB.stgmg_host_build(d, r, k, N, 1 if kind == 'vertex' else 0, tau, omega, prm.rho, prm.lam, prm.mu,
+                             prm.alpha, prm.c0, hostlib.ptr(K))
+    assert n > 0
+    return n
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_time_constants(k):
+    x, w, Dt, mt, e = (np.zeros(k + 1), np.zeros(k + 1), np.zeros((k + 1) ** 2), np.zeros(k + 1), np.zeros(k + 1))
+    LIB.stgmg_host_time(k, 0.3, *[hostlib.ptr(a) for a in (x, w, Dt, mt, e)])
+    D0, M0, e0, x0, w0 = timedg.time_matrices(k, 0.3)
+    assert np.allclose(x, x0, atol=1e-14, rtol=0) and np.allclose(w, w0, atol=1e-14, rtol=0)
+    assert np.allclose(Dt.reshape(k + 1, k + 1), D0, atol=1e-13, rtol=0)
+    assert np.allclose(np.diag(M0), mt, atol=1e-15, rtol=0) and np.allclose(e, e0, atol=1e-13, rtol=0)
+
+
+CASES = [(2, 2, 2, 1), (2, 3, 2, 2), (2, 2, 3, 1), (3, 2, 2, 1), (2, 2, 2, 0)]
+
+
+@pytest.mark.parametrize("d,N,r,k", CASES)
+def test_operator_matches_oracle(d, N, r, k):
+    rng = np.random.default_rng(7)
+    prm = problem.Params(rho=1.3, lam=2.5, mu=0.8, alpha=0.7, c0=0.02, K=np.exp(rng.standard_normal(N ** d)))
+    n = build(d, N, r, k, 'cell', prm, tau=0.05)
+    A = hostlib.csr(LIB, 0, n)
+    ref = problem.slab_operator(problem.SpaceBlocks(d, N, r, prm), k, 0.05)
+    assert A.shape == ref.shape
+    diff = abs(A - ref)
+    scale = abs(ref).max(axis=1).toarray().ravel()
+    # rounding: 1e-13 of the row, plus 1e-15 of the largest (Nitsche penalty) entries,
+    # which enter sums whose results can be much smaller
+    tol = 1e-13 * scale + 1e-15 * abs(ref).max()
+    assert (diff.max(axis=1).toarray().ravel() <= tol).all()
+
+
+@pytest.mark.parametrize("kind", ["cell", "vertex"])
+@pytest.mark.parametrize("d,N,k", [(2, 3, 1), (3, 2, 1), (2, 2, 2)])
+def test_patches_match_oracle(kind, d, N, k):
+    prm = problem.Params()
+    n = build(d, N, 2, k, kind, prm, omega=0.7)
+    npatch = LIB.stgmg_host_npatch()
+    tot = LIB.stgmg_host_patch_total()
+    poff = np.zeros(npatch + 1, dtype=np.int64)
+    pdof = np.zeros(tot, dtype=np.int32)
+    winv = np.zeros(n)
+    LIB.stgmg_host_patches(hostlib.ptr(poff), hostlib.ptr(pdof), hostlib.ptr(winv))
+    blocks = problem.SpaceBlocks(d, N, 2, prm)
+    cells = gmg.patch_cells(blocks.mesh, kind)
+    assert len(cells) == npatch
+    cnt = np.zeros(n)
+    for q, c in enumerate(cells):
+        Z = gmg.patch_dofs(blocks, k, c)
+        assert np.array_equal(pdof[poff[q]:poff[q + 1]], Z)
+        cnt[Z] += 1
+    assert np.allclose(winv, 0.7 / cnt, rtol=1e-15)
+
+
+@pytest.mark.parametrize("d,r,k,Nc", [(2, 2, 1, 2), (2, 2, 2, 1), (3, 2, 1, 1), (2, 3, 1, 2)])
+def test_prolongation_matches_oracle(d, r, k, Nc):
+    nnz = LIB.stgmg_host_prolongation(d, r, k, Nc)
+    assert nnz > 0
+    prm = problem.Params()
+    ref = gmg.prolongation(problem.SpaceBlocks(d, Nc, r, prm), problem.SpaceBlocks(d, 2 * Nc, r, prm), k)
+    ref.eliminate_zeros()
+    import scipy.sparse as sp
+    p = np.zeros(ref.shape[0] + 1, dtype=np.int64)
+    c = np.zeros(nnz, dtype=np.int32)
+    v = np.zeros(nnz)
+    LIB.stgmg_host_csr(2, hostlib.ptr(p), hostlib.ptr(c), hostlib.ptr(v))
+    P = sp.csr_matrix((v, c, p), shape=ref.shape)
+    assert abs(P - ref).max() < 1e-14
+    assert P.nnz == ref.nnz
+
+
+@pytest.mark.parametrize("d,N,K", [(2, 3, None), (3, 2, 'hetero')])
+def test_source_and_interpolant_match_oracle(d, N, K):
+    rng = np.random.default_rng(1)
+    Kc = np.exp(rng.standard_normal(N ** d)) if K else 1.0
+    prm = problem.Params(rho=1.2, lam=1.5, mu=0.9, alpha=0.8, c0=0.03, K=Kc)
+    build(d, N, 2, 1, 'cell', prm)
+    blocks = problem.SpaceBlocks(d, N, 2, prm)
+    sol = problem.ExactSolution(d, *workloads.builtin_solution_exprs(d), prm)
+    for t in (0.0, 0.37):
+        out = np.zeros(blocks.ns)
+        LIB.stgmg_host_source(t, prm.rho, prm.lam, prm.mu, prm.alpha, prm.c0, hostlib.ptr(out))
+        ref = problem.source_vector(blocks, sol, t)
+        # the oracle integrates the Nitsche data terms literally: sin(pi) = 1.2e-16 in
+        # floating point, times gamma_a/h_F ~ 1e6, leaves ~1e-11; the library uses the
+        # exact zero boundary data of this solution
+        assert np.abs(out - ref).max() < 1e-10 * np.abs(ref).max()
+        LIB.stgmg_host_interpolate(t, hostlib.ptr(out))
+        assert np.abs(out - problem.interpolate(blocks, sol, t)).max() < 1e-14
