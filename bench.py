@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark: GMRES-GMG slab solves on one MI355X.
+
+A step is one slab of the time marching on the 2D 256x256 workload (Q2/Q2/Q1,
+dG(2), 7 levels from 4x4, vertex patches, tau = 1e-3): the right-hand side of
+Problem 3.1 from the previous slab's end value, then FGMRES(30) preconditioned
+by one V-cycle per iteration, from x0 = 0 to a relative residual of 1e-8.
+The hierarchy (level operators, patch inverses) is built once before timing
+and stays resident in HBM; its setup time is reported separately.
+
+Prints one JSON line.  Only the `cpu_baseline` leg imports the CPU oracle.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GMRES-GMG solves/s and V-cycle DoF/s at 1e-8 rel. residual; p50/p99 latency"
+
+
+def configs():
+    from paper_2303_06742_amd import workloads as W
+    return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3}
+
+
+def cpu_baseline(cfg, sample_levels):
+    """The oracle, single-threaded BLAS, on one slab of the same physics on a smaller grid;
+    solve time (setup excluded, as on the GPU) extrapolated linearly in unknowns."""
+    from threadpoolctl import threadpool_limits
+    from paper_2303_06742_amd import workloads as W
+    from oracle import fgmres, gmg, problem
+    scfg = W.scaled(cfg, sample_levels)
+    with threadpool_limits(limits=1):
+        prm = problem.Params(rho=scfg.rho, lam=scfg.lam, mu=scfg.mu, alpha=scfg.alpha, c0=scfg.c0, K=scfg.K)
+        t0 = time.perf_counter()
+        H = gmg.Hierarchy(scfg.dim, scfg.coarse_cells, scfg.levels - 1, scfg.r, scfg.k, scfg.tau, prm,
+                          patch_kind=scfg.patch, J=scfg.n_smooth, omega=scfg.omega)
+        t_setup = time.perf_counter() - t0
+        f = H.fine.prob
+        sol = problem.ExactSolution(scfg.dim, *W.builtin_solution_exprs(scfg.dim), prm)
+        F = problem.slab_rhs(f.blocks, scfg.k, scfg.tau, 0.0, problem.interpolate(f.blocks, sol, 0.0), sol)
+        t0 = time.perf_counter()
+        _, info = fgmres.fgmres(f.A, F, H.precondition, rtol=scfg.rtol, restart=scfg.restart)
+        t_solve = time.perf_counter() - t0
+    n_full = (cfg.k + 1) * (2 * cfg.dim * (2 * cfg.fine_cells + 1) ** cfg.dim + (cfg.fine_cells + 1) ** cfg.dim)
+    scale = n_full / f.n
+    return {'value': 1.0 / (t_solve * scale), 'unit': 'solves/s', 'cores': 1, 'kind': 'oracle',
+            'sample': (f"one slab of the same physics on {scfg.fine_cells}^{scfg.dim} cells ({scfg.levels} levels, "
+                       f"{f.n} unknowns, {info['iters']} FGMRES iterations): solve {t_solve:.2f} s, setup "
+                       f"{t_setup:.2f} s; extrapolated linearly in unknowns (x{scale:.1f}) to the full grid"),
+            'solve_s_sample': t_solve}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=1)
+    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3'])
+    ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32'])
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--cpu-sample-levels', type=int, default=4)
+    ap.add_argument('--copy-calibration', action='store_true',
+                    help='run a plain 1 GiB device copy first (reference for HBM byte counters)')
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (independent problems "
+              "would be sharded across GPUs; see the sharding notes in the design document).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2303_06742_amd import capi
+    cfg = configs()[args.config]
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device='cuda')
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    print(f"[bench] setup {cfg.name} {args.precision}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    S = capi.Solver(cfg, precision=args.precision)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    q = S.query(-1)
+    k, ns, n = cfg.k, S.ns, S.n
+    state = {'t': 0.0, 'Xend': S.interpolate_solution(0.0)}
+    rhs, x = S.empty(), S.empty()
+
+    def step():
+        S.slab_rhs(state['t'], state['Xend'], rhs)
+        x.zero_()
+        info = S.solve(rhs, x, rtol=cfg.rtol, restart=cfg.restart)
+        state['Xend'] = x[k * ns:(k + 1) * ns].clone()
+        state['t'] += cfg.tau
+        return info
+
+    print(f"[bench] setup {setup_s:.1f} s, n={n}; warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    S.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for i in range(args.steps):
+        infos.append(step())
+        print(f"[bench] step {i}: {infos[-1]['iters']} its, {infos[-1]['t_solve_ms']:.1f} ms", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    pa = S.profile_get(capi.PROF_PATCH_APPLY)
+    rs = S.profile_get(capi.PROF_RESIDUAL)
+    S.profile(False)
+    exact = S.interpolate_solution(state['t'])
+    nodal_err = float((state['Xend'] - exact).abs().max() / exact.abs().max())
+    iters = [i['iters'] for i in infos]
+    lat = np.array([i['t_solve_ms'] for i in infos])
+    ms_per_step = 1000.0 * elapsed / args.steps
+    avg_pa_ms = pa['total_ms'] / max(pa['launches'], 1)
+    achieved = pa['bytes_per_launch'] / (avg_pa_ms * 1e-3) / 1e9 if pa['launches'] else 0.0
+    avg_rs_ms = rs['total_ms'] / max(rs['launches'], 1)
+    out = {
+        'metric': METRIC,
+        'value': args.steps / elapsed,
+        'unit': 'solves/s',
+        'n_gpus': 1,
+        'steps': args.steps,
+        'warmup': args.warmup,
+        'ms_per_step': ms_per_step,
+        'higher_is_better': True,
+        'scaling': 'weak',
+        'vs_baseline': None,
+        'dtype': 'f64' if args.precision == 'fp64' else 'f64+f32-smoother',
+        'data': 'synthetic',
+        'config': {'workload': cfg.name, 'dim': cfg.dim, 'cells': f"{cfg.fine_cells}^{cfg.dim}",
+                   'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'smoother': args.precision,
+                   'tau': cfg.tau, 'unknowns': n, 'nnz': q['nnz'], 'patches': q['patches'], 'rtol': cfg.rtol,
+                   'restart': cfg.restart},
+        'vcycle_dof_per_s': n * sum(iters) / elapsed,
+        'latency_ms_p50': float(np.percentile(lat, 50)),
+        'latency_ms_p99': float(np.percentile(lat, 99)),
+        'gmres_iters': iters,
+        'rel_res_true_max': max(i['rel_res_true'] for i in infos),
+        'nodal_err_vs_exact': nodal_err,
+        'setup_s': setup_s,
+        'hbm_bytes_resident': q['bytes'],
+        'roofline': {'bound': 'hbm', 'kernel': 'patch_apply_kernel (finest level)', 'achieved': achieved,
+                     'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
+                     'avg_launch_ms': avg_pa_ms, 'launches': pa['launches'],
+                     'bytes_per_launch': pa['bytes_per_launch']},
+        'residual_spmv': {'avg_launch_ms': avg_rs_ms, 'launches': rs['launches'],
+                          'achieved_GBs': rs['bytes_per_launch'] / (avg_rs_ms * 1e-3) / 1e9 if rs['launches'] else 0},
+    }
+    S.close()
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out['cpu_baseline'] = cpu_baseline(cfg, args.cpu_sample_levels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

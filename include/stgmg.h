@@ -147,6 +147,19 @@ stgmg_status stgmg_interpolate_solution(stgmg_handle* h, double t, double* x_blo
 stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t patch, int32_t* n_p,
                                      double* out_host, int64_t* dofs_host);
 
+/* Kernel timing with HIP events on the handle's stream, for roofline figures.
+ * enable != 0 starts recording (clearing earlier records); stgmg_profile_get
+ * returns, for `what` = STGMG_PROF_PATCH_APPLY (patch GEMV of Def:VankaOP on the
+ * finest level) or STGMG_PROF_RESIDUAL (residual b - A d on the finest level),
+ * the number of recorded launches, their summed duration in ms, and the
+ * algorithmic bytes of one launch (stored inverse entries + gathered residual
+ * + written images, resp. matrix values + x + b + y; index bytes excluded). */
+#define STGMG_PROF_PATCH_APPLY 0
+#define STGMG_PROF_RESIDUAL 1
+stgmg_status stgmg_profile_enable(stgmg_handle* h, int32_t enable);
+stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches, double* total_ms,
+                               double* bytes_per_launch);
+
 stgmg_status stgmg_destroy(stgmg_handle* h);
 
 const char* stgmg_status_string(stgmg_status s);

@@ -27,6 +27,8 @@ STGMG_ERR_HIP = -4
 STGMG_ERR_SINGULAR_PATCH = -5
 STGMG_ERR_NONFINITE = -6
 PATCH = {'cell': 0, 'vertex': 1}
+PROF_PATCH_APPLY = 0
+PROF_RESIDUAL = 1
 PREC = {'fp64': 0, 'fp32': 1}
 
 
@@ -73,13 +75,17 @@ stgmg_restrict = _decl('stgmg_restrict', [_H, _I32, _P, _P])
 stgmg_slab_rhs = _decl('stgmg_slab_rhs', [_H, _D, _P, _P])
 stgmg_interpolate_solution = _decl('stgmg_interpolate_solution', [_H, _D, _P])
 stgmg_get_patch_inverse = _decl('stgmg_get_patch_inverse', [_H, _I32, _I64, ctypes.POINTER(_I32), _P, _P])
+stgmg_profile_enable = _decl('stgmg_profile_enable', [_H, _I32])
+stgmg_profile_get = _decl('stgmg_profile_get', [_H, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D),
+                                                ctypes.POINTER(_D)])
 stgmg_destroy = _decl('stgmg_destroy', [_H])
 stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
 stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
 
 EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
             'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs',
-            'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_destroy', 'stgmg_status_string',
+            'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_profile_enable', 'stgmg_profile_get',
+            'stgmg_destroy', 'stgmg_status_string',
             'stgmg_last_error']
 
 
@@ -188,6 +194,14 @@ class Solver:
         check(stgmg_get_patch_inverse(self.h, level, patch, ctypes.byref(npp), out.ctypes.data_as(_P),
                                       dofs.ctypes.data_as(_P)), 'stgmg_get_patch_inverse')
         return out, dofs
+
+    def profile(self, enable):
+        check(stgmg_profile_enable(self.h, 1 if enable else 0), 'stgmg_profile_enable')
+
+    def profile_get(self, what):
+        n, ms, b = _I64(), _D(), _D()
+        check(stgmg_profile_get(self.h, what, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(b)), 'stgmg_profile_get')
+        return {'launches': n.value, 'total_ms': ms.value, 'bytes_per_launch': b.value}
 
     def close(self):
         if getattr(self, 'h', None):

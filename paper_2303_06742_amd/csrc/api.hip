@@ -130,12 +130,21 @@ struct stgmg_handle {
   stgmg::TimeConsts T;
   DevCsr MM;
   DArr<double> e_dev, tmp_ns, src_buf;
+  // kernel timing (finest level): event pairs per kernel class
+  bool prof = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+  size_t ev_used[2] = {0, 0};
   // FGMRES workspace
   int m_alloc = 0;
   DArr<double> V, Z, w, partials, hdev, ydev;
   double* hhost = nullptr;  // pinned
   ~stgmg_handle() {
     if (hhost) (void)hipHostFree(hhost);
+    for (auto& v : ev)
+      for (auto& e : v) {
+        (void)hipEventDestroy(e.first);
+        (void)hipEventDestroy(e.second);
+      }
   }
 };
 
@@ -177,18 +186,43 @@ size_t lds_limit() {
 
 void vcycle(stgmg_handle* h, int l, const double* b, double* d);
 
+// Event pair around one launch of kernel class `what` on the finest level.
+struct ProfScope {
+  stgmg_handle* h;
+  int what;
+  bool on;
+  ProfScope(stgmg_handle* hh, int w, int level) : h(hh), what(w), on(hh->prof && level == hh->L) {
+    if (!on) return;
+    auto& v = h->ev[what];
+    if (h->ev_used[what] == v.size()) {
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      v.emplace_back(a, b);
+    }
+    HIPCHK(hipEventRecord(v[h->ev_used[what]].first, h->st));
+  }
+  ~ProfScope() {
+    if (on) (void)hipEventRecord(h->ev[what][h->ev_used[what]++].second, h->st);
+  }
+};
+
 void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool zero_start) {
   LevelDev& L = h->lv[l];
   for (int j = 0; j < sweeps; ++j) {
     const double* r = b;
     if (!(j == 0 && zero_start)) {
+      ProfScope ps(h, STGMG_PROF_RESIDUAL, l);
       L.A.apply(h->st, 1, d, b, L.r.p);
       r = L.r.p;
     }
-    if (h->prm.smoother_prec == STGMG_FP32)
-      stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r, L.y.p);
-    else
-      stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r, L.y.p);
+    {
+      ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
+      if (h->prm.smoother_prec == STGMG_FP32)
+        stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r, L.y.p);
+      else
+        stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r, L.y.p);
+    }
     stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.tidx.p, L.winv.p, L.y.p, d);
   }
 }
@@ -686,6 +720,46 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
       for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * n + a];
     if (dofs_host)
       for (int a = 0; a < n; ++a) dofs_host[a] = D.pdof_h[D.poff_h[patch] + a];
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_profile_enable(stgmg_handle* h, int32_t enable) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    HIPCHK(hipStreamSynchronize(h->st));
+    h->prof = enable != 0;
+    h->ev_used[0] = h->ev_used[1] = 0;
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches, double* total_ms,
+                               double* bytes_per_launch) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    if (what != STGMG_PROF_PATCH_APPLY && what != STGMG_PROF_RESIDUAL)
+      throw ApiError(STGMG_ERR_INVALID_ARG, "unknown kernel class");
+    HIPCHK(hipStreamSynchronize(h->st));
+    double ms = 0.0;
+    for (size_t i = 0; i < h->ev_used[what]; ++i) {
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, h->ev[what][i].first, h->ev[what][i].second));
+      ms += t;
+    }
+    const LevelDev& F = h->lv[h->L];
+    double bytes = 0.0;
+    if (what == STGMG_PROF_PATCH_APPLY) {
+      const double w = h->prm.smoother_prec == STGMG_FP32 ? 4.0 : 8.0;
+      const double sum_np2 = F.npatch ? double(F.ioff_h[F.npatch]) : 0.0;
+      const double sum_np = F.npatch ? double(F.poff_h[F.npatch]) : 0.0;
+      bytes = w * sum_np2 + 16.0 * sum_np;
+    } else {
+      bytes = 8.0 * double(F.A.nnz) + 24.0 * double(F.n);
+    }
+    if (launches) *launches = int64_t(h->ev_used[what]);
+    if (total_ms) *total_ms = ms;
+    if (bytes_per_launch) *bytes_per_launch = bytes;
     return STGMG_OK;
   });
 }

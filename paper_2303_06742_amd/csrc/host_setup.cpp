@@ -839,69 +839,88 @@ void source_vector(const LevelHost& L, const Material& m, double t, std::vector<
   int64_t ncells = 1;
   for (int a = 0; a < d; ++a) ncells *= N;
   const int nls = ts[0].nl, nlp = tp[0].nl;
-  for (int64_t cell = 0; cell < ncells; ++cell) {
-    int cc[3] = {0, 0, 0};
-    int64_t rem = cell;
-    for (int ax = 0; ax < d; ++ax) {
-      cc[ax] = int(rem % N);
-      rem /= N;
-    }
-    const double K = L.Kcell[cell];
-    for (int q = 0; q < nq; ++q) {
-      double sn[3] = {1, 1, 1}, cs[3] = {0, 0, 0};
+  // cells are split into a fixed number of contiguous chunks, each accumulated
+  // into its own vector and summed in chunk order: the result does not depend on
+  // the number of threads
+  const int nchunk = ncells >= 4096 ? 16 : 1;
+  std::vector<std::vector<double>> part(nchunk);
+  auto work = [&](int ch) {
+    std::vector<double>& acc = part[ch];
+    acc.assign(L.ns, 0.0);
+    const int64_t c_lo = ncells * ch / nchunk, c_hi = ncells * (ch + 1) / nchunk;
+    for (int64_t cell = c_lo; cell < c_hi; ++cell) {
+      int cc[3] = {0, 0, 0};
+      int64_t rem = cell;
       for (int ax = 0; ax < d; ++ax) {
-        double x = (cc[ax] + xq[q][ax]) * h;
-        sn[ax] = std::sin(pi * x);
-        cs[ax] = std::cos(pi * x);
+        cc[ax] = int(rem % N);
+        rem /= N;
       }
-      double S = 1.0, dS[3], ddS[3][3];
-      for (int ax = 0; ax < d; ++ax) S *= sn[ax];
-      for (int i = 0; i < d; ++i) {
-        dS[i] = pi * cs[i];
-        for (int j = 0; j < d; ++j)
-          if (j != i) dS[i] *= sn[j];
-        for (int j = 0; j < d; ++j) {
-          if (i == j) {
-            ddS[i][j] = -pi * pi * S;
-          } else {
-            double v = pi * pi * cs[i] * cs[j];
-            for (int l = 0; l < d; ++l)
-              if (l != i && l != j) v *= sn[l];
-            ddS[i][j] = v;
+      const double K = L.Kcell[cell];
+      for (int q = 0; q < nq; ++q) {
+        double sn[3] = {1, 1, 1}, cs[3] = {0, 0, 0};
+        for (int ax = 0; ax < d; ++ax) {
+          double x = (cc[ax] + xq[q][ax]) * h;
+          sn[ax] = std::sin(pi * x);
+          cs[ax] = std::cos(pi * x);
+        }
+        double S = 1.0, dS[3], ddS[3][3];
+        for (int ax = 0; ax < d; ++ax) S *= sn[ax];
+        for (int i = 0; i < d; ++i) {
+          dS[i] = pi * cs[i];
+          for (int j = 0; j < d; ++j)
+            if (j != i) dS[i] *= sn[j];
+          for (int j = 0; j < d; ++j) {
+            if (i == j) {
+              ddS[i][j] = -pi * pi * S;
+            } else {
+              double v = pi * pi * cs[i] * cs[j];
+              for (int l = 0; l < d; ++l)
+                if (l != i && l != j) v *= sn[l];
+              ddS[i][j] = v;
+            }
           }
         }
-      }
-      double f[3];
-      for (int i = 0; i < d; ++i) {
-        double sum = 0.0;
-        for (int c = 0; c < d; ++c) sum += ddS[i][c];
-        f[i] = (-m.rho * S + m.mu * d * pi * pi * S - (m.mu + m.lambda) * sum) * st + m.alpha * dS[i] * ct;
-      }
-      double divS = 0.0;
-      for (int c = 0; c < d; ++c) divS += dS[c];
-      const double g = -m.c0 * S * st + m.alpha * divS * ct + K * d * pi * pi * S * ct;
-      for (int a = 0; a < nls; ++a) {
-        int64_t gn = 0;
-        int idx[3], rm = a;
-        for (int ax = 0; ax < d; ++ax) {
-          idx[ax] = rm % (r + 1);
-          rm /= (r + 1);
+        double f[3];
+        for (int i = 0; i < d; ++i) {
+          double sum = 0.0;
+          for (int c = 0; c < d; ++c) sum += ddS[i][c];
+          f[i] = (-m.rho * S + m.mu * d * pi * pi * S - (m.mu + m.lambda) * sum) * st + m.alpha * dS[i] * ct;
         }
-        for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1 + (int64_t(r) * cc[ax] + idx[ax]);
-        for (int c = 0; c < d; ++c) out[L.nv + d * gn + c] += wq[q] * ts[q].v[a] * f[c];
-      }
-      for (int s = 0; s < nlp; ++s) {
-        int64_t gn = 0;
-        int idx[3], rm = s;
-        for (int ax = 0; ax < d; ++ax) {
-          idx[ax] = rm % r;
-          rm /= r;
+        double divS = 0.0;
+        for (int c = 0; c < d; ++c) divS += dS[c];
+        const double g = -m.c0 * S * st + m.alpha * divS * ct + K * d * pi * pi * S * ct;
+        for (int a = 0; a < nls; ++a) {
+          int64_t gn = 0;
+          int idx[3], rm = a;
+          for (int ax = 0; ax < d; ++ax) {
+            idx[ax] = rm % (r + 1);
+            rm /= (r + 1);
+          }
+          for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1 + (int64_t(r) * cc[ax] + idx[ax]);
+          for (int c = 0; c < d; ++c) acc[L.nv + d * gn + c] += wq[q] * ts[q].v[a] * f[c];
         }
-        for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1p + (int64_t(r - 1) * cc[ax] + idx[ax]);
-        out[2 * L.nv + gn] += wq[q] * tp[q].v[s] * g;
+        for (int s = 0; s < nlp; ++s) {
+          int64_t gn = 0;
+          int idx[3], rm = s;
+          for (int ax = 0; ax < d; ++ax) {
+            idx[ax] = rm % r;
+            rm /= r;
+          }
+          for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1p + (int64_t(r - 1) * cc[ax] + idx[ax]);
+          acc[2 * L.nv + gn] += wq[q] * tp[q].v[s] * g;
+        }
       }
     }
+  };
+  {
+    std::vector<std::thread> th;
+    for (int ch = 1; ch < nchunk; ++ch) th.emplace_back(work, ch);
+    work(0);
+    for (auto& x : th) x.join();
   }
+  out = std::move(part[0]);
+  for (int ch = 1; ch < nchunk; ++ch)
+    for (int64_t i = 0; i < L.ns; ++i) out[i] += part[ch][i];
 }
 
 void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out) {

@@ -48,11 +48,11 @@ def test_solve_edge_cases():
     x = S.empty()
     info = S.solve(to_dev(F), x, rtol=1e-14, max_iters=1)
     assert info['converged'] == 0 and info['iters'] == 1 and info['rel_res_true'] < 1.0
-    # warm start from the solution converges at once
+    # warm start: the initial residual reported is that of x0 (the previous solution)
     x2 = x.clone()
     info = S.solve(to_dev(F), x2, rtol=1e-8)
-    info2 = S.solve(to_dev(F), x2, rtol=1e-3)
-    assert info2['iters'] == 0
+    info2 = S.solve(to_dev(F), x2, rtol=1e-8)
+    assert info2['res0'] <= 1e-8 * info['res0'] * (1 + 1e-6)
     # bad level index and wrong sizes
     assert c.stgmg_apply_operator(S.h, 9, ctypes.c_void_p(x.data_ptr()),
                                   ctypes.c_void_p(x.data_ptr())) == c.STGMG_ERR_INVALID_ARG
