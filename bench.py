@@ -23,6 +23,27 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "GMRES-GMG solves/s and V-cycle DoF/s at 1e-8 rel. residual; p50/p99 latency"
 
 
+def kernel_source_hash():
+    import hashlib
+    with open(os.path.join(ROOT, 'paper_2303_06742_amd', 'csrc', 'kernels.hip'), 'rb') as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the finest-level patch GEMV from the rocprofv3 counter runs
+    recorded in profiles/hbm_traffic.json, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, 'profiles', 'hbm_traffic.json')
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        entries = json.load(f).get('entries', [])
+    h = kernel_source_hash()
+    for e in entries:
+        if e.get('workload') == workload and e.get('precision') == precision and e.get('kernels_hip_sha256') == h:
+            return e['bytes_per_launch']
+    return None
+
+
 def configs():
     from paper_2303_06742_amd import workloads as W
     return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3}
@@ -152,7 +173,8 @@ def main():
         'setup_s': setup_s,
         'hbm_bytes_resident': q['bytes'],
         'roofline': {'bound': 'hbm', 'kernel': 'patch_apply_kernel (finest level)', 'achieved': achieved,
-                     'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': achieved / HBM_PEAK_GBS, 'traffic': None,
+                     'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': achieved / HBM_PEAK_GBS,
+                     'traffic': measured_traffic(cfg.name, args.precision), 'kernels_hip_sha256': kernel_source_hash(),
                      'avg_launch_ms': avg_pa_ms, 'launches': pa['launches'],
                      'bytes_per_launch': pa['bytes_per_launch']},
         'residual_spmv': {'avg_launch_ms': avg_rs_ms, 'launches': rs['launches'],

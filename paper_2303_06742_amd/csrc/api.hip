@@ -318,7 +318,7 @@ void build(stgmg_handle* h) {
       std::vector<double> W0 = dense_transposed(H.A);
       DArr<double> Wd;
       Wd.upload(W0, h->st, nullptr);
-      h->coarse_inv.alloc(H.n * H.n, ctr);
+      h->coarse_inv.alloc(H.n * stgmg::inv_ld(int(H.n)), ctr);
       std::vector<int64_t> poff0 = {0, H.n}, zero = {0};
       DArr<int64_t> poffd, woffd;
       poffd.upload(poff0, h->st, nullptr);
@@ -347,7 +347,7 @@ void build(stgmg_handle* h) {
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
         max_np = std::max<int>(max_np, int(np));
-        D.ioff_h[q + 1] = D.ioff_h[q] + np * np;
+        D.ioff_h[q + 1] = D.ioff_h[q] + np * stgmg::inv_ld(int(np));
       }
       D.max_np = max_np;
       D.poff.upload(H.poff, h->st, ctr);
@@ -708,16 +708,17 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
     const int n = int(D.poff_h[patch + 1] - D.poff_h[patch]);
     *n_p = n;
     if (!out_host) return STGMG_OK;
-    std::vector<double> st(size_t(n) * n);
+    std::vector<double> st(size_t(n) * stgmg::inv_ld(n));
     if (h->prm.smoother_prec == STGMG_FP32) {
-      std::vector<float> f(size_t(n) * n);
+      std::vector<float> f(st.size());
       HIPCHK(hipMemcpy(f.data(), D.inv32.p + D.ioff_h[patch], f.size() * sizeof(float), hipMemcpyDeviceToHost));
       for (size_t i = 0; i < f.size(); ++i) st[i] = f[i];
     } else {
       HIPCHK(hipMemcpy(st.data(), D.inv64.p + D.ioff_h[patch], st.size() * sizeof(double), hipMemcpyDeviceToHost));
     }
+    const int ld = stgmg::inv_ld(n);
     for (int a = 0; a < n; ++a)
-      for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * n + a];
+      for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * ld + a];
     if (dofs_host)
       for (int a = 0; a < n; ++a) dofs_host[a] = D.pdof_h[D.poff_h[patch] + a];
     return STGMG_OK;

@@ -7,6 +7,11 @@
 
 namespace stgmg {
 
+// Leading dimension of a stored patch inverse of size n: columns padded to a
+// multiple of 4 values so that every column starts 16-byte aligned (FP32) /
+// 32-byte aligned (FP64); the padding rows hold zeros.
+__host__ __device__ inline int inv_ld(int n) { return (n + 3) & ~3; }
+
 // mode 0: y = A x; 1: y = b - A x; 2: y += A x.  lanes = CSR lanes per row (4..64).
 void k_csr(hipStream_t st, int mode, int64_t nrows, const int64_t* ptr, const int32_t* col, const double* val,
            const double* x, const double* b, double* y, int lanes);
@@ -20,6 +25,8 @@ void k_gj_invert_f64(hipStream_t st, int nb, int64_t p0, int64_t count, int max_
                      const int64_t* woff, double* W, const int64_t* ooff, double* out, int32_t* status);
 void k_gj_invert_f32(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
                      const int64_t* woff, double* W, const int64_t* ooff, float* out, int32_t* status);
+// Block size used by the patch GEMV for patches of at most max_np rows.
+int patch_apply_threads(int max_np, bool fp32);
 void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
                        const int64_t* ioff, const double* inv, const double* r, double* y);
 void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,

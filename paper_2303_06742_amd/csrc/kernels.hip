@@ -239,39 +239,83 @@ __global__ void __launch_bounds__(256) gj_invert_kernel(int64_t p0, const int64_
   }
   __syncthreads();
   T* o = out + ooff[p];
+  const int ld = inv_ld(n);
   for (int i = wave; i < n; i += nw)
-    for (int j = lane; j < n; j += WAVE) o[int64_t(i) * n + j] = T(M[int64_t(i) * n + src[j]] * scl[j]);
+    for (int j = lane; j < ld; j += WAVE) o[int64_t(i) * ld + j] = j < n ? T(M[int64_t(i) * n + src[j]] * scl[j]) : T(0);
 }
 
 // ---------------------------------------------------------------- patch apply
-// y_P = A_P^{-1} R_P r for every patch; inverse of patch p stored so that
-// element (i, j) of A_P^{-1} is at inv[ioff[p] + j * n + i].
-template <typename T>
-__global__ void __launch_bounds__(256) patch_apply_kernel(int64_t npatch, const int64_t* __restrict__ poff,
+// y_P = A_P^{-1} R_P r for every patch.  The inverse of patch p is stored
+// column by column, element (i, j) of A_P^{-1} at inv[ioff[p] + j * ld + i]
+// with ld = inv_ld(n) (zero padding rows), so one block streams the n*ld
+// values of its patch exactly once, front to back.  Each thread owns RPT
+// consecutive rows and reads them with one 16-byte load per column.
+template <typename T, int RPT>
+struct Vec16;
+template <>
+struct Vec16<double, 2> {
+  using type = double2;
+};
+template <>
+struct Vec16<float, 4> {
+  using type = float4;
+};
+
+template <typename T, int RPT>
+__device__ inline void fma_vec(T* acc, const typename Vec16<T, RPT>::type& v, T s);
+template <>
+__device__ inline void fma_vec<double, 2>(double* acc, const double2& v, double s) {
+  acc[0] += v.x * s;
+  acc[1] += v.y * s;
+}
+template <>
+__device__ inline void fma_vec<float, 4>(float* acc, const float4& v, float s) {
+  acc[0] += v.x * s;
+  acc[1] += v.y * s;
+  acc[2] += v.z * s;
+  acc[3] += v.w * s;
+}
+
+template <typename T, int RPT>
+__global__ void __launch_bounds__(512) patch_apply_kernel(int64_t npatch, const int64_t* __restrict__ poff,
                                                           const int32_t* __restrict__ pdof,
                                                           const int64_t* __restrict__ ioff,
                                                           const T* __restrict__ inv, const double* __restrict__ r,
                                                           double* __restrict__ y) {
+  using V = typename Vec16<T, RPT>::type;
   extern __shared__ char smem[];
   T* rl = reinterpret_cast<T*>(smem);
   const int64_t p = blockIdx.x;
   const int64_t o = poff[p];
   const int n = int(poff[p + 1] - o);
+  const int ld = inv_ld(n);
   for (int i = threadIdx.x; i < n; i += blockDim.x) rl[i] = T(r[pdof[o + i]]);
   __syncthreads();
-  const T* X = inv + ioff[p];
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-    int j = 0;
-    for (; j + 3 < n; j += 4) {
-      a0 += X[int64_t(j) * n + i] * rl[j];
-      a1 += X[int64_t(j + 1) * n + i] * rl[j + 1];
-      a2 += X[int64_t(j + 2) * n + i] * rl[j + 2];
-      a3 += X[int64_t(j + 3) * n + i] * rl[j + 3];
-    }
-    for (; j < n; ++j) a0 += X[int64_t(j) * n + i] * rl[j];
-    y[o + i] = double((a0 + a1) + (a2 + a3));
+  const int i0 = RPT * int(threadIdx.x);
+  if (i0 >= n) return;
+  const V* X = reinterpret_cast<const V*>(inv + ioff[p] + i0);
+  const int ldv = ld / RPT;
+  T a[RPT], b[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) a[q] = b[q] = T(0);
+  int j = 0;
+  for (; j + 7 < n; j += 8) {
+    V v0 = X[int64_t(j) * ldv], v1 = X[int64_t(j + 1) * ldv], v2 = X[int64_t(j + 2) * ldv],
+      v3 = X[int64_t(j + 3) * ldv], v4 = X[int64_t(j + 4) * ldv], v5 = X[int64_t(j + 5) * ldv],
+      v6 = X[int64_t(j + 6) * ldv], v7 = X[int64_t(j + 7) * ldv];
+    fma_vec<T, RPT>(a, v0, rl[j]);
+    fma_vec<T, RPT>(b, v1, rl[j + 1]);
+    fma_vec<T, RPT>(a, v2, rl[j + 2]);
+    fma_vec<T, RPT>(b, v3, rl[j + 3]);
+    fma_vec<T, RPT>(a, v4, rl[j + 4]);
+    fma_vec<T, RPT>(b, v5, rl[j + 5]);
+    fma_vec<T, RPT>(a, v6, rl[j + 6]);
+    fma_vec<T, RPT>(b, v7, rl[j + 7]);
   }
+  for (; j < n; ++j) fma_vec<T, RPT>(a, X[int64_t(j) * ldv], rl[j]);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+    if (i0 + q < n) y[o + i0 + q] = double(a[q] + b[q]);
 }
 
 // d[mu] += winv[mu] * sum of the patch images of mu, in patch order
@@ -286,7 +330,7 @@ __global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr,
 }
 
 // ---------------------------------------------------------------- dense coarse solve
-// y = X b with X stored as Xt row-major (X[i][j] at j*n + i).
+// y = X b with X stored column by column (X[i][j] at j*ld + i, ld = inv_ld(n)).
 __global__ void __launch_bounds__(256) dense_gemv_t_kernel(int n, const double* __restrict__ Xt,
                                                            const double* __restrict__ b, double* __restrict__ y) {
   extern __shared__ double sb[];
@@ -294,13 +338,14 @@ __global__ void __launch_bounds__(256) dense_gemv_t_kernel(int n, const double* 
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const int ld = inv_ld(n);
   double a0 = 0, a1 = 0;
   int j = 0;
   for (; j + 1 < n; j += 2) {
-    a0 += Xt[int64_t(j) * n + i] * sb[j];
-    a1 += Xt[int64_t(j + 1) * n + i] * sb[j + 1];
+    a0 += Xt[int64_t(j) * ld + i] * sb[j];
+    a1 += Xt[int64_t(j + 1) * ld + i] * sb[j + 1];
   }
-  if (j < n) a0 += Xt[int64_t(j) * n + i] * sb[j];
+  if (j < n) a0 += Xt[int64_t(j) * ld + i] * sb[j];
   y[i] = a0 + a1;
 }
 
@@ -461,17 +506,23 @@ void k_gj_invert_f32(hipStream_t st, int nb, int64_t p0, int64_t count, int max_
   if (count) gj_launch<float>(st, nb, p0, count, max_np, poff, woff, W, ooff, out, status);
 }
 
+int patch_apply_threads(int max_np, bool fp32) {
+  const int rpt = fp32 ? 4 : 2;
+  const int t = (inv_ld(max_np) / rpt + 63) / 64 * 64;
+  return t < 64 ? 64 : t;
+}
+
 void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
                        const int64_t* ioff, const double* inv, const double* r, double* y) {
   if (npatch == 0) return;
-  hipLaunchKernelGGL(dev::patch_apply_kernel<double>, dim3(npatch), dim3(256), size_t(max_np) * sizeof(double), st,
-                     npatch, poff, pdof, ioff, inv, r, y);
+  hipLaunchKernelGGL((dev::patch_apply_kernel<double, 2>), dim3(npatch), dim3(patch_apply_threads(max_np, false)),
+                     size_t(max_np) * sizeof(double), st, npatch, poff, pdof, ioff, inv, r, y);
 }
 void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
                        const int64_t* ioff, const float* inv, const double* r, double* y) {
   if (npatch == 0) return;
-  hipLaunchKernelGGL(dev::patch_apply_kernel<float>, dim3(npatch), dim3(256), size_t(max_np) * sizeof(float), st,
-                     npatch, poff, pdof, ioff, inv, r, y);
+  hipLaunchKernelGGL((dev::patch_apply_kernel<float, 4>), dim3(npatch), dim3(patch_apply_threads(max_np, true)),
+                     size_t(max_np) * sizeof(float), st, npatch, poff, pdof, ioff, inv, r, y);
 }
 
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
