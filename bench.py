@@ -57,7 +57,9 @@ def cpu_baseline(cfg, sample_levels):
     from oracle import fgmres, gmg, problem
     scfg = W.scaled(cfg, sample_levels)
     with threadpool_limits(limits=1):
-        prm = problem.Params(rho=scfg.rho, lam=scfg.lam, mu=scfg.mu, alpha=scfg.alpha, c0=scfg.c0, K=scfg.K)
+        Kc = scfg.K_cells()
+        prm = problem.Params(rho=scfg.rho, lam=scfg.lam, mu=scfg.mu, alpha=scfg.alpha, c0=scfg.c0,
+                             K=scfg.K if Kc is None else Kc)
         t0 = time.perf_counter()
         H = gmg.Hierarchy(scfg.dim, scfg.coarse_cells, scfg.levels - 1, scfg.r, scfg.k, scfg.tau, prm,
                           patch_kind=scfg.patch, J=scfg.n_smooth, omega=scfg.omega)
@@ -85,7 +87,8 @@ def main():
     ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3'])
     ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32'])
     ap.add_argument('--no-cpu-baseline', action='store_true')
-    ap.add_argument('--cpu-sample-levels', type=int, default=4)
+    ap.add_argument('--cpu-sample-levels', type=int, default=None,
+                    help='levels of the grid the oracle times (default: 32^2 cells in 2D, 8^3 in 3D)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run a plain 1 GiB device copy first (reference for HBM byte counters)')
     args = ap.parse_args()
@@ -183,7 +186,8 @@ def main():
     S.close()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
-        out['cpu_baseline'] = cpu_baseline(cfg, args.cpu_sample_levels)
+        lv = args.cpu_sample_levels or (4 if cfg.dim == 2 else 2)
+        out['cpu_baseline'] = cpu_baseline(cfg, min(lv, cfg.levels))
     print(json.dumps(out), flush=True)
 
 

@@ -1,7 +1,8 @@
 """Geometric multigrid V-cycle with the patchwise Vanka smoother (Sec. 4).
 
 * Levels l = 0..L on N_l = N_c 2^l cells per axis; A_l is re-assembled on each
-  level (the paper uses deal.II level matrices).
+  level (the paper uses deal.II level matrices); a per-cell permeability is
+  averaged over the children of each coarse cell.
 * Prolongation = interpolation of the coarse finite element function at the
   fine nodes, per field, component and Gauss-Radau node (no coarsening in
   time); restriction = its transpose (Sec. 4, list of GMRES-GMG ingredients).
@@ -89,6 +90,26 @@ def patch_dofs(blocks, k, cells):
     return np.sort(np.concatenate([m * blocks.ns + one for m in range(k + 1)]))
 
 
+def coarsen_K(K, d, Nf):
+    """Per-cell K of the next coarser mesh: the mean over the 2^d children of each cell."""
+    Kf = np.asarray(K, dtype=float).reshape((Nf,) * d)  # index order [z][y][x]
+    return Kf.reshape(*([Nf // 2, 2] * d)).mean(axis=tuple(range(1, 2 * d, 2))).reshape(-1)
+
+
+def level_params(prm, d, Nfine, N):
+    """Parameters of the level with N cells per axis; a per-cell K given on the finest
+    mesh is averaged over the children on every coarser level."""
+    if np.ndim(prm.K) == 0:
+        return prm
+    K = np.asarray(prm.K, dtype=float)
+    n = Nfine
+    while n > N:
+        K = coarsen_K(K, d, n)
+        n //= 2
+    return problem.Params(rho=prm.rho, lam=prm.lam, mu=prm.mu, alpha=prm.alpha, c0=prm.c0, K=K,
+                          gamma_a=prm.gamma_a, gamma_b=prm.gamma_b)
+
+
 class Level:
     def __init__(self, d, N, r, k, tau, prm, patch_kind):
         self.prob = problem.SlabProblem(d, N, r, k, tau, prm)
@@ -131,7 +152,8 @@ class Hierarchy:
 
     def __init__(self, d, Nc, L, r, k, tau, prm, patch_kind='vertex', J=4, omega=0.7):
         self.J, self.omega = J, omega
-        self.levels = [Level(d, Nc * 2 ** l, r, k, tau, prm, patch_kind) for l in range(L + 1)]
+        self.levels = [Level(d, Nc * 2 ** l, r, k, tau, level_params(prm, d, Nc * 2 ** L, Nc * 2 ** l), patch_kind)
+                       for l in range(L + 1)]
         for lev in self.levels[1:]:
             lev.build_smoother()
         self.P = [None] + [prolongation(self.levels[l - 1].prob.blocks, self.levels[l].prob.blocks, k)

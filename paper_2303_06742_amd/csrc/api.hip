@@ -123,7 +123,7 @@ struct stgmg_handle {
   int64_t bytes = 0;
   // coarse solve
   int n0 = 0;
-  DArr<double> coarse_inv;
+  DArr<double> coarse_inv, coarse_part;
   // finest level data for the right-hand side
   stgmg::LevelHost fine_info;  // sizes, Kcell (no matrices)
   stgmg::Material mat{};
@@ -229,7 +229,7 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
 
 void vcycle(stgmg_handle* h, int l, const double* b, double* d) {
   if (l == 0) {
-    stgmg::k_dense_gemv_t(h->st, h->n0, h->coarse_inv.p, b, d);
+    stgmg::k_dense_gemv_t(h->st, h->n0, h->coarse_inv.p, b, h->coarse_part.p, d);
     return;
   }
   LevelDev& L = h->lv[l];
@@ -313,22 +313,49 @@ void build(stgmg_handle* h) {
     D.d.alloc(H.n, ctr);
     D.r.alloc(H.n, ctr);
     if (l == 0) {
-      if (H.n > 1400) throw ApiError(STGMG_ERR_UNSUPPORTED, "coarsest level too large for the dense inverse");
+      if (H.n > 20000) throw ApiError(STGMG_ERR_UNSUPPORTED, "coarsest level too large for the dense inverse");
       h->n0 = int(H.n);
       std::vector<double> W0 = dense_transposed(H.A);
       DArr<double> Wd;
       Wd.upload(W0, h->st, nullptr);
+      W0 = std::vector<double>();
       h->coarse_inv.alloc(H.n * stgmg::inv_ld(int(H.n)), ctr);
-      std::vector<int64_t> poff0 = {0, H.n}, zero = {0};
-      DArr<int64_t> poffd, woffd;
-      poffd.upload(poff0, h->st, nullptr);
-      woffd.upload(zero, h->st, nullptr);
+      h->coarse_part.alloc(int64_t(stgmg::dense_gemv_chunks(int(H.n))) * H.n, ctr);
       DArr<int32_t> stat;
       stat.upload(std::vector<int32_t>(1, 0), h->st, nullptr);
       const int nb = stgmg::gj_panel_width(int(H.n), lds_limit());
-      if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "coarse inverse does not fit in LDS");
-      stgmg::k_gj_invert_f64(h->st, nb, 0, 1, int(H.n), poffd.p, woffd.p, Wd.p, woffd.p, h->coarse_inv.p, stat.p);
-      HIPCHK(hipGetLastError());
+      if (nb != 0) {
+        // one workgroup holds the whole inversion
+        std::vector<int64_t> poff0 = {0, H.n}, zero = {0};
+        DArr<int64_t> poffd, woffd;
+        poffd.upload(poff0, h->st, nullptr);
+        woffd.upload(zero, h->st, nullptr);
+        stgmg::k_gj_invert_f64(h->st, nb, 0, 1, int(H.n), poffd.p, woffd.p, Wd.p, woffd.p, h->coarse_inv.p, stat.p);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->st));
+      } else {
+        // panels over many workgroups
+        const int n0 = int(H.n), pnb = 32;
+        DArr<double> scl, Wb;
+        DArr<int> perm, src;
+        scl.alloc(n0, nullptr);
+        Wb.alloc(int64_t(pnb) * n0, nullptr);
+        perm.alloc(n0, nullptr);
+        src.alloc(n0, nullptr);
+        stgmg::k_gj_large_rowscale(h->st, n0, Wd.p, scl.p);
+        for (int k0 = 0; k0 < n0; k0 += pnb)
+          stgmg::k_gj_large_step(h->st, n0, k0, std::min(pnb, n0 - k0), Wd.p, perm.p, Wb.p, stat.p);
+        HIPCHK(hipGetLastError());
+        std::vector<int> perm_h(n0), src_h(n0);
+        HIPCHK(hipMemcpyAsync(perm_h.data(), perm.p, n0 * sizeof(int), hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipStreamSynchronize(h->st));
+        for (int j = 0; j < n0; ++j) src_h[j] = j;
+        for (int k = n0 - 1; k >= 0; --k) std::swap(src_h[k], src_h[perm_h[k]]);
+        HIPCHK(hipMemcpyAsync(src.p, src_h.data(), n0 * sizeof(int), hipMemcpyHostToDevice, h->st));
+        stgmg::k_gj_large_output(h->st, n0, Wd.p, src.p, scl.p, h->coarse_inv.p);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(h->st));
+      }
       int32_t s = 0;
       HIPCHK(hipMemcpyAsync(&s, stat.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
       HIPCHK(hipStreamSynchronize(h->st));

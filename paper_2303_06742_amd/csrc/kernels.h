@@ -33,7 +33,14 @@ void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t
                        const int64_t* ioff, const float* inv, const double* r, double* y);
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
                     const double* y, double* d);
-void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* y);
+// y = X b for a dense inverse in the padded column layout; part holds dense_gemv_chunks(n) * n doubles
+int dense_gemv_chunks(int n);
+void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* part, double* y);
+// Multi-workgroup Gauss-Jordan of one row-major n x n matrix (panels of nb <= 32 columns):
+// rowscale once, one step per panel, then the un-permuted, re-scaled output.
+void k_gj_large_rowscale(hipStream_t st, int n, double* M, double* scl);
+void k_gj_large_step(hipStream_t st, int n, int k0, int nb, double* M, int* perm, double* Wb, int32_t* status);
+void k_gj_large_output(hipStream_t st, int n, const double* M, const int* src, const double* scl, double* out);
 int dot_blocks(int64_t n);
 // out[v] (+)= V_v . w for v < m (V rows of length n, leading dimension ldv); partials >= m * dot_blocks(n)
 void k_multi_dot(hipStream_t st, const double* V, int64_t ldv, int m, const double* w, int64_t n, double* partials,

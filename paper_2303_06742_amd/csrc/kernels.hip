@@ -331,22 +331,176 @@ __global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr,
 
 // ---------------------------------------------------------------- dense coarse solve
 // y = X b with X stored column by column (X[i][j] at j*ld + i, ld = inv_ld(n)).
-__global__ void __launch_bounds__(256) dense_gemv_t_kernel(int n, const double* __restrict__ Xt,
-                                                           const double* __restrict__ b, double* __restrict__ y) {
-  extern __shared__ double sb[];
-  for (int j = threadIdx.x; j < n; j += blockDim.x) sb[j] = b[j];
+// Block (bx, by) sums columns [by*GEMV_COLS, ...) for rows [bx*256, ...) into
+// part[by][i]; dense_gemv_reduce adds the column chunks in order.
+constexpr int GEMV_COLS = 1024;
+__global__ void __launch_bounds__(256) dense_gemv_part_kernel(int n, const double* __restrict__ Xt,
+                                                              const double* __restrict__ b,
+                                                              double* __restrict__ part) {
+  __shared__ double sb[GEMV_COLS];
+  const int j0 = blockIdx.y * GEMV_COLS, j1 = min(n, j0 + GEMV_COLS);
+  for (int j = j0 + threadIdx.x; j < j1; j += blockDim.x) sb[j - j0] = b[j];
   __syncthreads();
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int ld = inv_ld(n);
   double a0 = 0, a1 = 0;
-  int j = 0;
-  for (; j + 1 < n; j += 2) {
-    a0 += Xt[int64_t(j) * ld + i] * sb[j];
-    a1 += Xt[int64_t(j + 1) * ld + i] * sb[j + 1];
+  int j = j0;
+  for (; j + 1 < j1; j += 2) {
+    a0 += Xt[int64_t(j) * ld + i] * sb[j - j0];
+    a1 += Xt[int64_t(j + 1) * ld + i] * sb[j + 1 - j0];
   }
-  if (j < n) a0 += Xt[int64_t(j) * ld + i] * sb[j];
-  y[i] = a0 + a1;
+  if (j < j1) a0 += Xt[int64_t(j) * ld + i] * sb[j - j0];
+  part[int64_t(blockIdx.y) * n + i] = a0 + a1;
+}
+
+__global__ void dense_gemv_reduce_kernel(int n, int nchunk, const double* __restrict__ part, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[int64_t(c) * n + i];
+  y[i] = s;
+}
+
+// ---------------------------------------------------------------- large Gauss-Jordan
+// The same blocked Gauss-Jordan as gj_invert_kernel for one matrix too large
+// for a workgroup: per panel of nb columns, gj_large_panel factors the n x nb
+// panel in place (one workgroup), gj_large_swap applies the panel's row swaps to
+// the other columns and copies the pivot rows to Wb, gj_large_update performs
+// the rank-nb update over 2D tiles.  M is row-major n x n.
+__global__ void __launch_bounds__(1024) gj_large_rowscale_kernel(int n, double* __restrict__ M,
+                                                                 double* __restrict__ scl) {
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+  const int i = blockIdx.x * (blockDim.x / WAVE) + wave;
+  if (i >= n) return;
+  double m = 0.0;
+  for (int j = lane; j < n; j += WAVE) m = fmax(m, fabs(M[int64_t(i) * n + j]));
+  for (int off = WAVE / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+  const double s = (m > 0.0 && isfinite(m)) ? ldexp(1.0, -ilogb(m)) : 1.0;
+  for (int j = lane; j < n; j += WAVE) M[int64_t(i) * n + j] *= s;
+  if (lane == 0) scl[i] = s;
+}
+
+__global__ void __launch_bounds__(1024) gj_large_panel_kernel(int n, int k0, int nb, double* __restrict__ M,
+                                                              int* __restrict__ perm, int32_t* __restrict__ status) {
+  __shared__ double rv[1024 / WAVE];
+  __shared__ int ri[1024 / WAVE];
+  __shared__ int s_piv;
+  const int tid = threadIdx.x, bs = blockDim.x, wave = tid / WAVE, lane = tid % WAVE, nw = bs / WAVE;
+  for (int c = 0; c < nb; ++c) {
+    const int k = k0 + c;
+    double bv = -1.0;
+    int bi = n;
+    for (int i = k + tid; i < n; i += bs) {
+      const double v = fabs(M[int64_t(i) * n + k]);
+      if (v > bv) {
+        bv = v;
+        bi = i;
+      }
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      rv[wave] = bv;
+      ri[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = rv[0];
+      int ii = ri[0];
+      for (int w = 1; w < nw; ++w)
+        if (rv[w] > v || (rv[w] == v && ri[w] < ii)) {
+          v = rv[w];
+          ii = ri[w];
+        }
+      if (!(v > 0.0) || !isfinite(v) || ii >= n) {
+        status[0] = 1;
+        ii = k;
+      }
+      perm[k] = ii;
+      s_piv = ii;
+    }
+    __syncthreads();
+    const int q = s_piv;
+    if (q != k && tid < nb) {
+      const double t = M[int64_t(k) * n + k0 + tid];
+      M[int64_t(k) * n + k0 + tid] = M[int64_t(q) * n + k0 + tid];
+      M[int64_t(q) * n + k0 + tid] = t;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double piv = M[int64_t(k) * n + k];
+      if (piv == 0.0 || !isfinite(piv)) piv = 1.0;
+      const double rp = 1.0 / piv;
+      M[int64_t(k) * n + k] = 1.0;
+      for (int cc = 0; cc < nb; ++cc) M[int64_t(k) * n + k0 + cc] *= rp;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += bs) {
+      if (i == k) continue;
+      double* row = M + int64_t(i) * n + k0;
+      const double f = row[c];
+      row[c] = 0.0;
+      for (int cc = 0; cc < nb; ++cc) row[cc] -= f * M[int64_t(k) * n + k0 + cc];
+    }
+    __syncthreads();
+  }
+}
+
+// columns outside the panel: apply the row swaps of this panel, copy the pivot rows to Wb[c][j]
+__global__ void gj_large_swap_kernel(int n, int k0, int nb, double* __restrict__ M, const int* __restrict__ perm,
+                                     double* __restrict__ Wb) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + nb)) return;
+  for (int c = 0; c < nb; ++c) {
+    const int k = k0 + c, q = perm[k];
+    if (q != k) {
+      const double a = M[int64_t(k) * n + j];
+      M[int64_t(k) * n + j] = M[int64_t(q) * n + j];
+      M[int64_t(q) * n + j] = a;
+    }
+  }
+  for (int c = 0; c < nb; ++c) Wb[int64_t(c) * n + j] = M[int64_t(k0 + c) * n + j];
+}
+
+// M[i][j] = [i not in panel rows] M[i][j] + sum_c M[i][k0+c] Wb[c][j], j outside the panel
+constexpr int GJL_ROWS = 128;
+__global__ void __launch_bounds__(256) gj_large_update_kernel(int n, int k0, int nb, double* __restrict__ M,
+                                                              const double* __restrict__ Wb) {
+  __shared__ double pn[GJL_ROWS * 32];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i0 = blockIdx.y * GJL_ROWS, i1 = min(n, i0 + GJL_ROWS);
+  for (int t = threadIdx.x; t < (i1 - i0) * nb; t += blockDim.x) {
+    const int i = t / nb, c = t % nb;
+    pn[i * 32 + c] = M[int64_t(i0 + i) * n + k0 + c];
+  }
+  __syncthreads();
+  if (j >= n || (j >= k0 && j < k0 + nb)) return;
+  double w[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) w[c] = c < nb ? Wb[int64_t(c) * n + j] : 0.0;
+  for (int i = i0; i < i1; ++i) {
+    double acc = (i >= k0 && i < k0 + nb) ? 0.0 : M[int64_t(i) * n + j];
+#pragma unroll
+    for (int c = 0; c < 32; ++c) acc += pn[(i - i0) * 32 + c] * w[c];
+    M[int64_t(i) * n + j] = acc;
+  }
+}
+
+// out[i * ld + j] = M[i][src[j]] * scl[j] (zero padding for j >= n)
+__global__ void gj_large_output_kernel(int n, const double* __restrict__ M, const int* __restrict__ src,
+                                       const double* __restrict__ scl, double* __restrict__ out) {
+  const int ld = inv_ld(n);
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (j >= ld) return;
+  out[int64_t(i) * ld + j] = j < n ? M[int64_t(i) * n + src[j]] * scl[j] : 0.0;
 }
 
 // ---------------------------------------------------------------- BLAS-1 (FGMRES)
@@ -532,9 +686,26 @@ void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_
                      d);
 }
 
-void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* y) {
-  hipLaunchKernelGGL(dev::dense_gemv_t_kernel, dim3(blocks_for(n, 256)), dim3(256), size_t(n) * sizeof(double), st,
-                     n, Xt, b, y);
+int dense_gemv_chunks(int n) { return (n + dev::GEMV_COLS - 1) / dev::GEMV_COLS; }
+
+void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* part, double* y) {
+  const int nc = dense_gemv_chunks(n);
+  hipLaunchKernelGGL(dev::dense_gemv_part_kernel, dim3(blocks_for(n, 256), nc), dim3(256), 0, st, n, Xt, b, part);
+  hipLaunchKernelGGL(dev::dense_gemv_reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, nc, part, y);
+}
+
+void k_gj_large_rowscale(hipStream_t st, int n, double* M, double* scl) {
+  hipLaunchKernelGGL(dev::gj_large_rowscale_kernel, dim3(blocks_for(n, 16)), dim3(1024), 0, st, n, M, scl);
+}
+void k_gj_large_step(hipStream_t st, int n, int k0, int nb, double* M, int* perm, double* Wb, int32_t* status) {
+  hipLaunchKernelGGL(dev::gj_large_panel_kernel, dim3(1), dim3(1024), 0, st, n, k0, nb, M, perm, status);
+  hipLaunchKernelGGL(dev::gj_large_swap_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, k0, nb, M, perm, Wb);
+  hipLaunchKernelGGL(dev::gj_large_update_kernel, dim3(blocks_for(n, 256), blocks_for(n, dev::GJL_ROWS)), dim3(256),
+                     0, st, n, k0, nb, M, Wb);
+}
+void k_gj_large_output(hipStream_t st, int n, const double* M, const int* src, const double* scl, double* out) {
+  hipLaunchKernelGGL(dev::gj_large_output_kernel, dim3(blocks_for(inv_ld(n), 256), n), dim3(256), 0, st, n, M, src,
+                     scl, out);
 }
 
 int dot_blocks(int64_t n) {

@@ -131,3 +131,18 @@ def test_fgmres_finite_termination_and_restart():
     assert info['iters'] <= n and np.linalg.norm(A @ x - b) < 1e-11 * np.linalg.norm(b)
     x2, info2 = fgmres.fgmres(A, b, lambda v: v, rtol=1e-12, restart=3, maxiter=500)
     assert info2['converged'] and np.linalg.norm(A @ x2 - b) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_coarsened_permeability_is_child_mean():
+    """Coarse-level K (per cell) = mean of the 2^d children, in lexicographic cell order."""
+    for d in (2, 3):
+        Nf = 4
+        K = np.arange(Nf ** d, dtype=float)
+        Kc = gmg.coarsen_K(K, d, Nf)
+        for c in range(2 ** d):
+            ci = [(c >> a) & 1 for a in range(d)]  # coarse multi-index (x, y[, z]) with 2 cells per axis
+            kids = []
+            for ch in range(2 ** d):
+                fi = [2 * ci[a] + ((ch >> a) & 1) for a in range(d)]
+                kids.append(sum(fi[a] * Nf ** a for a in range(d)))
+            assert Kc[sum(ci[a] * 2 ** a for a in range(d))] == np.mean(K[kids])
