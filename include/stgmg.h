@@ -43,6 +43,7 @@ extern "C" {
 typedef int32_t stgmg_status;
 #define STGMG_OK 0
 #define STGMG_NOT_CONVERGED 1        /* x holds the last iterate */
+#define STGMG_PENDING 2              /* server: the request has not finished yet */
 #define STGMG_ERR_INVALID_ARG (-1)
 #define STGMG_ERR_UNSUPPORTED (-2)
 #define STGMG_ERR_OOM (-3)
@@ -75,6 +76,8 @@ typedef struct {
   double K;              /* permeability K*I when K_cells == NULL */
   const double* K_cells; /* host, optional: K per fine cell, lexicographic (x fastest);
                             coarse cells take the mean of their 2^d children. Copied. */
+  int32_t graph;         /* V-cycle as a captured HIP graph: -1 automatic (hierarchies below
+                            2^21 fine unknowns, where launch latency matters), 0 never, 1 always */
 } stgmg_params;
 
 typedef struct {
@@ -91,8 +94,9 @@ typedef struct {
  * operators (Eq:DefAab, re-assembled on every level), grid transfers, patch
  * tables, the patch inverses A_P^{-1} of Def:VankaOP (extracted from the
  * assembled level matrix and inverted on the GPU) and the coarse inverse.
- * hip_stream: a hipStream_t (NULL = default stream) on which all later work of
- * this handle is enqueued.  Returns STGMG_ERR_SINGULAR_PATCH if any A_P is
+ * hip_stream: the caller's hipStream_t (NULL = default stream).  The handle
+ * runs on a stream of its own; every call first waits for the work already
+ * enqueued on hip_stream and returns after its own work has completed.  Returns STGMG_ERR_SINGULAR_PATCH if any A_P is
  * singular, STGMG_ERR_OOM if device memory runs out. */
 stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_handle** out);
 
@@ -161,6 +165,46 @@ stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches,
                                double* bytes_per_launch);
 
 stgmg_status stgmg_destroy(stgmg_handle* h);
+
+/* Closed-form sizes for admission control, without building anything: n (unknowns
+ * of the finest level, the length of rhs and x), the device bytes a handle holds
+ * after stgmg_setup plus the FGMRES workspace for `restart`, and the peak bytes
+ * during setup (resident + temporary extraction/inversion buffers).  Exact up to
+ * allocation granularity. */
+stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_t* n_dofs, int64_t* resident_bytes,
+                             int64_t* setup_peak_bytes);
+
+/* Solve count independent problems (Problem 4.1 each) at the same time: every
+ * handle runs on its own stream, driven by its own host thread (at most 16 at
+ * once); kernels of different problems overlap on the GPU.  Each problem's result
+ * is bitwise the same as that of stgmg_solve alone.  statuses[i] and infos[i]
+ * (either may be NULL) receive the per-problem outcome; the return value is
+ * STGMG_OK if every problem returned STGMG_OK, else the first non-OK status. */
+stgmg_status stgmg_solve_batch(int32_t count, stgmg_handle* const* handles, const double* const* rhs_dev,
+                               double* const* x_dev, double rtol, int32_t restart, int32_t max_iters,
+                               stgmg_info* infos, stgmg_status* statuses);
+
+/* Serving loop for a stream of solve requests (continuous batching): requests
+ * are admitted as soon as their footprint fits in hbm_budget bytes next to the
+ * running and resident problems; up to max_slots run at once, each with its own
+ * stream and host thread; hierarchies of finished requests with a non-zero
+ * problem_key stay resident (at most resident_max, least recently used evicted
+ * first) and are reused by later requests with the same key (follow-on slabs). */
+typedef struct stgmg_server stgmg_server;
+stgmg_status stgmg_server_create(int64_t hbm_budget, int32_t max_slots, int32_t resident_max, stgmg_server** out);
+/* Queue a request: params (copied, K_cells included), problem_key (0 = never
+ * reused; equal keys must mean equal params), rhs_host (n doubles, copied; n from
+ * stgmg_footprint), x0 = 0, relative tolerance rtol, restart 30.  STGMG_ERR_OOM if
+ * the problem can never fit the budget. */
+stgmg_status stgmg_server_submit(stgmg_server* srv, const stgmg_params* params, uint64_t problem_key,
+                                 const double* rhs_host, double rtol, uint64_t* ticket);
+/* STGMG_PENDING while the request is queued or running; otherwise its final
+ * status, with x_host (n doubles, may be NULL), info and latency_ms (submit to
+ * completion, may be NULL) filled.  A finished ticket can be polled again. */
+stgmg_status stgmg_server_poll(stgmg_server* srv, uint64_t ticket, double* x_host, stgmg_info* info,
+                               double* latency_ms);
+/* Waits for all queued and running requests, then frees everything. */
+stgmg_status stgmg_server_destroy(stgmg_server* srv);
 
 const char* stgmg_status_string(stgmg_status s);
 const char* stgmg_last_error(void);

@@ -20,6 +20,7 @@ SOURCES = [
     ('host_setup.cpp', False),
     ('kernels.hip', True),
     ('api.hip', True),
+    ('server.cpp', True),
 ]
 
 

@@ -20,6 +20,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 STGMG_OK = 0
 STGMG_NOT_CONVERGED = 1
+STGMG_PENDING = 2
 STGMG_ERR_INVALID_ARG = -1
 STGMG_ERR_UNSUPPORTED = -2
 STGMG_ERR_OOM = -3
@@ -38,7 +39,7 @@ class Params(ctypes.Structure):
                 ('smoother_prec', ctypes.c_int32), ('n_smooth', ctypes.c_int32), ('omega', ctypes.c_double),
                 ('tau', ctypes.c_double), ('rho', ctypes.c_double), ('lam', ctypes.c_double),
                 ('mu', ctypes.c_double), ('alpha', ctypes.c_double), ('c0', ctypes.c_double),
-                ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p)]
+                ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p), ('graph', ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -78,6 +79,15 @@ stgmg_get_patch_inverse = _decl('stgmg_get_patch_inverse', [_H, _I32, _I64, ctyp
 stgmg_profile_enable = _decl('stgmg_profile_enable', [_H, _I32])
 stgmg_profile_get = _decl('stgmg_profile_get', [_H, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_D),
                                                 ctypes.POINTER(_D)])
+stgmg_footprint = _decl('stgmg_footprint', [ctypes.POINTER(Params), _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                                            ctypes.POINTER(_I64)])
+stgmg_solve_batch = _decl('stgmg_solve_batch', [_I32, ctypes.POINTER(_H), ctypes.POINTER(_P), ctypes.POINTER(_P), _D,
+                                                _I32, _I32, ctypes.POINTER(Info), ctypes.POINTER(_S)])
+stgmg_server_create = _decl('stgmg_server_create', [_I64, _I32, _I32, ctypes.POINTER(_P)])
+stgmg_server_submit = _decl('stgmg_server_submit', [_P, ctypes.POINTER(Params), ctypes.c_uint64, _P, _D,
+                                                    ctypes.POINTER(ctypes.c_uint64)])
+stgmg_server_poll = _decl('stgmg_server_poll', [_P, ctypes.c_uint64, _P, ctypes.POINTER(Info), ctypes.POINTER(_D)])
+stgmg_server_destroy = _decl('stgmg_server_destroy', [_P])
 stgmg_destroy = _decl('stgmg_destroy', [_H])
 stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
 stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
@@ -85,8 +95,8 @@ stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
 EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
             'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs',
             'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_profile_enable', 'stgmg_profile_get',
-            'stgmg_destroy', 'stgmg_status_string',
-            'stgmg_last_error']
+            'stgmg_destroy', 'stgmg_status_string', 'stgmg_last_error', 'stgmg_footprint', 'stgmg_solve_batch',
+            'stgmg_server_create', 'stgmg_server_submit', 'stgmg_server_poll', 'stgmg_server_destroy']
 
 
 class StgmgError(RuntimeError):
@@ -112,21 +122,97 @@ def _dptr(t, n=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def make_params(cfg, precision=None, graph=-1):
+    """(Params, K array kept alive by the caller) for a workloads.Config."""
+    K = cfg.K_cells()
+    if K is not None:
+        K = np.ascontiguousarray(K, dtype=np.float64)
+    p = Params(dim=cfg.dim, coarse_cells=cfg.coarse_cells, levels=cfg.levels, r=cfg.r, k=cfg.k,
+               patch=PATCH[cfg.patch], smoother_prec=PREC[precision or cfg.precision], n_smooth=cfg.n_smooth,
+               omega=cfg.omega, tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
+               K=cfg.K, K_cells=None if K is None else K.ctypes.data, graph=graph)
+    return p, K
+
+
+def footprint(cfg, precision=None, restart=30, graph=-1):
+    """Closed-form (n, resident bytes, setup peak bytes) without building anything."""
+    p, _K = make_params(cfg, precision, graph)
+    n, res, peak = _I64(), _I64(), _I64()
+    check(stgmg_footprint(ctypes.byref(p), restart, ctypes.byref(n), ctypes.byref(res), ctypes.byref(peak)),
+          'stgmg_footprint')
+    return n.value, res.value, peak.value
+
+
+def solve_batch(solvers, rhs, xs, rtol=1e-8, restart=30, max_iters=1000):
+    """Solve independent problems at once (stgmg_solve_batch); returns per-problem info dicts."""
+    cnt = len(solvers)
+    hs = (_H * cnt)(*[s.h for s in solvers])
+    rp = (_P * cnt)(*[_dptr(r, s.n).value for r, s in zip(rhs, solvers)])
+    xp = (_P * cnt)(*[_dptr(x, s.n).value for x, s in zip(xs, solvers)])
+    infos = (Info * cnt)()
+    sts = (_S * cnt)()
+    stgmg_solve_batch(cnt, hs, rp, xp, rtol, restart, max_iters, infos, sts)
+    for i in range(cnt):
+        check(sts[i], f'stgmg_solve_batch[{i}]', allow=(STGMG_OK, STGMG_NOT_CONVERGED))
+    return [infos[i].as_dict() for i in range(cnt)]
+
+
+class Server:
+    """The serving loop (stgmg_server_*): host vectors in, host vectors out."""
+
+    def __init__(self, hbm_budget, max_slots=8, resident_max=16):
+        s = _P()
+        check(stgmg_server_create(hbm_budget, max_slots, resident_max, ctypes.byref(s)), 'stgmg_server_create')
+        self.s = s
+        self.n = {}
+
+    def submit(self, cfg, rhs, key=0, rtol=1e-8, precision=None):
+        p, _K = make_params(cfg, precision)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        t = ctypes.c_uint64()
+        check(stgmg_server_submit(self.s, ctypes.byref(p), key, rhs.ctypes.data_as(_P), rtol, ctypes.byref(t)),
+              'stgmg_server_submit')
+        self.n[t.value] = rhs.shape[0]
+        return t.value
+
+    def poll(self, ticket):
+        """None while pending, else (status, x, info, latency_ms)."""
+        x = np.empty(self.n[ticket])
+        info = Info()
+        lat = _D()
+        st = stgmg_server_poll(self.s, ticket, x.ctypes.data_as(_P), ctypes.byref(info), ctypes.byref(lat))
+        if st == STGMG_PENDING:
+            return None
+        return st, x, info.as_dict(), lat.value
+
+    def wait(self, ticket, poll_s=0.0005):
+        import time
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            time.sleep(poll_s)
+
+    def close(self):
+        if getattr(self, 's', None):
+            stgmg_server_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Solver:
     """One problem hierarchy (stgmg_setup) and the calls on it."""
 
-    def __init__(self, cfg, precision=None, stream=None):
+    def __init__(self, cfg, precision=None, stream=None, graph=-1):
         import torch
         self._torch = torch
         self.cfg = cfg
-        prec = precision or cfg.precision
-        self._K = cfg.K_cells()
-        if self._K is not None:
-            self._K = np.ascontiguousarray(self._K, dtype=np.float64)
-        p = Params(dim=cfg.dim, coarse_cells=cfg.coarse_cells, levels=cfg.levels, r=cfg.r, k=cfg.k,
-                   patch=PATCH[cfg.patch], smoother_prec=PREC[prec], n_smooth=cfg.n_smooth, omega=cfg.omega,
-                   tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0, K=cfg.K,
-                   K_cells=None if self._K is None else self._K.ctypes.data)
+        p, self._K = make_params(cfg, precision, graph)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _H()
         check(stgmg_setup(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), 'stgmg_setup')

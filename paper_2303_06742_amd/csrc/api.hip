@@ -37,15 +37,18 @@ struct ApiError : std::runtime_error {
     }                                                                                                 \
   } while (0)
 
-// Owning device array.
+// Owning device array, allocated and freed stream-ordered on the stream given
+// at allocation (the owning handle's stream), so that releasing one problem's
+// memory does not synchronise the device for the other problems.
 template <class T>
 struct DArr {
   T* p = nullptr;
   int64_t n = 0;
+  hipStream_t s = nullptr;
   DArr() = default;
   DArr(const DArr&) = delete;
   DArr& operator=(const DArr&) = delete;
-  DArr(DArr&& o) noexcept : p(o.p), n(o.n) {
+  DArr(DArr&& o) noexcept : p(o.p), n(o.n), s(o.s) {
     o.p = nullptr;
     o.n = 0;
   }
@@ -54,6 +57,7 @@ struct DArr {
       release();
       p = o.p;
       n = o.n;
+      s = o.s;
       o.p = nullptr;
       o.n = 0;
     }
@@ -61,18 +65,19 @@ struct DArr {
   }
   ~DArr() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, s);
     p = nullptr;
     n = 0;
   }
-  void alloc(int64_t count, int64_t* counter) {
+  void alloc(int64_t count, int64_t* counter, hipStream_t stream) {
     release();
-    if (count > 0) HIPCHK(hipMalloc(&p, size_t(count) * sizeof(T)));
+    s = stream;
+    if (count > 0) HIPCHK(hipMallocAsync(reinterpret_cast<void**>(&p), size_t(count) * sizeof(T), s));
     n = count;
     if (counter) *counter += count * int64_t(sizeof(T));
   }
   void upload(const std::vector<T>& h, hipStream_t st, int64_t* counter) {
-    alloc(int64_t(h.size()), counter);
+    alloc(int64_t(h.size()), counter, st);
     if (!h.empty()) HIPCHK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
   }
 };
@@ -117,7 +122,13 @@ struct LevelDev {
 
 struct stgmg_handle {
   stgmg_params prm{};
-  hipStream_t st = nullptr;
+  hipStream_t st = nullptr;      // the handle's own stream (default priority, non-blocking)
+  hipStream_t caller = nullptr;  // the caller's stream: each call waits for it first
+  hipEvent_t enter_ev = nullptr;
+  // V-cycle graph: z = B r with r read from gin and z written to gout
+  bool use_graph = false;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
   int L = 0;  // finest level index
   std::vector<LevelDev> lv;
   int64_t bytes = 0;
@@ -138,19 +149,75 @@ struct stgmg_handle {
   int m_alloc = 0;
   DArr<double> V, Z, w, partials, hdev, ydev;
   double* hhost = nullptr;  // pinned
+  DArr<double> gin, gout;
   ~stgmg_handle() {
+    if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (enter_ev) (void)hipEventDestroy(enter_ev);
+    if (st) (void)hipStreamSynchronize(st);
     if (hhost) (void)hipHostFree(hhost);
     for (auto& v : ev)
       for (auto& e : v) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
       }
+    release_device_arrays();
+    if (st) (void)hipStreamDestroy(st);
   }
+  // device arrays are members and would be freed after the destructor body;
+  // they are released first so the stream is destroyed last
+  void release_device_arrays();
 };
+
+void stgmg_handle::release_device_arrays() {
+  lv.clear();
+  coarse_inv.release();
+  coarse_part.release();
+  MM.ptr.release();
+  MM.col.release();
+  MM.val.release();
+  e_dev.release();
+  tmp_ns.release();
+  src_buf.release();
+  V.release();
+  Z.release();
+  w.release();
+  partials.release();
+  hdev.release();
+  ydev.release();
+  gin.release();
+  gout.release();
+}
 
 namespace {
 
 using stgmg::LevelHost;
+
+void vcycle(stgmg_handle* h, int l, const double* b, double* d);
+
+// Order the handle's stream after the work enqueued on the caller's stream.
+void enter(stgmg_handle* h) {
+  HIPCHK(hipEventRecord(h->enter_ev, h->caller));
+  HIPCHK(hipStreamWaitEvent(h->st, h->enter_ev, 0));
+}
+
+// z = B r on the finest level: graph replay (through gin/gout) or direct launches.
+void apply_B(stgmg_handle* h, const double* r, double* z) {
+  if (!h->use_graph || h->prof) {
+    vcycle(h, h->L, r, z);
+    return;
+  }
+  const int64_t n = h->lv[h->L].n;
+  if (!h->graph_exec) {
+    HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+    vcycle(h, h->L, h->gin.p, h->gout.p);
+    HIPCHK(hipStreamEndCapture(h->st, &h->graph));
+    HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+  }
+  HIPCHK(hipMemcpyAsync(h->gin.p, r, n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipGraphLaunch(h->graph_exec, h->st));
+  HIPCHK(hipMemcpyAsync(z, h->gout.p, n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+}
 
 void check_params(const stgmg_params* p) {
   if (!p) throw ApiError(STGMG_ERR_INVALID_ARG, "params is NULL");
@@ -309,20 +376,20 @@ void build(stgmg_handle* h) {
     D.n = H.n;
     D.ns = H.ns;
     D.A.upload(H.A, h->st, ctr);
-    D.b.alloc(H.n, ctr);
-    D.d.alloc(H.n, ctr);
-    D.r.alloc(H.n, ctr);
+    D.b.alloc(H.n, ctr, h->st);
+    D.d.alloc(H.n, ctr, h->st);
+    D.r.alloc(H.n, ctr, h->st);
     if (l == 0) {
       if (H.n > 20000) throw ApiError(STGMG_ERR_UNSUPPORTED, "coarsest level too large for the dense inverse");
       h->n0 = int(H.n);
       std::vector<double> W0 = dense_transposed(H.A);
       DArr<double> Wd;
-      Wd.upload(W0, h->st, nullptr);
-      W0 = std::vector<double>();
-      h->coarse_inv.alloc(H.n * stgmg::inv_ld(int(H.n)), ctr);
-      h->coarse_part.alloc(int64_t(stgmg::dense_gemv_chunks(int(H.n))) * H.n, ctr);
+      Wd.upload(W0, h->st, nullptr);  // W0 (pageable) stays alive until the synchronisation below
+      h->coarse_inv.alloc(H.n * stgmg::inv_ld(int(H.n)), ctr, h->st);
+      h->coarse_part.alloc(int64_t(stgmg::dense_gemv_chunks(int(H.n))) * H.n, ctr, h->st);
       DArr<int32_t> stat;
-      stat.upload(std::vector<int32_t>(1, 0), h->st, nullptr);
+      const std::vector<int32_t> stat0(1, 0);
+      stat.upload(stat0, h->st, nullptr);
       const int nb = stgmg::gj_panel_width(int(H.n), lds_limit());
       if (nb != 0) {
         // one workgroup holds the whole inversion
@@ -338,10 +405,10 @@ void build(stgmg_handle* h) {
         const int n0 = int(H.n), pnb = 32;
         DArr<double> scl, Wb;
         DArr<int> perm, src;
-        scl.alloc(n0, nullptr);
-        Wb.alloc(int64_t(pnb) * n0, nullptr);
-        perm.alloc(n0, nullptr);
-        src.alloc(n0, nullptr);
+        scl.alloc(n0, nullptr, h->st);
+        Wb.alloc(int64_t(pnb) * n0, nullptr, h->st);
+        perm.alloc(n0, nullptr, h->st);
+        src.alloc(n0, nullptr, h->st);
         stgmg::k_gj_large_rowscale(h->st, n0, Wd.p, scl.p);
         for (int k0 = 0; k0 < n0; k0 += pnb)
           stgmg::k_gj_large_step(h->st, n0, k0, std::min(pnb, n0 - k0), Wd.p, perm.p, Wb.p, stat.p);
@@ -383,25 +450,26 @@ void build(stgmg_handle* h) {
       D.tptr.upload(H.tptr, h->st, ctr);
       D.tidx.upload(H.tidx, h->st, ctr);
       D.winv.upload(H.winv, h->st, ctr);
-      D.y.alloc(int64_t(H.pdof.size()), ctr);
+      D.y.alloc(int64_t(H.pdof.size()), ctr, h->st);
       const int64_t tot = D.ioff_h[H.npatch];
       if (p.smoother_prec == STGMG_FP32)
-        D.inv32.alloc(tot, ctr);
+        D.inv32.alloc(tot, ctr, h->st);
       else
-        D.inv64.alloc(tot, ctr);
+        D.inv64.alloc(tot, ctr, h->st);
       // extraction + inversion in batches through a dense work buffer
       const int nb = stgmg::gj_panel_width(max_np, lds_limit());
       if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
       const int64_t stride = int64_t(max_np) * max_np;
       int64_t batch = std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / (stride * 8)));
       DArr<double> Wb;
-      Wb.alloc(batch * stride, nullptr);
+      Wb.alloc(batch * stride, nullptr, h->st);
       std::vector<int64_t> woff_h(batch);
       for (int64_t i = 0; i < batch; ++i) woff_h[i] = i * stride;
       DArr<int64_t> woff;
       woff.upload(woff_h, h->st, nullptr);
       DArr<int32_t> stat;
-      stat.upload(std::vector<int32_t>(H.npatch, 0), h->st, nullptr);
+      const std::vector<int32_t> stat0(H.npatch, 0);
+      stat.upload(stat0, h->st, nullptr);
       for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
         const int64_t cnt = std::min(batch, H.npatch - p0);
         stgmg::k_fill_zero(h->st, Wb.p, cnt * stride);
@@ -448,8 +516,8 @@ void build(stgmg_handle* h) {
     prev.n = H.n;
   }
   h->e_dev.upload(h->T.e, h->st, ctr);
-  h->tmp_ns.alloc(h->fine_info.ns, ctr);
-  h->src_buf.alloc(h->fine_info.n, ctr);
+  h->tmp_ns.alloc(h->fine_info.ns, ctr, h->st);
+  h->src_buf.alloc(h->fine_info.n, ctr, h->st);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 256 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(h->st));
 }
@@ -457,12 +525,12 @@ void build(stgmg_handle* h) {
 void ensure_krylov(stgmg_handle* h, int m) {
   if (h->m_alloc >= m) return;
   const int64_t n = h->lv[h->L].n;
-  h->V.alloc(int64_t(m + 1) * n, &h->bytes);
-  h->Z.alloc(int64_t(m) * n, &h->bytes);
-  h->w.alloc(n, &h->bytes);
-  h->partials.alloc(int64_t(m + 2) * stgmg::dot_blocks(n), &h->bytes);
-  h->hdev.alloc(2 * (m + 2) + 4, &h->bytes);
-  h->ydev.alloc(m + 1, &h->bytes);
+  h->V.alloc(int64_t(m + 1) * n, &h->bytes, h->st);
+  h->Z.alloc(int64_t(m) * n, &h->bytes, h->st);
+  h->w.alloc(n, &h->bytes, h->st);
+  h->partials.alloc(int64_t(m + 2) * stgmg::dot_blocks(n), &h->bytes, h->st);
+  h->hdev.alloc(2 * (m + 2) + 4, &h->bytes, h->st);
+  h->ydev.alloc(m + 1, &h->bytes, h->st);
   h->m_alloc = m;
 }
 
@@ -509,7 +577,7 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
     for (int j = 0; j < m; ++j) {
       double* vj = h->V.p + int64_t(j) * n;
       double* zj = h->Z.p + int64_t(j) * n;
-      vcycle(h, h->L, vj, zj);
+      apply_B(h, vj, zj);
       A.apply(st, 0, zj, nullptr, h->w.p);
       // classical Gram-Schmidt, twice (CGS2)
       double* h1 = h->hdev.p;
@@ -602,12 +670,19 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     *out = nullptr;
     check_params(params);
     std::unique_ptr<stgmg_handle> h(new stgmg_handle());
-    h->prm = *params;
-    h->prm.K_cells = nullptr;  // copied into the level data, never kept
-    h->st = reinterpret_cast<hipStream_t>(hip_stream);
-    stgmg_params tmp = *params;
-    h->prm = tmp;
+    h->prm = *params;  // K_cells is read during build() and cleared afterwards
+    h->caller = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->enter_ev, hipEventDisableTiming));
+    enter(h.get());
     build(h.get());
+    h->prm.K_cells = nullptr;  // copied into the level data, never kept
+    const int64_t nf = h->lv[h->L].n;
+    h->use_graph = params->graph == 1 || (params->graph == -1 && nf < (int64_t(1) << 21));
+    if (h->use_graph) {
+      h->gin.alloc(nf, &h->bytes, h->st);
+      h->gout.alloc(nf, &h->bytes, h->st);
+    }
     h->prm.K_cells = nullptr;
     *out = h.release();
     return STGMG_OK;
@@ -631,6 +706,7 @@ stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, 
                          int32_t max_iters, stgmg_info* info) {
   return guarded([&] {
     if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    enter(h);
     return do_solve(h, rhs_dev, x_dev, rtol, restart, max_iters, info);
   });
 }
@@ -638,6 +714,7 @@ stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, 
 stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* x_dev, double* y_dev) {
   return guarded([&] {
     if (!h || !x_dev || !y_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    enter(h);
     const int l = level_index(h, level);
     h->lv[l].A.apply(h->st, 0, x_dev, nullptr, y_dev);
     HIPCHK(hipGetLastError());
@@ -649,7 +726,8 @@ stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* 
 stgmg_status stgmg_apply_vcycle(stgmg_handle* h, const double* r_dev, double* z_dev) {
   return guarded([&] {
     if (!h || !r_dev || !z_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
-    vcycle(h, h->L, r_dev, z_dev);
+    enter(h);
+    apply_B(h, r_dev, z_dev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->st));
     return STGMG_OK;
@@ -659,6 +737,7 @@ stgmg_status stgmg_apply_vcycle(stgmg_handle* h, const double* r_dev, double* z_
 stgmg_status stgmg_smooth(stgmg_handle* h, int32_t level, const double* b_dev, double* d_dev, int32_t sweeps) {
   return guarded([&] {
     if (!h || !b_dev || !d_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    enter(h);
     const int l = level_index(h, level);
     if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level 0 has no smoother");
     if (sweeps < 0) throw ApiError(STGMG_ERR_INVALID_ARG, "sweeps < 0");
@@ -672,6 +751,7 @@ stgmg_status stgmg_smooth(stgmg_handle* h, int32_t level, const double* b_dev, d
 stgmg_status stgmg_prolongate_add(stgmg_handle* h, int32_t level, const double* e_coarse_dev, double* d_fine_dev) {
   return guarded([&] {
     if (!h || !e_coarse_dev || !d_fine_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    enter(h);
     const int l = level_index(h, level);
     if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
     h->lv[l].P.apply(h->st, 2, e_coarse_dev, nullptr, d_fine_dev);
@@ -684,6 +764,7 @@ stgmg_status stgmg_prolongate_add(stgmg_handle* h, int32_t level, const double* 
 stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine_dev, double* b_coarse_dev) {
   return guarded([&] {
     if (!h || !r_fine_dev || !b_coarse_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    enter(h);
     const int l = level_index(h, level);
     if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
     h->lv[l].R.apply(h->st, 0, r_fine_dev, nullptr, b_coarse_dev);
@@ -696,6 +777,7 @@ stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine
 stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_prev_end_dev, double* rhs_dev) {
   return guarded([&] {
     if (!h || !x_prev_end_dev || !rhs_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    enter(h);
     const auto& F = h->fine_info;
     const int nt = h->T.k + 1;
     std::vector<double> src(size_t(nt) * F.ns), one;
@@ -716,6 +798,7 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
 stgmg_status stgmg_interpolate_solution(stgmg_handle* h, double t, double* x_block_dev) {
   return guarded([&] {
     if (!h || !x_block_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    enter(h);
     std::vector<double> v;
     stgmg::interpolate_solution(h->fine_info, t, v);
     HIPCHK(hipMemcpyAsync(x_block_dev, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
@@ -738,16 +821,62 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
     std::vector<double> st(size_t(n) * stgmg::inv_ld(n));
     if (h->prm.smoother_prec == STGMG_FP32) {
       std::vector<float> f(st.size());
-      HIPCHK(hipMemcpy(f.data(), D.inv32.p + D.ioff_h[patch], f.size() * sizeof(float), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(f.data(), D.inv32.p + D.ioff_h[patch], f.size() * sizeof(float), hipMemcpyDeviceToHost,
+                            h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
       for (size_t i = 0; i < f.size(); ++i) st[i] = f[i];
     } else {
-      HIPCHK(hipMemcpy(st.data(), D.inv64.p + D.ioff_h[patch], st.size() * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(st.data(), D.inv64.p + D.ioff_h[patch], st.size() * sizeof(double),
+                            hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
     }
     const int ld = stgmg::inv_ld(n);
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * ld + a];
     if (dofs_host)
       for (int a = 0; a < n; ++a) dofs_host[a] = D.pdof_h[D.poff_h[patch] + a];
+    return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_t* n_dofs, int64_t* resident_bytes,
+                             int64_t* setup_peak_bytes) {
+  return guarded([&] {
+    check_params(params);
+    if (restart < 1 || restart > 100) throw ApiError(STGMG_ERR_INVALID_ARG, "restart out of range");
+    const stgmg_params& p = *params;
+    const int L = p.levels - 1, d = p.dim;
+    const int64_t w = p.smoother_prec == STGMG_FP32 ? 4 : 8;
+    int64_t res = 0, temp_peak = 0, n_prev = 0, n_fine = 0;
+    for (int l = 0; l <= L; ++l) {
+      const stgmg::LevelSizes S = stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch);
+      const int64_t n = S.n;
+      res += (n + 1) * 8 + S.nnzA * 12 + 3 * n * 8;
+      if (l == 0) {
+        res += n * stgmg::inv_ld(int(n)) * 8 + int64_t(stgmg::dense_gemv_chunks(int(n))) * n * 8;
+        temp_peak = std::max(temp_peak, n * n * 8 + 32 * n * 8 + 3 * n * 8 + 64);
+      } else {
+        res += (n + 1) * 8 + S.nnzP * 12 + (n_prev + 1) * 8 + S.nnzP * 12;
+        res += 2 * (S.npatch + 1) * 8 + S.sum_np * 4 + (n + 1) * 8 + S.sum_np * 8 + n * 8 + S.sum_np * 8;
+        res += S.sum_np_ld * w;
+        const int64_t stride = int64_t(S.max_np) * S.max_np;
+        const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / (stride * 8)));
+        temp_peak = std::max(temp_peak, batch * stride * 8 + batch * 8 + S.npatch * 4);
+      }
+      if (l == L) {
+        res += (S.ns + 1) * 8 + S.nnzMM * 12 + (p.k + 1) * 8 + S.ns * 8 + n * 8;
+        const bool graph = p.graph == 1 || (p.graph == -1 && n < (int64_t(1) << 21));
+        if (graph) res += 2 * n * 8;
+        n_fine = n;
+      }
+      n_prev = n;
+    }
+    const int64_t m = restart;
+    const int64_t krylov = (2 * m + 2) * n_fine * 8 + (m + 2) * stgmg::dot_blocks(n_fine) * 8 + (2 * (m + 2) + 4) * 8 +
+                           (m + 1) * 8;
+    if (n_dofs) *n_dofs = n_fine;
+    if (resident_bytes) *resident_bytes = res + krylov;
+    if (setup_peak_bytes) *setup_peak_bytes = res + krylov + temp_peak;
     return STGMG_OK;
   });
 }

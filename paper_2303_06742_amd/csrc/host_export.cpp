@@ -97,4 +97,17 @@ void stgmg_host_interpolate(double t, double* out) {
   std::memcpy(out, g_vec.data(), g_vec.size() * sizeof(double));
 }
 
+// Closed-form sizes: out = {n, nnzA, nnzMM, nnzP, npatch, sum_np, sum_np_ld, max_np}
+void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out) {
+  stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind);
+  out[0] = S.n;
+  out[1] = S.nnzA;
+  out[2] = S.nnzMM;
+  out[3] = S.nnzP;
+  out[4] = S.npatch;
+  out[5] = S.sum_np;
+  out[6] = S.sum_np_ld;
+  out[7] = S.max_np;
+}
+
 }  // extern "C"

@@ -804,6 +804,94 @@ Csr transpose(const Csr& a, int64_t ncols_out) {
   return t;
 }
 
+// ------------------------------------------------------------- closed-form sizes
+namespace {
+int interp_weights_1d(int p, int Nc, int64_t g, int64_t* cols, double* w);
+// cells of an N-cell axis touching lattice point g of a degree-p lattice
+int adj_cells(int64_t g, int p, int N) {
+  if (g % p != 0) return 1;
+  const int64_t c = g / p;
+  return int(c - 1 >= 0) + int(c < N);
+}
+}  // namespace
+
+LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
+  LevelSizes S;
+  const int64_t n1 = int64_t(r) * N + 1, n1p = int64_t(r - 1) * N + 1;
+  // per-axis sums over a lattice of the closure sizes of the adjacent cells
+  auto axis_sum = [&](int lat_p, int64_t lat_n, int clos_p) {
+    int64_t s = 0;
+    for (int64_t g = 0; g < lat_n; ++g) s += int64_t(adj_cells(g, lat_p, N)) * clos_p + 1;
+    return s;
+  };
+  const int64_t sQQ = axis_sum(r, n1, r), sQP = axis_sum(r, n1, r - 1);
+  const int64_t sPP = axis_sum(r - 1, n1p, r - 1), sPQ = axis_sum(r - 1, n1p, r);
+  int64_t QQ = 1, QP = 1, PP = 1, PQ = 1, nQ = 1, nP = 1;
+  for (int a = 0; a < d; ++a) {
+    QQ *= sQQ;
+    QP *= sQP;
+    PP *= sPP;
+    PQ *= sPQ;
+    nQ *= n1;
+    nP *= n1p;
+  }
+  const int64_t kt = k + 1;
+  S.ns = 2 * d * nQ + nP;
+  S.n = kt * S.ns;
+  // u-eq rows: MM (M_rho on U) and KK (-M_rho on V), same component, disjoint columns
+  // v-eq rows: MM (M_rho on V, same comp); KK (A on U, all comps; C^T on P)
+  // p-eq rows: MM (c0 M_p on P); KK (-C on V, all comps; B on P, same columns as MM)
+  const int64_t u_rows = kt * d * (kt + 1) * QQ;
+  const int64_t v_rows = kt * d * ((kt + d) * QQ + QP);
+  const int64_t p_rows = kt * (kt * PP + d * PQ);
+  S.nnzA = u_rows + v_rows + p_rows;
+  S.nnzMM = 2 * d * QQ + PP;
+  // prolongation from N/2 cells: nonzero 1D interpolation weights per fine lattice point
+  if (N % 2 == 0) {
+    auto pro_sum = [&](int p) {
+      int64_t s = 0, cols[8];
+      double w[8];
+      for (int64_t g = 0; g <= int64_t(p) * N; ++g) s += interp_weights_1d(p, N / 2, g, cols, w);
+      return s;
+    };
+    const int64_t a = pro_sum(r), b = pro_sum(r - 1);
+    int64_t A = 1, B = 1;
+    for (int x = 0; x < d; ++x) {
+      A *= a;
+      B *= b;
+    }
+    S.nnzP = kt * (2 * d * A + B);
+  }
+  // patches: per axis a patch spans 1 or 2 cells; enumerate the 2^d width classes
+  int64_t cnt1 = 0, cnt2 = 0;  // per axis: patches (vertices or cells) of width 1 / 2
+  if (patch_kind == 1) {
+    cnt2 = N - 1;
+    cnt1 = N >= 1 ? 2 : 0;
+    if (N == 1) {
+      cnt1 = 2;
+      cnt2 = 0;
+    }
+  } else {
+    cnt1 = N;
+  }
+  for (int mask = 0; mask < (1 << d); ++mask) {
+    int64_t mult = 1, q = 1, pp = 1;
+    for (int a = 0; a < d; ++a) {
+      const int w = (mask >> a) & 1 ? 2 : 1;
+      mult *= (w == 2 ? cnt2 : cnt1);
+      q *= int64_t(r) * w + 1;
+      pp *= int64_t(r - 1) * w + 1;
+    }
+    if (mult == 0) continue;
+    const int64_t np = kt * (2 * d * q + pp);
+    S.npatch += mult;
+    S.sum_np += mult * np;
+    S.sum_np_ld += mult * np * ((np + 3) & ~int64_t(3));
+    S.max_np = std::max<int>(S.max_np, int(np));
+  }
+  return S;
+}
+
 // ------------------------------------------------------------- built-in solution
 // u_i = S sin t, v_i = S cos t, p = S cos t, S = prod_j sin(pi x_j).
 // f_i = rho u_tt - div sigma(u) + alpha d_i p

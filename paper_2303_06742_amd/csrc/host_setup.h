@@ -73,6 +73,14 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
 Csr build_prolongation(const LevelHost& coarse, const LevelHost& fine);
 Csr transpose(const Csr& a, int64_t ncols_out);
 
+// Closed-form sizes of one level, without building it (exact structural counts).
+struct LevelSizes {
+  int64_t n = 0, ns = 0, nnzA = 0, nnzMM = 0, nnzP = 0;  // nnzP: prolongation into this level
+  int64_t npatch = 0, sum_np = 0, sum_np_ld = 0;         // sum n_P, sum n_P * inv_ld(n_P)
+  int max_np = 0;
+};
+LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind);
+
 // Built-in prescribed solution u_i = S sin t, p = S cos t, S = prod sin(pi x_j):
 // source vector S(t) of one time node (u-eq rows zero), and nodal interpolant.
 void source_vector(const LevelHost& L, const Material& m, double t, std::vector<double>& out);

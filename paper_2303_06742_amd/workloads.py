@@ -74,3 +74,49 @@ def scaled(cfg, levels, name=None, **kw):
 
 def random_vector(n, seed):
     return np.random.default_rng(seed).standard_normal(n)
+
+
+def _random_physics(rng):
+    """lambda, mu ~ U[0.5, 5], alpha ~ U[0.5, 1], c0 = 10^U[-4,-1], K = 10^U[-3,0], rho = 1."""
+    return dict(lam=float(rng.uniform(0.5, 5)), mu=float(rng.uniform(0.5, 5)), alpha=float(rng.uniform(0.5, 1)),
+                c0=float(10 ** rng.uniform(-4, -1)), K=float(10 ** rng.uniform(-3, 0)), rho=1.0)
+
+
+def batch_configs(count, seed=0, sizes=(16, 32, 64, 128)):
+    """Independent 2D problems: N ~ U(sizes) cells per axis from a 4x4 coarsest grid, dG(1) or dG(2),
+    vertex patches, one slab of tau = 1e-3, random physics, FP32 smoother."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        N = int(rng.choice(sizes))
+        k = int(rng.integers(1, 3))
+        levels = int(np.log2(N // 4)) + 1
+        out.append(Config(f'batch{i}-2d-{N}-dg{k}', dim=2, coarse_cells=4, levels=levels, k=k, patch='vertex',
+                          tau=1e-3, slabs=1, precision='fp32', **_random_physics(rng)))
+    return out
+
+
+def serve_mix(count, seed=0, sizes2d=(32, 64, 128), sizes3d=(8, 16), p3d=0.3, p_follow=0.5):
+    """Request stream of the serving workload: 70% 2D (vertex patches) and 30% 3D (cell patches)
+    problems, dG(1)/dG(2), random physics, FP32 smoother; about half the requests are follow-on
+    slabs of an earlier problem (same key).  Returns a list of (key, Config)."""
+    rng = np.random.default_rng(seed)
+    problems = []
+    out = []
+    for i in range(count):
+        if problems and rng.random() < p_follow:
+            key, cfg = problems[int(rng.integers(len(problems)))]
+        else:
+            k = int(rng.integers(1, 3))
+            if rng.random() < p3d:
+                N = int(rng.choice(sizes3d))
+                cfg = Config(f'serve{i}-3d-{N}-dg{k}', dim=3, coarse_cells=2, levels=int(np.log2(N // 2)) + 1, k=k,
+                             patch='cell', tau=1e-3, slabs=1, precision='fp32', **_random_physics(rng))
+            else:
+                N = int(rng.choice(sizes2d))
+                cfg = Config(f'serve{i}-2d-{N}-dg{k}', dim=2, coarse_cells=4, levels=int(np.log2(N // 4)) + 1, k=k,
+                             patch='vertex', tau=1e-3, slabs=1, precision='fp32', **_random_physics(rng))
+            key = len(problems) + 1
+            problems.append((key, cfg))
+        out.append((key, cfg))
+    return out

@@ -42,3 +42,10 @@ def csr(lib, which, nrows):
     v = np.zeros(nnz)
     lib.stgmg_host_csr(which, ptr(p), ptr(c), ptr(v))
     return sp.csr_matrix((v, c, p), shape=(nrows, nrows if which != 2 else int(c.max()) + 1 if nnz else 0))
+
+
+def sizes(lib, d, r, k, N, kind):
+    out = np.zeros(8, dtype=np.int64)
+    lib.stgmg_host_sizes.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p]
+    lib.stgmg_host_sizes(d, r, k, N, kind, ptr(out))
+    return dict(zip(['n', 'nnzA', 'nnzMM', 'nnzP', 'npatch', 'sum_np', 'sum_np_ld', 'max_np'], out.tolist()))

@@ -1,0 +1,81 @@
+"""Batched solves and the serving loop: footprints, and results that are the same
+alone and in a mix (bitwise: no reduction crosses problems)."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import CONFIGS, require_gpu, to_dev, to_host
+from paper_2303_06742_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def capi():
+    require_gpu()
+    from paper_2303_06742_amd import capi as c
+    return c
+
+
+@pytest.mark.parametrize("key", ['c1', 'c2s', 'c3s'])
+def test_footprint_is_what_setup_allocates(key):
+    c = capi()
+    cfg = CONFIGS[key]
+    n, res, peak = c.footprint(cfg)
+    S = c.Solver(cfg)
+    x = S.empty()
+    S.solve(to_dev(workloads.random_vector(S.n, 1)), x)  # allocates the Krylov workspace
+    q = S.query(-1)
+    assert n == S.n and q['bytes'] == res and peak >= res
+    S.close()
+
+
+def test_batch_equals_alone():
+    c = capi()
+    cfgs = workloads.batch_configs(4, seed=3, sizes=(16, 32))
+    solvers = [c.Solver(cfg) for cfg in cfgs]
+    rhs = [to_dev(workloads.random_vector(s.n, 10 + i)) for i, s in enumerate(solvers)]
+    alone = []
+    for s, r in zip(solvers, rhs):
+        x = s.empty()
+        s.solve(r, x)
+        alone.append(to_host(x))
+    xs = [s.empty() for s in solvers]
+    infos = c.solve_batch(solvers, rhs, xs)
+    for a, x, i in zip(alone, xs, infos):
+        assert i['converged'] == 1 and np.array_equal(a, to_host(x))
+    for s in solvers:
+        s.close()
+
+
+def test_server_alone_and_in_mix():
+    c = capi()
+    target = workloads.batch_configs(1, seed=5, sizes=(32,))[0]
+    n, _, _ = c.footprint(target)
+    F = workloads.random_vector(n, 99)
+    srv = c.Server(hbm_budget=64 << 30, max_slots=4, resident_max=4)
+    st, x_alone, info, lat = srv.wait(srv.submit(target, F, key=1))
+    assert st == c.STGMG_OK and info['converged'] == 1
+    # the same request inside a mix of other problems, some of them resident follow-ons
+    mix = workloads.serve_mix(8, seed=6, sizes2d=(16, 32), sizes3d=(4,))
+    tickets = []
+    for j, (key, cfg) in enumerate(mix):
+        nn, _, _ = c.footprint(cfg)
+        tickets.append(srv.submit(cfg, workloads.random_vector(nn, 200 + j), key=100 + key))
+        if j == 3:
+            t_target = srv.submit(target, F, key=1)  # resident hierarchy reused
+    for t in tickets:
+        st2, _, inf2, _ = srv.wait(t)
+        assert st2 == c.STGMG_OK and inf2['converged'] == 1
+    st, x_mix, info2, _ = srv.wait(t_target)
+    assert st == c.STGMG_OK and np.array_equal(x_alone, x_mix)
+    srv.close()
+
+
+def test_server_refuses_what_cannot_fit():
+    c = capi()
+    cfg = CONFIGS['c2s']
+    n, res, peak = c.footprint(cfg)
+    srv = c.Server(hbm_budget=res // 2, max_slots=1, resident_max=0)
+    with pytest.raises(c.StgmgError) as e:
+        srv.submit(cfg, np.zeros(n))
+    assert e.value.status == c.STGMG_ERR_OOM
+    srv.close()

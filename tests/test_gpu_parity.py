@@ -162,3 +162,25 @@ def test_deterministic():
     S.solve(F, a)
     S.solve(F, b)
     assert np.array_equal(to_host(a), to_host(b))
+
+
+@pytest.mark.parametrize("key", ['c1', 'c2s'])
+def test_graph_replays_match_eager(key):
+    """The captured V-cycle graph, replayed several times with eager work and
+    synchronisations between the replays, equals the directly launched V-cycle bitwise."""
+    require_gpu()
+    from paper_2303_06742_amd import capi
+    Sg = capi.Solver(CONFIGS[key], graph=1)
+    Se = capi.Solver(CONFIGS[key], graph=0)
+    for rep in range(4):
+        r = to_dev(workloads.random_vector(Sg.n, 70 + rep))
+        zg = to_host(Sg.vcycle(r))
+        ze = to_host(Se.vcycle(r))
+        assert np.array_equal(zg, ze), (key, rep)
+        Sg.apply_operator(r)  # eager work on the same handle between replays
+    F = to_dev(workloads.random_vector(Sg.n, 80))
+    xg, xe = Sg.empty(), Se.empty()
+    ig, ie = Sg.solve(F, xg), Se.solve(F, xe)
+    assert ig['iters'] == ie['iters'] and np.array_equal(to_host(xg), to_host(xe))
+    Sg.close()
+    Se.close()

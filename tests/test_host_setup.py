@@ -104,3 +104,25 @@ def test_source_and_interpolant_match_oracle(d, N, K):
         assert np.abs(out - ref).max() < 1e-10 * np.abs(ref).max()
         LIB.stgmg_host_interpolate(t, hostlib.ptr(out))
         assert np.abs(out - problem.interpolate(blocks, sol, t)).max() < 1e-14
+
+
+@pytest.mark.parametrize("d,r,k,N,kind", [(2, 2, 1, 4, 'cell'), (2, 2, 2, 4, 'vertex'), (2, 3, 1, 2, 'vertex'),
+                                          (3, 2, 1, 2, 'cell'), (3, 2, 2, 2, 'vertex'), (2, 2, 0, 1, 'vertex'),
+                                          (2, 2, 2, 1, 'cell')])
+def test_closed_form_sizes(d, r, k, N, kind):
+    """The admission footprint's closed-form counts equal what the assembly builds."""
+    prm = problem.Params()
+    n = build(d, N, r, k, kind, prm)
+    S = hostlib.sizes(LIB, d, r, k, N, 1 if kind == 'vertex' else 0)
+    assert S['n'] == n
+    assert S['nnzA'] == LIB.stgmg_host_nnz(0)
+    assert S['nnzMM'] == LIB.stgmg_host_nnz(1)
+    assert S['npatch'] == LIB.stgmg_host_npatch() and S['sum_np'] == LIB.stgmg_host_patch_total()
+    tot = LIB.stgmg_host_patch_total()
+    poff = np.zeros(S['npatch'] + 1, dtype=np.int64)
+    pdof = np.zeros(tot, dtype=np.int32)
+    LIB.stgmg_host_patches(hostlib.ptr(poff), hostlib.ptr(pdof), hostlib.ptr(np.zeros(n)))
+    npp = np.diff(poff)
+    assert S['max_np'] == npp.max() and S['sum_np_ld'] == int(np.sum(npp * ((npp + 3) // 4 * 4)))
+    if N >= 2 and N % 2 == 0:
+        assert S['nnzP'] == LIB.stgmg_host_prolongation(d, r, k, N // 2)
