@@ -79,12 +79,120 @@ def cpu_baseline(cfg, sample_levels):
             'solve_s_sample': t_solve}
 
 
+def run_batch(args):
+    """Independent 2D problems (16^2..128^2, dG(1)/dG(2), random physics, FP32 smoother), set up in
+    waves that fit the HBM budget; each wave solved concurrently (stgmg_solve_batch) and, for
+    comparison, one after another."""
+    import numpy as np
+    import torch
+    from paper_2303_06742_amd import capi, workloads as W
+    cfgs = W.batch_configs(args.batch_count, seed=args.seed)
+    budget = int(args.hbm_budget_gb * 2 ** 30)
+    t_setup = t_batch = t_seq = 0.0
+    iters, res, max_dev = [], [], 0.0
+    i = 0
+    waves = 0
+    while i < len(cfgs):
+        wave, used = [], 0
+        while i < len(cfgs):
+            _, res_b, peak_b = capi.footprint(cfgs[i])
+            if wave and used + peak_b > budget:
+                break
+            t0 = time.perf_counter()
+            wave.append(capi.Solver(cfgs[i]))
+            t_setup += time.perf_counter() - t0
+            used += res_b
+            i += 1
+        waves += 1
+        rhs = [torch.from_numpy(W.random_vector(s.n, 1000 + j)).cuda() for j, s in enumerate(wave)]
+        xs = [s.empty() for s in wave]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = capi.solve_batch(wave, rhs, xs, rtol=1e-8)
+        torch.cuda.synchronize()
+        t_batch += time.perf_counter() - t0
+        xq = [s.empty() for s in wave]
+        t0 = time.perf_counter()
+        for s, r, x in zip(wave, rhs, xq):
+            s.solve(r, x, rtol=1e-8)
+        torch.cuda.synchronize()
+        t_seq += time.perf_counter() - t0
+        for x, y, inf in zip(xs, xq, infos):
+            max_dev = max(max_dev, float((x - y).abs().max()))
+            iters.append(inf['iters'])
+            res.append(inf['rel_res_true'])
+        for s in wave:
+            s.close()
+        print(f"[bench] wave {waves}: {len(wave)} problems", file=sys.stderr, flush=True)
+    n = len(cfgs)
+    out = {'metric': 'batched GMRES-GMG solves/s (independent problems, 1e-8 rel. residual)', 'value': n / t_batch,
+           'unit': 'solves/s', 'n_gpus': 1, 'steps': n, 'warmup': 0, 'ms_per_step': 1000 * t_batch / n,
+           'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64+f32-smoother',
+           'data': 'synthetic',
+           'config': {'workload': f'batch of {n} 2D problems 16^2..128^2, dG(1)/dG(2), vertex patches',
+                      'seed': args.seed, 'waves': waves, 'hbm_budget_gb': args.hbm_budget_gb},
+           'sequential_solves_per_s': n / t_seq, 'setup_plus_solve_per_s': n / (t_setup + t_batch),
+           'setup_s': t_setup, 'gmres_iters_mean': float(np.mean(iters)), 'rel_res_true_max': float(max(res)),
+           'batch_vs_alone_max_abs_diff': max_dev}
+    print(json.dumps(out), flush=True)
+
+
+def run_serve(args):
+    """Serving loop: a seeded request mix (70% 2D 32^2..128^2 vertex patches, 30% 3D 8^3..16^3 cell
+    patches, dG(1)/dG(2), half of them follow-on slabs of an earlier problem), first all at once
+    (saturated throughput), then with Poisson arrivals at fractions of that throughput."""
+    import numpy as np
+    from paper_2303_06742_amd import capi, workloads as W
+    mix = W.serve_mix(args.serve_count, seed=args.seed)
+    rhs = [W.random_vector(capi.footprint(cfg)[0], 2000 + j) for j, (_, cfg) in enumerate(mix)]
+    budget = int(args.hbm_budget_gb * 2 ** 30)
+
+    def run(rate, tag):
+        srv = capi.Server(budget, max_slots=args.slots, resident_max=32)
+        rng = np.random.default_rng(args.seed + 17)
+        t0 = time.perf_counter()
+        tickets = []
+        for j, (key, cfg) in enumerate(mix):
+            if rate:
+                time.sleep(float(rng.exponential(1.0 / rate)))
+            tickets.append(srv.submit(cfg, rhs[j], key=key + 1000 * hash(tag) % 1000000))
+        lat, ok = [], 0
+        for t in tickets:
+            st, _, inf, l = srv.wait(t)
+            ok += int(st == capi.STGMG_OK and inf['converged'] == 1)
+            lat.append(l)
+        el = time.perf_counter() - t0
+        srv.close()
+        print(f"[bench] serve {tag}: {len(mix) / el:.2f} solves/s p50 {np.percentile(lat, 50):.0f} ms", file=sys.stderr,
+              flush=True)
+        return {'offered_rate': rate, 'solves_per_s': len(mix) / el, 'p50_ms': float(np.percentile(lat, 50)),
+                'p99_ms': float(np.percentile(lat, 99)), 'converged': ok}
+
+    sat = run(0.0, 'saturated')
+    rows = [run(f * sat['solves_per_s'], f'rate{f}') for f in args.serve_rates]
+    out = {'metric': 'served GMRES-GMG solves/s with p50/p99 latency (setup on admission, resident reuse)',
+           'value': sat['solves_per_s'], 'unit': 'solves/s', 'n_gpus': 1, 'steps': len(mix), 'warmup': 0,
+           'ms_per_step': 1000.0 / sat['solves_per_s'], 'higher_is_better': True, 'scaling': 'weak',
+           'vs_baseline': None, 'dtype': 'f64+f32-smoother', 'data': 'synthetic',
+           'config': {'workload': f'{len(mix)} requests, 70% 2D 32^2..128^2 vertex / 30% 3D 8^3..16^3 cell, '
+                                  'half follow-on slabs', 'seed': args.seed, 'slots': args.slots,
+                      'hbm_budget_gb': args.hbm_budget_gb},
+           'latency_ms_p50': sat['p50_ms'], 'latency_ms_p99': sat['p99_ms'], 'poisson': rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=5)
     ap.add_argument('--warmup', type=int, default=1)
-    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3'])
+    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3', 'batch', 'serve'])
+    ap.add_argument('--batch-count', type=int, default=64)
+    ap.add_argument('--serve-count', type=int, default=48)
+    ap.add_argument('--serve-rates', type=float, nargs='*', default=[0.5, 0.9])
+    ap.add_argument('--slots', type=int, default=8)
+    ap.add_argument('--seed', type=int, default=0)
+    ap.add_argument('--hbm-budget-gb', type=float, default=200.0)
     ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32'])
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-sample-levels', type=int, default=None,
@@ -96,6 +204,10 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (independent problems "
               "would be sharded across GPUs; see the sharding notes in the design document).", file=sys.stderr)
         sys.exit(2)
+    if args.config == 'batch':
+        return run_batch(args)
+    if args.config == 'serve':
+        return run_serve(args)
     import numpy as np
     import torch
     from paper_2303_06742_amd import capi

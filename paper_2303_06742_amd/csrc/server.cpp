@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -58,6 +59,7 @@ struct stgmg_server {
   std::deque<Request*> queue;
   std::map<uint64_t, std::unique_ptr<Request>> all;
   std::vector<Resident> res;
+  std::set<uint64_t> active_keys;  // keys with a request running: later slabs of that problem wait
   std::vector<std::thread> workers;
   uint64_t next_ticket = 1, clock = 0;
   int running = 0;
@@ -82,18 +84,18 @@ Request* pick(stgmg_server* S, int* slot, std::vector<Resident>* evicted) {
   for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
     Request* q = *it;
     if (q->key != 0) {
-      bool blocked = false;
+      if (S->active_keys.count(q->key)) continue;  // same problem running: keep its slabs in order
+      bool found = false;
       for (size_t i = 0; i < S->res.size(); ++i)
         if (S->res[i].key == q->key) {
-          if (S->res[i].busy) {
-            blocked = true;  // same problem already running: keep slabs in order
-            break;
-          }
           *slot = int(i);
-          S->queue.erase(it);
-          return q;
+          found = true;
+          break;
         }
-      if (blocked) continue;
+      if (found) {
+        S->queue.erase(it);
+        return q;
+      }
     }
     int64_t free_b = S->budget - S->used;
     if (q->peak > free_b) {
@@ -128,6 +130,7 @@ void worker(stgmg_server* S) {
     Request* q = nullptr;
     int slot = -1;
     std::vector<Resident> evicted;
+    Resident R;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       S->cv.wait(lk, [&] {
@@ -138,19 +141,19 @@ void worker(stgmg_server* S) {
       if (!q) return;
       q->state = 1;
       S->running++;
+      if (q->key != 0) S->active_keys.insert(q->key);
       if (slot >= 0) {
+        // copy the resident entry now: other workers may erase entries (and shift
+        // indices) as soon as the lock is released; a busy entry is never evicted
         S->res[slot].busy = true;
         S->res[slot].last_use = ++S->clock;
+        R = S->res[slot];
       }
     }
     for (auto& e : evicted) free_resident(e);
-    Resident R;
-    bool fresh = slot < 0;
+    const bool fresh = slot < 0;
     stgmg_status st = STGMG_OK;
-    if (!fresh) {
-      std::lock_guard<std::mutex> lk(S->mu);
-      R = S->res[slot];
-    } else {
+    if (fresh) {
       R.key = q->key;
       R.n = q->n;
       stgmg_params p = q->prm;
@@ -180,6 +183,7 @@ void worker(stgmg_server* S) {
       q->state = 2;
       q->t_done = clk::now();
       S->running--;
+      if (q->key != 0) S->active_keys.erase(q->key);
       if (fresh) {
         S->used -= q->peak;  // setup temporaries are gone; the hierarchy holds `resident`
         keep = st == STGMG_OK && q->key != 0 && int(S->res.size()) < S->resident_max;

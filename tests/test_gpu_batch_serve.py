@@ -70,6 +70,28 @@ def test_server_alone_and_in_mix():
     srv.close()
 
 
+def test_server_every_result_same_alone_and_in_mix():
+    """Twelve requests (repeated keys = follow-on slabs on resident hierarchies, evictions under a
+    tight budget) run concurrently; each result equals the same request solved alone, bitwise."""
+    c = capi()
+    mix = workloads.serve_mix(12, seed=8, sizes2d=(16, 32), sizes3d=(4,))
+    rhs = [workloads.random_vector(c.footprint(cfg)[0], 300 + j) for j, (_, cfg) in enumerate(mix)]
+    alone = []
+    solo = c.Server(hbm_budget=64 << 30, max_slots=1, resident_max=0)
+    for (key, cfg), F in zip(mix, rhs):
+        st, x, info, _ = solo.wait(solo.submit(cfg, F))
+        assert st == c.STGMG_OK
+        alone.append(x)
+    solo.close()
+    peak = max(c.footprint(cfg)[2] + 16 * len(F) for (_, cfg), F in zip(mix, rhs))
+    srv = c.Server(hbm_budget=3 * peak, max_slots=4, resident_max=3)
+    tickets = [srv.submit(cfg, F, key=key) for (key, cfg), F in zip(mix, rhs)]
+    for t, x0 in zip(tickets, alone):
+        st, x, info, _ = srv.wait(t)
+        assert st == c.STGMG_OK and info['converged'] == 1 and np.array_equal(x, x0)
+    srv.close()
+
+
 def test_server_refuses_what_cannot_fit():
     c = capi()
     cfg = CONFIGS['c2s']
