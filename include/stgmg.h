@@ -78,6 +78,11 @@ typedef struct {
                             coarse cells take the mean of their 2^d children. Copied. */
   int32_t graph;         /* V-cycle as a captured HIP graph: -1 automatic (hierarchies below
                             2^21 fine unknowns, where launch latency matters), 0 never, 1 always */
+  int32_t time_blocks;   /* 1: each patch solve A_P^{-1} is applied through the eigen-
+                            decomposition of (M^t)^{-1} D^t, since A_P = D^t (x) MM_P + M^t (x) KK_P:
+                            (k+1) spatial inverses of n_P/(k+1) rows are stored instead of one
+                            of n_P rows (the same operator, (k+1)x fewer stored values);
+                            0: the full space-time inverse of Def:VankaOP is stored */
 } stgmg_params;
 
 typedef struct {

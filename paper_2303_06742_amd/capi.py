@@ -39,7 +39,8 @@ class Params(ctypes.Structure):
                 ('smoother_prec', ctypes.c_int32), ('n_smooth', ctypes.c_int32), ('omega', ctypes.c_double),
                 ('tau', ctypes.c_double), ('rho', ctypes.c_double), ('lam', ctypes.c_double),
                 ('mu', ctypes.c_double), ('alpha', ctypes.c_double), ('c0', ctypes.c_double),
-                ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p), ('graph', ctypes.c_int32)]
+                ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p), ('graph', ctypes.c_int32),
+                ('time_blocks', ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -122,7 +123,7 @@ def _dptr(t, n=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_params(cfg, precision=None, graph=-1):
+def make_params(cfg, precision=None, graph=-1, time_blocks=None):
     """(Params, K array kept alive by the caller) for a workloads.Config."""
     K = cfg.K_cells()
     if K is not None:
@@ -130,13 +131,14 @@ def make_params(cfg, precision=None, graph=-1):
     p = Params(dim=cfg.dim, coarse_cells=cfg.coarse_cells, levels=cfg.levels, r=cfg.r, k=cfg.k,
                patch=PATCH[cfg.patch], smoother_prec=PREC[precision or cfg.precision], n_smooth=cfg.n_smooth,
                omega=cfg.omega, tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
-               K=cfg.K, K_cells=None if K is None else K.ctypes.data, graph=graph)
+               K=cfg.K, K_cells=None if K is None else K.ctypes.data, graph=graph,
+               time_blocks=cfg.time_blocks if time_blocks is None else time_blocks)
     return p, K
 
 
-def footprint(cfg, precision=None, restart=30, graph=-1):
+def footprint(cfg, precision=None, restart=30, graph=-1, time_blocks=None):
     """Closed-form (n, resident bytes, setup peak bytes) without building anything."""
-    p, _K = make_params(cfg, precision, graph)
+    p, _K = make_params(cfg, precision, graph, time_blocks)
     n, res, peak = _I64(), _I64(), _I64()
     check(stgmg_footprint(ctypes.byref(p), restart, ctypes.byref(n), ctypes.byref(res), ctypes.byref(peak)),
           'stgmg_footprint')
@@ -208,11 +210,11 @@ class Server:
 class Solver:
     """One problem hierarchy (stgmg_setup) and the calls on it."""
 
-    def __init__(self, cfg, precision=None, stream=None, graph=-1):
+    def __init__(self, cfg, precision=None, stream=None, graph=-1, time_blocks=None):
         import torch
         self._torch = torch
         self.cfg = cfg
-        p, self._K = make_params(cfg, precision, graph)
+        p, self._K = make_params(cfg, precision, graph, time_blocks)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _H()
         check(stgmg_setup(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), 'stgmg_setup')

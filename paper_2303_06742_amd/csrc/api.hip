@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -113,6 +114,8 @@ struct LevelDev {
   DArr<double> inv64, winv, y;
   DArr<float> inv32;
   DevCsr P, R;  // prolongation from level-1 and its transpose
+  DevCsr MMs, KKs;  // spatial MM and KK (time-block patch solves)
+  double alg_inv_entries = 0;  // stored inverse values excluding padding
   DArr<double> b, d, r;
   std::vector<int64_t> poff_h, ioff_h;
   std::vector<int32_t> pdof_h;
@@ -139,6 +142,8 @@ struct stgmg_handle {
   stgmg::LevelHost fine_info;  // sizes, Kcell (no matrices)
   stgmg::Material mat{};
   stgmg::TimeConsts T;
+  stgmg::TimeBlockConsts tbc{};
+  bool tb = false;
   DevCsr MM;
   DArr<double> e_dev, tmp_ns, src_buf;
   // kernel timing (finest level): event pairs per kernel class
@@ -285,7 +290,14 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
     }
     {
       ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
-      if (h->prm.smoother_prec == STGMG_FP32)
+      const bool f32 = h->prm.smoother_prec == STGMG_FP32;
+      if (h->tb && f32)
+        stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r,
+                                    L.y.p);
+      else if (h->tb)
+        stgmg::k_patch_apply_tb_f64(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r,
+                                    L.y.p);
+      else if (f32)
         stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r, L.y.p);
       else
         stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r, L.y.p);
@@ -326,6 +338,26 @@ void build(stgmg_handle* h) {
   h->L = L;
   h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
   h->T = stgmg::make_time_consts(p.k, p.tau);
+  h->tb = p.time_blocks != 0;
+  if (h->tb) {
+    const stgmg::TimeBlocks B = stgmg::make_time_blocks(h->T);
+    h->tbc.nt = B.nt;
+    h->tbc.nblk = B.nblk;
+    for (int a = 0; a < B.nblk; ++a) {
+      h->tbc.lam[2 * a] = B.lam[a].real();
+      h->tbc.lam[2 * a + 1] = B.lam[a].imag();
+      h->tbc.cplx[a] = B.is_complex[a];
+      for (int b = 0; b < B.nt; ++b) {
+        h->tbc.tin[2 * (a * B.nt + b)] = B.tin[a * B.nt + b].real();
+        h->tbc.tin[2 * (a * B.nt + b) + 1] = B.tin[a * B.nt + b].imag();
+      }
+    }
+    for (int b = 0; b < B.nt; ++b)
+      for (int a = 0; a < B.nblk; ++a) {
+        h->tbc.qout[2 * (b * B.nblk + a)] = B.qout[b * B.nblk + a].real();
+        h->tbc.qout[2 * (b * B.nblk + a) + 1] = B.qout[b * B.nblk + a].imag();
+      }
+  }
   const int nth = host_threads();
   int64_t* ctr = &h->bytes;
   // permeability per level: finest from the caller, coarse = mean of the 2^d children
@@ -369,7 +401,8 @@ void build(stgmg_handle* h) {
   LevelHost prev;
   for (int l = 0; l <= L; ++l) {
     LevelHost H;
-    stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1, l == L};
+    stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1,
+                          l == L || (h->tb && l >= 1), h->tb && l >= 1};
     stgmg::build_level(o, h->mat, Kl[l], H, nth);
     LevelDev& D = h->lv[l];
     D.N = H.N;
@@ -393,11 +426,11 @@ void build(stgmg_handle* h) {
       const int nb = stgmg::gj_panel_width(int(H.n), lds_limit());
       if (nb != 0) {
         // one workgroup holds the whole inversion
-        std::vector<int64_t> poff0 = {0, H.n}, zero = {0};
-        DArr<int64_t> poffd, woffd;
-        poffd.upload(poff0, h->st, nullptr);
-        woffd.upload(zero, h->st, nullptr);
-        stgmg::k_gj_invert_f64(h->st, nb, 0, 1, int(H.n), poffd.p, woffd.p, Wd.p, woffd.p, h->coarse_inv.p, stat.p);
+        const int n0 = int(H.n);
+        const std::vector<stgmg::GjDesc> d0 = {{n0, n0, stgmg::inv_ld(n0), 0, 0, 0, 0, 0}};
+        DArr<stgmg::GjDesc> dd;
+        dd.upload(d0, h->st, nullptr);
+        stgmg::k_gj_invert_f64(h->st, nb, 1, n0, dd.p, Wd.p, h->coarse_inv.p, stat.p);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(h->st));
       } else {
@@ -441,7 +474,18 @@ void build(stgmg_handle* h) {
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
         max_np = std::max<int>(max_np, int(np));
-        D.ioff_h[q + 1] = D.ioff_h[q] + np * stgmg::inv_ld(int(np));
+        if (h->tb) {
+          const int64_t ns = np / (p.k + 1), ldh = stgmg::inv_ld(int(ns));
+          int64_t sz = 0;
+          for (int a = 0; a < h->tbc.nblk; ++a) {
+            sz += h->tbc.cplx[a] ? ns * 2 * ldh : ns * ldh;
+            D.alg_inv_entries += double(h->tbc.cplx[a] ? 2 * ns * ns : ns * ns);
+          }
+          D.ioff_h[q + 1] = D.ioff_h[q] + sz;
+        } else {
+          D.ioff_h[q + 1] = D.ioff_h[q] + np * stgmg::inv_ld(int(np));
+          D.alg_inv_entries += double(np * np);
+        }
       }
       D.max_np = max_np;
       D.poff.upload(H.poff, h->st, ctr);
@@ -456,30 +500,106 @@ void build(stgmg_handle* h) {
         D.inv32.alloc(tot, ctr, h->st);
       else
         D.inv64.alloc(tot, ctr, h->st);
-      // extraction + inversion in batches through a dense work buffer
-      const int nb = stgmg::gj_panel_width(max_np, lds_limit());
-      if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
-      const int64_t stride = int64_t(max_np) * max_np;
-      int64_t batch = std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / (stride * 8)));
-      DArr<double> Wb;
-      Wb.alloc(batch * stride, nullptr, h->st);
-      std::vector<int64_t> woff_h(batch);
-      for (int64_t i = 0; i < batch; ++i) woff_h[i] = i * stride;
-      DArr<int64_t> woff;
-      woff.upload(woff_h, h->st, nullptr);
       DArr<int32_t> stat;
       const std::vector<int32_t> stat0(H.npatch, 0);
       stat.upload(stat0, h->st, nullptr);
-      for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
-        const int64_t cnt = std::min(batch, H.npatch - p0);
-        stgmg::k_fill_zero(h->st, Wb.p, cnt * stride);
-        stgmg::k_patch_extract_t(h->st, p0, cnt, max_np, D.poff.p, D.pdof.p, D.A.ptr.p, D.A.col.p, D.A.val.p, woff.p,
-                                 Wb.p);
-        if (p.smoother_prec == STGMG_FP32)
-          stgmg::k_gj_invert_f32(h->st, nb, p0, cnt, max_np, D.poff.p, woff.p, Wb.p, D.ioff.p, D.inv32.p, stat.p);
-        else
-          stgmg::k_gj_invert_f64(h->st, nb, p0, cnt, max_np, D.poff.p, woff.p, Wb.p, D.ioff.p, D.inv64.p, stat.p);
-        HIPCHK(hipGetLastError());
+      if (!h->tb) {
+        // full space-time inverses: extraction + inversion in batches through a dense work buffer
+        const int nb = stgmg::gj_panel_width(max_np, lds_limit());
+        if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
+        const int64_t stride = int64_t(max_np) * max_np;
+        int64_t batch = std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / (stride * 8)));
+        DArr<double> Wb;
+        Wb.alloc(batch * stride, nullptr, h->st);
+        std::vector<int64_t> woff_h(batch);
+        for (int64_t i = 0; i < batch; ++i) woff_h[i] = i * stride;
+        DArr<int64_t> woff;
+        woff.upload(woff_h, h->st, nullptr);
+        std::vector<std::vector<stgmg::GjDesc>> descs;
+        std::vector<DArr<stgmg::GjDesc>> ddesc;
+        for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
+          const int64_t cnt = std::min(batch, H.npatch - p0);
+          std::vector<stgmg::GjDesc> dd(cnt);
+          for (int64_t i = 0; i < cnt; ++i) {
+            const int np = int(H.poff[p0 + i + 1] - H.poff[p0 + i]);
+            dd[i] = {np, np, stgmg::inv_ld(np), 0, 0, int32_t(p0 + i), i * stride, D.ioff_h[p0 + i]};
+          }
+          descs.push_back(std::move(dd));
+          ddesc.emplace_back();
+          ddesc.back().upload(descs.back(), h->st, nullptr);
+          stgmg::k_fill_zero(h->st, Wb.p, cnt * stride);
+          stgmg::k_patch_extract_t(h->st, p0, cnt, max_np, D.poff.p, D.pdof.p, D.A.ptr.p, D.A.col.p, D.A.val.p,
+                                   woff.p, Wb.p);
+          if (p.smoother_prec == STGMG_FP32)
+            stgmg::k_gj_invert_f32(h->st, nb, cnt, max_np, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
+          else
+            stgmg::k_gj_invert_f64(h->st, nb, cnt, max_np, ddesc.back().p, Wb.p, D.inv64.p, stat.p);
+          HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipStreamSynchronize(h->st));
+      } else {
+        // time-block inverses: spatial MM_P, KK_P -> one (real or 2x2-block complex) matrix per
+        // kept eigenvalue -> batched Gauss-Jordan, output mapped into the block layout
+        D.MMs.upload(H.MM, h->st, ctr);
+        D.KKs.upload(H.KK, h->st, ctr);
+        const int nt = p.k + 1, nblk = h->tbc.nblk;
+        const int max_ns = max_np / nt;
+        bool any_c = false;
+        int64_t per_patch = 0;
+        std::vector<int64_t> blk_woff(nblk);
+        for (int a = 0; a < nblk; ++a) {
+          blk_woff[a] = per_patch;
+          const int64_t na = h->tbc.cplx[a] ? 2 * max_ns : max_ns;
+          per_patch += na * na;
+          any_c = any_c || h->tbc.cplx[a];
+        }
+        const int max_n = any_c ? 2 * max_ns : max_ns;
+        const int nb = stgmg::gj_panel_width(max_n, lds_limit());
+        if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
+        const int64_t sq = int64_t(max_ns) * max_ns;
+        const int64_t batch =
+            std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
+        DArr<double> Wb, wmm, wkk;
+        Wb.alloc(batch * per_patch, nullptr, h->st);
+        wmm.alloc(batch * sq, nullptr, h->st);
+        wkk.alloc(batch * sq, nullptr, h->st);
+        std::vector<std::vector<stgmg::GjDesc>> descs;
+        std::vector<std::vector<int32_t>> nss;
+        std::vector<DArr<stgmg::GjDesc>> ddesc;
+        std::vector<DArr<int32_t>> dns;
+        for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
+          const int64_t cnt = std::min(batch, H.npatch - p0);
+          std::vector<stgmg::GjDesc> dd(cnt * nblk);
+          std::vector<int32_t> ns_of(cnt);
+          for (int64_t i = 0; i < cnt; ++i) {
+            const int ns = int(H.poff[p0 + i + 1] - H.poff[p0 + i]) / nt, ldh = stgmg::inv_ld(ns);
+            ns_of[i] = ns;
+            int64_t oo = D.ioff_h[p0 + i];
+            for (int a = 0; a < nblk; ++a) {
+              const bool c = h->tbc.cplx[a] != 0;
+              dd[i * nblk + a] = {c ? 2 * ns : ns, ns, c ? 2 * ldh : ldh, c ? ns : 0, ldh, int32_t(p0 + i),
+                                  i * per_patch + blk_woff[a], oo};
+              oo += int64_t(ns) * (c ? 2 * ldh : ldh);
+            }
+          }
+          descs.push_back(std::move(dd));
+          nss.push_back(std::move(ns_of));
+          ddesc.emplace_back();
+          ddesc.back().upload(descs.back(), h->st, nullptr);
+          dns.emplace_back();
+          dns.back().upload(nss.back(), h->st, nullptr);
+          stgmg::k_fill_zero(h->st, wmm.p, cnt * sq);
+          stgmg::k_fill_zero(h->st, wkk.p, cnt * sq);
+          stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
+                                           D.MMs.val.p, D.KKs.ptr.p, D.KKs.col.p, D.KKs.val.p, wmm.p, wkk.p);
+          stgmg::k_form_time_blocks(h->st, cnt, h->tbc, max_ns, dns.back().p, wmm.p, wkk.p, ddesc.back().p, Wb.p);
+          if (p.smoother_prec == STGMG_FP32)
+            stgmg::k_gj_invert_f32(h->st, nb, cnt * nblk, max_n, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
+          else
+            stgmg::k_gj_invert_f64(h->st, nb, cnt * nblk, max_n, ddesc.back().p, Wb.p, D.inv64.p, stat.p);
+          HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipStreamSynchronize(h->st));
       }
       std::vector<int32_t> st_h(H.npatch);
       HIPCHK(hipMemcpyAsync(st_h.data(), stat.p, st_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
@@ -818,7 +938,8 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
     const int n = int(D.poff_h[patch + 1] - D.poff_h[patch]);
     *n_p = n;
     if (!out_host) return STGMG_OK;
-    std::vector<double> st(size_t(n) * stgmg::inv_ld(n));
+    const int64_t cnt = D.ioff_h[patch + 1] - D.ioff_h[patch];
+    std::vector<double> st(cnt);
     if (h->prm.smoother_prec == STGMG_FP32) {
       std::vector<float> f(st.size());
       HIPCHK(hipMemcpyAsync(f.data(), D.inv32.p + D.ioff_h[patch], f.size() * sizeof(float), hipMemcpyDeviceToHost,
@@ -830,9 +951,34 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
                             hipMemcpyDeviceToHost, h->st));
       HIPCHK(hipStreamSynchronize(h->st));
     }
-    const int ld = stgmg::inv_ld(n);
-    for (int a = 0; a < n; ++a)
-      for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * ld + a];
+    if (!h->tb) {
+      const int ld = stgmg::inv_ld(n);
+      for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * ld + a];
+    } else {
+      // A_P^{-1}[(b,i)][(c,j)] = sum_a Q[b][a] X_a[i][j] Tin[a][c] (pairs: twice the real part)
+      const auto& tb = h->tbc;
+      const int nt = tb.nt, ns = n / nt, ldh = stgmg::inv_ld(ns);
+      std::fill(out_host, out_host + size_t(n) * n, 0.0);
+      int64_t off = 0;
+      for (int a = 0; a < tb.nblk; ++a) {
+        const bool c = tb.cplx[a] != 0;
+        const int64_t ldc = c ? 2 * ldh : ldh;
+        for (int b = 0; b < nt; ++b)
+          for (int cc = 0; cc < nt; ++cc) {
+            const std::complex<double> q(tb.qout[2 * (b * tb.nblk + a)], tb.qout[2 * (b * tb.nblk + a) + 1]);
+            const std::complex<double> t(tb.tin[2 * (a * nt + cc)], tb.tin[2 * (a * nt + cc) + 1]);
+            const std::complex<double> qt = q * t;
+            for (int i = 0; i < ns; ++i)
+              for (int j = 0; j < ns; ++j) {
+                const std::complex<double> x(st[off + size_t(j) * ldc + i], c ? st[off + size_t(j) * ldc + ldh + i] : 0.0);
+                const std::complex<double> v = qt * x;
+                out_host[size_t(b * ns + i) * n + cc * ns + j] += c ? 2.0 * v.real() : v.real();
+              }
+          }
+        off += int64_t(ns) * ldc;
+      }
+    }
     if (dofs_host)
       for (int a = 0; a < n; ++a) dofs_host[a] = D.pdof_h[D.poff_h[patch] + a];
     return STGMG_OK;
@@ -848,6 +994,11 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
     const int L = p.levels - 1, d = p.dim;
     const int64_t w = p.smoother_prec == STGMG_FP32 ? 4 : 8;
     int64_t res = 0, temp_peak = 0, n_prev = 0, n_fine = 0;
+    int nreal = 0, ncplx = 0;
+    if (p.time_blocks) {
+      const stgmg::TimeBlocks B = stgmg::make_time_blocks(stgmg::make_time_consts(p.k, p.tau));
+      for (int a = 0; a < B.nblk; ++a) (B.is_complex[a] ? ncplx : nreal)++;
+    }
     for (int l = 0; l <= L; ++l) {
       const stgmg::LevelSizes S = stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch);
       const int64_t n = S.n;
@@ -858,10 +1009,24 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       } else {
         res += (n + 1) * 8 + S.nnzP * 12 + (n_prev + 1) * 8 + S.nnzP * 12;
         res += 2 * (S.npatch + 1) * 8 + S.sum_np * 4 + (n + 1) * 8 + S.sum_np * 8 + n * 8 + S.sum_np * 8;
-        res += S.sum_np_ld * w;
-        const int64_t stride = int64_t(S.max_np) * S.max_np;
-        const int64_t batch = std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / (stride * 8)));
-        temp_peak = std::max(temp_peak, batch * stride * 8 + batch * 8 + S.npatch * 4);
+        if (!p.time_blocks) {
+          res += S.sum_np_ld * w;
+          const int64_t stride = int64_t(S.max_np) * S.max_np;
+          const int64_t batch =
+              std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / (stride * 8)));
+          temp_peak = std::max(temp_peak, batch * stride * 8 + batch * 8 + int64_t(sizeof(stgmg::GjDesc)) * batch +
+                                              S.npatch * 4);
+        } else {
+          res += (nreal + 2 * ncplx) * S.sum_ns_ldh * w;
+          res += 2 * (S.ns + 1) * 8 + (S.nnzMM + S.nnzKK) * 12;
+          const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
+          const int64_t per_patch = (nreal + 4 * ncplx) * sq;
+          const int64_t batch =
+              std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
+          temp_peak = std::max(temp_peak, batch * (per_patch + 2 * sq) * 8 +
+                                              int64_t(sizeof(stgmg::GjDesc)) * batch * (nreal + ncplx) + batch * 4 +
+                                              S.npatch * 4);
+        }
       }
       if (l == L) {
         res += (S.ns + 1) * 8 + S.nnzMM * 12 + (p.k + 1) * 8 + S.ns * 8 + n * 8;
@@ -908,9 +1073,8 @@ stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches,
     double bytes = 0.0;
     if (what == STGMG_PROF_PATCH_APPLY) {
       const double w = h->prm.smoother_prec == STGMG_FP32 ? 4.0 : 8.0;
-      const double sum_np2 = F.npatch ? double(F.ioff_h[F.npatch]) : 0.0;
       const double sum_np = F.npatch ? double(F.poff_h[F.npatch]) : 0.0;
-      bytes = w * sum_np2 + 16.0 * sum_np;
+      bytes = w * F.alg_inv_entries + 16.0 * sum_np;
     } else {
       bytes = 8.0 * double(F.A.nnz) + 24.0 * double(F.n);
     }

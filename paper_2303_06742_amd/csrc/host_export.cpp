@@ -20,7 +20,7 @@ long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double ta
     long long nc = 1;
     for (int a = 0; a < d; ++a) nc *= N;
     std::vector<double> K(Kcell, Kcell + nc);
-    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true};
+    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true};
     stgmg::Material m{rho, lambda, mu, alpha, c0};
     g_level = stgmg::LevelHost();
     stgmg::build_level(o, m, K, g_level, 4);
@@ -31,13 +31,13 @@ long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double ta
 }
 
 long long stgmg_host_nnz(int which) {
-  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : g_P;
+  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : which == 3 ? g_level.KK : g_P;
   return (long long)c.col.size();
 }
 
 // which: 0 = A, 1 = MM, 2 = last prolongation
 void stgmg_host_csr(int which, long long* ptr, int* col, double* val) {
-  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : g_P;
+  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : which == 3 ? g_level.KK : g_P;
   for (size_t i = 0; i < c.ptr.size(); ++i) ptr[i] = c.ptr[i];
   std::memcpy(col, c.col.data(), c.col.size() * sizeof(int));
   std::memcpy(val, c.val.data(), c.val.size() * sizeof(double));
@@ -97,6 +97,28 @@ void stgmg_host_interpolate(double t, double* out) {
   std::memcpy(out, g_vec.data(), g_vec.size() * sizeof(double));
 }
 
+// Time-block eigen-decomposition: returns nblk; lam (2*nblk: re, im), cplx (nblk),
+// tin (2*nblk*nt), qout (2*nt*nblk), complex values interleaved (re, im).
+int stgmg_host_time_blocks(int k, double tau, double* lam, int* cplx, double* tin, double* qout) {
+  stgmg::TimeConsts T = stgmg::make_time_consts(k, tau);
+  stgmg::TimeBlocks B = stgmg::make_time_blocks(T);
+  for (int a = 0; a < B.nblk; ++a) {
+    lam[2 * a] = B.lam[a].real();
+    lam[2 * a + 1] = B.lam[a].imag();
+    cplx[a] = B.is_complex[a];
+  }
+  for (size_t i = 0; i < B.tin.size(); ++i) {
+    tin[2 * i] = B.tin[i].real();
+    tin[2 * i + 1] = B.tin[i].imag();
+  }
+  for (size_t i = 0; i < B.qout.size(); ++i) {
+    qout[2 * i] = B.qout[i].real();
+    qout[2 * i + 1] = B.qout[i].imag();
+  }
+  return B.nblk;
+}
+
+// KK CSR of the last built level (which = 3 in stgmg_host_csr)
 // Closed-form sizes: out = {n, nnzA, nnzMM, nnzP, npatch, sum_np, sum_np_ld, max_np}
 void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out) {
   stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind);
@@ -108,6 +130,7 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[5] = S.sum_np;
   out[6] = S.sum_np_ld;
   out[7] = S.max_np;
+  out[8] = S.nnzKK;
 }
 
 }  // extern "C"

@@ -193,6 +193,148 @@ TimeConsts make_time_consts(int k, double tau) {
   return T;
 }
 
+// ------------------------------------------------------------- time blocks
+namespace {
+using cd = std::complex<double>;
+
+// x = A^{-1} b for a small complex matrix (Gaussian elimination, partial pivoting)
+std::vector<cd> csolve(std::vector<cd> A, std::vector<cd> b, int n) {
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(A[r * n + c]) > std::abs(A[piv * n + c])) piv = r;
+    if (piv != c) {
+      for (int j = 0; j < n; ++j) std::swap(A[c * n + j], A[piv * n + j]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const cd f = A[r * n + c] / A[c * n + c];
+      for (int j = c; j < n; ++j) A[r * n + j] -= f * A[c * n + j];
+      b[r] -= f * b[c];
+    }
+  }
+  std::vector<cd> x(n);
+  for (int r = n - 1; r >= 0; --r) {
+    cd sum = b[r];
+    for (int j = r + 1; j < n; ++j) sum -= A[r * n + j] * x[j];
+    x[r] = sum / A[r * n + r];
+  }
+  return x;
+}
+}  // namespace
+
+TimeBlocks make_time_blocks(const TimeConsts& Tc) {
+  const int n = Tc.k + 1;
+  TimeBlocks B;
+  B.nt = n;
+  std::vector<double> T(n * n);
+  for (int b = 0; b < n; ++b)
+    for (int a = 0; a < n; ++a) T[b * n + a] = Tc.Dt[b * n + a] / Tc.mt[b];
+  // characteristic polynomial by Faddeev-LeVerrier: p(x) = x^n + c[n-1] x^{n-1} + ... + c[0]
+  std::vector<double> c(n + 1, 0.0), Mk(n * n, 0.0), AM(n * n);
+  c[n] = 1.0;
+  for (int k = 1; k <= n; ++k) {
+    // M_k = A M_{k-1} + c_{n-k+1} I ; c_{n-k} = -tr(A M_k) / k
+    std::vector<double> Mn(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double sum = 0.0;
+        for (int l = 0; l < n; ++l) sum += T[i * n + l] * Mk[l * n + j];
+        Mn[i * n + j] = sum + (i == j ? c[n - k + 1] : 0.0);
+      }
+    Mk = Mn;
+    double tr = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int l = 0; l < n; ++l) tr += T[i * n + l] * Mk[l * n + i];
+    c[n - k] = -tr / k;
+  }
+  auto poly = [&](cd x) {
+    cd v = 1.0;
+    for (int k = n - 1; k >= 0; --k) v = v * x + c[k];
+    return v;
+  };
+  // Durand-Kerner roots, scaled by the Cauchy bound
+  double bound = 0.0;
+  for (int k = 0; k < n; ++k) bound = std::max(bound, std::fabs(c[k]));
+  bound += 1.0;
+  std::vector<cd> z(n);
+  for (int i = 0; i < n; ++i) z[i] = bound * std::pow(cd(0.4, 0.9), i);
+  for (int it = 0; it < 2000; ++it) {
+    double change = 0.0;
+    for (int i = 0; i < n; ++i) {
+      cd den = 1.0;
+      for (int j = 0; j < n; ++j)
+        if (j != i) den *= (z[i] - z[j]);
+      const cd dz = poly(z[i]) / den;
+      z[i] -= dz;
+      change = std::max(change, std::abs(dz) / std::max(1.0, std::abs(z[i])));
+    }
+    if (change < 1e-16) break;
+  }
+  // eigenvectors by inverse iteration; kept set: real ones and Im > 0 of each pair
+  std::vector<cd> Q(n * n);
+  std::vector<cd> lam_all(n);
+  std::vector<int> order;
+  for (int i = 0; i < n; ++i)
+    if (std::fabs(z[i].imag()) <= 1e-9 * std::abs(z[i])) z[i] = cd(z[i].real(), 0.0);
+  std::vector<int> used(n, 0);
+  std::vector<cd> lam_sorted;
+  for (int i = 0; i < n; ++i)
+    if (z[i].imag() == 0.0) lam_sorted.push_back(z[i]);
+  for (int i = 0; i < n; ++i)
+    if (z[i].imag() > 0.0) {
+      lam_sorted.push_back(z[i]);
+      lam_sorted.push_back(std::conj(z[i]));
+    }
+  if (int(lam_sorted.size()) != n) throw std::runtime_error("time eigenvalues: unpaired complex root");
+  for (int a = 0; a < n; ++a) {
+    const cd lam = lam_sorted[a];
+    const cd shift = lam * (1.0 + 1e-10) + cd(1e-12, 0.0);
+    std::vector<cd> M(n * n), v(n, cd(1.0, 0.0));
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) M[i * n + j] = cd(T[i * n + j], 0.0) - (i == j ? shift : cd(0.0, 0.0));
+    for (int it = 0; it < 3; ++it) {
+      v = csolve(M, v, n);
+      double nv = 0.0;
+      int imax = 0;
+      for (int i = 0; i < n; ++i)
+        if (std::abs(v[i]) > nv) {
+          nv = std::abs(v[i]);
+          imax = i;
+        }
+      const cd s = v[imax];
+      for (auto& x : v) x /= s;  // largest entry = 1 (a real eigenvector stays real)
+    }
+    if (lam.imag() == 0.0)
+      for (auto& x : v) x = cd(x.real(), 0.0);
+    for (int i = 0; i < n; ++i) Q[i * n + a] = v[i];
+    lam_all[a] = lam;
+  }
+  // Q^{-1} column by column
+  std::vector<cd> Qi(n * n);
+  for (int j = 0; j < n; ++j) {
+    std::vector<cd> e(n, cd(0.0, 0.0));
+    e[j] = 1.0;
+    std::vector<cd> col = csolve(Q, e, n);
+    for (int i = 0; i < n; ++i) Qi[i * n + j] = col[i];
+  }
+  for (int a = 0; a < n; ++a) {
+    if (lam_all[a].imag() < 0.0) continue;  // partner of the previous kept eigenvalue
+    B.lam.push_back(lam_all[a]);
+    B.is_complex.push_back(lam_all[a].imag() > 0.0 ? 1 : 0);
+    for (int b = 0; b < n; ++b) B.tin.push_back(Qi[a * n + b] / Tc.mt[b]);
+  }
+  B.nblk = int(B.lam.size());
+  B.qout.resize(size_t(n) * B.nblk);
+  int kb = 0;
+  for (int a = 0; a < n; ++a) {
+    if (lam_all[a].imag() < 0.0) continue;
+    for (int b = 0; b < n; ++b) B.qout[size_t(b) * B.nblk + kb] = Q[b * n + a];
+    ++kb;
+  }
+  return B;
+}
+
 // ------------------------------------------------------------- cell matrices
 CellMats make_cell_mats(int d, int r, double h, const Material& m) {
   CellMats C;
@@ -536,7 +678,7 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
 
   // pass 1: space-time row lengths
   std::vector<int64_t> slen(ns);  // length of one space-time row for spatial row i (same for every b)
-  std::vector<int64_t> mmlen(ns);
+  std::vector<int64_t> mmlen(ns), kklen(ns);
   parallel_for(ns, nthreads, [&](int64_t lo, int64_t hi) {
     std::vector<Entry> mm, kk;
     for (int64_t i = lo; i < hi; ++i) {
@@ -556,6 +698,7 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
       }
       slen[i] = int64_t(k) * int64_t(mm.size()) + int64_t(u);
       mmlen[i] = int64_t(mm.size());
+      kklen[i] = int64_t(kk.size());
     }
   });
   L.A.nrows = L.n;
@@ -576,6 +719,14 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
     L.MM.col.resize(L.MM.ptr[ns]);
     L.MM.val.resize(L.MM.ptr[ns]);
   }
+  if (o.need_KK) {
+    L.KK.nrows = ns;
+    L.KK.ncols = ns;
+    L.KK.ptr.assign(ns + 1, 0);
+    for (int64_t i = 0; i < ns; ++i) L.KK.ptr[i + 1] = L.KK.ptr[i] + kklen[i];
+    L.KK.col.resize(L.KK.ptr[ns]);
+    L.KK.val.resize(L.KK.ptr[ns]);
+  }
   // pass 2: fill
   parallel_for(ns, nthreads, [&](int64_t lo, int64_t hi) {
     std::vector<Entry> mm, kk;
@@ -586,6 +737,13 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
         for (auto& e : mm) {
           L.MM.col[p] = int32_t(e.col);
           L.MM.val[p++] = e.val;
+        }
+      }
+      if (o.need_KK) {
+        int64_t p = L.KK.ptr[i];
+        for (auto& e : kk) {
+          L.KK.col[p] = int32_t(e.col);
+          L.KK.val[p++] = e.val;
         }
       }
       for (int b = 0; b < nt; ++b) {
@@ -846,6 +1004,7 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
   const int64_t p_rows = kt * (kt * PP + d * PQ);
   S.nnzA = u_rows + v_rows + p_rows;
   S.nnzMM = 2 * d * QQ + PP;
+  S.nnzKK = d * QQ + d * (d * QQ + QP) + (d * PQ + PP);
   // prolongation from N/2 cells: nonzero 1D interpolation weights per fine lattice point
   if (N % 2 == 0) {
     auto pro_sum = [&](int p) {
@@ -884,6 +1043,8 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
     }
     if (mult == 0) continue;
     const int64_t np = kt * (2 * d * q + pp);
+    const int64_t nsp = 2 * d * q + pp;
+    S.sum_ns_ldh += mult * nsp * ((nsp + 3) & ~int64_t(3));
     S.npatch += mult;
     S.sum_np += mult * np;
     S.sum_np_ld += mult * np * ((np + 3) & ~int64_t(3));

@@ -2,6 +2,7 @@
 // integrals, space-time operators in CSR, patch tables and grid transfers.
 // Plain C++17, no HIP; the device side only uploads what is built here.
 #pragma once
+#include <complex>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -21,6 +22,21 @@ struct TimeConsts {
   std::vector<double> x, w, Dt, mt, e;
 };
 TimeConsts make_time_consts(int k, double tau);
+
+// Eigen-decomposition of T = (M^t)^{-1} D^t = Q diag(lambda) Q^{-1}, used to split a
+// space-time patch solve A_P^{-1} = (Q x I) blockdiag((lambda_a MM_P + KK_P)^{-1})
+// (Q^{-1} (M^t)^{-1} x I) into spatial solves.  Kept eigenvalues: every real one and
+// the one with positive imaginary part of each complex-conjugate pair (its partner's
+// contribution is the complex conjugate).
+struct TimeBlocks {
+  int nt = 0;       // k + 1
+  int nblk = 0;     // kept eigenvalues
+  std::vector<std::complex<double>> lam;   // [nblk]
+  std::vector<int> is_complex;             // [nblk]
+  std::vector<std::complex<double>> tin;   // [nblk][nt]: rows of Q^{-1} (M^t)^{-1}
+  std::vector<std::complex<double>> qout;  // [nt][nblk]: columns of Q (a pair counts twice via 2 Re)
+};
+TimeBlocks make_time_blocks(const TimeConsts& T);
 
 // Element and boundary-face matrices of one cell [0,h]^d, indexed [test][trial]
 // row-major.  Vector local index = d*a + c (a = lexicographic local node).
@@ -46,7 +62,8 @@ struct LevelHost {
   int64_t nQ = 0, nP = 0, nv = 0, ns = 0, n = 0;
   std::vector<double> Kcell;
   Csr A;   // space-time operator D^t (x) MM + M^t (x) KK
-  Csr MM;  // spatial MM (finest level only, used for the jump term of the rhs)
+  Csr MM;  // spatial MM (finest level, and every smoothed level for time-block patch solves)
+  Csr KK;  // spatial KK (smoothed levels, time-block patch solves)
   // patches: dofs of patch p are pdof[poff[p] .. poff[p+1]) in increasing order
   int64_t npatch = 0;
   std::vector<int64_t> poff;
@@ -63,6 +80,7 @@ struct BuildOptions {
   double tau, omega;
   bool need_patches;
   bool need_MM;
+  bool need_KK = false;
 };
 
 // Assemble one level.  Kcell: per-cell K (N^d values).
@@ -77,6 +95,8 @@ Csr transpose(const Csr& a, int64_t ncols_out);
 struct LevelSizes {
   int64_t n = 0, ns = 0, nnzA = 0, nnzMM = 0, nnzP = 0;  // nnzP: prolongation into this level
   int64_t npatch = 0, sum_np = 0, sum_np_ld = 0;         // sum n_P, sum n_P * inv_ld(n_P)
+  int64_t sum_ns_ldh = 0;  // sum over patches of ns * inv_ld(ns), ns = n_P / (k+1)
+  int64_t nnzKK = 0;       // spatial KK
   int max_np = 0;
 };
 LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind);

@@ -19,12 +19,40 @@ void k_fill_zero(hipStream_t st, double* a, int64_t n);
 void k_patch_extract_t(hipStream_t st, int64_t p0, int64_t count, int max_np, const int64_t* poff,
                        const int32_t* pdof, const int64_t* ptr, const int32_t* col, const double* val,
                        const int64_t* woff, double* W);
+// One matrix of a batched Gauss-Jordan inversion: size n, row-major input at woff
+// (overwritten), output rows i < keep of inv(input) written to out + ooff + i * ld_out,
+// with column j placed at j (split == 0) or, for j >= split, at ldh + (j - split); all
+// other positions of the kept rows are zero.  status[patch] is set on a zero pivot.
+struct GjDesc {
+  int32_t n, keep, ld_out, split, ldh, patch;
+  int64_t woff, ooff;
+};
 size_t gj_lds_bytes(int max_np, int nb);
 int gj_panel_width(int max_np, size_t lds_limit);
-void k_gj_invert_f64(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
-                     const int64_t* woff, double* W, const int64_t* ooff, double* out, int32_t* status);
-void k_gj_invert_f32(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
-                     const int64_t* woff, double* W, const int64_t* ooff, float* out, int32_t* status);
+void k_gj_invert_f64(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, double* out,
+                     int32_t* status);
+void k_gj_invert_f32(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, float* out,
+                     int32_t* status);
+// Time-block patch solves.  Constants: tin [nblk][nt] and qout [nt][nblk] complex
+// (re, im interleaved), lam [nblk] complex, cplx [nblk].
+struct TimeBlockConsts {
+  int nt, nblk;
+  double tin[2 * 4 * 4], qout[2 * 4 * 4], lam[2 * 4];
+  int cplx[4];
+};
+// dense spatial MM_P^T and KK_P^T (ns x ns, ns = n_P / nt) of patches [p0, p0 + count) at wmm + i * max_ns^2 etc.
+void k_patch_extract_spatial_t(hipStream_t st, int64_t p0, int64_t count, int nt, int max_ns, const int64_t* poff,
+                               const int32_t* pdof, const int64_t* mptr, const int32_t* mcol, const double* mval,
+                               const int64_t* kptr, const int32_t* kcol, const double* kval, double* wmm,
+                               double* wkk);
+// block matrices (transposed, row-major) for the Gauss-Jordan work area, one per (patch, kept eigenvalue)
+void k_form_time_blocks(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int max_ns, const int32_t* ns_of,
+                        const double* wmm, const double* wkk, const GjDesc* desc, double* W);
+int patch_apply_tb_threads(int max_ns, bool fp32);
+void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
+                          const int32_t* pdof, const int64_t* ioff, const double* inv, const double* r, double* y);
+void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
+                          const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y);
 // Block size used by the patch GEMV for patches of at most max_np rows.
 int patch_apply_threads(int max_np, bool fp32);
 void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,

@@ -11,6 +11,7 @@
 //                      reduction order (bitwise reproducible).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "kernels.h"
@@ -90,6 +91,78 @@ __global__ void __launch_bounds__(256) patch_extract_t_kernel(
   }
 }
 
+// Dense spatial blocks of a patch (time-block solves): S_P = the first n_P / nt dofs
+// of the patch (time node 0, whose global numbers are the spatial numbers);
+// wmm[mu * ns + nu] = MM[S(nu)][S(mu)], wkk likewise (transposed).  Zero on entry.
+__global__ void __launch_bounds__(256) patch_extract_spatial_t_kernel(
+    int64_t p0, int nt, int max_ns, const int64_t* __restrict__ poff, const int32_t* __restrict__ pdof,
+    const int64_t* __restrict__ mptr, const int32_t* __restrict__ mcol, const double* __restrict__ mval,
+    const int64_t* __restrict__ kptr, const int32_t* __restrict__ kcol, const double* __restrict__ kval,
+    double* __restrict__ wmm, double* __restrict__ wkk) {
+  extern __shared__ int32_t sdof[];
+  const int64_t p = p0 + blockIdx.x;
+  const int64_t o = poff[p];
+  const int ns = int(poff[p + 1] - o) / nt;
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) sdof[i] = pdof[o + i];
+  __syncthreads();
+  double* Wm = wmm + int64_t(blockIdx.x) * max_ns * max_ns;
+  double* Wk = wkk + int64_t(blockIdx.x) * max_ns * max_ns;
+  const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE, nw = blockDim.x / WAVE;
+  for (int t = wave; t < 2 * ns; t += nw) {
+    const int nu = t % ns;
+    const bool is_k = t >= ns;
+    const int64_t g = sdof[nu];
+    const int64_t* ptr = is_k ? kptr : mptr;
+    const int32_t* col = is_k ? kcol : mcol;
+    const double* val = is_k ? kval : mval;
+    double* Wd = is_k ? Wk : Wm;
+    for (int64_t q = ptr[g] + lane; q < ptr[g + 1]; q += WAVE) {
+      const int32_t c = col[q];
+      int lo = 0, hi = ns - 1;
+      while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (sdof[mid] < c)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (sdof[lo] == c) Wd[int64_t(lo) * ns + nu] = val[q];
+    }
+  }
+}
+
+// Block matrix (transposed) of descriptor m = (patch i = m / nblk, eigenvalue a = m % nblk):
+// real lambda: lambda MM^T + KK^T; complex lambda = al + i be: the transpose of the real form
+// [[al MM + KK, -be MM], [be MM, al MM + KK]].
+__global__ void form_time_blocks_kernel(TimeBlockConsts tb, int max_ns, const int32_t* __restrict__ ns_of,
+                                        const double* __restrict__ wmm, const double* __restrict__ wkk,
+                                        const GjDesc* __restrict__ desc, double* __restrict__ W) {
+  const int64_t m = blockIdx.y;
+  const int64_t i = m / tb.nblk;
+  const int a = int(m % tb.nblk);
+  const int ns = ns_of[i];
+  const double* Mt = wmm + i * max_ns * max_ns;
+  const double* Kt = wkk + i * max_ns * max_ns;
+  double* Wd = W + desc[m].woff;
+  const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+  if (!tb.cplx[a]) {
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < int64_t(ns) * ns;
+         q += int64_t(gridDim.x) * blockDim.x)
+      Wd[q] = al * Mt[q] + Kt[q];
+  } else {
+    const int n2 = 2 * ns;
+    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < int64_t(ns) * ns;
+         q += int64_t(gridDim.x) * blockDim.x) {
+      const int mu = int(q / ns), nu = int(q % ns);
+      const double d = al * Mt[q] + Kt[q], b = be * Mt[q];
+      Wd[int64_t(mu) * n2 + nu] = d;
+      Wd[int64_t(mu) * n2 + ns + nu] = b;
+      Wd[int64_t(ns + mu) * n2 + nu] = -b;
+      Wd[int64_t(ns + mu) * n2 + ns + nu] = d;
+    }
+  }
+}
+
 __global__ void fill_zero_kernel(double* __restrict__ a, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
     a[i] = 0.0;
@@ -104,14 +177,12 @@ __global__ void fill_zero_kernel(double* __restrict__ a, int64_t n) {
 // with W = the (swapped) pivot rows of M[:, rest].  The result
 // inv(M) = inv(S M) S, columns un-permuted, is written row-major to out.
 template <typename T, int NB>
-__global__ void __launch_bounds__(256) gj_invert_kernel(int64_t p0, const int64_t* __restrict__ poff,
-                                                        const int64_t* __restrict__ woff, double* __restrict__ W,
-                                                        const int64_t* __restrict__ ooff, T* __restrict__ out,
-                                                        int32_t* __restrict__ status) {
+__global__ void __launch_bounds__(256) gj_invert_kernel(const GjDesc* __restrict__ desc, double* __restrict__ W,
+                                                        T* __restrict__ out, int32_t* __restrict__ status) {
   extern __shared__ double lds[];
-  const int64_t p = p0 + blockIdx.x;
-  const int n = int(poff[p + 1] - poff[p]);
-  double* M = W + woff[blockIdx.x];
+  const GjDesc D = desc[blockIdx.x];
+  const int n = D.n;
+  double* M = W + D.woff;
   double* Pnl = lds;                                   // n * NB
   double* scl = lds + size_t(n) * NB;                  // n
   double* red_v = scl + n;                             // 4 waves
@@ -235,13 +306,22 @@ __global__ void __launch_bounds__(256) gj_invert_kernel(int64_t p0, const int64_
       src[k] = src[q];
       src[q] = t;
     }
-    if (s_flag) status[p] = 1;
+    if (s_flag) status[D.patch] = 1;
   }
   __syncthreads();
-  T* o = out + ooff[p];
-  const int ld = inv_ld(n);
-  for (int i = wave; i < n; i += nw)
-    for (int j = lane; j < ld; j += WAVE) o[int64_t(i) * ld + j] = j < n ? T(M[int64_t(i) * n + src[j]] * scl[j]) : T(0);
+  T* o = out + D.ooff;
+  for (int i = wave; i < D.keep; i += nw)
+    for (int q = lane; q < D.ld_out; q += WAVE) {
+      int j = -1;
+      if (D.split == 0) {
+        j = q < n ? q : -1;
+      } else if (q < D.split) {
+        j = q;
+      } else if (q >= D.ldh && q - D.ldh < n - D.split) {
+        j = D.split + (q - D.ldh);
+      }
+      o[int64_t(i) * D.ld_out + q] = j >= 0 ? T(M[int64_t(i) * n + src[j]] * scl[j]) : T(0);
+    }
 }
 
 // ---------------------------------------------------------------- patch apply
@@ -316,6 +396,119 @@ __global__ void __launch_bounds__(512) patch_apply_kernel(int64_t npatch, const 
 #pragma unroll
   for (int q = 0; q < RPT; ++q)
     if (i0 + q < n) y[o + i0 + q] = double(a[q] + b[q]);
+}
+
+// Time-block patch solve: y_P = (Q x I) blockdiag(X_a) (Q^{-1} (M^t)^{-1} x I) r_P with the
+// spatial block inverses X_a stored per patch one after another: a real block as ns
+// columns of stride inv_ld(ns); a complex block as ns columns of stride 2 inv_ld(ns)
+// holding Re X_a in rows [0, ns) and Im X_a in rows [inv_ld(ns), inv_ld(ns) + ns).
+template <typename T, int RPT>
+__global__ void __launch_bounds__(256) patch_apply_tb_kernel(TimeBlockConsts tb, const int64_t* __restrict__ poff,
+                                                             const int32_t* __restrict__ pdof,
+                                                             const int64_t* __restrict__ ioff,
+                                                             const T* __restrict__ inv, const double* __restrict__ r,
+                                                             double* __restrict__ y) {
+  using V = typename Vec16<T, RPT>::type;
+  extern __shared__ double sm[];
+  const int64_t p = blockIdx.x;
+  const int64_t o = poff[p];
+  const int n = int(poff[p + 1] - o);
+  const int nt = tb.nt, nblk = tb.nblk;
+  const int ns = n / nt, ldh = inv_ld(ns);
+  double* rl = sm;                              // n
+  T* sv = reinterpret_cast<T*>(sm + n);         // nblk * 2 * ldh (re, im)
+  double* tv = sm + n + 2 * nblk * ldh;         // nblk * 2 * ldh (re, im)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) rl[i] = r[pdof[o + i]];
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += blockDim.x)
+    for (int a = 0; a < nblk; ++a) {
+      double sr = 0.0, si = 0.0;
+      for (int b = 0; b < nt; ++b) {
+        const double x = rl[b * ns + i];
+        sr += tb.tin[2 * (a * nt + b)] * x;
+        si += tb.tin[2 * (a * nt + b) + 1] * x;
+      }
+      sv[(2 * a) * ldh + i] = T(sr);
+      sv[(2 * a + 1) * ldh + i] = T(si);
+    }
+  __syncthreads();
+  const int i0 = RPT * int(threadIdx.x);
+  int64_t off = ioff[p];
+  for (int a = 0; a < nblk; ++a) {
+    const T* sr = sv + (2 * a) * ldh;
+    const T* si = sv + (2 * a + 1) * ldh;
+    if (!tb.cplx[a]) {
+      if (i0 < ns) {
+        const V* X = reinterpret_cast<const V*>(inv + off + i0);
+        const int ldv = ldh / RPT;
+        T acc[RPT], acc2[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) acc[q] = acc2[q] = T(0);
+        int j = 0;
+        for (; j + 3 < ns; j += 4) {
+          V v0 = X[int64_t(j) * ldv], v1 = X[int64_t(j + 1) * ldv], v2 = X[int64_t(j + 2) * ldv],
+            v3 = X[int64_t(j + 3) * ldv];
+          fma_vec<T, RPT>(acc, v0, sr[j]);
+          fma_vec<T, RPT>(acc2, v1, sr[j + 1]);
+          fma_vec<T, RPT>(acc, v2, sr[j + 2]);
+          fma_vec<T, RPT>(acc2, v3, sr[j + 3]);
+        }
+        for (; j < ns; ++j) fma_vec<T, RPT>(acc, X[int64_t(j) * ldv], sr[j]);
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          tv[(2 * a) * ldh + i0 + q] = double(acc[q] + acc2[q]);
+          tv[(2 * a + 1) * ldh + i0 + q] = 0.0;
+        }
+      }
+      off += int64_t(ns) * ldh;
+    } else {
+      if (i0 < ns) {
+        const V* Xr = reinterpret_cast<const V*>(inv + off + i0);
+        const V* Xi = reinterpret_cast<const V*>(inv + off + ldh + i0);
+        const int ldv = 2 * ldh / RPT;
+        T tr[RPT], ti[RPT], tr2[RPT], ti2[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) tr[q] = ti[q] = tr2[q] = ti2[q] = T(0);
+        int j = 0;
+        for (; j + 1 < ns; j += 2) {
+          V a0 = Xr[int64_t(j) * ldv], b0 = Xi[int64_t(j) * ldv];
+          V a1 = Xr[int64_t(j + 1) * ldv], b1 = Xi[int64_t(j + 1) * ldv];
+          fma_vec<T, RPT>(tr, a0, sr[j]);
+          fma_vec<T, RPT>(tr, b0, -si[j]);
+          fma_vec<T, RPT>(ti, b0, sr[j]);
+          fma_vec<T, RPT>(ti, a0, si[j]);
+          fma_vec<T, RPT>(tr2, a1, sr[j + 1]);
+          fma_vec<T, RPT>(tr2, b1, -si[j + 1]);
+          fma_vec<T, RPT>(ti2, b1, sr[j + 1]);
+          fma_vec<T, RPT>(ti2, a1, si[j + 1]);
+        }
+        for (; j < ns; ++j) {
+          V a0 = Xr[int64_t(j) * ldv], b0 = Xi[int64_t(j) * ldv];
+          fma_vec<T, RPT>(tr, a0, sr[j]);
+          fma_vec<T, RPT>(tr, b0, -si[j]);
+          fma_vec<T, RPT>(ti, b0, sr[j]);
+          fma_vec<T, RPT>(ti, a0, si[j]);
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+          tv[(2 * a) * ldh + i0 + q] = double(tr[q] + tr2[q]);
+          tv[(2 * a + 1) * ldh + i0 + q] = double(ti[q] + ti2[q]);
+        }
+      }
+      off += int64_t(ns) * 2 * ldh;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += blockDim.x)
+    for (int b = 0; b < nt; ++b) {
+      double acc = 0.0;
+      for (int a = 0; a < nblk; ++a) {
+        const double qr = tb.qout[2 * (b * nblk + a)], qi = tb.qout[2 * (b * nblk + a) + 1];
+        const double t_r = tv[(2 * a) * ldh + i], t_i = tv[(2 * a + 1) * ldh + i];
+        acc += tb.cplx[a] ? 2.0 * (qr * t_r - qi * t_i) : qr * t_r;
+      }
+      y[o + b * ns + i] = acc;
+    }
 }
 
 // d[mu] += winv[mu] * sum of the patch images of mu, in patch order
@@ -628,36 +821,32 @@ int gj_panel_width(int max_np, size_t lds_limit) {
 }
 
 template <typename T>
-static void gj_launch(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
-                      const int64_t* woff, double* W, const int64_t* ooff, T* out, int32_t* status) {
-  const size_t lds = gj_lds_bytes(max_np, nb);
+static void gj_launch(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, T* out,
+                      int32_t* status) {
+  const size_t lds = gj_lds_bytes(max_n, nb);
   switch (nb) {
     case 32:
-      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 32>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
-                         out, status);
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 32>), dim3(count), dim3(256), lds, st, desc, W, out, status);
       break;
     case 16:
-      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 16>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
-                         out, status);
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 16>), dim3(count), dim3(256), lds, st, desc, W, out, status);
       break;
     case 8:
-      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 8>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
-                         out, status);
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 8>), dim3(count), dim3(256), lds, st, desc, W, out, status);
       break;
     default:
-      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 4>), dim3(count), dim3(256), lds, st, p0, poff, woff, W, ooff,
-                         out, status);
+      hipLaunchKernelGGL((dev::gj_invert_kernel<T, 4>), dim3(count), dim3(256), lds, st, desc, W, out, status);
       break;
   }
 }
 
-void k_gj_invert_f64(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
-                     const int64_t* woff, double* W, const int64_t* ooff, double* out, int32_t* status) {
-  if (count) gj_launch<double>(st, nb, p0, count, max_np, poff, woff, W, ooff, out, status);
+void k_gj_invert_f64(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, double* out,
+                     int32_t* status) {
+  if (count) gj_launch<double>(st, nb, count, max_n, desc, W, out, status);
 }
-void k_gj_invert_f32(hipStream_t st, int nb, int64_t p0, int64_t count, int max_np, const int64_t* poff,
-                     const int64_t* woff, double* W, const int64_t* ooff, float* out, int32_t* status) {
-  if (count) gj_launch<float>(st, nb, p0, count, max_np, poff, woff, W, ooff, out, status);
+void k_gj_invert_f32(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, float* out,
+                     int32_t* status) {
+  if (count) gj_launch<float>(st, nb, count, max_n, desc, W, out, status);
 }
 
 int patch_apply_threads(int max_np, bool fp32) {
@@ -677,6 +866,49 @@ void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t
   if (npatch == 0) return;
   hipLaunchKernelGGL((dev::patch_apply_kernel<float, 4>), dim3(npatch), dim3(patch_apply_threads(max_np, true)),
                      size_t(max_np) * sizeof(float), st, npatch, poff, pdof, ioff, inv, r, y);
+}
+
+void k_patch_extract_spatial_t(hipStream_t st, int64_t p0, int64_t count, int nt, int max_ns, const int64_t* poff,
+                               const int32_t* pdof, const int64_t* mptr, const int32_t* mcol, const double* mval,
+                               const int64_t* kptr, const int32_t* kcol, const double* kval, double* wmm,
+                               double* wkk) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(dev::patch_extract_spatial_t_kernel, dim3(count), dim3(256), size_t(max_ns) * sizeof(int32_t),
+                     st, p0, nt, max_ns, poff, pdof, mptr, mcol, mval, kptr, kcol, kval, wmm, wkk);
+}
+
+void k_form_time_blocks(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int max_ns, const int32_t* ns_of,
+                        const double* wmm, const double* wkk, const GjDesc* desc, double* W) {
+  if (count == 0) return;
+  const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (int64_t(max_ns) * max_ns + 255) / 256));
+  hipLaunchKernelGGL(dev::form_time_blocks_kernel, dim3(gx, count * tb.nblk), dim3(256), 0, st, tb, max_ns, ns_of,
+                     wmm, wkk, desc, W);
+}
+
+static size_t tb_lds(int max_np, int nblk) {
+  const int ldh = inv_ld(max_np);
+  return (size_t(max_np) + 4 * size_t(nblk) * ldh) * sizeof(double);
+}
+
+int patch_apply_tb_threads(int max_ns, bool fp32) {
+  const int rpt = fp32 ? 4 : 2;
+  const int t = (inv_ld(max_ns) / rpt + 63) / 64 * 64;
+  return t < 64 ? 64 : t;
+}
+
+void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
+                          const int32_t* pdof, const int64_t* ioff, const double* inv, const double* r, double* y) {
+  if (npatch == 0) return;
+  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<double, 2>), dim3(npatch),
+                     dim3(patch_apply_tb_threads(max_np / tb.nt, false)), tb_lds(max_np, tb.nblk), st, tb, poff, pdof,
+                     ioff, inv, r, y);
+}
+void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
+                          const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y) {
+  if (npatch == 0) return;
+  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<float, 4>), dim3(npatch),
+                     dim3(patch_apply_tb_threads(max_np / tb.nt, true)), tb_lds(max_np, tb.nblk), st, tb, poff, pdof,
+                     ioff, inv, r, y);
 }
 
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,

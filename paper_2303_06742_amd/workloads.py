@@ -39,6 +39,7 @@ class Config:
     omega: float = 0.7
     restart: int = 30
     rtol: float = 1e-8
+    time_blocks: int = 1  # patch solves through the time eigen-decomposition (0: full inverses)
     extra: dict = field(default_factory=dict)
 
     @property

@@ -26,7 +26,7 @@ def rel_err(a, b, scale=None):
     return np.abs(a - b).max() / s
 
 
-KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0']
+KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'c1_full', 'c2s_full', 'c3s_full']
 
 
 @pytest.mark.parametrize("key", KEYS)

@@ -117,6 +117,7 @@ def test_closed_form_sizes(d, r, k, N, kind):
     assert S['n'] == n
     assert S['nnzA'] == LIB.stgmg_host_nnz(0)
     assert S['nnzMM'] == LIB.stgmg_host_nnz(1)
+    assert S['nnzKK'] == LIB.stgmg_host_nnz(3)
     assert S['npatch'] == LIB.stgmg_host_npatch() and S['sum_np'] == LIB.stgmg_host_patch_total()
     tot = LIB.stgmg_host_patch_total()
     poff = np.zeros(S['npatch'] + 1, dtype=np.int64)
@@ -126,3 +127,38 @@ def test_closed_form_sizes(d, r, k, N, kind):
     assert S['max_np'] == npp.max() and S['sum_np_ld'] == int(np.sum(npp * ((npp + 3) // 4 * 4)))
     if N >= 2 and N % 2 == 0:
         assert S['nnzP'] == LIB.stgmg_host_prolongation(d, r, k, N // 2)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_time_blocks_diagonalise_the_slab_operator(k):
+    """A_P^{-1} = (Q x I) blockdiag((lambda MM + KK)^{-1}) (Q^{-1} M^t^{-1} x I): the host's
+    eigen-decomposition reproduces the inverse of a random D^t (x) MM + M^t (x) KK."""
+    import ctypes
+    tau = 0.37
+    nt = k + 1
+    lam = np.zeros(2 * nt); cplx = np.zeros(nt, dtype=np.int32)
+    tin = np.zeros(2 * nt * nt); qout = np.zeros(2 * nt * nt)
+    LIB.stgmg_host_time_blocks.restype = ctypes.c_int
+    LIB.stgmg_host_time_blocks.argtypes = [ctypes.c_int, ctypes.c_double] + [ctypes.c_void_p] * 4
+    nb = LIB.stgmg_host_time_blocks(k, tau, *[hostlib.ptr(a) for a in (lam, cplx, tin, qout)])
+    lam = lam[0::2][:nb] + 1j * lam[1::2][:nb]
+    tin = (tin[0::2] + 1j * tin[1::2])[:nb * nt].reshape(nb, nt)
+    qout = (qout[0::2] + 1j * qout[1::2])[:nt * nb].reshape(nt, nb)
+    Dt, Mt, _, _, _ = timedg.time_matrices(k, tau)
+    ev = np.linalg.eigvals(np.linalg.solve(Mt, Dt))
+    for l in lam:
+        assert np.min(np.abs(ev - l)) < 1e-10 * np.abs(l)
+    assert sum(2 if c else 1 for c in cplx[:nb]) == nt
+    rng = np.random.default_rng(k)
+    m = 5
+    MM = rng.standard_normal((m, m)) + 4 * np.eye(m)
+    KK = rng.standard_normal((m, m)) + 4 * np.eye(m)
+    A = np.kron(Dt, MM) + np.kron(Mt, KK)
+    r = rng.standard_normal(nt * m).reshape(nt, m)
+    y = np.zeros((nt, m))
+    for a in range(nb):
+        s = tin[a] @ r
+        t = np.linalg.solve(lam[a] * MM + KK, s)
+        contrib = np.outer(qout[:, a], t)
+        y += 2 * contrib.real if cplx[a] else contrib.real
+    assert np.abs(y.reshape(-1) - np.linalg.solve(A, r.reshape(-1))).max() < 1e-12 * np.abs(y).max()
