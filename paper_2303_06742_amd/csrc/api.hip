@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -97,6 +98,10 @@ struct DevCsr {
     val.upload(c.val, st, counter);
     const double avg = nrows ? double(nnz) / double(nrows) : 0.0;
     lanes = avg < 12 ? 4 : avg < 24 ? 8 : avg < 100 ? 16 : avg < 200 ? 32 : 64;
+    if (const char* e = std::getenv("STGMG_CSR_LANES")) {  // tuning override: lanes per row for rows of > 24 entries
+      const int v = std::atoi(e);
+      if ((v == 4 || v == 8 || v == 16 || v == 32 || v == 64) && avg >= 24) lanes = v;
+    }
   }
   void apply(hipStream_t st, int mode, const double* x, const double* b, double* y) const {
     stgmg::k_csr(st, mode, nrows, ptr.p, col.p, val.p, x, b, y, lanes);
@@ -123,9 +128,22 @@ struct LevelDev {
 
 }  // namespace
 
+// The handle's own stream.  Declared as the first member of the handle so that it is
+// destroyed last: every device array is freed stream-ordered on it before.
+struct OwnStream {
+  hipStream_t s = nullptr;
+  ~OwnStream() {
+    if (s) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  }
+};
+
 struct stgmg_handle {
+  OwnStream own;
   stgmg_params prm{};
-  hipStream_t st = nullptr;      // the handle's own stream (default priority, non-blocking)
+  hipStream_t st = nullptr;      // == own.s (default priority, non-blocking)
   hipStream_t caller = nullptr;  // the caller's stream: each call waits for it first
   hipEvent_t enter_ev = nullptr;
   // V-cycle graph: z = B r with r read from gin and z written to gout
@@ -146,6 +164,7 @@ struct stgmg_handle {
   bool tb = false;
   DevCsr MM;
   DArr<double> e_dev, tmp_ns, src_buf;
+  DArr<double> src_xq, src_wq, src_bq, src_bp, kfine;  // device source tables
   // kernel timing (finest level): event pairs per kernel class
   bool prof = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
@@ -159,40 +178,14 @@ struct stgmg_handle {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (enter_ev) (void)hipEventDestroy(enter_ev);
-    if (st) (void)hipStreamSynchronize(st);
     if (hhost) (void)hipHostFree(hhost);
     for (auto& v : ev)
       for (auto& e : v) {
         (void)hipEventDestroy(e.first);
         (void)hipEventDestroy(e.second);
       }
-    release_device_arrays();
-    if (st) (void)hipStreamDestroy(st);
   }
-  // device arrays are members and would be freed after the destructor body;
-  // they are released first so the stream is destroyed last
-  void release_device_arrays();
 };
-
-void stgmg_handle::release_device_arrays() {
-  lv.clear();
-  coarse_inv.release();
-  coarse_part.release();
-  MM.ptr.release();
-  MM.col.release();
-  MM.val.release();
-  e_dev.release();
-  tmp_ns.release();
-  src_buf.release();
-  V.release();
-  Z.release();
-  w.release();
-  partials.release();
-  hdev.release();
-  ydev.release();
-  gin.release();
-  gout.release();
-}
 
 namespace {
 
@@ -636,6 +629,16 @@ void build(stgmg_handle* h) {
     prev.n = H.n;
   }
   h->e_dev.upload(h->T.e, h->st, ctr);
+  {
+    std::vector<double> xq, wq, bq, bp;
+    stgmg::source_tables(d, p.r, xq, wq, bq, bp);
+    h->src_xq.upload(xq, h->st, ctr);
+    h->src_wq.upload(wq, h->st, ctr);
+    h->src_bq.upload(bq, h->st, ctr);
+    h->src_bp.upload(bp, h->st, ctr);
+    h->kfine.upload(h->fine_info.Kcell, h->st, ctr);
+    HIPCHK(hipStreamSynchronize(h->st));
+  }
   h->tmp_ns.alloc(h->fine_info.ns, ctr, h->st);
   h->src_buf.alloc(h->fine_info.n, ctr, h->st);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 256 * sizeof(double), hipHostMallocDefault));
@@ -792,7 +795,8 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     std::unique_ptr<stgmg_handle> h(new stgmg_handle());
     h->prm = *params;  // K_cells is read during build() and cleared afterwards
     h->caller = reinterpret_cast<hipStream_t>(hip_stream);
-    HIPCHK(hipStreamCreateWithFlags(&h->st, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&h->own.s, hipStreamNonBlocking));
+    h->st = h->own.s;
     HIPCHK(hipEventCreateWithFlags(&h->enter_ev, hipEventDisableTiming));
     enter(h.get());
     build(h.get());
@@ -900,13 +904,28 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
     enter(h);
     const auto& F = h->fine_info;
     const int nt = h->T.k + 1;
-    std::vector<double> src(size_t(nt) * F.ns), one;
     for (int b = 0; b < nt; ++b) {
-      const double tb = t_start + 0.5 * h->prm.tau * (1.0 + h->T.x[b]);
-      stgmg::source_vector(F, h->mat, tb, one);
-      for (int64_t i = 0; i < F.ns; ++i) src[size_t(b) * F.ns + i] = h->T.mt[b] * one[i];
+      stgmg::SourceArgs a{};
+      a.d = F.d;
+      a.r = F.r;
+      a.N = F.N;
+      a.nq = 1;
+      for (int x = 0; x < F.d; ++x) a.nq *= F.r + 2;
+      a.n1 = F.n1;
+      a.n1p = F.n1p;
+      a.nv = F.nv;
+      a.ns = F.ns;
+      a.h = 1.0 / F.N;
+      a.rho = h->mat.rho;
+      a.lam = h->mat.lambda;
+      a.mu = h->mat.mu;
+      a.alpha = h->mat.alpha;
+      a.c0 = h->mat.c0;
+      a.t = t_start + 0.5 * h->prm.tau * (1.0 + h->T.x[b]);
+      a.scale = h->T.mt[b];
+      stgmg::k_source(h->st, a, h->src_xq.p, h->src_wq.p, h->src_bq.p, h->src_bp.p, h->kfine.p,
+                      h->src_buf.p + int64_t(b) * F.ns);
     }
-    HIPCHK(hipMemcpyAsync(h->src_buf.p, src.data(), src.size() * sizeof(double), hipMemcpyHostToDevice, h->st));
     h->MM.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
     stgmg::k_slab_rhs(h->st, nt, F.ns, h->e_dev.p, h->tmp_ns.p, h->src_buf.p, rhs_dev);
     HIPCHK(hipGetLastError());
@@ -1030,6 +1049,14 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       }
       if (l == L) {
         res += (S.ns + 1) * 8 + S.nnzMM * 12 + (p.k + 1) * 8 + S.ns * 8 + n * 8;
+        int64_t nq = 1, nls = 1, nlp = 1, ncell = 1;
+        for (int a = 0; a < d; ++a) {
+          nq *= p.r + 2;
+          nls *= p.r + 1;
+          nlp *= p.r;
+          ncell *= int64_t(p.coarse_cells) << l;
+        }
+        res += (4 * nq + (nls + nlp) * nq + ncell) * 8;  // device source tables and K
         const bool graph = p.graph == 1 || (p.graph == -1 && n < (int64_t(1) << 21));
         if (graph) res += 2 * n * 8;
         n_fine = n;

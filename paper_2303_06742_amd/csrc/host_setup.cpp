@@ -1172,6 +1172,39 @@ void source_vector(const LevelHost& L, const Material& m, double t, std::vector<
     for (int64_t i = 0; i < L.ns; ++i) out[i] += part[ch][i];
 }
 
+void source_tables(int d, int r, std::vector<double>& xq, std::vector<double>& wq, std::vector<double>& bq,
+                   std::vector<double>& bp) {
+  std::vector<double> gx, gw;
+  gauss_legendre01(r + 2, gx, gw);
+  const int nq1 = r + 2;
+  int nq = 1;
+  for (int a = 0; a < d; ++a) nq *= nq1;
+  xq.assign(3 * nq, 0.0);
+  wq.assign(nq, 1.0);
+  Tab ts, tp;
+  int nls = 1, nlp = 1;
+  for (int a = 0; a < d; ++a) {
+    nls *= r + 1;
+    nlp *= r;
+  }
+  bq.assign(size_t(nls) * nq, 0.0);
+  bp.assign(size_t(nlp) * nq, 0.0);
+  for (int q = 0; q < nq; ++q) {
+    double xi[3] = {0, 0, 0};
+    int rem = q;
+    for (int ax = 0; ax < d; ++ax) {
+      xi[ax] = gx[rem % nq1];
+      wq[q] *= gw[rem % nq1];
+      rem /= nq1;
+      xq[3 * q + ax] = xi[ax];
+    }
+    tabulate(r, d, xi, 1.0, ts);
+    tabulate(r - 1, d, xi, 1.0, tp);
+    for (int a = 0; a < nls; ++a) bq[size_t(a) * nq + q] = ts.v[a];
+    for (int a = 0; a < nlp; ++a) bp[size_t(a) * nq + q] = tp.v[a];
+  }
+}
+
 void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out) {
   const int d = L.d;
   out.assign(L.ns, 0.0);

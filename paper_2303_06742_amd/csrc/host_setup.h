@@ -104,6 +104,10 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind);
 // Built-in prescribed solution u_i = S sin t, p = S cos t, S = prod sin(pi x_j):
 // source vector S(t) of one time node (u-eq rows zero), and nodal interpolant.
 void source_vector(const LevelHost& L, const Material& m, double t, std::vector<double>& out);
+// Reference-cell tables for the device source: (r+2)^d Gauss points xq[nq][3] (on [0,1]^d),
+// weights wq[nq] (reference cell, summing to 1), basis values bq[(r+1)^d][nq], bp[r^d][nq].
+void source_tables(int d, int r, std::vector<double>& xq, std::vector<double>& wq, std::vector<double>& bq,
+                   std::vector<double>& bp);
 void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out);
 
 }  // namespace stgmg

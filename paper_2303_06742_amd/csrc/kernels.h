@@ -77,6 +77,18 @@ void k_multi_axpy(hipStream_t st, const double* V, int64_t ldv, int m, const dou
                   int64_t n);
 void k_scale_copy(hipStream_t st, const double* src, const double* nrm2, double* dst, int64_t n);
 void k_axpby(hipStream_t st, double a, const double* x, double b, const double* y, double* out, int64_t n);
+// Source S(t) of the built-in prescribed solution on one level (one time node, n_s values,
+// u-equation rows zero): for every node, the sum over its adjacent cells and their
+// (r+2)^d Gauss points of w_q phi_node(x_q) f(x_q, t) (v-equation rows) or g (p-equation
+// rows).  Tables (host): reference points xq[nq][3], weights wq[nq] (reference cell),
+// basis values bq[nloc_r][nq] of Q_r and bp[nloc_{r-1}][nq] of Q_{r-1}.
+struct SourceArgs {
+  int d, r, N, nq;
+  int64_t n1, n1p, nv, ns;
+  double h, rho, lam, mu, alpha, c0, t, scale;
+};
+void k_source(hipStream_t st, const SourceArgs& a, const double* xq, const double* wq, const double* bq,
+              const double* bp, const double* Kcell, double* out);
 void k_slab_rhs(hipStream_t st, int nt, int64_t ns, const double* e, const double* mmx, const double* src,
                 double* rhs);
 
