@@ -119,7 +119,8 @@ struct LevelDev {
   DArr<double> inv64, winv, y;
   DArr<float> inv32;
   DevCsr P, R;  // prolongation from level-1 and its transpose
-  DevCsr MMs, KKs;  // spatial MM and KK (time-block patch solves)
+  DevCsr MMs, KKs;  // spatial MM and KK: the level operator A = D^t (x) MM + M^t (x) KK
+  int op_lanes = 16;
   double alg_inv_entries = 0;  // stored inverse values excluding padding
   DArr<double> b, d, r;
   std::vector<int64_t> poff_h, ioff_h;
@@ -161,8 +162,8 @@ struct stgmg_handle {
   stgmg::Material mat{};
   stgmg::TimeConsts T;
   stgmg::TimeBlockConsts tbc{};
+  stgmg::TimeOp top{};
   bool tb = false;
-  DevCsr MM;
   DArr<double> e_dev, tmp_ns, src_buf;
   DArr<double> src_xq, src_wq, src_bq, src_bp, kfine;  // device source tables
   // kernel timing (finest level): event pairs per kernel class
@@ -272,13 +273,20 @@ struct ProfScope {
   }
 };
 
+// Level operator: mode 0 y = A_l x, mode 1 y = b - A_l x (factored form).
+void op_apply(stgmg_handle* h, int l, int mode, const double* x, const double* b, double* y) {
+  const LevelDev& L = h->lv[l];
+  stgmg::k_kron_spmv(h->st, mode, h->top, L.ns, L.MMs.ptr.p, L.MMs.col.p, L.MMs.val.p, L.KKs.ptr.p, L.KKs.col.p,
+                     L.KKs.val.p, x, b, y, L.op_lanes);
+}
+
 void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool zero_start) {
   LevelDev& L = h->lv[l];
   for (int j = 0; j < sweeps; ++j) {
     const double* r = b;
     if (!(j == 0 && zero_start)) {
       ProfScope ps(h, STGMG_PROF_RESIDUAL, l);
-      L.A.apply(h->st, 1, d, b, L.r.p);
+      op_apply(h, l, 1, d, b, L.r.p);
       r = L.r.p;
     }
     {
@@ -309,7 +317,7 @@ void vcycle(stgmg_handle* h, int l, const double* b, double* d) {
   const int J = h->prm.n_smooth;
   stgmg::k_fill_zero(h->st, d, L.n);
   smooth(h, l, b, d, J, true);
-  L.A.apply(h->st, 1, d, b, L.r.p);
+  op_apply(h, l, 1, d, b, L.r.p);
   L.R.apply(h->st, 0, L.r.p, nullptr, C.b.p);
   vcycle(h, l - 1, C.b.p, C.d.p);
   L.P.apply(h->st, 2, C.d.p, nullptr, d);
@@ -332,6 +340,11 @@ void build(stgmg_handle* h) {
   h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
   h->T = stgmg::make_time_consts(p.k, p.tau);
   h->tb = p.time_blocks != 0;
+  h->top.nt = p.k + 1;
+  for (int b = 0; b <= p.k; ++b) {
+    h->top.mt[b] = h->T.mt[b];
+    for (int a = 0; a <= p.k; ++a) h->top.D[b * (p.k + 1) + a] = h->T.Dt[b * (p.k + 1) + a];
+  }
   if (h->tb) {
     const stgmg::TimeBlocks B = stgmg::make_time_blocks(h->T);
     h->tbc.nt = B.nt;
@@ -394,14 +407,25 @@ void build(stgmg_handle* h) {
   LevelHost prev;
   for (int l = 0; l <= L; ++l) {
     LevelHost H;
-    stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1,
-                          l == L || (h->tb && l >= 1), h->tb && l >= 1};
+    stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1, true, true,
+                          l == 0 || !h->tb};
     stgmg::build_level(o, h->mat, Kl[l], H, nth);
     LevelDev& D = h->lv[l];
     D.N = H.N;
     D.n = H.n;
     D.ns = H.ns;
-    D.A.upload(H.A, h->st, ctr);
+    if (l >= 1 && !h->tb) D.A.upload(H.A, h->st, ctr);  // full-inverse patch extraction reads it
+    D.MMs.upload(H.MM, h->st, ctr);
+    D.KKs.upload(H.KK, h->st, ctr);
+    {
+      const double avg = H.ns ? double(H.MM.col.size() + H.KK.col.size()) / double(H.ns) : 0.0;
+      D.op_lanes = avg < 12 ? 4 : 8;  // 8 lanes per spatial row measured best on the 256^2 dG(2) operator
+      if (const char* e = std::getenv("STGMG_OP_LANES")) {  // tuning override
+        const int v = std::atoi(e);
+        if (v == 4 || v == 8 || v == 16 || v == 32) D.op_lanes = std::max(v, p.k + 1);
+      }
+      D.op_lanes = std::max(D.op_lanes, 4);
+    }
     D.b.alloc(H.n, ctr, h->st);
     D.d.alloc(H.n, ctr, h->st);
     D.r.alloc(H.n, ctr, h->st);
@@ -533,8 +557,6 @@ void build(stgmg_handle* h) {
       } else {
         // time-block inverses: spatial MM_P, KK_P -> one (real or 2x2-block complex) matrix per
         // kept eigenvalue -> batched Gauss-Jordan, output mapped into the block layout
-        D.MMs.upload(H.MM, h->st, ctr);
-        D.KKs.upload(H.KK, h->st, ctr);
         const int nt = p.k + 1, nblk = h->tbc.nblk;
         const int max_ns = max_np / nt;
         bool any_c = false;
@@ -603,10 +625,10 @@ void build(stgmg_handle* h) {
                          "patch " + std::to_string(q) + " of level " + std::to_string(l) + " is singular");
     }
     if (l == L) {
-      h->MM.upload(H.MM, h->st, ctr);
       h->fine_info = H;
       h->fine_info.A = stgmg::Csr();
       h->fine_info.MM = stgmg::Csr();
+      h->fine_info.KK = stgmg::Csr();
       h->fine_info.pdof.clear();
       h->fine_info.pdof.shrink_to_fit();
       h->fine_info.poff.clear();
@@ -671,11 +693,11 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
   auto t0 = std::chrono::steady_clock::now();
   ensure_krylov(h, m);
   const int64_t n = h->lv[h->L].n;
-  const DevCsr& A = h->lv[h->L].A;
+  const int Lf = h->L;
   hipStream_t st = h->st;
   stgmg_info inf{};
   // r0 = rhs - A x0
-  A.apply(st, 1, x, rhs, h->w.p);
+  op_apply(h, Lf, 1, x, rhs, h->w.p);
   const double b0sq = device_norm2(h, h->w.p, n);
   if (!std::isfinite(b0sq)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite initial residual (rhs or x0)");
   const double beta0 = std::sqrt(b0sq);
@@ -701,7 +723,7 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
       double* vj = h->V.p + int64_t(j) * n;
       double* zj = h->Z.p + int64_t(j) * n;
       apply_B(h, vj, zj);
-      A.apply(st, 0, zj, nullptr, h->w.p);
+      op_apply(h, Lf, 0, zj, nullptr, h->w.p);
       // classical Gram-Schmidt, twice (CGS2)
       double* h1 = h->hdev.p;
       double* h2 = h->hdev.p + (m + 2);
@@ -744,7 +766,7 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
     }
     HIPCHK(hipMemcpyAsync(h->ydev.p, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
     stgmg::k_multi_axpy(st, h->Z.p, n, jd, h->ydev.p, 1.0, x, n);
-    A.apply(st, 1, x, rhs, h->w.p);
+    op_apply(h, Lf, 1, x, rhs, h->w.p);
     beta = std::sqrt(device_norm2(h, h->w.p, n));
     if (!std::isfinite(beta)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite residual");
     if (beta > target) inf.restarts++;
@@ -820,7 +842,7 @@ stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, 
     const int l = level_index(h, level);
     if (n_dofs) *n_dofs = h->lv[l].n;
     if (n_patches) *n_patches = h->lv[l].npatch;
-    if (nnz) *nnz = h->lv[l].A.nnz;
+    if (nnz) *nnz = h->lv[l].MMs.nnz + h->lv[l].KKs.nnz;
     if (hbm_bytes) *hbm_bytes = h->bytes;
     return STGMG_OK;
   });
@@ -840,7 +862,7 @@ stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* 
     if (!h || !x_dev || !y_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
     enter(h);
     const int l = level_index(h, level);
-    h->lv[l].A.apply(h->st, 0, x_dev, nullptr, y_dev);
+    op_apply(h, l, 0, x_dev, nullptr, y_dev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->st));
     return STGMG_OK;
@@ -926,7 +948,7 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
       stgmg::k_source(h->st, a, h->src_xq.p, h->src_wq.p, h->src_bq.p, h->src_bp.p, h->kfine.p,
                       h->src_buf.p + int64_t(b) * F.ns);
     }
-    h->MM.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
+    h->lv[h->L].MMs.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
     stgmg::k_slab_rhs(h->st, nt, F.ns, h->e_dev.p, h->tmp_ns.p, h->src_buf.p, rhs_dev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1021,7 +1043,8 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
     for (int l = 0; l <= L; ++l) {
       const stgmg::LevelSizes S = stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch);
       const int64_t n = S.n;
-      res += (n + 1) * 8 + S.nnzA * 12 + 3 * n * 8;
+      // factored operator: spatial MM and KK; vectors b, d, r
+      res += 2 * (S.ns + 1) * 8 + (S.nnzMM + S.nnzKK) * 12 + 3 * n * 8;
       if (l == 0) {
         res += n * stgmg::inv_ld(int(n)) * 8 + int64_t(stgmg::dense_gemv_chunks(int(n))) * n * 8;
         temp_peak = std::max(temp_peak, n * n * 8 + 32 * n * 8 + 3 * n * 8 + 64);
@@ -1029,6 +1052,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
         res += (n + 1) * 8 + S.nnzP * 12 + (n_prev + 1) * 8 + S.nnzP * 12;
         res += 2 * (S.npatch + 1) * 8 + S.sum_np * 4 + (n + 1) * 8 + S.sum_np * 8 + n * 8 + S.sum_np * 8;
         if (!p.time_blocks) {
+          res += (n + 1) * 8 + S.nnzA * 12;  // assembled space-time CSR for the patch extraction
           res += S.sum_np_ld * w;
           const int64_t stride = int64_t(S.max_np) * S.max_np;
           const int64_t batch =
@@ -1037,7 +1061,6 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
                                               S.npatch * 4);
         } else {
           res += (nreal + 2 * ncplx) * S.sum_ns_ldh * w;
-          res += 2 * (S.ns + 1) * 8 + (S.nnzMM + S.nnzKK) * 12;
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
           const int64_t per_patch = (nreal + 4 * ncplx) * sq;
           const int64_t batch =
@@ -1048,7 +1071,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
         }
       }
       if (l == L) {
-        res += (S.ns + 1) * 8 + S.nnzMM * 12 + (p.k + 1) * 8 + S.ns * 8 + n * 8;
+        res += (p.k + 1) * 8 + S.ns * 8 + n * 8;  // e, MM x_prev, source
         int64_t nq = 1, nls = 1, nlp = 1, ncell = 1;
         for (int a = 0; a < d; ++a) {
           nq *= p.r + 2;
@@ -1103,7 +1126,7 @@ stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches,
       const double sum_np = F.npatch ? double(F.poff_h[F.npatch]) : 0.0;
       bytes = w * F.alg_inv_entries + 16.0 * sum_np;
     } else {
-      bytes = 8.0 * double(F.A.nnz) + 24.0 * double(F.n);
+      bytes = 8.0 * double(F.MMs.nnz + F.KKs.nnz) + 24.0 * double(F.n);
     }
     if (launches) *launches = int64_t(h->ev_used[what]);
     if (total_ms) *total_ms = ms;

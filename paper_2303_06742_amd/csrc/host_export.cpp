@@ -20,7 +20,7 @@ long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double ta
     long long nc = 1;
     for (int a = 0; a < d; ++a) nc *= N;
     std::vector<double> K(Kcell, Kcell + nc);
-    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true};
+    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true, true};
     stgmg::Material m{rho, lambda, mu, alpha, c0};
     g_level = stgmg::LevelHost();
     stgmg::build_level(o, m, K, g_level, 4);

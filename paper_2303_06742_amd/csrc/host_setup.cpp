@@ -701,16 +701,18 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
       kklen[i] = int64_t(kk.size());
     }
   });
-  L.A.nrows = L.n;
-  L.A.ncols = L.n;
-  L.A.ptr.assign(L.n + 1, 0);
-  for (int b = 0; b < nt; ++b)
-    for (int64_t i = 0; i < ns; ++i) L.A.ptr[b * ns + i + 1] = slen[i];
-  for (int64_t i = 0; i < L.n; ++i) L.A.ptr[i + 1] += L.A.ptr[i];
-  const int64_t nnz = L.A.ptr[L.n];
-  if (nnz > INT64_C(4000000000)) throw std::runtime_error("level operator too large");
-  L.A.col.resize(nnz);
-  L.A.val.resize(nnz);
+  if (o.need_A) {
+    L.A.nrows = L.n;
+    L.A.ncols = L.n;
+    L.A.ptr.assign(L.n + 1, 0);
+    for (int b = 0; b < nt; ++b)
+      for (int64_t i = 0; i < ns; ++i) L.A.ptr[b * ns + i + 1] = slen[i];
+    for (int64_t i = 0; i < L.n; ++i) L.A.ptr[i + 1] += L.A.ptr[i];
+    const int64_t nnz = L.A.ptr[L.n];
+    if (nnz > INT64_C(4000000000)) throw std::runtime_error("level operator too large");
+    L.A.col.resize(nnz);
+    L.A.val.resize(nnz);
+  }
   if (o.need_MM) {
     L.MM.nrows = ns;
     L.MM.ncols = ns;
@@ -746,7 +748,7 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
           L.KK.val[p++] = e.val;
         }
       }
-      for (int b = 0; b < nt; ++b) {
+      for (int b = 0; b < nt && o.need_A; ++b) {
         int64_t p = L.A.ptr[b * ns + i];
         for (int a = 0; a < nt; ++a) {
           const double D = T.Dt[b * nt + a];

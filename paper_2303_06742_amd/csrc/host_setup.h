@@ -81,6 +81,7 @@ struct BuildOptions {
   bool need_patches;
   bool need_MM;
   bool need_KK = false;
+  bool need_A = true;  // the assembled space-time CSR (otherwise only the spatial MM, KK)
 };
 
 // Assemble one level.  Kcell: per-cell K (N^d values).

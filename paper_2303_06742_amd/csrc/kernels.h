@@ -16,6 +16,15 @@ __host__ __device__ inline int inv_ld(int n) { return (n + 3) & ~3; }
 void k_csr(hipStream_t st, int mode, int64_t nrows, const int64_t* ptr, const int32_t* col, const double* val,
            const double* x, const double* b, double* y, int lanes);
 void k_fill_zero(hipStream_t st, double* a, int64_t n);
+// Level operator in factored form A = D^t (x) MM + M^t (x) KK (spatial CSRs MM, KK of n_s rows):
+// mode 0: y = A x; mode 1: y = b - A x.  nt = k + 1 <= 4.
+struct TimeOp {
+  int nt;
+  double D[16], mt[4];
+};
+void k_kron_spmv(hipStream_t st, int mode, const TimeOp& top, int64_t ns, const int64_t* mptr, const int32_t* mcol,
+                 const double* mval, const int64_t* kptr, const int32_t* kcol, const double* kval, const double* x,
+                 const double* b, double* y, int lanes);
 void k_patch_extract_t(hipStream_t st, int64_t p0, int64_t count, int max_np, const int64_t* poff,
                        const int32_t* pdof, const int64_t* ptr, const int32_t* col, const double* val,
                        const int64_t* woff, double* W);

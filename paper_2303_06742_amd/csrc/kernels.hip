@@ -59,6 +59,82 @@ static void launch_csr(hipStream_t st, int64_t nrows, const int64_t* ptr, const 
   hipLaunchKernelGGL((csr_kernel<G, MODE>), dim3(grid), dim3(bs), 0, st, nrows, ptr, col, val, x, b, y);
 }
 
+// Factored level operator: G lanes per spatial row i read the row of MM and of KK once
+// and accumulate u_a = MM[i,:] x_a, v_a = KK[i,:] x_a for every time node a; then
+// (A x)_b[i] = sum_a D[b][a] u_a + mt[b] v_b.
+template <int G, int MODE, int NT>
+__global__ void __launch_bounds__(256) kron_spmv_kernel(TimeOp top, int64_t ns, const int64_t* __restrict__ mptr,
+                                                        const int32_t* __restrict__ mcol,
+                                                        const double* __restrict__ mval,
+                                                        const int64_t* __restrict__ kptr,
+                                                        const int32_t* __restrict__ kcol,
+                                                        const double* __restrict__ kval,
+                                                        const double* __restrict__ x, const double* __restrict__ b,
+                                                        double* __restrict__ y) {
+  const int lane = threadIdx.x % G;
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+  if (row >= ns) return;
+  double u[NT], v[NT];
+#pragma unroll
+  for (int a = 0; a < NT; ++a) u[a] = v[a] = 0.0;
+  for (int64_t p = mptr[row] + lane; p < mptr[row + 1]; p += G) {
+    const int64_t c = mcol[p];
+    const double w = mval[p];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) u[a] += w * x[a * ns + c];
+  }
+  for (int64_t p = kptr[row] + lane; p < kptr[row + 1]; p += G) {
+    const int64_t c = kcol[p];
+    const double w = kval[p];
+#pragma unroll
+    for (int a = 0; a < NT; ++a) v[a] += w * x[a * ns + c];
+  }
+#pragma unroll
+  for (int a = 0; a < NT; ++a) {
+    u[a] = group_sum<G>(u[a]);
+    v[a] = group_sum<G>(v[a]);
+  }
+  if (lane < NT) {
+    const int bb = lane;  // this lane writes time node bb (register arrays indexed with constants only)
+    double vb = 0.0, s = 0.0;
+#pragma unroll
+    for (int a = 0; a < NT; ++a) {
+      if (a == bb) vb = v[a];
+      s += top.D[bb * NT + a] * u[a];
+    }
+    const double acc = s + top.mt[bb] * vb;
+    const int64_t o = bb * ns + row;
+    if (MODE == 0) y[o] = acc;
+    if (MODE == 1) y[o] = b[o] - acc;
+  }
+}
+
+template <int G, int MODE>
+static void launch_kron(hipStream_t st, const TimeOp& top, int64_t ns, const int64_t* mptr, const int32_t* mcol,
+                        const double* mval, const int64_t* kptr, const int32_t* kcol, const double* kval,
+                        const double* x, const double* b, double* y) {
+  const int bs = 256;
+  const int64_t grid = (ns + bs / G - 1) / (bs / G);
+  switch (top.nt) {
+    case 1:
+      hipLaunchKernelGGL((kron_spmv_kernel<G, MODE, 1>), dim3(grid), dim3(bs), 0, st, top, ns, mptr, mcol, mval, kptr,
+                         kcol, kval, x, b, y);
+      break;
+    case 2:
+      hipLaunchKernelGGL((kron_spmv_kernel<G, MODE, 2>), dim3(grid), dim3(bs), 0, st, top, ns, mptr, mcol, mval, kptr,
+                         kcol, kval, x, b, y);
+      break;
+    case 3:
+      hipLaunchKernelGGL((kron_spmv_kernel<G, MODE, 3>), dim3(grid), dim3(bs), 0, st, top, ns, mptr, mcol, mval, kptr,
+                         kcol, kval, x, b, y);
+      break;
+    default:
+      hipLaunchKernelGGL((kron_spmv_kernel<G, MODE, 4>), dim3(grid), dim3(bs), 0, st, top, ns, mptr, mcol, mval, kptr,
+                         kcol, kval, x, b, y);
+      break;
+  }
+}
+
 // ---------------------------------------------------------------- patch extraction
 // One block per patch of the batch: W (row-major n x n) receives A_P^T, i.e.
 // W[mu * n + nu] = A[dof(nu)][dof(mu)].  W must be zero on entry.
@@ -904,6 +980,26 @@ void k_csr(hipStream_t st, int mode, int64_t nrows, const int64_t* ptr, const in
     STGMG_CSR(64)
   }
 #undef STGMG_CSR
+}
+
+void k_kron_spmv(hipStream_t st, int mode, const TimeOp& top, int64_t ns, const int64_t* mptr, const int32_t* mcol,
+                 const double* mval, const int64_t* kptr, const int32_t* kcol, const double* kval, const double* x,
+                 const double* b, double* y, int lanes) {
+  if (ns == 0) return;
+  // at least nt lanes per row: lane b writes time node b
+#define STGMG_KRON(G)                                                                              \
+  if (mode == 0) dev::launch_kron<G, 0>(st, top, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y); \
+  else dev::launch_kron<G, 1>(st, top, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y);
+  if (lanes <= 4) {
+    STGMG_KRON(4)
+  } else if (lanes <= 8) {
+    STGMG_KRON(8)
+  } else if (lanes <= 16) {
+    STGMG_KRON(16)
+  } else {
+    STGMG_KRON(32)
+  }
+#undef STGMG_KRON
 }
 
 void k_fill_zero(hipStream_t st, double* a, int64_t n) {
