@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 
 #include "kernels.h"
 
@@ -407,38 +408,12 @@ __global__ void __launch_bounds__(256) gj_invert_kernel(const GjDesc* __restrict
 // values of its patch exactly once, front to back.  Each thread owns RPT
 // consecutive rows and reads them with one 16-byte load per column.
 template <typename T, int RPT>
-struct Vec16;
-template <>
-struct Vec16<double, 2> {
-  using type = double2;
-};
-template <>
-struct Vec16<float, 4> {
-  using type = float4;
-};
-
-template <typename T, int RPT>
-__device__ inline void fma_vec(T* acc, const typename Vec16<T, RPT>::type& v, T s);
-template <>
-__device__ inline void fma_vec<double, 2>(double* acc, const double2& v, double s) {
-  acc[0] += v.x * s;
-  acc[1] += v.y * s;
-}
-template <>
-__device__ inline void fma_vec<float, 4>(float* acc, const float4& v, float s) {
-  acc[0] += v.x * s;
-  acc[1] += v.y * s;
-  acc[2] += v.z * s;
-  acc[3] += v.w * s;
-}
-
-template <typename T, int RPT>
 __global__ void __launch_bounds__(512) patch_apply_kernel(int64_t npatch, const int64_t* __restrict__ poff,
                                                           const int32_t* __restrict__ pdof,
                                                           const int64_t* __restrict__ ioff,
                                                           const T* __restrict__ inv, const double* __restrict__ r,
                                                           double* __restrict__ y) {
-  using V = typename Vec16<T, RPT>::type;
+  typedef T V __attribute__((ext_vector_type(RPT)));
   extern __shared__ char smem[];
   T* rl = reinterpret_cast<T*>(smem);
   const int64_t p = blockIdx.x;
@@ -451,49 +426,80 @@ __global__ void __launch_bounds__(512) patch_apply_kernel(int64_t npatch, const 
   if (i0 >= n) return;
   const V* X = reinterpret_cast<const V*>(inv + ioff[p] + i0);
   const int ldv = ld / RPT;
-  T a[RPT], b[RPT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) a[q] = b[q] = T(0);
+  V a = V(0), b = V(0);
   int j = 0;
   for (; j + 7 < n; j += 8) {
-    V v0 = X[int64_t(j) * ldv], v1 = X[int64_t(j + 1) * ldv], v2 = X[int64_t(j + 2) * ldv],
-      v3 = X[int64_t(j + 3) * ldv], v4 = X[int64_t(j + 4) * ldv], v5 = X[int64_t(j + 5) * ldv],
-      v6 = X[int64_t(j + 6) * ldv], v7 = X[int64_t(j + 7) * ldv];
-    fma_vec<T, RPT>(a, v0, rl[j]);
-    fma_vec<T, RPT>(b, v1, rl[j + 1]);
-    fma_vec<T, RPT>(a, v2, rl[j + 2]);
-    fma_vec<T, RPT>(b, v3, rl[j + 3]);
-    fma_vec<T, RPT>(a, v4, rl[j + 4]);
-    fma_vec<T, RPT>(b, v5, rl[j + 5]);
-    fma_vec<T, RPT>(a, v6, rl[j + 6]);
-    fma_vec<T, RPT>(b, v7, rl[j + 7]);
+    const V v0 = __builtin_nontemporal_load(X + int64_t(j) * ldv);
+    const V v1 = __builtin_nontemporal_load(X + int64_t(j + 1) * ldv);
+    const V v2 = __builtin_nontemporal_load(X + int64_t(j + 2) * ldv);
+    const V v3 = __builtin_nontemporal_load(X + int64_t(j + 3) * ldv);
+    const V v4 = __builtin_nontemporal_load(X + int64_t(j + 4) * ldv);
+    const V v5 = __builtin_nontemporal_load(X + int64_t(j + 5) * ldv);
+    const V v6 = __builtin_nontemporal_load(X + int64_t(j + 6) * ldv);
+    const V v7 = __builtin_nontemporal_load(X + int64_t(j + 7) * ldv);
+    a += v0 * rl[j];
+    b += v1 * rl[j + 1];
+    a += v2 * rl[j + 2];
+    b += v3 * rl[j + 3];
+    a += v4 * rl[j + 4];
+    b += v5 * rl[j + 5];
+    a += v6 * rl[j + 6];
+    b += v7 * rl[j + 7];
   }
-  for (; j < n; ++j) fma_vec<T, RPT>(a, X[int64_t(j) * ldv], rl[j]);
+  for (; j < n; ++j) a += __builtin_nontemporal_load(X + int64_t(j) * ldv) * rl[j];
+  a += b;
 #pragma unroll
   for (int q = 0; q < RPT; ++q)
-    if (i0 + q < n) y[o + i0 + q] = double(a[q] + b[q]);
+    if (i0 + q < n) y[o + i0 + q] = double(a[q]);
 }
 
 // Time-block patch solve: y_P = (Q x I) blockdiag(X_a) (Q^{-1} (M^t)^{-1} x I) r_P with the
 // spatial block inverses X_a stored per patch one after another: a real block as ns
 // columns of stride inv_ld(ns); a complex block as ns columns of stride 2 inv_ld(ns)
 // holding Re X_a in rows [0, ns) and Im X_a in rows [inv_ld(ns), inv_ld(ns) + ns).
-template <typename T, int RPT>
-__global__ void __launch_bounds__(256) patch_apply_tb_kernel(TimeBlockConsts tb, const int64_t* __restrict__ poff,
+// Each thread owns R consecutive rows (one 16-byte load per column); W waves split the
+// columns of every block into W contiguous ranges and their partial images are summed
+// in LDS; NTL selects streaming (non-temporal) loads for the stored inverses.
+template <typename T>
+struct NV16;
+template <>
+struct NV16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int R = 2;
+};
+template <>
+struct NV16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int R = 4;
+};
+
+template <bool NTL, typename V>
+__device__ inline V ld16(const V* p) {
+  if constexpr (NTL)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <typename T, int W, bool NTL>
+__global__ void __launch_bounds__(512) patch_apply_tb_kernel(TimeBlockConsts tb, const int64_t* __restrict__ poff,
                                                              const int32_t* __restrict__ pdof,
                                                              const int64_t* __restrict__ ioff,
                                                              const T* __restrict__ inv, const double* __restrict__ r,
                                                              double* __restrict__ y) {
-  using V = typename Vec16<T, RPT>::type;
+  using V = typename NV16<T>::type;
+  constexpr int R = NV16<T>::R;
   extern __shared__ double sm[];
   const int64_t p = blockIdx.x;
   const int64_t o = poff[p];
   const int n = int(poff[p + 1] - o);
   const int nt = tb.nt, nblk = tb.nblk;
   const int ns = n / nt, ldh = inv_ld(ns);
-  double* rl = sm;                              // n
-  T* sv = reinterpret_cast<T*>(sm + n);         // nblk * 2 * ldh (re, im)
-  double* tv = sm + n + 2 * nblk * ldh;         // nblk * 2 * ldh (re, im)
+  const int per_w = blockDim.x / W;  // threads per column range
+  const int w = threadIdx.x / per_w, tl = threadIdx.x % per_w;
+  double* rl = sm;                          // n
+  T* sv = reinterpret_cast<T*>(sm + n);     // nblk * 2 * ldh (re, im) as T
+  double* tv = sm + n + 2 * nblk * ldh;     // W partial images, nblk * 2 * ldh each
   for (int i = threadIdx.x; i < n; i += blockDim.x) rl[i] = r[pdof[o + i]];
   __syncthreads();
   for (int i = threadIdx.x; i < ns; i += blockDim.x)
@@ -508,7 +514,9 @@ __global__ void __launch_bounds__(256) patch_apply_tb_kernel(TimeBlockConsts tb,
       sv[(2 * a + 1) * ldh + i] = T(si);
     }
   __syncthreads();
-  const int i0 = RPT * int(threadIdx.x);
+  const int i0 = R * tl;
+  const int jc = (ns + W - 1) / W, j0 = w * jc, j1 = min(ns, j0 + jc);
+  double* tw = tv + int64_t(w) * nblk * 2 * ldh;
   int64_t off = ioff[p];
   for (int a = 0; a < nblk; ++a) {
     const T* sr = sv + (2 * a) * ldh;
@@ -516,24 +524,23 @@ __global__ void __launch_bounds__(256) patch_apply_tb_kernel(TimeBlockConsts tb,
     if (!tb.cplx[a]) {
       if (i0 < ns) {
         const V* X = reinterpret_cast<const V*>(inv + off + i0);
-        const int ldv = ldh / RPT;
-        T acc[RPT], acc2[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) acc[q] = acc2[q] = T(0);
-        int j = 0;
-        for (; j + 3 < ns; j += 4) {
-          V v0 = X[int64_t(j) * ldv], v1 = X[int64_t(j + 1) * ldv], v2 = X[int64_t(j + 2) * ldv],
-            v3 = X[int64_t(j + 3) * ldv];
-          fma_vec<T, RPT>(acc, v0, sr[j]);
-          fma_vec<T, RPT>(acc2, v1, sr[j + 1]);
-          fma_vec<T, RPT>(acc, v2, sr[j + 2]);
-          fma_vec<T, RPT>(acc2, v3, sr[j + 3]);
+        const int ldv = ldh / R;
+        V acc = V(0), acc2 = V(0);
+        int j = j0;
+        for (; j + 3 < j1; j += 4) {
+          const V v0 = ld16<NTL>(X + int64_t(j) * ldv), v1 = ld16<NTL>(X + int64_t(j + 1) * ldv);
+          const V v2 = ld16<NTL>(X + int64_t(j + 2) * ldv), v3 = ld16<NTL>(X + int64_t(j + 3) * ldv);
+          acc += v0 * sr[j];
+          acc2 += v1 * sr[j + 1];
+          acc += v2 * sr[j + 2];
+          acc2 += v3 * sr[j + 3];
         }
-        for (; j < ns; ++j) fma_vec<T, RPT>(acc, X[int64_t(j) * ldv], sr[j]);
+        for (; j < j1; ++j) acc += ld16<NTL>(X + int64_t(j) * ldv) * sr[j];
+        acc += acc2;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          tv[(2 * a) * ldh + i0 + q] = double(acc[q] + acc2[q]);
-          tv[(2 * a + 1) * ldh + i0 + q] = 0.0;
+        for (int q = 0; q < R; ++q) {
+          tw[(2 * a) * ldh + i0 + q] = double(acc[q]);
+          tw[(2 * a + 1) * ldh + i0 + q] = 0.0;
         }
       }
       off += int64_t(ns) * ldh;
@@ -541,34 +548,28 @@ __global__ void __launch_bounds__(256) patch_apply_tb_kernel(TimeBlockConsts tb,
       if (i0 < ns) {
         const V* Xr = reinterpret_cast<const V*>(inv + off + i0);
         const V* Xi = reinterpret_cast<const V*>(inv + off + ldh + i0);
-        const int ldv = 2 * ldh / RPT;
-        T tr[RPT], ti[RPT], tr2[RPT], ti2[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) tr[q] = ti[q] = tr2[q] = ti2[q] = T(0);
-        int j = 0;
-        for (; j + 1 < ns; j += 2) {
-          V a0 = Xr[int64_t(j) * ldv], b0 = Xi[int64_t(j) * ldv];
-          V a1 = Xr[int64_t(j + 1) * ldv], b1 = Xi[int64_t(j + 1) * ldv];
-          fma_vec<T, RPT>(tr, a0, sr[j]);
-          fma_vec<T, RPT>(tr, b0, -si[j]);
-          fma_vec<T, RPT>(ti, b0, sr[j]);
-          fma_vec<T, RPT>(ti, a0, si[j]);
-          fma_vec<T, RPT>(tr2, a1, sr[j + 1]);
-          fma_vec<T, RPT>(tr2, b1, -si[j + 1]);
-          fma_vec<T, RPT>(ti2, b1, sr[j + 1]);
-          fma_vec<T, RPT>(ti2, a1, si[j + 1]);
+        const int ldv = 2 * ldh / R;
+        V tr = V(0), ti = V(0), tr2 = V(0), ti2 = V(0);
+        int j = j0;
+        for (; j + 1 < j1; j += 2) {
+          const V a0 = ld16<NTL>(Xr + int64_t(j) * ldv), b0 = ld16<NTL>(Xi + int64_t(j) * ldv);
+          const V a1 = ld16<NTL>(Xr + int64_t(j + 1) * ldv), b1 = ld16<NTL>(Xi + int64_t(j + 1) * ldv);
+          tr += a0 * sr[j] - b0 * si[j];
+          ti += b0 * sr[j] + a0 * si[j];
+          tr2 += a1 * sr[j + 1] - b1 * si[j + 1];
+          ti2 += b1 * sr[j + 1] + a1 * si[j + 1];
         }
-        for (; j < ns; ++j) {
-          V a0 = Xr[int64_t(j) * ldv], b0 = Xi[int64_t(j) * ldv];
-          fma_vec<T, RPT>(tr, a0, sr[j]);
-          fma_vec<T, RPT>(tr, b0, -si[j]);
-          fma_vec<T, RPT>(ti, b0, sr[j]);
-          fma_vec<T, RPT>(ti, a0, si[j]);
+        for (; j < j1; ++j) {
+          const V a0 = ld16<NTL>(Xr + int64_t(j) * ldv), b0 = ld16<NTL>(Xi + int64_t(j) * ldv);
+          tr += a0 * sr[j] - b0 * si[j];
+          ti += b0 * sr[j] + a0 * si[j];
         }
+        tr += tr2;
+        ti += ti2;
 #pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-          tv[(2 * a) * ldh + i0 + q] = double(tr[q] + tr2[q]);
-          tv[(2 * a + 1) * ldh + i0 + q] = double(ti[q] + ti2[q]);
+        for (int q = 0; q < R; ++q) {
+          tw[(2 * a) * ldh + i0 + q] = double(tr[q]);
+          tw[(2 * a + 1) * ldh + i0 + q] = double(ti[q]);
         }
       }
       off += int64_t(ns) * 2 * ldh;
@@ -580,7 +581,11 @@ __global__ void __launch_bounds__(256) patch_apply_tb_kernel(TimeBlockConsts tb,
       double acc = 0.0;
       for (int a = 0; a < nblk; ++a) {
         const double qr = tb.qout[2 * (b * nblk + a)], qi = tb.qout[2 * (b * nblk + a) + 1];
-        const double t_r = tv[(2 * a) * ldh + i], t_i = tv[(2 * a + 1) * ldh + i];
+        double t_r = 0.0, t_i = 0.0;
+        for (int ww = 0; ww < W; ++ww) {
+          t_r += tv[int64_t(ww) * nblk * 2 * ldh + (2 * a) * ldh + i];
+          t_i += tv[int64_t(ww) * nblk * 2 * ldh + (2 * a + 1) * ldh + i];
+        }
         acc += tb.cplx[a] ? 2.0 * (qr * t_r - qi * t_i) : qr * t_r;
       }
       y[o + b * ns + i] = acc;
@@ -1092,11 +1097,11 @@ void k_form_time_blocks(hipStream_t st, int64_t count, const TimeBlockConsts& tb
                      wmm, wkk, desc, W);
 }
 
-// r_P (n_P values), then the transformed right-hand sides and the block images, 2 * ldh
-// each per kept eigenvalue (ldh = inv_ld(n_P / nt)).
-static size_t tb_lds(int max_np, int nt, int nblk) {
+// r_P (n_P values), the transformed right-hand sides (2 * ldh per kept eigenvalue) and W
+// partial block images (2 * ldh per kept eigenvalue each), ldh = inv_ld(n_P / nt).
+static size_t tb_lds(int max_np, int nt, int nblk, int W) {
   const int ldh = inv_ld(max_np / nt);
-  return (size_t(max_np) + 4 * size_t(nblk) * ldh) * sizeof(double);
+  return (size_t(max_np) + 2 * size_t(nblk) * ldh * (1 + W)) * sizeof(double);
 }
 
 int patch_apply_tb_threads(int max_ns, bool fp32) {
@@ -1105,19 +1110,40 @@ int patch_apply_tb_threads(int max_ns, bool fp32) {
   return t < 64 ? 64 : t;
 }
 
+// tuning: STGMG_TB_WAVES (1 or 2 column ranges per patch), STGMG_TB_NT (1: streaming loads)
+static void tb_variant(int* W, bool* ntl) {
+  *W = 1;       // measured on the 256^2 dG(2) workload: a second wave per patch does not help,
+  *ntl = true;  // streaming loads do (+9% FP64, +6% FP32)
+  if (const char* e = std::getenv("STGMG_TB_WAVES")) *W = std::atoi(e) == 2 ? 2 : 1;
+  if (const char* e = std::getenv("STGMG_TB_NT")) *ntl = std::atoi(e) != 0;
+}
+
+template <typename T>
+static void launch_tb(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
+                      const int32_t* pdof, const int64_t* ioff, const T* inv, const double* r, double* y) {
+  if (npatch == 0) return;
+  int W;
+  bool ntl;
+  tb_variant(&W, &ntl);
+  const int th = patch_apply_tb_threads(max_np / tb.nt, sizeof(T) == 4) * W;
+  const size_t lds = tb_lds(max_np, tb.nt, tb.nblk, W);
+#define STGMG_TB(WW, NN)                                                                                      \
+  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<T, WW, NN>), dim3(npatch), dim3(th), lds, st, tb, poff, pdof, \
+                     ioff, inv, r, y)
+  if (W == 1 && !ntl) STGMG_TB(1, false);
+  else if (W == 1) STGMG_TB(1, true);
+  else if (!ntl) STGMG_TB(2, false);
+  else STGMG_TB(2, true);
+#undef STGMG_TB
+}
+
 void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
                           const int32_t* pdof, const int64_t* ioff, const double* inv, const double* r, double* y) {
-  if (npatch == 0) return;
-  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<double, 2>), dim3(npatch),
-                     dim3(patch_apply_tb_threads(max_np / tb.nt, false)), tb_lds(max_np, tb.nt, tb.nblk), st, tb, poff, pdof,
-                     ioff, inv, r, y);
+  launch_tb<double>(st, npatch, max_np, tb, poff, pdof, ioff, inv, r, y);
 }
 void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
                           const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y) {
-  if (npatch == 0) return;
-  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<float, 4>), dim3(npatch),
-                     dim3(patch_apply_tb_threads(max_np / tb.nt, true)), tb_lds(max_np, tb.nt, tb.nblk), st, tb, poff, pdof,
-                     ioff, inv, r, y);
+  launch_tb<float>(st, npatch, max_np, tb, poff, pdof, ioff, inv, r, y);
 }
 
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
