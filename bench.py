@@ -20,6 +20,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PATCH_KERNEL = {0: 'patch_apply_kernel', 1: 'patch_apply_tb_kernel'}
 METRIC = "GMRES-GMG solves/s and V-cycle DoF/s at 1e-8 rel. residual; p50/p99 latency"
 
 
@@ -287,7 +288,7 @@ def main():
         'nodal_err_vs_exact': nodal_err,
         'setup_s': setup_s,
         'hbm_bytes_resident': q['bytes'],
-        'roofline': {'bound': 'hbm', 'kernel': 'patch_apply_kernel (finest level)', 'achieved': achieved,
+        'roofline': {'bound': 'hbm', 'kernel': PATCH_KERNEL[cfg.time_blocks] + ' (finest level)', 'achieved': achieved,
                      'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': achieved / HBM_PEAK_GBS,
                      'traffic': measured_traffic(cfg.name, args.precision), 'kernels_hip_sha256': kernel_source_hash(),
                      'avg_launch_ms': avg_pa_ms, 'launches': pa['launches'],
