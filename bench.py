@@ -20,7 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PATCH_KERNEL = {0: 'patch_apply_kernel', 1: 'patch_apply_tb_kernel'}
+PATCH_KERNEL = {0: 'patch_apply_kernel', 1: 'patch_apply_tb_kernel', 2: 'patch_apply_red_kernel'}
+PATCH_SOLVE = {'full': 0, 'tb': 1, 'reduced': 2}
 METRIC = "GMRES-GMG solves/s and V-cycle DoF/s at 1e-8 rel. residual; p50/p99 latency"
 
 
@@ -198,6 +199,9 @@ def main():
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-sample-levels', type=int, default=None,
                     help='levels of the grid the oracle times (default: 32^2 cells in 2D, 8^3 in 3D)')
+    ap.add_argument('--patch-solve', choices=sorted(PATCH_SOLVE), default=None,
+                    help='storage of the patch solves: full space-time inverses, time blocks, or time blocks '
+                         'with the u-equation rows eliminated (default: the workload default)')
     ap.add_argument('--copy-calibration', action='store_true',
                     help='run a plain 1 GiB device copy first (reference for HBM byte counters)')
     args = ap.parse_args()
@@ -213,6 +217,9 @@ def main():
     import torch
     from paper_2303_06742_amd import capi
     cfg = configs()[args.config]
+    if args.patch_solve is not None:
+        from paper_2303_06742_amd import workloads as W
+        cfg = W.scaled(cfg, cfg.levels, name=cfg.name, time_blocks=PATCH_SOLVE[args.patch_solve])
     torch.cuda.set_device(0)
     if args.copy_calibration:
         a = torch.ones(1 << 27, dtype=torch.float64, device='cuda')

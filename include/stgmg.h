@@ -78,11 +78,17 @@ typedef struct {
                             coarse cells take the mean of their 2^d children. Copied. */
   int32_t graph;         /* V-cycle as a captured HIP graph: -1 automatic (hierarchies below
                             2^21 fine unknowns, where launch latency matters), 0 never, 1 always */
-  int32_t time_blocks;   /* 1: each patch solve A_P^{-1} is applied through the eigen-
-                            decomposition of (M^t)^{-1} D^t, since A_P = D^t (x) MM_P + M^t (x) KK_P:
-                            (k+1) spatial inverses of n_P/(k+1) rows are stored instead of one
-                            of n_P rows (the same operator, (k+1)x fewer stored values);
-                            0: the full space-time inverse of Def:VankaOP is stored */
+  int32_t time_blocks;   /* how A_P^{-1} of Def:VankaOP is stored and applied (the same operator
+                            in every mode, up to rounding):
+                            0: the full space-time inverse (n_P^2 values);
+                            1: through the eigen-decomposition of (M^t)^{-1} D^t, since
+                               A_P = D^t (x) MM_P + M^t (x) KK_P: one spatial inverse of n_P/(k+1)
+                               rows per eigenvalue ((k+1)x fewer values);
+                            2: as 1, with the u-equation rows of each spatial block eliminated
+                               (V = lam U - (rho M)^{-1} r_u): stored are (rho M)^{-1} on the
+                               patch nodes, KK_pV (rho M)^{-1}, and one Schur complement inverse
+                               of n_P/(k+1) - nU rows per eigenvalue (about 3x fewer again).
+                            Default of the Python workloads: 2. */
 } stgmg_params;
 
 typedef struct {

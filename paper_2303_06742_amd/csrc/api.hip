@@ -116,6 +116,8 @@ struct LevelDev {
   int max_np = 0;
   DArr<int64_t> poff, ioff, tptr, tidx;
   DArr<int32_t> pdof;
+  DArr<int32_t> pnu;  // reduced solves: velocity dofs nU per patch (one time node)
+  int max_nu = 0, max_nr = 0, max_npr = 0;
   DArr<double> inv64, winv, y;
   DArr<float> inv32;
   DevCsr P, R;  // prolongation from level-1 and its transpose
@@ -124,7 +126,7 @@ struct LevelDev {
   double alg_inv_entries = 0;  // stored inverse values excluding padding
   DArr<double> b, d, r;
   std::vector<int64_t> poff_h, ioff_h;
-  std::vector<int32_t> pdof_h;
+  std::vector<int32_t> pdof_h, pnu_h;
 };
 
 }  // namespace
@@ -163,7 +165,8 @@ struct stgmg_handle {
   stgmg::TimeConsts T;
   stgmg::TimeBlockConsts tbc{};
   stgmg::TimeOp top{};
-  bool tb = false;
+  bool tb = false;   // patch solves through the time eigen-decomposition
+  bool red = false;  // ... with the u-equation rows eliminated
   DArr<double> e_dev, tmp_ns, src_buf;
   DArr<double> src_xq, src_wq, src_bq, src_bp, kfine;  // device source tables
   // kernel timing (finest level): event pairs per kernel class
@@ -236,6 +239,7 @@ void check_params(const stgmg_params* p) {
   const int64_t Nf = int64_t(p->coarse_cells) << (p->levels - 1);
   if (Nf > 4096) throw ApiError(STGMG_ERR_UNSUPPORTED, "grid too fine");
   if (!p->K_cells && !(p->K > 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "K must be > 0");
+  if (p->time_blocks < 0 || p->time_blocks > 2) throw ApiError(STGMG_ERR_INVALID_ARG, "time_blocks must be 0, 1 or 2");
 }
 
 int host_threads() {
@@ -292,7 +296,13 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
     {
       ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
       const bool f32 = h->prm.smoother_prec == STGMG_FP32;
-      if (h->tb && f32)
+      if (h->red && f32)
+        stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, h->tbc, h->prm.dim, L.poff.p,
+                                     L.pdof.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
+      else if (h->red)
+        stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, h->tbc, h->prm.dim, L.poff.p,
+                                     L.pdof.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
+      else if (h->tb && f32)
         stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r,
                                     L.y.p);
       else if (h->tb)
@@ -340,6 +350,7 @@ void build(stgmg_handle* h) {
   h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
   h->T = stgmg::make_time_consts(p.k, p.tau);
   h->tb = p.time_blocks != 0;
+  h->red = p.time_blocks == 2;
   h->top.nt = p.k + 1;
   for (int b = 0; b <= p.k; ++b) {
     h->top.mt[b] = h->T.mt[b];
@@ -440,7 +451,9 @@ void build(stgmg_handle* h) {
       DArr<int32_t> stat;
       const std::vector<int32_t> stat0(1, 0);
       stat.upload(stat0, h->st, nullptr);
-      const int nb = stgmg::gj_panel_width(int(H.n), lds_limit());
+      // one workgroup for small matrices; above a few hundred rows the panel steps over many
+      // workgroups win (1047 rows: 357 ms in one workgroup)
+      const int nb = H.n <= 384 ? stgmg::gj_panel_width(int(H.n), lds_limit()) : 0;
       if (nb != 0) {
         // one workgroup holds the whole inversion
         const int n0 = int(H.n);
@@ -488,10 +501,29 @@ void build(stgmg_handle* h) {
       D.pdof_h = H.pdof;
       D.ioff_h.assign(H.npatch + 1, 0);
       int max_np = 0;
+      if (h->red) D.pnu_h.assign(H.npatch, 0);
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
         max_np = std::max<int>(max_np, int(np));
-        if (h->tb) {
+        if (h->red) {
+          // time node 0 of the patch: V dofs (spatial numbers < nv), U dofs, P dofs
+          const int64_t ns = np / (p.k + 1);
+          int64_t nU = 0;
+          for (int64_t t = 0; t < ns; ++t) nU += H.pdof[H.poff[q] + t] < H.nv ? 1 : 0;
+          const int64_t nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
+          if (nU % d != 0 || nP < 0) throw ApiError(STGMG_ERR_HIP, "unexpected patch layout");
+          D.pnu_h[q] = int32_t(nU);
+          D.max_nu = std::max<int>(D.max_nu, int(nU));
+          D.max_nr = std::max<int>(D.max_nr, int(nr));
+          D.max_npr = std::max<int>(D.max_npr, int(nP));
+          int64_t sz = nn * stgmg::inv_ld(int(nn)) + nU * stgmg::inv_ld(int(nP));
+          D.alg_inv_entries += double(nn * nn + nP * nU);
+          for (int a = 0; a < h->tbc.nblk; ++a) {
+            sz += h->tbc.cplx[a] ? nr * 2 * stgmg::inv_ld(int(nr)) : nr * stgmg::inv_ld(int(nr));
+            D.alg_inv_entries += double(h->tbc.cplx[a] ? 2 * nr * nr : nr * nr);
+          }
+          D.ioff_h[q + 1] = D.ioff_h[q] + sz;
+        } else if (h->tb) {
           const int64_t ns = np / (p.k + 1), ldh = stgmg::inv_ld(int(ns));
           int64_t sz = 0;
           for (int a = 0; a < h->tbc.nblk; ++a) {
@@ -508,6 +540,7 @@ void build(stgmg_handle* h) {
       D.poff.upload(H.poff, h->st, ctr);
       D.pdof.upload(H.pdof, h->st, ctr);
       D.ioff.upload(D.ioff_h, h->st, ctr);
+      if (h->red) D.pnu.upload(D.pnu_h, h->st, ctr);
       D.tptr.upload(H.tptr, h->st, ctr);
       D.tidx.upload(H.tidx, h->st, ctr);
       D.winv.upload(H.winv, h->st, ctr);
@@ -551,6 +584,87 @@ void build(stgmg_handle* h) {
             stgmg::k_gj_invert_f32(h->st, nb, cnt, max_np, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
           else
             stgmg::k_gj_invert_f64(h->st, nb, cnt, max_np, ddesc.back().p, Wb.p, D.inv64.p, stat.p);
+          HIPCHK(hipGetLastError());
+        }
+        HIPCHK(hipStreamSynchronize(h->st));
+      } else if (h->red) {
+        // reduced time-block inverses: spatial MM_P, KK_P -> node mass block and one Schur
+        // complement per kept eigenvalue (real or 2x2-block complex) -> batched Gauss-Jordan;
+        // the (p-equation, V) block of KK_P is copied into the stored layout by the form kernel
+        // and multiplied by the mass inverse after the inversion
+        const int nt = p.k + 1, nblk = h->tbc.nblk;
+        const int max_ns = max_np / nt, max_nr = D.max_nr, max_nn = D.max_nu / d;
+        bool any_c = false;
+        int64_t per_patch = int64_t(max_nn) * max_nn;
+        std::vector<int64_t> blk_woff(nblk);
+        for (int a = 0; a < nblk; ++a) {
+          blk_woff[a] = per_patch;
+          const int64_t na = h->tbc.cplx[a] ? 2 * max_nr : max_nr;
+          per_patch += na * na;
+          any_c = any_c || h->tbc.cplx[a];
+        }
+        const int max_n = std::max(any_c ? 2 * max_nr : max_nr, max_nn);
+        const int nb = stgmg::gj_panel_width(max_n, lds_limit());
+        if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
+        if (stgmg::patch_apply_red_threads(max_nr, p.smoother_prec == STGMG_FP32) > 512 || D.max_nu > 64 * 32)
+          throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the reduced patch solve");
+        const int64_t sq = int64_t(max_ns) * max_ns;
+        const int64_t batch =
+            std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
+        DArr<double> Wb, wmm, wkk;
+        Wb.alloc(batch * per_patch, nullptr, h->st);
+        wmm.alloc(batch * sq, nullptr, h->st);
+        wkk.alloc(batch * sq, nullptr, h->st);
+        std::vector<std::vector<stgmg::GjDesc>> descs;
+        std::vector<std::vector<int32_t>> nss, nus;
+        std::vector<DArr<stgmg::GjDesc>> ddesc;
+        std::vector<DArr<int32_t>> dns, dnu;
+        for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
+          const int64_t cnt = std::min(batch, H.npatch - p0);
+          std::vector<stgmg::GjDesc> dd(cnt * (nblk + 1));
+          std::vector<int32_t> ns_of(cnt), nu_of(cnt);
+          for (int64_t i = 0; i < cnt; ++i) {
+            const int ns = int(H.poff[p0 + i + 1] - H.poff[p0 + i]) / nt, nU = D.pnu_h[p0 + i];
+            const int nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
+            const int ldn = stgmg::inv_ld(nn), ldp = stgmg::inv_ld(nP), ldr = stgmg::inv_ld(nr);
+            ns_of[i] = ns;
+            nu_of[i] = nU;
+            int64_t oo = D.ioff_h[p0 + i];
+            dd[i * (nblk + 1)] = {nn, nn, ldn, 0, 0, int32_t(p0 + i), i * per_patch, oo};
+            oo += int64_t(nn) * ldn + int64_t(nU) * ldp;
+            for (int a = 0; a < nblk; ++a) {
+              const bool c = h->tbc.cplx[a] != 0;
+              dd[i * (nblk + 1) + 1 + a] = {c ? 2 * nr : nr, nr, c ? 2 * ldr : ldr, c ? nr : 0, ldr,
+                                            int32_t(p0 + i), i * per_patch + blk_woff[a], oo};
+              oo += int64_t(nr) * (c ? 2 * ldr : ldr);
+            }
+          }
+          descs.push_back(std::move(dd));
+          nss.push_back(std::move(ns_of));
+          nus.push_back(std::move(nu_of));
+          ddesc.emplace_back();
+          ddesc.back().upload(descs.back(), h->st, nullptr);
+          dns.emplace_back();
+          dns.back().upload(nss.back(), h->st, nullptr);
+          dnu.emplace_back();
+          dnu.back().upload(nus.back(), h->st, nullptr);
+          stgmg::k_fill_zero(h->st, wmm.p, cnt * sq);
+          stgmg::k_fill_zero(h->st, wkk.p, cnt * sq);
+          stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
+                                           D.MMs.val.p, D.KKs.ptr.p, D.KKs.col.p, D.KKs.val.p, wmm.p, wkk.p);
+          if (p.smoother_prec == STGMG_FP32) {
+            stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, max_ns, max_nr, dns.back().p, dnu.back().p, wmm.p,
+                                             wkk.p, ddesc.back().p, Wb.p, D.inv32.p);
+            stgmg::k_gj_invert_f32(h->st, nb, cnt * (nblk + 1), max_n, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
+            stgmg::k_fold_reduced_f32(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, ddesc.back().p,
+                                      nblk + 1, D.inv32.p);
+          } else {
+            stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, max_ns, max_nr, dns.back().p, dnu.back().p, wmm.p,
+                                             wkk.p, ddesc.back().p, Wb.p, D.inv64.p);
+            stgmg::k_gj_invert_f64(h->st, nb, cnt * (nblk + 1), max_n, ddesc.back().p, Wb.p, D.inv64.p, stat.p);
+            stgmg::k_fold_reduced_f64(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, ddesc.back().p,
+                                      nblk + 1, D.inv64.p);
+          }
           HIPCHK(hipGetLastError());
         }
         HIPCHK(hipStreamSynchronize(h->st));
@@ -997,27 +1111,76 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
       for (int a = 0; a < n; ++a)
         for (int b = 0; b < n; ++b) out_host[size_t(a) * n + b] = st[size_t(b) * ld + a];
     } else {
-      // A_P^{-1}[(b,i)][(c,j)] = sum_a Q[b][a] X_a[i][j] Tin[a][c] (pairs: twice the real part)
+      // spatial block inverses X_a = (lam_a MM_P + KK_P)^{-1} (complex, ns x ns, row-major)
       const auto& tb = h->tbc;
       const int nt = tb.nt, ns = n / nt, ldh = stgmg::inv_ld(ns);
+      std::vector<std::vector<std::complex<double>>> X(tb.nblk);
+      if (!h->red) {
+        int64_t off = 0;
+        for (int a = 0; a < tb.nblk; ++a) {
+          const bool c = tb.cplx[a] != 0;
+          const int64_t ldc = c ? 2 * ldh : ldh;
+          X[a].resize(size_t(ns) * ns);
+          for (int i = 0; i < ns; ++i)
+            for (int j = 0; j < ns; ++j)
+              X[a][size_t(i) * ns + j] = {st[off + size_t(j) * ldc + i], c ? st[off + size_t(j) * ldc + ldh + i] : 0.0};
+          off += int64_t(ns) * ldc;
+        }
+      } else {
+        // column j of X_a: the reduced solve of the unit vector e_j
+        const int d = h->prm.dim, nU = D.pnu_h[patch], nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
+        const int ldn = stgmg::inv_ld(nn), ldp = stgmg::inv_ld(nP), ldr = stgmg::inv_ld(nr);
+        const double* Minv = st.data();
+        const double* G = Minv + size_t(nn) * ldn;  // KK_pV ((rho M)^{-1} (x) I), column-major
+        int64_t off = int64_t(nn) * ldn + int64_t(nU) * ldp;
+        for (int a = 0; a < tb.nblk; ++a) {
+          const bool c = tb.cplx[a] != 0;
+          const int64_t ldc = c ? 2 * ldr : ldr;
+          const std::complex<double> lam(tb.lam[2 * a], tb.lam[2 * a + 1]);
+          X[a].assign(size_t(ns) * ns, 0.0);
+          std::vector<std::complex<double>> w(nU), z(nr), t(nr);
+          for (int j = 0; j < ns; ++j) {
+            std::vector<double> e(ns, 0.0);
+            e[j] = 1.0;
+            for (int i = 0; i < nU; ++i) {
+              double acc = 0.0;
+              for (int b = 0; b < nn; ++b) acc += Minv[size_t(b) * ldn + i / d] * e[b * d + i % d];
+              w[i] = acc;
+              z[i] = e[nU + i] + lam * e[i];
+            }
+            for (int x = 0; x < nP; ++x) {
+              double acc = e[2 * nU + x];
+              for (int q = 0; q < nU; ++q) acc += G[size_t(q) * ldp + x] * e[q];
+              z[nU + x] = acc;
+            }
+            for (int i = 0; i < nr; ++i) {
+              std::complex<double> acc = 0.0;
+              for (int q = 0; q < nr; ++q)
+                acc += std::complex<double>(st[off + size_t(q) * ldc + i], c ? st[off + size_t(q) * ldc + ldr + i] : 0.0) *
+                       z[q];
+              t[i] = acc;
+            }
+            for (int i = 0; i < ns; ++i)
+              X[a][size_t(i) * ns + j] = i < nU ? lam * t[i] - w[i] : t[i - nU];
+          }
+          off += int64_t(nr) * ldc;
+        }
+      }
+      // A_P^{-1}[(b,i)][(c,j)] = sum_a Q[b][a] X_a[i][j] Tin[a][c] (pairs: twice the real part)
       std::fill(out_host, out_host + size_t(n) * n, 0.0);
-      int64_t off = 0;
       for (int a = 0; a < tb.nblk; ++a) {
         const bool c = tb.cplx[a] != 0;
-        const int64_t ldc = c ? 2 * ldh : ldh;
         for (int b = 0; b < nt; ++b)
           for (int cc = 0; cc < nt; ++cc) {
             const std::complex<double> q(tb.qout[2 * (b * tb.nblk + a)], tb.qout[2 * (b * tb.nblk + a) + 1]);
-            const std::complex<double> t(tb.tin[2 * (a * nt + cc)], tb.tin[2 * (a * nt + cc) + 1]);
-            const std::complex<double> qt = q * t;
+            const std::complex<double> tt(tb.tin[2 * (a * nt + cc)], tb.tin[2 * (a * nt + cc) + 1]);
+            const std::complex<double> qt = q * tt;
             for (int i = 0; i < ns; ++i)
               for (int j = 0; j < ns; ++j) {
-                const std::complex<double> x(st[off + size_t(j) * ldc + i], c ? st[off + size_t(j) * ldc + ldh + i] : 0.0);
-                const std::complex<double> v = qt * x;
+                const std::complex<double> v = qt * X[a][size_t(i) * ns + j];
                 out_host[size_t(b * ns + i) * n + cc * ns + j] += c ? 2.0 * v.real() : v.real();
               }
           }
-        off += int64_t(ns) * ldc;
       }
     }
     if (dofs_host)
@@ -1059,6 +1222,15 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
               std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / (stride * 8)));
           temp_peak = std::max(temp_peak, batch * stride * 8 + batch * 8 + int64_t(sizeof(stgmg::GjDesc)) * batch +
                                               S.npatch * 4);
+        } else if (p.time_blocks == 2) {
+          res += (S.sum_red_fixed + (nreal + 2 * ncplx) * S.sum_nr_ldr) * w + S.npatch * 4;
+          const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
+          const int64_t per_patch = int64_t(S.max_nn) * S.max_nn + (nreal + 4 * ncplx) * int64_t(S.max_nr) * S.max_nr;
+          const int64_t batch =
+              std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
+          temp_peak = std::max(temp_peak, batch * (per_patch + 2 * sq) * 8 +
+                                              int64_t(sizeof(stgmg::GjDesc)) * batch * (nreal + ncplx + 1) +
+                                              2 * batch * 4 + S.npatch * 4);
         } else {
           res += (nreal + 2 * ncplx) * S.sum_ns_ldh * w;
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;

@@ -119,7 +119,8 @@ int stgmg_host_time_blocks(int k, double tau, double* lam, int* cplx, double* ti
 }
 
 // KK CSR of the last built level (which = 3 in stgmg_host_csr)
-// Closed-form sizes: out = {n, nnzA, nnzMM, nnzP, npatch, sum_np, sum_np_ld, max_np}
+// Closed-form sizes: out = {n, nnzA, nnzMM, nnzP, npatch, sum_np, sum_np_ld, max_np, nnzKK,
+//                          sum_red_fixed, sum_nr_ldr, max_nr, max_nn}
 void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out) {
   stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind);
   out[0] = S.n;
@@ -131,6 +132,10 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[6] = S.sum_np_ld;
   out[7] = S.max_np;
   out[8] = S.nnzKK;
+  out[9] = S.sum_red_fixed;
+  out[10] = S.sum_nr_ldr;
+  out[11] = S.max_nr;
+  out[12] = S.max_nn;
 }
 
 }  // extern "C"

@@ -1051,6 +1051,14 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
     S.sum_np += mult * np;
     S.sum_np_ld += mult * np * ((np + 3) & ~int64_t(3));
     S.max_np = std::max<int>(S.max_np, int(np));
+    const int64_t nU = d * q, nr = nU + pp;
+    auto ld4 = [](int64_t v) { return (v + 3) & ~int64_t(3); };
+    S.sum_red_fixed += mult * (q * ld4(q) + nU * ld4(pp));
+    S.sum_nr_ldr += mult * nr * ld4(nr);
+    S.alg_red_fixed += mult * (q * q + pp * nU);
+    S.sum_nr2 += mult * nr * nr;
+    S.max_nr = std::max<int>(S.max_nr, int(nr));
+    S.max_nn = std::max<int>(S.max_nn, int(q));
   }
   return S;
 }

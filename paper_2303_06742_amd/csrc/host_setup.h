@@ -99,6 +99,12 @@ struct LevelSizes {
   int64_t sum_ns_ldh = 0;  // sum over patches of ns * inv_ld(ns), ns = n_P / (k+1)
   int64_t nnzKK = 0;       // spatial KK
   int max_np = 0;
+  // reduced time-block solves (per patch: nn nodes, nU = d nn, nP pressure dofs, nr = nU + nP)
+  int64_t sum_red_fixed = 0;  // sum of nn * inv_ld(nn) + nU * inv_ld(nP)
+  int64_t sum_nr_ldr = 0;     // sum of nr * inv_ld(nr)
+  int64_t alg_red_fixed = 0;  // sum of nn^2 + nP nU
+  int64_t sum_nr2 = 0;        // sum of nr^2
+  int max_nr = 0, max_nn = 0;
 };
 LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind);
 

@@ -62,6 +62,30 @@ void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const Time
                           const int32_t* pdof, const int64_t* ioff, const double* inv, const double* r, double* y);
 void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
                           const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y);
+// Reduced time-block patch solves (u-equation rows eliminated): per batch item, the node
+// mass block, the Schur complement S(lam_a) of every kept eigenvalue (transposed, real form if
+// complex) into the Gauss-Jordan work area via desc (nblk + 1 per patch: mass, blocks), and the
+// (p-equation, V) block of KK_P straight into the stored layout (out, after the mass inverse).
+// nu_of: velocity dofs nU per patch (per time node).
+void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+                               int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
+                               const double* wkk, const GjDesc* desc, double* W, double* out);
+void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+                               int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
+                               const double* wkk, const GjDesc* desc, double* W, float* out);
+// after the inversion: G = KK_pV ((rho M)^{-1} (x) I_d) replaces KK_pV in the stored layout;
+// desc[i * dstride] is the mass descriptor of batch item i, max_npr the largest nP.
+void k_fold_reduced_f64(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
+                        const int32_t* nu_of, const GjDesc* desc, int dstride, double* out);
+void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
+                        const int32_t* nu_of, const GjDesc* desc, int dstride, float* out);
+int patch_apply_red_threads(int max_nr, bool fp32);
+void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y);
+void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y);
 // Block size used by the patch GEMV for patches of at most max_np rows.
 int patch_apply_threads(int max_np, bool fp32);
 void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,

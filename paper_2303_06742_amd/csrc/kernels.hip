@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(256) patch_extract_spatial_t_kernel(
 __global__ void form_time_blocks_kernel(TimeBlockConsts tb, int max_ns, const int32_t* __restrict__ ns_of,
                                         const double* __restrict__ wmm, const double* __restrict__ wkk,
                                         const GjDesc* __restrict__ desc, double* __restrict__ W) {
-  const int64_t m = blockIdx.y;
+  const int64_t m = blockIdx.x;
   const int64_t i = m / tb.nblk;
   const int a = int(m % tb.nblk);
   const int ns = ns_of[i];
@@ -223,19 +223,84 @@ __global__ void form_time_blocks_kernel(TimeBlockConsts tb, int max_ns, const in
   double* Wd = W + desc[m].woff;
   const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
   if (!tb.cplx[a]) {
-    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < int64_t(ns) * ns;
-         q += int64_t(gridDim.x) * blockDim.x)
+    for (int64_t q = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; q < int64_t(ns) * ns;
+         q += int64_t(gridDim.y) * blockDim.x)
       Wd[q] = al * Mt[q] + Kt[q];
   } else {
     const int n2 = 2 * ns;
-    for (int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; q < int64_t(ns) * ns;
-         q += int64_t(gridDim.x) * blockDim.x) {
+    for (int64_t q = int64_t(blockIdx.y) * blockDim.x + threadIdx.x; q < int64_t(ns) * ns;
+         q += int64_t(gridDim.y) * blockDim.x) {
       const int mu = int(q / ns), nu = int(q % ns);
       const double d = al * Mt[q] + Kt[q], b = be * Mt[q];
       Wd[int64_t(mu) * n2 + nu] = d;
       Wd[int64_t(mu) * n2 + ns + nu] = b;
       Wd[int64_t(ns + mu) * n2 + nu] = -b;
       Wd[int64_t(ns + mu) * n2 + ns + nu] = d;
+    }
+  }
+}
+
+// Reduced time-block solves: the u-equation rows of every block lam MM_P + KK_P are
+// eliminated.  Patch-local order per time node: V [0, nU), U [nU, 2nU), P [2nU, ns) for the
+// columns and the u-, v-, p-equation rows alike; nU = d nn (nn patch nodes, components
+// interleaved), nP = ns - 2 nU.  Index x of the reduced system (rows: v-, p-equation;
+// columns: U, P) is patch index nU + x.  With B = lam MM_P + KK_P, B_uV = -rho M,
+// B_uU = lam rho M and the other u-row blocks zero, the Schur complement is
+//   S(lam)[x][y] = lam^2 A2 + lam A1 + A0,  A2 = [y < nU] MM[nU+x][y],
+//   A1 = MM[nU+x][nU+y] + [y < nU] KK[nU+x][y],  A0 = KK[nU+x][nU+y].
+// Work items m = (patch i, slot s) of the batch on blockIdx.x, nslot = nblk + 2:
+//   s = 0: the transposed node mass block rho M (component 0 of the u-rows and U columns);
+//   s = 1 + a: the transposed S(lam_a), in the real form [[Re, -Im], [Im, Re]] if complex;
+//   s = 1 + nblk: KK[2nU + x][y] (x < nP, y < nU) written to out column-major with leading
+//            dimension inv_ld(nP) (zero padding rows), right after the stored mass inverse.
+// desc holds nblk + 1 Gauss-Jordan descriptors per patch (mass, then the blocks); wmm, wkk
+// are the transposed dense spatial blocks of the patch (stride max_ns^2).
+template <typename T>
+__global__ void form_reduced_blocks_kernel(TimeBlockConsts tb, int d, int max_ns, const int32_t* __restrict__ ns_of,
+                                           const int32_t* __restrict__ nu_of, const double* __restrict__ wmm,
+                                           const double* __restrict__ wkk, const GjDesc* __restrict__ desc,
+                                           double* __restrict__ W, T* __restrict__ out) {
+  const int nslot = tb.nblk + 2;
+  const int64_t m = blockIdx.x;
+  const int64_t i = m / nslot;
+  const int s = int(m % nslot);
+  const int ns = ns_of[i], nU = nu_of[i], nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
+  const double* Mt = wmm + i * max_ns * max_ns;  // Mt[c * ns + r] = MM[r][c]
+  const double* Kt = wkk + i * max_ns * max_ns;
+  const GjDesc* dp = desc + i * (tb.nblk + 1);
+  const int64_t t0 = int64_t(blockIdx.y) * blockDim.x + threadIdx.x, step = int64_t(gridDim.y) * blockDim.x;
+  if (s == 0) {
+    double* Wd = W + dp[0].woff;
+    for (int64_t q = t0; q < int64_t(nn) * nn; q += step) {
+      const int b = int(q / nn), a = int(q % nn);
+      Wd[q] = Mt[int64_t(nU + b * d) * ns + a * d];
+    }
+  } else if (s <= tb.nblk) {
+    const int a = s - 1;
+    const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+    double* Wd = W + dp[s].woff;
+    for (int64_t q = t0; q < int64_t(nr) * nr; q += step) {
+      const int y = int(q / nr), x = int(q % nr);
+      const double A2 = y < nU ? Mt[int64_t(y) * ns + nU + x] : 0.0;
+      const double A1 = Mt[int64_t(nU + y) * ns + nU + x] + (y < nU ? Kt[int64_t(y) * ns + nU + x] : 0.0);
+      const double A0 = Kt[int64_t(nU + y) * ns + nU + x];
+      if (!tb.cplx[a]) {
+        Wd[q] = (al * al) * A2 + al * A1 + A0;
+      } else {
+        const int n2 = 2 * nr;
+        const double sr = (al * al - be * be) * A2 + al * A1 + A0, si = (2.0 * al * be) * A2 + be * A1;
+        Wd[int64_t(y) * n2 + x] = sr;
+        Wd[int64_t(y) * n2 + nr + x] = si;
+        Wd[int64_t(nr + y) * n2 + x] = -si;
+        Wd[int64_t(nr + y) * n2 + nr + x] = sr;
+      }
+    }
+  } else {
+    const int ldp = inv_ld(nP);
+    T* o = out + dp[0].ooff + int64_t(nn) * inv_ld(nn);
+    for (int64_t q = t0; q < int64_t(nU) * ldp; q += step) {
+      const int y = int(q / ldp), x = int(q % ldp);
+      o[q] = x < nP ? T(Kt[int64_t(y) * ns + 2 * nU + x]) : T(0);
     }
   }
 }
@@ -590,6 +655,307 @@ __global__ void __launch_bounds__(512) patch_apply_tb_kernel(TimeBlockConsts tb,
       }
       y[o + b * ns + i] = acc;
     }
+}
+
+// Reduced time-block patch solve.  Per kept eigenvalue lam of (M^t)^{-1} D^t and the
+// transformed right-hand side (r_u, r_v, r_p) of the patch:
+//   w = (rho M)^{-1} r_u,  [U; P] = S(lam)^{-1} [r_v + lam r_u; r_p + G r_u],  V = lam U - w,
+// with G = KK_pV (rho M)^{-1}: the exact solution of (lam MM_P + KK_P) [V; U; P] = [r_u; r_v; r_p]
+// (S as in form_reduced_blocks_kernel).  Stored per patch at ioff[p]: (rho M)^{-1} (nn columns,
+// stride inv_ld(nn), applied per velocity component), G (nU columns, stride inv_ld(nP)), then
+// one S^{-1} per kept eigenvalue (nr = nU + nP columns: stride inv_ld(nr) if real, 2 inv_ld(nr)
+// with Re in rows [0, nr) and Im in rows [inv_ld(nr), inv_ld(nr) + nr) if complex).  All sums
+// are in FP64 whatever the storage type T.  At most RED_MAXB kept eigenvalues (k <= 3).
+//
+// One block per patch.  The stored values are read with buffer loads: the patch's region is
+// the buffer (range-checked), the lane's rows a 32-bit vector offset and the column a scalar
+// offset, so that no 64-bit address is held per load (the start of a lane's column range is
+// part of its vector offset: the scalar offset has to be the same on all lanes of a wave, and
+// a wave can hold two ranges).  The S^{-1} stream runs in batches of 8 columns per lane (16
+// loads for a complex block; the compiler pipelines two batches of a real block).
+// Thread layout of the S^{-1} product: W column ranges of blockDim / W threads, R consecutive
+// rows per thread (one 16-byte load per column).
+constexpr int RED_MAXB = 2;
+
+
+template <typename T, bool NTL>
+__device__ inline T bld1(__amdgpu_buffer_rsrc_t rs, int voff) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, NTL ? 2 : 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, 0, NTL ? 2 : 0));
+}
+
+template <typename V, bool NTL>
+__device__ inline V bld16(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
+  static_assert(sizeof(V) == 16, "16-byte loads");
+  return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, NTL ? 2 : 0));
+}
+
+template <typename T>
+__device__ inline __amdgpu_buffer_rsrc_t patch_rsrc(const T* p, int64_t count) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, int(count * int64_t(sizeof(T))), 0x00020000);
+}
+
+template <typename T, int R, bool NTL>
+__global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb, int d, int W,
+                                                              const int64_t* __restrict__ poff,
+                                                              const int32_t* __restrict__ pdof,
+                                                              const int32_t* __restrict__ pnu,
+                                                              const int64_t* __restrict__ ioff,
+                                                              const T* __restrict__ inv, const double* __restrict__ r,
+                                                              double* __restrict__ y) {
+  typedef T V __attribute__((ext_vector_type(R)));
+  extern __shared__ double sm[];
+  const int64_t p = blockIdx.x;
+  const int64_t o = poff[p];
+  const int n = int(poff[p + 1] - o);
+  const int nt = tb.nt, nblk = tb.nblk;
+  const int ns = n / nt, nU = pnu[p], nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
+  const int ldn = inv_ld(nn), ldp = inv_ld(nP), ldr = inv_ld(nr);
+  // region A: r_P, later w [a][re, im][nU] and z [a][re, im][ldr];
+  // region B: transformed right-hand sides [a][re, im][ns], later W partial images [w][a][re, im][ldr]
+  const int szA = max(n, 2 * nblk * (nU + ldr));
+  double* rl = sm;
+  double* wv = sm;
+  double* z = sm + 2 * nblk * nU;
+  double* sv = sm + szA;
+  double* tv = sm + szA;
+  const int64_t base = ioff[p];
+  const int64_t nsmall = int64_t(nn) * ldn + int64_t(nU) * ldp;  // (rho M)^{-1} and G
+  // gather r_P: batches of independent index and value loads
+  for (int ib = threadIdx.x; ib < n; ib += 8 * blockDim.x) {
+    int32_t g[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = ib + u * blockDim.x;
+      g[u] = i < n ? pdof[o + i] : 0;
+    }
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ib + u * blockDim.x < n ? r[g[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (ib + u * blockDim.x < n) rl[ib + u * blockDim.x] = v[u];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += blockDim.x)
+    for (int a = 0; a < nblk; ++a) {
+      double sr = 0.0, si = 0.0;
+      for (int b = 0; b < nt; ++b) {
+        const double x = rl[b * ns + i];
+        sr += tb.tin[2 * (a * nt + b)] * x;
+        si += tb.tin[2 * (a * nt + b) + 1] * x;
+      }
+      sv[(2 * a) * ns + i] = sr;
+      sv[(2 * a + 1) * ns + i] = si;
+    }
+  __syncthreads();
+  // items [0, nU): w = (rho M)^{-1} r_u per component and z_U = r_v + lam r_u;
+  // items [nU, nr): z_P = r_p + G r_u
+  {
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + base, nsmall);
+    for (int it = threadIdx.x; it < nr; it += blockDim.x) {
+      double ar[RED_MAXB] = {0, 0}, ai[RED_MAXB] = {0, 0};
+      const bool vel = it < nU;
+      // element j of the row: byte offset e0 + j * es (column-major: adjacent lanes read
+      // adjacent entries)
+      const int e0 = int(sizeof(T)) * (vel ? it / d : nn * ldn + (it - nU));
+      const int es = int(sizeof(T)) * (vel ? ldn : ldp);
+      const int m = vel ? nn : nU;
+      const int sstep = vel ? d : 1, s0 = vel ? it % d : 0;  // r_u entries: j * d + c (mass) or j (G)
+      int j = 0;
+      for (; j + 7 < m; j += 8) {
+        T mv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) mv[u] = bld1<T, NTL>(rs, e0 + (j + u) * es);
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int a = 0; a < RED_MAXB; ++a)
+            if (a < nblk) {
+              ar[a] += double(mv[u]) * sv[(2 * a) * ns + (j + u) * sstep + s0];
+              ai[a] += double(mv[u]) * sv[(2 * a + 1) * ns + (j + u) * sstep + s0];
+            }
+      }
+      for (; j < m; ++j) {
+        const double mv = double(bld1<T, NTL>(rs, e0 + j * es));
+#pragma unroll
+        for (int a = 0; a < RED_MAXB; ++a)
+          if (a < nblk) {
+            ar[a] += mv * sv[(2 * a) * ns + j * sstep + s0];
+            ai[a] += mv * sv[(2 * a + 1) * ns + j * sstep + s0];
+          }
+      }
+#pragma unroll
+      for (int a = 0; a < RED_MAXB; ++a)
+        if (a < nblk) {
+          if (vel) {
+            const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+            const double ur = sv[(2 * a) * ns + it], ui = sv[(2 * a + 1) * ns + it];
+            wv[(2 * a) * nU + it] = ar[a];
+            wv[(2 * a + 1) * nU + it] = ai[a];
+            z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + al * ur - be * ui;
+            z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + al * ui + be * ur;
+          } else {
+            z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + ar[a];
+            z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + ai[a];
+          }
+        }
+    }
+  }
+  __syncthreads();
+  // [U; P] = S^{-1} z per kept eigenvalue
+  {
+    const int per_w = blockDim.x / W;
+    const int w = threadIdx.x / per_w, tl = threadIdx.x % per_w;
+    const int i0 = R * tl;
+    const int jc = (nr + W - 1) / W, j0 = w * jc, j1 = min(nr, j0 + jc);
+    const int voff = i0 * int(sizeof(T));
+    int64_t off = base + nsmall;
+    for (int a = 0; a < nblk; ++a) {
+      const double* zr = z + (2 * a) * ldr;
+      const double* zi = z + (2 * a + 1) * ldr;
+      double* twr = tv + (int64_t(w) * nblk + a) * 2 * ldr;
+      double* twi = twr + ldr;
+      const bool cp = tb.cplx[a] != 0;
+      const int64_t cnt = int64_t(nr) * (cp ? 2 * ldr : ldr);
+      if (w < W && i0 < ldr) {
+        const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
+        double accr[R], acci[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) accr[q] = acci[q] = 0.0;
+        if (!cp) {
+          const int cb = ldr * int(sizeof(T));  // bytes per column
+          const int vo = voff + j0 * cb;
+          V A[8];
+          auto load = [&](V* buf, int jr) {  // columns j0 + jr + u
+#pragma unroll
+            for (int u = 0; u < 8; ++u) buf[u] = bld16<V, NTL>(rs, vo, (jr + u) * cb);
+          };
+          auto sum = [&](const V* buf, int jj) {
+#pragma unroll
+            for (int u = 0; u < 8; u += 2)
+#pragma unroll
+              for (int q = 0; q < R; ++q) {
+                accr[q] += double(buf[u][q]) * zr[jj + u];
+                acci[q] += double(buf[u + 1][q]) * zr[jj + u + 1];
+              }
+          };
+          const int nb = (j1 - j0) / 8;
+          for (int b = 0; b < nb; ++b) {
+            load(A, 8 * b);
+            sum(A, j0 + 8 * b);
+          }
+          const int jt = j0 + 8 * nb, vt = voff + jt * cb;
+          for (int t = 0; t < j1 - jt; ++t) {
+            const V v0 = bld16<V, NTL>(rs, vt, t * cb);
+#pragma unroll
+            for (int q = 0; q < R; ++q) accr[q] += double(v0[q]) * zr[jt + t];
+          }
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            twr[i0 + q] = accr[q] + acci[q];
+            twi[i0 + q] = 0.0;
+          }
+        } else {
+          const int cb = 2 * ldr * int(sizeof(T)), ib = ldr * int(sizeof(T));  // column, Im offset
+          const int vo = voff + j0 * cb;
+          V Ar[8], Ai[8];
+          const int nb = (j1 - j0) / 8;
+          for (int b = 0; b < nb; ++b) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              Ar[u] = bld16<V, NTL>(rs, vo, (8 * b + u) * cb);
+              Ai[u] = bld16<V, NTL>(rs, vo + ib, (8 * b + u) * cb);
+            }
+            const int jj = j0 + 8 * b;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+              for (int q = 0; q < R; ++q) {
+                accr[q] += double(Ar[u][q]) * zr[jj + u] - double(Ai[u][q]) * zi[jj + u];
+                acci[q] += double(Ai[u][q]) * zr[jj + u] + double(Ar[u][q]) * zi[jj + u];
+              }
+          }
+          const int jt = j0 + 8 * nb, vt = voff + jt * cb;
+          for (int t = 0; t < j1 - jt; ++t) {
+            const V a0 = bld16<V, NTL>(rs, vt, t * cb), b0 = bld16<V, NTL>(rs, vt + ib, t * cb);
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              accr[q] += double(a0[q]) * zr[jt + t] - double(b0[q]) * zi[jt + t];
+              acci[q] += double(b0[q]) * zr[jt + t] + double(a0[q]) * zi[jt + t];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < R; ++q) {
+            twr[i0 + q] = accr[q];
+            twi[i0 + q] = acci[q];
+          }
+        }
+      }
+      off += cnt;
+    }
+  }
+  __syncthreads();
+  // spatial images [lam U - w; U; P], transformed back to the time nodes
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+    const int ii = i < nU ? i : i - nU;
+    double hr[RED_MAXB], hi[RED_MAXB];
+#pragma unroll
+    for (int a = 0; a < RED_MAXB; ++a)
+      if (a < nblk) {
+        double t_r = 0.0, t_i = 0.0;
+        for (int ww = 0; ww < W; ++ww) {
+          t_r += tv[(int64_t(ww) * nblk + a) * 2 * ldr + ii];
+          t_i += tv[(int64_t(ww) * nblk + a) * 2 * ldr + ldr + ii];
+        }
+        if (i < nU) {
+          const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+          hr[a] = al * t_r - be * t_i - wv[(2 * a) * nU + i];
+          hi[a] = al * t_i + be * t_r - wv[(2 * a + 1) * nU + i];
+        } else {
+          hr[a] = t_r;
+          hi[a] = t_i;
+        }
+      }
+    for (int b = 0; b < nt; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < RED_MAXB; ++a)
+        if (a < nblk) {
+          const double qr = tb.qout[2 * (b * nblk + a)], qi = tb.qout[2 * (b * nblk + a) + 1];
+          acc += tb.cplx[a] ? 2.0 * (qr * hr[a] - qi * hi[a]) : qr * hr[a];
+        }
+      y[o + b * ns + i] = acc;
+    }
+  }
+}
+
+// G = KK_pV ((rho M)^{-1} (x) I_d) in place of KK_pV in the stored layout of the reduced
+// solves (column-major, leading dimension inv_ld(nP)), one block per patch of the batch:
+// G[x][m d + c] = sum_b KK_pV[x][b d + c] Minv[b][m].
+template <typename T>
+__global__ void __launch_bounds__(256) fold_reduced_kernel(int d, const int32_t* __restrict__ ns_of,
+                                                           const int32_t* __restrict__ nu_of,
+                                                           const GjDesc* __restrict__ desc, int dstride,
+                                                           T* __restrict__ out) {
+  extern __shared__ double kl[];  // KK_pV, nU x ldp (column-major, as stored)
+  const int64_t i = blockIdx.x;
+  const int ns = ns_of[i], nU = nu_of[i], nP = ns - 2 * nU, nn = nU / d;
+  const int ldn = inv_ld(nn), ldp = inv_ld(nP);
+  const T* Minv = out + desc[i * dstride].ooff;
+  T* Gp = out + desc[i * dstride].ooff + int64_t(nn) * ldn;
+  for (int q = threadIdx.x; q < nU * ldp; q += blockDim.x) kl[q] = double(Gp[q]);
+  __syncthreads();
+  for (int q = threadIdx.x; q < nU * ldp; q += blockDim.x) {
+    const int col = q / ldp, x = q % ldp;  // G[x][col], col = m d + c
+    if (x >= nP) continue;                 // padding rows stay zero
+    const int m = col / d, c = col % d;
+    double acc = 0.0;
+    for (int b = 0; b < nn; ++b) acc += kl[(b * d + c) * ldp + x] * double(Minv[int64_t(m) * ldn + b]);
+    Gp[q] = T(acc);
+  }
 }
 
 // d[mu] += winv[mu] * sum of the patch images of mu, in patch order
@@ -1093,7 +1459,7 @@ void k_form_time_blocks(hipStream_t st, int64_t count, const TimeBlockConsts& tb
                         const double* wmm, const double* wkk, const GjDesc* desc, double* W) {
   if (count == 0) return;
   const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (int64_t(max_ns) * max_ns + 255) / 256));
-  hipLaunchKernelGGL(dev::form_time_blocks_kernel, dim3(gx, count * tb.nblk), dim3(256), 0, st, tb, max_ns, ns_of,
+  hipLaunchKernelGGL(dev::form_time_blocks_kernel, dim3(count * tb.nblk, gx), dim3(256), 0, st, tb, max_ns, ns_of,
                      wmm, wkk, desc, W);
 }
 
@@ -1144,6 +1510,102 @@ void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const Time
 void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
                           const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y) {
   launch_tb<float>(st, npatch, max_np, tb, poff, pdof, ioff, inv, r, y);
+}
+
+// Reduced time-block solves: LDS regions A = max(n_P, 2 nblk (nU + ldr)) and
+// B = max(2 nblk ns, W 2 nblk ldr) doubles (bounds from the maxima over the patches).
+static size_t red_lds(int max_np, int max_nu, int max_nr, int nt, int nblk, int W) {
+  const size_t ldr = inv_ld(max_nr), ns = max_np / nt;
+  const size_t a = std::max<size_t>(max_np, 2 * size_t(nblk) * (max_nu + ldr));
+  const size_t b = std::max<size_t>(2 * size_t(nblk) * ns, size_t(W) * 2 * nblk * ldr);
+  return (a + b) * sizeof(double);
+}
+
+// Rows per thread R (one 16-byte load per column for FP64 R = 2 / FP32 R = 4), threads per
+// column range = ceil(inv_ld(max_nr) / R), blocks of whole waves holding W >= 1 such ranges.
+static void red_layout(int max_nr, int R, int* th, int* W) {
+  const int per_w = (inv_ld(max_nr) + R - 1) / R;
+  *th = std::max(64, (per_w + 63) / 64 * 64);
+  if (const char* e = std::getenv("STGMG_RED_WAVES")) {  // tuning: waves per block
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= 8 && 64 * v >= *th) *th = 64 * v;
+  }
+  *W = std::max(1, *th / per_w);
+  if (const char* e = std::getenv("STGMG_RED_RANGES")) {  // tuning: column ranges per block
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= *W) *W = v;
+  }
+}
+
+int patch_apply_red_threads(int max_nr, bool fp32) {
+  int th, W;
+  red_layout(max_nr, fp32 ? 4 : 2, &th, &W);
+  return th;
+}
+
+// tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads)
+template <typename T>
+static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+                       const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                       const int32_t* pnu, const int64_t* ioff, const T* inv, const double* r, double* y) {
+  if (npatch == 0) return;
+  constexpr int R = sizeof(T) == 4 ? 4 : 2;
+  int th, W;
+  red_layout(max_nr, R, &th, &W);
+  bool ntl = true;
+  if (const char* e = std::getenv("STGMG_RED_NT")) ntl = std::atoi(e) != 0;
+  const size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
+  if (ntl)
+    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, true>), dim3(npatch), dim3(th), lds, st, tb, d, W, poff,
+                       pdof, pnu, ioff, inv, r, y);
+  else
+    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, false>), dim3(npatch), dim3(th), lds, st, tb, d, W, poff,
+                       pdof, pnu, ioff, inv, r, y);
+}
+
+void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y) {
+  launch_red<double>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, pnu, ioff, inv, r, y);
+}
+void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y) {
+  launch_red<float>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, pnu, ioff, inv, r, y);
+}
+
+template <typename T>
+static void launch_fold(hipStream_t st, int64_t count, int d, int max_nu, int max_np_sp, const int32_t* ns_of,
+                        const int32_t* nu_of, const GjDesc* desc, int dstride, T* out) {
+  if (count == 0) return;
+  const size_t lds = size_t(max_nu) * inv_ld(max_np_sp) * sizeof(double);
+  hipLaunchKernelGGL(dev::fold_reduced_kernel<T>, dim3(count), dim3(256), lds, st, d, ns_of, nu_of, desc, dstride,
+                     out);
+}
+void k_fold_reduced_f64(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
+                        const int32_t* nu_of, const GjDesc* desc, int dstride, double* out) {
+  launch_fold<double>(st, count, d, max_nu, max_npr, ns_of, nu_of, desc, dstride, out);
+}
+void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
+                        const int32_t* nu_of, const GjDesc* desc, int dstride, float* out) {
+  launch_fold<float>(st, count, d, max_nu, max_npr, ns_of, nu_of, desc, dstride, out);
+}
+
+void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+                               int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
+                               const double* wkk, const GjDesc* desc, double* W, double* out) {
+  if (count == 0) return;
+  const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (4 * int64_t(max_nr) * max_nr + 255) / 256));
+  hipLaunchKernelGGL(dev::form_reduced_blocks_kernel<double>, dim3(count * (tb.nblk + 2), gx), dim3(256), 0, st, tb,
+                     d, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
+}
+void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+                               int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
+                               const double* wkk, const GjDesc* desc, double* W, float* out) {
+  if (count == 0) return;
+  const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (4 * int64_t(max_nr) * max_nr + 255) / 256));
+  hipLaunchKernelGGL(dev::form_reduced_blocks_kernel<float>, dim3(count * (tb.nblk + 2), gx), dim3(256), 0, st, tb, d,
+                     max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
 }
 
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,

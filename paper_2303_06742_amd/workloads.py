@@ -39,7 +39,8 @@ class Config:
     omega: float = 0.7
     restart: int = 30
     rtol: float = 1e-8
-    time_blocks: int = 1  # patch solves through the time eigen-decomposition (0: full inverses)
+    # patch solves: 2 time blocks with the u-equation rows eliminated, 1 time blocks, 0 full inverses
+    time_blocks: int = 2
     extra: dict = field(default_factory=dict)
 
     @property

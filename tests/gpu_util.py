@@ -24,7 +24,8 @@ def to_host(t):
 @functools.lru_cache(maxsize=8)
 def oracle_hierarchy(cfg_key):
     from oracle import gmg, problem
-    cfg_key = cfg_key.replace('_full', '')  # the patch-solver storage does not change the operator
+    # the storage of the patch solves does not change the operator
+    cfg_key = cfg_key.replace('_full', '').replace('_tb', '')
     cfg = CONFIGS[cfg_key]
     K = cfg.K_cells()
     prm = problem.Params(rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
@@ -42,8 +43,13 @@ CONFIGS = {
     'c3s': W.scaled(W.C3, 2, name='3d-8cube-dg1-cell-lognormal'),   # C3 physics, 8^3, 2 levels
     'k0': W.scaled(W.C1, 2, name='2d-8x8-dg0-vertex', k=0, patch='vertex'),
     'one_level': W.scaled(W.C1, 1, name='2d-4x4-dg1-direct'),
-    # the same operators with the full space-time patch inverses instead of the time blocks
+    # the same operators with the full space-time patch inverses
     'c1_full': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-full', time_blocks=0),
     'c2s_full': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-full', time_blocks=0),
     'c3s_full': W.scaled(W.C3, 2, name='3d-8cube-dg1-cell-lognormal-full', time_blocks=0),
+    # time-block solves without the elimination of the u-equation rows
+    'c1_tb': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-tb', time_blocks=1),
+    'c2s_tb': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-tb', time_blocks=1),
+    'c3s_tb': W.scaled(W.C3, 2, name='3d-8cube-dg1-cell-lognormal-tb', time_blocks=1),
+    'k0_tb': W.scaled(W.C1, 2, name='2d-8x8-dg0-vertex-tb', k=0, patch='vertex', time_blocks=1),
 }

@@ -26,7 +26,8 @@ def rel_err(a, b, scale=None):
     return np.abs(a - b).max() / s
 
 
-KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'c1_full', 'c2s_full', 'c3s_full']
+KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb', 'c3s_tb',
+        'k0_tb']
 
 
 @pytest.mark.parametrize("key", KEYS)
@@ -147,6 +148,20 @@ def test_fp32_smoother_meets_tolerances():
     S64 = solver('c2s')
     S32 = solver('c2s', 'fp32')
     F = workloads.random_vector(S64.n, 51)
+    x64, x32 = S64.empty(), S32.empty()
+    i64 = S64.solve(to_dev(F), x64, rtol=1e-10)
+    i32 = S32.solve(to_dev(F), x32, rtol=1e-10)
+    assert i32['converged'] and i32['rel_res_true'] <= 1e-10
+    assert rel_err(to_host(x32), to_host(x64)) < 1e-7
+    assert i32['iters'] <= i64['iters'] + 2
+
+
+@pytest.mark.parametrize("key", ['c2s_tb', 'c3s'])
+def test_fp32_storage_meets_tolerances(key):
+    """FP32 storage of the patch solves inside FP64 FGMRES (time blocks; reduced, FP64 sums)."""
+    S64 = solver(key)
+    S32 = solver(key, 'fp32')
+    F = workloads.random_vector(S64.n, 52)
     x64, x32 = S64.empty(), S32.empty()
     i64 = S64.solve(to_dev(F), x64, rtol=1e-10)
     i32 = S32.solve(to_dev(F), x32, rtol=1e-10)

@@ -1,0 +1,135 @@
+"""The reduced time-block patch solve, checked on the CPU with the host-assembled spatial
+MM and KK and the host patch tables.
+
+Each spatial block lam MM_P + KK_P has the u-equation rows [-rho M, lam rho M, 0] on the
+columns (V, U, P).  So V = lam U - (rho M)^{-1} r_u can be eliminated, and (U, P) solve a
+Schur complement S(lam) of n_P/(k+1) - nU rows.  These tests check two things.  First, the
+structural facts the elimination uses hold exactly in the assembled matrices.  Second, the
+reduced solve, with the index mapping and formulas of the device setup and apply kernels
+restated in numpy, reproduces the direct solve for real and complex lam."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from tests import hostlib
+
+LIB = hostlib.load()
+
+
+def build(d, N, k, kind, K=1.0):
+    Kc = np.full(N ** d, K)
+    n = LIB.stgmg_host_build(d, 2, k, N, 1 if kind == 'vertex' else 0, 0.01, 0.7, 1.3, 2.5, 0.8, 0.7, 0.02,
+                             hostlib.ptr(Kc))
+    assert n > 0
+    ns = n // (k + 1)
+    MM = hostlib.csr(LIB, 1, ns).toarray()
+    KK = hostlib.csr(LIB, 3, ns).toarray()
+    npatch = LIB.stgmg_host_npatch()
+    poff = np.zeros(npatch + 1, dtype=np.int64)
+    pdof = np.zeros(LIB.stgmg_host_patch_total(), dtype=np.int32)
+    LIB.stgmg_host_patches(hostlib.ptr(poff), hostlib.ptr(pdof), hostlib.ptr(np.zeros(n)))
+    nq = (2 * N + 1) ** d
+    return MM, KK, poff, pdof, d * nq, ns
+
+
+def patch_blocks(MM, KK, poff, pdof, nv, k, p):
+    ns = (poff[p + 1] - poff[p]) // (k + 1)
+    dofs = pdof[poff[p]:poff[p] + ns]  # time node 0: the spatial numbers
+    nU = int(np.sum(dofs < nv))
+    return MM[np.ix_(dofs, dofs)], KK[np.ix_(dofs, dofs)], nU
+
+
+def reduced_solve(MMp, KKp, nU, d, lam, rhs):
+    """(lam MM_P + KK_P)^{-1} rhs through the u-equation elimination, with the same
+    formulas and index mapping as the device form and apply kernels."""
+    ns = MMp.shape[0]
+    nP = ns - 2 * nU
+    nr = nU + nP
+    nn = nU // d
+    Mn = MMp[0:nU:d, nU:2 * nU:d]  # rho M on the nodes: component 0 of (u-rows, U columns)
+    Minv = np.linalg.inv(Mn)
+    S = np.zeros((nr, nr), dtype=complex)
+    for x in range(nr):
+        for y in range(nr):
+            A2 = MMp[nU + x, y] if y < nU else 0.0
+            A1 = MMp[nU + x, nU + y] + (KKp[nU + x, y] if y < nU else 0.0)
+            A0 = KKp[nU + x, nU + y]
+            S[x, y] = lam * lam * A2 + lam * A1 + A0
+    Kpv = KKp[2 * nU:, :nU]
+    G = np.zeros((nP, nU))  # KK_pV ((rho M)^{-1} (x) I_d), folded at setup
+    for x in range(nP):
+        for col in range(nU):
+            m, c = divmod(col, d)
+            G[x, col] = sum(Kpv[x, b * d + c] * Minv[b, m] for b in range(nn))
+    ru, rv, rp = rhs[:nU], rhs[nU:2 * nU], rhs[2 * nU:]
+    w = np.zeros(nU, dtype=complex)
+    for i in range(nU):
+        w[i] = sum(Minv[i // d, b] * ru[b * d + i % d] for b in range(nn))
+    z = np.concatenate([rv + lam * ru, rp + G @ ru])
+    t = np.linalg.solve(S, z)
+    return np.concatenate([lam * t[:nU] - w, t])
+
+
+@pytest.mark.parametrize("d,N,k,kind", [(2, 4, 2, 'vertex'), (2, 3, 1, 'cell'), (3, 2, 1, 'cell'),
+                                        (3, 2, 0, 'vertex')])
+def test_u_rows_have_the_eliminated_structure(d, N, k, kind):
+    MM, KK, poff, pdof, nv, ns = build(d, N, k, kind)
+    V, U, P = slice(0, nv), slice(nv, 2 * nv), slice(2 * nv, ns)
+    # u-equation rows: MM = [0, rho M, 0], KK = [-rho M, 0, 0]
+    assert not MM[V, V].any() and not MM[V, P].any()
+    assert not KK[V, U].any() and not KK[V, P].any()
+    assert np.array_equal(KK[V, V], -MM[V, U])
+    # v-equation rows: MM = [rho M, 0, 0] with the same rho M; KK has no V columns
+    assert np.array_equal(MM[U, V], MM[V, U])
+    assert not MM[U, U].any() and not MM[U, P].any() and not KK[U, V].any()
+    # p-equation rows: no U columns at all, no V columns in MM
+    assert not MM[P, V].any() and not MM[P, U].any() and not KK[P, U].any()
+    # rho M couples equal components only and is the same scalar matrix for each
+    Mv = MM[V, U]
+    for c in range(d):
+        for c2 in range(d):
+            blk = Mv[c::d, c2::d]
+            assert (not blk.any()) if c != c2 else np.array_equal(blk, Mv[0::d, 0::d])
+
+
+@pytest.mark.parametrize("d,N,k,kind", [(2, 4, 2, 'vertex'), (3, 2, 1, 'cell'), (2, 2, 1, 'vertex')])
+def test_reduced_solve_reproduces_the_block_inverse(d, N, k, kind):
+    MM, KK, poff, pdof, nv, ns = build(d, N, k, kind, K=0.3)
+    nt = k + 1
+    lam = np.zeros(2 * nt); cplx = np.zeros(nt, dtype=np.int32)
+    tin = np.zeros(2 * nt * nt); qout = np.zeros(2 * nt * nt)
+    LIB.stgmg_host_time_blocks.restype = ctypes.c_int
+    LIB.stgmg_host_time_blocks.argtypes = [ctypes.c_int, ctypes.c_double] + [ctypes.c_void_p] * 4
+    nb = LIB.stgmg_host_time_blocks(k, 0.01, *[hostlib.ptr(a) for a in (lam, cplx, tin, qout)])
+    lams = lam[0::2][:nb] + 1j * lam[1::2][:nb]
+    rng = np.random.default_rng(3)
+    npatch = len(poff) - 1
+    for p in sorted({0, npatch // 2, npatch - 1, int(rng.integers(npatch))}):  # corner, interior, random
+        MMp, KKp, nU = patch_blocks(MM, KK, poff, pdof, nv, k, p)
+        assert 0 < nU and nU % d == 0 and MMp.shape[0] - 2 * nU > 0
+        for l in list(lams) + [1.7, 0.4 + 2.1j]:
+            B = l * MMp + KKp
+            rhs = rng.standard_normal(MMp.shape[0]) + 1j * rng.standard_normal(MMp.shape[0])
+            ref = np.linalg.solve(B, rhs)
+            got = reduced_solve(MMp, KKp, nU, d, l, rhs)
+            assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max(), (p, l)
+
+
+@pytest.mark.parametrize("d,r,k,N,kind", [(2, 2, 2, 8, 'vertex'), (3, 2, 1, 4, 'cell'), (2, 2, 1, 4, 'cell'),
+                                          (3, 2, 1, 2, 'vertex')])
+def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
+    """Closed-form sums of the reduced storage equal the counts over the built patches."""
+    MM, KK, poff, pdof, nv, ns = build(d, N, k, kind)
+    S = hostlib.sizes(LIB, d, r, k, N, 1 if kind == 'vertex' else 0)
+    ld4 = lambda v: (v + 3) // 4 * 4
+    fixed = nrl = max_nr = max_nn = 0
+    for p in range(len(poff) - 1):
+        nsp = (poff[p + 1] - poff[p]) // (k + 1)
+        nU = int(np.sum(pdof[poff[p]:poff[p] + nsp] < nv))
+        nP, nn = nsp - 2 * nU, nU // d
+        nr = nU + nP
+        fixed += nn * ld4(nn) + nU * ld4(nP)
+        nrl += nr * ld4(nr)
+        max_nr, max_nn = max(max_nr, nr), max(max_nn, nn)
+    assert (S['sum_red_fixed'], S['sum_nr_ldr'], S['max_nr'], S['max_nn']) == (fixed, nrl, max_nr, max_nn)
