@@ -114,7 +114,8 @@ struct LevelDev {
   DevCsr A;
   int64_t npatch = 0;
   int max_np = 0;
-  DArr<int64_t> poff, ioff, tptr, tidx;
+  DArr<int64_t> poff, ioff, tptr;
+  DArr<int32_t> tpos;  // dof-major slot of each patch entry
   DArr<int32_t> pdof;
   DArr<int32_t> pnu;  // reduced solves: velocity dofs nU per patch (one time node)
   int max_nu = 0, max_nr = 0, max_npr = 0;
@@ -298,22 +299,22 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
       const bool f32 = h->prm.smoother_prec == STGMG_FP32;
       if (h->red && f32)
         stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, h->tbc, h->prm.dim, L.poff.p,
-                                     L.pdof.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
+                                     L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
       else if (h->red)
         stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, h->tbc, h->prm.dim, L.poff.p,
-                                     L.pdof.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
+                                     L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
       else if (h->tb && f32)
-        stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r,
+        stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r,
                                     L.y.p);
       else if (h->tb)
-        stgmg::k_patch_apply_tb_f64(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r,
+        stgmg::k_patch_apply_tb_f64(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv64.p, r,
                                     L.y.p);
       else if (f32)
-        stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv32.p, r, L.y.p);
+        stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r, L.y.p);
       else
-        stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.ioff.p, L.inv64.p, r, L.y.p);
+        stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv64.p, r, L.y.p);
     }
-    stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.tidx.p, L.winv.p, L.y.p, d);
+    stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.winv.p, L.y.p, d);
   }
 }
 
@@ -542,7 +543,19 @@ void build(stgmg_handle* h) {
       D.ioff.upload(D.ioff_h, h->st, ctr);
       if (h->red) D.pnu.upload(D.pnu_h, h->st, ctr);
       D.tptr.upload(H.tptr, h->st, ctr);
-      D.tidx.upload(H.tidx, h->st, ctr);
+      {
+        // tidx lists the patch entries of each dof; its inverse is the dof-major slot of an entry
+        if (H.tidx.size() >= (size_t(1) << 31)) throw ApiError(STGMG_ERR_UNSUPPORTED, "too many patch entries");
+        std::vector<int32_t> tpos(H.tidx.size(), -1);
+        for (size_t t = 0; t < H.tidx.size(); ++t) {
+          const int64_t e = H.tidx[t];
+          if (e < 0 || size_t(e) >= tpos.size() || tpos[size_t(e)] >= 0)
+            throw ApiError(STGMG_ERR_HIP, "patch entry table is not a permutation");
+          tpos[size_t(e)] = int32_t(t);
+        }
+        D.tpos.upload(tpos, h->st, ctr);
+        HIPCHK(hipStreamSynchronize(h->st));  // tpos (pageable) is freed at the end of this scope
+      }
       D.winv.upload(H.winv, h->st, ctr);
       D.y.alloc(int64_t(H.pdof.size()), ctr, h->st);
       const int64_t tot = D.ioff_h[H.npatch];
@@ -1213,7 +1226,8 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
         temp_peak = std::max(temp_peak, n * n * 8 + 32 * n * 8 + 3 * n * 8 + 64);
       } else {
         res += (n + 1) * 8 + S.nnzP * 12 + (n_prev + 1) * 8 + S.nnzP * 12;
-        res += 2 * (S.npatch + 1) * 8 + S.sum_np * 4 + (n + 1) * 8 + S.sum_np * 8 + n * 8 + S.sum_np * 8;
+        // poff, ioff; pdof, tpos; tptr; winv; y
+        res += 2 * (S.npatch + 1) * 8 + S.sum_np * 4 + S.sum_np * 4 + (n + 1) * 8 + n * 8 + S.sum_np * 8;
         if (!p.time_blocks) {
           res += (n + 1) * 8 + S.nnzA * 12;  // assembled space-time CSR for the patch extraction
           res += S.sum_np_ld * w;

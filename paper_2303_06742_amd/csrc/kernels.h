@@ -42,6 +42,7 @@ void k_gj_invert_f64(hipStream_t st, int nb, int64_t count, int max_n, const GjD
                      int32_t* status);
 void k_gj_invert_f32(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, float* out,
                      int32_t* status);
+// Patch kernels: y_P = A_P^{-1} R_P r, entry l of patch p written to y[tpos[poff[p] + l]].
 // Time-block patch solves.  Constants: tin [nblk][nt] and qout [nt][nblk] complex
 // (re, im interleaved), lam [nblk] complex, cplx [nblk].
 struct TimeBlockConsts {
@@ -59,9 +60,9 @@ void k_form_time_blocks(hipStream_t st, int64_t count, const TimeBlockConsts& tb
                         const double* wmm, const double* wkk, const GjDesc* desc, double* W);
 int patch_apply_tb_threads(int max_ns, bool fp32);
 void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
-                          const int32_t* pdof, const int64_t* ioff, const double* inv, const double* r, double* y);
+                          const int32_t* pdof, const int32_t* tpos, const int64_t* ioff, const double* inv, const double* r, double* y);
 void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
-                          const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y);
+                          const int32_t* pdof, const int32_t* tpos, const int64_t* ioff, const float* inv, const double* r, double* y);
 // Reduced time-block patch solves (u-equation rows eliminated): per batch item, the node
 // mass block, the Schur complement S(lam_a) of every kept eigenvalue (transposed, real form if
 // complex) into the Gauss-Jordan work area via desc (nblk + 1 per patch: mass, blocks), and the
@@ -81,19 +82,19 @@ void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int ma
                         const int32_t* nu_of, const GjDesc* desc, int dstride, float* out);
 int patch_apply_red_threads(int max_nr, bool fp32);
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y);
 void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y);
 // Block size used by the patch GEMV for patches of at most max_np rows.
 int patch_apply_threads(int max_np, bool fp32);
-void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int64_t* ioff, const double* inv, const double* r, double* y);
-void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int64_t* ioff, const float* inv, const double* r, double* y);
-void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
-                    const double* y, double* d);
+// patch images y stored dof-major (slots [tptr[mu], tptr[mu + 1]) of dof mu): d += winv (sum of the slots)
+void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d);
 // y = X b for a dense inverse in the padded column layout; part holds dense_gemv_chunks(n) * n doubles
 int dense_gemv_chunks(int n);
 void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* part, double* y);

@@ -22,6 +22,30 @@ namespace dev {
 
 constexpr int WAVE = 64;
 
+// Workgroups are dispatched round-robin over the XCDs, each with its own L2.  xcd_block maps
+// the dispatch index b of nb blocks to a logical block index such that every XCD processes
+// one contiguous range of logical blocks: neighbouring rows, which read the same vector
+// entries, then meet in the same L2.  A bijection on [0, nb).  (Measured on the 256^2 dG(2)
+// workload: it helps the gathering Vanka update, and slows the streaming SpMV and patch
+// kernels, whose round-robin order keeps the whole chip on one moving address window.)
+constexpr int NXCD = 8;
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+  const int64_t x = b % NXCD, i = b / NXCD, q = nb / NXCD, rem = nb % NXCD;
+  return x * q + (x < rem ? x : rem) + i;
+}
+
+// Chunked variant: chunks of c consecutive logical blocks go round-robin to the XCDs, so that
+// neighbours within a chunk share an L2 while the XCDs stay on one moving address window.
+// The blocks past the last whole round of NXCD chunks keep their index.  c <= 0: identity.
+// A bijection on [0, nb).
+__device__ inline int64_t xcd_chunk(int64_t b, int64_t nb, int64_t c) {
+  if (c <= 0) return b;
+  const int64_t nfull = nb / (NXCD * c) * (NXCD * c);
+  if (b >= nfull) return b;
+  const int64_t x = b % NXCD, i = b / NXCD;
+  return ((i / c) * NXCD + x) * c + i % c;
+}
+
 template <int G>
 __device__ inline double group_sum(double v) {
 #pragma unroll
@@ -475,6 +499,7 @@ __global__ void __launch_bounds__(256) gj_invert_kernel(const GjDesc* __restrict
 template <typename T, int RPT>
 __global__ void __launch_bounds__(512) patch_apply_kernel(int64_t npatch, const int64_t* __restrict__ poff,
                                                           const int32_t* __restrict__ pdof,
+                                                          const int32_t* __restrict__ tpos,
                                                           const int64_t* __restrict__ ioff,
                                                           const T* __restrict__ inv, const double* __restrict__ r,
                                                           double* __restrict__ y) {
@@ -515,7 +540,7 @@ __global__ void __launch_bounds__(512) patch_apply_kernel(int64_t npatch, const 
   a += b;
 #pragma unroll
   for (int q = 0; q < RPT; ++q)
-    if (i0 + q < n) y[o + i0 + q] = double(a[q]);
+    if (i0 + q < n) y[tpos[o + i0 + q]] = double(a[q]);
 }
 
 // Time-block patch solve: y_P = (Q x I) blockdiag(X_a) (Q^{-1} (M^t)^{-1} x I) r_P with the
@@ -549,6 +574,7 @@ __device__ inline V ld16(const V* p) {
 template <typename T, int W, bool NTL>
 __global__ void __launch_bounds__(512) patch_apply_tb_kernel(TimeBlockConsts tb, const int64_t* __restrict__ poff,
                                                              const int32_t* __restrict__ pdof,
+                                                             const int32_t* __restrict__ tpos,
                                                              const int64_t* __restrict__ ioff,
                                                              const T* __restrict__ inv, const double* __restrict__ r,
                                                              double* __restrict__ y) {
@@ -653,7 +679,7 @@ __global__ void __launch_bounds__(512) patch_apply_tb_kernel(TimeBlockConsts tb,
         }
         acc += tb.cplx[a] ? 2.0 * (qr * t_r - qi * t_i) : qr * t_r;
       }
-      y[o + b * ns + i] = acc;
+      y[tpos[o + b * ns + i]] = acc;
     }
 }
 
@@ -698,16 +724,17 @@ __device__ inline __amdgpu_buffer_rsrc_t patch_rsrc(const T* p, int64_t count) {
 }
 
 template <typename T, int R, bool NTL>
-__global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb, int d, int W,
+__global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb, int d, int W, int xc,
                                                               const int64_t* __restrict__ poff,
                                                               const int32_t* __restrict__ pdof,
+                                                              const int32_t* __restrict__ tpos,
                                                               const int32_t* __restrict__ pnu,
                                                               const int64_t* __restrict__ ioff,
                                                               const T* __restrict__ inv, const double* __restrict__ r,
                                                               double* __restrict__ y) {
   typedef T V __attribute__((ext_vector_type(R)));
   extern __shared__ double sm[];
-  const int64_t p = blockIdx.x;
+  const int64_t p = xcd_chunk(blockIdx.x, gridDim.x, xc);
   const int64_t o = poff[p];
   const int n = int(poff[p + 1] - o);
   const int nt = tb.nt, nblk = tb.nblk;
@@ -927,7 +954,7 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
           const double qr = tb.qout[2 * (b * nblk + a)], qi = tb.qout[2 * (b * nblk + a) + 1];
           acc += tb.cplx[a] ? 2.0 * (qr * hr[a] - qi * hi[a]) : qr * hr[a];
         }
-      y[o + b * ns + i] = acc;
+      y[tpos[o + b * ns + i]] = acc;
     }
   }
 }
@@ -958,14 +985,15 @@ __global__ void __launch_bounds__(256) fold_reduced_kernel(int d, const int32_t*
   }
 }
 
-// d[mu] += winv[mu] * sum of the patch images of mu, in patch order
-__global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr, const int64_t* __restrict__ tidx,
-                                    const double* __restrict__ winv, const double* __restrict__ y,
-                                    double* __restrict__ d) {
-  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+// d[mu] += winv[mu] * sum of the patch images of mu, stored dof-major: the patch kernels write
+// the image of patch entry (p, l) at tpos[poff[p] + l], and the slots of mu are
+// [tptr[mu], tptr[mu + 1]) in patch order.
+__global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr, const double* __restrict__ winv,
+                                    const double* __restrict__ y, double* __restrict__ d) {
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int64_t t = tptr[i]; t < tptr[i + 1]; ++t) s += y[tidx[t]];
+  for (int64_t t = tptr[i]; t < tptr[i + 1]; ++t) s += y[t];
   d[i] += winv[i] * s;
 }
 
@@ -1433,17 +1461,17 @@ int patch_apply_threads(int max_np, bool fp32) {
   return t < 64 ? 64 : t;
 }
 
-void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int64_t* ioff, const double* inv, const double* r, double* y) {
   if (npatch == 0) return;
   hipLaunchKernelGGL((dev::patch_apply_kernel<double, 2>), dim3(npatch), dim3(patch_apply_threads(max_np, false)),
-                     size_t(max_np) * sizeof(double), st, npatch, poff, pdof, ioff, inv, r, y);
+                     size_t(max_np) * sizeof(double), st, npatch, poff, pdof, tpos, ioff, inv, r, y);
 }
-void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof,
+void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int64_t* ioff, const float* inv, const double* r, double* y) {
   if (npatch == 0) return;
   hipLaunchKernelGGL((dev::patch_apply_kernel<float, 4>), dim3(npatch), dim3(patch_apply_threads(max_np, true)),
-                     size_t(max_np) * sizeof(float), st, npatch, poff, pdof, ioff, inv, r, y);
+                     size_t(max_np) * sizeof(float), st, npatch, poff, pdof, tpos, ioff, inv, r, y);
 }
 
 void k_patch_extract_spatial_t(hipStream_t st, int64_t p0, int64_t count, int nt, int max_ns, const int64_t* poff,
@@ -1486,7 +1514,7 @@ static void tb_variant(int* W, bool* ntl) {
 
 template <typename T>
 static void launch_tb(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
-                      const int32_t* pdof, const int64_t* ioff, const T* inv, const double* r, double* y) {
+                      const int32_t* pdof, const int32_t* tpos, const int64_t* ioff, const T* inv, const double* r, double* y) {
   if (npatch == 0) return;
   int W;
   bool ntl;
@@ -1494,7 +1522,7 @@ static void launch_tb(hipStream_t st, int64_t npatch, int max_np, const TimeBloc
   const int th = patch_apply_tb_threads(max_np / tb.nt, sizeof(T) == 4) * W;
   const size_t lds = tb_lds(max_np, tb.nt, tb.nblk, W);
 #define STGMG_TB(WW, NN)                                                                                      \
-  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<T, WW, NN>), dim3(npatch), dim3(th), lds, st, tb, poff, pdof, \
+  hipLaunchKernelGGL((dev::patch_apply_tb_kernel<T, WW, NN>), dim3(npatch), dim3(th), lds, st, tb, poff, pdof, tpos, \
                      ioff, inv, r, y)
   if (W == 1 && !ntl) STGMG_TB(1, false);
   else if (W == 1) STGMG_TB(1, true);
@@ -1504,12 +1532,12 @@ static void launch_tb(hipStream_t st, int64_t npatch, int max_np, const TimeBloc
 }
 
 void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
-                          const int32_t* pdof, const int64_t* ioff, const double* inv, const double* r, double* y) {
-  launch_tb<double>(st, npatch, max_np, tb, poff, pdof, ioff, inv, r, y);
+                          const int32_t* pdof, const int32_t* tpos, const int64_t* ioff, const double* inv, const double* r, double* y) {
+  launch_tb<double>(st, npatch, max_np, tb, poff, pdof, tpos, ioff, inv, r, y);
 }
 void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
-                          const int32_t* pdof, const int64_t* ioff, const float* inv, const double* r, double* y) {
-  launch_tb<float>(st, npatch, max_np, tb, poff, pdof, ioff, inv, r, y);
+                          const int32_t* pdof, const int32_t* tpos, const int64_t* ioff, const float* inv, const double* r, double* y) {
+  launch_tb<float>(st, npatch, max_np, tb, poff, pdof, tpos, ioff, inv, r, y);
 }
 
 // Reduced time-block solves: LDS regions A = max(n_P, 2 nblk (nU + ldr)) and
@@ -1543,10 +1571,10 @@ int patch_apply_red_threads(int max_nr, bool fp32) {
   return th;
 }
 
-// tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads)
+// tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
 static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
-                       const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                       const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int32_t* pnu, const int64_t* ioff, const T* inv, const double* r, double* y) {
   if (npatch == 0) return;
   constexpr int R = sizeof(T) == 4 ? 4 : 2;
@@ -1554,24 +1582,28 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   red_layout(max_nr, R, &th, &W);
   bool ntl = true;
   if (const char* e = std::getenv("STGMG_RED_NT")) ntl = std::atoi(e) != 0;
+  // chunks of 16 patches per XCD: measured best of {off, 16, 64, 256, 1024, contiguous} on the
+  // 256^2 dG(2) workload (the dof-major image writes of neighbouring patches share lines)
+  int xc = 16;
+  if (const char* e = std::getenv("STGMG_XCD_CHUNK")) xc = std::atoi(e);  // tuning: 0 = round-robin
   const size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
   if (ntl)
-    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, true>), dim3(npatch), dim3(th), lds, st, tb, d, W, poff,
-                       pdof, pnu, ioff, inv, r, y);
+    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, true>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff,
+                       pdof, tpos, pnu, ioff, inv, r, y);
   else
-    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, false>), dim3(npatch), dim3(th), lds, st, tb, d, W, poff,
-                       pdof, pnu, ioff, inv, r, y);
+    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, false>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff,
+                       pdof, tpos, pnu, ioff, inv, r, y);
 }
 
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y) {
-  launch_red<double>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, pnu, ioff, inv, r, y);
+  launch_red<double>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y) {
-  launch_red<float>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, pnu, ioff, inv, r, y);
+  launch_red<float>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 
 template <typename T>
@@ -1608,11 +1640,9 @@ void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockCon
                      max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
 }
 
-void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const int64_t* tidx, const double* winv,
-                    const double* y, double* d) {
+void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d) {
   if (n == 0) return;
-  hipLaunchKernelGGL(dev::vanka_update_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tptr, tidx, winv, y,
-                     d);
+  hipLaunchKernelGGL(dev::vanka_update_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tptr, winv, y, d);
 }
 
 int dense_gemv_chunks(int n) { return (n + dev::GEMV_COLS - 1) / dev::GEMV_COLS; }
