@@ -48,7 +48,7 @@ def measured_traffic(workload, precision):
 
 def configs():
     from paper_2303_06742_amd import workloads as W
-    return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3}
+    return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3, 'c3v': W.C3V}
 
 
 def cpu_baseline(cfg, sample_levels):
@@ -188,7 +188,7 @@ def main():
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=5)
     ap.add_argument('--warmup', type=int, default=1)
-    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3', 'batch', 'serve'])
+    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3', 'c3v', 'batch', 'serve'])
     ap.add_argument('--batch-count', type=int, default=64)
     ap.add_argument('--serve-count', type=int, default=48)
     ap.add_argument('--serve-rates', type=float, nargs='*', default=[0.5, 0.9])

@@ -62,6 +62,10 @@ C2 = Config('2d-256x256-dg2-vertex', dim=2, coarse_cells=4, levels=7, k=2, patch
 # 3D unit cube, 32^3 hexes (4 levels), dG(1), 10 slabs, lognormal K (log-sd 1), alpha=1, c0=1e-3, cell patches
 C3 = Config('3d-32cube-dg1-cell', dim=3, coarse_cells=4, levels=4, k=1, patch='cell', tau=1e-3, slabs=10,
             alpha=1.0, c0=1e-3, K_logsd=1.0, seed=0)
+# the same 3D physics with vertex patches (2x2x2 cells, the paper's 3D smoother); stored with the
+# reduced time-block solves it takes about 104 GB (FP64)
+C3V = Config('3d-32cube-dg1-vertex', dim=3, coarse_cells=4, levels=4, k=1, patch='vertex', tau=1e-3, slabs=10,
+             alpha=1.0, c0=1e-3, K_logsd=1.0, seed=0)
 
 
 def scaled(cfg, levels, name=None, **kw):

@@ -42,7 +42,10 @@ CONFIGS = {
     'c2s_cell': W.scaled(W.C2, 3, name='2d-16x16-dg2-cell', patch='cell'),
     'c3s': W.scaled(W.C3, 2, name='3d-8cube-dg1-cell-lognormal'),   # C3 physics, 8^3, 2 levels
     'k0': W.scaled(W.C1, 2, name='2d-8x8-dg0-vertex', k=0, patch='vertex'),
+    'k3': W.scaled(W.C1, 2, name='2d-8x8-dg3-cell', k=3),  # two complex eigenvalue pairs
     'one_level': W.scaled(W.C1, 1, name='2d-4x4-dg1-direct'),
+    # 3D vertex patches (up to 1,554 rows; reduced solves of 402-row Schur blocks), 4^3 fine
+    'c3v': W.scaled(W.C3, 2, name='3d-4cube-dg1-vertex-lognormal', coarse_cells=2, patch='vertex'),
     # the same operators with the full space-time patch inverses
     'c1_full': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-full', time_blocks=0),
     'c2s_full': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-full', time_blocks=0),

@@ -26,8 +26,8 @@ def rel_err(a, b, scale=None):
     return np.abs(a - b).max() / s
 
 
-KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb', 'c3s_tb',
-        'k0_tb']
+KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'k3', 'c3v', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb',
+        'c3s_tb', 'k0_tb']
 
 
 @pytest.mark.parametrize("key", KEYS)
