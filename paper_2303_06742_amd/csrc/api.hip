@@ -493,9 +493,19 @@ void build(stgmg_handle* h) {
       if (s) throw ApiError(STGMG_ERR_SINGULAR_PATCH, "coarse operator is singular");
     }
     if (l >= 1) {
-      stgmg::Csr P = stgmg::build_prolongation(prev, H);
+      stgmg::Csr P = stgmg::build_prolongation(prev, H, nth);
       D.P.upload(P, h->st, ctr);
-      D.R.upload(stgmg::transpose(P, H.n), h->st, ctr);
+      {
+        // P is block diagonal over (time node, field): V, U, P rows of each fine time node
+        // interpolate from the same block of the coarse time node
+        std::vector<int64_t> rb{0}, cb{0};
+        for (int tn = 0; tn <= p.k; ++tn)
+          for (int f = 0; f < 3; ++f) {
+            rb.push_back(tn * H.ns + (f == 0 ? H.nv : f == 1 ? 2 * H.nv : H.ns));
+            cb.push_back(tn * prev.ns + (f == 0 ? prev.nv : f == 1 ? 2 * prev.nv : prev.ns));
+          }
+        D.R.upload(stgmg::transpose_block_diag(P, H.n, rb, cb, nth), h->st, ctr);
+      }
       // patches
       D.npatch = H.npatch;
       D.poff_h = H.poff;
@@ -543,19 +553,8 @@ void build(stgmg_handle* h) {
       D.ioff.upload(D.ioff_h, h->st, ctr);
       if (h->red) D.pnu.upload(D.pnu_h, h->st, ctr);
       D.tptr.upload(H.tptr, h->st, ctr);
-      {
-        // tidx lists the patch entries of each dof; its inverse is the dof-major slot of an entry
-        if (H.tidx.size() >= (size_t(1) << 31)) throw ApiError(STGMG_ERR_UNSUPPORTED, "too many patch entries");
-        std::vector<int32_t> tpos(H.tidx.size(), -1);
-        for (size_t t = 0; t < H.tidx.size(); ++t) {
-          const int64_t e = H.tidx[t];
-          if (e < 0 || size_t(e) >= tpos.size() || tpos[size_t(e)] >= 0)
-            throw ApiError(STGMG_ERR_HIP, "patch entry table is not a permutation");
-          tpos[size_t(e)] = int32_t(t);
-        }
-        D.tpos.upload(tpos, h->st, ctr);
-        HIPCHK(hipStreamSynchronize(h->st));  // tpos (pageable) is freed at the end of this scope
-      }
+      if (H.tpos.size() >= (size_t(1) << 31)) throw ApiError(STGMG_ERR_UNSUPPORTED, "too many patch entries");
+      D.tpos.upload(H.tpos, h->st, ctr);
       D.winv.upload(H.winv, h->st, ctr);
       D.y.alloc(int64_t(H.pdof.size()), ctr, h->st);
       const int64_t tot = D.ioff_h[H.npatch];
@@ -760,7 +759,7 @@ void build(stgmg_handle* h) {
       h->fine_info.pdof.shrink_to_fit();
       h->fine_info.poff.clear();
       h->fine_info.tptr.clear();
-      h->fine_info.tidx.clear();
+      h->fine_info.tpos.clear();
       h->fine_info.winv.clear();
     }
     HIPCHK(hipStreamSynchronize(h->st));  // host vectors of H are freed below

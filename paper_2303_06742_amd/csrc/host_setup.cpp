@@ -13,6 +13,7 @@
 #include "host_setup.h"
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <functional>
@@ -676,6 +677,49 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
   const int64_t ns = L.ns;
   const int nt = k + 1;
 
+  if (!o.need_A) {
+    // no space-time matrix: each spatial row of MM and KK is built once into the buffer of its
+    // chunk of rows, and the chunks are copied into place behind the prefix sums
+    const int nch = int(std::max<int64_t>(1, std::min<int64_t>(nthreads, (ns + 4095) / 4096)));
+    const int64_t chunk = (ns + nch - 1) / nch;
+    std::vector<std::vector<Entry>> bm(nch), bk(nch);
+    std::vector<int64_t> mmlen(ns), kklen(ns);
+    auto run = [&](auto&& body) {
+      std::vector<std::thread> th;
+      for (int c = 1; c < nch; ++c) th.emplace_back([&body, c] { body(c); });
+      body(0);
+      for (auto& x : th) x.join();
+    };
+    run([&](int c) {
+      std::vector<Entry> mm, kk;
+      for (int64_t i = c * chunk; i < std::min(ns, (c + 1) * chunk); ++i) {
+        rb.row(i, mm, kk);
+        mmlen[i] = int64_t(mm.size());
+        kklen[i] = int64_t(kk.size());
+        if (o.need_MM) bm[c].insert(bm[c].end(), mm.begin(), mm.end());
+        if (o.need_KK) bk[c].insert(bk[c].end(), kk.begin(), kk.end());
+      }
+    });
+    auto finish = [&](bool need, Csr& M, const std::vector<int64_t>& len, std::vector<std::vector<Entry>>& buf) {
+      if (!need) return;
+      M.nrows = ns;
+      M.ncols = ns;
+      M.ptr.assign(ns + 1, 0);
+      for (int64_t i = 0; i < ns; ++i) M.ptr[i + 1] = M.ptr[i] + len[i];
+      M.col.resize(M.ptr[ns]);
+      M.val.resize(M.ptr[ns]);
+      run([&](int c) {
+        int64_t q = M.ptr[std::min(ns, c * chunk)];
+        for (const Entry& e : buf[c]) {
+          M.col[q] = int32_t(e.col);
+          M.val[q++] = e.val;
+        }
+        std::vector<Entry>().swap(buf[c]);
+      });
+    };
+    finish(o.need_MM, L.MM, mmlen, bm);
+    finish(o.need_KK, L.KK, kklen, bk);
+  } else {
   // pass 1: space-time row lengths
   std::vector<int64_t> slen(ns);  // length of one space-time row for spatial row i (same for every b)
   std::vector<int64_t> mmlen(ns), kklen(ns);
@@ -783,6 +827,8 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
     }
   });
 
+  }  // need_A
+
   if (!o.need_patches) return;
   // ------------------------------------------------------------ patches
   // vertex patch at grid vertex v: the cells with c in {v-1, v} (per axis) that exist;
@@ -852,14 +898,30 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
       }
     }
   });
-  // transposed map and weights (deterministic: patches in increasing order)
+  // dof-major slots of the patch entries (deterministic: patches in increasing order).  The
+  // entries of one (time node, field) of a patch are contiguous and touch only that block of
+  // dofs, so the nt * 3 blocks are independent streams.
   L.tptr.assign(L.n + 1, 0);
   for (int64_t t = 0; t < int64_t(L.pdof.size()); ++t) L.tptr[L.pdof[t] + 1]++;
   for (int64_t i = 0; i < L.n; ++i) L.tptr[i + 1] += L.tptr[i];
-  L.tidx.resize(L.pdof.size());
+  L.tpos.resize(L.pdof.size());
   {
     std::vector<int64_t> fill(L.tptr.begin(), L.tptr.end() - 1);
-    for (int64_t t = 0; t < int64_t(L.pdof.size()); ++t) L.tidx[fill[L.pdof[t]]++] = t;
+    const int nstream = nt * 3;
+    parallel_for(nstream * 4096, std::min(nthreads, nstream), [&](int64_t lo, int64_t hi) {
+      for (int64_t sidx = lo / 4096; sidx < (hi + 4095) / 4096 && sidx < nstream; ++sidx) {
+        if (sidx * 4096 < lo) continue;  // each stream is handled by the thread holding its first index
+        const int tn = int(sidx / 3), field = int(sidx % 3);
+        for (int64_t pi = 0; pi < L.npatch; ++pi) {
+          const int64_t o = L.poff[pi], nsp = (L.poff[pi + 1] - o) / nt;
+          const int32_t* b0 = L.pdof.data() + o + tn * nsp;
+          const int64_t nU = std::lower_bound(L.pdof.data() + o, L.pdof.data() + o + nsp, int32_t(L.nv)) -
+                             (L.pdof.data() + o);
+          const int64_t f0 = field == 0 ? 0 : field == 1 ? nU : 2 * nU, f1 = field == 0 ? nU : field == 1 ? 2 * nU : nsp;
+          for (int64_t l = f0; l < f1; ++l) L.tpos[o + tn * nsp + l] = int32_t(fill[b0[l]]++);
+        }
+      }
+    });
   }
   L.winv.resize(L.n);
   for (int64_t i = 0; i < L.n; ++i) {
@@ -888,16 +950,26 @@ int interp_weights_1d(int p, int Nc, int64_t g, int64_t* cols, double* w) {
 }
 }  // namespace
 
-Csr build_prolongation(const LevelHost& C, const LevelHost& F) {
-  const int d = F.d, r = F.r, nt = F.k + 1;
+Csr build_prolongation(const LevelHost& C, const LevelHost& F, int nthreads) {
+  const int d = F.d, r = F.r;
   Csr P;
   P.nrows = F.n;
   P.ncols = C.n;
   P.ptr.assign(F.n + 1, 0);
-  // rows in order; build row by row
-  std::vector<int64_t> cols;
-  std::vector<double> vals;
-  auto emit_scalar = [&](int p, int64_t fnode, int64_t fn1, int64_t cn1, int64_t base_col, int stride, int comp) {
+  // entries of one row (at most 3^d: the 1D weights have at most 3 nonzeros), columns ascending
+  auto row_entries = [&](int64_t row, int64_t* cols, double* vals) {
+    const int tn = int(row / F.ns);
+    const int64_t s = row % F.ns;
+    const int64_t coff = int64_t(tn) * C.ns;
+    int p, comp, stride;
+    int64_t fnode, fn1, cn1, base_col;
+    if (s < 2 * F.nv) {
+      const int field = s < F.nv ? 0 : 1;
+      const int64_t iv = s - field * F.nv;
+      p = r, fnode = iv / d, fn1 = F.n1, cn1 = C.n1, base_col = coff + field * C.nv, stride = d, comp = int(iv % d);
+    } else {
+      p = r - 1, fnode = s - 2 * F.nv, fn1 = F.n1p, cn1 = C.n1p, base_col = coff + 2 * C.nv, stride = 1, comp = 0;
+    }
     int64_t g[3], rem = fnode;
     for (int ax = 0; ax < d; ++ax) {
       g[ax] = rem % fn1;
@@ -907,8 +979,8 @@ Csr build_prolongation(const LevelHost& C, const LevelHost& F) {
     double w1[3][8];
     int n1[3] = {1, 1, 1};
     for (int ax = 0; ax < d; ++ax) n1[ax] = interp_weights_1d(p, C.N, g[ax], c1[ax], w1[ax]);
-    // columns ascending: z outer, x inner
-    for (int iz = 0; iz < (d > 2 ? n1[2] : 1); ++iz)
+    int cnt = 0;
+    for (int iz = 0; iz < (d > 2 ? n1[2] : 1); ++iz)  // z outer, x inner
       for (int iy = 0; iy < (d > 1 ? n1[1] : 1); ++iy)
         for (int ix = 0; ix < n1[0]; ++ix) {
           int64_t node = c1[0][ix];
@@ -921,28 +993,75 @@ Csr build_prolongation(const LevelHost& C, const LevelHost& F) {
             node += cn1 * cn1 * c1[2][iz];
             w *= w1[2][iz];
           }
-          cols.push_back(base_col + stride * node + comp);
-          vals.push_back(w);
+          if (cols) {
+            cols[cnt] = base_col + stride * node + comp;
+            vals[cnt] = w;
+          }
+          ++cnt;
         }
+    return cnt;
   };
-  for (int64_t row = 0; row < F.n; ++row) {
-    const int tn = int(row / F.ns);
-    const int64_t s = row % F.ns;
-    const int64_t coff = int64_t(tn) * C.ns;
-    if (s < 2 * F.nv) {
-      const int field = s < F.nv ? 0 : 1;
-      const int64_t iv = s - field * F.nv;
-      emit_scalar(r, iv / d, F.n1, C.n1, coff + field * C.nv, d, int(iv % d));
-    } else {
-      emit_scalar(r - 1, s - 2 * F.nv, F.n1p, C.n1p, coff + 2 * C.nv, 1, 0);
+  parallel_for(F.n, nthreads, [&](int64_t lo, int64_t hi) {
+    for (int64_t row = lo; row < hi; ++row) P.ptr[row + 1] = row_entries(row, nullptr, nullptr);
+  });
+  for (int64_t row = 0; row < F.n; ++row) P.ptr[row + 1] += P.ptr[row];
+  P.col.resize(P.ptr[F.n]);
+  P.val.resize(P.ptr[F.n]);
+  parallel_for(F.n, nthreads, [&](int64_t lo, int64_t hi) {
+    int64_t cols[64];
+    double vals[64];
+    for (int64_t row = lo; row < hi; ++row) {
+      const int cnt = row_entries(row, cols, vals);
+      for (int q = 0; q < cnt; ++q) {
+        P.col[P.ptr[row] + q] = int32_t(cols[q]);
+        P.val[P.ptr[row] + q] = vals[q];
+      }
     }
-    P.ptr[row + 1] = int64_t(cols.size());
-  }
-  P.col.resize(cols.size());
-  for (size_t i = 0; i < cols.size(); ++i) P.col[i] = int32_t(cols[i]);
-  P.val = std::move(vals);
-  (void)nt;
+  });
   return P;
+}
+
+Csr transpose_block_diag(const Csr& a, int64_t ncols_out, const std::vector<int64_t>& rb,
+                         const std::vector<int64_t>& cb, int nthreads) {
+  const int nb = int(rb.size()) - 1;
+  if (int(cb.size()) != nb + 1 || rb[nb] != a.nrows || cb[nb] != a.ncols)
+    throw std::runtime_error("transpose_block_diag: block ranges do not cover the matrix");
+  Csr t;
+  t.nrows = a.ncols;
+  t.ncols = ncols_out;
+  t.ptr.assign(a.ncols + 1, 0);
+  std::atomic<bool> bad{false};
+  auto blocks = [&](auto&& body) {
+    parallel_for(int64_t(nb) * 4096, std::min(nthreads, nb), [&](int64_t lo, int64_t hi) {
+      for (int64_t b = lo / 4096; b < nb && b * 4096 < hi; ++b)
+        if (b * 4096 >= lo) body(int(b));
+    });
+  };
+  blocks([&](int b) {  // counts of the columns of block b (disjoint column ranges)
+    for (int64_t row = rb[b]; row < rb[b + 1]; ++row)
+      for (int64_t p = a.ptr[row]; p < a.ptr[row + 1]; ++p) {
+        const int64_t c = a.col[p];
+        if (c < cb[b] || c >= cb[b + 1]) {
+          bad = true;
+          return;
+        }
+        t.ptr[c + 1]++;
+      }
+  });
+  if (bad) throw std::runtime_error("transpose_block_diag: an entry lies outside its diagonal block");
+  for (int64_t i = 0; i < a.ncols; ++i) t.ptr[i + 1] += t.ptr[i];
+  t.col.resize(a.col.size());
+  t.val.resize(a.val.size());
+  blocks([&](int b) {  // rows in increasing order within every column
+    std::vector<int64_t> fill(t.ptr.begin() + cb[b], t.ptr.begin() + cb[b + 1]);
+    for (int64_t row = rb[b]; row < rb[b + 1]; ++row)
+      for (int64_t p = a.ptr[row]; p < a.ptr[row + 1]; ++p) {
+        const int64_t q = fill[a.col[p] - cb[b]]++;
+        t.col[q] = int32_t(row);
+        t.val[q] = a.val[p];
+      }
+  });
+  return t;
 }
 
 Csr transpose(const Csr& a, int64_t ncols_out) {

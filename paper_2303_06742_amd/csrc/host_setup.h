@@ -68,9 +68,10 @@ struct LevelHost {
   int64_t npatch = 0;
   std::vector<int64_t> poff;
   std::vector<int32_t> pdof;
-  // averaged scatter: entries of dof mu are at positions tidx[tptr[mu]..tptr[mu+1]) of pdof
+  // dof-major slots: entry t of pdof has slot tpos[t]; the slots of dof mu are
+  // [tptr[mu], tptr[mu+1]), in increasing patch order
   std::vector<int64_t> tptr;
-  std::vector<int64_t> tidx;
+  std::vector<int32_t> tpos;
   std::vector<double> winv;  // omega / (number of patches containing mu)
 };
 
@@ -89,8 +90,12 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
                  int nthreads);
 
 // Space-time prolongation from the coarse level to the next finer one.
-Csr build_prolongation(const LevelHost& coarse, const LevelHost& fine);
+Csr build_prolongation(const LevelHost& coarse, const LevelHost& fine, int nthreads = 1);
 Csr transpose(const Csr& a, int64_t ncols_out);
+// Transpose of a block-diagonal matrix: rows [rb[i], rb[i+1]) have their columns in
+// [cb[i], cb[i+1]) (checked); the blocks are transposed in parallel.
+Csr transpose_block_diag(const Csr& a, int64_t ncols_out, const std::vector<int64_t>& rb,
+                         const std::vector<int64_t>& cb, int nthreads);
 
 // Closed-form sizes of one level, without building it (exact structural counts).
 struct LevelSizes {
