@@ -46,6 +46,28 @@ def measured_traffic(workload, precision):
     return None
 
 
+def measured_read_peak(torch):
+    """Reference HBM read rate on this GPU: the best of torch.sum over a 4 GiB FP64 tensor and
+    torch's device copy of the same (read + write counted), three timed runs each."""
+    a = torch.ones(1 << 29, dtype=torch.float64, device='cuda')
+    b = torch.empty_like(a)
+    best = {}
+    for name, fn, nbytes in (('sum', lambda: a.sum(), a.numel() * 8),
+                              ('copy', lambda: b.copy_(a), 2 * a.numel() * 8)):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        best[name] = nbytes / (e0.elapsed_time(e1) / 3 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return best
+
+
 def configs():
     from paper_2303_06742_amd import workloads as W
     return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3, 'c3v': W.C3V}
@@ -304,6 +326,10 @@ def main():
                           'achieved_GBs': rs['bytes_per_launch'] / (avg_rs_ms * 1e-3) / 1e9 if rs['launches'] else 0},
     }
     S.close()
+    peak = measured_read_peak(torch)
+    # torch's own streaming kernels on the same GPU, for context (not the roofline peak)
+    out['roofline']['torch_stream_reference'] = {'unit': 'GB/s', 'sum': peak['sum'], 'copy': peak['copy'],
+                                                 'achieved_over_best': achieved / max(peak.values())}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         lv = args.cpu_sample_levels or (4 if cfg.dim == 2 else 2)

@@ -255,6 +255,15 @@ size_t lds_limit() {
   return 64 * 1024;
 }
 
+// LDS one workgroup may use on the current device (160 KiB on gfx950)
+size_t lds_per_block() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 64 * 1024;
+  return size_t(v);
+}
+
 void vcycle(stgmg_handle* h, int l, const double* b, double* d);
 
 // Event pair around one launch of kernel class `what` on the finest level.
@@ -607,16 +616,20 @@ void build(stgmg_handle* h) {
         const int nt = p.k + 1, nblk = h->tbc.nblk;
         const int max_ns = max_np / nt, max_nr = D.max_nr, max_nn = D.max_nu / d;
         bool any_c = false;
+        for (int a = 0; a < nblk; ++a) any_c = any_c || h->tbc.cplx[a];
+        // blocks held entirely in LDS when they fit in one workgroup's LDS (complex blocks then
+        // inverted in complex arithmetic), else the panel kernel on the 2x2-block real form
+        const bool in_lds = stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
+                            stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block();
         int64_t per_patch = int64_t(max_nn) * max_nn;
         std::vector<int64_t> blk_woff(nblk);
         for (int a = 0; a < nblk; ++a) {
           blk_woff[a] = per_patch;
-          const int64_t na = h->tbc.cplx[a] ? 2 * max_nr : max_nr;
-          per_patch += na * na;
-          any_c = any_c || h->tbc.cplx[a];
+          const bool c = h->tbc.cplx[a] != 0;
+          per_patch += in_lds ? (c ? 2 : 1) * int64_t(max_nr) * max_nr : (c ? 4 : 1) * int64_t(max_nr) * max_nr;
         }
         const int max_n = std::max(any_c ? 2 * max_nr : max_nr, max_nn);
-        const int nb = stgmg::gj_panel_width(max_n, lds_limit());
+        const int nb = in_lds ? 32 : stgmg::gj_panel_width(max_n, lds_limit());
         if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
         if (stgmg::patch_apply_red_threads(max_nr, p.smoother_prec == STGMG_FP32) > 512 || D.max_nu > 64 * 32)
           throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the reduced patch solve");
@@ -646,16 +659,36 @@ void build(stgmg_handle* h) {
             oo += int64_t(nn) * ldn + int64_t(nU) * ldp;
             for (int a = 0; a < nblk; ++a) {
               const bool c = h->tbc.cplx[a] != 0;
-              dd[i * (nblk + 1) + 1 + a] = {c ? 2 * nr : nr, nr, c ? 2 * ldr : ldr, c ? nr : 0, ldr,
+              const int n_in = c && !in_lds ? 2 * nr : nr;  // LDS kernel: complex n x n
+              dd[i * (nblk + 1) + 1 + a] = {n_in, nr, c ? 2 * ldr : ldr, c ? nr : 0, ldr,
                                             int32_t(p0 + i), i * per_patch + blk_woff[a], oo};
               oo += int64_t(nr) * (c ? 2 * ldr : ldr);
             }
           }
+          // descriptors grouped by kernel for the LDS path: mass blocks, real blocks, complex blocks
+          std::vector<stgmg::GjDesc> grp;
+          int64_t n_mass = 0, n_real = 0;
+          if (in_lds) {
+            for (int g = 0; g < 3; ++g)
+              for (int64_t i = 0; i < cnt; ++i)
+                for (int sl = 0; sl <= nblk; ++sl) {
+                  const int kind = sl == 0 ? 0 : h->tbc.cplx[sl - 1] ? 2 : 1;
+                  if (kind == g) grp.push_back(dd[i * (nblk + 1) + sl]);
+                }
+            n_mass = cnt;
+            for (int a = 0; a < nblk; ++a) n_real += h->tbc.cplx[a] ? 0 : cnt;
+          }
+          const int64_t n_cplx = int64_t(grp.size()) - n_mass - n_real;
           descs.push_back(std::move(dd));
+          descs.push_back(std::move(grp));
           nss.push_back(std::move(ns_of));
           nus.push_back(std::move(nu_of));
           ddesc.emplace_back();
-          ddesc.back().upload(descs.back(), h->st, nullptr);
+          ddesc.back().upload(descs[descs.size() - 2], h->st, nullptr);
+          ddesc.emplace_back();
+          if (in_lds) ddesc.back().upload(descs.back(), h->st, nullptr);
+          const stgmg::GjDesc* dper = ddesc[ddesc.size() - 2].p;
+          const stgmg::GjDesc* dgrp = ddesc.back().p;
           dns.emplace_back();
           dns.back().upload(nss.back(), h->st, nullptr);
           dnu.emplace_back();
@@ -665,17 +698,29 @@ void build(stgmg_handle* h) {
           stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
                                            D.MMs.val.p, D.KKs.ptr.p, D.KKs.col.p, D.KKs.val.p, wmm.p, wkk.p);
           if (p.smoother_prec == STGMG_FP32) {
-            stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, max_ns, max_nr, dns.back().p, dnu.back().p, wmm.p,
-                                             wkk.p, ddesc.back().p, Wb.p, D.inv32.p);
-            stgmg::k_gj_invert_f32(h->st, nb, cnt * (nblk + 1), max_n, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
-            stgmg::k_fold_reduced_f32(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, ddesc.back().p,
-                                      nblk + 1, D.inv32.p);
+            stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
+                                             dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv32.p);
+            if (in_lds) {
+              stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
+              stgmg::k_gj_lds_f32(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv32.p, stat.p);
+              stgmg::k_gj_lds_f32(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv32.p, stat.p);
+            } else {
+              stgmg::k_gj_invert_f32(h->st, nb, cnt * (nblk + 1), max_n, dper, Wb.p, D.inv32.p, stat.p);
+            }
+            stgmg::k_fold_reduced_f32(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, dper, nblk + 1,
+                                      D.inv32.p);
           } else {
-            stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, max_ns, max_nr, dns.back().p, dnu.back().p, wmm.p,
-                                             wkk.p, ddesc.back().p, Wb.p, D.inv64.p);
-            stgmg::k_gj_invert_f64(h->st, nb, cnt * (nblk + 1), max_n, ddesc.back().p, Wb.p, D.inv64.p, stat.p);
-            stgmg::k_fold_reduced_f64(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, ddesc.back().p,
-                                      nblk + 1, D.inv64.p);
+            stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
+                                             dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv64.p);
+            if (in_lds) {
+              stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv64.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv64.p, stat.p);
+            } else {
+              stgmg::k_gj_invert_f64(h->st, nb, cnt * (nblk + 1), max_n, dper, Wb.p, D.inv64.p, stat.p);
+            }
+            stgmg::k_fold_reduced_f64(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, dper, nblk + 1,
+                                      D.inv64.p);
           }
           HIPCHK(hipGetLastError());
         }
@@ -1238,11 +1283,14 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
         } else if (p.time_blocks == 2) {
           res += (S.sum_red_fixed + (nreal + 2 * ncplx) * S.sum_nr_ldr) * w + S.npatch * 4;
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
-          const int64_t per_patch = int64_t(S.max_nn) * S.max_nn + (nreal + 4 * ncplx) * int64_t(S.max_nr) * S.max_nr;
+          const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
+                              stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
+          const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
+                                    (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
           const int64_t batch =
               std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
           temp_peak = std::max(temp_peak, batch * (per_patch + 2 * sq) * 8 +
-                                              int64_t(sizeof(stgmg::GjDesc)) * batch * (nreal + ncplx + 1) +
+                                              2 * int64_t(sizeof(stgmg::GjDesc)) * batch * (nreal + ncplx + 1) +
                                               2 * batch * 4 + S.npatch * 4);
         } else {
           res += (nreal + 2 * ncplx) * S.sum_ns_ldh * w;

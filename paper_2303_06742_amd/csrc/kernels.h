@@ -64,14 +64,15 @@ void k_patch_apply_tb_f64(hipStream_t st, int64_t npatch, int max_np, const Time
 void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const TimeBlockConsts& tb, const int64_t* poff,
                           const int32_t* pdof, const int32_t* tpos, const int64_t* ioff, const float* inv, const double* r, double* y);
 // Reduced time-block patch solves (u-equation rows eliminated): per batch item, the node
-// mass block, the Schur complement S(lam_a) of every kept eigenvalue (transposed, real form if
-// complex) into the Gauss-Jordan work area via desc (nblk + 1 per patch: mass, blocks), and the
+// mass block, the Schur complement S(lam_a) of every kept eigenvalue (transposed; if complex,
+// real form (cplanes = 0) or real and imaginary planes (cplanes = 1)) into the Gauss-Jordan
+// work area via desc (nblk + 1 per patch: mass, blocks), and the
 // (p-equation, V) block of KK_P straight into the stored layout (out, after the mass inverse).
 // nu_of: velocity dofs nU per patch (per time node).
-void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes, int max_ns,
                                int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
                                const double* wkk, const GjDesc* desc, double* W, double* out);
-void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes, int max_ns,
                                int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
                                const double* wkk, const GjDesc* desc, double* W, float* out);
 // after the inversion: G = KK_pV ((rho M)^{-1} (x) I_d) replaces KK_pV in the stored layout;
@@ -80,6 +81,14 @@ void k_fold_reduced_f64(hipStream_t st, int64_t count, int d, int max_nu, int ma
                         const int32_t* nu_of, const GjDesc* desc, int dstride, double* out);
 void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
                         const int32_t* nu_of, const GjDesc* desc, int dstride, float* out);
+// Gauss-Jordan of matrices held entirely in LDS (one workgroup each, descriptors as for
+// k_gj_invert_*; cplx: input = real plane then imaginary plane of an n x n complex matrix,
+// output Re at column position j and Im at ldh + j).  LDS bytes per workgroup for size max_n:
+size_t gj_lds_kernel_bytes(int max_n, bool cplx);
+void k_gj_lds_f64(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                  double* out, int32_t* status);
+void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                  float* out, int32_t* status);
 int patch_apply_red_threads(int max_nr, bool fp32);
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
                            const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,

@@ -274,13 +274,15 @@ __global__ void form_time_blocks_kernel(TimeBlockConsts tb, int max_ns, const in
 //   A1 = MM[nU+x][nU+y] + [y < nU] KK[nU+x][y],  A0 = KK[nU+x][nU+y].
 // Work items m = (patch i, slot s) of the batch on blockIdx.x, nslot = nblk + 2:
 //   s = 0: the transposed node mass block rho M (component 0 of the u-rows and U columns);
-//   s = 1 + a: the transposed S(lam_a), in the real form [[Re, -Im], [Im, Re]] if complex;
+//   s = 1 + a: the transposed S(lam_a); if complex, in the real form [[Re, -Im], [Im, Re]]
+//            (cplanes == 0) or as the real plane followed by the imaginary plane (cplanes != 0);
 //   s = 1 + nblk: KK[2nU + x][y] (x < nP, y < nU) written to out column-major with leading
 //            dimension inv_ld(nP) (zero padding rows), right after the stored mass inverse.
 // desc holds nblk + 1 Gauss-Jordan descriptors per patch (mass, then the blocks); wmm, wkk
 // are the transposed dense spatial blocks of the patch (stride max_ns^2).
 template <typename T>
-__global__ void form_reduced_blocks_kernel(TimeBlockConsts tb, int d, int max_ns, const int32_t* __restrict__ ns_of,
+__global__ void form_reduced_blocks_kernel(TimeBlockConsts tb, int d, int cplanes, int max_ns,
+                                           const int32_t* __restrict__ ns_of,
                                            const int32_t* __restrict__ nu_of, const double* __restrict__ wmm,
                                            const double* __restrict__ wkk, const GjDesc* __restrict__ desc,
                                            double* __restrict__ W, T* __restrict__ out) {
@@ -310,6 +312,9 @@ __global__ void form_reduced_blocks_kernel(TimeBlockConsts tb, int d, int max_ns
       const double A0 = Kt[int64_t(nU + y) * ns + nU + x];
       if (!tb.cplx[a]) {
         Wd[q] = (al * al) * A2 + al * A1 + A0;
+      } else if (cplanes) {
+        Wd[q] = (al * al - be * be) * A2 + al * A1 + A0;
+        Wd[int64_t(nr) * nr + q] = (2.0 * al * be) * A2 + be * A1;
       } else {
         const int n2 = 2 * nr;
         const double sr = (al * al - be * be) * A2 + al * A1 + A0, si = (2.0 * al * be) * A2 + be * A1;
@@ -487,6 +492,158 @@ __global__ void __launch_bounds__(256) gj_invert_kernel(const GjDesc* __restrict
         j = D.split + (q - D.ldh);
       }
       o[int64_t(i) * D.ld_out + q] = j >= 0 ? T(M[int64_t(i) * n + src[j]] * scl[j]) : T(0);
+    }
+}
+
+// Gauss-Jordan inversion of a matrix held entirely in LDS, one workgroup per descriptor:
+// the same steps and conventions as gj_invert_kernel (power-of-two row equilibration,
+// partial pivoting on the scaled matrix with ties to the lowest row, output rows i < keep of
+// the inverse with the columns un-permuted and re-scaled), without panels.  CPLX: the input
+// at woff holds the real plane (n x n, row-major) followed by the imaginary plane, the pivot
+// size is |re| + |im|, and output row i is written as Re of column j at position j and Im at
+// ldh + j (all other positions of the row are zero).
+template <typename T, bool CPLX>
+__global__ void __launch_bounds__(256) gj_lds_kernel(const GjDesc* __restrict__ desc, const double* __restrict__ W,
+                                                     T* __restrict__ out, int32_t* __restrict__ status) {
+  extern __shared__ double lds[];
+  const GjDesc D = desc[blockIdx.x];
+  const int n = D.n, nn = n * n;
+  double* Ar = lds;                              // n x n
+  double* Ai = CPLX ? lds + nn : nullptr;        // n x n
+  double* fr = lds + (CPLX ? 2 : 1) * nn;        // column k before the update
+  double* fi = CPLX ? fr + n : nullptr;
+  double* scl = fr + (CPLX ? 2 : 1) * n;
+  int* perm = reinterpret_cast<int*>(scl + n);
+  int* src = perm + n;
+  __shared__ int s_piv, s_flag;
+  const int tid = threadIdx.x, bs = blockDim.x;
+  const int wave = tid / WAVE, lane = tid % WAVE, nw = bs / WAVE;
+  const double* M = W + D.woff;
+  for (int t = tid; t < nn; t += bs) {
+    Ar[t] = M[t];
+    if constexpr (CPLX) Ai[t] = M[nn + t];
+  }
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  for (int i = wave; i < n; i += nw) {
+    double m = 0.0;
+    for (int j = lane; j < n; j += WAVE) {
+      m = fmax(m, fabs(Ar[i * n + j]));
+      if constexpr (CPLX) m = fmax(m, fabs(Ai[i * n + j]));
+    }
+    for (int off = WAVE / 2; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    const double sc = (m > 0.0 && isfinite(m)) ? ldexp(1.0, -ilogb(m)) : 1.0;
+    for (int j = lane; j < n; j += WAVE) {
+      Ar[i * n + j] *= sc;
+      if constexpr (CPLX) Ai[i * n + j] *= sc;
+    }
+    if (lane == 0) scl[i] = sc;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    if (wave == 0) {  // pivot: largest scaled entry of column k in rows k..n-1
+      double bv = -1.0;
+      int bi = n;
+      for (int i = k + lane; i < n; i += WAVE) {
+        double v = fabs(Ar[i * n + k]);
+        if constexpr (CPLX) v += fabs(Ai[i * n + k]);
+        if (v > bv) {
+          bv = v;
+          bi = i;
+        }
+      }
+      for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        if (!(bv > 0.0) || !isfinite(bv) || bi >= n) {
+          s_flag = 1;
+          bi = k;
+        }
+        s_piv = bi;
+        perm[k] = bi;
+      }
+    }
+    __syncthreads();
+    const int pr = s_piv;
+    if (pr != k)
+      for (int j = tid; j < n; j += bs) {
+        const double t = Ar[k * n + j];
+        Ar[k * n + j] = Ar[pr * n + j];
+        Ar[pr * n + j] = t;
+        if constexpr (CPLX) {
+          const double u = Ai[k * n + j];
+          Ai[k * n + j] = Ai[pr * n + j];
+          Ai[pr * n + j] = u;
+        }
+      }
+    __syncthreads();
+    // reciprocal of the pivot (every thread), then the pivot row scaled and column k saved
+    double pr_r = Ar[k * n + k], pr_i = CPLX ? Ai[k * n + k] : 0.0;
+    if (!(fabs(pr_r) + fabs(pr_i) > 0.0) || !isfinite(pr_r) || !isfinite(pr_i)) {
+      pr_r = 1.0;
+      pr_i = 0.0;
+    }
+    const double den = pr_r * pr_r + pr_i * pr_i;
+    const double rr = CPLX ? pr_r / den : 1.0 / pr_r, ri = CPLX ? -pr_i / den : 0.0;
+    __syncthreads();
+    for (int j = tid; j < n; j += bs) {
+      const double a = j == k ? 1.0 : Ar[k * n + j];
+      const double b = CPLX ? (j == k ? 0.0 : Ai[k * n + j]) : 0.0;
+      Ar[k * n + j] = a * rr - b * ri;
+      if constexpr (CPLX) Ai[k * n + j] = a * ri + b * rr;
+    }
+    for (int i = tid; i < n; i += bs) {
+      fr[i] = i == k ? 0.0 : Ar[i * n + k];
+      if constexpr (CPLX) fi[i] = i == k ? 0.0 : Ai[i * n + k];
+      if (i != k) {
+        Ar[i * n + k] = 0.0;
+        if constexpr (CPLX) Ai[i * n + k] = 0.0;
+      }
+    }
+    __syncthreads();
+    for (int t = tid; t < nn; t += bs) {
+      const int i = t / n, j = t - i * n;
+      if (i == k) continue;
+      if constexpr (CPLX) {
+        const double a = fr[i], b = fi[i], c = Ar[k * n + j], e = Ai[k * n + j];
+        Ar[t] -= a * c - b * e;
+        Ai[t] -= a * e + b * c;
+      } else {
+        Ar[t] -= fr[i] * Ar[k * n + j];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int j = 0; j < n; ++j) src[j] = j;
+    for (int k = n - 1; k >= 0; --k) {
+      const int q = perm[k];
+      const int t = src[k];
+      src[k] = src[q];
+      src[q] = t;
+    }
+    if (s_flag) status[D.patch] = 1;
+  }
+  __syncthreads();
+  T* o = out + D.ooff;
+  for (int i = wave; i < D.keep; i += nw)
+    for (int q = lane; q < D.ld_out; q += WAVE) {
+      double v = 0.0;
+      if constexpr (CPLX) {
+        if (q < n)
+          v = Ar[i * n + src[q]] * scl[q];
+        else if (q >= D.ldh && q - D.ldh < n)
+          v = Ai[i * n + src[q - D.ldh]] * scl[q - D.ldh];
+      } else {
+        if (q < n) v = Ar[i * n + src[q]] * scl[q];
+      }
+      o[int64_t(i) * D.ld_out + q] = T(v);
     }
 }
 
@@ -1623,21 +1780,50 @@ void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int ma
   launch_fold<float>(st, count, d, max_nu, max_npr, ns_of, nu_of, desc, dstride, out);
 }
 
-void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+size_t gj_lds_kernel_bytes(int max_n, bool cplx) {
+  const size_t nn = size_t(max_n) * max_n;
+  return ((cplx ? 2 : 1) * (nn + max_n) + max_n) * sizeof(double) + 2 * size_t(max_n) * sizeof(int);
+}
+
+template <typename T>
+static void gj_lds_launch(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                          T* out, int32_t* status) {
+  if (count == 0) return;
+  const size_t lds = gj_lds_kernel_bytes(max_n, cplx);
+  if (cplx) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::gj_lds_kernel<T, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    hipLaunchKernelGGL((dev::gj_lds_kernel<T, true>), dim3(count), dim3(256), lds, st, desc, W, out, status);
+  } else {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::gj_lds_kernel<T, false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    hipLaunchKernelGGL((dev::gj_lds_kernel<T, false>), dim3(count), dim3(256), lds, st, desc, W, out, status);
+  }
+}
+void k_gj_lds_f64(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                  double* out, int32_t* status) {
+  gj_lds_launch<double>(st, cplx, count, max_n, desc, W, out, status);
+}
+void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                  float* out, int32_t* status) {
+  gj_lds_launch<float>(st, cplx, count, max_n, desc, W, out, status);
+}
+
+void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes, int max_ns,
                                int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
                                const double* wkk, const GjDesc* desc, double* W, double* out) {
   if (count == 0) return;
   const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (4 * int64_t(max_nr) * max_nr + 255) / 256));
   hipLaunchKernelGGL(dev::form_reduced_blocks_kernel<double>, dim3(count * (tb.nblk + 2), gx), dim3(256), 0, st, tb,
-                     d, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
+                     d, cplanes, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
 }
-void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int max_ns,
+void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes, int max_ns,
                                int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
                                const double* wkk, const GjDesc* desc, double* W, float* out) {
   if (count == 0) return;
   const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (4 * int64_t(max_nr) * max_nr + 255) / 256));
   hipLaunchKernelGGL(dev::form_reduced_blocks_kernel<float>, dim3(count * (tb.nblk + 2), gx), dim3(256), 0, st, tb, d,
-                     max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
+                     cplanes, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
 }
 
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d) {
