@@ -1158,7 +1158,7 @@ __global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr,
 // y = X b with X stored column by column (X[i][j] at j*ld + i, ld = inv_ld(n)).
 // Block (bx, by) sums columns [by*GEMV_COLS, ...) for rows [bx*256, ...) into
 // part[by][i]; dense_gemv_reduce adds the column chunks in order.
-constexpr int GEMV_COLS = 1024;
+constexpr int GEMV_COLS = 64;  // column chunk per workgroup: about 85 workgroups for 1,047 unknowns
 __global__ void __launch_bounds__(256) dense_gemv_part_kernel(int n, const double* __restrict__ Xt,
                                                               const double* __restrict__ b,
                                                               double* __restrict__ part) {
