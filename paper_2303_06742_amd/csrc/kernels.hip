@@ -871,8 +871,11 @@ __device__ inline T bld1(__amdgpu_buffer_rsrc_t rs, int voff) {
 
 template <typename V, bool NTL>
 __device__ inline V bld16(__amdgpu_buffer_rsrc_t rs, int voff, int soff) {
-  static_assert(sizeof(V) == 16, "16-byte loads");
-  return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, NTL ? 2 : 0));
+  static_assert(sizeof(V) == 16 || sizeof(V) == 8, "16- or 8-byte loads");
+  if constexpr (sizeof(V) == 16)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, soff, NTL ? 2 : 0));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, soff, NTL ? 2 : 0));
 }
 
 template <typename T>
@@ -1722,9 +1725,18 @@ static void red_layout(int max_nr, int R, int* th, int* W) {
   }
 }
 
+// rows per thread of the reduced patch GEMV: two (16-byte FP64 or 8-byte FP32 loads); for
+// FP32, STGMG_RED_R=4 selects four rows (16-byte loads), measured 6% slower on the 256^2
+// dG(2) workload (0.884 ms against 0.834 ms per finest-level launch)
+static int red_rows(bool fp32) {
+  if (const char* e = std::getenv("STGMG_RED_R"))
+    if (fp32 && std::atoi(e) == 4) return 4;
+  return 2;
+}
+
 int patch_apply_red_threads(int max_nr, bool fp32) {
   int th, W;
-  red_layout(max_nr, fp32 ? 4 : 2, &th, &W);
+  red_layout(max_nr, red_rows(fp32), &th, &W);
   return th;
 }
 
@@ -1734,9 +1746,9 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
                        const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int32_t* pnu, const int64_t* ioff, const T* inv, const double* r, double* y) {
   if (npatch == 0) return;
-  constexpr int R = sizeof(T) == 4 ? 4 : 2;
+  const int rr = red_rows(sizeof(T) == 4);
   int th, W;
-  red_layout(max_nr, R, &th, &W);
+  red_layout(max_nr, rr, &th, &W);
   bool ntl = true;
   if (const char* e = std::getenv("STGMG_RED_NT")) ntl = std::atoi(e) != 0;
   // chunks of 16 patches per XCD: measured best of {off, 16, 64, 256, 1024, contiguous} on the
@@ -1744,12 +1756,19 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   int xc = 16;
   if (const char* e = std::getenv("STGMG_XCD_CHUNK")) xc = std::atoi(e);  // tuning: 0 = round-robin
   const size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
-  if (ntl)
-    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, true>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff,
-                       pdof, tpos, pnu, ioff, inv, r, y);
-  else
-    hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, R, false>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff,
-                       pdof, tpos, pnu, ioff, inv, r, y);
+#define STGMG_RED(RR, NT)                                                                                       \
+  hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, RR, NT>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff, \
+                     pdof, tpos, pnu, ioff, inv, r, y)
+  if constexpr (sizeof(T) == 4) {
+    if (rr == 4) {
+      if (ntl) STGMG_RED(4, true);
+      else STGMG_RED(4, false);
+      return;
+    }
+  }
+  if (ntl) STGMG_RED(2, true);
+  else STGMG_RED(2, false);
+#undef STGMG_RED
 }
 
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
