@@ -1,8 +1,8 @@
 """Tensor-product Lagrange elements and the cell/face integrals of the forms.
 
 Paper, Sec. 2 (Def:VhQh, Eq:DefVhQh): V_h = continuous Q_r^d for u and v,
-Q_h = continuous Q_{r-1} for p (Taylor-Hood), on a mesh of axis-parallel
-squares/cubes.  Sec. 3 (Def:ACB, Def:ab) gives the forms
+Q_h = continuous Q_{r-1} for p (Taylor-Hood) or the broken space P_{r-1}^disc,
+on a mesh of axis-parallel squares/cubes.  Sec. 3 (Def:ACB, Def:ab) gives the forms
 
     A_gamma(w, chi) = <C eps(w), eps(chi)> - <C eps(w) n, chi>_G + a_gamma(w, chi)
     a_gamma(w, chi) = -<w, C eps(chi) n>_G + gamma_a/h_F <w, chi>_G
@@ -13,6 +13,15 @@ squares/cubes.  Sec. 3 (Def:ACB, Def:ab) gives the forms
 with C eps(w) = 2 mu eps(w) + lambda div(w) I (isotropic), G = the Dirichlet
 boundary (all of the boundary here), gamma_a = 5e4 r (r+1), gamma_b = r(r-1)/2
 and, on a boundary face, h_F = |K|_d, the d-dimensional measure of the cell.
+
+For Q_h = P_{r-1}^disc, B_gamma is the symmetric interior penalty form of Def:B
+(second option): the volume term per cell, and on every face F (interior and
+boundary) -<{K grad q} . n, [psi]>_F - <[q], {K grad psi} . n>_F
++ gamma/h_F <[q], [psi]>_F with {w} = (w+ + w-)/2, [w] = w+ - w- and n the unit
+normal pointing out of K+ (on a boundary face {w} = [w] = w|K), gamma = gamma_b,
+h_F = (|K+|_d + |K-|_d)/2 (= |K|_d on this uniform mesh), and no separate
+b_gamma term (N^B omitted, Problem 4.1).  On a boundary face this is the same
+expression as the continuous-pressure boundary terms.
 
 Everything here works on one reference cell [0, h]^d: basis functions are
 evaluated at Gauss points and the integrals are sums over those points.  The
@@ -77,6 +86,36 @@ def scalar_basis(p, d, pts, h):
     return val, grad
 
 
+def pdisc_exponents(p, d):
+    """Exponents alpha (|alpha| <= p) of the P_p^disc basis: the lexicographic order of the
+    (p+1)^d lattice (x fastest), keeping total degree <= p."""
+    return [a for a in local_lattice(p, d) if sum(a) <= p]
+
+
+def pdisc_basis(p, d, pts, h):
+    """Values (nq, n) and physical gradients (nq, n, d) of the broken P_p basis on [0,h]^d at
+    reference points pts: the monomials prod_ax (xi_ax - 1/2)^alpha_ax, centred in the cell."""
+    pts = np.atleast_2d(pts)
+    z = pts - 0.5
+    ex = pdisc_exponents(p, d)
+    val = np.ones((pts.shape[0], len(ex)))
+    grad = np.ones((pts.shape[0], len(ex), d))
+    for j, a in enumerate(ex):
+        for ax in range(d):
+            val[:, j] *= z[:, ax] ** a[ax]
+            for g in range(d):
+                if g == ax:
+                    grad[:, j, g] *= a[ax] * z[:, ax] ** max(a[ax] - 1, 0) / h
+                else:
+                    grad[:, j, g] *= z[:, ax] ** a[ax]
+    return val, grad
+
+
+def pressure_basis(kind, r, d, pts, h):
+    """Pressure basis of the pair: 'cont' = Q_{r-1} (nodal), 'disc' = P_{r-1}^disc (monomials)."""
+    return scalar_basis(r - 1, d, pts, h) if kind == 'cont' else pdisc_basis(r - 1, d, pts, h)
+
+
 def cell_rule(n, d, h):
     """Tensor Gauss rule with n points per axis on [0,h]^d: reference points (nq,d), weights (nq,)."""
     x, w = gauss01(n)
@@ -126,18 +165,20 @@ class CellMatrices:
     """All cell and boundary-face matrices on the cell [0,h]^d for Q_r^d / Q_{r-1}.
 
     Matrices are indexed [test, trial].  K-dependent parts are returned for K=1
-    and scaled by the caller with the cell's permeability.
+    and scaled by the caller with the cell's permeability.  With pressure='disc' the
+    pressure basis is P_{r-1}^disc and Bint holds the interior-face parts of the SIPG form.
     """
 
-    def __init__(self, d, r, h, lam, mu, rho, alpha, gamma_a=None, gamma_b=None, nq=None):
+    def __init__(self, d, r, h, lam, mu, rho, alpha, gamma_a=None, gamma_b=None, nq=None, pressure='cont'):
         self.d, self.r, self.h = d, r, h
+        self.pressure = pressure
         self.gamma_a = 5e4 * r * (r + 1) if gamma_a is None else gamma_a
         self.gamma_b = 0.5 * r * (r - 1) if gamma_b is None else gamma_b
         self.hF = h ** d  # boundary face: the measure of its cell
         nq = r + 1 if nq is None else nq
         pts, wts = cell_rule(nq, d, h)
         sv, sg = scalar_basis(r, d, pts, h)
-        pv, pg = scalar_basis(r - 1, d, pts, h)
+        pv, pg = pressure_basis(pressure, r, d, pts, h)
         W, G = vector_fields(sv, sg, d)
         S = stress(G, lam, mu)
         eps = 0.5 * (G + np.swapaxes(G, -1, -2))
@@ -157,7 +198,7 @@ class CellMatrices:
             for side in (0, 1):
                 fp, fw, n = face_rule(nq, d, h, axis, side)
                 sv_, sg_ = scalar_basis(r, d, fp, h)
-                pv_, pg_ = scalar_basis(r - 1, d, fp, h)
+                pv_, pg_ = pressure_basis(pressure, r, d, fp, h)
                 W_, G_ = vector_fields(sv_, sg_, d)
                 S_ = stress(G_, lam, mu)
                 Sn = np.einsum('qiab,b->qia', S_, n)  # traction sigma(w) n
@@ -173,3 +214,27 @@ class CellMatrices:
                 self.Bface_K[(axis, side)] = -np.einsum('q,qs,qr->rs', fw, gn, pv_) - np.einsum('q,qs,qr->rs', fw, pv_, gn)
                 # gamma_b/h_F <q, psi>
                 self.Bface_pen[(axis, side)] = (self.gamma_b / self.hF) * np.einsum('q,qs,qr->rs', fw, pv_, pv_)
+        # interior faces (disc only): Bint[axis][(b, a)] = (T1, T2, Pen) for the face between
+        # K+ = the lower cell (its side-1 face, n = +e_axis) and K- = the upper cell; a, b = 0
+        # for K+, 1 for K-; the block of test functions on cell b and trial functions on cell
+        # a is K_a T1 + K_b T2 + Pen
+        self.Bint = {}
+        if pressure == 'disc':
+            sgn = (1.0, -1.0)
+            for axis in range(d):
+                fp1, fw, n = face_rule(nq, d, h, axis, 1)
+                fp0, _, _ = face_rule(nq, d, h, axis, 0)
+                v, g = [None, None], [None, None]
+                v[0], gr0 = pdisc_basis(r - 1, d, fp1, h)
+                v[1], gr1 = pdisc_basis(r - 1, d, fp0, h)
+                g[0], g[1] = gr0 @ n, gr1 @ n
+                blocks = {}
+                for b in (0, 1):
+                    for a in (0, 1):
+                        # -<{K grad q} . n, [psi]>: q on cell a, average weight 1/2, jump sign of b
+                        T1 = -0.5 * sgn[b] * np.einsum('q,qs,qr->rs', fw, g[a], v[b])
+                        # -<[q], {K grad psi} . n>
+                        T2 = -0.5 * sgn[a] * np.einsum('q,qs,qr->rs', fw, v[a], g[b])
+                        Pen = (self.gamma_b / self.hF) * sgn[a] * sgn[b] * np.einsum('q,qs,qr->rs', fw, v[a], v[b])
+                        blocks[(b, a)] = (T1, T2, Pen)
+                self.Bint[axis] = blocks

@@ -6,6 +6,9 @@
 * Prolongation = interpolation of the coarse finite element function at the
   fine nodes, per field, component and Gauss-Radau node (no coarsening in
   time); restriction = its transpose (Sec. 4, list of GMRES-GMG ingredients).
+  A discontinuous pressure is prolongated by the L2 projection onto each child
+  cell, which is exact: the coarse P_{r-1} piece restricted to a child is in
+  P_{r-1} there.
 * Patches P_l^m (Eq:DefPlm): the union of the cells that touch grid node
   xi_l^m ("vertex" patches: 4 cells in 2D / 8 in 3D inside, fewer at the
   boundary), or single cells ("cell" patches).  Z_l(P) = every degree of freedom
@@ -48,11 +51,41 @@ def interp_nd(p, Nc, d):
     return out.tocsr()
 
 
+def disc_prolongation(coarse, fine):
+    """P_{r-1}^disc prolongation: on each fine cell, the L2 projection of the parent cell's
+    basis functions onto the fine cell's basis."""
+    d, r, Nc = coarse.d, coarse.r, coarse.N
+    mf = fine.mesh
+    pts, wts = fem.cell_rule(r + 1, d, mf.h)
+    vf, _ = fine.pbasis(pts)
+    Mf = np.einsum('q,qr,qs->rs', wts, vf, vf)
+    nl = fine.nploc
+    rows, cols, vals = [], [], []
+    for cf in range(mf.ncells):
+        fi = np.array(mf.cell_index(cf))
+        ci = fi // 2
+        cc = 0
+        for ax in reversed(range(d)):
+            cc = cc * Nc + ci[ax]
+        # the fine points in the reference coordinates of the parent cell
+        vc, _ = coarse.pbasis(((fi % 2)[None, :] + pts) / 2.0)
+        blk = np.linalg.solve(Mf, np.einsum('q,qr,qs->rs', wts, vf, vc))
+        for i in range(nl):
+            for j in range(nl):
+                rows.append(cf * nl + i)
+                cols.append(cc * nl + j)
+                vals.append(blk[i, j])
+    out = sp.csr_matrix((vals, (rows, cols)), shape=(fine.nP, coarse.nP))
+    out.data[np.abs(out.data) < 1e-15] = 0.0
+    out.eliminate_zeros()
+    return out
+
+
 def prolongation(coarse, fine, k):
     """Space-time prolongation from level l-1 to l: block-diagonal over time nodes and fields."""
     d, r = coarse.d, coarse.r
     IQ = sp.kron(interp_nd(r, coarse.N, d), sp.eye(d))
-    IP = interp_nd(r - 1, coarse.N, d)
+    IP = interp_nd(r - 1, coarse.N, d) if coarse.pressure == 'cont' else disc_prolongation(coarse, fine)
     one = sp.block_diag([IQ, IQ, IP])
     return sp.block_diag([one] * (k + 1)).tocsr()
 
@@ -107,7 +140,7 @@ def level_params(prm, d, Nfine, N):
         K = coarsen_K(K, d, n)
         n //= 2
     return problem.Params(rho=prm.rho, lam=prm.lam, mu=prm.mu, alpha=prm.alpha, c0=prm.c0, K=K,
-                          gamma_a=prm.gamma_a, gamma_b=prm.gamma_b)
+                          gamma_a=prm.gamma_a, gamma_b=prm.gamma_b, pressure=prm.pressure)
 
 
 class Level:

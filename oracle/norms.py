@@ -20,7 +20,7 @@ class _Evaluator:
         pts, self.wts = fem.cell_rule(nq, d, m.h)
         sv, sg = fem.scalar_basis(r, d, pts, m.h)
         self.W, self.G = fem.vector_fields(sv, sg, d)
-        self.pv, _ = fem.scalar_basis(r - 1, d, pts, m.h)
+        self.pv, _ = blocks.pbasis(pts)
         origins = np.array([m.cell_origin(c) for c in range(m.ncells)])
         self.xs = (origins[:, None, :] + m.h * pts[None, :, :]).reshape(-1, d)
         self.nc, self.nq = m.ncells, len(self.wts)

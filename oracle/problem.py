@@ -4,7 +4,8 @@ system A_n X_n = F_n of Problem 4.1, on the unit square/cube.
 Unknown vector (Eq:DefXn): X_n = (V_1, U_1, P_1, ..., V_{k+1}, U_{k+1}, P_{k+1}),
 time node outermost.  Inside one time node: V and U are node-major over the
 lexicographic Q_r lattice (x fastest), components interleaved (d*node + c); P
-is over the lexicographic Q_{r-1} lattice.
+is over the lexicographic Q_{r-1} lattice (Taylor-Hood), or cell-major with the
+P_{r-1}^disc basis of each cell (cell * n_loc + j) for the discontinuous pair.
 
 Block structure (Problem 3.1 tested with chi_b, rows = (u-eq, v-eq, p-eq),
 columns = (V, U, P); the u-equation multiplied by rho as noted after
@@ -36,10 +37,13 @@ from . import fem, timedg
 class Params:
     """Material and discretisation parameters (Sec. 1, Eq:HPS; Sec. 3)."""
 
-    def __init__(self, rho=1.0, lam=1.0, mu=1.0, alpha=0.9, c0=0.01, K=1.0, gamma_a=None, gamma_b=None):
+    def __init__(self, rho=1.0, lam=1.0, mu=1.0, alpha=0.9, c0=0.01, K=1.0, gamma_a=None, gamma_b=None,
+                 pressure='cont'):
         self.rho, self.lam, self.mu, self.alpha, self.c0 = rho, lam, mu, alpha, c0
         self.K = K  # scalar, or array of per-cell values (lexicographic, x fastest)
         self.gamma_a, self.gamma_b = gamma_a, gamma_b
+        assert pressure in ('cont', 'disc')
+        self.pressure = pressure  # Q_h of Eq:DefVhQh: 'cont' (Q_{r-1}) or 'disc' (P_{r-1}^disc)
 
 
 def lame_from_young(E, nu):
@@ -99,6 +103,11 @@ class Mesh:
     def cell_origin(self, c):
         return np.array(self.cell_index(c), dtype=float) * self.h
 
+    def interior_faces(self, axis):
+        """(lower cell, upper cell) pairs of the interior faces normal to axis."""
+        st = self.N ** axis
+        return [(c, c + st) for c in range(self.ncells) if self.cell_index(c)[axis] < self.N - 1]
+
 
 def vec_dofs(sdofs, d):
     """Scalar node numbers -> interleaved vector dof numbers d*node + c (local order d*a + c)."""
@@ -119,16 +128,22 @@ class SpaceBlocks:
         self.d, self.N, self.r, self.prm = d, N, r, prm
         self.mesh = Mesh(d, N)
         m = self.mesh
+        self.pressure = prm.pressure
         self.nQ = m.lattice_size(r)
-        self.nP = m.lattice_size(r - 1)
+        self.nploc = len(fem.pdisc_exponents(r - 1, d)) if self.pressure == 'disc' else r ** d
+        self.nP = m.lattice_size(r - 1) if self.pressure == 'cont' else m.ncells * self.nploc
         self.nv = d * self.nQ
         self.ns = 2 * self.nv + self.nP
-        cm = fem.CellMatrices(d, r, m.h, prm.lam, prm.mu, prm.rho, prm.alpha, prm.gamma_a, prm.gamma_b)
+        cm = fem.CellMatrices(d, r, m.h, prm.lam, prm.mu, prm.rho, prm.alpha, prm.gamma_a, prm.gamma_b,
+                              pressure=self.pressure)
         self.cm = cm
         Kc = np.broadcast_to(np.asarray(prm.K, dtype=float), (m.ncells,)).copy()
         self.Kcell = Kc
         qd = m.cell_dofs(r)
-        pd = m.cell_dofs(r - 1)
+        if self.pressure == 'cont':
+            pd = m.cell_dofs(r - 1)
+        else:
+            pd = np.arange(self.nP, dtype=np.int64).reshape(m.ncells, self.nploc)
         vd = vec_dofs(qd, d)
         self.qdofs, self.pdofs, self.vdofs = qd, pd, vd
         nc = m.ncells
@@ -147,11 +162,25 @@ class SpaceBlocks:
             A = A + _scatter(vd[fc], vd[fc], Af, (self.nv, self.nv))
             C = C + _scatter(pd[fc], vd[fc], Cf, (self.nP, self.nv))
             B = B + _scatter(pd[fc], pd[fc], Bf, (self.nP, self.nP))
+        if self.pressure == 'disc':
+            # SIPG terms of the interior faces (Def:B, second option)
+            for axis in range(d):
+                pairs = np.array(m.interior_faces(axis), dtype=np.int64).reshape(-1, 2)
+                if len(pairs) == 0:
+                    continue
+                for (b, a), (T1, T2, Pen) in cm.Bint[axis].items():
+                    cb, ca = pairs[:, b], pairs[:, a]
+                    blk = Kc[ca][:, None, None] * T1 + Kc[cb][:, None, None] * T2 + Pen
+                    B = B + _scatter(pd[cb], pd[ca], blk, (self.nP, self.nP))
         self.A, self.C, self.B = A.tocsr(), C.tocsr(), B.tocsr()
         Z = None
         c0 = prm.c0
         self.MM = sp.bmat([[Z, self.Mrho, Z], [self.Mrho, Z, Z], [Z, Z, c0 * self.Mp]], format='csr')
         self.KK = sp.bmat([[-self.Mrho, Z, Z], [Z, self.A, self.C.T], [-self.C, Z, self.B]], format='csr')
+
+    def pbasis(self, pts):
+        """Pressure basis values and gradients at reference points of a cell of this mesh."""
+        return fem.pressure_basis(self.pressure, self.r, self.d, pts, self.mesh.h)
 
 
 def slab_operator(blocks, k, tau):
@@ -227,11 +256,22 @@ class ExactSolution:
 
 
 def interpolate(blocks, sol, t):
-    """Nodal interpolant (V, U, P) of the prescribed solution at time t (one time-node block)."""
+    """Nodal interpolant (V, U, P) of the prescribed solution at time t (one time-node block);
+    for the discontinuous pressure, P is the L2 projection onto P_{r-1} of each cell
+    ((r+2)^d Gauss points)."""
     m = blocks.mesh
     xq = m.node_coords(blocks.r)
-    xp = m.node_coords(blocks.r - 1)
-    return np.concatenate([sol.v(xq, t).reshape(-1), sol.u(xq, t).reshape(-1), sol.p(xp, t)])
+    if blocks.pressure == 'cont':
+        P = sol.p(m.node_coords(blocks.r - 1), t)
+    else:
+        pts, wts = fem.cell_rule(blocks.r + 2, blocks.d, m.h)
+        pv, _ = blocks.pbasis(pts)
+        Mc = np.einsum('q,qr,qs->rs', wts, pv, pv)
+        origins = np.array([m.cell_origin(c) for c in range(m.ncells)])
+        xs = (origins[:, None, :] + m.h * pts[None, :, :]).reshape(-1, blocks.d)
+        pq = sol.p(xs, t).reshape(m.ncells, len(wts))
+        P = np.linalg.solve(Mc, np.einsum('q,qr,cq->rc', wts, pv, pq)).T.reshape(-1)
+    return np.concatenate([sol.v(xq, t).reshape(-1), sol.u(xq, t).reshape(-1), P])
 
 
 def source_vector(blocks, sol, t, nq=None):
@@ -244,7 +284,7 @@ def source_vector(blocks, sol, t, nq=None):
     nq = r + 2 if nq is None else nq
     pts, wts = fem.cell_rule(nq, d, h)
     sv, _ = fem.scalar_basis(r, d, pts, h)
-    pv, _ = fem.scalar_basis(r - 1, d, pts, h)
+    pv, _ = blocks.pbasis(pts)
     origins = np.array([m.cell_origin(c) for c in range(m.ncells)])
     xs = (origins[:, None, :] + h * pts[None, :, :]).reshape(-1, d)
     fv = sol.f(xs, t).reshape(m.ncells, len(wts), d)
@@ -264,7 +304,7 @@ def source_vector(blocks, sol, t, nq=None):
             xs = (origins[cells][:, None, :] + h * fp[None, :, :]).reshape(-1, d)
             nf = len(fw)
             sv_, sg_ = fem.scalar_basis(r, d, fp, h)
-            pv_, pg_ = fem.scalar_basis(r - 1, d, fp, h)
+            pv_, pg_ = blocks.pbasis(fp)
             W_, G_ = fem.vector_fields(sv_, sg_, d)
             Sn = np.einsum('qiab,b->qia', fem.stress(G_, prm.lam, prm.mu), n)
             uD = sol.u(xs, t).reshape(len(cells), nf, d)
