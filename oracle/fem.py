@@ -32,7 +32,6 @@ import itertools
 
 import numpy as np
 from numpy.polynomial import legendre as L
-from numpy.polynomial import polynomial as Pw
 
 
 def gauss01(n):
@@ -41,22 +40,25 @@ def gauss01(n):
     return 0.5 * (x + 1.0), 0.5 * w
 
 
-def lagrange_1d(p):
-    """Coefficients of the degree-p Lagrange polynomials on equispaced nodes of [0, 1]."""
-    nodes = np.linspace(0.0, 1.0, p + 1)
-    out = []
-    for a in range(p + 1):
-        c = Pw.polyfromroots(np.delete(nodes, a)) if p > 0 else np.array([1.0])
-        out.append(c / Pw.polyval(nodes[a], c))
-    return out
-
-
 def basis_1d(p, xi):
-    """(values, derivatives) of the degree-p 1D basis at reference points xi; shape (len(xi), p+1)."""
-    polys = lagrange_1d(p)
+    """(values, derivatives) of the degree-p Lagrange basis on the equispaced nodes of [0, 1] at
+    reference points xi; shape (len(xi), p+1).  Evaluated in product form,
+    l_a(x) = prod_{b != a} (x - x_b)/(x_a - x_b), so that l_a is exactly 0 at every other node
+    (the stiff Nitsche penalty would amplify rounding noise there)."""
+    nodes = np.linspace(0.0, 1.0, p + 1)
     xi = np.asarray(xi, dtype=float)
-    v = np.stack([Pw.polyval(xi, c) for c in polys], axis=-1)
-    dv = np.stack([Pw.polyval(xi, Pw.polyder(c)) if p > 0 else 0.0 * xi for c in polys], axis=-1)
+    v = np.ones((len(xi), p + 1))
+    dv = np.zeros((len(xi), p + 1))
+    for a in range(p + 1):
+        others = [b for b in range(p + 1) if b != a]
+        for b in others:
+            v[:, a] *= (xi - nodes[b]) / (nodes[a] - nodes[b])
+        for c in others:  # derivative: one factor differentiated at a time
+            t = np.full(len(xi), 1.0 / (nodes[a] - nodes[c]))
+            for b in others:
+                if b != c:
+                    t *= (xi - nodes[b]) / (nodes[a] - nodes[b])
+            dv[:, a] += t
     return v, dv
 
 

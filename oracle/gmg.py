@@ -38,7 +38,9 @@ def interp_1d(p, Nc):
         v, _ = fem.basis_1d(p, [xi])
         for a in range(p + 1):
             M[i, p * c + a] += v[0, a]
-    M[np.abs(M) < 1e-15] = 0.0
+    # a coarse basis function at a coarse node of another index is exactly 0; the
+    # evaluation leaves rounding noise (up to ~1e-14 at r = 4)
+    M[np.abs(M) < 1e-12] = 0.0
     return sp.csr_matrix(M)
 
 
@@ -76,7 +78,9 @@ def disc_prolongation(coarse, fine):
                 cols.append(cc * nl + j)
                 vals.append(blk[i, j])
     out = sp.csr_matrix((vals, (rows, cols)), shape=(fine.nP, coarse.nP))
-    out.data[np.abs(out.data) < 1e-15] = 0.0
+    # coefficients of fine functions absent from the parent's expansion are zero up to the
+    # rounding of the solve with the (monomial) cell mass
+    out.data[np.abs(out.data) < 1e-12] = 0.0
     out.eliminate_zeros()
     return out
 
