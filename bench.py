@@ -70,7 +70,7 @@ def measured_read_peak(torch):
 
 def configs():
     from paper_2303_06742_amd import workloads as W
-    return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3, 'c3v': W.C3V}
+    return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3, 'c3v': W.C3V, 'c2d': W.C2D}
 
 
 def cpu_baseline(cfg, sample_levels):
@@ -210,7 +210,7 @@ def main():
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=5)
     ap.add_argument('--warmup', type=int, default=1)
-    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3', 'c3v', 'batch', 'serve'])
+    ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3', 'c3v', 'c2d', 'batch', 'serve'])
     ap.add_argument('--batch-count', type=int, default=64)
     ap.add_argument('--serve-count', type=int, default=48)
     ap.add_argument('--serve-rates', type=float, nargs='*', default=[0.5, 0.9])
@@ -306,7 +306,7 @@ def main():
         'dtype': 'f64' if args.precision == 'fp64' else 'f64+f32-smoother',
         'data': 'synthetic',
         'config': {'workload': cfg.name, 'dim': cfg.dim, 'cells': f"{cfg.fine_cells}^{cfg.dim}",
-                   'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'smoother': args.precision,
+                   'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'pressure': cfg.pressure, 'smoother': args.precision,
                    'tau': cfg.tau, 'unknowns': n, 'nnz': q['nnz'], 'patches': q['patches'], 'rtol': cfg.rtol,
                    'restart': cfg.restart},
         'vcycle_dof_per_s': n * sum(iters) / elapsed,

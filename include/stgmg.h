@@ -57,6 +57,11 @@ typedef int32_t stgmg_status;
 #define STGMG_FP64 0 /* patch inverses stored and applied in FP64 */
 #define STGMG_FP32 1 /* patch inverses computed in FP64, stored and applied in FP32 */
 
+/* pressure space Q_h of Def:VhQh / Eq:DefVhQh */
+#define STGMG_PRESSURE_CONT 0 /* continuous Q_{r-1} (Taylor-Hood), B_gamma with Nitsche terms (Def:B, first option) */
+#define STGMG_PRESSURE_DISC 1 /* broken P_{r-1}^disc: per cell the monomials prod (xi - 1/2)^a, |a| <= r-1, cell-major;
+                                 B_gamma the symmetric interior penalty form (Def:B, second option) */
+
 typedef struct stgmg_handle stgmg_handle;
 
 /* Problem and solver parameters.  Fine level: coarse_cells << (levels-1) cells
@@ -65,7 +70,7 @@ typedef struct {
   int32_t dim;           /* 2 or 3 */
   int32_t coarse_cells;  /* cells per axis on level 0 (>= 1) */
   int32_t levels;        /* number of levels L+1 >= 1 */
-  int32_t r;             /* displacement degree (Q_r^d); pressure Q_{r-1}; 2 <= r <= 4 */
+  int32_t r;             /* displacement degree (Q_r^d); pressure degree r-1 (see pressure); 2 <= r <= 4 */
   int32_t k;             /* dG(k) in time, 0 <= k <= 3 */
   int32_t patch;         /* STGMG_PATCH_CELL or STGMG_PATCH_VERTEX */
   int32_t smoother_prec; /* STGMG_FP64 or STGMG_FP32 */
@@ -89,6 +94,7 @@ typedef struct {
                                patch nodes, KK_pV (rho M)^{-1}, and one Schur complement inverse
                                of n_P/(k+1) - nU rows per eigenvalue (about 3x fewer again).
                             Default of the Python workloads: 2. */
+  int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
 } stgmg_params;
 
 typedef struct {

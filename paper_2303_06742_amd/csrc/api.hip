@@ -241,6 +241,8 @@ void check_params(const stgmg_params* p) {
   if (Nf > 4096) throw ApiError(STGMG_ERR_UNSUPPORTED, "grid too fine");
   if (!p->K_cells && !(p->K > 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "K must be > 0");
   if (p->time_blocks < 0 || p->time_blocks > 2) throw ApiError(STGMG_ERR_INVALID_ARG, "time_blocks must be 0, 1 or 2");
+  if (p->pressure != STGMG_PRESSURE_CONT && p->pressure != STGMG_PRESSURE_DISC)
+    throw ApiError(STGMG_ERR_INVALID_ARG, "unknown pressure space");
 }
 
 int host_threads() {
@@ -429,7 +431,7 @@ void build(stgmg_handle* h) {
   for (int l = 0; l <= L; ++l) {
     LevelHost H;
     stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1, true, true,
-                          l == 0 || !h->tb};
+                          l == 0 || !h->tb, p.pressure == STGMG_PRESSURE_DISC};
     stgmg::build_level(o, h->mat, Kl[l], H, nth);
     LevelDev& D = h->lv[l];
     D.N = H.N;
@@ -815,6 +817,8 @@ void build(stgmg_handle* h) {
     prev.N = H.N;
     prev.n1 = H.n1;
     prev.n1p = H.n1p;
+    prev.disc = H.disc;
+    prev.nlp = H.nlp;
     prev.nQ = H.nQ;
     prev.nP = H.nP;
     prev.nv = H.nv;
@@ -824,7 +828,7 @@ void build(stgmg_handle* h) {
   h->e_dev.upload(h->T.e, h->st, ctr);
   {
     std::vector<double> xq, wq, bq, bp;
-    stgmg::source_tables(d, p.r, xq, wq, bq, bp);
+    stgmg::source_tables(d, p.r, xq, wq, bq, bp, p.pressure == STGMG_PRESSURE_DISC);
     h->src_xq.upload(xq, h->st, ctr);
     h->src_wq.upload(wq, h->st, ctr);
     h->src_bq.upload(bq, h->st, ctr);
@@ -1106,6 +1110,8 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
       for (int x = 0; x < F.d; ++x) a.nq *= F.r + 2;
       a.n1 = F.n1;
       a.n1p = F.n1p;
+      a.disc = F.disc ? 1 : 0;
+      a.nlp = F.nlp;
       a.nv = F.nv;
       a.ns = F.ns;
       a.h = 1.0 / F.N;
@@ -1261,7 +1267,8 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       for (int a = 0; a < B.nblk; ++a) (B.is_complex[a] ? ncplx : nreal)++;
     }
     for (int l = 0; l <= L; ++l) {
-      const stgmg::LevelSizes S = stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch);
+      const stgmg::LevelSizes S =
+          stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch, p.pressure == STGMG_PRESSURE_DISC);
       const int64_t n = S.n;
       // factored operator: spatial MM and KK; vectors b, d, r
       res += 2 * (S.ns + 1) * 8 + (S.nnzMM + S.nnzKK) * 12 + 3 * n * 8;

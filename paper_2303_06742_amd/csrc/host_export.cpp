@@ -9,9 +9,14 @@ namespace {
 stgmg::LevelHost g_level;
 stgmg::Csr g_P;
 std::vector<double> g_vec;
+bool g_disc = false;  // pressure pair of the following builds
 }  // namespace
 
 extern "C" {
+
+// Pressure pair of the following builds, prolongations and sizes: 0 = Q_{r-1} (Taylor-Hood),
+// 1 = P_{r-1}^disc with the interior penalty form.
+void stgmg_host_set_pressure(int disc) { g_disc = disc != 0; }
 
 // Build one level; returns n (space-time unknowns) or -1 on error.
 long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double tau, double omega, double rho,
@@ -20,7 +25,7 @@ long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double ta
     long long nc = 1;
     for (int a = 0; a < d; ++a) nc *= N;
     std::vector<double> K(Kcell, Kcell + nc);
-    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true, true};
+    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true, true, g_disc};
     stgmg::Material m{rho, lambda, mu, alpha, c0};
     g_level = stgmg::LevelHost();
     stgmg::build_level(o, m, K, g_level, 4);
@@ -65,8 +70,8 @@ long long stgmg_host_prolongation(int d, int r, int k, int Nc) {
     Kc.assign(ncc, 1.0);
     Kf.assign(ncf, 1.0);
     stgmg::Material m{1, 1, 1, 1, 1};
-    stgmg::build_level({d, r, k, Nc, 0, 0.1, 0.7, false, false}, m, Kc, C, 4);
-    stgmg::build_level({d, r, k, 2 * Nc, 0, 0.1, 0.7, false, false}, m, Kf, F, 4);
+    stgmg::build_level({d, r, k, Nc, 0, 0.1, 0.7, false, false, false, true, g_disc}, m, Kc, C, 4);
+    stgmg::build_level({d, r, k, 2 * Nc, 0, 0.1, 0.7, false, false, false, true, g_disc}, m, Kf, F, 4);
     g_P = stgmg::build_prolongation(C, F);
     return (long long)g_P.col.size();
   } catch (...) {
@@ -122,7 +127,7 @@ int stgmg_host_time_blocks(int k, double tau, double* lam, int* cplx, double* ti
 // Closed-form sizes: out = {n, nnzA, nnzMM, nnzP, npatch, sum_np, sum_np_ld, max_np, nnzKK,
 //                          sum_red_fixed, sum_nr_ldr, max_nr, max_nn}
 void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out) {
-  stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind);
+  stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind, g_disc);
   out[0] = S.n;
   out[1] = S.nnzA;
   out[2] = S.nnzMM;

@@ -1,7 +1,8 @@
 // Host construction of the slab operators, patch tables and transfers.
 //
 // Discretisation (paper Sec. 2-4): dG(k) in time with the Lagrange basis at the
-// right Gauss-Radau points (Eq:GF, Eq:TimeExp), Taylor-Hood Q_r^d / Q_{r-1} in
+// right Gauss-Radau points (Eq:GF, Eq:TimeExp), Taylor-Hood Q_r^d / Q_{r-1} or
+// Q_r^d / P_{r-1}^disc with the symmetric interior penalty form of Def:B in
 // space on axis-parallel square/cube cells (Def:VhQh), Nitsche boundary terms
 // (Def:ACB, Def:ab) with gamma_a = 5e4 r(r+1), gamma_b = r(r-1)/2 and
 // h_F = |K|_d on boundary faces.  The slab matrix of Problem 4.1 (v-form of
@@ -21,6 +22,23 @@
 #include <thread>
 
 namespace stgmg {
+
+std::vector<std::array<int, 3>> pdisc_exponents(int p, int d) {
+  std::vector<std::array<int, 3>> out;
+  int n = 1;
+  for (int a = 0; a < d; ++a) n *= p + 1;
+  for (int i = 0; i < n; ++i) {
+    std::array<int, 3> e = {0, 0, 0};
+    int rem = i, deg = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      e[ax] = rem % (p + 1);
+      rem /= p + 1;
+      deg += e[ax];
+    }
+    if (deg <= p) out.push_back(e);
+  }
+  return out;
+}
 
 namespace {
 
@@ -97,6 +115,31 @@ void tabulate(int p, int d, const double* xi, double h, Tab& t) {
       for (int ax = 0; ax < d; ++ax)
         t.g[a * 3 + g] *= (g == ax) ? d1[ax][idx[ax]] / h : v1[ax][idx[ax]];
   }
+}
+
+// P_p^disc basis (pdisc_exponents) on [0,h]^d at a reference point: values and physical gradients.
+void tabulate_pdisc(int p, int d, const double* xi, double h, Tab& t) {
+  const auto ex = pdisc_exponents(p, d);
+  t.nl = int(ex.size());
+  t.v.assign(t.nl, 1.0);
+  t.g.assign(size_t(t.nl) * 3, 1.0);
+  for (int a = 0; a < t.nl; ++a) {
+    for (int ax = 0; ax < d; ++ax) {
+      const double z = xi[ax] - 0.5;
+      const int e = ex[a][ax];
+      const double pw = std::pow(z, e), dpw = e > 0 ? e * std::pow(z, e - 1) / h : 0.0;
+      t.v[a] *= pw;
+      for (int g = 0; g < d; ++g) t.g[a * 3 + g] *= (g == ax) ? dpw : pw;
+    }
+  }
+}
+
+// pressure basis of the pair: Q_{r-1} or P_{r-1}^disc
+void tabulate_p(bool disc, int r, int d, const double* xi, double h, Tab& t) {
+  if (disc)
+    tabulate_pdisc(r - 1, d, xi, h, t);
+  else
+    tabulate(r - 1, d, xi, h, t);
 }
 
 template <class F>
@@ -337,15 +380,17 @@ TimeBlocks make_time_blocks(const TimeConsts& Tc) {
 }
 
 // ------------------------------------------------------------- cell matrices
-CellMats make_cell_mats(int d, int r, double h, const Material& m) {
+CellMats make_cell_mats(int d, int r, double h, const Material& m, bool disc) {
   CellMats C;
   C.d = d;
   C.r = r;
+  C.disc = disc;
   int ns = 1, np = 1;
   for (int a = 0; a < d; ++a) {
     ns *= (r + 1);
     np *= r;
   }
+  if (disc) np = int(pdisc_exponents(r - 1, d).size());
   C.nls = ns;
   C.nlv = d * ns;
   C.nlp = np;
@@ -374,7 +419,7 @@ CellMats make_cell_mats(int d, int r, double h, const Material& m) {
       rem /= nq1;
     }
     tabulate(r, d, xi, h, s);
-    tabulate(r - 1, d, xi, h, p);
+    tabulate_p(disc, r, d, xi, h, p);
     for (int b = 0; b < ns; ++b)
       for (int a = 0; a < ns; ++a) {
         double mass = wq * s.v[a] * s.v[b];
@@ -430,7 +475,7 @@ CellMats make_cell_mats(int d, int r, double h, const Material& m) {
           rem /= nq1;
         }
         tabulate(r, d, xi, h, s);
-        tabulate(r - 1, d, xi, h, p);
+        tabulate_p(disc, r, d, xi, h, p);
         for (int b = 0; b < ns; ++b)
           for (int a = 0; a < ns; ++a) {
             double dna = 0.0, dnb = 0.0;
@@ -462,6 +507,49 @@ CellMats make_cell_mats(int d, int r, double h, const Material& m) {
         }
       }
     }
+  if (!disc) return C;
+  // interior faces normal to axis: K+ (lower cell) sees the face at xi_axis = 1, K- (upper
+  // cell) at xi_axis = 0, the same physical points; n = +e_axis; jump sign +1 on K+, -1 on K-
+  for (int axis = 0; axis < d; ++axis) {
+    for (int ba = 0; ba < 4; ++ba) {
+      C.BiT1[axis][ba].assign(size_t(np) * np, 0.0);
+      C.BiT2[axis][ba].assign(size_t(np) * np, 0.0);
+      C.BiPen[axis][ba].assign(size_t(np) * np, 0.0);
+    }
+    for (int q = 0; q < nqf; ++q) {
+      double xp[3] = {0, 0, 0}, xm[3] = {0, 0, 0}, wq = 1.0;
+      int rem = q;
+      for (int ax = 0; ax < d; ++ax) {
+        if (ax == axis) {
+          xp[ax] = 1.0;
+          xm[ax] = 0.0;
+          continue;
+        }
+        xp[ax] = xm[ax] = gx[rem % nq1];
+        wq *= gw[rem % nq1] * h;
+        rem /= nq1;
+      }
+      Tab side[2];
+      tabulate_pdisc(r - 1, d, xp, h, side[0]);
+      tabulate_pdisc(r - 1, d, xm, h, side[1]);
+      const double sgn[2] = {1.0, -1.0};
+      for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) {
+          auto& T1 = C.BiT1[axis][2 * b + a];
+          auto& T2 = C.BiT2[axis][2 * b + a];
+          auto& Pn = C.BiPen[axis][2 * b + a];
+          for (int t = 0; t < np; ++t)      // test function on cell b
+            for (int u = 0; u < np; ++u) {  // trial function on cell a
+              const double qv = side[a].v[u], qn = side[a].g[u * 3 + axis];
+              const double pv = side[b].v[t], pn = side[b].g[t * 3 + axis];
+              // -<{K grad q} . n, [psi]>, -<[q], {K grad psi} . n>, gamma/h_F <[q], [psi]>
+              T1[size_t(t) * np + u] += wq * (-0.5 * qn * sgn[b] * pv);
+              T2[size_t(t) * np + u] += wq * (-0.5 * sgn[a] * qv * pn);
+              Pn[size_t(t) * np + u] += wq * C.gamma_b / C.hF * sgn[a] * qv * sgn[b] * pv;
+            }
+        }
+    }
+  }
   return C;
 }
 
@@ -523,6 +611,69 @@ struct RowBuilder {
         v[w++] = v[i];
     }
     v.resize(w);
+  }
+
+  // p-equation row of pressure dof j (cell j / nlp, local function j % nlp) for the broken
+  // pressure: -C on V, c0 M_p and the SIPG form (volume, boundary faces, interior faces with
+  // the neighbour's functions as further columns).
+  void disc_prow(int64_t j, std::vector<Entry>& mm, std::vector<Entry>& kk) const {
+    const int d = o->d, r = o->r, N = o->N;
+    const int64_t nv = L->nv;
+    const int nlv = cm->nlv, nls = cm->nls, nlp = cm->nlp;
+    const int64_t cell = j / nlp;
+    const int st = int(j % nlp);
+    int cc[3] = {0, 0, 0};
+    int64_t rem = cell;
+    for (int ax = 0; ax < d; ++ax) {
+      cc[ax] = int(rem % N);
+      rem /= N;
+    }
+    const double K = L->Kcell[cell];
+    int faces[6], nf = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      if (cc[ax] == 0) faces[nf++] = 2 * ax;
+      if (cc[ax] == N - 1) faces[nf++] = 2 * ax + 1;
+    }
+    for (int a = 0; a < nls; ++a) {
+      const int64_t gn = gnode(cc, a, r, L->n1);
+      for (int c = 0; c < d; ++c) {
+        const int at = d * a + c;
+        double cv = cm->Cvol[size_t(st) * nlv + at];
+        for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(st) * nlv + at];
+        kk.push_back({d * gn + c, -cv});
+      }
+    }
+    // own cell: volume, boundary faces, and the own-cell blocks of its interior faces
+    std::vector<double> own(nlp, 0.0);
+    for (int s = 0; s < nlp; ++s) {
+      double bv = K * cm->Bvol[size_t(st) * nlp + s];
+      for (int f = 0; f < nf; ++f)
+        bv += K * cm->BfaceK[faces[f]][size_t(st) * nlp + s] + cm->Bpen[faces[f]][size_t(st) * nlp + s];
+      own[s] = bv;
+    }
+    int64_t stride = 1;
+    for (int ax = 0; ax < d; ++ax) {
+      for (int side = 0; side < 2; ++side) {
+        // side 1: the upper neighbour exists, this cell is K+ (index 0); side 0: lower, this is K-
+        if (side == 1 ? cc[ax] == N - 1 : cc[ax] == 0) continue;
+        const int64_t nb = side == 1 ? cell + stride : cell - stride;
+        const int me = side == 1 ? 0 : 1, ot = 1 - me;
+        const double Kn = L->Kcell[nb];
+        const size_t bo = size_t(2 * me + ot), bs = size_t(2 * me + me);
+        for (int s = 0; s < nlp; ++s) {
+          const size_t e = size_t(st) * nlp + s;
+          own[s] += K * cm->BiT1[ax][bs][e] + K * cm->BiT2[ax][bs][e] + cm->BiPen[ax][bs][e];
+          kk.push_back({2 * nv + nb * nlp + s,
+                        Kn * cm->BiT1[ax][bo][e] + K * cm->BiT2[ax][bo][e] + cm->BiPen[ax][bo][e]});
+        }
+      }
+      stride *= N;
+    }
+    for (int s = 0; s < nlp; ++s) {
+      const int64_t gp = 2 * nv + cell * nlp + s;
+      mm.push_back({gp, m->c0 * cm->Mp[size_t(st) * nlp + s]});
+      kk.push_back({gp, own[s]});
+    }
   }
 
   // Spatial row i of MM and KK (sorted, merged).
@@ -591,10 +742,13 @@ struct RowBuilder {
             // (C^T)[i][s] = C(psi_i, xi_s): stored as Cvol[s][i]
             double cv = cm->Cvol[size_t(s) * nlv + bt];
             for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(s) * nlv + bt];
-            kk.push_back({2 * nv + gnode(cc, s, r - 1, L->n1p), cv});
+            const int64_t pc = L->disc ? cell * nlp + s : gnode(cc, s, r - 1, L->n1p);
+            kk.push_back({2 * nv + pc, cv});
           }
         }
       }
+    } else if (L->disc) {
+      disc_prow(i - 2 * nv, mm, kk);
     } else {
       const int64_t node = i - 2 * nv;
       int64_t g[3];
@@ -666,12 +820,19 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
     L.nQ *= L.n1;
     L.nP *= L.n1p;
   }
+  L.disc = o.disc;
+  int64_t ncells_l = 1;
+  for (int a = 0; a < d; ++a) ncells_l *= N;
+  if (o.disc) {
+    L.nlp = int(pdisc_exponents(r - 1, d).size());
+    L.nP = ncells_l * L.nlp;
+  }
   L.nv = d * L.nQ;
   L.ns = 2 * L.nv + L.nP;
   L.n = (k + 1) * L.ns;
   L.Kcell = Kcell;
   const double h = 1.0 / N;
-  CellMats cm = make_cell_mats(d, r, h, m);
+  CellMats cm = make_cell_mats(d, r, h, m, o.disc);
   TimeConsts T = make_time_consts(k, o.tau);
   RowBuilder rb{&o, &cm, &L, &m};
   const int64_t ns = L.ns;
@@ -860,11 +1021,13 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
   for (int64_t pi = 0; pi < L.npatch; ++pi) {
     int cmin[3], cmax[3];
     patch_box(pi, cmin, cmax);
-    int64_t q = 1, pp = 1;
+    int64_t q = 1, pp = 1, pc = 1;
     for (int ax = 0; ax < d; ++ax) {
       q *= int64_t(r) * (cmax[ax] + 1 - cmin[ax]) + 1;
       pp *= int64_t(r - 1) * (cmax[ax] + 1 - cmin[ax]) + 1;
+      pc *= cmax[ax] + 1 - cmin[ax];
     }
+    if (o.disc) pp = pc * L.nlp;
     L.poff[pi + 1] = L.poff[pi] + nt * (2 * d * q + pp);
   }
   L.pdof.resize(L.poff[L.npatch]);
@@ -891,10 +1054,20 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
                 int64_t node = x + L.n1 * (y + L.n1 * int64_t(z));
                 for (int c = 0; c < d; ++c) L.pdof[w++] = int32_t(off + field * L.nv + d * node + c);
               }
-        for (int z = lop[2]; z <= hip3[2]; ++z)
-          for (int y = lop[1]; y <= hip3[1]; ++y)
-            for (int x = lop[0]; x <= hip3[0]; ++x)
-              L.pdof[w++] = int32_t(off + 2 * L.nv + x + L.n1p * (y + L.n1p * int64_t(z)));
+        if (o.disc) {
+          // the pressure functions of the patch cells, cells in increasing order
+          for (int z = cmin[2]; z <= cmax[2]; ++z)
+            for (int y = cmin[1]; y <= cmax[1]; ++y)
+              for (int x = cmin[0]; x <= cmax[0]; ++x) {
+                const int64_t cell = x + int64_t(N) * (y + int64_t(N) * z);
+                for (int s = 0; s < L.nlp; ++s) L.pdof[w++] = int32_t(off + 2 * L.nv + cell * L.nlp + s);
+              }
+        } else {
+          for (int z = lop[2]; z <= hip3[2]; ++z)
+            for (int y = lop[1]; y <= hip3[1]; ++y)
+              for (int x = lop[0]; x <= hip3[0]; ++x)
+                L.pdof[w++] = int32_t(off + 2 * L.nv + x + L.n1p * (y + L.n1p * int64_t(z)));
+        }
       }
     }
   });
@@ -950,17 +1123,61 @@ int interp_weights_1d(int p, int Nc, int64_t g, int64_t* cols, double* w) {
 }
 }  // namespace
 
+namespace {
+// 1D coefficient of the coarse monomial (xi_c - 1/2)^b in the child monomial (xi_f - 1/2)^a
+// for the child at offset o (0: lower half, 1: upper half): xi_c - 1/2 = z/2 + (2o - 1)/4 with
+// z = xi_f - 1/2, so the coefficient is binom(b, a) 2^-a ((2o - 1)/4)^(b - a) for a <= b.
+double disc_child_coef(int o, int a, int b) {
+  if (a > b) return 0.0;
+  double binom = 1.0;
+  for (int i = 0; i < a; ++i) binom = binom * (b - i) / (i + 1);
+  return binom * std::ldexp(1.0, -a) * std::pow((2 * o - 1) * 0.25, b - a);
+}
+}  // namespace
+
 Csr build_prolongation(const LevelHost& C, const LevelHost& F, int nthreads) {
   const int d = F.d, r = F.r;
   Csr P;
   P.nrows = F.n;
   P.ncols = C.n;
   P.ptr.assign(F.n + 1, 0);
+  const auto pex = F.disc ? pdisc_exponents(r - 1, d) : std::vector<std::array<int, 3>>();
   // entries of one row (at most 3^d: the 1D weights have at most 3 nonzeros), columns ascending
   auto row_entries = [&](int64_t row, int64_t* cols, double* vals) {
     const int tn = int(row / F.ns);
     const int64_t s = row % F.ns;
     const int64_t coff = int64_t(tn) * C.ns;
+    if (F.disc && s >= 2 * F.nv) {
+      // broken pressure: the parent's functions restricted to the child, exactly
+      const int64_t j = s - 2 * F.nv, cf = j / F.nlp;
+      const auto& a = pex[j % F.nlp];
+      int64_t rem = cf, cc = 0, mul = 1;
+      int o[3] = {0, 0, 0};
+      for (int ax = 0; ax < d; ++ax) {
+        const int64_t c = rem % F.N;
+        rem /= F.N;
+        o[ax] = int(c % 2);
+        cc += mul * (c / 2);
+        mul *= C.N;
+      }
+      int cnt = 0;
+      for (int jb = 0; jb < C.nlp; ++jb) {
+        const auto& b = pex[jb];
+        bool ok = true;
+        double w = 1.0;
+        for (int ax = 0; ax < d; ++ax) {
+          if (a[ax] > b[ax]) ok = false;
+          else w *= disc_child_coef(o[ax], a[ax], b[ax]);
+        }
+        if (!ok) continue;
+        if (cols) {
+          cols[cnt] = coff + 2 * C.nv + cc * C.nlp + jb;
+          vals[cnt] = w;
+        }
+        ++cnt;
+      }
+      return cnt;
+    }
     int p, comp, stride;
     int64_t fnode, fn1, cn1, base_col;
     if (s < 2 * F.nv) {
@@ -1094,7 +1311,7 @@ int adj_cells(int64_t g, int p, int N) {
 }
 }  // namespace
 
-LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
+LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc) {
   LevelSizes S;
   const int64_t n1 = int64_t(r) * N + 1, n1p = int64_t(r - 1) * N + 1;
   // per-axis sums over a lattice of the closure sizes of the adjacent cells
@@ -1115,6 +1332,26 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
     nP *= n1p;
   }
   const int64_t kt = k + 1;
+  int64_t PPm = PP;  // MM (c0 M_p) entries of the p-rows; PP: KK (B) entries
+  int nlp = 0;
+  if (disc) {
+    // broken pressure: nlp functions per cell; a Q_r node's row couples the functions of its
+    // adjacent cells, a pressure row the (r+1)^d nodes of its cell and, through B, the
+    // functions of its cell and its face neighbours
+    nlp = int(pdisc_exponents(r - 1, d).size());
+    int64_t sQc = 0, cells = 1, nface = 0, Nd1 = 1, rq = 1;
+    for (int64_t g = 0; g < n1; ++g) sQc += adj_cells(g, r, N);
+    for (int a = 0; a < d; ++a) cells *= N;
+    for (int a = 0; a < d - 1; ++a) Nd1 *= N;
+    for (int a = 0; a < d; ++a) rq *= r + 1;
+    nface = int64_t(d) * Nd1 * (N - 1);
+    nP = cells * nlp;
+    QP = nlp;
+    for (int a = 0; a < d; ++a) QP *= sQc;
+    PQ = cells * nlp * rq;
+    PPm = cells * int64_t(nlp) * nlp;
+    PP = (cells + 2 * nface) * int64_t(nlp) * nlp;
+  }
   S.ns = 2 * d * nQ + nP;
   S.n = kt * S.ns;
   // u-eq rows: MM (M_rho on U) and KK (-M_rho on V), same component, disjoint columns
@@ -1122,9 +1359,9 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
   // p-eq rows: MM (c0 M_p on P); KK (-C on V, all comps; B on P, same columns as MM)
   const int64_t u_rows = kt * d * (kt + 1) * QQ;
   const int64_t v_rows = kt * d * ((kt + d) * QQ + QP);
-  const int64_t p_rows = kt * (kt * PP + d * PQ);
+  const int64_t p_rows = kt * ((kt - 1) * PPm + PP + d * PQ);
   S.nnzA = u_rows + v_rows + p_rows;
-  S.nnzMM = 2 * d * QQ + PP;
+  S.nnzMM = 2 * d * QQ + PPm;
   S.nnzKK = d * QQ + d * (d * QQ + QP) + (d * PQ + PP);
   // prolongation from N/2 cells: nonzero 1D interpolation weights per fine lattice point
   if (N % 2 == 0) {
@@ -1139,6 +1376,15 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
     for (int x = 0; x < d; ++x) {
       A *= a;
       B *= b;
+    }
+    if (disc) {
+      // per fine cell: the pairs (alpha, beta) with alpha <= beta componentwise
+      const auto ex = pdisc_exponents(r - 1, d);
+      int64_t pairs = 0, cells = 1;
+      for (const auto& x : ex)
+        for (const auto& y : ex) pairs += (x[0] <= y[0] && x[1] <= y[1] && x[2] <= y[2]) ? 1 : 0;
+      for (int x = 0; x < d; ++x) cells *= N;
+      B = cells * pairs;
     }
     S.nnzP = kt * (2 * d * A + B);
   }
@@ -1155,14 +1401,16 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind) {
     cnt1 = N;
   }
   for (int mask = 0; mask < (1 << d); ++mask) {
-    int64_t mult = 1, q = 1, pp = 1;
+    int64_t mult = 1, q = 1, pp = 1, pc = 1;
     for (int a = 0; a < d; ++a) {
       const int w = (mask >> a) & 1 ? 2 : 1;
       mult *= (w == 2 ? cnt2 : cnt1);
       q *= int64_t(r) * w + 1;
       pp *= int64_t(r - 1) * w + 1;
+      pc *= w;
     }
     if (mult == 0) continue;
+    if (disc) pp = pc * nlp;
     const int64_t np = kt * (2 * d * q + pp);
     const int64_t nsp = 2 * d * q + pp;
     S.sum_ns_ldh += mult * nsp * ((nsp + 3) & ~int64_t(3));
@@ -1209,7 +1457,7 @@ void source_vector(const LevelHost& L, const Material& m, double t, std::vector<
       rem /= nq1;
     }
     tabulate(r, d, xi, h, ts[q]);
-    tabulate(r - 1, d, xi, h, tp[q]);
+    tabulate_p(L.disc, r, d, xi, h, tp[q]);
     wq[q] = w;
     xq[q] = {xi[0], xi[1], xi[2]};
   }
@@ -1279,12 +1527,16 @@ void source_vector(const LevelHost& L, const Material& m, double t, std::vector<
         }
         for (int s = 0; s < nlp; ++s) {
           int64_t gn = 0;
-          int idx[3], rm = s;
-          for (int ax = 0; ax < d; ++ax) {
-            idx[ax] = rm % r;
-            rm /= r;
+          if (L.disc) {
+            gn = cell * nlp + s;
+          } else {
+            int idx[3], rm = s;
+            for (int ax = 0; ax < d; ++ax) {
+              idx[ax] = rm % r;
+              rm /= r;
+            }
+            for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1p + (int64_t(r - 1) * cc[ax] + idx[ax]);
           }
-          for (int ax = d - 1; ax >= 0; --ax) gn = gn * L.n1p + (int64_t(r - 1) * cc[ax] + idx[ax]);
           acc[2 * L.nv + gn] += wq[q] * tp[q].v[s] * g;
         }
       }
@@ -1302,7 +1554,7 @@ void source_vector(const LevelHost& L, const Material& m, double t, std::vector<
 }
 
 void source_tables(int d, int r, std::vector<double>& xq, std::vector<double>& wq, std::vector<double>& bq,
-                   std::vector<double>& bp) {
+                   std::vector<double>& bp, bool disc) {
   std::vector<double> gx, gw;
   gauss_legendre01(r + 2, gx, gw);
   const int nq1 = r + 2;
@@ -1316,6 +1568,7 @@ void source_tables(int d, int r, std::vector<double>& xq, std::vector<double>& w
     nls *= r + 1;
     nlp *= r;
   }
+  if (disc) nlp = int(pdisc_exponents(r - 1, d).size());
   bq.assign(size_t(nls) * nq, 0.0);
   bp.assign(size_t(nlp) * nq, 0.0);
   for (int q = 0; q < nq; ++q) {
@@ -1328,7 +1581,7 @@ void source_tables(int d, int r, std::vector<double>& xq, std::vector<double>& w
       xq[3 * q + ax] = xi[ax];
     }
     tabulate(r, d, xi, 1.0, ts);
-    tabulate(r - 1, d, xi, 1.0, tp);
+    tabulate_p(disc, r, d, xi, 1.0, tp);
     for (int a = 0; a < nls; ++a) bq[size_t(a) * nq + q] = ts.v[a];
     for (int a = 0; a < nlp; ++a) bp[size_t(a) * nq + q] = tp.v[a];
   }
@@ -1354,7 +1607,68 @@ void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out
       out[L.nv + d * q + c] = S * std::sin(t);
     }
   }
-  for (int64_t q = 0; q < L.nP; ++q) out[2 * L.nv + q] = S_at(q, L.n1p, L.r - 1) * std::cos(t);
+  if (!L.disc) {
+    for (int64_t q = 0; q < L.nP; ++q) out[2 * L.nv + q] = S_at(q, L.n1p, L.r - 1) * std::cos(t);
+    return;
+  }
+  // broken pressure: the L2 projection onto P_{r-1} of each cell ((r+2)^d Gauss points);
+  // the cell mass matrix is the same in every cell (reference coordinates)
+  const int nlp = L.nlp, nq1 = L.r + 2;
+  std::vector<double> gx, gw;
+  gauss_legendre01(nq1, gx, gw);
+  int nq = 1;
+  for (int a = 0; a < d; ++a) nq *= nq1;
+  std::vector<Tab> tp(nq);
+  std::vector<double> wq(nq, 1.0), M(size_t(nlp) * nlp, 0.0);
+  std::vector<std::array<double, 3>> xq(nq);
+  for (int q = 0; q < nq; ++q) {
+    double xi[3] = {0, 0, 0};
+    int rem = q;
+    for (int ax = 0; ax < d; ++ax) {
+      xi[ax] = gx[rem % nq1];
+      wq[q] *= gw[rem % nq1];
+      rem /= nq1;
+    }
+    xq[q] = {xi[0], xi[1], xi[2]};
+    tabulate_pdisc(L.r - 1, d, xi, 1.0, tp[q]);
+    for (int i = 0; i < nlp; ++i)
+      for (int j = 0; j < nlp; ++j) M[size_t(i) * nlp + j] += wq[q] * tp[q].v[i] * tp[q].v[j];
+  }
+  // Cholesky of the (symmetric positive definite) reference mass
+  std::vector<double> Lc(M);
+  for (int j = 0; j < nlp; ++j) {
+    for (int kk = 0; kk < j; ++kk)
+      for (int i = j; i < nlp; ++i) Lc[size_t(i) * nlp + j] -= Lc[size_t(i) * nlp + kk] * Lc[size_t(j) * nlp + kk];
+    const double dj = std::sqrt(Lc[size_t(j) * nlp + j]);
+    for (int i = j; i < nlp; ++i) Lc[size_t(i) * nlp + j] /= dj;
+  }
+  int64_t ncells = 1;
+  for (int a = 0; a < d; ++a) ncells *= L.N;
+  const double h = 1.0 / L.N;
+  std::vector<double> rhs(nlp);
+  for (int64_t cell = 0; cell < ncells; ++cell) {
+    int cc[3] = {0, 0, 0};
+    int64_t rem = cell;
+    for (int ax = 0; ax < d; ++ax) {
+      cc[ax] = int(rem % L.N);
+      rem /= L.N;
+    }
+    std::fill(rhs.begin(), rhs.end(), 0.0);
+    for (int q = 0; q < nq; ++q) {
+      double S = 1.0;
+      for (int ax = 0; ax < d; ++ax) S *= std::sin(M_PI * (cc[ax] + xq[q][ax]) * h);
+      for (int i = 0; i < nlp; ++i) rhs[i] += wq[q] * tp[q].v[i] * S;
+    }
+    for (int i = 0; i < nlp; ++i) {  // forward
+      for (int kk = 0; kk < i; ++kk) rhs[i] -= Lc[size_t(i) * nlp + kk] * rhs[kk];
+      rhs[i] /= Lc[size_t(i) * nlp + i];
+    }
+    for (int i = nlp - 1; i >= 0; --i) {  // backward
+      for (int kk = i + 1; kk < nlp; ++kk) rhs[i] -= Lc[size_t(kk) * nlp + i] * rhs[kk];
+      rhs[i] /= Lc[size_t(i) * nlp + i];
+    }
+    for (int i = 0; i < nlp; ++i) out[2 * L.nv + cell * nlp + i] = rhs[i] * std::cos(t);
+  }
 }
 
 }  // namespace stgmg

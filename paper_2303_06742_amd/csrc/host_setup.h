@@ -2,6 +2,7 @@
 // integrals, space-time operators in CSR, patch tables and grid transfers.
 // Plain C++17, no HIP; the device side only uploads what is built here.
 #pragma once
+#include <array>
 #include <complex>
 #include <cstdint>
 #include <string>
@@ -38,16 +39,28 @@ struct TimeBlocks {
 };
 TimeBlocks make_time_blocks(const TimeConsts& T);
 
+// Broken pressure space P_p^disc on a cell: the monomials prod_ax (xi_ax - 1/2)^alpha_ax in
+// the cell-centred reference coordinate, |alpha| <= p, in the lexicographic order of the
+// (p+1)^d lattice (x fastest) restricted to total degree <= p.
+std::vector<std::array<int, 3>> pdisc_exponents(int p, int d);
+
 // Element and boundary-face matrices of one cell [0,h]^d, indexed [test][trial]
-// row-major.  Vector local index = d*a + c (a = lexicographic local node).
+// row-major.  Vector local index = d*a + c (a = lexicographic local node).  The pressure
+// basis is Q_{r-1} (Taylor-Hood) or, with disc, P_{r-1}^disc; then the interior faces
+// normal to each axis carry the symmetric interior penalty parts of Def:B: for the face
+// between K+ (the lower cell, n = +e_axis) and K- (the upper cell), the block of test
+// functions on cell b and trial functions on cell a (0 = K+, 1 = K-) is
+// K_a BiT1 + K_b BiT2 + BiPen, each stored at [axis][2 * b + a].
 struct CellMats {
   int d = 0, r = 0;
-  int nls = 0, nlv = 0, nlp = 0;  // local scalar Q_r, vector, Q_{r-1} counts
+  bool disc = false;
+  int nls = 0, nlv = 0, nlp = 0;  // local scalar Q_r, vector, pressure counts
   double gamma_a = 0, gamma_b = 0, hF = 0;
   std::vector<double> Mrho, Avol, Cvol, Bvol, Mp;  // Cvol: [p-test][v-trial]
   std::vector<double> Aface[6], Cface[6], BfaceK[6], Bpen[6];  // face = 2*axis + side
+  std::vector<double> BiT1[3][4], BiT2[3][4], BiPen[3][4];    // disc only
 };
-CellMats make_cell_mats(int d, int r, double h, const Material& m);
+CellMats make_cell_mats(int d, int r, double h, const Material& m, bool disc = false);
 
 struct Csr {
   int64_t nrows = 0, ncols = 0;
@@ -58,6 +71,8 @@ struct Csr {
 
 struct LevelHost {
   int d = 0, r = 0, k = 0, N = 0;
+  bool disc = false;        // pressure P_{r-1}^disc (cell-major, nlp per cell) instead of Q_{r-1}
+  int nlp = 0;              // pressure dofs per cell (disc)
   int64_t n1 = 0, n1p = 0;  // lattice points per axis, Q_r and Q_{r-1}
   int64_t nQ = 0, nP = 0, nv = 0, ns = 0, n = 0;
   std::vector<double> Kcell;
@@ -83,6 +98,7 @@ struct BuildOptions {
   bool need_MM;
   bool need_KK = false;
   bool need_A = true;  // the assembled space-time CSR (otherwise only the spatial MM, KK)
+  bool disc = false;   // pressure pair Q_r^d / P_{r-1}^disc with the SIPG form
 };
 
 // Assemble one level.  Kcell: per-cell K (N^d values).
@@ -111,15 +127,16 @@ struct LevelSizes {
   int64_t sum_nr2 = 0;        // sum of nr^2
   int max_nr = 0, max_nn = 0;
 };
-LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind);
+LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc = false);
 
 // Built-in prescribed solution u_i = S sin t, p = S cos t, S = prod sin(pi x_j):
 // source vector S(t) of one time node (u-eq rows zero), and nodal interpolant.
 void source_vector(const LevelHost& L, const Material& m, double t, std::vector<double>& out);
 // Reference-cell tables for the device source: (r+2)^d Gauss points xq[nq][3] (on [0,1]^d),
-// weights wq[nq] (reference cell, summing to 1), basis values bq[(r+1)^d][nq], bp[r^d][nq].
+// weights wq[nq] (reference cell, summing to 1), basis values bq[(r+1)^d][nq] and
+// bp[nlp][nq] of the pressure basis (Q_{r-1}, or P_{r-1}^disc with disc).
 void source_tables(int d, int r, std::vector<double>& xq, std::vector<double>& wq, std::vector<double>& bq,
-                   std::vector<double>& bp);
+                   std::vector<double>& bp, bool disc = false);
 void interpolate_solution(const LevelHost& L, double t, std::vector<double>& out);
 
 }  // namespace stgmg

@@ -125,8 +125,10 @@ void k_axpby(hipStream_t st, double a, const double* x, double b, const double* 
 // (r+2)^d Gauss points of w_q phi_node(x_q) f(x_q, t) (v-equation rows) or g (p-equation
 // rows).  Tables (host): reference points xq[nq][3], weights wq[nq] (reference cell),
 // basis values bq[nloc_r][nq] of Q_r and bp[nloc_{r-1}][nq] of Q_{r-1}.
+// disc: pressure rows are cell-major (cell * nlp + j) with the basis values bp[nlp][nq] of the
+// broken P_{r-1}, integrated over their own cell only.
 struct SourceArgs {
-  int d, r, N, nq;
+  int d, r, N, nq, disc, nlp;
   int64_t n1, n1p, nv, ns;
   double h, rho, lam, mu, alpha, c0, t, scale;
 };

@@ -44,7 +44,8 @@ __device__ inline void builtin_fg(const SourceArgs& a, const double* x, double K
   *g = -a.c0 * S * st + a.alpha * divS * ct + K * a.d * pi * pi * S * ct;
 }
 
-// one thread per Q_r node (v-equation rows, all components) or Q_{r-1} node (p-equation rows)
+// one thread per Q_r node (v-equation rows, all components) or pressure function (p-equation
+// rows: a Q_{r-1} node, or one broken P_{r-1} function of one cell)
 __global__ void source_kernel(SourceArgs a, const double* __restrict__ xq, const double* __restrict__ wq,
                               const double* __restrict__ bq, const double* __restrict__ bp,
                               const double* __restrict__ Kcell, double* __restrict__ out) {
@@ -52,6 +53,30 @@ __global__ void source_kernel(SourceArgs a, const double* __restrict__ xq, const
   const int64_t nQ = a.nv / a.d, nP = a.ns - 2 * a.nv;
   if (t >= nQ + nP) return;
   const bool isP = t >= nQ;
+  if (isP && a.disc) {
+    // broken pressure: function j of one cell, integrated over that cell
+    const int64_t jj = t - nQ, cell = jj / a.nlp;
+    const int s = int(jj % a.nlp);
+    int cc[3] = {0, 0, 0};
+    int64_t rem = cell;
+    for (int ax = 0; ax < a.d; ++ax) {
+      cc[ax] = int(rem % a.N);
+      rem /= a.N;
+    }
+    const double K = Kcell[cell];
+    const double vol = a.d == 2 ? a.h * a.h : a.h * a.h * a.h;
+    const double* bt = bp + int64_t(s) * a.nq;
+    double accg = 0.0;
+    for (int q = 0; q < a.nq; ++q) {
+      double x[3];
+      for (int ax = 0; ax < a.d; ++ax) x[ax] = (cc[ax] + xq[3 * q + ax]) * a.h;
+      double f[3], gg;
+      builtin_fg(a, x, K, f, &gg);
+      accg += wq[q] * vol * bt[q] * gg;
+    }
+    out[2 * a.nv + jj] = a.scale * accg;
+    return;
+  }
   const int p = isP ? a.r - 1 : a.r;
   const int64_t node = isP ? t - nQ : t;
   const int64_t n1 = isP ? a.n1p : a.n1;

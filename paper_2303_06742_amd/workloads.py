@@ -41,6 +41,7 @@ class Config:
     rtol: float = 1e-8
     # patch solves: 2 time blocks with the u-equation rows eliminated, 1 time blocks, 0 full inverses
     time_blocks: int = 2
+    pressure: str = 'cont'  # 'cont': Q_{r-1} (Taylor-Hood); 'disc': P_{r-1}^disc with interior penalty
     extra: dict = field(default_factory=dict)
 
     @property
@@ -66,6 +67,12 @@ C3 = Config('3d-32cube-dg1-cell', dim=3, coarse_cells=4, levels=4, k=1, patch='c
 # reduced time-block solves it takes about 104 GB (FP64)
 C3V = Config('3d-32cube-dg1-vertex', dim=3, coarse_cells=4, levels=4, k=1, patch='vertex', tau=1e-3, slabs=10,
              alpha=1.0, c0=1e-3, K_logsd=1.0, seed=0)
+
+
+# the discontinuous-pressure pair of the paper's convergence study (Q3^2/P2^disc, dG(2), Table 5.1)
+# on 128x128 quads (6 levels from 4^2), vertex patches, 10 slabs of 1e-3
+C2D = Config('2d-128x128-q3p2disc-dg2-vertex', dim=2, coarse_cells=4, levels=6, k=2, patch='vertex', tau=1e-3,
+             slabs=10, r=3, pressure='disc')
 
 
 def scaled(cfg, levels, name=None, **kw):

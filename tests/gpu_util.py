@@ -29,7 +29,7 @@ def oracle_hierarchy(cfg_key):
     cfg = CONFIGS[cfg_key]
     K = cfg.K_cells()
     prm = problem.Params(rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
-                         K=cfg.K if K is None else K)
+                         K=cfg.K if K is None else K, pressure=cfg.pressure)
     return gmg.Hierarchy(cfg.dim, cfg.coarse_cells, cfg.levels - 1, cfg.r, cfg.k, cfg.tau, prm,
                          patch_kind=cfg.patch, J=cfg.n_smooth, omega=cfg.omega)
 
@@ -55,4 +55,9 @@ CONFIGS = {
     'c2s_tb': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-tb', time_blocks=1),
     'c3s_tb': W.scaled(W.C3, 2, name='3d-8cube-dg1-cell-lognormal-tb', time_blocks=1),
     'k0_tb': W.scaled(W.C1, 2, name='2d-8x8-dg0-vertex-tb', k=0, patch='vertex', time_blocks=1),
+    # the discontinuous pressure pair with the interior penalty form
+    'c1_disc': W.scaled(W.C1, 2, name='2d-8x8-q2p1disc-dg1-cell', pressure='disc'),
+    'c2d': W.scaled(W.C2D, 2, name='2d-8x8-q3p2disc-dg2-vertex'),
+    'c3s_disc': W.scaled(W.C3, 2, name='3d-8cube-q2p1disc-dg1-cell-lognormal', pressure='disc'),
+    'c2d_full': W.scaled(W.C2D, 2, name='2d-8x8-q3p2disc-dg2-vertex-full', time_blocks=0),
 }
