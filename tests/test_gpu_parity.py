@@ -135,7 +135,12 @@ def test_time_marching_rhs(key):
     prob = H.levels[-1].prob
     sol = problem.ExactSolution(cfg.dim, *workloads.builtin_solution_exprs(cfg.dim), prob.prm)
     X0 = to_host(S.interpolate_solution(0.0))
-    assert rel_err(X0, problem.interpolate(prob.blocks, sol, 0.0)) < 1e-14
+    tol = 1e-14
+    if cfg.pressure == 'disc':
+        # the projection solves with the cell mass of the monomials (LU here, Cholesky in the
+        # library): rounding up to a few cond(M_p) eps
+        tol = max(tol, 4 * np.linalg.cond(prob.blocks.cm.Mp) * np.finfo(float).eps)
+    assert rel_err(X0, problem.interpolate(prob.blocks, sol, 0.0)) < tol
     Xp = workloads.random_vector(S.ns, 41)
     F = to_host(S.slab_rhs(0.25, to_dev(Xp)))
     ref = problem.slab_rhs(prob.blocks, cfg.k, cfg.tau, 0.25, Xp, sol)
