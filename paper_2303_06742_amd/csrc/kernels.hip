@@ -1614,18 +1614,23 @@ static void red_layout(int max_nr, int R, int* th, int* W) {
   }
 }
 
-// rows per thread of the reduced patch GEMV: two (16-byte FP64 or 8-byte FP32 loads); for
-// FP32, STGMG_RED_R=4 selects four rows (16-byte loads), measured 6% slower on the 256^2
-// dG(2) workload (0.884 ms against 0.834 ms per finest-level launch)
-static int red_rows(bool fp32) {
-  if (const char* e = std::getenv("STGMG_RED_R"))
-    if (fp32 && std::atoi(e) == 4) return 4;
-  return 2;
+// rows per thread of the reduced patch GEMV: two for FP64 (16-byte loads); for FP32 two
+// (8-byte loads) on short columns and four (16-byte loads) on columns of more than 128
+// values.  Measured per finest-level launch: 256^2 dG(2) vertex patches (Schur blocks of 59
+// rows) 0.834 ms with two against 0.884 ms with four; 32^3 dG(1) vertex patches (402 rows)
+// 11.06 ms with two against 10.30 ms with four.  STGMG_RED_R=2|4 overrides for FP32.
+static int red_rows(bool fp32, int max_nr) {
+  if (!fp32) return 2;
+  if (const char* e = std::getenv("STGMG_RED_R")) {
+    const int v = std::atoi(e);
+    if (v == 2 || v == 4) return v;
+  }
+  return inv_ld(max_nr) > 128 ? 4 : 2;
 }
 
 int patch_apply_red_threads(int max_nr, bool fp32) {
   int th, W;
-  red_layout(max_nr, red_rows(fp32), &th, &W);
+  red_layout(max_nr, red_rows(fp32, max_nr), &th, &W);
   return th;
 }
 
@@ -1635,7 +1640,7 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
                        const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int32_t* pnu, const int64_t* ioff, const T* inv, const double* r, double* y) {
   if (npatch == 0) return;
-  const int rr = red_rows(sizeof(T) == 4);
+  const int rr = red_rows(sizeof(T) == 4, max_nr);
   int th, W;
   red_layout(max_nr, rr, &th, &W);
   bool ntl = true;
