@@ -11,7 +11,7 @@ computation of dynamic poro- and thermoelasticity", arXiv:2303.06742):
 * ``timedg``   -- right Gauss-Radau rule and dG(k) Lagrange time basis (Sec. 2, Eq:GF, Eq:TimeExp).
 * ``fem``      -- tensor Lagrange elements Q_r^d / Q_{r-1} and the broken P_{r-1}^disc,
                    the forms Def:ACB, Def:ab (SIPG B_gamma for the discontinuous pressure).
-* ``problem``  -- Problem 3.1 assembled into the algebraic slab system of Problem 4.1.
+* ``problem``  -- Problem 3.1 (or Problem B.1) assembled into the algebraic slab system of Problem 4.1.
 * ``gmg``      -- grid transfers, vertex/cell patches, Def. 4.2 and Alg. 4.1, V-cycle.
 * ``fgmres``   -- flexible (right-preconditioned) restarted GMRES.
 * ``norms``    -- the discrete error norms of Sec. 5.1.
@@ -31,6 +31,8 @@ What pins it (tests/test_oracle_*.py, all CPU):
                              symmetry and coercivity, exact reproduction, exact
                              transfer, Table 5.1 rows 1-2 (grad u and v errors to
                              0.5 %, rates), Table 5.2 row 1 relation to Taylor-Hood;
+  Problem B.1             -- exact reproduction (both pressure pairs, 2D/3D), and the
+                             coincidence with Problem 3.1 on Table 5.1 row 1;
   multigrid / Krylov      -- polynomial reproduction of the transfers, the
                              exact-local-solve invariant of Def:VankaOP, the
                              averaging identity of Alg. 4.1, one-level V-cycle =

@@ -144,7 +144,7 @@ def level_params(prm, d, Nfine, N):
         K = coarsen_K(K, d, n)
         n //= 2
     return problem.Params(rho=prm.rho, lam=prm.lam, mu=prm.mu, alpha=prm.alpha, c0=prm.c0, K=K,
-                          gamma_a=prm.gamma_a, gamma_b=prm.gamma_b, pressure=prm.pressure)
+                          gamma_a=prm.gamma_a, gamma_b=prm.gamma_b, pressure=prm.pressure, form=prm.form)
 
 
 class Level:

@@ -38,12 +38,14 @@ class Params:
     """Material and discretisation parameters (Sec. 1, Eq:HPS; Sec. 3)."""
 
     def __init__(self, rho=1.0, lam=1.0, mu=1.0, alpha=0.9, c0=0.01, K=1.0, gamma_a=None, gamma_b=None,
-                 pressure='cont'):
+                 pressure='cont', form='v'):
         self.rho, self.lam, self.mu, self.alpha, self.c0 = rho, lam, mu, alpha, c0
         self.K = K  # scalar, or array of per-cell values (lexicographic, x fastest)
         self.gamma_a, self.gamma_b = gamma_a, gamma_b
         assert pressure in ('cont', 'disc')
         self.pressure = pressure  # Q_h of Eq:DefVhQh: 'cont' (Q_{r-1}) or 'disc' (P_{r-1}^disc)
+        assert form in ('v', 'dtu')
+        self.form = form  # 'v': Problem 3.1; 'dtu': Problem B.1 (-C(d_t u, psi) in the third equation)
 
 
 def lame_from_young(E, nu):
@@ -153,6 +155,7 @@ class SpaceBlocks:
         C = _scatter(pd, vd, rep(cm.Cvol), (self.nP, self.nv))
         B = _scatter(pd, pd, Kc[:, None, None] * cm.Bvol[None], (self.nP, self.nP))
         self.Mp = _scatter(pd, pd, rep(cm.Mp), (self.nP, self.nP))
+        self.Cv = C.tocsr()  # volume part of C (the jump term of Problem B.1 uses it alone)
         faces = m.boundary_faces()
         if faces:
             fc = np.array([f[0] for f in faces])
@@ -175,8 +178,18 @@ class SpaceBlocks:
         self.A, self.C, self.B = A.tocsr(), C.tocsr(), B.tocsr()
         Z = None
         c0 = prm.c0
-        self.MM = sp.bmat([[Z, self.Mrho, Z], [self.Mrho, Z, Z], [Z, Z, c0 * self.Mp]], format='csr')
-        self.KK = sp.bmat([[-self.Mrho, Z, Z], [Z, self.A, self.C.T], [-self.C, Z, self.B]], format='csr')
+        self.form = prm.form
+        if self.form == 'v':
+            self.MM = sp.bmat([[Z, self.Mrho, Z], [self.Mrho, Z, Z], [Z, Z, c0 * self.Mp]], format='csr')
+            self.KK = sp.bmat([[-self.Mrho, Z, Z], [Z, self.A, self.C.T], [-self.C, Z, self.B]], format='csr')
+        else:
+            # Problem B.1: Q_n(<c0 d_t p, psi> - C(d_t u, psi) + B(p, psi)) with the jump of
+            # c0 p - C(u, .): both time-derivative terms belong to MM; KK keeps only B
+            self.MM = sp.bmat([[Z, self.Mrho, Z], [self.Mrho, Z, Z], [Z, -self.C, c0 * self.Mp]], format='csr')
+            self.KK = sp.bmat([[-self.Mrho, Z, Z], [Z, self.A, self.C.T], [Z, Z, self.B]], format='csr')
+            # the right-hand side's jump: <c0 p^{n-1} + alpha div u^{n-1}, psi> with the boundary
+            # value u_D(t_{n-1}) in place of u^{n-1} . n on the boundary
+            self.Jmm = sp.bmat([[Z, self.Mrho, Z], [self.Mrho, Z, Z], [Z, -self.Cv, c0 * self.Mp]], format='csr')
 
     def pbasis(self, pts):
         """Pressure basis values and gradients at reference points of a cell of this mesh."""
@@ -323,11 +336,38 @@ def source_vector(blocks, sol, t, nq=None):
     return np.concatenate([np.zeros(blocks.nv), Fv, Fp])
 
 
+def boundary_normal_u(blocks, sol, t):
+    """alpha <u_D(t) . n, psi>_G for every pressure test function (one time node, n_s values,
+    non-zero only in the p-equation rows)."""
+    d, r, m, prm = blocks.d, blocks.r, blocks.mesh, blocks.prm
+    h = m.h
+    out = np.zeros(blocks.nP)
+    origins = np.array([m.cell_origin(c) for c in range(m.ncells)])
+    faces = m.boundary_faces()
+    for axis in range(d):
+        for side in (0, 1):
+            cells = np.array([f[0] for f in faces if f[1] == axis and f[2] == side], dtype=np.int64)
+            if len(cells) == 0:
+                continue
+            fp, fw, n = fem.face_rule(r + 2, d, h, axis, side)
+            xs = (origins[cells][:, None, :] + h * fp[None, :, :]).reshape(-1, d)
+            pv_, _ = blocks.pbasis(fp)
+            uD = sol.u(xs, t).reshape(len(cells), len(fw), d)
+            np.add.at(out, blocks.pdofs[cells], prm.alpha * np.einsum('q,cq,qr->cr', fw, uD @ n, pv_))
+    return np.concatenate([np.zeros(2 * blocks.nv), out])
+
+
 def slab_rhs(blocks, k, tau, t_start, X_prev_end, sol=None):
-    """F_n of Problem 4.1: (tau/2) w_b S(t_{n,b}) + e_b MM X_{n-1,end}, for b = 1..k+1."""
+    """F_n of Problem 4.1: (tau/2) w_b S(t_{n,b}) + e_b MM X_{n-1,end}, for b = 1..k+1.
+    Problem B.1: the jump is e_b (Jmm X_{n-1,end} - alpha <u_D(t_{n-1}) . n, psi>_G)."""
     _, _, e, _, w = timedg.time_matrices(k, tau)
     tn = timedg.slab_nodes(t_start, tau, k)
-    jump = blocks.MM @ X_prev_end
+    if blocks.form == 'v':
+        jump = blocks.MM @ X_prev_end
+    else:
+        jump = blocks.Jmm @ X_prev_end
+        if sol is not None:
+            jump = jump - boundary_normal_u(blocks, sol, t_start)
     parts = []
     for b in range(k + 1):
         Fb = e[b] * jump
