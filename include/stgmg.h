@@ -62,6 +62,11 @@ typedef int32_t stgmg_status;
 #define STGMG_PRESSURE_DISC 1 /* broken P_{r-1}^disc: per cell the monomials prod (xi - 1/2)^a, |a| <= r-1, cell-major;
                                  B_gamma the symmetric interior penalty form (Def:B, second option) */
 
+/* formulation of the third equation */
+#define STGMG_FORM_V   0 /* Problem 3.1: -C(v, psi) */
+#define STGMG_FORM_DTU 1 /* Problem B.1: -C(d_t u, psi), the jump of c0 p + alpha div u and
+                            -alpha <u . n, psi> on the boundary (u_D(t_{n-1}) on the right) */
+
 typedef struct stgmg_handle stgmg_handle;
 
 /* Problem and solver parameters.  Fine level: coarse_cells << (levels-1) cells
@@ -95,6 +100,7 @@ typedef struct {
                                of n_P/(k+1) - nU rows per eigenvalue (about 3x fewer again).
                             Default of the Python workloads: 2. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
+  int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */
 } stgmg_params;
 
 typedef struct {

@@ -32,6 +32,7 @@ PROF_PATCH_APPLY = 0
 PROF_RESIDUAL = 1
 PREC = {'fp64': 0, 'fp32': 1}
 PRESSURE = {'cont': 0, 'disc': 1}  # Q_{r-1} (Taylor-Hood) or P_{r-1}^disc with the interior penalty form
+FORM = {'v': 0, 'dtu': 1}  # Problem 3.1 or Problem B.1
 
 
 class Params(ctypes.Structure):
@@ -41,7 +42,7 @@ class Params(ctypes.Structure):
                 ('tau', ctypes.c_double), ('rho', ctypes.c_double), ('lam', ctypes.c_double),
                 ('mu', ctypes.c_double), ('alpha', ctypes.c_double), ('c0', ctypes.c_double),
                 ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p), ('graph', ctypes.c_int32),
-                ('time_blocks', ctypes.c_int32), ('pressure', ctypes.c_int32)]
+                ('time_blocks', ctypes.c_int32), ('pressure', ctypes.c_int32), ('form', ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -134,7 +135,7 @@ def make_params(cfg, precision=None, graph=-1, time_blocks=None):
                omega=cfg.omega, tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
                K=cfg.K, K_cells=None if K is None else K.ctypes.data, graph=graph,
                time_blocks=cfg.time_blocks if time_blocks is None else time_blocks,
-               pressure=PRESSURE[cfg.pressure])
+               pressure=PRESSURE[cfg.pressure], form=FORM[cfg.form])
     return p, K
 
 

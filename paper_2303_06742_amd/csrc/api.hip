@@ -169,6 +169,7 @@ struct stgmg_handle {
   bool tb = false;   // patch solves through the time eigen-decomposition
   bool red = false;  // ... with the u-equation rows eliminated
   DArr<double> e_dev, tmp_ns, src_buf;
+  DevCsr cface;  // Problem B.1: boundary part of C on the finest level (right-hand side's jump)
   DArr<double> src_xq, src_wq, src_bq, src_bp, kfine;  // device source tables
   // kernel timing (finest level): event pairs per kernel class
   bool prof = false;
@@ -243,6 +244,7 @@ void check_params(const stgmg_params* p) {
   if (p->time_blocks < 0 || p->time_blocks > 2) throw ApiError(STGMG_ERR_INVALID_ARG, "time_blocks must be 0, 1 or 2");
   if (p->pressure != STGMG_PRESSURE_CONT && p->pressure != STGMG_PRESSURE_DISC)
     throw ApiError(STGMG_ERR_INVALID_ARG, "unknown pressure space");
+  if (p->form != STGMG_FORM_V && p->form != STGMG_FORM_DTU) throw ApiError(STGMG_ERR_INVALID_ARG, "unknown formulation");
 }
 
 int host_threads() {
@@ -431,7 +433,8 @@ void build(stgmg_handle* h) {
   for (int l = 0; l <= L; ++l) {
     LevelHost H;
     stgmg::BuildOptions o{d, p.r, p.k, p.coarse_cells << l, p.patch, p.tau, p.omega, l >= 1, true, true,
-                          l == 0 || !h->tb, p.pressure == STGMG_PRESSURE_DISC};
+                          l == 0 || !h->tb, p.pressure == STGMG_PRESSURE_DISC, p.form == STGMG_FORM_DTU,
+                          p.form == STGMG_FORM_DTU && l == L};
     stgmg::build_level(o, h->mat, Kl[l], H, nth);
     LevelDev& D = h->lv[l];
     D.N = H.N;
@@ -440,6 +443,7 @@ void build(stgmg_handle* h) {
     if (l >= 1 && !h->tb) D.A.upload(H.A, h->st, ctr);  // full-inverse patch extraction reads it
     D.MMs.upload(H.MM, h->st, ctr);
     D.KKs.upload(H.KK, h->st, ctr);
+    if (l == L && p.form == STGMG_FORM_DTU) h->cface.upload(H.Cface, h->st, ctr);
     {
       const double avg = H.ns ? double(H.MM.col.size() + H.KK.col.size()) / double(H.ns) : 0.0;
       D.op_lanes = avg < 12 ? 4 : 8;  // 8 lanes per spatial row measured best on the 256^2 dG(2) operator
@@ -1126,6 +1130,11 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
                       h->src_buf.p + int64_t(b) * F.ns);
     }
     h->lv[h->L].MMs.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
+    // Problem B.1: the jump carries alpha div u^{n-1} (the volume part of C) and the boundary
+    // value u_D(t_{n-1}) in place of u^{n-1} . n; MM holds all of C, so add the boundary part
+    // back (u_D is zero on the boundary for the built-in solution)
+    if (h->prm.form == STGMG_FORM_DTU)
+      h->cface.apply(h->st, 2, x_prev_end_dev + F.nv, nullptr, h->tmp_ns.p + 2 * F.nv);
     stgmg::k_slab_rhs(h->st, nt, F.ns, h->e_dev.p, h->tmp_ns.p, h->src_buf.p, rhs_dev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->st));
@@ -1267,11 +1276,12 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       for (int a = 0; a < B.nblk; ++a) (B.is_complex[a] ? ncplx : nreal)++;
     }
     for (int l = 0; l <= L; ++l) {
-      const stgmg::LevelSizes S =
-          stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch, p.pressure == STGMG_PRESSURE_DISC);
+      const stgmg::LevelSizes S = stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch,
+                                                     p.pressure == STGMG_PRESSURE_DISC, p.form == STGMG_FORM_DTU);
       const int64_t n = S.n;
       // factored operator: spatial MM and KK; vectors b, d, r
       res += 2 * (S.ns + 1) * 8 + (S.nnzMM + S.nnzKK) * 12 + 3 * n * 8;
+      if (l == L && p.form == STGMG_FORM_DTU) res += (S.nP + 1) * 8 + S.nnzCface * 12;  // boundary part of C
       if (l == 0) {
         res += n * stgmg::inv_ld(int(n)) * 8 + int64_t(stgmg::dense_gemv_chunks(int(n))) * n * 8;
         temp_peak = std::max(temp_peak, n * n * 8 + 32 * n * 8 + 3 * n * 8 + 64);
@@ -1319,6 +1329,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
           nlp *= p.r;
           ncell *= int64_t(p.coarse_cells) << l;
         }
+        if (p.pressure == STGMG_PRESSURE_DISC) nlp = int64_t(stgmg::pdisc_exponents(p.r - 1, d).size());
         res += (4 * nq + (nls + nlp) * nq + ncell) * 8;  // device source tables and K
         const bool graph = p.graph == 1 || (p.graph == -1 && n < (int64_t(1) << 21));
         if (graph) res += 2 * n * 8;

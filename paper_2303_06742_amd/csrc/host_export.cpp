@@ -10,6 +10,7 @@ stgmg::LevelHost g_level;
 stgmg::Csr g_P;
 std::vector<double> g_vec;
 bool g_disc = false;  // pressure pair of the following builds
+bool g_dtu = false;   // Problem B.1 instead of Problem 3.1 in the following builds
 }  // namespace
 
 extern "C" {
@@ -17,6 +18,8 @@ extern "C" {
 // Pressure pair of the following builds, prolongations and sizes: 0 = Q_{r-1} (Taylor-Hood),
 // 1 = P_{r-1}^disc with the interior penalty form.
 void stgmg_host_set_pressure(int disc) { g_disc = disc != 0; }
+// Formulation of the following builds and sizes: 0 = Problem 3.1 (v-form), 1 = Problem B.1.
+void stgmg_host_set_form(int dtu) { g_dtu = dtu != 0; }
 
 // Build one level; returns n (space-time unknowns) or -1 on error.
 long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double tau, double omega, double rho,
@@ -25,7 +28,7 @@ long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double ta
     long long nc = 1;
     for (int a = 0; a < d; ++a) nc *= N;
     std::vector<double> K(Kcell, Kcell + nc);
-    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true, true, g_disc};
+    stgmg::BuildOptions o{d, r, k, N, patch_kind, tau, omega, true, true, true, true, g_disc, g_dtu, g_dtu};
     stgmg::Material m{rho, lambda, mu, alpha, c0};
     g_level = stgmg::LevelHost();
     stgmg::build_level(o, m, K, g_level, 4);
@@ -36,13 +39,15 @@ long long stgmg_host_build(int d, int r, int k, int N, int patch_kind, double ta
 }
 
 long long stgmg_host_nnz(int which) {
-  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : which == 3 ? g_level.KK : g_P;
+  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : which == 3 ? g_level.KK
+                       : which == 4 ? g_level.Cface : g_P;
   return (long long)c.col.size();
 }
 
 // which: 0 = A, 1 = MM, 2 = last prolongation
 void stgmg_host_csr(int which, long long* ptr, int* col, double* val) {
-  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : which == 3 ? g_level.KK : g_P;
+  const stgmg::Csr& c = which == 0 ? g_level.A : which == 1 ? g_level.MM : which == 3 ? g_level.KK
+                       : which == 4 ? g_level.Cface : g_P;
   for (size_t i = 0; i < c.ptr.size(); ++i) ptr[i] = c.ptr[i];
   std::memcpy(col, c.col.data(), c.col.size() * sizeof(int));
   std::memcpy(val, c.val.data(), c.val.size() * sizeof(double));
@@ -123,11 +128,12 @@ int stgmg_host_time_blocks(int k, double tau, double* lam, int* cplx, double* ti
   return B.nblk;
 }
 
-// KK CSR of the last built level (which = 3 in stgmg_host_csr)
+// KK CSR of the last built level (which = 3 in stgmg_host_csr); which = 4: the boundary part
+// of C (Problem B.1 builds), nP rows
 // Closed-form sizes: out = {n, nnzA, nnzMM, nnzP, npatch, sum_np, sum_np_ld, max_np, nnzKK,
-//                          sum_red_fixed, sum_nr_ldr, max_nr, max_nn}
+//                          sum_red_fixed, sum_nr_ldr, max_nr, max_nn, nnzCface}
 void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out) {
-  stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind, g_disc);
+  stgmg::LevelSizes S = stgmg::level_sizes(d, r, k, N, patch_kind, g_disc, g_dtu);
   out[0] = S.n;
   out[1] = S.nnzA;
   out[2] = S.nnzMM;
@@ -141,6 +147,7 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[10] = S.sum_nr_ldr;
   out[11] = S.max_nr;
   out[12] = S.max_nn;
+  out[13] = S.nnzCface;
 }
 
 }  // extern "C"

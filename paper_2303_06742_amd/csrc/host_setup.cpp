@@ -640,7 +640,10 @@ struct RowBuilder {
         const int at = d * a + c;
         double cv = cm->Cvol[size_t(st) * nlv + at];
         for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(st) * nlv + at];
-        kk.push_back({d * gn + c, -cv});
+        if (o->dtu)
+          mm.push_back({nv + d * gn + c, -cv});  // -C(d_t u, psi): on U, time-derivative part
+        else
+          kk.push_back({d * gn + c, -cv});       // -C(v, psi): on V
       }
     }
     // own cell: volume, boundary faces, and the own-cell blocks of its interior faces
@@ -674,6 +677,59 @@ struct RowBuilder {
       mm.push_back({gp, m->c0 * cm->Mp[size_t(st) * nlp + s]});
       kk.push_back({gp, own[s]});
     }
+  }
+
+  // Boundary-face part of C in p-equation row j (columns: velocity dofs), sorted and merged.
+  void cface_row(int64_t j, std::vector<Entry>& out) const {
+    out.clear();
+    const int d = o->d, r = o->r, N = o->N;
+    const int nlv = cm->nlv, nls = cm->nls;
+    int cl[3][2], ll[3][2], cn[3] = {1, 1, 1};
+    if (L->disc) {
+      int64_t rem = j / cm->nlp;
+      for (int ax = 0; ax < d; ++ax) {
+        cl[ax][0] = int(rem % N);
+        rem /= N;
+        ll[ax][0] = 0;
+      }
+    } else {
+      int64_t rem = j;
+      for (int ax = 0; ax < d; ++ax) {
+        cn[ax] = cells_axis(rem % L->n1p, r - 1, N, cl[ax], ll[ax]);
+        rem /= L->n1p;
+      }
+    }
+    int combos = 1;
+    for (int ax = 0; ax < d; ++ax) combos *= cn[ax];
+    for (int cb = 0; cb < combos; ++cb) {
+      int cc[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, t = cb;
+      for (int ax = 0; ax < d; ++ax) {
+        cc[ax] = cl[ax][t % cn[ax]];
+        lo[ax] = ll[ax][t % cn[ax]];
+        t /= cn[ax];
+      }
+      int st = 0;
+      if (L->disc) {
+        st = int(j % cm->nlp);
+      } else {
+        for (int ax = d - 1; ax >= 0; --ax) st = st * r + lo[ax];
+      }
+      int faces[6], nf = 0;
+      for (int ax = 0; ax < d; ++ax) {
+        if (cc[ax] == 0) faces[nf++] = 2 * ax;
+        if (cc[ax] == N - 1) faces[nf++] = 2 * ax + 1;
+      }
+      if (nf == 0) continue;
+      for (int a = 0; a < nls; ++a) {
+        const int64_t gn = gnode(cc, a, r, L->n1);
+        for (int c = 0; c < d; ++c) {
+          double cv = 0.0;
+          for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(st) * nlv + d * a + c];
+          out.push_back({d * gn + c, cv});
+        }
+      }
+    }
+    sort_merge(out);
   }
 
   // Spatial row i of MM and KK (sorted, merged).
@@ -778,14 +834,17 @@ struct RowBuilder {
           if (cc[ax] == 0) faces[nf++] = 2 * ax;
           if (cc[ax] == N - 1) faces[nf++] = 2 * ax + 1;
         }
-        // -C(v, psi_st) on V
+        // -C(v, psi_st) on V (Problem 3.1) or -C(d_t u, psi_st) on U (Problem B.1)
         for (int a = 0; a < nls; ++a) {
           const int64_t gn = gnode(cc, a, r, L->n1);
           for (int c = 0; c < d; ++c) {
             const int at = d * a + c;
             double cv = cm->Cvol[size_t(st) * nlv + at];
             for (int f = 0; f < nf; ++f) cv += cm->Cface[faces[f]][size_t(st) * nlv + at];
-            kk.push_back({d * gn + c, -cv});
+            if (o->dtu)
+              mm.push_back({nv + d * gn + c, -cv});
+            else
+              kk.push_back({d * gn + c, -cv});
           }
         }
         for (int s = 0; s < nlp; ++s) {
@@ -821,6 +880,7 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
     L.nP *= L.n1p;
   }
   L.disc = o.disc;
+  L.dtu = o.dtu;
   int64_t ncells_l = 1;
   for (int a = 0; a < d; ++a) ncells_l *= N;
   if (o.disc) {
@@ -989,6 +1049,22 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
   });
 
   }  // need_A
+
+  if (o.need_Cface) {
+    L.Cface = Csr();
+    L.Cface.nrows = L.nP;
+    L.Cface.ncols = L.nv;
+    L.Cface.ptr.assign(L.nP + 1, 0);
+    std::vector<Entry> e;
+    for (int64_t j = 0; j < L.nP; ++j) {
+      rb.cface_row(j, e);
+      L.Cface.ptr[j + 1] = L.Cface.ptr[j] + int64_t(e.size());
+      for (const Entry& x : e) {
+        L.Cface.col.push_back(int32_t(x.col));
+        L.Cface.val.push_back(x.val);
+      }
+    }
+  }
 
   if (!o.need_patches) return;
   // ------------------------------------------------------------ patches
@@ -1311,7 +1387,7 @@ int adj_cells(int64_t g, int p, int N) {
 }
 }  // namespace
 
-LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc) {
+LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bool dtu) {
   LevelSizes S;
   const int64_t n1 = int64_t(r) * N + 1, n1p = int64_t(r - 1) * N + 1;
   // per-axis sums over a lattice of the closure sizes of the adjacent cells
@@ -1354,15 +1430,82 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc) {
   }
   S.ns = 2 * d * nQ + nP;
   S.n = kt * S.ns;
+  S.nP = nP;
+  if (dtu) {
+    // boundary part of C: a pressure row couples the velocity nodes of its adjacent boundary
+    // cells; the union of their node boxes is counted by inclusion-exclusion
+    auto is_bnd = [&](const int* c) {
+      for (int a = 0; a < d; ++a)
+        if (c[a] == 0 || c[a] == N - 1) return true;
+      return false;
+    };
+    if (disc) {
+      int64_t bcells = 0, cells = 1, rq = 1;
+      for (int a = 0; a < d; ++a) cells *= N, rq *= r + 1;
+      for (int64_t c = 0; c < cells; ++c) {
+        int cc[3] = {0, 0, 0};
+        int64_t rem = c;
+        for (int a = 0; a < d; ++a) cc[a] = int(rem % N), rem /= N;
+        bcells += is_bnd(cc);
+      }
+      S.nnzCface = bcells * nlp * d * rq;
+    } else {
+      for (int64_t j = 0; j < nP; ++j) {
+        int cl[3][2], cn[3] = {1, 1, 1};
+        int64_t rem = j;
+        for (int a = 0; a < d; ++a) {
+          const int64_t g = rem % n1p;
+          rem /= n1p;
+          cn[a] = 0;
+          if (g % (r - 1) == 0) {
+            const int64_t c = g / (r - 1);
+            if (c - 1 >= 0) cl[a][cn[a]++] = int(c - 1);
+            if (c < N) cl[a][cn[a]++] = int(c);
+          } else {
+            cl[a][cn[a]++] = int(g / (r - 1));
+          }
+        }
+        int bl[8][3], nb = 0, combos = 1;
+        for (int a = 0; a < d; ++a) combos *= cn[a];
+        for (int cb = 0; cb < combos; ++cb) {
+          int cc[3] = {0, 0, 0}, t = cb;
+          for (int a = 0; a < d; ++a) cc[a] = cl[a][t % cn[a]], t /= cn[a];
+          if (is_bnd(cc)) {
+            for (int a = 0; a < 3; ++a) bl[nb][a] = cc[a];
+            ++nb;
+          }
+        }
+        int64_t uni = 0;
+        for (int sub = 1; sub < (1 << nb); ++sub) {
+          int64_t vol = 1;
+          int bits = 0;
+          for (int a = 0; a < d; ++a) {
+            int lo = -1 << 30, hi = 1 << 30;
+            for (int q = 0; q < nb; ++q)
+              if (sub >> q & 1) {
+                lo = std::max(lo, r * bl[q][a]);
+                hi = std::min(hi, r * (bl[q][a] + 1));
+              }
+            vol *= std::max(0, hi - lo + 1);
+          }
+          for (int q = 0; q < nb; ++q) bits += sub >> q & 1;
+          uni += (bits % 2 ? 1 : -1) * vol;
+        }
+        S.nnzCface += uni * d;
+      }
+    }
+  }
   // u-eq rows: MM (M_rho on U) and KK (-M_rho on V), same component, disjoint columns
   // v-eq rows: MM (M_rho on V, same comp); KK (A on U, all comps; C^T on P)
   // p-eq rows: MM (c0 M_p on P); KK (-C on V, all comps; B on P, same columns as MM)
   const int64_t u_rows = kt * d * (kt + 1) * QQ;
   const int64_t v_rows = kt * d * ((kt + d) * QQ + QP);
-  const int64_t p_rows = kt * ((kt - 1) * PPm + PP + d * PQ);
+  // Problem B.1 moves -C from KK (on V) to MM (on U): the same union on the diagonal time
+  // block, and d PQ more entries in every off-diagonal one
+  const int64_t p_rows = kt * ((kt - 1) * (PPm + (dtu ? d * PQ : 0)) + PP + d * PQ);
   S.nnzA = u_rows + v_rows + p_rows;
-  S.nnzMM = 2 * d * QQ + PPm;
-  S.nnzKK = d * QQ + d * (d * QQ + QP) + (d * PQ + PP);
+  S.nnzMM = 2 * d * QQ + PPm + (dtu ? d * PQ : 0);
+  S.nnzKK = d * QQ + d * (d * QQ + QP) + ((dtu ? 0 : d * PQ) + PP);
   // prolongation from N/2 cells: nonzero 1D interpolation weights per fine lattice point
   if (N % 2 == 0) {
     auto pro_sum = [&](int p) {

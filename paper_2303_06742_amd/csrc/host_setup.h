@@ -72,6 +72,7 @@ struct Csr {
 struct LevelHost {
   int d = 0, r = 0, k = 0, N = 0;
   bool disc = false;        // pressure P_{r-1}^disc (cell-major, nlp per cell) instead of Q_{r-1}
+  bool dtu = false;         // Problem B.1: -C(d_t u, psi) in the p-equation (MM's p-rows carry -C on U)
   int nlp = 0;              // pressure dofs per cell (disc)
   int64_t n1 = 0, n1p = 0;  // lattice points per axis, Q_r and Q_{r-1}
   int64_t nQ = 0, nP = 0, nv = 0, ns = 0, n = 0;
@@ -88,6 +89,9 @@ struct LevelHost {
   std::vector<int64_t> tptr;
   std::vector<int32_t> tpos;
   std::vector<double> winv;  // omega / (number of patches containing mu)
+  // Problem B.1: the boundary-face part of C (nP rows, columns = velocity dofs 0..nv-1): the
+  // slab right-hand side's jump uses only the volume part of C on u^{n-1}
+  Csr Cface;
 };
 
 struct BuildOptions {
@@ -99,6 +103,8 @@ struct BuildOptions {
   bool need_KK = false;
   bool need_A = true;  // the assembled space-time CSR (otherwise only the spatial MM, KK)
   bool disc = false;   // pressure pair Q_r^d / P_{r-1}^disc with the SIPG form
+  bool dtu = false;    // Problem B.1 instead of Problem 3.1
+  bool need_Cface = false;  // build LevelHost::Cface (Problem B.1, finest level)
 };
 
 // Assemble one level.  Kcell: per-cell K (N^d values).
@@ -126,8 +132,10 @@ struct LevelSizes {
   int64_t alg_red_fixed = 0;  // sum of nn^2 + nP nU
   int64_t sum_nr2 = 0;        // sum of nr^2
   int max_nr = 0, max_nn = 0;
+  int64_t nP = 0;
+  int64_t nnzCface = 0;  // Problem B.1: nonzeros of the boundary part of C (LevelHost::Cface)
 };
-LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc = false);
+LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc = false, bool dtu = false);
 
 // Built-in prescribed solution u_i = S sin t, p = S cos t, S = prod sin(pi x_j):
 // source vector S(t) of one time node (u-eq rows zero), and nodal interpolant.

@@ -42,6 +42,7 @@ class Config:
     # patch solves: 2 time blocks with the u-equation rows eliminated, 1 time blocks, 0 full inverses
     time_blocks: int = 2
     pressure: str = 'cont'  # 'cont': Q_{r-1} (Taylor-Hood); 'disc': P_{r-1}^disc with interior penalty
+    form: str = 'v'         # 'v': Problem 3.1; 'dtu': Problem B.1
     extra: dict = field(default_factory=dict)
 
     @property

@@ -29,7 +29,7 @@ def oracle_hierarchy(cfg_key):
     cfg = CONFIGS[cfg_key]
     K = cfg.K_cells()
     prm = problem.Params(rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
-                         K=cfg.K if K is None else K, pressure=cfg.pressure)
+                         K=cfg.K if K is None else K, pressure=cfg.pressure, form=cfg.form)
     return gmg.Hierarchy(cfg.dim, cfg.coarse_cells, cfg.levels - 1, cfg.r, cfg.k, cfg.tau, prm,
                          patch_kind=cfg.patch, J=cfg.n_smooth, omega=cfg.omega)
 
@@ -60,4 +60,10 @@ CONFIGS = {
     'c2d': W.scaled(W.C2D, 2, name='2d-8x8-q3p2disc-dg2-vertex'),
     'c3s_disc': W.scaled(W.C3, 2, name='3d-8cube-q2p1disc-dg1-cell-lognormal', pressure='disc'),
     'c2d_full': W.scaled(W.C2D, 2, name='2d-8x8-q3p2disc-dg2-vertex-full', time_blocks=0),
+    # Problem B.1 (-C(d_t u, psi)): reduced, time-block and full patch solves, both pressure pairs
+    'c2s_b1': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-b1', form='dtu'),
+    'c1_b1': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1', form='dtu'),
+    'c1_b1_tb': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-tb', form='dtu', time_blocks=1),
+    'c1_b1_full': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-full', form='dtu', time_blocks=0),
+    'c3s_disc_b1': W.scaled(W.C3, 2, name='3d-8cube-q2p1disc-dg1-cell-lognormal-b1', pressure='disc', form='dtu'),
 }

@@ -15,7 +15,7 @@ def capi():
     return c
 
 
-@pytest.mark.parametrize("key", ['c1', 'c2s', 'c3s'])
+@pytest.mark.parametrize("key", ['c1', 'c2s', 'c3s', 'c2s_b1', 'c1_disc', 'c2d', 'c3s_disc_b1'])
 def test_footprint_is_what_setup_allocates(key):
     c = capi()
     cfg = CONFIGS[key]

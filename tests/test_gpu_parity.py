@@ -27,7 +27,8 @@ def rel_err(a, b, scale=None):
 
 
 KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'k3', 'c3v', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb',
-        'c3s_tb', 'k0_tb', 'c1_disc', 'c2d', 'c3s_disc', 'c2d_full']
+        'c3s_tb', 'k0_tb', 'c1_disc', 'c2d', 'c3s_disc', 'c2d_full', 'c2s_b1', 'c1_b1_tb', 'c1_b1_full',
+        'c3s_disc_b1']
 
 
 @pytest.mark.parametrize("key", KEYS)
@@ -124,7 +125,7 @@ def test_solve_against_oracle(key):
     assert rel_err(xs, xg) < 1e-8, rel_err(xs, xg)
 
 
-@pytest.mark.parametrize("key", ['c1', 'c2s', 'c1_disc', 'c2d', 'c3s_disc'])
+@pytest.mark.parametrize("key", ['c1', 'c2s', 'c1_disc', 'c2d', 'c3s_disc', 'c2s_b1', 'c3s_disc_b1'])
 def test_time_marching_rhs(key):
     """Right-hand side of Problem 3.1 for the built-in prescribed solution, and the
     nodal interpolant at t0 (initial data; the L2 projection for a broken pressure)."""
