@@ -20,8 +20,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PATCH_KERNEL = {0: 'patch_apply_kernel', 1: 'patch_apply_tb_kernel', 2: 'patch_apply_red_kernel'}
-PATCH_SOLVE = {'full': 0, 'tb': 1, 'reduced': 2}
+PATCH_KERNEL = {0: 'patch_apply_kernel', 1: 'patch_apply_tb_kernel', 2: 'patch_apply_red_kernel',
+                3: 'patch_apply_red_kernel (symmetric tiles)'}
+PATCH_SOLVE = {'full': 0, 'tb': 1, 'reduced': 2, 'sym': 3}
 METRIC = "GMRES-GMG solves/s and V-cycle DoF/s at 1e-8 rel. residual; p50/p99 latency"
 
 

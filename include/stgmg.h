@@ -97,8 +97,13 @@ typedef struct {
                             2: as 1, with the u-equation rows of each spatial block eliminated
                                (V = lam U - (rho M)^{-1} r_u): stored are (rho M)^{-1} on the
                                patch nodes, KK_pV (rho M)^{-1}, and one Schur complement inverse
-                               of n_P/(k+1) - nU rows per eigenvalue (about 3x fewer again).
-                            Default of the Python workloads: 2. */
+                               of n_P/(k+1) - nU rows per eigenvalue (about 3x fewer again);
+                            3: as 2, with each Schur inverse stored through its symmetric form:
+                               X = (D1 S D2)^{-1}, D1 = diag(I, -lam^{-1/2}), D2 = diag(I, lam^{1/2})
+                               on the (U, P) rows, is symmetric, and its lower 8x8 tiles are kept
+                               (about 0.65x the values of 2 at 59 rows); applies where the blocks
+                               are inverted in LDS, otherwise as 2.
+                            Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
   int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */
 } stgmg_params;

@@ -119,6 +119,7 @@ struct LevelDev {
   DArr<int32_t> pdof;
   DArr<int32_t> pnu;  // reduced solves: velocity dofs nU per patch (one time node)
   int max_nu = 0, max_nr = 0, max_npr = 0;
+  bool sym = false;  // reduced solves with the Schur inverses as symmetric tiles
   DArr<double> inv64, winv, y;
   DArr<float> inv32;
   DevCsr P, R;  // prolongation from level-1 and its transpose
@@ -241,7 +242,7 @@ void check_params(const stgmg_params* p) {
   const int64_t Nf = int64_t(p->coarse_cells) << (p->levels - 1);
   if (Nf > 4096) throw ApiError(STGMG_ERR_UNSUPPORTED, "grid too fine");
   if (!p->K_cells && !(p->K > 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "K must be > 0");
-  if (p->time_blocks < 0 || p->time_blocks > 2) throw ApiError(STGMG_ERR_INVALID_ARG, "time_blocks must be 0, 1 or 2");
+  if (p->time_blocks < 0 || p->time_blocks > 3) throw ApiError(STGMG_ERR_INVALID_ARG, "time_blocks must be 0..3");
   if (p->pressure != STGMG_PRESSURE_CONT && p->pressure != STGMG_PRESSURE_DISC)
     throw ApiError(STGMG_ERR_INVALID_ARG, "unknown pressure space");
   if (p->form != STGMG_FORM_V && p->form != STGMG_FORM_DTU) throw ApiError(STGMG_ERR_INVALID_ARG, "unknown formulation");
@@ -269,6 +270,27 @@ size_t lds_per_block() {
 }
 
 void vcycle(stgmg_handle* h, int l, const double* b, double* d);
+
+// reduced solves: all blocks of a level inverted by the kernel that holds a matrix in LDS
+bool red_blocks_in_lds(const stgmg::TimeBlockConsts& tb, int max_nr, int max_nn) {
+  bool any_c = false;
+  for (int a = 0; a < tb.nblk; ++a) any_c = any_c || tb.cplx[a];
+  return stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
+         stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block();
+}
+
+// symmetric tiles need real kept eigenvalues > 0 (real square roots); true for dG(k)
+bool red_sym_possible(const stgmg::TimeBlockConsts& tb) {
+  for (int a = 0; a < tb.nblk; ++a)
+    if (!tb.cplx[a] && !(tb.lam[2 * a] > 0.0)) return false;
+  return true;
+}
+
+// 8x8 tiles of the lower triangle of an nr x nr matrix
+int64_t red_sym_tiles(int nr) {
+  const int64_t b = (nr + 7) / 8;
+  return b * (b + 1) / 2;
+}
 
 // Event pair around one launch of kernel class `what` on the finest level.
 struct ProfScope {
@@ -311,11 +333,11 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
       ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
       const bool f32 = h->prm.smoother_prec == STGMG_FP32;
       if (h->red && f32)
-        stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, h->tbc, h->prm.dim, L.poff.p,
-                                     L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
+        stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->tbc, h->prm.dim,
+                                     L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
       else if (h->red)
-        stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, h->tbc, h->prm.dim, L.poff.p,
-                                     L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
+        stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->tbc, h->prm.dim,
+                                     L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
       else if (h->tb && f32)
         stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r,
                                     L.y.p);
@@ -364,7 +386,7 @@ void build(stgmg_handle* h) {
   h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
   h->T = stgmg::make_time_consts(p.k, p.tau);
   h->tb = p.time_blocks != 0;
-  h->red = p.time_blocks == 2;
+  h->red = p.time_blocks >= 2;
   h->top.nt = p.k + 1;
   for (int b = 0; b <= p.k; ++b) {
     h->top.mt[b] = h->T.mt[b];
@@ -527,26 +549,41 @@ void build(stgmg_handle* h) {
       D.pdof_h = H.pdof;
       D.ioff_h.assign(H.npatch + 1, 0);
       int max_np = 0;
-      if (h->red) D.pnu_h.assign(H.npatch, 0);
-      for (int64_t q = 0; q < H.npatch; ++q) {
-        const int64_t np = H.poff[q + 1] - H.poff[q];
-        max_np = std::max<int>(max_np, int(np));
-        if (h->red) {
+      bool red_in_lds = false;
+      if (h->red) {
+        D.pnu_h.assign(H.npatch, 0);
+        for (int64_t q = 0; q < H.npatch; ++q) {
           // time node 0 of the patch: V dofs (spatial numbers < nv), U dofs, P dofs
-          const int64_t ns = np / (p.k + 1);
+          const int64_t ns = (H.poff[q + 1] - H.poff[q]) / (p.k + 1);
           int64_t nU = 0;
           for (int64_t t = 0; t < ns; ++t) nU += H.pdof[H.poff[q] + t] < H.nv ? 1 : 0;
-          const int64_t nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
+          const int64_t nP = ns - 2 * nU, nr = nU + nP;
           if (nU % d != 0 || nP < 0) throw ApiError(STGMG_ERR_HIP, "unexpected patch layout");
           D.pnu_h[q] = int32_t(nU);
           D.max_nu = std::max<int>(D.max_nu, int(nU));
           D.max_nr = std::max<int>(D.max_nr, int(nr));
           D.max_npr = std::max<int>(D.max_npr, int(nP));
+        }
+        red_in_lds = red_blocks_in_lds(h->tbc, D.max_nr, D.max_nu / d);
+        D.sym = p.time_blocks == 3 && red_in_lds && red_sym_possible(h->tbc);
+      }
+      for (int64_t q = 0; q < H.npatch; ++q) {
+        const int64_t np = H.poff[q + 1] - H.poff[q];
+        max_np = std::max<int>(max_np, int(np));
+        if (h->red) {
+          const int64_t ns = np / (p.k + 1), nU = D.pnu_h[q];
+          const int64_t nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
           int64_t sz = nn * stgmg::inv_ld(int(nn)) + nU * stgmg::inv_ld(int(nP));
           D.alg_inv_entries += double(nn * nn + nP * nU);
           for (int a = 0; a < h->tbc.nblk; ++a) {
-            sz += h->tbc.cplx[a] ? nr * 2 * stgmg::inv_ld(int(nr)) : nr * stgmg::inv_ld(int(nr));
-            D.alg_inv_entries += double(h->tbc.cplx[a] ? 2 * nr * nr : nr * nr);
+            const int64_t planes = h->tbc.cplx[a] ? 2 : 1;
+            if (D.sym) {
+              sz += planes * red_sym_tiles(int(nr)) * 64;
+              D.alg_inv_entries += double(planes * nr * (nr + 1) / 2);
+            } else {
+              sz += planes * nr * stgmg::inv_ld(int(nr));
+              D.alg_inv_entries += double(planes * nr * nr);
+            }
           }
           D.ioff_h[q + 1] = D.ioff_h[q] + sz;
         } else if (h->tb) {
@@ -625,8 +662,8 @@ void build(stgmg_handle* h) {
         for (int a = 0; a < nblk; ++a) any_c = any_c || h->tbc.cplx[a];
         // blocks held entirely in LDS when they fit in one workgroup's LDS (complex blocks then
         // inverted in complex arithmetic), else the panel kernel on the 2x2-block real form
-        const bool in_lds = stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
-                            stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block();
+        const bool in_lds = red_in_lds;
+        (void)any_c;
         int64_t per_patch = int64_t(max_nn) * max_nn;
         std::vector<int64_t> blk_woff(nblk);
         for (int a = 0; a < nblk; ++a) {
@@ -640,35 +677,53 @@ void build(stgmg_handle* h) {
         if (stgmg::patch_apply_red_threads(max_nr, p.smoother_prec == STGMG_FP32) > 512 || D.max_nu > 64 * 32)
           throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the reduced patch solve");
         const int64_t sq = int64_t(max_ns) * max_ns;
-        const int64_t batch =
-            std::max<int64_t>(1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
-        DArr<double> Wb, wmm, wkk;
+        // symmetric tiles: the Schur blocks are inverted into a square FP64 scratch per batch
+        // item and packed from there
+        int64_t sq_item = 0;
+        if (D.sym)
+          for (int a = 0; a < nblk; ++a) sq_item += (h->tbc.cplx[a] ? 2 : 1) * int64_t(max_nr) * stgmg::inv_ld(max_nr);
+        const int64_t batch = std::max<int64_t>(
+            1, std::min<int64_t>(H.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq + sq_item) * 8)));
+        DArr<double> Wb, wmm, wkk, Sq;
         Wb.alloc(batch * per_patch, nullptr, h->st);
         wmm.alloc(batch * sq, nullptr, h->st);
         wkk.alloc(batch * sq, nullptr, h->st);
+        if (D.sym) Sq.alloc(batch * sq_item, nullptr, h->st);
         std::vector<std::vector<stgmg::GjDesc>> descs;
-        std::vector<std::vector<int32_t>> nss, nus;
+        std::vector<std::vector<int32_t>> nss, nus, nrs;
+        std::vector<std::vector<int64_t>> soffs, toffs;
         std::vector<DArr<stgmg::GjDesc>> ddesc;
-        std::vector<DArr<int32_t>> dns, dnu;
+        std::vector<DArr<int32_t>> dns, dnu, dnr;
+        std::vector<DArr<int64_t>> dsoff, dtoff;
         for (int64_t p0 = 0; p0 < H.npatch; p0 += batch) {
           const int64_t cnt = std::min(batch, H.npatch - p0);
           std::vector<stgmg::GjDesc> dd(cnt * (nblk + 1));
-          std::vector<int32_t> ns_of(cnt), nu_of(cnt);
+          std::vector<int32_t> ns_of(cnt), nu_of(cnt), nr_of(cnt);
+          std::vector<int64_t> soff(D.sym ? cnt * nblk : 0), toff(D.sym ? cnt * nblk : 0);
           for (int64_t i = 0; i < cnt; ++i) {
             const int ns = int(H.poff[p0 + i + 1] - H.poff[p0 + i]) / nt, nU = D.pnu_h[p0 + i];
             const int nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
             const int ldn = stgmg::inv_ld(nn), ldp = stgmg::inv_ld(nP), ldr = stgmg::inv_ld(nr);
             ns_of[i] = ns;
             nu_of[i] = nU;
+            nr_of[i] = nr;
             int64_t oo = D.ioff_h[p0 + i];
             dd[i * (nblk + 1)] = {nn, nn, ldn, 0, 0, int32_t(p0 + i), i * per_patch, oo};
             oo += int64_t(nn) * ldn + int64_t(nU) * ldp;
+            int64_t so = i * sq_item;
             for (int a = 0; a < nblk; ++a) {
               const bool c = h->tbc.cplx[a] != 0;
               const int n_in = c && !in_lds ? 2 * nr : nr;  // LDS kernel: complex n x n
               dd[i * (nblk + 1) + 1 + a] = {n_in, nr, c ? 2 * ldr : ldr, c ? nr : 0, ldr,
-                                            int32_t(p0 + i), i * per_patch + blk_woff[a], oo};
-              oo += int64_t(nr) * (c ? 2 * ldr : ldr);
+                                            int32_t(p0 + i), i * per_patch + blk_woff[a], D.sym ? so : oo};
+              if (D.sym) {
+                soff[i * nblk + a] = so;
+                toff[i * nblk + a] = oo;
+                so += int64_t(nr) * (c ? 2 * ldr : ldr);
+                oo += (c ? 2 : 1) * red_sym_tiles(nr) * 64;
+              } else {
+                oo += int64_t(nr) * (c ? 2 * ldr : ldr);
+              }
             }
           }
           // descriptors grouped by kernel for the LDS path: mass blocks, real blocks, complex blocks
@@ -699,6 +754,17 @@ void build(stgmg_handle* h) {
           dns.back().upload(nss.back(), h->st, nullptr);
           dnu.emplace_back();
           dnu.back().upload(nus.back(), h->st, nullptr);
+          if (D.sym) {
+            nrs.push_back(std::move(nr_of));
+            soffs.push_back(std::move(soff));
+            toffs.push_back(std::move(toff));
+            dnr.emplace_back();
+            dnr.back().upload(nrs.back(), h->st, nullptr);
+            dsoff.emplace_back();
+            dsoff.back().upload(soffs.back(), h->st, nullptr);
+            dtoff.emplace_back();
+            dtoff.back().upload(toffs.back(), h->st, nullptr);
+          }
           stgmg::k_fill_zero(h->st, wmm.p, cnt * sq);
           stgmg::k_fill_zero(h->st, wkk.p, cnt * sq);
           stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
@@ -706,7 +772,13 @@ void build(stgmg_handle* h) {
           if (p.smoother_prec == STGMG_FP32) {
             stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv32.p);
-            if (in_lds) {
+            if (in_lds && D.sym) {
+              stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+              stgmg::k_pack_red_sym_f32(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
+                                        dtoff.back().p, Sq.p, D.inv32.p);
+            } else if (in_lds) {
               stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
               stgmg::k_gj_lds_f32(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv32.p, stat.p);
               stgmg::k_gj_lds_f32(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv32.p, stat.p);
@@ -718,7 +790,13 @@ void build(stgmg_handle* h) {
           } else {
             stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv64.p);
-            if (in_lds) {
+            if (in_lds && D.sym) {
+              stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+              stgmg::k_pack_red_sym_f64(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
+                                        dtoff.back().p, Sq.p, D.inv64.p);
+            } else if (in_lds) {
               stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv64.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv64.p, stat.p);
@@ -1209,6 +1287,18 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
           const bool c = tb.cplx[a] != 0;
           const int64_t ldc = c ? 2 * ldr : ldr;
           const std::complex<double> lam(tb.lam[2 * a], tb.lam[2 * a + 1]);
+          // S(lam)^{-1}(i, q): square column-major, or D2 X D1 from the symmetric tiles
+          const std::complex<double> mu2 = std::sqrt(lam), mu1 = -1.0 / mu2;
+          const int64_t ntl = red_sym_tiles(nr);
+          auto sinv = [&](int i, int q) -> std::complex<double> {
+            if (!D.sym) return {st[off + size_t(q) * ldc + i], c ? st[off + size_t(q) * ldc + ldr + i] : 0.0};
+            const int hi = std::max(i, q), lo = std::min(i, q), I = hi / 8, J = lo / 8;
+            const int64_t e = (int64_t(I) * (I + 1) / 2 + J) * 64 + (lo % 8) * 8 + hi % 8;  // column-major tile
+            std::complex<double> x(st[off + e], c ? st[off + ntl * 64 + e] : 0.0);
+            if (i >= nU) x *= mu2;
+            if (q >= nU) x *= mu1;
+            return x;
+          };
           X[a].assign(size_t(ns) * ns, 0.0);
           std::vector<std::complex<double>> w(nU), z(nr), t(nr);
           for (int j = 0; j < ns; ++j) {
@@ -1227,15 +1317,13 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
             }
             for (int i = 0; i < nr; ++i) {
               std::complex<double> acc = 0.0;
-              for (int q = 0; q < nr; ++q)
-                acc += std::complex<double>(st[off + size_t(q) * ldc + i], c ? st[off + size_t(q) * ldc + ldr + i] : 0.0) *
-                       z[q];
+              for (int q = 0; q < nr; ++q) acc += sinv(i, q) * z[q];
               t[i] = acc;
             }
             for (int i = 0; i < ns; ++i)
               X[a][size_t(i) * ns + j] = i < nU ? lam * t[i] - w[i] : t[i - nU];
           }
-          off += int64_t(nr) * ldc;
+          off += D.sym ? (c ? 2 : 1) * ntl * 64 : int64_t(nr) * ldc;
         }
       }
       // A_P^{-1}[(b,i)][(c,j)] = sum_a Q[b][a] X_a[i][j] Tin[a][c] (pairs: twice the real part)
@@ -1271,9 +1359,13 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
     const int64_t w = p.smoother_prec == STGMG_FP32 ? 4 : 8;
     int64_t res = 0, temp_peak = 0, n_prev = 0, n_fine = 0;
     int nreal = 0, ncplx = 0;
+    bool sym_ok = true;  // real kept eigenvalues > 0
     if (p.time_blocks) {
       const stgmg::TimeBlocks B = stgmg::make_time_blocks(stgmg::make_time_consts(p.k, p.tau));
-      for (int a = 0; a < B.nblk; ++a) (B.is_complex[a] ? ncplx : nreal)++;
+      for (int a = 0; a < B.nblk; ++a) {
+        (B.is_complex[a] ? ncplx : nreal)++;
+        if (!B.is_complex[a] && !(B.lam[a].real() > 0.0)) sym_ok = false;
+      }
     }
     for (int l = 0; l <= L; ++l) {
       const stgmg::LevelSizes S = stgmg::level_sizes(d, p.r, p.k, p.coarse_cells << l, p.patch,
@@ -1297,18 +1389,21 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
               std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / (stride * 8)));
           temp_peak = std::max(temp_peak, batch * stride * 8 + batch * 8 + int64_t(sizeof(stgmg::GjDesc)) * batch +
                                               S.npatch * 4);
-        } else if (p.time_blocks == 2) {
-          res += (S.sum_red_fixed + (nreal + 2 * ncplx) * S.sum_nr_ldr) * w + S.npatch * 4;
+        } else if (p.time_blocks >= 2) {
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
           const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
                               stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
+          const bool sym = p.time_blocks == 3 && in_lds && sym_ok;
+          res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? S.sum_tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
                                     (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
-          const int64_t batch =
-              std::max<int64_t>(1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq) * 8)));
-          temp_peak = std::max(temp_peak, batch * (per_patch + 2 * sq) * 8 +
+          const int64_t sq_item = sym ? (nreal + 2 * ncplx) * int64_t(S.max_nr) * stgmg::inv_ld(S.max_nr) : 0;
+          const int64_t batch = std::max<int64_t>(
+              1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq + sq_item) * 8)));
+          temp_peak = std::max(temp_peak, batch * (per_patch + 2 * sq + sq_item) * 8 +
                                               2 * int64_t(sizeof(stgmg::GjDesc)) * batch * (nreal + ncplx + 1) +
-                                              2 * batch * 4 + S.npatch * 4);
+                                              (sym ? 3 : 2) * batch * 4 + (sym ? 2 * batch * (nreal + ncplx) * 8 : 0) +
+                                              S.npatch * 4);
         } else {
           res += (nreal + 2 * ncplx) * S.sum_ns_ldh * w;
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;

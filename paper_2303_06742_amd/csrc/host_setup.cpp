@@ -1567,6 +1567,7 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bo
     S.sum_nr_ldr += mult * nr * ld4(nr);
     S.alg_red_fixed += mult * (q * q + pp * nU);
     S.sum_nr2 += mult * nr * nr;
+    S.sum_tiles += mult * ((nr + 7) / 8) * ((nr + 7) / 8 + 1) / 2;
     S.max_nr = std::max<int>(S.max_nr, int(nr));
     S.max_nn = std::max<int>(S.max_nn, int(q));
   }

@@ -90,12 +90,24 @@ void k_gj_lds_f64(hipStream_t st, bool cplx, int64_t count, int max_n, const GjD
 void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
                   float* out, int32_t* status);
 int patch_apply_red_threads(int max_nr, bool fp32);
-void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+// sym: the Schur inverses stored as symmetric 8x8 tiles of X = D2^{-1} S^{-1} D1^{-1} (see
+// k_pack_red_sym_*), applied by one wave per patch; else square, column-major, padded.
+void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
                            const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y);
-void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
                            const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y);
+// Symmetric tiles from square Schur inverses: one (batch item i, kept eigenvalue a) per block m =
+// i * nblk + a: S^{-1} square in sq at soff[m] (as written by k_gj_lds_f64 with ld_out = ldr or
+// 2 ldr), tiles of X = D2^{-1} S^{-1} D1^{-1}, (X + X^T)/2, written at out + toff[m]:
+// ntl = b(b+1)/2 tiles of 64 values, b = ceil(nr/8), lower tiles I-major, row-major inside,
+// complex: Re tiles then Im tiles.  D1 = diag(I_nU, mu1), D2 = diag(I_nU, mu2), mu2 = sqrt(lam),
+// mu1 = -1/mu2.  All real kept eigenvalues must be positive.
+void k_pack_red_sym_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
+                        const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, double* out);
+void k_pack_red_sym_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
+                        const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, float* out);
 // Block size used by the patch GEMV for patches of at most max_np rows.
 int patch_apply_threads(int max_np, bool fp32);
 void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,

@@ -860,6 +860,82 @@ __global__ void __launch_bounds__(512) patch_apply_tb_kernel(TimeBlockConsts tb,
 // rows per thread (one 16-byte load per column).
 constexpr int RED_MAXB = 2;
 
+// Balanced symmetrising factors of a Schur complement S(lam) = [[lam^2 rho M + A, C^T],
+// [-lam C, lam c0 M_p + B]]: with mu2 = sqrt(lam) (principal root) and mu1 = -1/mu2,
+// D1 S D2 is (complex) symmetric for D1 = diag(I_nU, mu1 I_nP), D2 = diag(I_nU, mu2 I_nP)
+// (mu2 C^T is the transpose of -lam mu1 C, and mu1 mu2 = -1 leaves the pressure block symmetric).
+__device__ inline void sym_factors(double al, double be, double* m1r, double* m1i, double* m2r, double* m2i) {
+  const double mod = sqrt(al * al + be * be);
+  const double sr = sqrt(0.5 * (mod + al)), si = copysign(sqrt(0.5 * fmax(mod - al, 0.0)), be);
+  const double q = sr * sr + si * si;
+  *m2r = sr;
+  *m2i = si;
+  *m1r = -sr / q;
+  *m1i = si / q;
+}
+
+// Symmetric tiled storage of the Schur inverses: X = (D1 S D2)^{-1} = D2^{-1} S^{-1} D1^{-1} is
+// symmetric; its lower 8x8 tiles (I, J), J <= I, are stored I-major (tile index I(I+1)/2 + J),
+// each column-major (entry (r, c) = X[8I + r][8J + c] at 8c + r, zero beyond nr); a complex X
+// as the Re tiles followed by the Im tiles.  One block per (batch item, kept eigenvalue); S^{-1} is read
+// from the square scratch (column j of Re at soff + j * ldc, Im rows after ldr) and
+// symmetrised as (X + X^T) / 2.
+template <typename T>
+__global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, const int32_t* __restrict__ nu_of,
+                                                           const int32_t* __restrict__ nr_of,
+                                                           const int64_t* __restrict__ soff,
+                                                           const int64_t* __restrict__ toff,
+                                                           const double* __restrict__ sq, T* __restrict__ out) {
+  const int nblk = tb.nblk;
+  const int64_t m = blockIdx.x;
+  const int64_t i = m / nblk;
+  const int a = int(m % nblk);
+  const int nU = nu_of[i], nr = nr_of[i], ldr = inv_ld(nr);
+  const bool cp = tb.cplx[a] != 0;
+  const int ldc = cp ? 2 * ldr : ldr;
+  const int nbk = (nr + 7) >> 3, ntl = nbk * (nbk + 1) / 2;
+  double m1r, m1i, m2r, m2i;
+  sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
+  // 1/mu2 and 1/mu1 = -mu2
+  const double q2 = m2r * m2r + m2i * m2i;
+  const double f2r = m2r / q2, f2i = -m2i / q2, g1r = -m2r, g1i = -m2i;
+  const double* S = sq + soff[m];
+  T* o = out + toff[m];
+  auto X = [&](int row, int col, double* xr, double* xi) {  // S^{-1}(row, col) / (d2_row d1_col)
+    double vr = S[int64_t(col) * ldc + row], vi = cp ? S[int64_t(col) * ldc + ldr + row] : 0.0;
+    if (row >= nU) {
+      const double tr = vr * f2r - vi * f2i, ti = vr * f2i + vi * f2r;
+      vr = tr;
+      vi = ti;
+    }
+    if (col >= nU) {
+      const double tr = vr * g1r - vi * g1i, ti = vr * g1i + vi * g1r;
+      vr = tr;
+      vi = ti;
+    }
+    *xr = vr;
+    *xi = vi;
+  };
+  for (int q = threadIdx.x; q < ntl * 64; q += blockDim.x) {
+    const int t = q >> 6, e = q & 63;
+    int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > t) --I;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    const int row = 8 * I + (e & 7), col = 8 * J + (e >> 3);
+    double vr = 0.0, vi = 0.0;
+    if (row < nr && col < nr) {
+      double ar, ai, br, bi;
+      X(row, col, &ar, &ai);
+      X(col, row, &br, &bi);
+      vr = 0.5 * (ar + br);
+      vi = 0.5 * (ai + bi);
+    }
+    o[q] = T(vr);
+    if (cp) o[int64_t(ntl) * 64 + q] = T(vi);
+  }
+}
+
 
 template <typename T, bool NTL>
 __device__ inline T bld1(__amdgpu_buffer_rsrc_t rs, int voff) {
@@ -883,15 +959,108 @@ __device__ inline __amdgpu_buffer_rsrc_t patch_rsrc(const T* p, int64_t count) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, int(count * int64_t(sizeof(T))), 0x00020000);
 }
 
-template <typename T, int R, bool NTL>
-__global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb, int d, int W, int xc,
-                                                              const int64_t* __restrict__ poff,
-                                                              const int32_t* __restrict__ pdof,
-                                                              const int32_t* __restrict__ tpos,
-                                                              const int32_t* __restrict__ pnu,
-                                                              const int64_t* __restrict__ ioff,
-                                                              const T* __restrict__ inv, const double* __restrict__ r,
-                                                              double* __restrict__ y) {
+// Sum of a double over the 8 consecutive lanes of each group (lanes 8g .. 8g+7), through DPP
+// (quad xor 1, quad xor 2, mirror within 8); every lane of the group ends with the sum.
+__device__ inline double dpp_sum8(double v) {
+  auto step = [](double x, int ctrl) {
+    const int2 b = __builtin_bit_cast(int2, x);
+    int2 o;
+    switch (ctrl) {
+      case 0:
+        o.x = __builtin_amdgcn_update_dpp(0, b.x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+        o.y = __builtin_amdgcn_update_dpp(0, b.y, 0xB1, 0xF, 0xF, false);
+        break;
+      case 1:
+        o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+        o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x4E, 0xF, 0xF, false);
+        break;
+      default:
+        o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+        o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x141, 0xF, 0xF, false);
+        break;
+    }
+    return x + __builtin_bit_cast(double, o);
+  };
+  v = step(v, 0);
+  v = step(v, 1);
+  return step(v, 2);
+}
+
+// y += X zt for one plane of symmetric tiles (ntl lower 8x8 tiles, I-major, column-major inside;
+// see pack_red_sym_kernel), one wave: lane (r, c) = (lane % 8, lane / 8) of tile (I, J) adds
+// X[8I+r][8J+c] zt[8J+c] to its row partial (summed over c when block row I closes) and, below
+// the diagonal, X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  zt and y are
+// LDS vectors (re at [0, ldt), im at [ldt, 2 ldt)); y must start at zero.
+template <typename T, bool NTL, bool CP>
+__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const double* zt, int ldt, double* y) {
+  const int lane = threadIdx.x & 63, rr = lane & 7, cc = lane >> 3;
+  const double* zr = zt;
+  const double* zi = zt + ldt;
+  double* yr = y;
+  double* yi = y + ldt;
+  const int im = ntl * 64 * int(sizeof(T));
+  int I = 0, J = 0;
+  double rowr = 0.0, rowi = 0.0;
+  for (int t0 = 0; t0 < ntl; t0 += 8) {
+    T xr[8], xi[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool ok = t0 + u < ntl;
+      const int e = ((t0 + u) * 64 + lane) * int(sizeof(T));
+      xr[u] = ok ? bld1<T, NTL>(rs, e) : T(0);
+      if constexpr (CP) xi[u] = ok ? bld1<T, NTL>(rs, e + im) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (t0 + u >= ntl) break;
+      const double ar = double(xr[u]);
+      const double ai = CP ? double(xi[u]) : 0.0;
+      const double zjr = zr[8 * J + cc];
+      if constexpr (CP) {
+        const double zji = zi[8 * J + cc];
+        rowr += ar * zjr - ai * zji;
+        rowi += ar * zji + ai * zjr;
+      } else {
+        rowr += ar * zjr;
+      }
+      if (J < I) {  // the transposed entry: column 8J + c of row 8I + r, summed over r
+        const double zir = zr[8 * I + rr];
+        if constexpr (CP) {
+          const double zii = zi[8 * I + rr];
+          const double cr = dpp_sum8(ar * zir - ai * zii), ci = dpp_sum8(ar * zii + ai * zir);
+          if (rr == 0) {
+            yr[8 * J + cc] += cr;
+            yi[8 * J + cc] += ci;
+          }
+        } else {
+          const double cr = dpp_sum8(ar * zir);
+          if (rr == 0) yr[8 * J + cc] += cr;
+        }
+        ++J;
+      } else {  // the diagonal tile closes block row I: sum the row partials over c
+#pragma unroll
+        for (int sh = 8; sh < 64; sh <<= 1) {
+          rowr += __shfl_xor(rowr, sh);
+          if constexpr (CP) rowi += __shfl_xor(rowi, sh);
+        }
+        if (cc == 0) {
+          yr[8 * I + rr] += rowr;
+          if constexpr (CP) yi[8 * I + rr] += rowi;
+        }
+        rowr = rowi = 0.0;
+        ++I;
+        J = 0;
+      }
+    }
+  }
+}
+
+template <typename T, int R, bool NTL, bool SYM>
+__device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, int W, int xc,
+                                                     const int64_t* __restrict__ poff, const int32_t* __restrict__ pdof,
+                                                     const int32_t* __restrict__ tpos, const int32_t* __restrict__ pnu,
+                                                     const int64_t* __restrict__ ioff, const T* __restrict__ inv,
+                                                     const double* __restrict__ r, double* __restrict__ y) {
   typedef T V __attribute__((ext_vector_type(R)));
   extern __shared__ double sm[];
   const int64_t p = xcd_chunk(blockIdx.x, gridDim.x, xc);
@@ -992,8 +1161,53 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
     }
   }
   __syncthreads();
-  // [U; P] = S^{-1} z per kept eigenvalue
-  {
+  // symmetric tiles (one wave): t = D2 X D1 z per kept eigenvalue into region B, stride LDT
+  const int LDT = SYM ? 8 * ((nr + 7) >> 3) : ldr;
+  if constexpr (SYM) {
+    const int nbk = (nr + 7) >> 3, ntl = nbk * (nbk + 1) / 2;
+    double* tt = tv;                   // [a][re, im][LDT], read by the back-transform
+    double* zt = tv + 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
+    for (int x = threadIdx.x; x < LDT; x += blockDim.x)
+#pragma unroll
+      for (int a = 0; a < RED_MAXB; ++a)
+        if (a < nblk) {
+          double m1r, m1i, m2r, m2i;
+          sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
+          double vr = x < nr ? z[(2 * a) * ldr + x] : 0.0, vi = x < nr ? z[(2 * a + 1) * ldr + x] : 0.0;
+          if (x >= nU) {
+            const double ur = vr * m1r - vi * m1i, ui = vr * m1i + vi * m1r;
+            vr = ur;
+            vi = ui;
+          }
+          zt[(2 * a) * LDT + x] = vr;
+          zt[(2 * a + 1) * LDT + x] = vi;
+          tt[(2 * a) * LDT + x] = 0.0;
+          tt[(2 * a + 1) * LDT + x] = 0.0;
+        }
+    __syncthreads();
+    int64_t off = base + nsmall;
+    for (int a = 0; a < nblk; ++a) {
+      const bool cp = tb.cplx[a] != 0;
+      const int64_t cnt = int64_t(cp ? 2 : 1) * ntl * 64;
+      const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
+      if (cp)
+        sym_tiles_apply<T, NTL, true>(rs, ntl, zt + (2 * a) * LDT, LDT, tt + (2 * a) * LDT);
+      else
+        sym_tiles_apply<T, NTL, false>(rs, ntl, zt + (2 * a) * LDT, LDT, tt + (2 * a) * LDT);
+      off += cnt;
+    }
+    __syncthreads();
+    for (int x = nU + threadIdx.x; x < nr; x += blockDim.x)  // t_P = mu2 (X D1 z)_P
+#pragma unroll
+      for (int a = 0; a < RED_MAXB; ++a)
+        if (a < nblk) {
+          double m1r, m1i, m2r, m2i;
+          sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
+          const double vr = tt[(2 * a) * LDT + x], vi = tt[(2 * a + 1) * LDT + x];
+          tt[(2 * a) * LDT + x] = vr * m2r - vi * m2i;
+          tt[(2 * a + 1) * LDT + x] = vr * m2i + vi * m2r;
+        }
+  } else {
     const int per_w = blockDim.x / W;
     const int w = threadIdx.x / per_w, tl = threadIdx.x % per_w;
     const int i0 = R * tl;
@@ -1085,7 +1299,8 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
     }
   }
   __syncthreads();
-  // spatial images [lam U - w; U; P], transformed back to the time nodes
+  // spatial images [lam U - w; U; P], transformed back to the time nodes (products at stride
+  // LDT: the square path's W partial images, or the tiled path's single result)
   for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     const int ii = i < nU ? i : i - nU;
     double hr[RED_MAXB], hi[RED_MAXB];
@@ -1094,8 +1309,8 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
       if (a < nblk) {
         double t_r = 0.0, t_i = 0.0;
         for (int ww = 0; ww < W; ++ww) {
-          t_r += tv[(int64_t(ww) * nblk + a) * 2 * ldr + ii];
-          t_i += tv[(int64_t(ww) * nblk + a) * 2 * ldr + ldr + ii];
+          t_r += tv[(int64_t(ww) * nblk + a) * 2 * LDT + ii];
+          t_i += tv[(int64_t(ww) * nblk + a) * 2 * LDT + LDT + ii];
         }
         if (i < nU) {
           const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
@@ -1117,6 +1332,33 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
       y[tpos[o + b * ns + i]] = acc;
     }
   }
+}
+
+// Square Schur inverses: W column ranges per block of up to 512 threads.
+template <typename T, int R, bool NTL>
+__global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb, int d, int W, int xc,
+                                                              const int64_t* __restrict__ poff,
+                                                              const int32_t* __restrict__ pdof,
+                                                              const int32_t* __restrict__ tpos,
+                                                              const int32_t* __restrict__ pnu,
+                                                              const int64_t* __restrict__ ioff,
+                                                              const T* __restrict__ inv, const double* __restrict__ r,
+                                                              double* __restrict__ y) {
+  patch_apply_red_body<T, R, NTL, false>(tb, d, W, xc, poff, pdof, tpos, pnu, ioff, inv, r, y);
+}
+
+// Symmetric tiles: one wave per patch; the register budget is held to STGMG_SYM_WAVES waves per
+// SIMD (the kernel is bound by HBM streams, which want many waves in flight).
+#ifndef STGMG_SYM_WAVES
+#define STGMG_SYM_WAVES 6
+#endif
+template <typename T, bool NTL>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(STGMG_SYM_WAVES)))
+patch_apply_red_sym_kernel(TimeBlockConsts tb, int d, int xc, const int64_t* __restrict__ poff,
+                           const int32_t* __restrict__ pdof, const int32_t* __restrict__ tpos,
+                           const int32_t* __restrict__ pnu, const int64_t* __restrict__ ioff,
+                           const T* __restrict__ inv, const double* __restrict__ r, double* __restrict__ y) {
+  patch_apply_red_body<T, 2, NTL, true>(tb, d, 1, xc, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 
 // G = KK_pV ((rho M)^{-1} (x) I_d) in place of KK_pV in the stored layout of the reduced
@@ -1636,23 +1878,40 @@ int patch_apply_red_threads(int max_nr, bool fp32) {
 
 // tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
-static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
                        const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int32_t* pnu, const int64_t* ioff, const T* inv, const double* r, double* y) {
   if (npatch == 0) return;
   const int rr = red_rows(sizeof(T) == 4, max_nr);
   int th, W;
   red_layout(max_nr, rr, &th, &W);
+  size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
+  if (sym) {  // one wave per patch; region B holds the products and D1 z at stride 8 ceil(nr / 8)
+    th = 64;
+    W = 1;
+    const size_t ldr = inv_ld(max_nr), ns = max_np / tb.nt, ldt = 8 * ((max_nr + 7) / 8);
+    const size_t a = std::max<size_t>(max_np, 2 * size_t(tb.nblk) * (max_nu + ldr));
+    const size_t b = std::max<size_t>(2 * size_t(tb.nblk) * ns, 4 * size_t(tb.nblk) * ldt);
+    lds = (a + b) * sizeof(double);
+  }
   bool ntl = true;
   if (const char* e = std::getenv("STGMG_RED_NT")) ntl = std::atoi(e) != 0;
   // chunks of 16 patches per XCD: measured best of {off, 16, 64, 256, 1024, contiguous} on the
   // 256^2 dG(2) workload (the dof-major image writes of neighbouring patches share lines)
   int xc = 16;
   if (const char* e = std::getenv("STGMG_XCD_CHUNK")) xc = std::atoi(e);  // tuning: 0 = round-robin
-  const size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
 #define STGMG_RED(RR, NT)                                                                                       \
   hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, RR, NT>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff, \
                      pdof, tpos, pnu, ioff, inv, r, y)
+  if (sym) {
+    if (ntl)
+      hipLaunchKernelGGL((dev::patch_apply_red_sym_kernel<T, true>), dim3(npatch), dim3(64), lds, st, tb, d, xc, poff,
+                         pdof, tpos, pnu, ioff, inv, r, y);
+    else
+      hipLaunchKernelGGL((dev::patch_apply_red_sym_kernel<T, false>), dim3(npatch), dim3(64), lds, st, tb, d, xc,
+                         poff, pdof, tpos, pnu, ioff, inv, r, y);
+    return;
+  }
   if constexpr (sizeof(T) == 4) {
     if (rr == 4) {
       if (ntl) STGMG_RED(4, true);
@@ -1665,15 +1924,28 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
 #undef STGMG_RED
 }
 
-void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
                            const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y) {
-  launch_red<double>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
+  launch_red<double>(st, npatch, max_np, max_nu, max_nr, sym, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
-void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr,
+void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
                            const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y) {
-  launch_red<float>(st, npatch, max_np, max_nu, max_nr, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
+  launch_red<float>(st, npatch, max_np, max_nu, max_nr, sym, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
+}
+
+void k_pack_red_sym_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
+                        const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, double* out) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(dev::pack_red_sym_kernel<double>, dim3(count * tb.nblk), dim3(256), 0, st, tb, nu_of, nr_of, soff,
+                     toff, sq, out);
+}
+void k_pack_red_sym_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
+                        const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, float* out) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(dev::pack_red_sym_kernel<float>, dim3(count * tb.nblk), dim3(256), 0, st, tb, nu_of, nr_of, soff,
+                     toff, sq, out);
 }
 
 template <typename T>

@@ -39,8 +39,9 @@ class Config:
     omega: float = 0.7
     restart: int = 30
     rtol: float = 1e-8
-    # patch solves: 2 time blocks with the u-equation rows eliminated, 1 time blocks, 0 full inverses
-    time_blocks: int = 2
+    # patch solves: 3 reduced with symmetric tiled Schur inverses, 2 reduced (square), 1 time
+    # blocks, 0 full inverses
+    time_blocks: int = 3
     pressure: str = 'cont'  # 'cont': Q_{r-1} (Taylor-Hood); 'disc': P_{r-1}^disc with interior penalty
     form: str = 'v'         # 'v': Problem 3.1; 'dtu': Problem B.1
     extra: dict = field(default_factory=dict)

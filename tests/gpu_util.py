@@ -25,7 +25,7 @@ def to_host(t):
 def oracle_hierarchy(cfg_key):
     from oracle import gmg, problem
     # the storage of the patch solves does not change the operator
-    cfg_key = cfg_key.replace('_full', '').replace('_tb', '')
+    cfg_key = cfg_key.replace('_full', '').replace('_tb', '').replace('_red', '')
     cfg = CONFIGS[cfg_key]
     K = cfg.K_cells()
     prm = problem.Params(rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
@@ -63,6 +63,14 @@ CONFIGS = {
     # Problem B.1 (-C(d_t u, psi)): reduced, time-block and full patch solves, both pressure pairs
     'c2s_b1': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-b1', form='dtu'),
     'c1_b1': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1', form='dtu'),
+    # reduced solves with the square (column-major) Schur inverses instead of symmetric tiles
+    'c2s_red': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-red', time_blocks=2),
+    'c3s_red': W.scaled(W.C3, 2, name='3d-8cube-dg1-cell-lognormal-red', time_blocks=2),
+    'k3_red': W.scaled(W.C1, 2, name='2d-8x8-dg3-cell-red', k=3, time_blocks=2),
+    'c3v_red': W.scaled(W.C3, 2, name='3d-4cube-dg1-vertex-lognormal-red', coarse_cells=2, patch='vertex',
+                        time_blocks=2),
+    'c2d_red': W.scaled(W.C2D, 2, name='2d-8x8-q3p2disc-dg2-vertex-red', time_blocks=2),
+    'c2s_b1_red': W.scaled(W.C2, 3, name='2d-16x16-dg2-vertex-b1-red', form='dtu', time_blocks=2),
     'c1_b1_tb': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-tb', form='dtu', time_blocks=1),
     'c1_b1_full': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-full', form='dtu', time_blocks=0),
     'c3s_disc_b1': W.scaled(W.C3, 2, name='3d-8cube-q2p1disc-dg1-cell-lognormal-b1', pressure='disc', form='dtu'),

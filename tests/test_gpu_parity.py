@@ -28,7 +28,7 @@ def rel_err(a, b, scale=None):
 
 KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'k3', 'c3v', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb',
         'c3s_tb', 'k0_tb', 'c1_disc', 'c2d', 'c3s_disc', 'c2d_full', 'c2s_b1', 'c1_b1_tb', 'c1_b1_full',
-        'c3s_disc_b1']
+        'c3s_disc_b1', 'c2s_red', 'c3s_red', 'k3_red', 'c3v_red', 'c2d_red', 'c2s_b1_red']
 
 
 @pytest.mark.parametrize("key", KEYS)
@@ -162,7 +162,7 @@ def test_fp32_smoother_meets_tolerances():
     assert i32['iters'] <= i64['iters'] + 2
 
 
-@pytest.mark.parametrize("key", ['c2s_tb', 'c3s'])
+@pytest.mark.parametrize("key", ['c2s_tb', 'c3s', 'c2s_red', 'c3s_red'])
 def test_fp32_storage_meets_tolerances(key):
     """FP32 storage of the patch solves inside FP64 FGMRES (time blocks; reduced, FP64 sums)."""
     S64 = solver(key)

@@ -133,3 +133,75 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
         nrl += nr * ld4(nr)
         max_nr, max_nn = max(max_nr, nr), max(max_nn, nn)
     assert (S['sum_red_fixed'], S['sum_nr_ldr'], S['max_nr'], S['max_nn']) == (fixed, nrl, max_nr, max_nn)
+
+
+def sym_factors(lam):
+    """mu1, mu2 with D1 S(lam) D2 symmetric, D1 = diag(I_nU, mu1 I), D2 = diag(I_nU, mu2 I):
+    mu2 = principal sqrt(lam), mu1 = -1/mu2 (then mu2 C^T = (-lam mu1 C)^T and mu1 mu2 = -1)."""
+    mu2 = np.sqrt(complex(lam))
+    return -1.0 / mu2, mu2
+
+
+def pack_tiles(X, nr):
+    """Lower 8x8 tiles of the symmetric X, I-major (tile (I, J), J <= I, at I(I+1)/2 + J), each
+    column-major (entry (r, c) at 8c + r); entries beyond nr are zero; X is symmetrised as
+    (X + X^T)/2."""
+    nb = (nr + 7) // 8
+    Xs = np.zeros((8 * nb, 8 * nb), dtype=complex)
+    Xs[:nr, :nr] = 0.5 * (X + X.T)
+    out = []
+    for I in range(nb):
+        for J in range(I + 1):
+            out.append(Xs[8 * I:8 * I + 8, 8 * J:8 * J + 8].reshape(-1, order='F'))
+    return np.concatenate(out)
+
+
+def tile_apply(tiles, nr, zt):
+    """y = X zt from the lower tiles the way one wave does it: lane (r, c) of tile (I, J) adds
+    X[8I+r][8J+c] zt[8J+c] to row 8I+r and, below the diagonal tiles, X[8I+r][8J+c] zt[8I+r]
+    to row 8J+c."""
+    nb = (nr + 7) // 8
+    y = np.zeros(8 * nb, dtype=complex)
+    t = 0
+    for I in range(nb):
+        for J in range(I + 1):
+            T = tiles[64 * t:64 * t + 64].reshape(8, 8, order='F')
+            y[8 * I:8 * I + 8] += T @ zt[8 * J:8 * J + 8]
+            if J < I:
+                y[8 * J:8 * J + 8] += T.T @ zt[8 * I:8 * I + 8]
+            t += 1
+    return y
+
+
+@pytest.mark.parametrize("d,N,k,kind", [(2, 4, 2, 'vertex'), (3, 2, 1, 'cell'), (2, 2, 1, 'vertex')])
+def test_symmetric_tiles_reproduce_the_schur_inverse(d, N, k, kind):
+    """The balanced scaling makes D1 S(lam) D2 symmetric for real and complex lam, and the
+    packed lower tiles of X = (D1 S D2)^{-1}, applied as D2 X D1 z, reproduce S(lam)^{-1} z."""
+    MM, KK, poff, pdof, nv, ns = build(d, N, k, kind, K=0.3)
+    rng = np.random.default_rng(4)
+    for p in sorted({0, (len(poff) - 1) // 2, len(poff) - 2}):
+        MMp, KKp, nU = patch_blocks(MM, KK, poff, pdof, nv, k, p)
+        nsp = MMp.shape[0]
+        nP = nsp - 2 * nU
+        nr = nU + nP
+        for lam in (1.7, 0.4 + 2.1j, 3.3 - 0.7j):
+            S = np.zeros((nr, nr), dtype=complex)
+            for x in range(nr):
+                for y in range(nr):
+                    A2 = MMp[nU + x, y] if y < nU else 0.0
+                    A1 = MMp[nU + x, nU + y] + (KKp[nU + x, y] if y < nU else 0.0)
+                    S[x, y] = lam * lam * A2 + lam * A1 + KKp[nU + x, nU + y]
+            mu1, mu2 = sym_factors(lam)
+            D1 = np.diag([1.0] * nU + [mu1] * nP)
+            D2 = np.diag([1.0] * nU + [mu2] * nP)
+            Ssym = D1 @ S @ D2
+            assert np.abs(Ssym - Ssym.T).max() <= 1e-13 * np.abs(Ssym).max()
+            X = np.linalg.inv(Ssym)
+            tiles = pack_tiles(X, nr)
+            assert len(tiles) == 64 * ((nr + 7) // 8) * ((nr + 7) // 8 + 1) // 2
+            z = rng.standard_normal(nr) + 1j * rng.standard_normal(nr)
+            zt = np.zeros(8 * ((nr + 7) // 8), dtype=complex)
+            zt[:nr] = np.diag(D1) * z
+            y = np.diag(D2) * tile_apply(tiles, nr, zt)[:nr]
+            ref = np.linalg.solve(S, z)
+            assert np.abs(y - ref).max() <= 1e-11 * np.abs(ref).max(), (p, lam)
