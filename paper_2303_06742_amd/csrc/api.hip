@@ -565,7 +565,10 @@ void build(stgmg_handle* h) {
           D.max_npr = std::max<int>(D.max_npr, int(nP));
         }
         red_in_lds = red_blocks_in_lds(h->tbc, D.max_nr, D.max_nu / d);
-        D.sym = p.time_blocks == 3 && red_in_lds && red_sym_possible(h->tbc);
+        // FP32 storage keeps the square layout: 4-byte tile loads (256 bytes per wave
+        // instruction) measured slower than the square GEMV's 8-byte column loads (256^2 dG(2):
+        // 1.09 against 0.82 ms)
+        D.sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && red_in_lds && red_sym_possible(h->tbc);
       }
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
@@ -1393,7 +1396,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
           const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
                               stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
-          const bool sym = p.time_blocks == 3 && in_lds && sym_ok;
+          const bool sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && in_lds && sym_ok;
           res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? S.sum_tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
                                     (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
