@@ -69,6 +69,32 @@ def measured_read_peak(torch):
     return best
 
 
+def dense_inverse_bytes(cfg, w=8):
+    """Bytes one finest-level sweep would move with the paper's dense patch inverses (Def:VankaOP
+    literally): w * sum over patches of n_P^2 + 32 n.  Patch sizes by closed form: per axis a
+    vertex patch spans 2 cells inside and 1 at the two boundary vertices, a cell patch 1."""
+    from itertools import product
+    from math import comb
+    d, r, k, N = cfg.dim, cfg.r, cfg.k, cfg.fine_cells
+    widths = [(2, N - 1), (1, 2)] if cfg.patch == 'vertex' else [(1, N)]
+    nlp = comb(r - 1 + d, d)
+    total = 0
+    for combo in product(widths, repeat=d):
+        mult, q, pp, cells = 1, 1, 1, 1
+        for wdt, cnt in combo:
+            mult *= cnt
+            q *= r * wdt + 1
+            pp *= (r - 1) * wdt + 1
+            cells *= wdt
+        if cfg.pressure == 'disc':
+            pp = cells * nlp
+        n_p = (k + 1) * (2 * d * q + pp)
+        total += mult * n_p * n_p
+    n1, n1p = r * N + 1, (r - 1) * N + 1
+    n_s = 2 * d * n1 ** d + (N ** d * nlp if cfg.pressure == 'disc' else n1p ** d)
+    return w * total + 32 * (k + 1) * n_s
+
+
 def configs():
     from paper_2303_06742_amd import workloads as W
     return {'c2': W.C2, 'c1': W.C1, 'c3': W.C3, 'c3v': W.C3V, 'c2d': W.C2D}
@@ -219,6 +245,8 @@ def main():
     ap.add_argument('--seed', type=int, default=0)
     ap.add_argument('--hbm-budget-gb', type=float, default=200.0)
     ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32'])
+    ap.add_argument('--graph', type=int, default=-1, choices=[-1, 0, 1],
+                    help='V-cycle as a captured HIP graph: -1 automatic (below 2^21 unknowns), 0 never, 1 always')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-sample-levels', type=int, default=None,
                     help='levels of the grid the oracle times (default: 32^2 cells in 2D, 8^3 in 3D)')
@@ -257,7 +285,7 @@ def main():
         del a, b
     print(f"[bench] setup {cfg.name} {args.precision}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    S = capi.Solver(cfg, precision=args.precision)
+    S = capi.Solver(cfg, precision=args.precision, graph=args.graph)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     q = S.query(-1)
@@ -326,7 +354,14 @@ def main():
                      'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': achieved / HBM_PEAK_GBS,
                      'traffic': measured_traffic(cfg.name, args.precision), 'kernels_hip_sha256': kernel_source_hash(),
                      'avg_launch_ms': avg_pa_ms, 'launches': pa['launches'],
-                     'bytes_per_launch': pa['bytes_per_launch']},
+                     'bytes_per_launch': pa['bytes_per_launch'],
+                     # context: the same sweep with the paper's dense A_P^{-1} (the per-unit figure
+                     # w * sum n_P^2 + 32 n) would have to move this many bytes; the rate is the
+                     # equivalent throughput of the reformulated patch solve, not HBM traffic
+                     'dense_inverse_equivalent': {
+                         'bytes_per_launch': dense_inverse_bytes(cfg, 8 if args.precision == 'fp64' else 4),
+                         'GBs': dense_inverse_bytes(cfg, 8 if args.precision == 'fp64' else 4) /
+                         (avg_pa_ms * 1e-3) / 1e9 if pa['launches'] else 0.0}},
         'residual_spmv': {'avg_launch_ms': avg_rs_ms, 'launches': rs['launches'],
                           'achieved_GBs': rs['bytes_per_launch'] / (avg_rs_ms * 1e-3) / 1e9 if rs['launches'] else 0},
     }
