@@ -1,0 +1,135 @@
+"""The benchmark workload at its full size (2D 256x256, dG(2), 7 levels, vertex patches, FP64,
+the default patch storage) against the oracle on sampled outputs: the oracle assembles the
+finest level's spatial MM and KK (seconds) and computes, one by one, what the GPU produced for
+sampled rows, patches and dofs; the solve is checked through the oracle's own operator."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import require_gpu, to_dev, to_host
+from paper_2303_06742_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+CFG = W.C2
+
+
+@pytest.fixture(scope='module')
+def ctx():
+    require_gpu()
+    from oracle import gmg, problem, timedg
+    from paper_2303_06742_amd import capi
+    print(f"[setup] {CFG.name} fp64 (full size)", flush=True)
+    S = capi.Solver(CFG)
+    prm = problem.Params(rho=CFG.rho, lam=CFG.lam, mu=CFG.mu, alpha=CFG.alpha, c0=CFG.c0, K=CFG.K)
+    blocks = problem.SpaceBlocks(CFG.dim, CFG.fine_cells, CFG.r, prm)
+    Dt, Mt, _, _, _ = timedg.time_matrices(CFG.k, CFG.tau)
+    cells = gmg.patch_cells(blocks.mesh, CFG.patch)
+    yield {'S': S, 'b': blocks, 'Dt': Dt, 'Mt': np.diag(Mt), 'gmg': gmg, 'cells': cells}
+    S.close()
+
+
+def apply_rows(c, X, rows=None, absolute=False):
+    """(A X)[rows] with A = D^t (x) MM + M^t (x) KK (Problem 4.1) from the oracle's spatial
+    blocks; rows are space-time indices (all rows if None).  absolute: |A| |X| instead."""
+    b, nt = c['b'], CFG.k + 1
+    ns = b.ns
+    MM, KK, Dt = (abs(b.MM), abs(b.KK), np.abs(c['Dt'])) if absolute else (b.MM, b.KK, c['Dt'])
+    Mt = c['Mt']
+    Xs = X.reshape(nt, ns)
+    if rows is None:
+        t = np.repeat(np.arange(nt), ns)
+        s = np.tile(np.arange(ns), nt)
+        U = np.stack([np.tile(MM @ Xs[a], nt) for a in range(nt)])
+        V = np.stack([np.tile(KK @ Xs[a], nt) for a in range(nt)])
+    else:
+        t, s = np.divmod(np.asarray(rows, dtype=np.int64), ns)
+        MMr, KKr = MM[s], KK[s]
+        U = np.stack([MMr @ Xs[a] for a in range(nt)])
+        V = np.stack([KKr @ Xs[a] for a in range(nt)])
+    idx = np.arange(len(t))
+    return sum(Dt[t, a] * U[a] for a in range(nt)) + Mt[t] * V[t, idx]
+
+
+def test_operator_sampled_rows(ctx):
+    S = ctx['S']
+    x = W.random_vector(S.n, 901)
+    y = to_host(S.apply_operator(to_dev(x), level=-1))
+    rng = np.random.default_rng(902)
+    rows = np.concatenate([rng.integers(0, S.n, 400), [0, S.n - 1]])
+    ref = apply_rows(ctx, x, rows)
+    bound = apply_rows(ctx, np.abs(x), rows, absolute=True)
+    assert np.all(np.abs(y[rows] - ref) <= 1e-13 * bound)
+
+
+def patch_dofs_of(c, cells):
+    return c['gmg'].patch_dofs(c['b'], CFG.k, cells)
+
+
+def patch_matrix(c, Z):
+    """A_P = A[Z, Z] = D^t (x) MM[z, z] + M^t (x) KK[z, z], z the spatial dofs of time node 0."""
+    ns, nt = c['b'].ns, CFG.k + 1
+    z = Z[:len(Z) // nt]
+    assert np.array_equal(Z, np.concatenate([t * ns + z for t in range(nt)]))
+    MMp = c['b'].MM[z][:, z].toarray()
+    KKp = c['b'].KK[z][:, z].toarray()
+    return np.kron(c['Dt'], MMp) + np.kron(np.diag(c['Mt']), KKp)
+
+
+def test_patch_inverses_sampled(ctx):
+    S = ctx['S']
+    cells = ctx['cells']
+    N1 = CFG.fine_cells + 1
+    picks = [0, 1, N1 // 2, N1 * (N1 // 2) + N1 // 2, len(cells) - 1]  # corner, edge, edge, interior, corner
+    for q in picks:
+        X, dofs = S.patch_inverse(-1, q)
+        Z = patch_dofs_of(ctx, cells[q])
+        assert np.array_equal(dofs, Z)
+        Ap = patch_matrix(ctx, Z)
+        ref = np.linalg.inv(Ap)
+        res = np.abs(Ap @ X - np.eye(len(Z))).max()
+        res_ref = np.abs(Ap @ ref - np.eye(len(Z))).max()
+        assert res < max(1e-9, 100 * res_ref), (q, res, res_ref)
+
+
+def test_one_sweep_sampled_dofs(ctx):
+    """Algorithm 4.1, one sweep from a random iterate: at sampled dofs mu the GPU's new iterate
+    equals d0 + omega / p(mu) sum_{P contains mu} (A_P^{-1} R_P (b - A d0))[mu]."""
+    S = ctx['S']
+    b = W.random_vector(S.n, 911)
+    d0 = W.random_vector(S.n, 912)
+    d1 = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 1))
+    ns = ctx['b'].ns
+    cells = ctx['cells']
+    # the vertex patches that contain a Q_r node: those of the grid vertices of its adjacent cells
+    N, r = CFG.fine_cells, CFG.r
+    rng = np.random.default_rng(913)
+    n1 = r * N + 1
+    for node in list(rng.integers(0, n1 * n1, 6)) + [0, n1 * n1 - 1]:
+        gx, gy = node % n1, node // n1
+        cxs = sorted({min(max((gx - 1) // r, 0), N - 1), min(gx // r, N - 1)})
+        cys = sorted({min(max((gy - 1) // r, 0), N - 1), min(gy // r, N - 1)})
+        verts = {vx + (N + 1) * vy for cx in cxs for cy in cys for vx in (cx, cx + 1) for vy in (cy, cy + 1)}
+        mu = ns + ctx['b'].nv + CFG.dim * node  # time node 1, U component 0 of this node (nt >= 2)
+        acc, cnt = 0.0, 0
+        for v in sorted(verts):
+            Z = patch_dofs_of(ctx, cells[v])
+            pos = np.searchsorted(Z, mu)
+            if pos >= len(Z) or Z[pos] != mu:
+                continue
+            rP = b[Z] - apply_rows(ctx, d0, Z)
+            y = np.linalg.solve(patch_matrix(ctx, Z), rP)
+            acc += y[pos]
+            cnt += 1
+        assert cnt >= 1
+        ref = d0[mu] + CFG.omega * acc / cnt
+        assert abs(d1[mu] - ref) <= 1e-10 * max(1.0, abs(ref)), (node, d1[mu], ref)
+
+
+def test_solve_true_residual_through_the_oracle_operator(ctx):
+    S = ctx['S']
+    F = W.random_vector(S.n, 921)
+    x = S.empty()
+    info = S.solve(to_dev(F), x, rtol=1e-8)
+    assert info['converged'] == 1
+    res = np.linalg.norm(F - apply_rows(ctx, to_host(x)))
+    assert res <= 1e-8 * np.linalg.norm(F) * (1 + 1e-6), (res, info)
