@@ -245,6 +245,8 @@ def main():
     ap.add_argument('--seed', type=int, default=0)
     ap.add_argument('--hbm-budget-gb', type=float, default=200.0)
     ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32'])
+    ap.add_argument('--form', default='v', choices=['v', 'dtu'],
+                    help="third equation: 'v' Problem 3.1, 'dtu' Problem B.1")
     ap.add_argument('--graph', type=int, default=-1, choices=[-1, 0, 1],
                     help='V-cycle as a captured HIP graph: -1 automatic (below 2^21 unknowns), 0 never, 1 always')
     ap.add_argument('--no-cpu-baseline', action='store_true')
@@ -271,6 +273,9 @@ def main():
     if args.patch_solve is not None:
         from paper_2303_06742_amd import workloads as W
         cfg = W.scaled(cfg, cfg.levels, name=cfg.name, time_blocks=PATCH_SOLVE[args.patch_solve])
+    if args.form == 'dtu':  # Problem B.1 on the same workload
+        from paper_2303_06742_amd import workloads as W
+        cfg = W.scaled(cfg, cfg.levels, name=cfg.name + '-b1', form='dtu')
     torch.cuda.set_device(0)
     if args.copy_calibration:
         # kernels of known traffic for the HBM counter runs: 1 GiB read + 1 GiB written by the
@@ -339,7 +344,7 @@ def main():
         'dtype': 'f64' if args.precision == 'fp64' else 'f64+f32-smoother',
         'data': 'synthetic',
         'config': {'workload': cfg.name, 'dim': cfg.dim, 'cells': f"{cfg.fine_cells}^{cfg.dim}",
-                   'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'pressure': cfg.pressure, 'smoother': args.precision,
+                   'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'pressure': cfg.pressure, 'form': cfg.form, 'smoother': args.precision,
                    'tau': cfg.tau, 'unknowns': n, 'nnz': q['nnz'], 'patches': q['patches'], 'rtol': cfg.rtol,
                    'restart': cfg.restart},
         'vcycle_dof_per_s': n * sum(iters) / elapsed,

@@ -101,8 +101,8 @@ typedef struct {
                             3: as 2, with each Schur inverse stored through its symmetric form:
                                X = (D1 S D2)^{-1}, D1 = diag(I, -lam^{-1/2}), D2 = diag(I, lam^{1/2})
                                on the (U, P) rows, is symmetric, and its lower 8x8 tiles are kept
-                               (about 0.65x the values of 2 at 59 rows); applies to FP64 storage
-                               where the blocks are inverted in LDS, otherwise as 2.
+                               (about 0.65x the values of 2 at 59 rows); applies to FP64 storage,
+                               FP32 storage is kept as 2.
                             Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
   int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */

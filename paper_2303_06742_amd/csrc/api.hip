@@ -568,7 +568,7 @@ void build(stgmg_handle* h) {
         // FP32 storage keeps the square layout: 4-byte tile loads (256 bytes per wave
         // instruction) measured slower than the square GEMV's 8-byte column loads (256^2 dG(2):
         // 1.09 against 0.82 ms)
-        D.sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && red_in_lds && red_sym_possible(h->tbc);
+        D.sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && red_sym_possible(h->tbc);
       }
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
@@ -729,10 +729,12 @@ void build(stgmg_handle* h) {
               }
             }
           }
-          // descriptors grouped by kernel for the LDS path: mass blocks, real blocks, complex blocks
+          // descriptors grouped by kernel for the LDS path, and by destination for the symmetric
+          // tiles (mass blocks into the stored layout, Schur blocks into the scratch): mass
+          // blocks, real blocks, complex blocks
           std::vector<stgmg::GjDesc> grp;
           int64_t n_mass = 0, n_real = 0;
-          if (in_lds) {
+          if (in_lds || D.sym) {
             for (int g = 0; g < 3; ++g)
               for (int64_t i = 0; i < cnt; ++i)
                 for (int sl = 0; sl <= nblk; ++sl) {
@@ -750,7 +752,7 @@ void build(stgmg_handle* h) {
           ddesc.emplace_back();
           ddesc.back().upload(descs[descs.size() - 2], h->st, nullptr);
           ddesc.emplace_back();
-          if (in_lds) ddesc.back().upload(descs.back(), h->st, nullptr);
+          if (in_lds || D.sym) ddesc.back().upload(descs.back(), h->st, nullptr);
           const stgmg::GjDesc* dper = ddesc[ddesc.size() - 2].p;
           const stgmg::GjDesc* dgrp = ddesc.back().p;
           dns.emplace_back();
@@ -803,6 +805,11 @@ void build(stgmg_handle* h) {
               stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv64.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv64.p, stat.p);
+            } else if (D.sym) {
+              stgmg::k_gj_invert_f64(h->st, nb, n_mass, max_n, dgrp, Wb.p, D.inv64.p, stat.p);
+              stgmg::k_gj_invert_f64(h->st, nb, n_real + n_cplx, max_n, dgrp + n_mass, Wb.p, Sq.p, stat.p);
+              stgmg::k_pack_red_sym_f64(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
+                                        dtoff.back().p, Sq.p, D.inv64.p);
             } else {
               stgmg::k_gj_invert_f64(h->st, nb, cnt * (nblk + 1), max_n, dper, Wb.p, D.inv64.p, stat.p);
             }
@@ -1396,7 +1403,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
           const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
                               stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
-          const bool sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && in_lds && sym_ok;
+          const bool sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && sym_ok;
           res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? S.sum_tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
                                     (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
