@@ -987,32 +987,56 @@ __device__ inline double dpp_sum8(double v) {
 }
 
 // y += X zt for one plane of symmetric tiles (ntl lower 8x8 tiles, I-major, column-major inside;
-// see pack_red_sym_kernel), one wave: lane (r, c) = (lane % 8, lane / 8) of tile (I, J) adds
-// X[8I+r][8J+c] zt[8J+c] to its row partial (summed over c when block row I closes) and, below
-// the diagonal, X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  zt and y are
-// LDS vectors (re at [0, ldt), im at [ldt, 2 ldt)); y must start at zero.
+// see pack_red_sym_kernel), by wave w of nw: it takes the tiles w, w + nw, w + 2 nw, ...  Lane
+// (r, c) = (lane % 8, lane / 8) of tile (I, J) adds X[8I+r][8J+c] zt[8J+c] to its row partial
+// (summed over c when the wave leaves block row I) and, below the diagonal, X[8I+r][8J+c]
+// zt[8I+r] to column 8J+c (summed over r at once).  zt and y are LDS vectors (re at [0, ldt),
+// im at [ldt, 2 ldt)); y is this wave's own buffer and must start at zero.
 template <typename T, bool NTL, bool CP>
-__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const double* zt, int ldt, double* y) {
+__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const double* zt, int ldt, double* y,
+                                       int w, int nw) {
   const int lane = threadIdx.x & 63, rr = lane & 7, cc = lane >> 3;
   const double* zr = zt;
   const double* zi = zt + ldt;
   double* yr = y;
   double* yi = y + ldt;
   const int im = ntl * 64 * int(sizeof(T));
-  int I = 0, J = 0;
+  int I = 0, J = w;  // the tile w: I(I+1)/2 + J = w, J <= I
+  while (J > I) {
+    J -= I + 1;
+    ++I;
+  }
+  int curI = I;
   double rowr = 0.0, rowi = 0.0;
-  for (int t0 = 0; t0 < ntl; t0 += 8) {
+  auto flush = [&](int Ir) {  // sum the row partials of block row Ir over c
+#pragma unroll
+    for (int sh = 8; sh < 64; sh <<= 1) {
+      rowr += __shfl_xor(rowr, sh);
+      if constexpr (CP) rowi += __shfl_xor(rowi, sh);
+    }
+    if (cc == 0) {
+      yr[8 * Ir + rr] += rowr;
+      if constexpr (CP) yi[8 * Ir + rr] += rowi;
+    }
+    rowr = rowi = 0.0;
+  };
+  for (int t0 = w; t0 < ntl; t0 += 8 * nw) {
     T xr[8], xi[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const bool ok = t0 + u < ntl;
-      const int e = ((t0 + u) * 64 + lane) * int(sizeof(T));
+      const int t = t0 + u * nw;
+      const bool ok = t < ntl;
+      const int e = (t * 64 + lane) * int(sizeof(T));
       xr[u] = ok ? bld1<T, NTL>(rs, e) : T(0);
       if constexpr (CP) xi[u] = ok ? bld1<T, NTL>(rs, e + im) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (t0 + u >= ntl) break;
+      if (t0 + u * nw >= ntl) break;
+      if (I != curI) {
+        flush(curI);
+        curI = I;
+      }
       const double ar = double(xr[u]);
       const double ai = CP ? double(xi[u]) : 0.0;
       const double zjr = zr[8 * J + cc];
@@ -1036,23 +1060,15 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const
           const double cr = dpp_sum8(ar * zir);
           if (rr == 0) yr[8 * J + cc] += cr;
         }
-        ++J;
-      } else {  // the diagonal tile closes block row I: sum the row partials over c
-#pragma unroll
-        for (int sh = 8; sh < 64; sh <<= 1) {
-          rowr += __shfl_xor(rowr, sh);
-          if constexpr (CP) rowi += __shfl_xor(rowi, sh);
-        }
-        if (cc == 0) {
-          yr[8 * I + rr] += rowr;
-          if constexpr (CP) yi[8 * I + rr] += rowi;
-        }
-        rowr = rowi = 0.0;
+      }
+      J += nw;  // the next tile of this wave
+      while (J > I) {
+        J -= I + 1;
         ++I;
-        J = 0;
       }
     }
   }
+  flush(curI);
 }
 
 template <typename T, int R, bool NTL, bool SYM>
@@ -1164,9 +1180,13 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
   // symmetric tiles (one wave): t = D2 X D1 z per kept eigenvalue into region B, stride LDT
   const int LDT = SYM ? 8 * ((nr + 7) >> 3) : ldr;
   if constexpr (SYM) {
+    // W waves: wave w's products at tv + w * 2 nblk LDT ([a][re, im][LDT], the partial images
+    // the back-transform sums), then D1 z shared by all waves
     const int nbk = (nr + 7) >> 3, ntl = nbk * (nbk + 1) / 2;
-    double* tt = tv;                   // [a][re, im][LDT], read by the back-transform
-    double* zt = tv + 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
+    const int wv_i = threadIdx.x >> 6;
+    double* tt = tv;
+    double* zt = tv + int64_t(W) * 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
+    for (int x = threadIdx.x; x < int64_t(W) * 2 * nblk * LDT; x += blockDim.x) tt[x] = 0.0;
     for (int x = threadIdx.x; x < LDT; x += blockDim.x)
 #pragma unroll
       for (int a = 0; a < RED_MAXB; ++a)
@@ -1181,8 +1201,6 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
           }
           zt[(2 * a) * LDT + x] = vr;
           zt[(2 * a + 1) * LDT + x] = vi;
-          tt[(2 * a) * LDT + x] = 0.0;
-          tt[(2 * a + 1) * LDT + x] = 0.0;
         }
     __syncthreads();
     int64_t off = base + nsmall;
@@ -1190,22 +1208,25 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
       const bool cp = tb.cplx[a] != 0;
       const int64_t cnt = int64_t(cp ? 2 : 1) * ntl * 64;
       const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
+      double* yw = tt + (int64_t(wv_i) * nblk + a) * 2 * LDT;
       if (cp)
-        sym_tiles_apply<T, NTL, true>(rs, ntl, zt + (2 * a) * LDT, LDT, tt + (2 * a) * LDT);
+        sym_tiles_apply<T, NTL, true>(rs, ntl, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
       else
-        sym_tiles_apply<T, NTL, false>(rs, ntl, zt + (2 * a) * LDT, LDT, tt + (2 * a) * LDT);
+        sym_tiles_apply<T, NTL, false>(rs, ntl, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
       off += cnt;
     }
     __syncthreads();
-    for (int x = nU + threadIdx.x; x < nr; x += blockDim.x)  // t_P = mu2 (X D1 z)_P
+    for (int q = threadIdx.x; q < W * nP; q += blockDim.x)  // t_P = mu2 (X D1 z)_P, every wave's part
 #pragma unroll
       for (int a = 0; a < RED_MAXB; ++a)
         if (a < nblk) {
+          const int ww = q / nP, x = nU + q % nP;
           double m1r, m1i, m2r, m2i;
           sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
-          const double vr = tt[(2 * a) * LDT + x], vi = tt[(2 * a + 1) * LDT + x];
-          tt[(2 * a) * LDT + x] = vr * m2r - vi * m2i;
-          tt[(2 * a + 1) * LDT + x] = vr * m2i + vi * m2r;
+          double* yb = tt + (int64_t(ww) * nblk + a) * 2 * LDT;
+          const double vr = yb[x], vi = yb[LDT + x];
+          yb[x] = vr * m2r - vi * m2i;
+          yb[LDT + x] = vr * m2i + vi * m2r;
         }
   } else {
     const int per_w = blockDim.x / W;
@@ -1347,18 +1368,20 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
   patch_apply_red_body<T, R, NTL, false>(tb, d, W, xc, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 
-// Symmetric tiles: one wave per patch; the register budget is held to STGMG_SYM_WAVES waves per
+// Symmetric tiles: NW waves per patch (one on large levels, several where the level has too
+// few patches to fill the chip and a patch's serial chain sets the time); the register budget
+// is held to STGMG_SYM_WAVES waves per
 // SIMD (the kernel is bound by HBM streams, which want many waves in flight).
 #ifndef STGMG_SYM_WAVES
 #define STGMG_SYM_WAVES 6
 #endif
-template <typename T, bool NTL>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(STGMG_SYM_WAVES)))
+template <typename T, bool NTL, int NW>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(STGMG_SYM_WAVES)))
 patch_apply_red_sym_kernel(TimeBlockConsts tb, int d, int xc, const int64_t* __restrict__ poff,
                            const int32_t* __restrict__ pdof, const int32_t* __restrict__ tpos,
                            const int32_t* __restrict__ pnu, const int64_t* __restrict__ ioff,
                            const T* __restrict__ inv, const double* __restrict__ r, double* __restrict__ y) {
-  patch_apply_red_body<T, 2, NTL, true>(tb, d, 1, xc, poff, pdof, tpos, pnu, ioff, inv, r, y);
+  patch_apply_red_body<T, 2, NTL, true>(tb, d, NW, xc, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 
 // G = KK_pV ((rho M)^{-1} (x) I_d) in place of KK_pV in the stored layout of the reduced
@@ -1876,6 +1899,9 @@ int patch_apply_red_threads(int max_nr, bool fp32) {
   return th;
 }
 
+// levels with fewer patches than this run the tiled solve with 4 waves per patch
+constexpr int64_t SYM_MULTI_BELOW = 8192;
+
 // tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
 static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
@@ -1886,12 +1912,16 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   int th, W;
   red_layout(max_nr, rr, &th, &W);
   size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
-  if (sym) {  // one wave per patch; region B holds the products and D1 z at stride 8 ceil(nr / 8)
-    th = 64;
-    W = 1;
+  if (sym) {  // W waves per patch; region B holds W partial products and D1 z at stride 8 ceil(nr / 8)
+    W = npatch < SYM_MULTI_BELOW ? 4 : 1;
+    if (const char* e = std::getenv("STGMG_SYM_NW")) {  // tuning: 1 or 4
+      const int v = std::atoi(e);
+      if (v == 1 || v == 4) W = v;
+    }
+    th = 64 * W;
     const size_t ldr = inv_ld(max_nr), ns = max_np / tb.nt, ldt = 8 * ((max_nr + 7) / 8);
     const size_t a = std::max<size_t>(max_np, 2 * size_t(tb.nblk) * (max_nu + ldr));
-    const size_t b = std::max<size_t>(2 * size_t(tb.nblk) * ns, 4 * size_t(tb.nblk) * ldt);
+    const size_t b = std::max<size_t>(2 * size_t(tb.nblk) * ns, size_t(W + 1) * 2 * size_t(tb.nblk) * ldt);
     lds = (a + b) * sizeof(double);
   }
   bool ntl = true;
@@ -1904,12 +1934,17 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   hipLaunchKernelGGL((dev::patch_apply_red_kernel<T, RR, NT>), dim3(npatch), dim3(th), lds, st, tb, d, W, xc, poff, \
                      pdof, tpos, pnu, ioff, inv, r, y)
   if (sym) {
-    if (ntl)
-      hipLaunchKernelGGL((dev::patch_apply_red_sym_kernel<T, true>), dim3(npatch), dim3(64), lds, st, tb, d, xc, poff,
-                         pdof, tpos, pnu, ioff, inv, r, y);
-    else
-      hipLaunchKernelGGL((dev::patch_apply_red_sym_kernel<T, false>), dim3(npatch), dim3(64), lds, st, tb, d, xc,
-                         poff, pdof, tpos, pnu, ioff, inv, r, y);
+#define STGMG_SYM(NT, NW)                                                                                           \
+  hipLaunchKernelGGL((dev::patch_apply_red_sym_kernel<T, NT, NW>), dim3(npatch), dim3(64 * NW), lds, st, tb, d, xc, \
+                     poff, pdof, tpos, pnu, ioff, inv, r, y)
+    if (W == 4) {
+      if (ntl) STGMG_SYM(true, 4);
+      else STGMG_SYM(false, 4);
+    } else {
+      if (ntl) STGMG_SYM(true, 1);
+      else STGMG_SYM(false, 1);
+    }
+#undef STGMG_SYM
     return;
   }
   if constexpr (sizeof(T) == 4) {
