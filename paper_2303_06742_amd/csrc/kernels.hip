@@ -1880,9 +1880,10 @@ static void red_layout(int max_nr, int R, int* th, int* W) {
 }
 
 // rows per thread of the reduced patch GEMV: two for FP64 (16-byte loads); for FP32 two
-// (8-byte loads) on short columns and four (16-byte loads) on columns of more than 128
+// (8-byte loads) on short columns and four (16-byte loads) on columns of more than 64
 // values.  Measured per finest-level launch: 256^2 dG(2) vertex patches (Schur blocks of 59
-// rows) 0.834 ms with two against 0.884 ms with four; 32^3 dG(1) vertex patches (402 rows)
+// rows) 0.834 ms with two against 0.884 ms with four; 32^3 dG(1) cell patches (89 rows)
+// 0.616 ms with two against 0.560 ms with four; 32^3 dG(1) vertex patches (402 rows)
 // 11.06 ms with two against 10.30 ms with four.  STGMG_RED_R=2|4 overrides for FP32.
 static int red_rows(bool fp32, int max_nr) {
   if (!fp32) return 2;
@@ -1890,7 +1891,7 @@ static int red_rows(bool fp32, int max_nr) {
     const int v = std::atoi(e);
     if (v == 2 || v == 4) return v;
   }
-  return inv_ld(max_nr) > 128 ? 4 : 2;
+  return inv_ld(max_nr) > 64 ? 4 : 2;
 }
 
 int patch_apply_red_threads(int max_nr, bool fp32) {
