@@ -162,3 +162,25 @@ def test_time_blocks_diagonalise_the_slab_operator(k):
         contrib = np.outer(qout[:, a], t)
         y += 2 * contrib.real if cplx[a] else contrib.real
     assert np.abs(y.reshape(-1) - np.linalg.solve(A, r.reshape(-1))).max() < 1e-12 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("d,r,k,N,kind,pressure", [(2, 2, 2, 4, 'vertex', 'cont'), (3, 2, 1, 2, 'cell', 'cont'),
+                                                   (2, 3, 2, 4, 'vertex', 'disc')])
+def test_bench_dense_inverse_bytes_match_the_built_patches(d, r, k, N, kind, pressure):
+    """bench.py's closed form w sum n_P^2 + 32 n (the per-unit figure of the dense-inverse patch
+    solve) equals the count over the patches the host builds."""
+    import ctypes
+    import bench
+    LIB.stgmg_host_set_pressure.argtypes = [ctypes.c_int]
+    LIB.stgmg_host_set_pressure(1 if pressure == 'disc' else 0)
+    try:
+        n = build(d, N, r, k, kind, problem.Params(pressure=pressure))
+        npatch = LIB.stgmg_host_npatch()
+        poff = np.zeros(npatch + 1, dtype=np.int64)
+        pdof = np.zeros(LIB.stgmg_host_patch_total(), dtype=np.int32)
+        LIB.stgmg_host_patches(hostlib.ptr(poff), hostlib.ptr(pdof), hostlib.ptr(np.zeros(n)))
+    finally:
+        LIB.stgmg_host_set_pressure(0)
+    cfg = workloads.Config('t', dim=d, coarse_cells=N, levels=1, k=k, patch=kind, tau=0.01, slabs=1, r=r,
+                           pressure=pressure)
+    assert bench.dense_inverse_bytes(cfg) == 8 * int(np.sum(np.diff(poff) ** 2)) + 32 * n
