@@ -286,11 +286,8 @@ bool red_sym_possible(const stgmg::TimeBlockConsts& tb) {
   return true;
 }
 
-// 8x8 tiles of the lower triangle of an nr x nr matrix
-int64_t red_sym_tiles(int nr) {
-  const int64_t b = (nr + 7) / 8;
-  return b * (b + 1) / 2;
-}
+// 64-value tiles of the lower triangle of an nr x nr matrix
+int64_t red_sym_tiles(int nr) { return stgmg::sym_tiles(nr); }
 
 // Event pair around one launch of kernel class `what` on the finest level.
 struct ProfScope {
@@ -1302,8 +1299,7 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
           const int64_t ntl = red_sym_tiles(nr);
           auto sinv = [&](int i, int q) -> std::complex<double> {
             if (!D.sym) return {st[off + size_t(q) * ldc + i], c ? st[off + size_t(q) * ldc + ldr + i] : 0.0};
-            const int hi = std::max(i, q), lo = std::min(i, q), I = hi / 8, J = lo / 8;
-            const int64_t e = (int64_t(I) * (I + 1) / 2 + J) * 64 + (lo % 8) * 8 + hi % 8;  // column-major tile
+            const int64_t e = stgmg::sym_tile_elem(nr, std::max(i, q), std::min(i, q));
             std::complex<double> x(st[off + e], c ? st[off + ntl * 64 + e] : 0.0);
             if (i >= nU) x *= mu2;
             if (q >= nU) x *= mu1;

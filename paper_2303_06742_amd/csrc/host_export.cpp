@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "host_setup.h"
+#include "tile_layout.h"
 
 namespace {
 stgmg::LevelHost g_level;
@@ -148,6 +149,10 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[11] = S.max_nr;
   out[12] = S.max_nn;
   out[13] = S.nnzCface;
+  out[14] = S.sum_tiles;
 }
+
+// position of X[row][col], row >= col, in one plane of the symmetric tiled storage
+long long stgmg_host_sym_tile_elem(int nr, int row, int col) { return stgmg::sym_tile_elem(nr, row, col); }
 
 }  // extern "C"

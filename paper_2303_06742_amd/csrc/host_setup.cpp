@@ -12,6 +12,7 @@
 //     KK = [[-Mrho, 0, 0], [0, A_gamma, C^T], [-C, 0, B_gamma]]
 // with rows (u-eq, v-eq, p-eq) and columns (V, U, P).
 #include "host_setup.h"
+#include "tile_layout.h"
 
 #include <algorithm>
 #include <atomic>
@@ -1567,7 +1568,7 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bo
     S.sum_nr_ldr += mult * nr * ld4(nr);
     S.alg_red_fixed += mult * (q * q + pp * nU);
     S.sum_nr2 += mult * nr * nr;
-    S.sum_tiles += mult * ((nr + 7) / 8) * ((nr + 7) / 8 + 1) / 2;
+    S.sum_tiles += mult * sym_tiles(int(nr));
     S.max_nr = std::max<int>(S.max_nr, int(nr));
     S.max_nn = std::max<int>(S.max_nn, int(q));
   }

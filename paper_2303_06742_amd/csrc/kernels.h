@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "tile_layout.h"
+
 namespace stgmg {
 
 // Leading dimension of a stored patch inverse of size n: columns padded to a

@@ -875,9 +875,8 @@ __device__ inline void sym_factors(double al, double be, double* m1r, double* m1
 }
 
 // Symmetric tiled storage of the Schur inverses: X = (D1 S D2)^{-1} = D2^{-1} S^{-1} D1^{-1} is
-// symmetric; its lower 8x8 tiles (I, J), J <= I, are stored I-major (tile index I(I+1)/2 + J),
-// each column-major (entry (r, c) = X[8I + r][8J + c] at 8c + r, zero beyond nr); a complex X
-// as the Re tiles followed by the Im tiles.  One block per (batch item, kept eigenvalue); S^{-1} is read
+// symmetric; its lower triangle is stored in the tiles of tile_layout.h (8x8 tiles I-major, the
+// last block row possibly as 4x16 tiles); a complex X as the Re tiles followed by the Im tiles.  One block per (batch item, kept eigenvalue); S^{-1} is read
 // from the square scratch (column j of Re at soff + j * ldc, Im rows after ldr) and
 // symmetrised as (X + X^T) / 2.
 template <typename T>
@@ -893,7 +892,7 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
   const int nU = nu_of[i], nr = nr_of[i], ldr = inv_ld(nr);
   const bool cp = tb.cplx[a] != 0;
   const int ldc = cp ? 2 * ldr : ldr;
-  const int nbk = (nr + 7) >> 3, ntl = nbk * (nbk + 1) / 2;
+  const int ntf = sym_full_tiles(nr), ntl = sym_tiles(nr), Ilast = sym_nbk(nr) - 1;
   double m1r, m1i, m2r, m2i;
   sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
   // 1/mu2 and 1/mu1 = -mu2
@@ -918,11 +917,18 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
   };
   for (int q = threadIdx.x; q < ntl * 64; q += blockDim.x) {
     const int t = q >> 6, e = q & 63;
-    int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > t) --I;
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    const int J = t - I * (I + 1) / 2;
-    const int row = 8 * I + (e & 7), col = 8 * J + (e >> 3);
+    int row, col;
+    if (t >= ntf) {  // 4x16 tile of the last block row
+      row = 8 * Ilast + (e & 3);
+      col = 16 * (t - ntf) + (e >> 2);
+    } else {
+      int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (I * (I + 1) / 2 > t) --I;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = t - I * (I + 1) / 2;
+      row = 8 * I + (e & 7);
+      col = 8 * J + (e >> 3);
+    }
     double vr = 0.0, vi = 0.0;
     if (row < nr && col < nr) {
       double ar, ai, br, bi;
@@ -959,47 +965,52 @@ __device__ inline __amdgpu_buffer_rsrc_t patch_rsrc(const T* p, int64_t count) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), 0, int(count * int64_t(sizeof(T))), 0x00020000);
 }
 
-// Sum of a double over the 8 consecutive lanes of each group (lanes 8g .. 8g+7), through DPP
-// (quad xor 1, quad xor 2, mirror within 8); every lane of the group ends with the sum.
-__device__ inline double dpp_sum8(double v) {
-  auto step = [](double x, int ctrl) {
-    const int2 b = __builtin_bit_cast(int2, x);
-    int2 o;
-    switch (ctrl) {
-      case 0:
-        o.x = __builtin_amdgcn_update_dpp(0, b.x, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
-        o.y = __builtin_amdgcn_update_dpp(0, b.y, 0xB1, 0xF, 0xF, false);
-        break;
-      case 1:
-        o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
-        o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x4E, 0xF, 0xF, false);
-        break;
-      default:
-        o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x141, 0xF, 0xF, false);  // row_half_mirror
-        o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x141, 0xF, 0xF, false);
-        break;
-    }
-    return x + __builtin_bit_cast(double, o);
-  };
-  v = step(v, 0);
-  v = step(v, 1);
-  return step(v, 2);
+// One step of a DPP butterfly sum of a double: ctrl 0 adds the value of lane xor 1 (quad_perm
+// [1,0,3,2]), ctrl 1 that of lane xor 2 (quad_perm [2,3,0,1]), ctrl 2 the mirrored lane within
+// each group of 8 (row_half_mirror).
+__device__ inline double dpp_sum_step(double x, int ctrl) {
+  const int2 b = __builtin_bit_cast(int2, x);
+  int2 o;
+  switch (ctrl) {
+    case 0:
+      o.x = __builtin_amdgcn_update_dpp(0, b.x, 0xB1, 0xF, 0xF, false);
+      o.y = __builtin_amdgcn_update_dpp(0, b.y, 0xB1, 0xF, 0xF, false);
+      break;
+    case 1:
+      o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x4E, 0xF, 0xF, false);
+      o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x4E, 0xF, 0xF, false);
+      break;
+    default:
+      o.x = __builtin_amdgcn_update_dpp(0, b.x, 0x141, 0xF, 0xF, false);
+      o.y = __builtin_amdgcn_update_dpp(0, b.y, 0x141, 0xF, 0xF, false);
+      break;
+  }
+  return x + __builtin_bit_cast(double, o);
 }
+// Sum over the 8 consecutive lanes of each group (lanes 8g .. 8g+7); every lane of the group
+// ends with the sum.
+__device__ inline double dpp_sum8(double v) { return dpp_sum_step(dpp_sum_step(dpp_sum_step(v, 0), 1), 2); }
+// The same over the 4 lanes of each quad.
+__device__ inline double dpp_sum4(double v) { return dpp_sum_step(dpp_sum_step(v, 0), 1); }
 
-// y += X zt for one plane of symmetric tiles (ntl lower 8x8 tiles, I-major, column-major inside;
-// see pack_red_sym_kernel), by wave w of nw: it takes the tiles w, w + nw, w + 2 nw, ...  Lane
-// (r, c) = (lane % 8, lane / 8) of tile (I, J) adds X[8I+r][8J+c] zt[8J+c] to its row partial
-// (summed over c when the wave leaves block row I) and, below the diagonal, X[8I+r][8J+c]
-// zt[8I+r] to column 8J+c (summed over r at once).  zt and y are LDS vectors (re at [0, ldt),
-// im at [ldt, 2 ldt)); y is this wave's own buffer and must start at zero.
+// y += X zt for one plane of symmetric tiles (ntf 8x8 tiles, then nh 4x16 tiles of the last
+// block row; layout in tile_layout.h), by wave w of nw: it takes the 8x8 tiles w, w + nw, ...
+// and the 4x16 tiles w, w + nw, ...  Lane (r, c) = (lane % 8, lane / 8) of 8x8 tile (I, J) adds
+// X[8I+r][8J+c] zt[8J+c] to its row partial (summed over c when the wave leaves block row I)
+// and, below the diagonal, X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  Lane
+// (r, c) = (lane % 4, lane / 4) of 4x16 tile q does the same for row 8I+r, column 16q+c of the
+// last block row I, the transposed entry only left of the diagonal block (which the 4x16 tiles
+// hold in full).  zt and y are LDS vectors (re at [0, ldt), im at [ldt, 2 ldt), ldt >= 16 nh);
+// y is this wave's own buffer and must start at zero.
 template <typename T, bool NTL, bool CP>
-__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const double* zt, int ldt, double* y,
-                                       int w, int nw) {
+__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int nh, const double* zt, int ldt,
+                                       double* y, int w, int nw) {
   const int lane = threadIdx.x & 63, rr = lane & 7, cc = lane >> 3;
   const double* zr = zt;
   const double* zi = zt + ldt;
   double* yr = y;
   double* yi = y + ldt;
+  const int ntl = ntf + nh;
   const int im = ntl * 64 * int(sizeof(T));
   int I = 0, J = w;  // the tile w: I(I+1)/2 + J = w, J <= I
   while (J > I) {
@@ -1020,19 +1031,19 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const
     }
     rowr = rowi = 0.0;
   };
-  for (int t0 = w; t0 < ntl; t0 += 8 * nw) {
+  for (int t0 = w; t0 < ntf; t0 += 8 * nw) {
     T xr[8], xi[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int t = t0 + u * nw;
-      const bool ok = t < ntl;
+      const bool ok = t < ntf;
       const int e = (t * 64 + lane) * int(sizeof(T));
       xr[u] = ok ? bld1<T, NTL>(rs, e) : T(0);
       if constexpr (CP) xi[u] = ok ? bld1<T, NTL>(rs, e + im) : T(0);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      if (t0 + u * nw >= ntl) break;
+      if (t0 + u * nw >= ntf) break;
       if (I != curI) {
         flush(curI);
         curI = I;
@@ -1068,7 +1079,63 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntl, const
       }
     }
   }
-  flush(curI);
+  if (w < ntf) flush(curI);
+  if (w >= nh) return;
+  // 4x16 tiles of the last block row Ih = 2 nh - 1
+  const int hr = lane & 3, hc = lane >> 2, Ih = 2 * nh - 1;
+  const double zhr = zr[8 * Ih + hr];
+  const double zhi = CP ? zi[8 * Ih + hr] : 0.0;
+  rowr = rowi = 0.0;
+  for (int q0 = w; q0 < nh; q0 += 4 * nw) {
+    T xr[4], xi[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * nw;
+      const bool ok = q < nh;
+      const int e = ((ntf + q) * 64 + lane) * int(sizeof(T));
+      xr[u] = ok ? bld1<T, NTL>(rs, e) : T(0);
+      if constexpr (CP) xi[u] = ok ? bld1<T, NTL>(rs, e + im) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + u * nw;
+      if (q >= nh) break;
+      const int col = 16 * q + hc;
+      const double ar = double(xr[u]);
+      const double ai = CP ? double(xi[u]) : 0.0;
+      const double zjr = zr[col];
+      if constexpr (CP) {
+        const double zji = zi[col];
+        rowr += ar * zjr - ai * zji;
+        rowi += ar * zji + ai * zjr;
+      } else {
+        rowr += ar * zjr;
+      }
+      if (16 * q < 8 * Ih) {  // the tile has columns left of the diagonal block
+        const bool below = col < 8 * Ih;
+        if constexpr (CP) {
+          const double cr = dpp_sum4(below ? ar * zhr - ai * zhi : 0.0);
+          const double ci = dpp_sum4(below ? ar * zhi + ai * zhr : 0.0);
+          if (hr == 0 && below) {
+            yr[col] += cr;
+            yi[col] += ci;
+          }
+        } else {
+          const double cr = dpp_sum4(below ? ar * zhr : 0.0);
+          if (hr == 0 && below) yr[col] += cr;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int sh = 4; sh < 64; sh <<= 1) {  // row sums over c
+    rowr += __shfl_xor(rowr, sh);
+    if constexpr (CP) rowi += __shfl_xor(rowi, sh);
+  }
+  if (hc == 0) {
+    yr[8 * Ih + hr] += rowr;
+    if constexpr (CP) yi[8 * Ih + hr] += rowi;
+  }
 }
 
 template <typename T, int R, bool NTL, bool SYM>
@@ -1182,7 +1249,7 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
   if constexpr (SYM) {
     // W waves: wave w's products at tv + w * 2 nblk LDT ([a][re, im][LDT], the partial images
     // the back-transform sums), then D1 z shared by all waves
-    const int nbk = (nr + 7) >> 3, ntl = nbk * (nbk + 1) / 2;
+    const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr), ntl = ntf + nh;
     const int wv_i = threadIdx.x >> 6;
     double* tt = tv;
     double* zt = tv + int64_t(W) * 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
@@ -1210,9 +1277,9 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
       const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
       double* yw = tt + (int64_t(wv_i) * nblk + a) * 2 * LDT;
       if (cp)
-        sym_tiles_apply<T, NTL, true>(rs, ntl, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
+        sym_tiles_apply<T, NTL, true>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
       else
-        sym_tiles_apply<T, NTL, false>(rs, ntl, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
+        sym_tiles_apply<T, NTL, false>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
       off += cnt;
     }
     __syncthreads();

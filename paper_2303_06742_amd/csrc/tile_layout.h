@@ -1,0 +1,33 @@
+// Layout of the symmetric tiled storage of an nr x nr Schur inverse X (lower triangle in tiles,
+// tiles I-major).  Shared by the pack and apply kernels, the host readback and the footprint.
+//
+// Block rows of 8: nbk = ceil(nr / 8).  Block rows 0 .. nbk-2 are stored as 8x8 tiles (I, J),
+// J <= I, at tile index I(I+1)/2 + J, column-major inside (entry (r, c) = X[8I+r][8J+c] at 8c+r).
+// The last block row holds rem = nr - 8(nbk-1) rows.  When rem <= 4 and nbk is even it is stored
+// as nbk/2 tiles of 4x16 ("half tiles"), tile q covering rows 8(nbk-1) + r, r < 4, and columns
+// 16q + c, c < 16, entry (r, c) at 4c + r; the diagonal block is held in full there (both
+// triangles).  Otherwise the last block row is stored as 8x8 tiles like the others.  Entries
+// beyond nr are zero.  Every tile is 64 values.
+#pragma once
+
+namespace stgmg {
+
+constexpr int sym_nbk(int nr) { return (nr + 7) >> 3; }
+constexpr bool sym_half(int nr) {
+  return sym_nbk(nr) >= 2 && (sym_nbk(nr) & 1) == 0 && nr - 8 * (sym_nbk(nr) - 1) <= 4;
+}
+// 8x8 tiles (they come first)
+constexpr int sym_full_tiles(int nr) {
+  return sym_half(nr) ? sym_nbk(nr) * (sym_nbk(nr) - 1) / 2 : sym_nbk(nr) * (sym_nbk(nr) + 1) / 2;
+}
+// 4x16 tiles (after the 8x8 ones)
+constexpr int sym_half_tiles(int nr) { return sym_half(nr) ? sym_nbk(nr) / 2 : 0; }
+constexpr int sym_tiles(int nr) { return sym_full_tiles(nr) + sym_half_tiles(nr); }
+// Position of X[row][col], row >= col, within one plane of tiles.
+constexpr long long sym_tile_elem(int nr, int row, int col) {
+  return (sym_half(nr) && (row >> 3) == sym_nbk(nr) - 1)
+             ? (sym_full_tiles(nr) + (col >> 4)) * 64LL + 4 * (col & 15) + (row & 7)
+             : ((row >> 3) * ((row >> 3) + 1) / 2 + (col >> 3)) * 64LL + 8 * (col & 7) + (row & 7);
+}
+
+}  // namespace stgmg

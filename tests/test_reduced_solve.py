@@ -123,7 +123,7 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
     MM, KK, poff, pdof, nv, ns = build(d, N, k, kind)
     S = hostlib.sizes(LIB, d, r, k, N, 1 if kind == 'vertex' else 0)
     ld4 = lambda v: (v + 3) // 4 * 4
-    fixed = nrl = max_nr = max_nn = 0
+    fixed = nrl = max_nr = max_nn = tiles = 0
     for p in range(len(poff) - 1):
         nsp = (poff[p + 1] - poff[p]) // (k + 1)
         nU = int(np.sum(pdof[poff[p]:poff[p] + nsp] < nv))
@@ -131,8 +131,10 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
         nr = nU + nP
         fixed += nn * ld4(nn) + nU * ld4(nP)
         nrl += nr * ld4(nr)
+        tiles += len(tile_blocks(nr))
         max_nr, max_nn = max(max_nr, nr), max(max_nn, nn)
     assert (S['sum_red_fixed'], S['sum_nr_ldr'], S['max_nr'], S['max_nn']) == (fixed, nrl, max_nr, max_nn)
+    assert S['sum_tiles'] == tiles
 
 
 def sym_factors(lam):
@@ -142,35 +144,57 @@ def sym_factors(lam):
     return -1.0 / mu2, mu2
 
 
+def tile_blocks(nr):
+    """(row0, col0, rows, cols) of the stored tiles in order: 8x8 tiles (I, J), J <= I, I-major;
+    when the last block row holds at most 4 rows and the number nb of block rows is even, that
+    row as nb/2 tiles of 4x16 instead (the diagonal block in full)."""
+    nb = (nr + 7) // 8
+    half = nb >= 2 and nb % 2 == 0 and nr - 8 * (nb - 1) <= 4
+    out = [(8 * I, 8 * J, 8, 8) for I in range(nb - 1 if half else nb) for J in range(I + 1)]
+    if half:
+        out += [(8 * (nb - 1), 16 * q, 4, 16) for q in range(nb // 2)]
+    return out
+
+
 def pack_tiles(X, nr):
-    """Lower 8x8 tiles of the symmetric X, I-major (tile (I, J), J <= I, at I(I+1)/2 + J), each
-    column-major (entry (r, c) at 8c + r); entries beyond nr are zero; X is symmetrised as
-    (X + X^T)/2."""
+    """The tiles of tile_blocks(nr) of the symmetric X, each column-major (entry (r, c) at
+    rows * c + r); entries beyond nr are zero; X is symmetrised as (X + X^T)/2."""
     nb = (nr + 7) // 8
     Xs = np.zeros((8 * nb, 8 * nb), dtype=complex)
     Xs[:nr, :nr] = 0.5 * (X + X.T)
-    out = []
-    for I in range(nb):
-        for J in range(I + 1):
-            out.append(Xs[8 * I:8 * I + 8, 8 * J:8 * J + 8].reshape(-1, order='F'))
-    return np.concatenate(out)
+    return np.concatenate([Xs[r0:r0 + h, c0:c0 + w].reshape(-1, order='F') for r0, c0, h, w in tile_blocks(nr)])
 
 
 def tile_apply(tiles, nr, zt):
-    """y = X zt from the lower tiles the way one wave does it: lane (r, c) of tile (I, J) adds
-    X[8I+r][8J+c] zt[8J+c] to row 8I+r and, below the diagonal tiles, X[8I+r][8J+c] zt[8I+r]
-    to row 8J+c."""
+    """y = X zt from the stored tiles the way a wave does it: lane (r, c) of a tile adds
+    X[row][col] zt[col] to the row and, for columns left of the tile row's diagonal block,
+    X[row][col] zt[row] to the column."""
     nb = (nr + 7) // 8
     y = np.zeros(8 * nb, dtype=complex)
-    t = 0
-    for I in range(nb):
-        for J in range(I + 1):
-            T = tiles[64 * t:64 * t + 64].reshape(8, 8, order='F')
-            y[8 * I:8 * I + 8] += T @ zt[8 * J:8 * J + 8]
-            if J < I:
-                y[8 * J:8 * J + 8] += T.T @ zt[8 * I:8 * I + 8]
-            t += 1
+    for t, (r0, c0, h, w) in enumerate(tile_blocks(nr)):
+        T = tiles[64 * t:64 * t + 64].reshape(h, w, order='F')
+        y[r0:r0 + h] += T @ zt[c0:c0 + w]
+        below = np.arange(c0, c0 + w) < r0 // 8 * 8
+        y[c0:c0 + w] += np.where(below, T.T @ zt[r0:r0 + h], 0.0)
     return y
+
+
+@pytest.mark.parametrize("nr", [1, 5, 8, 9, 12, 13, 16, 18, 20, 21, 27, 29, 36, 40, 59, 60, 61, 64, 84, 100])
+def test_tile_layout_positions(nr):
+    """The kernels' and the readback's position of X[row][col] (tile_layout.h) is the position
+    of that entry in pack_tiles; every stored tile is 64 values, and the 4x16 tiles are used
+    exactly when the last block row holds at most 4 rows and the block rows are even."""
+    X = np.arange(nr * nr, dtype=float).reshape(nr, nr)
+    X = X + X.T + 1.0  # distinct symmetric values
+    tiles = pack_tiles(X, nr).real
+    for row in range(nr):
+        for col in range(row + 1):
+            e = LIB.stgmg_host_sym_tile_elem(nr, row, col)
+            assert tiles[e] == 0.5 * (X[row, col] + X[col, row]), (row, col, e)
+    nb = (nr + 7) // 8
+    half = any(h == 4 for _, _, h, _ in tile_blocks(nr))
+    assert half == (nb % 2 == 0 and nr - 8 * (nb - 1) <= 4)
+    assert len(tiles) == 64 * (nb * (nb - 1) // 2 + nb // 2 if half else nb * (nb + 1) // 2)
 
 
 @pytest.mark.parametrize("d,N,k,kind", [(2, 4, 2, 'vertex'), (3, 2, 1, 'cell'), (2, 2, 1, 'vertex')])
@@ -198,7 +222,7 @@ def test_symmetric_tiles_reproduce_the_schur_inverse(d, N, k, kind):
             assert np.abs(Ssym - Ssym.T).max() <= 1e-13 * np.abs(Ssym).max()
             X = np.linalg.inv(Ssym)
             tiles = pack_tiles(X, nr)
-            assert len(tiles) == 64 * ((nr + 7) // 8) * ((nr + 7) // 8 + 1) // 2
+            assert len(tiles) == 64 * len(tile_blocks(nr))
             z = rng.standard_normal(nr) + 1j * rng.standard_normal(nr)
             zt = np.zeros(8 * ((nr + 7) // 8), dtype=complex)
             zt[:nr] = np.diag(D1) * z
