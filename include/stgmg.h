@@ -100,8 +100,9 @@ typedef struct {
                                of n_P/(k+1) - nU rows per eigenvalue (about 3x fewer again);
                             3: as 2, with each Schur inverse stored through its symmetric form:
                                X = (D1 S D2)^{-1}, D1 = diag(I, -lam^{-1/2}), D2 = diag(I, lam^{1/2})
-                               on the (U, P) rows, is symmetric, and its lower 8x8 tiles are kept
-                               (about 0.65x the values of 2 at 59 rows); applies to FP64 storage,
+                               on the (U, P) rows, is symmetric, and its lower triangle is kept in
+                               8x8 tiles (a last block row of at most 4 rows in 4x16 tiles; about
+                               0.58x the values of 2 at 59 rows); applies to FP64 storage,
                                FP32 storage is kept as 2.
                             Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */

@@ -92,8 +92,9 @@ void k_gj_lds_f64(hipStream_t st, bool cplx, int64_t count, int max_n, const GjD
 void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
                   float* out, int32_t* status);
 int patch_apply_red_threads(int max_nr, bool fp32);
-// sym: the Schur inverses stored as symmetric 8x8 tiles of X = D2^{-1} S^{-1} D1^{-1} (see
-// k_pack_red_sym_*), applied by one wave per patch; else square, column-major, padded.
+// sym: the Schur inverses stored as the symmetric tiles (tile_layout.h) of X = D2^{-1} S^{-1} D1^{-1}
+// (see k_pack_red_sym_*), applied by one wave per patch (four on small levels); else square,
+// column-major, padded.
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
                            const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                            const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y);
