@@ -102,8 +102,8 @@ typedef struct {
                                X = (D1 S D2)^{-1}, D1 = diag(I, -lam^{-1/2}), D2 = diag(I, lam^{1/2})
                                on the (U, P) rows, is symmetric, and its lower triangle is kept in
                                8x8 tiles (a last block row of at most 4 rows in 4x16 tiles; about
-                               0.58x the values of 2 at 59 rows); applies to FP64 storage,
-                               FP32 storage is kept as 2.
+                               0.58x the values of 2 at 59 rows; FP32 storage pairs the tiles
+                               so that a lane loads 8 bytes).
                             Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
   int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */

@@ -286,8 +286,8 @@ bool red_sym_possible(const stgmg::TimeBlockConsts& tb) {
   return true;
 }
 
-// 64-value tiles of the lower triangle of an nr x nr matrix
-int64_t red_sym_tiles(int nr) { return stgmg::sym_tiles(nr); }
+// stored 64-value tiles of the lower triangle of an nr x nr matrix (FP32: tiles paired)
+int64_t red_sym_tiles(int nr, bool f32) { return stgmg::sym_slots(nr, f32 ? 2 : 1); }
 
 // Event pair around one launch of kernel class `what` on the finest level.
 struct ProfScope {
@@ -562,10 +562,7 @@ void build(stgmg_handle* h) {
           D.max_npr = std::max<int>(D.max_npr, int(nP));
         }
         red_in_lds = red_blocks_in_lds(h->tbc, D.max_nr, D.max_nu / d);
-        // FP32 storage keeps the square layout: 4-byte tile loads (256 bytes per wave
-        // instruction) measured slower than the square GEMV's 8-byte column loads (256^2 dG(2):
-        // 1.09 against 0.82 ms)
-        D.sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && red_sym_possible(h->tbc);
+        D.sym = p.time_blocks == 3 && red_sym_possible(h->tbc);
       }
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
@@ -578,7 +575,7 @@ void build(stgmg_handle* h) {
           for (int a = 0; a < h->tbc.nblk; ++a) {
             const int64_t planes = h->tbc.cplx[a] ? 2 : 1;
             if (D.sym) {
-              sz += planes * red_sym_tiles(int(nr)) * 64;
+              sz += planes * red_sym_tiles(int(nr), p.smoother_prec == STGMG_FP32) * 64;
               D.alg_inv_entries += double(planes * nr * (nr + 1) / 2);
             } else {
               sz += planes * nr * stgmg::inv_ld(int(nr));
@@ -720,7 +717,7 @@ void build(stgmg_handle* h) {
                 soff[i * nblk + a] = so;
                 toff[i * nblk + a] = oo;
                 so += int64_t(nr) * (c ? 2 * ldr : ldr);
-                oo += (c ? 2 : 1) * red_sym_tiles(nr) * 64;
+                oo += (c ? 2 : 1) * red_sym_tiles(nr, p.smoother_prec == STGMG_FP32) * 64;
               } else {
                 oo += int64_t(nr) * (c ? 2 * ldr : ldr);
               }
@@ -778,6 +775,11 @@ void build(stgmg_handle* h) {
               stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+              stgmg::k_pack_red_sym_f32(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
+                                        dtoff.back().p, Sq.p, D.inv32.p);
+            } else if (D.sym) {
+              stgmg::k_gj_invert_f32(h->st, nb, n_mass, max_n, dgrp, Wb.p, D.inv32.p, stat.p);
+              stgmg::k_gj_invert_f64(h->st, nb, n_real + n_cplx, max_n, dgrp + n_mass, Wb.p, Sq.p, stat.p);
               stgmg::k_pack_red_sym_f32(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
                                         dtoff.back().p, Sq.p, D.inv32.p);
             } else if (in_lds) {
@@ -1296,10 +1298,11 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
           const std::complex<double> lam(tb.lam[2 * a], tb.lam[2 * a + 1]);
           // S(lam)^{-1}(i, q): square column-major, or D2 X D1 from the symmetric tiles
           const std::complex<double> mu2 = std::sqrt(lam), mu1 = -1.0 / mu2;
-          const int64_t ntl = red_sym_tiles(nr);
+          const bool f32 = h->prm.smoother_prec == STGMG_FP32;
+          const int64_t ntl = red_sym_tiles(nr, f32);
           auto sinv = [&](int i, int q) -> std::complex<double> {
             if (!D.sym) return {st[off + size_t(q) * ldc + i], c ? st[off + size_t(q) * ldc + ldr + i] : 0.0};
-            const int64_t e = stgmg::sym_tile_elem(nr, std::max(i, q), std::min(i, q));
+            const int64_t e = stgmg::sym_slot_elem(nr, f32 ? 2 : 1, std::max(i, q), std::min(i, q));
             std::complex<double> x(st[off + e], c ? st[off + ntl * 64 + e] : 0.0);
             if (i >= nU) x *= mu2;
             if (q >= nU) x *= mu1;
@@ -1399,8 +1402,9 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
           const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
                               stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
-          const bool sym = p.time_blocks == 3 && p.smoother_prec == STGMG_FP64 && sym_ok;
-          res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? S.sum_tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
+          const bool sym = p.time_blocks == 3 && sym_ok;
+          const int64_t tiles = p.smoother_prec == STGMG_FP32 ? S.sum_tiles2 : S.sum_tiles;
+          res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
                                     (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
           const int64_t sq_item = sym ? (nreal + 2 * ncplx) * int64_t(S.max_nr) * stgmg::inv_ld(S.max_nr) : 0;

@@ -150,9 +150,11 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[12] = S.max_nn;
   out[13] = S.nnzCface;
   out[14] = S.sum_tiles;
+  out[15] = S.sum_tiles2;
 }
 
-// position of X[row][col], row >= col, in one plane of the symmetric tiled storage
-long long stgmg_host_sym_tile_elem(int nr, int row, int col) { return stgmg::sym_tile_elem(nr, row, col); }
+// position of X[row][col], row >= col, in one plane of the symmetric tiled storage with P tiles
+// interleaved per unit (1: FP64, 2: FP32)
+long long stgmg_host_sym_slot_elem(int nr, int P, int row, int col) { return stgmg::sym_slot_elem(nr, P, row, col); }
 
 }  // extern "C"

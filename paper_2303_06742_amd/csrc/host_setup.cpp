@@ -1569,6 +1569,7 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bo
     S.alg_red_fixed += mult * (q * q + pp * nU);
     S.sum_nr2 += mult * nr * nr;
     S.sum_tiles += mult * sym_tiles(int(nr));
+    S.sum_tiles2 += mult * sym_slots(int(nr), 2);
     S.max_nr = std::max<int>(S.max_nr, int(nr));
     S.max_nn = std::max<int>(S.max_nn, int(q));
   }

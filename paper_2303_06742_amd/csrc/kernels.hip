@@ -892,7 +892,9 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
   const int nU = nu_of[i], nr = nr_of[i], ldr = inv_ld(nr);
   const bool cp = tb.cplx[a] != 0;
   const int ldc = cp ? 2 * ldr : ldr;
-  const int ntf = sym_full_tiles(nr), ntl = sym_tiles(nr), Ilast = sym_nbk(nr) - 1;
+  constexpr int P = sizeof(T) == 4 ? 2 : 1;  // tiles interleaved per unit (tile_layout.h)
+  const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr), ntf2 = sym_full_slots(nr, P);
+  const int nsl = sym_slots(nr, P), Ilast = sym_nbk(nr) - 1;
   double m1r, m1i, m2r, m2i;
   sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
   // 1/mu2 and 1/mu1 = -mu2
@@ -915,13 +917,15 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
     *xr = vr;
     *xi = vi;
   };
-  for (int q = threadIdx.x; q < ntl * 64; q += blockDim.x) {
-    const int t = q >> 6, e = q & 63;
-    int row, col;
-    if (t >= ntf) {  // 4x16 tile of the last block row
-      row = 8 * Ilast + (e & 3);
-      col = 16 * (t - ntf) + (e >> 2);
-    } else {
+  for (int q = threadIdx.x; q < nsl * 64; q += blockDim.x) {
+    const int t = q / (64 * P) * P + q % P, e = q % (64 * P) / P;  // slot and entry of position q
+    int row = nr, col = nr;  // zero slots
+    if (t >= ntf2) {  // 4x16 tile of the last block row
+      if (t - ntf2 < nh) {
+        row = 8 * Ilast + (e & 3);
+        col = 16 * (t - ntf2) + (e >> 2);
+      }
+    } else if (t < ntf) {
       int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
       while (I * (I + 1) / 2 > t) --I;
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -938,7 +942,7 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
       vi = 0.5 * (ai + bi);
     }
     o[q] = T(vr);
-    if (cp) o[int64_t(ntl) * 64 + q] = T(vi);
+    if (cp) o[int64_t(nsl) * 64 + q] = T(vi);
   }
 }
 
@@ -993,26 +997,42 @@ __device__ inline double dpp_sum8(double v) { return dpp_sum_step(dpp_sum_step(d
 // The same over the 4 lanes of each quad.
 __device__ inline double dpp_sum4(double v) { return dpp_sum_step(dpp_sum_step(v, 0), 1); }
 
+// P values of one unit of tiles (tile_layout.h) at byte offset voff: one 8-byte load per lane.
+template <typename T, bool NTL>
+__device__ inline void bld_unit(__amdgpu_buffer_rsrc_t rs, int voff, T* out) {
+  if constexpr (sizeof(T) == 8) {
+    out[0] = bld1<T, NTL>(rs, voff);
+  } else {
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    const F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, NTL ? 2 : 0));
+    out[0] = v.x;
+    out[1] = v.y;
+  }
+}
+
 // y += X zt for one plane of symmetric tiles (ntf 8x8 tiles, then nh 4x16 tiles of the last
-// block row; layout in tile_layout.h), by wave w of nw: it takes the 8x8 tiles w, w + nw, ...
-// and the 4x16 tiles w, w + nw, ...  Lane (r, c) = (lane % 8, lane / 8) of 8x8 tile (I, J) adds
-// X[8I+r][8J+c] zt[8J+c] to its row partial (summed over c when the wave leaves block row I)
-// and, below the diagonal, X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  Lane
-// (r, c) = (lane % 4, lane / 4) of 4x16 tile q does the same for row 8I+r, column 16q+c of the
-// last block row I, the transposed entry only left of the diagonal block (which the 4x16 tiles
-// hold in full).  zt and y are LDS vectors (re at [0, ldt), im at [ldt, 2 ldt), ldt >= 16 nh);
-// y is this wave's own buffer and must start at zero.
+// block row; layout and the FP32 pairing of tiles in tile_layout.h), by wave w of nw: it takes
+// the units (P tiles each) w, w + nw, ... of the 8x8 tiles and of the 4x16 tiles.  Lane
+// (r, c) = (lane % 8, lane / 8) of 8x8 tile (I, J) adds X[8I+r][8J+c] zt[8J+c] to its row
+// partial (summed over c when the wave leaves block row I) and, below the diagonal,
+// X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  Lane (r, c) =
+// (lane % 4, lane / 4) of 4x16 tile q does the same for row 8I+r, column 16q+c of the last block
+// row I, the transposed entry only left of the diagonal block (which the 4x16 tiles hold in
+// full).  zt and y are LDS vectors (re at [0, ldt), im at [ldt, 2 ldt), ldt >= 16 nh); y is this
+// wave's own buffer and must start at zero.
 template <typename T, bool NTL, bool CP>
 __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int nh, const double* zt, int ldt,
                                        double* y, int w, int nw) {
+  constexpr int P = sizeof(T) == 4 ? 2 : 1;  // tiles per unit: one 8-byte load per lane
+  constexpr int UB = 8 / P;                  // units per batch of 8 tiles
   const int lane = threadIdx.x & 63, rr = lane & 7, cc = lane >> 3;
   const double* zr = zt;
   const double* zi = zt + ldt;
   double* yr = y;
   double* yi = y + ldt;
-  const int ntl = ntf + nh;
-  const int im = ntl * 64 * int(sizeof(T));
-  int I = 0, J = w;  // the tile w: I(I+1)/2 + J = w, J <= I
+  const int ntf2 = (ntf + P - 1) / P * P, nh2 = (nh + P - 1) / P * P;
+  const int im = (ntf2 + nh2) * 64 * int(sizeof(T));
+  int I = 0, J = w * P;  // the wave's first tile I(I+1)/2 + J, J <= I
   while (J > I) {
     J -= I + 1;
     ++I;
@@ -1031,25 +1051,29 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int n
     }
     rowr = rowi = 0.0;
   };
-  for (int t0 = w; t0 < ntf; t0 += 8 * nw) {
+  for (int u0 = w; u0 * P < ntf; u0 += UB * nw) {
     T xr[8], xi[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int t = t0 + u * nw;
-      const bool ok = t < ntf;
-      const int e = (t * 64 + lane) * int(sizeof(T));
-      xr[u] = ok ? bld1<T, NTL>(rs, e) : T(0);
-      if constexpr (CP) xi[u] = ok ? bld1<T, NTL>(rs, e + im) : T(0);
+    for (int b = 0; b < UB; ++b) {
+      const int u = u0 + b * nw;
+      const int e = (u * 64 + lane) * P * int(sizeof(T));
+      if (u * P < ntf) {
+        bld_unit<T, NTL>(rs, e, xr + b * P);
+        if constexpr (CP) bld_unit<T, NTL>(rs, e + im, xi + b * P);
+      } else {
+#pragma unroll
+        for (int s = 0; s < P; ++s) xr[b * P + s] = xi[b * P + s] = T(0);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      if (t0 + u * nw >= ntf) break;
+    for (int k = 0; k < 8; ++k) {
+      if ((u0 + (k / P) * nw) * P + k % P >= ntf) break;
       if (I != curI) {
         flush(curI);
         curI = I;
       }
-      const double ar = double(xr[u]);
-      const double ai = CP ? double(xi[u]) : 0.0;
+      const double ar = double(xr[k]);
+      const double ai = CP ? double(xi[k]) : 0.0;
       const double zjr = zr[8 * J + cc];
       if constexpr (CP) {
         const double zji = zi[8 * J + cc];
@@ -1072,37 +1096,42 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int n
           if (rr == 0) yr[8 * J + cc] += cr;
         }
       }
-      J += nw;  // the next tile of this wave
+      J += k % P == P - 1 ? P * nw - (P - 1) : 1;  // the next tile of this wave
       while (J > I) {
         J -= I + 1;
         ++I;
       }
     }
   }
-  if (w < ntf) flush(curI);
-  if (w >= nh) return;
-  // 4x16 tiles of the last block row Ih = 2 nh - 1
+  if (w * P < ntf) flush(curI);
+  if (w * P >= nh) return;
+  // 4x16 tiles of the last block row Ih = 2 nh - 1 (units after the ntf2 / P units of 8x8 tiles)
+  constexpr int UH = 4 / P;  // units per batch of 4 tiles
   const int hr = lane & 3, hc = lane >> 2, Ih = 2 * nh - 1;
   const double zhr = zr[8 * Ih + hr];
   const double zhi = CP ? zi[8 * Ih + hr] : 0.0;
   rowr = rowi = 0.0;
-  for (int q0 = w; q0 < nh; q0 += 4 * nw) {
+  for (int u0 = w; u0 * P < nh; u0 += UH * nw) {
     T xr[4], xi[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = q0 + u * nw;
-      const bool ok = q < nh;
-      const int e = ((ntf + q) * 64 + lane) * int(sizeof(T));
-      xr[u] = ok ? bld1<T, NTL>(rs, e) : T(0);
-      if constexpr (CP) xi[u] = ok ? bld1<T, NTL>(rs, e + im) : T(0);
+    for (int b = 0; b < UH; ++b) {
+      const int u = u0 + b * nw;
+      const int e = ((ntf2 / P + u) * 64 + lane) * P * int(sizeof(T));
+      if (u * P < nh) {
+        bld_unit<T, NTL>(rs, e, xr + b * P);
+        if constexpr (CP) bld_unit<T, NTL>(rs, e + im, xi + b * P);
+      } else {
+#pragma unroll
+        for (int s = 0; s < P; ++s) xr[b * P + s] = xi[b * P + s] = T(0);
+      }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int q = q0 + u * nw;
+    for (int k = 0; k < 4; ++k) {
+      const int q = (u0 + (k / P) * nw) * P + k % P;
       if (q >= nh) break;
       const int col = 16 * q + hc;
-      const double ar = double(xr[u]);
-      const double ai = CP ? double(xi[u]) : 0.0;
+      const double ar = double(xr[k]);
+      const double ai = CP ? double(xi[k]) : 0.0;
       const double zjr = zr[col];
       if constexpr (CP) {
         const double zji = zi[col];
@@ -1249,7 +1278,8 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
   if constexpr (SYM) {
     // W waves: wave w's products at tv + w * 2 nblk LDT ([a][re, im][LDT], the partial images
     // the back-transform sums), then D1 z shared by all waves
-    const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr), ntl = ntf + nh;
+    const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr);
+    const int nsl = sym_slots(nr, sizeof(T) == 4 ? 2 : 1);  // stored tiles per plane
     const int wv_i = threadIdx.x >> 6;
     double* tt = tv;
     double* zt = tv + int64_t(W) * 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
@@ -1273,7 +1303,7 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
     int64_t off = base + nsmall;
     for (int a = 0; a < nblk; ++a) {
       const bool cp = tb.cplx[a] != 0;
-      const int64_t cnt = int64_t(cp ? 2 : 1) * ntl * 64;
+      const int64_t cnt = int64_t(cp ? 2 : 1) * nsl * 64;
       const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
       double* yw = tt + (int64_t(wv_i) * nblk + a) * 2 * LDT;
       if (cp)

@@ -23,11 +23,20 @@ constexpr int sym_full_tiles(int nr) {
 // 4x16 tiles (after the 8x8 ones)
 constexpr int sym_half_tiles(int nr) { return sym_half(nr) ? sym_nbk(nr) / 2 : 0; }
 constexpr int sym_tiles(int nr) { return sym_full_tiles(nr) + sym_half_tiles(nr); }
-// Position of X[row][col], row >= col, within one plane of tiles.
-constexpr long long sym_tile_elem(int nr, int row, int col) {
-  return (sym_half(nr) && (row >> 3) == sym_nbk(nr) - 1)
-             ? (sym_full_tiles(nr) + (col >> 4)) * 64LL + 4 * (col & 15) + (row & 7)
-             : ((row >> 3) * ((row >> 3) + 1) / 2 + (col >> 3)) * 64LL + 8 * (col & 7) + (row & 7);
+
+// Storage of one plane with P tiles interleaved per unit (P = 1 for FP64 values; P = 2 for FP32
+// values, so that one 8-byte load per lane reads entry e of two tiles): the 8x8 and the 4x16
+// tile counts are each rounded up to a multiple of P with zero tiles (slots), and entry e of slot
+// t lies at (floor(t / P) 64 + e) P + t mod P.  P = 1 is the plain tile order.
+constexpr int sym_full_slots(int nr, int P) { return (sym_full_tiles(nr) + P - 1) / P * P; }
+constexpr int sym_half_slots(int nr, int P) { return (sym_half_tiles(nr) + P - 1) / P * P; }
+constexpr int sym_slots(int nr, int P) { return sym_full_slots(nr, P) + sym_half_slots(nr, P); }
+// Position of X[row][col], row >= col, within one plane.
+constexpr long long sym_slot_elem(int nr, int P, int row, int col) {
+  const bool half = sym_half(nr) && (row >> 3) == sym_nbk(nr) - 1;
+  const long long t = half ? sym_full_slots(nr, P) + (col >> 4) : (row >> 3) * ((row >> 3) + 1) / 2 + (col >> 3);
+  const int e = half ? 4 * (col & 15) + (row & 7) : 8 * (col & 7) + (row & 7);
+  return ((t / P) * 64 + e) * P + t % P;
 }
 
 }  // namespace stgmg

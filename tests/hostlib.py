@@ -27,8 +27,8 @@ def load():
     lib.stgmg_host_time.argtypes = [I, D, P, P, P, P, P]
     lib.stgmg_host_source.argtypes = [D, D, D, D, D, D, P]
     lib.stgmg_host_interpolate.argtypes = [D, P]
-    lib.stgmg_host_sym_tile_elem.restype = LL
-    lib.stgmg_host_sym_tile_elem.argtypes = [I, I, I]
+    lib.stgmg_host_sym_slot_elem.restype = LL
+    lib.stgmg_host_sym_slot_elem.argtypes = [I, I, I, I]
     return lib
 
 
@@ -47,8 +47,8 @@ def csr(lib, which, nrows):
 
 
 def sizes(lib, d, r, k, N, kind):
-    out = np.zeros(15, dtype=np.int64)
+    out = np.zeros(16, dtype=np.int64)
     lib.stgmg_host_sizes.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p]
     lib.stgmg_host_sizes(d, r, k, N, kind, ptr(out))
     return dict(zip(['n', 'nnzA', 'nnzMM', 'nnzP', 'npatch', 'sum_np', 'sum_np_ld', 'max_np', 'nnzKK',
-                    'sum_red_fixed', 'sum_nr_ldr', 'max_nr', 'max_nn', 'nnzCface', 'sum_tiles'], out.tolist()))
+                    'sum_red_fixed', 'sum_nr_ldr', 'max_nr', 'max_nn', 'nnzCface', 'sum_tiles', 'sum_tiles2'], out.tolist()))

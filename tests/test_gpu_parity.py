@@ -79,6 +79,21 @@ def test_patch_inverses(key):
         assert rel_err(X @ y, ref @ y) < 1e-9
 
 
+@pytest.mark.parametrize("key", ['c2s', 'k3', 'c3v', 'c2d'])
+def test_fp32_tile_readback(key):
+    """The paired FP32 tiles read back (through the host copy of the tile positions) as the FP64
+    tiles of the same patches, up to FP32 rounding amplified by the reconstruction of the dense
+    inverse from the reduced factors (measured 1.6e-5 of the largest entry); a misplaced entry
+    would differ by the size of the entries themselves."""
+    S64, S32 = solver(key), solver(key, 'fp32')
+    npatch = S64.query(-1)['patches']
+    for q in sorted(set([0, 1, npatch // 2, npatch - 1])):
+        X64, d64 = S64.patch_inverse(-1, q)
+        X32, d32 = S32.patch_inverse(-1, q)
+        assert np.array_equal(d64, d32)
+        assert np.abs(X32 - X64).max() <= 1e-3 * np.abs(X64).max(), (key, q)
+
+
 @pytest.mark.parametrize("key", KEYS)
 def test_smoother(key):
     """Algorithm 4.1 sweeps on the finest level from a random iterate."""
@@ -162,9 +177,11 @@ def test_fp32_smoother_meets_tolerances():
     assert i32['iters'] <= i64['iters'] + 2
 
 
-@pytest.mark.parametrize("key", ['c2s_tb', 'c3s', 'c2s_red', 'c3s_red'])
+@pytest.mark.parametrize("key", ['c2s_tb', 'c3s', 'c2s_red', 'c3s_red', 'k3', 'c3v', 'c2d', 'c2s_b1'])
 def test_fp32_storage_meets_tolerances(key):
-    """FP32 storage of the patch solves inside FP64 FGMRES (time blocks; reduced, FP64 sums)."""
+    """FP32 storage of the patch solves inside FP64 FGMRES (time blocks; reduced with square or
+    paired symmetric tiles, FP64 sums; complex pairs, 402-row panel-inverted blocks, the
+    discontinuous pressure, Problem B.1)."""
     S64 = solver(key)
     S32 = solver(key, 'fp32')
     F = workloads.random_vector(S64.n, 52)

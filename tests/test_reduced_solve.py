@@ -123,7 +123,7 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
     MM, KK, poff, pdof, nv, ns = build(d, N, k, kind)
     S = hostlib.sizes(LIB, d, r, k, N, 1 if kind == 'vertex' else 0)
     ld4 = lambda v: (v + 3) // 4 * 4
-    fixed = nrl = max_nr = max_nn = tiles = 0
+    fixed = nrl = max_nr = max_nn = tiles = tiles2 = 0
     for p in range(len(poff) - 1):
         nsp = (poff[p + 1] - poff[p]) // (k + 1)
         nU = int(np.sum(pdof[poff[p]:poff[p] + nsp] < nv))
@@ -132,9 +132,10 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
         fixed += nn * ld4(nn) + nU * ld4(nP)
         nrl += nr * ld4(nr)
         tiles += len(tile_blocks(nr))
+        tiles2 += len(pair_tiles(np.zeros(64 * len(tile_blocks(nr))), nr, 2)) // 64
         max_nr, max_nn = max(max_nr, nr), max(max_nn, nn)
     assert (S['sum_red_fixed'], S['sum_nr_ldr'], S['max_nr'], S['max_nn']) == (fixed, nrl, max_nr, max_nn)
-    assert S['sum_tiles'] == tiles
+    assert S['sum_tiles'] == tiles and S['sum_tiles2'] == tiles2
 
 
 def sym_factors(lam):
@@ -165,6 +166,18 @@ def pack_tiles(X, nr):
     return np.concatenate([Xs[r0:r0 + h, c0:c0 + w].reshape(-1, order='F') for r0, c0, h, w in tile_blocks(nr)])
 
 
+def pair_tiles(tiles, nr, P):
+    """The storage order with P tiles interleaved per unit (P = 2 for FP32 values): the 8x8 and
+    the 4x16 tile counts each padded with zero tiles to a multiple of P, then entry e of slot t
+    at (t // P * 64 + e) * P + t % P."""
+    blocks = tile_blocks(nr)
+    nf = sum(1 for b in blocks if b[2] == 8)
+    T = tiles.reshape(-1, 64)
+    pad = lambda A: np.concatenate([A, np.zeros((-len(A) % P, 64), dtype=A.dtype)])
+    S = np.concatenate([pad(T[:nf]), pad(T[nf:])])
+    return S.reshape(-1, P, 64).transpose(0, 2, 1).reshape(-1)
+
+
 def tile_apply(tiles, nr, zt):
     """y = X zt from the stored tiles the way a wave does it: lane (r, c) of a tile adds
     X[row][col] zt[col] to the row and, for columns left of the tile row's diagonal block,
@@ -179,18 +192,22 @@ def tile_apply(tiles, nr, zt):
     return y
 
 
-@pytest.mark.parametrize("nr", [1, 5, 8, 9, 12, 13, 16, 18, 20, 21, 27, 29, 36, 40, 59, 60, 61, 64, 84, 100])
-def test_tile_layout_positions(nr):
+@pytest.mark.parametrize("P", [1, 2])
+@pytest.mark.parametrize("nr", [1, 5, 8, 9, 12, 13, 16, 18, 20, 21, 27, 29, 36, 40, 59, 60, 61, 64, 84, 89, 100])
+def test_tile_layout_positions(nr, P):
     """The kernels' and the readback's position of X[row][col] (tile_layout.h) is the position
-    of that entry in pack_tiles; every stored tile is 64 values, and the 4x16 tiles are used
-    exactly when the last block row holds at most 4 rows and the block rows are even."""
+    of that entry in pack_tiles (P = 1) and in its FP32 pairing (P = 2); every stored tile is 64
+    values, and the 4x16 tiles are used exactly when the last block row holds at most 4 rows and
+    the block rows are even."""
     X = np.arange(nr * nr, dtype=float).reshape(nr, nr)
     X = X + X.T + 1.0  # distinct symmetric values
     tiles = pack_tiles(X, nr).real
+    stored = pair_tiles(tiles, nr, P)
+    assert np.count_nonzero(stored) == np.count_nonzero(tiles)
     for row in range(nr):
         for col in range(row + 1):
-            e = LIB.stgmg_host_sym_tile_elem(nr, row, col)
-            assert tiles[e] == 0.5 * (X[row, col] + X[col, row]), (row, col, e)
+            e = LIB.stgmg_host_sym_slot_elem(nr, P, row, col)
+            assert stored[e] == 0.5 * (X[row, col] + X[col, row]), (row, col, e)
     nb = (nr + 7) // 8
     half = any(h == 4 for _, _, h, _ in tile_blocks(nr))
     assert half == (nb % 2 == 0 and nr - 8 * (nb - 1) <= 4)
