@@ -103,7 +103,8 @@ typedef struct {
                                on the (U, P) rows, is symmetric, and its lower triangle is kept in
                                8x8 tiles (a last block row of at most 4 rows in 4x16 tiles; about
                                0.58x the values of 2 at 59 rows; FP32 storage pairs the tiles
-                               so that a lane loads 8 bytes).
+                               so that a lane loads 8 bytes, and keeps 2 for Schur blocks of
+                               more than 96 rows, where the square layout measured faster).
                             Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
   int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */

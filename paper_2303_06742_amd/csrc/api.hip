@@ -289,6 +289,16 @@ bool red_sym_possible(const stgmg::TimeBlockConsts& tb) {
 // stored 64-value tiles of the lower triangle of an nr x nr matrix (FP32: tiles paired)
 int64_t red_sym_tiles(int nr, bool f32) { return stgmg::sym_slots(nr, f32 ? 2 : 1); }
 
+// FP32 storage takes the tiles up to this many Schur rows and the square layout beyond: one
+// wave streams a patch's tiles, and with 4-byte values it keeps half the bytes of FP64 in
+// flight (larger batches spill registers), while the square kernel splits the columns over
+// several waves (measured FP32 patch kernels, tiles against square: 59 rows 0.744 / 0.842 ms,
+// 89 rows 0.486 / 0.559 ms, 122 rows 1.089 / 0.770 ms, 402 rows 18.4 / 10.3 ms)
+constexpr int FP32_SYM_MAX_NR = 96;
+bool red_sym_used(const stgmg_params& p, bool sym_possible, int max_nr) {
+  return p.time_blocks == 3 && sym_possible && (p.smoother_prec != STGMG_FP32 || max_nr <= FP32_SYM_MAX_NR);
+}
+
 // Event pair around one launch of kernel class `what` on the finest level.
 struct ProfScope {
   stgmg_handle* h;
@@ -562,7 +572,7 @@ void build(stgmg_handle* h) {
           D.max_npr = std::max<int>(D.max_npr, int(nP));
         }
         red_in_lds = red_blocks_in_lds(h->tbc, D.max_nr, D.max_nu / d);
-        D.sym = p.time_blocks == 3 && red_sym_possible(h->tbc);
+        D.sym = red_sym_used(p, red_sym_possible(h->tbc), D.max_nr);
       }
       for (int64_t q = 0; q < H.npatch; ++q) {
         const int64_t np = H.poff[q + 1] - H.poff[q];
@@ -1402,7 +1412,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
           const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
                               stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
-          const bool sym = p.time_blocks == 3 && sym_ok;
+          const bool sym = red_sym_used(p, sym_ok, int(S.max_nr));
           const int64_t tiles = p.smoother_prec == STGMG_FP32 ? S.sum_tiles2 : S.sum_tiles;
           res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +

@@ -81,8 +81,9 @@ def test_patch_inverses(key):
 
 @pytest.mark.parametrize("key", ['c2s', 'k3', 'c3v', 'c2d'])
 def test_fp32_tile_readback(key):
-    """The paired FP32 tiles read back (through the host copy of the tile positions) as the FP64
-    tiles of the same patches, up to FP32 rounding amplified by the reconstruction of the dense
+    """FP32 storage (paired tiles up to 96 Schur rows: c2s, k3; the square layout beyond: c3v,
+    c2d) reads back (through the host copy of the positions) as the FP64 tiles of the same
+    patches, up to FP32 rounding amplified by the reconstruction of the dense
     inverse from the reduced factors (measured 1.6e-5 of the largest entry); a misplaced entry
     would differ by the size of the entries themselves."""
     S64, S32 = solver(key), solver(key, 'fp32')
