@@ -87,7 +87,11 @@ typedef struct {
   const double* K_cells; /* host, optional: K per fine cell, lexicographic (x fastest);
                             coarse cells take the mean of their 2^d children. Copied. */
   int32_t graph;         /* V-cycle as a captured HIP graph: -1 automatic (hierarchies below
-                            2^21 fine unknowns, where launch latency matters), 0 never, 1 always */
+                            2^21 fine unknowns, where launch latency matters), 0 never, 1 always.
+                            The capture happens inside stgmg_setup; while it runs, null-stream
+                            work from other threads of the process fails (a runtime rule), so
+                            set up handles with graphs while no other thread uses the GPU
+                            through the null stream (the server launches directly). */
   int32_t time_blocks;   /* how A_P^{-1} of Def:VankaOP is stored and applied (the same operator
                             in every mode, up to rounding):
                             0: the full space-time inverse (n_P^2 values);
@@ -233,6 +237,10 @@ stgmg_status stgmg_server_submit(stgmg_server* srv, const stgmg_params* params, 
  * completion, may be NULL) filled.  A finished ticket can be polled again. */
 stgmg_status stgmg_server_poll(stgmg_server* srv, uint64_t ticket, double* x_host, stgmg_info* info,
                                double* latency_ms);
+/* The error text of a finished request that failed ("" otherwise, or for an
+ * unknown ticket); it stays valid until stgmg_server_destroy.  (The worker that ran
+ * the request is another thread, so stgmg_last_error does not see it.) */
+const char* stgmg_server_message(stgmg_server* srv, uint64_t ticket);
 /* Waits for all queued and running requests, then frees everything. */
 stgmg_status stgmg_server_destroy(stgmg_server* srv);
 

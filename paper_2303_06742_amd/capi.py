@@ -91,6 +91,7 @@ stgmg_server_submit = _decl('stgmg_server_submit', [_P, ctypes.POINTER(Params), 
                                                     ctypes.POINTER(ctypes.c_uint64)])
 stgmg_server_poll = _decl('stgmg_server_poll', [_P, ctypes.c_uint64, _P, ctypes.POINTER(Info), ctypes.POINTER(_D)])
 stgmg_server_destroy = _decl('stgmg_server_destroy', [_P])
+stgmg_server_message = _decl('stgmg_server_message', [_P, ctypes.c_uint64], ctypes.c_char_p)
 stgmg_destroy = _decl('stgmg_destroy', [_H])
 stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
 stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
@@ -99,7 +100,8 @@ EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_apply_operator',
             'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs',
             'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_profile_enable', 'stgmg_profile_get',
             'stgmg_destroy', 'stgmg_status_string', 'stgmg_last_error', 'stgmg_footprint', 'stgmg_solve_batch',
-            'stgmg_server_create', 'stgmg_server_submit', 'stgmg_server_poll', 'stgmg_server_destroy']
+            'stgmg_server_create', 'stgmg_server_submit', 'stgmg_server_poll', 'stgmg_server_message',
+            'stgmg_server_destroy']
 
 
 class StgmgError(RuntimeError):
@@ -189,6 +191,10 @@ class Server:
         if st == STGMG_PENDING:
             return None
         return st, x, info.as_dict(), lat.value
+
+    def message(self, ticket):
+        """Error text of a finished request that failed ('' otherwise)."""
+        return stgmg_server_message(self.s, ticket).decode(errors='replace')
 
     def wait(self, ticket, poll_s=0.0005):
         import time

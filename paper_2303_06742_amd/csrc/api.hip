@@ -206,6 +206,17 @@ void enter(stgmg_handle* h) {
   HIPCHK(hipStreamWaitEvent(h->st, h->enter_ev, 0));
 }
 
+// Capture the finest-level V-cycle (gin -> gout) as a graph.  Called at the end of setup:
+// while a stream captures, this runtime rejects null-stream work issued by other threads
+// (and that work invalidates the capture), so the capture happens in the thread that sets the
+// handle up, before the handle can be used from several threads.
+void capture_graph(stgmg_handle* h) {
+  HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  vcycle(h, h->L, h->gin.p, h->gout.p);
+  HIPCHK(hipStreamEndCapture(h->st, &h->graph));
+  HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+}
+
 // z = B r on the finest level: graph replay (through gin/gout) or direct launches.
 void apply_B(stgmg_handle* h, const double* r, double* z) {
   if (!h->use_graph || h->prof) {
@@ -213,12 +224,7 @@ void apply_B(stgmg_handle* h, const double* r, double* z) {
     return;
   }
   const int64_t n = h->lv[h->L].n;
-  if (!h->graph_exec) {
-    HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
-    vcycle(h, h->L, h->gin.p, h->gout.p);
-    HIPCHK(hipStreamEndCapture(h->st, &h->graph));
-    HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
-  }
+  if (!h->graph_exec) capture_graph(h);
   HIPCHK(hipMemcpyAsync(h->gin.p, r, n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
   HIPCHK(hipGraphLaunch(h->graph_exec, h->st));
   HIPCHK(hipMemcpyAsync(z, h->gout.p, n * sizeof(double), hipMemcpyDeviceToDevice, h->st));
@@ -1104,6 +1110,7 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     if (h->use_graph) {
       h->gin.alloc(nf, &h->bytes, h->st);
       h->gout.alloc(nf, &h->bytes, h->st);
+      capture_graph(h.get());
     }
     h->prm.K_cells = nullptr;
     *out = h.release();

@@ -18,6 +18,7 @@
 #include <memory>
 #include <mutex>
 #include <set>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -35,6 +36,7 @@ struct Request {
   int64_t n = 0, resident = 0, peak = 0;
   int state = 0;  // 0 queued, 1 running, 2 done
   stgmg_status status = STGMG_PENDING;
+  std::string message;  // error text of a failed request
   stgmg_info info{};
   clk::time_point t_submit, t_done;
 };
@@ -153,33 +155,48 @@ void worker(stgmg_server* S) {
     for (auto& e : evicted) free_resident(e);
     const bool fresh = slot < 0;
     stgmg_status st = STGMG_OK;
+    std::string msg;
+    auto hip_fail = [&](hipError_t e, const char* what) {
+      if (e == hipSuccess) return false;
+      msg = std::string(what) + ": " + hipGetErrorString(e);
+      return true;
+    };
     if (fresh) {
       R.key = q->key;
       R.n = q->n;
       stgmg_params p = q->prm;
       p.K_cells = q->K.empty() ? nullptr : q->K.data();
+      // no graph capture: the other workers issue null-stream copies at any time, which the
+      // runtime rejects (and which break the capture) while a stream is capturing
+      p.graph = 0;
       st = stgmg_setup(&p, nullptr, &R.h);
+      if (st != STGMG_OK) msg = std::string("setup: ") + stgmg_last_error();
       if (st == STGMG_OK &&
-          (hipMallocAsync(reinterpret_cast<void**>(&R.rhs), q->n * sizeof(double), nullptr) != hipSuccess ||
-           hipMallocAsync(reinterpret_cast<void**>(&R.x), q->n * sizeof(double), nullptr) != hipSuccess))
+          (hip_fail(hipMallocAsync(reinterpret_cast<void**>(&R.rhs), q->n * sizeof(double), nullptr), "hipMallocAsync") ||
+           hip_fail(hipMallocAsync(reinterpret_cast<void**>(&R.x), q->n * sizeof(double), nullptr), "hipMallocAsync")))
         st = STGMG_ERR_OOM;
       R.bytes = q->resident;
     }
     if (st == STGMG_OK) {
-      if (hipMemcpy(R.rhs, q->rhs.data(), q->n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-          hipMemset(R.x, 0, q->n * sizeof(double)) != hipSuccess)
+      if (hip_fail(hipMemcpy(R.rhs, q->rhs.data(), q->n * sizeof(double), hipMemcpyHostToDevice), "rhs upload") ||
+          hip_fail(hipMemset(R.x, 0, q->n * sizeof(double)), "x0 clear"))
         st = STGMG_ERR_HIP;
     }
-    if (st == STGMG_OK) st = stgmg_solve(R.h, R.rhs, R.x, q->rtol, 30, 1000, &q->info);
+    if (st == STGMG_OK) {
+      st = stgmg_solve(R.h, R.rhs, R.x, q->rtol, 30, 1000, &q->info);
+      if (st != STGMG_OK && st != STGMG_NOT_CONVERGED) msg = std::string("solve: ") + stgmg_last_error();
+    }
     if (st == STGMG_OK || st == STGMG_NOT_CONVERGED) {
       q->x.resize(q->n);
-      if (hipMemcpy(q->x.data(), R.x, q->n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) st = STGMG_ERR_HIP;
+      if (hip_fail(hipMemcpy(q->x.data(), R.x, q->n * sizeof(double), hipMemcpyDeviceToHost), "x download"))
+        st = STGMG_ERR_HIP;
     }
     std::vector<double>().swap(q->rhs);
     bool keep = false;
     {
       std::lock_guard<std::mutex> lk(S->mu);
       q->status = st;
+      q->message = msg;
       q->state = 2;
       q->t_done = clk::now();
       S->running--;
@@ -289,6 +306,14 @@ stgmg_status stgmg_server_poll(stgmg_server* S, uint64_t ticket, double* x_host,
   if (info) *info = q->info;
   if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count();
   return q->status;
+}
+
+const char* stgmg_server_message(stgmg_server* S, uint64_t ticket) {
+  if (!S) return "";
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end() || it->second->state != 2) return "";
+  return it->second->message.c_str();
 }
 
 stgmg_status stgmg_server_destroy(stgmg_server* S) {

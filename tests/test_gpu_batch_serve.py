@@ -92,6 +92,37 @@ def test_server_every_result_same_alone_and_in_mix():
     srv.close()
 
 
+def test_server_staggered_arrivals_all_succeed():
+    """Requests that arrive while others run (setups overlapping other workers' uploads,
+    solves and downloads) all finish OK and converged, with no error text, and equal the
+    same requests solved one at a time.  (A hierarchy captured as a HIP graph in one worker
+    once made the other workers' null-stream copies fail.)"""
+    import time
+    c = capi()
+    mix = workloads.serve_mix(16, seed=12, sizes2d=(16, 32, 64), sizes3d=(4, 8))
+    rhs = [workloads.random_vector(c.footprint(cfg)[0], 500 + j) for j, (_, cfg) in enumerate(mix)]
+    solo = c.Server(hbm_budget=64 << 30, max_slots=1, resident_max=0)
+    alone = []
+    for (key, cfg), F in zip(mix, rhs):
+        t0 = solo.submit(cfg, F)
+        st, x, info, _ = solo.wait(t0)
+        assert st == c.STGMG_OK, solo.message(t0)
+        alone.append(x)
+    solo.close()
+    srv = c.Server(hbm_budget=64 << 30, max_slots=4, resident_max=8)
+    rng = np.random.default_rng(13)
+    tickets = []
+    for (key, cfg), F in zip(mix, rhs):
+        time.sleep(float(rng.exponential(0.01)))
+        tickets.append(srv.submit(cfg, F, key=key))
+    for j, (t, x0) in enumerate(zip(tickets, alone)):
+        st, x, info, _ = srv.wait(t)
+        assert st == c.STGMG_OK and info['converged'] == 1, (j, st, srv.message(t))
+        assert srv.message(t) == ''
+        assert np.array_equal(x, x0), j
+    srv.close()
+
+
 def test_server_refuses_what_cannot_fit():
     c = capi()
     cfg = CONFIGS['c2s']
