@@ -261,8 +261,9 @@ def main():
                     help='run a plain 1 GiB device copy first (reference for HBM byte counters)')
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get('WORLD_SIZE', '1')) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (independent problems "
-              "would be sharded across GPUs; see the sharding notes in the design document).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (independent problems "
+              "would be placed one per GPU; one large problem would be split into slabs of cells with "
+              "halo exchanges).", file=sys.stderr)
         sys.exit(2)
     if args.config == 'batch':
         return run_batch(args)
