@@ -1997,8 +1997,10 @@ int patch_apply_red_threads(int max_nr, bool fp32) {
   return th;
 }
 
-// levels with fewer patches than this run the tiled solve with 4 waves per patch
-constexpr int64_t SYM_MULTI_BELOW = 8192;
+// levels with fewer patches than this run the tiled solve with 4 waves per patch (256^2 dG(2)
+// solves/s with the threshold at 0 / 256 / 1,024 / 4,096 / 8,192 / 20,000 patches: 18.0 / 18.1 /
+// 18.3 / 18.4 / 18.1 / 17.2; the 64^2 level's 4,225 patches run faster with one wave each)
+constexpr int64_t SYM_MULTI_BELOW = 4096;
 
 // tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
@@ -2011,7 +2013,9 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   red_layout(max_nr, rr, &th, &W);
   size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
   if (sym) {  // W waves per patch; region B holds W partial products and D1 z at stride 8 ceil(nr / 8)
-    W = npatch < SYM_MULTI_BELOW ? 4 : 1;
+    int64_t multi = SYM_MULTI_BELOW;
+    if (const char* e = std::getenv("STGMG_SYM_MULTI_BELOW")) multi = std::atoll(e);  // tuning
+    W = npatch < multi ? 4 : 1;
     if (const char* e = std::getenv("STGMG_SYM_NW")) {  // tuning: 1 or 4
       const int v = std::atoi(e);
       if (v == 1 || v == 4) W = v;
