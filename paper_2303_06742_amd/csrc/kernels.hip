@@ -1999,8 +1999,11 @@ int patch_apply_red_threads(int max_nr, bool fp32) {
 
 // levels with fewer patches than this run the tiled solve with 4 waves per patch (256^2 dG(2)
 // solves/s with the threshold at 0 / 256 / 1,024 / 4,096 / 8,192 / 20,000 patches: 18.0 / 18.1 /
-// 18.3 / 18.4 / 18.1 / 17.2; the 64^2 level's 4,225 patches run faster with one wave each)
+// 18.3 / 18.4 / 18.1 / 17.2; the 64^2 level's 4,225 patches run faster with one wave each);
+// larger Schur blocks (more tiles per patch) keep 4 waves up to twice as many patches (122 and
+// 402 rows: 2-3% faster with 8,192 than with 4,096)
 constexpr int64_t SYM_MULTI_BELOW = 4096;
+constexpr int SYM_LARGE_NR = 96;
 
 // tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
@@ -2013,7 +2016,7 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   red_layout(max_nr, rr, &th, &W);
   size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
   if (sym) {  // W waves per patch; region B holds W partial products and D1 z at stride 8 ceil(nr / 8)
-    int64_t multi = SYM_MULTI_BELOW;
+    int64_t multi = max_nr > SYM_LARGE_NR ? 2 * SYM_MULTI_BELOW : SYM_MULTI_BELOW;
     if (const char* e = std::getenv("STGMG_SYM_MULTI_BELOW")) multi = std::atoll(e);  // tuning
     W = npatch < multi ? 4 : 1;
     if (const char* e = std::getenv("STGMG_SYM_NW")) {  // tuning: 1 or 4
