@@ -25,7 +25,10 @@
  * patch inverses, Krylov bases) and frees them in stgmg_destroy.  The caller
  * owns every vector argument; the library never keeps a pointer past the call.
  * Device vectors must be 8-byte aligned, hold n doubles and must not alias
- * each other unless stated.
+ * each other unless stated.  Every entry point that takes device vectors checks
+ * them with hipPointerGetAttributes: a NULL vector is STGMG_ERR_INVALID_ARG; host
+ * memory (pinned or not), a pointer the runtime does not know, or a misaligned one
+ * is STGMG_ERR_BAD_POINTER, returned before anything is enqueued.
  *
  * Errors: every function returns a status; no C++ exception crosses this
  * interface.  stgmg_last_error() gives a thread-local text for the last
@@ -50,6 +53,7 @@ typedef int32_t stgmg_status;
 #define STGMG_ERR_HIP (-4)
 #define STGMG_ERR_SINGULAR_PATCH (-5) /* a patch matrix A_P had a zero pivot */
 #define STGMG_ERR_NONFINITE (-6)      /* NaN/Inf in rhs, x0 or a residual */
+#define STGMG_ERR_BAD_POINTER (-7)    /* a vector argument is not device memory, or not 8-byte aligned */
 
 #define STGMG_PATCH_CELL 0   /* one patch per cell */
 #define STGMG_PATCH_VERTEX 1 /* one patch per grid vertex: the cells that touch it (Eq:DefPlm) */
@@ -112,6 +116,10 @@ typedef struct {
                             Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
   int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */
+  int32_t waves_per_patch; /* time_blocks = 3 only: wavefronts that apply one patch's tiles: 0 automatic
+                              (4 on levels of fewer than 4,096 patches -- 8,192 for Schur blocks of
+                              more than 96 rows -- and 1 on larger levels), or 1 or 4 on every level.
+                              The same operator either way, up to the order of the sums. */
 } stgmg_params;
 
 typedef struct {
@@ -122,6 +130,7 @@ typedef struct {
   double rel_res_true;   /* ||b - A x||_2 / res0, recomputed at exit */
   double rel_res_est;    /* last Givens estimate */
   double t_solve_ms;     /* wall time of the solve (device synchronised) */
+  double t_vcycle_ms;    /* device time inside the V-cycles of the solve (HIP events around each) */
 } stgmg_info;
 
 /* Build the level hierarchy for Problem 4.1 with the given parameters: level

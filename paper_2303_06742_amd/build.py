@@ -31,8 +31,9 @@ def run(cmd):
 
 
 def build(verbose=True):
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src, is_hip in SOURCES:
         obj = os.path.join(BUILD, src + '.o')
         cmd = [HIPCC] + COMMON
@@ -41,8 +42,11 @@ def build(verbose=True):
         else:
             cmd += ['-x', 'c++']
         cmd += ['-c', os.path.join(CSRC, src), '-o', obj]
-        run(cmd)
+        cmds.append(cmd)
         objs.append(obj)
+    # the translation units compile independently
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+        list(ex.map(run, cmds))
     tmp = LIB + '.tmp'
     run([HIPCC, ARCH, '-shared', '-fPIC', '-o', tmp] + objs + ['-pthread'])
     os.replace(tmp, LIB)

@@ -27,6 +27,7 @@ STGMG_ERR_OOM = -3
 STGMG_ERR_HIP = -4
 STGMG_ERR_SINGULAR_PATCH = -5
 STGMG_ERR_NONFINITE = -6
+STGMG_ERR_BAD_POINTER = -7
 PATCH = {'cell': 0, 'vertex': 1}
 PROF_PATCH_APPLY = 0
 PROF_RESIDUAL = 1
@@ -42,13 +43,14 @@ class Params(ctypes.Structure):
                 ('tau', ctypes.c_double), ('rho', ctypes.c_double), ('lam', ctypes.c_double),
                 ('mu', ctypes.c_double), ('alpha', ctypes.c_double), ('c0', ctypes.c_double),
                 ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p), ('graph', ctypes.c_int32),
-                ('time_blocks', ctypes.c_int32), ('pressure', ctypes.c_int32), ('form', ctypes.c_int32)]
+                ('time_blocks', ctypes.c_int32), ('pressure', ctypes.c_int32), ('form', ctypes.c_int32),
+                ('waves_per_patch', ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [('iters', ctypes.c_int32), ('restarts', ctypes.c_int32), ('converged', ctypes.c_int32),
                 ('res0', ctypes.c_double), ('rel_res_true', ctypes.c_double), ('rel_res_est', ctypes.c_double),
-                ('t_solve_ms', ctypes.c_double)]
+                ('t_solve_ms', ctypes.c_double), ('t_vcycle_ms', ctypes.c_double)]
 
     def as_dict(self):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
@@ -127,8 +129,9 @@ def _dptr(t, n=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_params(cfg, precision=None, graph=-1, time_blocks=None):
-    """(Params, K array kept alive by the caller) for a workloads.Config."""
+def make_params(cfg, precision=None, graph=-1, time_blocks=None, waves=0):
+    """(Params, K array kept alive by the caller) for a workloads.Config.  waves: waves per patch of
+    the tiled patch solve (0 automatic, 1 or 4)."""
     K = cfg.K_cells()
     if K is not None:
         K = np.ascontiguousarray(K, dtype=np.float64)
@@ -137,7 +140,7 @@ def make_params(cfg, precision=None, graph=-1, time_blocks=None):
                omega=cfg.omega, tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
                K=cfg.K, K_cells=None if K is None else K.ctypes.data, graph=graph,
                time_blocks=cfg.time_blocks if time_blocks is None else time_blocks,
-               pressure=PRESSURE[cfg.pressure], form=FORM[cfg.form])
+               pressure=PRESSURE[cfg.pressure], form=FORM[cfg.form], waves_per_patch=waves)
     return p, K
 
 
@@ -219,11 +222,11 @@ class Server:
 class Solver:
     """One problem hierarchy (stgmg_setup) and the calls on it."""
 
-    def __init__(self, cfg, precision=None, stream=None, graph=-1, time_blocks=None):
+    def __init__(self, cfg, precision=None, stream=None, graph=-1, time_blocks=None, waves=0):
         import torch
         self._torch = torch
         self.cfg = cfg
-        p, self._K = make_params(cfg, precision, graph, time_blocks)
+        p, self._K = make_params(cfg, precision, graph, time_blocks, waves)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _H()
         check(stgmg_setup(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), 'stgmg_setup')

@@ -151,6 +151,7 @@ struct stgmg_handle {
   hipStream_t st = nullptr;      // == own.s (default priority, non-blocking)
   hipStream_t caller = nullptr;  // the caller's stream: each call waits for it first
   hipEvent_t enter_ev = nullptr;
+  hipEvent_t vc_ev[2] = {nullptr, nullptr};  // around each V-cycle of a solve (stgmg_info.t_vcycle_ms)
   // V-cycle graph: z = B r with r read from gin and z written to gout
   bool use_graph = false;
   hipGraphExec_t graph_exec = nullptr;
@@ -185,6 +186,8 @@ struct stgmg_handle {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (enter_ev) (void)hipEventDestroy(enter_ev);
+    for (auto e : vc_ev)
+      if (e) (void)hipEventDestroy(e);
     if (hhost) (void)hipHostFree(hhost);
     for (auto& v : ev)
       for (auto& e : v) {
@@ -252,6 +255,22 @@ void check_params(const stgmg_params* p) {
   if (p->pressure != STGMG_PRESSURE_CONT && p->pressure != STGMG_PRESSURE_DISC)
     throw ApiError(STGMG_ERR_INVALID_ARG, "unknown pressure space");
   if (p->form != STGMG_FORM_V && p->form != STGMG_FORM_DTU) throw ApiError(STGMG_ERR_INVALID_ARG, "unknown formulation");
+  if (p->waves_per_patch != 0 && p->waves_per_patch != 1 && p->waves_per_patch != 4)
+    throw ApiError(STGMG_ERR_INVALID_ARG, "waves_per_patch must be 0, 1 or 4");
+}
+
+// A vector argument must be device (or managed) memory known to the runtime, 8-byte aligned.
+void check_dev(const void* p, const char* what) {
+  if (!p) throw ApiError(STGMG_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) % sizeof(double) != 0)
+    throw ApiError(STGMG_ERR_BAD_POINTER, std::string(what) + " is not 8-byte aligned");
+  hipPointerAttribute_t a{};
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();  // the failed query must not surface in a later call
+    throw ApiError(STGMG_ERR_BAD_POINTER, std::string(what) + " is not memory the HIP runtime knows");
+  }
+  if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged && !a.isManaged)
+    throw ApiError(STGMG_ERR_BAD_POINTER, std::string(what) + " is not device memory");
 }
 
 int host_threads() {
@@ -346,10 +365,12 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
       ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
       const bool f32 = h->prm.smoother_prec == STGMG_FP32;
       if (h->red && f32)
-        stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->tbc, h->prm.dim,
+        stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->prm.waves_per_patch,
+                                     h->tbc, h->prm.dim,
                                      L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
       else if (h->red)
-        stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->tbc, h->prm.dim,
+        stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->prm.waves_per_patch,
+                                     h->tbc, h->prm.dim,
                                      L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
       else if (h->tb && f32)
         stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r,
@@ -392,8 +413,18 @@ std::vector<double> dense_transposed(const stgmg::Csr& A) {
   return W;
 }
 
+// Test hook: STGMG_TEST_ZERO_PATCH=q zeroes the first block that the setup inverts for patch q of
+// the finest level (the node mass block of the reduced solves, the whole A_P of the full
+// inverses, the first time block otherwise), so that the inversion meets a zero pivot and
+// stgmg_setup returns STGMG_ERR_SINGULAR_PATCH.  Unset in normal use.
+int64_t test_zero_patch() {
+  const char* e = std::getenv("STGMG_TEST_ZERO_PATCH");
+  return e ? std::atoll(e) : -1;
+}
+
 void build(stgmg_handle* h) {
   const stgmg_params& p = h->prm;
+  const int64_t zero_patch = test_zero_patch();
   const int d = p.dim, L = p.levels - 1;
   h->L = L;
   h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
@@ -657,6 +688,8 @@ void build(stgmg_handle* h) {
           stgmg::k_fill_zero(h->st, Wb.p, cnt * stride);
           stgmg::k_patch_extract_t(h->st, p0, cnt, max_np, D.poff.p, D.pdof.p, D.A.ptr.p, D.A.col.p, D.A.val.p,
                                    woff.p, Wb.p);
+          if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
+            stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * stride, stride);
           if (p.smoother_prec == STGMG_FP32)
             stgmg::k_gj_invert_f32(h->st, nb, cnt, max_np, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
           else
@@ -787,6 +820,8 @@ void build(stgmg_handle* h) {
           if (p.smoother_prec == STGMG_FP32) {
             stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv32.p);
+            if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
+              stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch, int64_t(max_nn) * max_nn);
             if (in_lds && D.sym) {
               stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
@@ -810,6 +845,8 @@ void build(stgmg_handle* h) {
           } else {
             stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv64.p);
+            if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
+              stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch, int64_t(max_nn) * max_nn);
             if (in_lds && D.sym) {
               stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
               stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
@@ -888,6 +925,9 @@ void build(stgmg_handle* h) {
           stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
                                            D.MMs.val.p, D.KKs.ptr.p, D.KKs.col.p, D.KKs.val.p, wmm.p, wkk.p);
           stgmg::k_form_time_blocks(h->st, cnt, h->tbc, max_ns, dns.back().p, wmm.p, wkk.p, ddesc.back().p, Wb.p);
+          if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
+            stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch + blk_woff[0],
+                               (h->tbc.cplx[0] ? 4 : 1) * sq);
           if (p.smoother_prec == STGMG_FP32)
             stgmg::k_gj_invert_f32(h->st, nb, cnt * nblk, max_n, ddesc.back().p, Wb.p, D.inv32.p, stat.p);
           else
@@ -964,13 +1004,16 @@ void ensure_krylov(stgmg_handle* h, int m) {
 double device_norm2(stgmg_handle* h, const double* x, int64_t n) {
   stgmg::k_multi_dot(h->st, x, n, 1, x, n, h->partials.p, h->hdev.p, 0);
   HIPCHK(hipMemcpyAsync(h->hhost, h->hdev.p, sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->st));
   return h->hhost[0];
 }
 
 stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol, int m, int maxit,
                       stgmg_info* info) {
-  if (!rhs || !x) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL vector");
+  check_dev(rhs, "rhs");
+  check_dev(x, "x");
+  if (rhs == x) throw ApiError(STGMG_ERR_INVALID_ARG, "x must not alias rhs");
   if (m < 1 || m > 100 || maxit < 1 || !(rtol >= 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "bad solver arguments");
   auto t0 = std::chrono::steady_clock::now();
   ensure_krylov(h, m);
@@ -990,6 +1033,7 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
   stgmg_status status = STGMG_OK;
   std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
   double est = beta0 > 0 ? 1.0 : 0.0;
+  double t_vc = 0.0;
   while (beta > target && beta0 > 0) {
     if (its >= maxit) {
       status = STGMG_NOT_CONVERGED;
@@ -1004,7 +1048,9 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
     for (int j = 0; j < m; ++j) {
       double* vj = h->V.p + int64_t(j) * n;
       double* zj = h->Z.p + int64_t(j) * n;
+      HIPCHK(hipEventRecord(h->vc_ev[0], st));
       apply_B(h, vj, zj);
+      HIPCHK(hipEventRecord(h->vc_ev[1], st));
       op_apply(h, Lf, 0, zj, nullptr, h->w.p);
       // classical Gram-Schmidt, twice (CGS2)
       double* h1 = h->hdev.p;
@@ -1017,7 +1063,13 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
       stgmg::k_multi_dot(st, h->w.p, n, 1, h->w.p, n, h->partials.p, hn, 0);
       stgmg::k_scale_copy(st, h->w.p, hn, h->V.p + int64_t(j + 1) * n, n);
       HIPCHK(hipMemcpyAsync(h->hhost, h->hdev.p, (2 * (m + 2) + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipGetLastError());  // a failed launch of this iteration is reported here
       HIPCHK(hipStreamSynchronize(st));
+      {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, h->vc_ev[0], h->vc_ev[1]));
+        t_vc += ms;
+      }
       for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = h->hhost[i] + h->hhost[m + 2 + i];
       const double hnn = std::sqrt(h->hhost[2 * (m + 2)]);
       if (!std::isfinite(hnn)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite value in the Arnoldi process");
@@ -1053,8 +1105,10 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
     if (!std::isfinite(beta)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite residual");
     if (beta > target) inf.restarts++;
   }
+  HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));
   inf.iters = its;
+  inf.t_vcycle_ms = t_vc;
   inf.converged = beta <= target ? 1 : 0;
   if (!inf.converged) status = STGMG_NOT_CONVERGED;
   if (inf.converged && inf.restarts > 0) inf.restarts--;  // the final check is not a restart
@@ -1102,6 +1156,8 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     HIPCHK(hipStreamCreateWithFlags(&h->own.s, hipStreamNonBlocking));
     h->st = h->own.s;
     HIPCHK(hipEventCreateWithFlags(&h->enter_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreate(&h->vc_ev[0]));
+    HIPCHK(hipEventCreate(&h->vc_ev[1]));
     enter(h.get());
     build(h.get());
     h->prm.K_cells = nullptr;  // copied into the level data, never kept
@@ -1142,7 +1198,9 @@ stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, 
 
 stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* x_dev, double* y_dev) {
   return guarded([&] {
-    if (!h || !x_dev || !y_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(x_dev, "x");
+    check_dev(y_dev, "y");
     enter(h);
     const int l = level_index(h, level);
     op_apply(h, l, 0, x_dev, nullptr, y_dev);
@@ -1154,7 +1212,9 @@ stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* 
 
 stgmg_status stgmg_apply_vcycle(stgmg_handle* h, const double* r_dev, double* z_dev) {
   return guarded([&] {
-    if (!h || !r_dev || !z_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(r_dev, "r");
+    check_dev(z_dev, "z");
     enter(h);
     apply_B(h, r_dev, z_dev);
     HIPCHK(hipGetLastError());
@@ -1165,7 +1225,9 @@ stgmg_status stgmg_apply_vcycle(stgmg_handle* h, const double* r_dev, double* z_
 
 stgmg_status stgmg_smooth(stgmg_handle* h, int32_t level, const double* b_dev, double* d_dev, int32_t sweeps) {
   return guarded([&] {
-    if (!h || !b_dev || !d_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(b_dev, "b");
+    check_dev(d_dev, "d");
     enter(h);
     const int l = level_index(h, level);
     if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level 0 has no smoother");
@@ -1179,7 +1241,9 @@ stgmg_status stgmg_smooth(stgmg_handle* h, int32_t level, const double* b_dev, d
 
 stgmg_status stgmg_prolongate_add(stgmg_handle* h, int32_t level, const double* e_coarse_dev, double* d_fine_dev) {
   return guarded([&] {
-    if (!h || !e_coarse_dev || !d_fine_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(e_coarse_dev, "e_coarse");
+    check_dev(d_fine_dev, "d_fine");
     enter(h);
     const int l = level_index(h, level);
     if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
@@ -1192,7 +1256,9 @@ stgmg_status stgmg_prolongate_add(stgmg_handle* h, int32_t level, const double* 
 
 stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine_dev, double* b_coarse_dev) {
   return guarded([&] {
-    if (!h || !r_fine_dev || !b_coarse_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(r_fine_dev, "r_fine");
+    check_dev(b_coarse_dev, "b_coarse");
     enter(h);
     const int l = level_index(h, level);
     if (l < 1) throw ApiError(STGMG_ERR_INVALID_ARG, "level must be >= 1");
@@ -1205,7 +1271,9 @@ stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine
 
 stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_prev_end_dev, double* rhs_dev) {
   return guarded([&] {
-    if (!h || !x_prev_end_dev || !rhs_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(x_prev_end_dev, "x_prev_end");
+    check_dev(rhs_dev, "rhs");
     enter(h);
     const auto& F = h->fine_info;
     const int nt = h->T.k + 1;
@@ -1248,7 +1316,8 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
 
 stgmg_status stgmg_interpolate_solution(stgmg_handle* h, double t, double* x_block_dev) {
   return guarded([&] {
-    if (!h || !x_block_dev) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL argument");
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_dev(x_block_dev, "x_block");
     enter(h);
     std::vector<double> v;
     stgmg::interpolate_solution(h->fine_info, t, v);
@@ -1528,6 +1597,8 @@ const char* stgmg_status_string(stgmg_status s) {
     case STGMG_ERR_HIP: return "HIP error";
     case STGMG_ERR_SINGULAR_PATCH: return "singular patch matrix";
     case STGMG_ERR_NONFINITE: return "non-finite value";
+    case STGMG_ERR_BAD_POINTER: return "bad device pointer";
+    case STGMG_PENDING: return "pending";
     default: return "unknown status";
   }
 }

@@ -1481,7 +1481,7 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bo
           int64_t vol = 1;
           int bits = 0;
           for (int a = 0; a < d; ++a) {
-            int lo = -1 << 30, hi = 1 << 30;
+            int lo = -(1 << 30), hi = 1 << 30;
             for (int q = 0; q < nb; ++q)
               if (sub >> q & 1) {
                 lo = std::max(lo, r * bl[q][a]);

@@ -93,14 +93,16 @@ void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjD
                   float* out, int32_t* status);
 int patch_apply_red_threads(int max_nr, bool fp32);
 // sym: the Schur inverses stored as the symmetric tiles (tile_layout.h) of X = D2^{-1} S^{-1} D1^{-1}
-// (see k_pack_red_sym_*), applied by one wave per patch (four on small levels); else square,
-// column-major, padded.
+// (see k_pack_red_sym_*), applied by `waves` waves per patch (1 or 4; 0: four on levels of fewer
+// than 4,096 patches -- 8,192 above 96 Schur rows -- else one); else square, column-major, padded.
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
-                           const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y);
+                           int waves, const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* tpos, const int32_t* pnu, const int64_t* ioff, const double* inv,
+                           const double* r, double* y);
 void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
-                           const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y);
+                           int waves, const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* tpos, const int32_t* pnu, const int64_t* ioff, const float* inv,
+                           const double* r, double* y);
 // Symmetric tiles from square Schur inverses: one (batch item i, kept eigenvalue a) per block m =
 // i * nblk + a: S^{-1} square in sq at soff[m] (as written by k_gj_lds_f64 with ld_out = ldr or
 // 2 ldr), tiles of X = D2^{-1} S^{-1} D1^{-1}, (X + X^T)/2, written at out + toff[m]:

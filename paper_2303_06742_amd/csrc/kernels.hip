@@ -2007,7 +2007,7 @@ constexpr int SYM_LARGE_NR = 96;
 
 // tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
-static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
+static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym, int waves,
                        const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int32_t* pnu, const int64_t* ioff, const T* inv, const double* r, double* y) {
   if (npatch == 0) return;
@@ -2018,11 +2018,7 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   if (sym) {  // W waves per patch; region B holds W partial products and D1 z at stride 8 ceil(nr / 8)
     int64_t multi = max_nr > SYM_LARGE_NR ? 2 * SYM_MULTI_BELOW : SYM_MULTI_BELOW;
     if (const char* e = std::getenv("STGMG_SYM_MULTI_BELOW")) multi = std::atoll(e);  // tuning
-    W = npatch < multi ? 4 : 1;
-    if (const char* e = std::getenv("STGMG_SYM_NW")) {  // tuning: 1 or 4
-      const int v = std::atoi(e);
-      if (v == 1 || v == 4) W = v;
-    }
+    W = waves == 1 || waves == 4 ? waves : npatch < multi ? 4 : 1;
     th = 64 * W;
     const size_t ldr = inv_ld(max_nr), ns = max_np / tb.nt, ldt = 8 * ((max_nr + 7) / 8);
     const size_t a = std::max<size_t>(max_np, 2 * size_t(tb.nblk) * (max_nu + ldr));
@@ -2065,14 +2061,16 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
 }
 
 void k_patch_apply_red_f64(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
-                           const int32_t* pnu, const int64_t* ioff, const double* inv, const double* r, double* y) {
-  launch_red<double>(st, npatch, max_np, max_nu, max_nr, sym, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
+                           int waves, const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* tpos, const int32_t* pnu, const int64_t* ioff, const double* inv,
+                           const double* r, double* y) {
+  launch_red<double>(st, npatch, max_np, max_nu, max_nr, sym, waves, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
-                           const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
-                           const int32_t* pnu, const int64_t* ioff, const float* inv, const double* r, double* y) {
-  launch_red<float>(st, npatch, max_np, max_nu, max_nr, sym, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
+                           int waves, const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                           const int32_t* tpos, const int32_t* pnu, const int64_t* ioff, const float* inv,
+                           const double* r, double* y) {
+  launch_red<float>(st, npatch, max_np, max_nu, max_nr, sym, waves, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
 
 void k_pack_red_sym_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,

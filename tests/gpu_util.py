@@ -21,15 +21,27 @@ def to_host(t):
     return t.detach().cpu().numpy()
 
 
+def oracle_params(cfg):
+    from oracle import problem
+    K = cfg.K_cells()
+    return problem.Params(rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
+                          K=cfg.K if K is None else K, pressure=cfg.pressure, form=cfg.form)
+
+
+def oracle_direct_solve(cfg, F):
+    """The oracle's sparse direct solve of the fine-level slab system of a config."""
+    from oracle import problem
+    prob = problem.SlabProblem(cfg.dim, cfg.fine_cells, cfg.r, cfg.k, cfg.tau, oracle_params(cfg))
+    return prob.direct_solve(F), prob.A
+
+
 @functools.lru_cache(maxsize=8)
 def oracle_hierarchy(cfg_key):
-    from oracle import gmg, problem
+    from oracle import gmg
     # the storage of the patch solves does not change the operator
     cfg_key = cfg_key.replace('_full', '').replace('_tb', '').replace('_red', '')
     cfg = CONFIGS[cfg_key]
-    K = cfg.K_cells()
-    prm = problem.Params(rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
-                         K=cfg.K if K is None else K, pressure=cfg.pressure, form=cfg.form)
+    prm = oracle_params(cfg)
     return gmg.Hierarchy(cfg.dim, cfg.coarse_cells, cfg.levels - 1, cfg.r, cfg.k, cfg.tau, prm,
                          patch_kind=cfg.patch, J=cfg.n_smooth, omega=cfg.omega)
 
@@ -74,4 +86,7 @@ CONFIGS = {
     'c1_b1_tb': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-tb', form='dtu', time_blocks=1),
     'c1_b1_full': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-full', form='dtu', time_blocks=0),
     'c3s_disc_b1': W.scaled(W.C3, 2, name='3d-8cube-q2p1disc-dg1-cell-lognormal-b1', pressure='disc', form='dtu'),
+    # the benchmark's physics on 64^2 (5 levels): 4,225 finest patches, where the tiled patch solve
+    # picks one wave per patch by itself (four on the coarser levels)
+    'c2_64': W.scaled(W.C2, 5, name='2d-64x64-dg2-vertex'),
 }

@@ -3,7 +3,7 @@ alone and in a mix (bitwise: no reduction crosses problems)."""
 import numpy as np
 import pytest
 
-from tests.gpu_util import CONFIGS, require_gpu, to_dev, to_host
+from tests.gpu_util import CONFIGS, oracle_direct_solve, require_gpu, to_dev, to_host
 from paper_2303_06742_amd import workloads
 
 pytestmark = pytest.mark.gpu
@@ -131,4 +131,46 @@ def test_server_refuses_what_cannot_fit():
     with pytest.raises(c.StgmgError) as e:
         srv.submit(cfg, np.zeros(n))
     assert e.value.status == c.STGMG_ERR_OOM
+    srv.close()
+
+
+def _check_against_oracle(cfg, F, x, info, what):
+    ref, A = oracle_direct_solve(cfg, F)
+    res = np.linalg.norm(F - A @ x) / np.linalg.norm(F)
+    err = np.abs(x - ref).max() / np.abs(ref).max()
+    print(f"[{what}] {cfg.name} iters={info['iters']} rel_res={res:.2e} err_vs_oracle={err:.2e}", flush=True)
+    assert info['converged'] == 1 and res <= 1e-10 * (1 + 1e-6) and err < 1e-7
+
+
+def test_batch_against_oracle():
+    """Batched random-physics problems (FP32 patch solves, FP64 FGMRES, rtol 1e-10) against the
+    oracle's sparse direct solve of the same problems: residual through the oracle's operator
+    <= 1e-10 and solution error < 1e-7."""
+    c = capi()
+    cfgs = workloads.batch_configs(3, seed=21, sizes=(16,))
+    solvers = [c.Solver(cfg) for cfg in cfgs]
+    F = [workloads.random_vector(s.n, 40 + i) for i, s in enumerate(solvers)]
+    xs = [s.empty() for s in solvers]
+    infos = c.solve_batch(solvers, [to_dev(f) for f in F], xs, rtol=1e-10)
+    for cfg, f, x, info in zip(cfgs, F, xs, infos):
+        _check_against_oracle(cfg, f, to_host(x), info, 'batch')
+    for s in solvers:
+        s.close()
+
+
+def test_server_against_oracle():
+    """Served random-physics requests (a 2D vertex-patch and a 3D cell-patch problem, FP32 patch
+    solves) against the oracle's sparse direct solve, as in the batch test."""
+    c = capi()
+    mix = workloads.serve_mix(6, seed=31, sizes2d=(16,), sizes3d=(4,), p3d=0.5, p_follow=0.0)
+    picked = [next(m for m in mix if m[1].dim == 2), next(m for m in mix if m[1].dim == 3)]
+    srv = c.Server(hbm_budget=64 << 30, max_slots=2, resident_max=2)
+    reqs = []
+    for j, (key, cfg) in enumerate(picked):
+        F = workloads.random_vector(c.footprint(cfg)[0], 70 + j)
+        reqs.append((cfg, F, srv.submit(cfg, F, key=key, rtol=1e-10)))
+    for cfg, F, t in reqs:
+        st, x, info, _ = srv.wait(t)
+        assert st == c.STGMG_OK, srv.message(t)
+        _check_against_oracle(cfg, F, x, info, 'serve')
     srv.close()

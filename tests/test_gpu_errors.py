@@ -72,3 +72,61 @@ def test_restart_short_cycles():
     assert ia['converged'] and ib['converged']
     d = np.abs(to_host(a) - to_host(b)).max() / np.abs(to_host(a)).max()
     assert d < 1e-6
+
+
+def test_bad_pointers_rejected_before_launch():
+    """Vector arguments are checked before anything is enqueued: NULL is INVALID_ARG; pinned host
+    memory, pageable host memory and a misaligned device address are BAD_POINTER.  The handle
+    stays usable afterwards."""
+    import torch
+    c = capi()
+    S = c.Solver(CONFIGS['c1'])
+    n = S.n
+    x = S.empty()
+    y = S.empty()
+    dp = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    assert c.stgmg_apply_operator(S.h, -1, None, dp(y)) == c.STGMG_ERR_INVALID_ARG
+    pinned = torch.zeros(n, dtype=torch.float64).pin_memory()
+    assert c.stgmg_apply_operator(S.h, -1, dp(pinned), dp(y)) == c.STGMG_ERR_BAD_POINTER
+    assert b"device memory" in c.stgmg_last_error()
+    host = np.zeros(n)
+    assert c.stgmg_apply_vcycle(S.h, host.ctypes.data_as(ctypes.c_void_p), dp(y)) == c.STGMG_ERR_BAD_POINTER
+    buf = S.empty(n + 1)
+    mis = ctypes.c_void_p(buf.data_ptr() + 4)
+    assert c.stgmg_apply_operator(S.h, -1, dp(x), mis) == c.STGMG_ERR_BAD_POINTER
+    assert b"aligned" in c.stgmg_last_error()
+    info = c.Info()
+    assert c.stgmg_solve(S.h, dp(pinned), dp(x), 1e-8, 30, 100, ctypes.byref(info)) == c.STGMG_ERR_BAD_POINTER
+    assert c.stgmg_solve(S.h, dp(x), dp(x), 1e-8, 30, 100, ctypes.byref(info)) == c.STGMG_ERR_INVALID_ARG
+    # still usable
+    F = to_dev(workloads.random_vector(n, 5))
+    info = S.solve(F, x)
+    assert info['converged'] == 1
+    assert 0.0 < info['t_vcycle_ms'] <= info['t_solve_ms']
+    S.close()
+
+
+def test_invalid_waves_rejected():
+    c = capi()
+    p, _K = c.make_params(CONFIGS['c1'], waves=2)
+    h = ctypes.c_void_p()
+    assert c.stgmg_setup(ctypes.byref(p), None, ctypes.byref(h)) == c.STGMG_ERR_INVALID_ARG
+    assert b"waves_per_patch" in c.stgmg_last_error()
+
+
+@pytest.mark.parametrize("key", ['c2s', 'c1_full', 'c1_tb'])
+def test_singular_patch_reported(key, monkeypatch):
+    """A patch block with a zero pivot (zeroed on the device by the setup's test hook) makes
+    stgmg_setup return SINGULAR_PATCH naming the patch; the inversion kernel flags the pivot and
+    finishes normally, and a following setup without the hook succeeds."""
+    c = capi()
+    monkeypatch.setenv('STGMG_TEST_ZERO_PATCH', '3')
+    with pytest.raises(c.StgmgError) as e:
+        c.Solver(CONFIGS[key])
+    assert e.value.status == c.STGMG_ERR_SINGULAR_PATCH
+    assert 'patch 3 ' in str(e.value)
+    monkeypatch.delenv('STGMG_TEST_ZERO_PATCH')
+    S = c.Solver(CONFIGS[key])
+    info = S.solve(to_dev(workloads.random_vector(S.n, 6)), S.empty())
+    assert info['converged'] == 1
+    S.close()

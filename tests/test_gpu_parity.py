@@ -11,13 +11,13 @@ pytestmark = pytest.mark.gpu
 _solvers = {}
 
 
-def solver(key, precision=None):
+def solver(key, precision=None, waves=0):
     require_gpu()
     from paper_2303_06742_amd import capi
-    tag = (key, precision)
+    tag = (key, precision, waves)
     if tag not in _solvers:
-        print(f"[setup] {CONFIGS[key].name} {precision or CONFIGS[key].precision}", flush=True)
-        _solvers[tag] = capi.Solver(CONFIGS[key], precision=precision)
+        print(f"[setup] {CONFIGS[key].name} {precision or CONFIGS[key].precision} waves={waves}", flush=True)
+        _solvers[tag] = capi.Solver(CONFIGS[key], precision=precision, waves=waves)
     return _solvers[tag]
 
 
@@ -29,6 +29,13 @@ def rel_err(a, b, scale=None):
 KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'k3', 'c3v', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb',
         'c3s_tb', 'k0_tb', 'c1_disc', 'c2d', 'c3s_disc', 'c2d_full', 'c2s_b1', 'c1_b1_tb', 'c1_b1_full',
         'c3s_disc_b1', 'c2s_red', 'c3s_red', 'k3_red', 'c3v_red', 'c2d_red', 'c2s_b1_red']
+# configs whose patch solves use the symmetric tiles (time_blocks = 3): the tile kernel runs with one
+# wave per patch on large levels and four on small ones; both variants are compared with the oracle
+TILED = [k for k in KEYS if CONFIGS[k].time_blocks == 3]
+# (key, waves per patch): 0 = automatic (four waves on these test sizes)
+CASES = [(k, 0) for k in KEYS if k not in TILED] + [(k, w) for k in TILED for w in (1, 4)]
+# FP32 storage keeps the tiles up to 96 Schur rows (c3v: 402-row blocks in the square layout)
+CASES32 = [(k, w) for k in TILED for w in (1, 4)]
 
 
 @pytest.mark.parametrize("key", KEYS)
@@ -95,11 +102,11 @@ def test_fp32_tile_readback(key):
         assert np.abs(X32 - X64).max() <= 1e-3 * np.abs(X64).max(), (key, q)
 
 
-@pytest.mark.parametrize("key", KEYS)
-def test_smoother(key):
+@pytest.mark.parametrize("key,waves", CASES)
+def test_smoother(key, waves):
     """Algorithm 4.1 sweeps on the finest level from a random iterate."""
     from oracle import gmg
-    S = solver(key)
+    S = solver(key, waves=waves)
     H = oracle_hierarchy(key)
     lev = H.levels[-1]
     b = workloads.random_vector(lev.n, 11)
@@ -110,9 +117,9 @@ def test_smoother(key):
         assert rel_err(d, ref) < 1e-10, (key, sweeps, rel_err(d, ref))
 
 
-@pytest.mark.parametrize("key", KEYS + ['one_level'])
-def test_vcycle(key):
-    S = solver(key)
+@pytest.mark.parametrize("key,waves", CASES + [('one_level', 0)])
+def test_vcycle(key, waves):
+    S = solver(key, waves=waves)
     H = oracle_hierarchy(key)
     r = workloads.random_vector(S.n, 21)
     z = to_host(S.vcycle(to_dev(r)))
@@ -120,12 +127,13 @@ def test_vcycle(key):
     assert rel_err(z, ref) < 1e-10, (key, rel_err(z, ref))
 
 
-@pytest.mark.parametrize("key", KEYS)
-def test_solve_against_oracle(key):
-    """FGMRES-GMG to rtol 1e-8: same iteration count as the oracle's FGMRES-GMG, and the
-    solution agrees with the oracle's direct solve to the accuracy the tolerance allows."""
+@pytest.mark.parametrize("key,waves", CASES)
+def test_solve_against_oracle(key, waves):
+    """FGMRES-GMG to rtol 1e-8: same iteration count as the oracle's FGMRES-GMG (+-1, the
+    stopping test sits on a rounding edge), and at equal iteration count the iterate agrees
+    with the oracle's FGMRES iterate to 1e-10."""
     from oracle import fgmres
-    S = solver(key)
+    S = solver(key, waves=waves)
     H = oracle_hierarchy(key)
     A = H.levels[-1].A
     F = workloads.random_vector(S.n, 31)
@@ -138,7 +146,50 @@ def test_solve_against_oracle(key):
     assert abs(info['iters'] - oi['iters']) <= 1, (info['iters'], oi['iters'])
     # equal iteration counts: the two iterates agree to the rounding of the V-cycle
     xg, _ = fgmres.fgmres(A, F, H.precondition, rtol=0.0, fixed_iters=info['iters'])
-    assert rel_err(xs, xg) < 1e-8, rel_err(xs, xg)
+    e = rel_err(xs, xg)
+    print(f"[iterate] {key} waves={waves} iters={info['iters']} rel_err={e:.2e}", flush=True)
+    assert e < 1e-10, e
+
+
+@pytest.mark.parametrize("key,waves", CASES32)
+def test_fp32_smoother_against_oracle(key, waves):
+    """FP32 storage of the patch solves (FP64 sums), Algorithm 4.1 sweeps against the oracle's
+    FP64 sweeps.  Each stored value carries a relative rounding of at most 2^-24; through the
+    reduced factors the applied inverse differs from the exact one by about 1e-6 of its largest
+    entries (the readback test measures 1.6e-5 of the largest entry in the reconstructed dense
+    inverse), so one sweep agrees to 1e-5 of max|d|."""
+    from oracle import gmg
+    S = solver(key, 'fp32', waves=waves)
+    H = oracle_hierarchy(key)
+    lev = H.levels[-1]
+    b = workloads.random_vector(lev.n, 13)
+    d0 = workloads.random_vector(lev.n, 14)
+    for sweeps in (1, 4):
+        d = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), sweeps))
+        ref = gmg.vanka_smooth(lev, b, d0, sweeps, H.omega)
+        e = rel_err(d, ref)
+        print(f"[fp32 smoother] {key} waves={waves} sweeps={sweeps} rel_err={e:.2e}", flush=True)
+        assert e < 1e-5, (key, sweeps, e)
+
+
+@pytest.mark.parametrize("key,waves", CASES32)
+def test_fp32_solve_against_oracle(key, waves):
+    """The mixed path (FP32 patch solves inside FP64 FGMRES) against the oracle's FP64 sparse
+    direct solve: stopped at rtol 1e-10, the true relative residual is <= 1e-10 (so <= 1e-8) and
+    the solution is within 1e-7 of the oracle's (relative, max norm)."""
+    from tests.gpu_util import oracle_direct_solve
+    S = solver(key, 'fp32', waves=waves)
+    cfg = CONFIGS[key]
+    F = workloads.random_vector(S.n, 53)
+    x = S.empty()
+    info = S.solve(to_dev(F), x, rtol=1e-10)
+    ref, A = oracle_direct_solve(cfg, F)
+    xs = to_host(x)
+    assert info['converged'] == 1
+    assert np.linalg.norm(F - A @ xs) <= 1e-10 * np.linalg.norm(F) * (1 + 1e-6)
+    e = rel_err(xs, ref)
+    print(f"[fp32 solve] {key} waves={waves} iters={info['iters']} err_vs_oracle={e:.2e}", flush=True)
+    assert e < 1e-7, e
 
 
 @pytest.mark.parametrize("key", ['c1', 'c2s', 'c1_disc', 'c2d', 'c3s_disc', 'c2s_b1', 'c3s_disc_b1'])
@@ -223,3 +274,43 @@ def test_graph_replays_match_eager(key):
     assert ig['iters'] == ie['iters'] and np.array_equal(to_host(xg), to_host(xe))
     Sg.close()
     Se.close()
+
+
+@pytest.mark.parametrize("precision", ['fp64', 'fp32'])
+def test_c2_64_automatic_waves(precision):
+    """The benchmark's physics on 64^2 with the automatic wave count: one wave per patch on the
+    finest level (4,225 patches), four on the coarser ones.  Smoother, V-cycle and FGMRES against
+    the oracle (FP64: 1e-10 and equal iteration counts +-1; FP32 storage: 1e-5 per sweep, and the
+    solution within 1e-7 of the oracle's direct solve)."""
+    from oracle import gmg
+    from tests.gpu_util import oracle_direct_solve
+    S = solver('c2_64', precision)
+    assert S.query(-1)['patches'] == 4225
+    H = oracle_hierarchy('c2_64')
+    lev = H.levels[-1]
+    tol = 1e-10 if precision == 'fp64' else 1e-5
+    b = workloads.random_vector(lev.n, 15)
+    d0 = workloads.random_vector(lev.n, 16)
+    d = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 1))
+    e = rel_err(d, gmg.vanka_smooth(lev, b, d0, 1, H.omega))
+    print(f"[c2_64 {precision}] smoother rel_err={e:.2e}", flush=True)
+    assert e < tol
+    r = workloads.random_vector(S.n, 22)
+    e = rel_err(to_host(S.vcycle(to_dev(r))), H.precondition(r))
+    print(f"[c2_64 {precision}] vcycle rel_err={e:.2e}", flush=True)
+    assert e < tol
+    F = workloads.random_vector(S.n, 32)
+    x = S.empty()
+    if precision == 'fp64':
+        from oracle import fgmres
+        info = S.solve(to_dev(F), x, rtol=1e-8)
+        xg, oi = fgmres.fgmres(lev.A, F, H.precondition, rtol=0.0, fixed_iters=info['iters'])
+        e = rel_err(to_host(x), xg)
+        print(f"[c2_64 fp64] iters={info['iters']} iterate rel_err={e:.2e}", flush=True)
+        assert info['converged'] == 1 and e < 1e-10
+    else:
+        info = S.solve(to_dev(F), x, rtol=1e-10)
+        ref, A = oracle_direct_solve(CONFIGS['c2_64'], F)
+        e = rel_err(to_host(x), ref)
+        print(f"[c2_64 fp32] iters={info['iters']} err_vs_oracle={e:.2e}", flush=True)
+        assert info['converged'] == 1 and e < 1e-7
