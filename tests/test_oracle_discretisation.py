@@ -98,24 +98,30 @@ def test_energy_decay():
     assert E[-1] < E[0]
 
 
-def test_table_c1_row1_magnitude():
-    """Appendix C, Table C.1, row 1 (Q4^2/Q3, dG(3), 4x4 cells, tau = 0.1, I = (1,2]).
+@pytest.mark.slow
+def test_table_c1_asymptotic_rates():
+    """Appendix C, Table C.1 (Q4^2/Q3, dG(3), I = (1,2], tau and h halved together): the oracle's
+    L2(L2) orders between rows 2 and 3 (8x8 cells, tau = 0.05; 16x16, tau = 0.025) equal the
+    printed asymptotic orders, those between rows 4 and 5 (4.00, 4.09, 4.03), to 0.1.
 
-    The printed errors are not reproduced digit for digit by the readings taken
-    here (they come out 1.4-7x smaller; the asymptotic rates agree).  This test
-    records the present values and bounds the mismatch; it is not a pin of the
-    error magnitudes."""
+    The printed magnitudes are not reproduced: the oracle's row-1 errors are 0.36 / 0.14 / 0.20
+    of the printed ones and its rows 2-3 already sit in the asymptotic regime, while the printed
+    row 1 is pre-asymptotic (orders 4.5 / 5.0 / 4.3 to row 2).  The readings tried (penalty
+    face size, rounded Lame constants, source quadrature in time, norm quadrature, interval,
+    displacement direction) leave the gap; the magnitudes are parity unpinned."""
     vals = {}
     for line in open(os.path.join(HERE, 'golden', 'table_c1_row1.txt')):
         if line.strip() and not line.startswith('#'):
             key, *nums = line.split()
             vals[key] = np.array([float(x) for x in nums])
+    printed = np.log2(vals['L2_row4'] / vals['L2_row5'])
     lam, mu = problem.lame_from_young(100.0, 0.35)
     prm = problem.Params(rho=1.0, lam=lam, mu=mu, alpha=0.9, c0=0.01, K=1.0)
     phi = "sin(pi*t**2)*sin(pi*x)*sin(pi*y)"
     sol = problem.ExactSolution(2, [phi, phi], phi, prm)
-    pr = problem.SlabProblem(2, 4, 4, 3, 0.1, prm)
-    Xs = pr.march(sol, 1.0, 10)
-    e = norms.error_norms(pr, sol, Xs, 1.0, M=100)
-    ratio = np.concatenate([e['L2'] / vals['L2'], e['Linf'] / vals['Linf']])
-    assert np.all((ratio > 0.08) & (ratio < 1.0)), ratio
+    errs = []
+    for lev in (1, 2):
+        pr = problem.SlabProblem(2, 4 * 2 ** lev, 4, 3, 0.1 / 2 ** lev, prm)
+        errs.append(norms.error_norms(pr, sol, pr.march(sol, 1.0, 10 * 2 ** lev), 1.0, M=4)['L2'])
+    eoc = np.log2(errs[0] / errs[1])
+    assert np.all(np.abs(eoc - printed) < 0.1), (eoc, printed)
