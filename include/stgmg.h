@@ -158,6 +158,21 @@ stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, 
 stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, double rtol,
                          int32_t restart, int32_t max_iters, stgmg_info* info);
 
+/* Allocation-free variant of stgmg_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * FGMRES and V-cycle kernels, with the FGMRES workspace (bases V and Z, Arnoldi vector, dot
+ * product partial sums, Hessenberg column, update coefficients: about (2 restart + 2) n doubles)
+ * in a static device array of STGMG_NOALLOC_SCRATCH_BYTES, which each GPU the library runs on
+ * holds until the process ends.  It calls no hipMalloc/hipFree (the hierarchy was allocated by
+ * stgmg_setup).  Returns STGMG_ERR_UNSUPPORTED, before anything is enqueued, when the workspace
+ * of n unknowns and `restart` does not fit (e.g. n above about 260,000 at restart 30).  All
+ * calls on one GPU share that GPU's array, whose contents persist from the last call: calls
+ * that overlap in time on one GPU (other threads, other handles) race and must be serialised
+ * by the caller.  Arguments, result and statuses as for stgmg_solve. */
+#define STGMG_NOALLOC_SCRATCH_BYTES (128LL << 20)
+stgmg_status stgmg_solve_noalloc(stgmg_handle* h, const double* rhs_dev, double* x_dev, double rtol,
+                                 int32_t restart, int32_t max_iters, stgmg_info* info);
+
 /* y = A_level x (the assembled level operator of Eq:DefAn). level -1 = finest. */
 stgmg_status stgmg_apply_operator(stgmg_handle* h, int32_t level, const double* x_dev, double* y_dev);
 

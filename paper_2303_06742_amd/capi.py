@@ -73,6 +73,7 @@ stgmg_setup = _decl('stgmg_setup', [ctypes.POINTER(Params), _P, ctypes.POINTER(_
 stgmg_query = _decl('stgmg_query', [_H, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                     ctypes.POINTER(_I64)])
 stgmg_solve = _decl('stgmg_solve', [_H, _P, _P, _D, _I32, _I32, ctypes.POINTER(Info)])
+stgmg_solve_noalloc = _decl('stgmg_solve_noalloc', [_H, _P, _P, _D, _I32, _I32, ctypes.POINTER(Info)])
 stgmg_apply_operator = _decl('stgmg_apply_operator', [_H, _I32, _P, _P])
 stgmg_apply_vcycle = _decl('stgmg_apply_vcycle', [_H, _P, _P])
 stgmg_smooth = _decl('stgmg_smooth', [_H, _I32, _P, _P, _I32])
@@ -98,7 +99,7 @@ stgmg_destroy = _decl('stgmg_destroy', [_H])
 stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
 stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
 
-EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
+EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_solve_noalloc', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
             'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs',
             'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_profile_enable', 'stgmg_profile_get',
             'stgmg_destroy', 'stgmg_status_string', 'stgmg_last_error', 'stgmg_footprint', 'stgmg_solve_batch',

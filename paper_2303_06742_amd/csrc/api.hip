@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -21,9 +22,20 @@
 #include "kernels.h"
 #include "stgmg.h"
 
+// Workspace of stgmg_solve_noalloc: one file-scope device array, so that the call allocates
+// nothing.  Every GPU the library runs on holds its own copy (loaded with the code object) until
+// the process ends.  Host code never passes `scratch` itself to a kernel (on the host the name
+// is only a stand-in for the symbol): it uses the device address that hipGetSymbolAddress returns
+// for the current device, kept per device in g_scratch.
+static __device__ __align__(256) double scratch[STGMG_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch[MAX_DEVICES] = {};  // device address of `scratch` on each device, once looked up
 
 struct ApiError : std::runtime_error {
   stgmg_status code;
@@ -152,6 +164,7 @@ struct stgmg_handle {
   hipStream_t caller = nullptr;  // the caller's stream: each call waits for it first
   hipEvent_t enter_ev = nullptr;
   hipEvent_t vc_ev[2] = {nullptr, nullptr};  // around each V-cycle of a solve (stgmg_info.t_vcycle_ms)
+  int dev = 0;  // the device current at setup (its static scratch serves stgmg_solve_noalloc)
   // V-cycle graph: z = B r with r read from gin and z written to gout
   bool use_graph = false;
   hipGraphExec_t graph_exec = nullptr;
@@ -180,7 +193,7 @@ struct stgmg_handle {
   // FGMRES workspace
   int m_alloc = 0;
   DArr<double> V, Z, w, partials, hdev, ydev;
-  double* hhost = nullptr;  // pinned
+  double* hhost = nullptr;  // pinned, 512 doubles: Hessenberg column reads, then the FGMRES update coefficients at 256
   DArr<double> gin, gout;
   ~stgmg_handle() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
@@ -985,45 +998,81 @@ void build(stgmg_handle* h) {
   }
   h->tmp_ns.alloc(h->fine_info.ns, ctr, h->st);
   h->src_buf.alloc(h->fine_info.n, ctr, h->st);
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 256 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 512 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(h->st));
 }
 
-void ensure_krylov(stgmg_handle* h, int m) {
-  if (h->m_alloc >= m) return;
-  const int64_t n = h->lv[h->L].n;
-  h->V.alloc(int64_t(m + 1) * n, &h->bytes, h->st);
-  h->Z.alloc(int64_t(m) * n, &h->bytes, h->st);
-  h->w.alloc(n, &h->bytes, h->st);
-  h->partials.alloc(int64_t(m + 2) * stgmg::dot_blocks(n), &h->bytes, h->st);
-  h->hdev.alloc(2 * (m + 2) + 4, &h->bytes, h->st);
-  h->ydev.alloc(m + 1, &h->bytes, h->st);
-  h->m_alloc = m;
+// FGMRES workspace of restart length m on n unknowns: the bases V (m+1 vectors) and Z (m), the
+// Arnoldi vector w, per-block partial sums of the dot products, the Hessenberg column (two CGS
+// passes and the norm) and the coefficients y of the update.
+struct Krylov {
+  double *V, *Z, *w, *partials, *hdev, *ydev;
+};
+constexpr int64_t KRYLOV_ALIGN = 32;  // doubles: every region starts 256-byte aligned
+int64_t krylov_region(int64_t count) { return (count + KRYLOV_ALIGN - 1) / KRYLOV_ALIGN * KRYLOV_ALIGN; }
+int64_t krylov_doubles(int64_t n, int m) {
+  return krylov_region(int64_t(m + 1) * n) + krylov_region(int64_t(m) * n) + krylov_region(n) +
+         krylov_region(int64_t(m + 2) * stgmg::dot_blocks(n)) + krylov_region(2 * (m + 2) + 4) + krylov_region(m + 1);
+}
+Krylov krylov_in(double* base, int64_t n, int m) {
+  Krylov k;
+  double* p = base;
+  k.V = p;
+  p += krylov_region(int64_t(m + 1) * n);
+  k.Z = p;
+  p += krylov_region(int64_t(m) * n);
+  k.w = p;
+  p += krylov_region(n);
+  k.partials = p;
+  p += krylov_region(int64_t(m + 2) * stgmg::dot_blocks(n));
+  k.hdev = p;
+  p += krylov_region(2 * (m + 2) + 4);
+  k.ydev = p;
+  return k;
 }
 
-double device_norm2(stgmg_handle* h, const double* x, int64_t n) {
-  stgmg::k_multi_dot(h->st, x, n, 1, x, n, h->partials.p, h->hdev.p, 0);
-  HIPCHK(hipMemcpyAsync(h->hhost, h->hdev.p, sizeof(double), hipMemcpyDeviceToHost, h->st));
+// The handle's own workspace, allocated on first use (and grown for a longer restart).
+Krylov ensure_krylov(stgmg_handle* h, int m) {
+  if (h->m_alloc < m) {
+    const int64_t n = h->lv[h->L].n;
+    h->V.alloc(int64_t(m + 1) * n, &h->bytes, h->st);
+    h->Z.alloc(int64_t(m) * n, &h->bytes, h->st);
+    h->w.alloc(n, &h->bytes, h->st);
+    h->partials.alloc(int64_t(m + 2) * stgmg::dot_blocks(n), &h->bytes, h->st);
+    h->hdev.alloc(2 * (m + 2) + 4, &h->bytes, h->st);
+    h->ydev.alloc(m + 1, &h->bytes, h->st);
+    h->m_alloc = m;
+  }
+  return Krylov{h->V.p, h->Z.p, h->w.p, h->partials.p, h->hdev.p, h->ydev.p};
+}
+
+double device_norm2(stgmg_handle* h, const Krylov& K, const double* x, int64_t n) {
+  stgmg::k_multi_dot(h->st, x, n, 1, x, n, K.partials, K.hdev, 0);
+  HIPCHK(hipMemcpyAsync(h->hhost, K.hdev, sizeof(double), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(h->st));
   return h->hhost[0];
 }
 
-stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol, int m, int maxit,
-                      stgmg_info* info) {
+void check_solve_args(const double* rhs, const double* x, double rtol, int m, int maxit) {
   check_dev(rhs, "rhs");
   check_dev(x, "x");
   if (rhs == x) throw ApiError(STGMG_ERR_INVALID_ARG, "x must not alias rhs");
   if (m < 1 || m > 100 || maxit < 1 || !(rtol >= 0)) throw ApiError(STGMG_ERR_INVALID_ARG, "bad solver arguments");
+}
+
+// FGMRES(m) with the workspace K (the handle's own, or the static scratch of the allocation-free
+// entry point); the arguments have been checked.
+stgmg_status do_solve(stgmg_handle* h, const Krylov& K, const double* rhs, double* x, double rtol, int m, int maxit,
+                      stgmg_info* info) {
   auto t0 = std::chrono::steady_clock::now();
-  ensure_krylov(h, m);
   const int64_t n = h->lv[h->L].n;
   const int Lf = h->L;
   hipStream_t st = h->st;
   stgmg_info inf{};
   // r0 = rhs - A x0
-  op_apply(h, Lf, 1, x, rhs, h->w.p);
-  const double b0sq = device_norm2(h, h->w.p, n);
+  op_apply(h, Lf, 1, x, rhs, K.w);
+  const double b0sq = device_norm2(h, K, K.w, n);
   if (!std::isfinite(b0sq)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite initial residual (rhs or x0)");
   const double beta0 = std::sqrt(b0sq);
   inf.res0 = beta0;
@@ -1040,29 +1089,29 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
       break;
     }
     // v_0 = r / beta   (h->hdev[0] still holds ||r||^2 from device_norm2)
-    stgmg::k_scale_copy(st, h->w.p, h->hdev.p, h->V.p, n);
+    stgmg::k_scale_copy(st, K.w, K.hdev, K.V, n);
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jd = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = h->V.p + int64_t(j) * n;
-      double* zj = h->Z.p + int64_t(j) * n;
+      double* vj = K.V + int64_t(j) * n;
+      double* zj = K.Z + int64_t(j) * n;
       HIPCHK(hipEventRecord(h->vc_ev[0], st));
       apply_B(h, vj, zj);
       HIPCHK(hipEventRecord(h->vc_ev[1], st));
-      op_apply(h, Lf, 0, zj, nullptr, h->w.p);
+      op_apply(h, Lf, 0, zj, nullptr, K.w);
       // classical Gram-Schmidt, twice (CGS2)
-      double* h1 = h->hdev.p;
-      double* h2 = h->hdev.p + (m + 2);
-      double* hn = h->hdev.p + 2 * (m + 2);
-      stgmg::k_multi_dot(st, h->V.p, n, j + 1, h->w.p, n, h->partials.p, h1, 0);
-      stgmg::k_multi_axpy(st, h->V.p, n, j + 1, h1, -1.0, h->w.p, n);
-      stgmg::k_multi_dot(st, h->V.p, n, j + 1, h->w.p, n, h->partials.p, h2, 0);
-      stgmg::k_multi_axpy(st, h->V.p, n, j + 1, h2, -1.0, h->w.p, n);
-      stgmg::k_multi_dot(st, h->w.p, n, 1, h->w.p, n, h->partials.p, hn, 0);
-      stgmg::k_scale_copy(st, h->w.p, hn, h->V.p + int64_t(j + 1) * n, n);
-      HIPCHK(hipMemcpyAsync(h->hhost, h->hdev.p, (2 * (m + 2) + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+      double* h1 = K.hdev;
+      double* h2 = K.hdev + (m + 2);
+      double* hn = K.hdev + 2 * (m + 2);
+      stgmg::k_multi_dot(st, K.V, n, j + 1, K.w, n, K.partials, h1, 0);
+      stgmg::k_multi_axpy(st, K.V, n, j + 1, h1, -1.0, K.w, n);
+      stgmg::k_multi_dot(st, K.V, n, j + 1, K.w, n, K.partials, h2, 0);
+      stgmg::k_multi_axpy(st, K.V, n, j + 1, h2, -1.0, K.w, n);
+      stgmg::k_multi_dot(st, K.w, n, 1, K.w, n, K.partials, hn, 0);
+      stgmg::k_scale_copy(st, K.w, hn, K.V + int64_t(j + 1) * n, n);
+      HIPCHK(hipMemcpyAsync(h->hhost, K.hdev, (2 * (m + 2) + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipGetLastError());  // a failed launch of this iteration is reported here
       HIPCHK(hipStreamSynchronize(st));
       {
@@ -1098,10 +1147,12 @@ stgmg_status do_solve(stgmg_handle* h, const double* rhs, double* x, double rtol
       for (int c = i + 1; c < jd; ++c) s -= H[size_t(i) * m + c] * y[c];
       y[i] = s / H[size_t(i) * m + i];
     }
-    HIPCHK(hipMemcpyAsync(h->ydev.p, y.data(), jd * sizeof(double), hipMemcpyHostToDevice, st));
-    stgmg::k_multi_axpy(st, h->Z.p, n, jd, h->ydev.p, 1.0, x, n);
-    op_apply(h, Lf, 1, x, rhs, h->w.p);
-    beta = std::sqrt(device_norm2(h, h->w.p, n));
+    // through the pinned buffer (the Hessenberg reads use its first 2 (m + 2) + 1 <= 205 values)
+    std::copy(y.begin(), y.begin() + jd, h->hhost + 256);
+    HIPCHK(hipMemcpyAsync(K.ydev, h->hhost + 256, jd * sizeof(double), hipMemcpyHostToDevice, st));
+    stgmg::k_multi_axpy(st, K.Z, n, jd, K.ydev, 1.0, x, n);
+    op_apply(h, Lf, 1, x, rhs, K.w);
+    beta = std::sqrt(device_norm2(h, K, K.w, n));
     if (!std::isfinite(beta)) throw ApiError(STGMG_ERR_NONFINITE, "non-finite residual");
     if (beta > target) inf.restarts++;
   }
@@ -1153,6 +1204,18 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     std::unique_ptr<stgmg_handle> h(new stgmg_handle());
     h->prm = *params;  // K_cells is read during build() and cleared afterwards
     h->caller = reinterpret_cast<hipStream_t>(hip_stream);
+    HIPCHK(hipGetDevice(&h->dev));
+    if (h->dev < 0 || h->dev >= MAX_DEVICES) throw ApiError(STGMG_ERR_UNSUPPORTED, "device index out of range");
+    {
+      // once per device, with that device current: the device address of the static scratch
+      std::lock_guard<std::mutex> lk(g_scratch_mu);
+      if (!g_scratch[h->dev]) {
+        void* ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw ApiError(STGMG_ERR_HIP, "no device address for the static scratch");
+        g_scratch[h->dev] = static_cast<double*>(ptr);
+      }
+    }
     HIPCHK(hipStreamCreateWithFlags(&h->own.s, hipStreamNonBlocking));
     h->st = h->own.s;
     HIPCHK(hipEventCreateWithFlags(&h->enter_ev, hipEventDisableTiming));
@@ -1191,8 +1254,30 @@ stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, 
                          int32_t max_iters, stgmg_info* info) {
   return guarded([&] {
     if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_solve_args(rhs_dev, x_dev, rtol, restart, max_iters);
     enter(h);
-    return do_solve(h, rhs_dev, x_dev, rtol, restart, max_iters, info);
+    const Krylov K = ensure_krylov(h, restart);
+    return do_solve(h, K, rhs_dev, x_dev, rtol, restart, max_iters, info);
+  });
+}
+
+stgmg_status stgmg_solve_noalloc(stgmg_handle* h, const double* rhs_dev, double* x_dev, double rtol,
+                                 int32_t restart, int32_t max_iters, stgmg_info* info) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    check_solve_args(rhs_dev, x_dev, rtol, restart, max_iters);
+    const int64_t n = h->lv[h->L].n;
+    const int64_t need = krylov_doubles(n, restart) * int64_t(sizeof(double));
+    if (need > STGMG_NOALLOC_SCRATCH_BYTES)
+      throw ApiError(STGMG_ERR_UNSUPPORTED,
+                     "stgmg_solve_noalloc needs " + std::to_string(need) + " bytes of workspace for " +
+                         std::to_string(n) + " unknowns and restart " + std::to_string(restart) +
+                         "; the static scratch holds " + std::to_string(STGMG_NOALLOC_SCRATCH_BYTES));
+    double* base = g_scratch[h->dev];  // looked up by stgmg_setup on this handle's device
+    if (!base) throw ApiError(STGMG_ERR_HIP, "static scratch not set up on this device");
+    enter(h);
+    // nothing in the workspace needs to start at zero: every region is written before it is read
+    return do_solve(h, krylov_in(base, n, restart), rhs_dev, x_dev, rtol, restart, max_iters, info);
   });
 }
 
