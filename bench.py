@@ -2,9 +2,10 @@
 """Benchmark: GMRES-GMG slab solves on one MI355X.
 
 A step is one slab of the time marching on the 2D 256x256 workload (Q2/Q2/Q1,
-dG(2), 7 levels from 4x4, vertex patches, tau = 1e-3): the right-hand side of
-Problem 3.1 from the previous slab's end value, then FGMRES(30) preconditioned
-by one V-cycle per iteration, from x0 = 0 to a relative residual of 1e-8.
+dG(2), 7 levels from 4x4, vertex patches, tau = 1e-3), run inside the library
+(stgmg_march): the right-hand side of Problem 3.1 from the previous slab's end
+value on the device, then FGMRES(30) preconditioned by one V-cycle per
+iteration, from x0 = 0 to a relative residual of 1e-8.
 The hierarchy (level operators, patch inverses) is built once before timing
 and stays resident in HBM; its setup time is reported separately.
 
@@ -182,20 +183,21 @@ def cpu_baseline(cfg, sample_levels, n_full):
 
 
 def run_batch(args):
-    """Independent 2D problems (16^2..128^2, dG(1)/dG(2), random physics, FP32 smoother), set up in
-    waves that fit the HBM budget; each wave solved concurrently (stgmg_solve_batch) and, for
-    comparison, one after another."""
+    """Independent 2D problems (16^2..128^2, dG(1)/dG(2), random physics, FP32 smoother, FP64 FGMRES),
+    set up in waves that fit the HBM budget; each wave solved concurrently (stgmg_solve_batch) and,
+    for comparison, one after another; then, with --compare-fp64, the same problems with FP64 patch
+    solves one after another (the plain FP64 GPU solve), and the two solutions compared."""
     import numpy as np
     import torch
     from paper_2303_06742_amd import capi, workloads as W
     cfgs = W.batch_configs(args.batch_count, seed=args.seed)
     budget = int(args.hbm_budget_gb * 2 ** 30)
-    t_setup = t_batch = t_seq = 0.0
-    iters, res, max_dev = [], [], 0.0
+    t_setup = t_batch = t_seq = t_setup64 = t_seq64 = 0.0
+    iters, iters64, res, max_dev, err64 = [], [], [], 0.0, []
     i = 0
     waves = 0
     while i < len(cfgs):
-        wave, used = [], 0
+        wave, wcfg, used = [], [], 0
         while i < len(cfgs):
             _, res_b, peak_b = capi.footprint(cfgs[i])
             if wave and used + peak_b > budget:
@@ -203,6 +205,7 @@ def run_batch(args):
             t0 = time.perf_counter()
             wave.append(capi.Solver(cfgs[i]))
             t_setup += time.perf_counter() - t0
+            wcfg.append(cfgs[i])
             used += res_b
             i += 1
         waves += 1
@@ -225,17 +228,44 @@ def run_batch(args):
             res.append(inf['rel_res_true'])
         for s in wave:
             s.close()
-        print(f"[bench] wave {waves}: {len(wave)} problems", file=sys.stderr, flush=True)
+        del xq
+        if args.compare_fp64:
+            t0 = time.perf_counter()
+            wave64 = [capi.Solver(c, precision='fp64') for c in wcfg]
+            torch.cuda.synchronize()
+            t_setup64 += time.perf_counter() - t0
+            x64 = [s.empty() for s in wave64]
+            t0 = time.perf_counter()
+            for s, r, x in zip(wave64, rhs, x64):
+                iters64.append(s.solve(r, x, rtol=1e-8)['iters'])
+            torch.cuda.synchronize()
+            t_seq64 += time.perf_counter() - t0
+            for x, y in zip(xs, x64):
+                err64.append(float((x - y).abs().max() / y.abs().max()))
+            for s in wave64:
+                s.close()
+            del x64
+        del xs, rhs
+        torch.cuda.empty_cache()
+        print(f"[bench] wave {waves}: {len(wave)} problems ({i}/{len(cfgs)})", file=sys.stderr, flush=True)
     n = len(cfgs)
     out = {'metric': 'batched GMRES-GMG solves/s (independent problems, 1e-8 rel. residual)', 'value': n / t_batch,
            'unit': 'solves/s', 'n_gpus': 1, 'steps': n, 'warmup': 0, 'ms_per_step': 1000 * t_batch / n,
            'higher_is_better': True, 'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f64+f32-smoother',
            'data': 'synthetic',
-           'config': {'workload': f'batch of {n} 2D problems 16^2..128^2, dG(1)/dG(2), vertex patches',
+           'config': {'workload': f'batch of {n} 2D problems 16^2..128^2, dG(1)/dG(2), vertex patches, random '
+                                  'physics, FP32 patch solves inside FP64 FGMRES',
                       'seed': args.seed, 'waves': waves, 'hbm_budget_gb': args.hbm_budget_gb},
            'sequential_solves_per_s': n / t_seq, 'setup_plus_solve_per_s': n / (t_setup + t_batch),
            'setup_s': t_setup, 'gmres_iters_mean': float(np.mean(iters)), 'rel_res_true_max': float(max(res)),
            'batch_vs_alone_max_abs_diff': max_dev}
+    if args.compare_fp64:
+        out['fp64_alone'] = {'solves_per_s': n / t_seq64, 'setup_plus_solve_per_s': n / (t_setup64 + t_seq64),
+                             'setup_s': t_setup64, 'gmres_iters_mean': float(np.mean(iters64)),
+                             'mixed_batched_over_fp64_alone': (n / t_batch) / (n / t_seq64),
+                             'max_rel_err_mixed_vs_fp64': float(max(err64)),
+                             'note': 'the same problems and right-hand sides, FP64 patch solves, one after another, '
+                                     'same rtol 1e-8'}
     print(json.dumps(out), flush=True)
 
 
@@ -245,7 +275,8 @@ def run_serve(args):
     (saturated throughput), then with Poisson arrivals at fractions of that throughput."""
     import numpy as np
     from paper_2303_06742_amd import capi, workloads as W
-    mix = W.serve_mix(args.serve_count, seed=args.seed)
+    mix = W.serve_mix(args.serve_count, seed=args.seed, sizes2d=tuple(args.serve_sizes_2d),
+                      sizes3d=tuple(args.serve_sizes_3d))
     rhs = [W.random_vector(capi.footprint(cfg)[0], 2000 + j) for j, (_, cfg) in enumerate(mix)]
     budget = int(args.hbm_budget_gb * 2 ** 30)
 
@@ -276,8 +307,9 @@ def run_serve(args):
            'value': sat['solves_per_s'], 'unit': 'solves/s', 'n_gpus': 1, 'steps': len(mix), 'warmup': 0,
            'ms_per_step': 1000.0 / sat['solves_per_s'], 'higher_is_better': True, 'scaling': 'weak',
            'vs_baseline': None, 'dtype': 'f64+f32-smoother', 'data': 'synthetic',
-           'config': {'workload': f'{len(mix)} requests, 70% 2D 32^2..128^2 vertex / 30% 3D 8^3..16^3 cell, '
-                                  'half follow-on slabs', 'seed': args.seed, 'slots': args.slots,
+           'config': {'workload': f'{len(mix)} requests, 70% 2D {args.serve_sizes_2d}^2 vertex / 30% 3D '
+                                  f'{args.serve_sizes_3d}^3 cell patches, dG(1)/dG(2), half follow-on slabs',
+                      'seed': args.seed, 'slots': args.slots,
                       'hbm_budget_gb': args.hbm_budget_gb},
            'latency_ms_p50': sat['p50_ms'], 'latency_ms_p99': sat['p99_ms'], 'poisson': rows}
     print(json.dumps(out), flush=True)
@@ -291,7 +323,11 @@ def main():
     ap.add_argument('--config', default='c2', choices=['c2', 'c1', 'c3', 'c3v', 'c2d', 'batch', 'serve'])
     ap.add_argument('--batch-count', type=int, default=64)
     ap.add_argument('--serve-count', type=int, default=48)
-    ap.add_argument('--serve-rates', type=float, nargs='*', default=[0.5, 0.9])
+    ap.add_argument('--serve-rates', type=float, nargs='*', default=[0.25, 0.5, 0.75, 0.9, 1.0, 1.25])
+    ap.add_argument('--serve-sizes-2d', type=int, nargs='*', default=[32, 64, 128, 256])
+    ap.add_argument('--serve-sizes-3d', type=int, nargs='*', default=[8, 16, 32])
+    ap.add_argument('--compare-fp64', action='store_true',
+                    help='batch: also solve every problem with FP64 patch solves, one after another')
     ap.add_argument('--slots', type=int, default=8)
     ap.add_argument('--seed', type=int, default=0)
     ap.add_argument('--hbm-budget-gb', type=float, default=200.0)
@@ -300,6 +336,10 @@ def main():
                     help="third equation: 'v' Problem 3.1, 'dtu' Problem B.1")
     ap.add_argument('--graph', type=int, default=-1, choices=[-1, 0, 1],
                     help='V-cycle as a captured HIP graph: -1 automatic (below 2^21 unknowns), 0 never, 1 always')
+    ap.add_argument('--waves', type=int, default=0, choices=[0, 1, 4],
+                    help='waves per patch of the tiled patch kernel: 0 by patch count or autotuned, 1 or 4')
+    ap.add_argument('--autotune', type=int, default=1, choices=[0, 1],
+                    help='time the launch shapes of the patch and operator kernels at setup (default 1)')
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--cpu-sample-levels', type=int, default=None,
                     help='levels of the grid the oracle times (default: 32^2 cells in 2D, 8^3 in 3D)')
@@ -342,25 +382,24 @@ def main():
         del a, b
     print(f"[bench] setup {cfg.name} {args.precision}", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    S = capi.Solver(cfg, precision=args.precision, graph=args.graph)
+    S = capi.Solver(cfg, precision=args.precision, graph=args.graph, waves=args.waves, autotune=args.autotune)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     q = S.query(-1)
     k, ns, n = cfg.k, S.ns, S.n
     state = {'t': 0.0, 'Xend': S.interpolate_solution(0.0)}
-    rhs, x = S.empty(), S.empty()
-
-    kept = []  # mixed precision: (rhs, x) of every timed slab, compared with FP64 solves afterwards
+    x = S.empty()
+    kept = []  # mixed precision: (t, start values, x) of every timed slab, compared with FP64 afterwards
 
     def step(keep=False):
-        S.slab_rhs(state['t'], state['Xend'], rhs)
-        x.zero_()
-        info = S.solve(rhs, x, rtol=cfg.rtol, restart=cfg.restart)
-        state['Xend'] = x[k * ns:(k + 1) * ns].clone()
-        state['t'] += cfg.tau
+        # one slab inside the library (stgmg_march): right-hand side on the device from the end
+        # values of the previous slab (updated in place), x0 = 0, FGMRES-GMG to rtol
+        start = state['Xend'].clone() if keep else None
+        _, infos_ = S.march(state['t'], 1, state['Xend'], x, rtol=cfg.rtol, restart=cfg.restart)
         if keep:
-            kept.append((rhs.clone(), x.clone()))
-        return info
+            kept.append((state['t'], start, x.clone()))
+        state['t'] += cfg.tau
+        return infos_[0]
 
     print(f"[bench] setup {setup_s:.1f} s, n={n}; warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -402,7 +441,7 @@ def main():
         'config': {'workload': cfg.name, 'dim': cfg.dim, 'cells': f"{cfg.fine_cells}^{cfg.dim}",
                    'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'pressure': cfg.pressure, 'form': cfg.form, 'smoother': args.precision,
                    'tau': cfg.tau, 'unknowns': n, 'nnz': q['nnz'], 'patches': q['patches'], 'rtol': cfg.rtol,
-                   'restart': cfg.restart},
+                   'restart': cfg.restart, 'waves_per_patch': args.waves, 'autotune': args.autotune},
         'vcycle_dof_per_s': n * sum(iters) / elapsed,
         'latency_ms_p50': float(np.percentile(lat, 50)),
         'latency_ms_p99': float(np.percentile(lat, 99)),
@@ -425,7 +464,8 @@ def main():
                          'bytes_per_launch': dense_inverse_bytes(cfg, 8 if args.precision == 'fp64' else 4),
                          'GBs': dense_inverse_bytes(cfg, 8 if args.precision == 'fp64' else 4) /
                          (avg_pa_ms * 1e-3) / 1e9 if pa['launches'] else 0.0}},
-        'residual_spmv': {'avg_launch_ms': avg_rs_ms, 'launches': rs['launches'],
+        'residual_spmv': {'kernel': 'node_op_kernel (finest level)', 'avg_launch_ms': avg_rs_ms,
+                          'launches': rs['launches'], 'bytes_per_launch': rs['bytes_per_launch'],
                           'achieved_GBs': rs['bytes_per_launch'] / (avg_rs_ms * 1e-3) / 1e9 if rs['launches'] else 0},
     }
     S.close()
@@ -434,7 +474,8 @@ def main():
         # slab system (the FP64 path agrees with the oracle to 1e-10 in the parity tests)
         S64 = capi.Solver(cfg, precision='fp64', graph=args.graph)
         errs, iters64 = [], []
-        for r_, x_ in kept:
+        for t_, start_, x_ in kept:
+            r_ = S64.slab_rhs(t_, start_)
             x64 = S64.empty()
             i64 = S64.solve(r_, x64, rtol=cfg.rtol, restart=cfg.restart)
             iters64.append(i64['iters'])

@@ -116,10 +116,17 @@ typedef struct {
                             Default of the Python workloads: 3. */
   int32_t pressure;      /* STGMG_PRESSURE_CONT (0, the zero-initialised default) or STGMG_PRESSURE_DISC */
   int32_t form;          /* STGMG_FORM_V (0, default) or STGMG_FORM_DTU */
-  int32_t waves_per_patch; /* time_blocks = 3 only: wavefronts that apply one patch's tiles: 0 automatic
-                              (4 on levels of fewer than 4,096 patches -- 8,192 for Schur blocks of
-                              more than 96 rows -- and 1 on larger levels), or 1 or 4 on every level.
-                              The same operator either way, up to the order of the sums. */
+  int32_t waves_per_patch; /* time_blocks = 3 only: wavefronts that apply one patch's tiles: 0 by the
+                              patch count (4 on levels of fewer than 4,096 patches -- 8,192 for Schur
+                              blocks of more than 96 rows -- and 1 on larger levels; see autotune), or
+                              1 or 4 on every level.  The same operator either way, up to the order of
+                              the sums. */
+  int32_t autotune;      /* 1: stgmg_setup times the candidate launch shapes on every level and keeps
+                            the fastest -- the waves per patch of the tiled patch solve (1 or 4, when
+                            waves_per_patch is 0) and the lanes per node of the level operator
+                            (2, 4, 8 or 16) -- adding a few milliseconds per level.  The results then
+                            depend on the timing in their last bits (the order of sums), so two
+                            handles of one problem may differ by rounding.  0: fixed rules. */
 } stgmg_params;
 
 typedef struct {
@@ -197,6 +204,19 @@ stgmg_status stgmg_restrict(stgmg_handle* h, int32_t level, const double* r_fine
  * x_prev_end_dev: the previous slab's values at t_{n-1} (n_s doubles, one time
  * node block).  rhs_dev: n doubles. */
 stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_prev_end_dev, double* rhs_dev);
+
+/* Time marching of Problem 3.1 (or B.1) with the built-in prescribed solution over n_slabs
+ * slabs (t_start + s tau, t_start + (s+1) tau], s = 0 .. n_slabs-1, inside the library: for
+ * every slab the right-hand side of stgmg_slab_rhs from the previous slab's end values (on the
+ * device; a captured HIP graph for hierarchies that capture the V-cycle), x0 = 0, stgmg_solve
+ * with rtol / restart / max_iters, and the last time-node block of the solution (the values at
+ * t_n, the right Radau node) as the next slab's start values (Problem 3.1, the jump term of
+ * Def:LG).  x_end_dev (n_s doubles): in = the values at t_start, out = those at
+ * t_start + n_slabs tau.  x_dev (n doubles): workspace; out = the last slab's solution.
+ * infos (n_slabs entries, may be NULL): per slab.  Returns STGMG_OK if every slab converged,
+ * else the first non-OK status of a slab (marching continues after NOT_CONVERGED). */
+stgmg_status stgmg_march(stgmg_handle* h, double t_start, int32_t n_slabs, double* x_end_dev, double* x_dev,
+                         double rtol, int32_t restart, int32_t max_iters, stgmg_info* infos);
 
 /* Nodal interpolant (V, U, P) of the built-in prescribed solution at time t,
  * n_s doubles (one time-node block), on the finest level. */

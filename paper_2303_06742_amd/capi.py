@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ('mu', ctypes.c_double), ('alpha', ctypes.c_double), ('c0', ctypes.c_double),
                 ('K', ctypes.c_double), ('K_cells', ctypes.c_void_p), ('graph', ctypes.c_int32),
                 ('time_blocks', ctypes.c_int32), ('pressure', ctypes.c_int32), ('form', ctypes.c_int32),
-                ('waves_per_patch', ctypes.c_int32)]
+                ('waves_per_patch', ctypes.c_int32), ('autotune', ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -80,6 +80,7 @@ stgmg_smooth = _decl('stgmg_smooth', [_H, _I32, _P, _P, _I32])
 stgmg_prolongate_add = _decl('stgmg_prolongate_add', [_H, _I32, _P, _P])
 stgmg_restrict = _decl('stgmg_restrict', [_H, _I32, _P, _P])
 stgmg_slab_rhs = _decl('stgmg_slab_rhs', [_H, _D, _P, _P])
+stgmg_march = _decl('stgmg_march', [_H, _D, _I32, _P, _P, _D, _I32, _I32, ctypes.POINTER(Info)])
 stgmg_interpolate_solution = _decl('stgmg_interpolate_solution', [_H, _D, _P])
 stgmg_get_patch_inverse = _decl('stgmg_get_patch_inverse', [_H, _I32, _I64, ctypes.POINTER(_I32), _P, _P])
 stgmg_profile_enable = _decl('stgmg_profile_enable', [_H, _I32])
@@ -100,7 +101,7 @@ stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
 stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
 
 EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_solve_noalloc', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
-            'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs',
+            'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs', 'stgmg_march',
             'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_profile_enable', 'stgmg_profile_get',
             'stgmg_destroy', 'stgmg_status_string', 'stgmg_last_error', 'stgmg_footprint', 'stgmg_solve_batch',
             'stgmg_server_create', 'stgmg_server_submit', 'stgmg_server_poll', 'stgmg_server_message',
@@ -130,9 +131,9 @@ def _dptr(t, n=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def make_params(cfg, precision=None, graph=-1, time_blocks=None, waves=0):
+def make_params(cfg, precision=None, graph=-1, time_blocks=None, waves=0, autotune=0):
     """(Params, K array kept alive by the caller) for a workloads.Config.  waves: waves per patch of
-    the tiled patch solve (0 automatic, 1 or 4)."""
+    the tiled patch solve (0 by patch count, 1 or 4); autotune: 1 to time the launch shapes at setup."""
     K = cfg.K_cells()
     if K is not None:
         K = np.ascontiguousarray(K, dtype=np.float64)
@@ -141,7 +142,7 @@ def make_params(cfg, precision=None, graph=-1, time_blocks=None, waves=0):
                omega=cfg.omega, tau=cfg.tau, rho=cfg.rho, lam=cfg.lam, mu=cfg.mu, alpha=cfg.alpha, c0=cfg.c0,
                K=cfg.K, K_cells=None if K is None else K.ctypes.data, graph=graph,
                time_blocks=cfg.time_blocks if time_blocks is None else time_blocks,
-               pressure=PRESSURE[cfg.pressure], form=FORM[cfg.form], waves_per_patch=waves)
+               pressure=PRESSURE[cfg.pressure], form=FORM[cfg.form], waves_per_patch=waves, autotune=autotune)
     return p, K
 
 
@@ -223,11 +224,11 @@ class Server:
 class Solver:
     """One problem hierarchy (stgmg_setup) and the calls on it."""
 
-    def __init__(self, cfg, precision=None, stream=None, graph=-1, time_blocks=None, waves=0):
+    def __init__(self, cfg, precision=None, stream=None, graph=-1, time_blocks=None, waves=0, autotune=0):
         import torch
         self._torch = torch
         self.cfg = cfg
-        p, self._K = make_params(cfg, precision, graph, time_blocks, waves)
+        p, self._K = make_params(cfg, precision, graph, time_blocks, waves, autotune)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = _H()
         check(stgmg_setup(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)), 'stgmg_setup')
@@ -281,6 +282,16 @@ class Solver:
         rhs = self.empty() if rhs is None else rhs
         check(stgmg_slab_rhs(self.h, t_start, _dptr(x_prev_end, self.ns), _dptr(rhs, self.n)), 'stgmg_slab_rhs')
         return rhs
+
+    def march(self, t_start, n_slabs, x_end, x=None, rtol=1e-8, restart=30, max_iters=1000):
+        """stgmg_march: n_slabs slabs of time marching inside the library; x_end (n_s values) is
+        updated in place to the end values; returns (x of the last slab, per-slab info dicts)."""
+        x = self.empty() if x is None else x
+        infos = (Info * max(n_slabs, 1))()
+        st = stgmg_march(self.h, t_start, n_slabs, _dptr(x_end, self.ns), _dptr(x, self.n), rtol, restart, max_iters,
+                         infos)
+        check(st, 'stgmg_march', allow=(STGMG_OK, STGMG_NOT_CONVERGED))
+        return x, [infos[i].as_dict() for i in range(n_slabs)]
 
     def interpolate_solution(self, t):
         out = self.empty(self.ns)

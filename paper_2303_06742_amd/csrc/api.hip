@@ -132,10 +132,19 @@ struct LevelDev {
   DArr<int32_t> pnu;  // reduced solves: velocity dofs nU per patch (one time node)
   int max_nu = 0, max_nr = 0, max_npr = 0;
   bool sym = false;  // reduced solves with the Schur inverses as symmetric tiles
+  int waves = 0;     // waves per patch of the tiled patch kernel on this level (0: by patch count)
   DArr<double> inv64, winv, y;
   DArr<float> inv32;
   DevCsr P, R;  // prolongation from level-1 and its transpose
   DevCsr MMs, KKs;  // spatial MM and KK: the level operator A = D^t (x) MM + M^t (x) KK
+  // the velocity rows of the same operator by node pairs (rhoM_ij, A_ij, C^T), used by the
+  // residual and operator kernel when the level has that structure (node_ok)
+  bool node_ok = false;
+  stgmg::NodeOpDev node{};
+  DArr<int64_t> nptr, ncptr;
+  DArr<int32_t> ncol, nccol;
+  DArr<double> nm, na, nc;
+  double alg_op_values = 0;  // values the operator kernel reads (node form: each stored once)
   int op_lanes = 16;
   double alg_inv_entries = 0;  // stored inverse values excluding padding
   DArr<double> b, d, r;
@@ -184,6 +193,11 @@ struct stgmg_handle {
   bool tb = false;   // patch solves through the time eigen-decomposition
   bool red = false;  // ... with the u-equation rows eliminated
   DArr<double> e_dev, tmp_ns, src_buf;
+  // time marching (stgmg_march): the slab start values at t_{n-1}, the slab's Radau times on the
+  // device, and the right-hand side assembly captured as a graph (hierarchies with a V-cycle graph)
+  DArr<double> xend, tdev;
+  hipGraph_t rhs_graph = nullptr;
+  hipGraphExec_t rhs_exec = nullptr;
   DevCsr cface;  // Problem B.1: boundary part of C on the finest level (right-hand side's jump)
   DArr<double> src_xq, src_wq, src_bq, src_bp, kfine;  // device source tables
   // kernel timing (finest level): event pairs per kernel class
@@ -198,6 +212,8 @@ struct stgmg_handle {
   ~stgmg_handle() {
     if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (rhs_exec) (void)hipGraphExecDestroy(rhs_exec);
+    if (rhs_graph) (void)hipGraphDestroy(rhs_graph);
     if (enter_ev) (void)hipEventDestroy(enter_ev);
     for (auto e : vc_ev)
       if (e) (void)hipEventDestroy(e);
@@ -226,11 +242,19 @@ void enter(stgmg_handle* h) {
 // while a stream captures, this runtime rejects null-stream work issued by other threads
 // (and that work invalidates the capture), so the capture happens in the thread that sets the
 // handle up, before the handle can be used from several threads.
+void enqueue_slab_rhs(stgmg_handle* h, double t_start, const double* tdev, const double* x_prev_end_dev,
+                      double* rhs_dev);
+
 void capture_graph(stgmg_handle* h) {
   HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
   vcycle(h, h->L, h->gin.p, h->gout.p);
   HIPCHK(hipStreamEndCapture(h->st, &h->graph));
   HIPCHK(hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0));
+  // the slab right-hand side of time marching: xend -> src_buf, times read from tdev
+  HIPCHK(hipStreamBeginCapture(h->st, hipStreamCaptureModeThreadLocal));
+  enqueue_slab_rhs(h, 0.0, h->tdev.p, h->xend.p, h->src_buf.p);
+  HIPCHK(hipStreamEndCapture(h->st, &h->rhs_graph));
+  HIPCHK(hipGraphInstantiate(&h->rhs_exec, h->rhs_graph, nullptr, nullptr, 0));
 }
 
 // z = B r on the finest level: graph replay (through gin/gout) or direct launches.
@@ -270,6 +294,7 @@ void check_params(const stgmg_params* p) {
   if (p->form != STGMG_FORM_V && p->form != STGMG_FORM_DTU) throw ApiError(STGMG_ERR_INVALID_ARG, "unknown formulation");
   if (p->waves_per_patch != 0 && p->waves_per_patch != 1 && p->waves_per_patch != 4)
     throw ApiError(STGMG_ERR_INVALID_ARG, "waves_per_patch must be 0, 1 or 4");
+  if (p->autotune != 0 && p->autotune != 1) throw ApiError(STGMG_ERR_INVALID_ARG, "autotune must be 0 or 1");
 }
 
 // A vector argument must be device (or managed) memory known to the runtime, 8-byte aligned.
@@ -361,8 +386,92 @@ struct ProfScope {
 // Level operator: mode 0 y = A_l x, mode 1 y = b - A_l x (factored form).
 void op_apply(stgmg_handle* h, int l, int mode, const double* x, const double* b, double* y) {
   const LevelDev& L = h->lv[l];
+  if (L.node_ok) {
+    stgmg::k_node_op(h->st, mode, h->top, L.node, L.ns, L.MMs.ptr.p, L.MMs.col.p, L.MMs.val.p, L.KKs.ptr.p,
+                     L.KKs.col.p, L.KKs.val.p, x, b, y);
+    return;
+  }
   stgmg::k_kron_spmv(h->st, mode, h->top, L.ns, L.MMs.ptr.p, L.MMs.col.p, L.MMs.val.p, L.KKs.ptr.p, L.KKs.col.p,
                      L.KKs.val.p, x, b, y, L.op_lanes);
+}
+
+// The patch solves y_P = A_P^{-1} R_P r of one level, in the level's storage mode.
+void launch_patch_apply(stgmg_handle* h, LevelDev& L, const double* r) {
+  const bool f32 = h->prm.smoother_prec == STGMG_FP32;
+  if (h->red && f32)
+    stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, L.waves,
+                                 h->tbc, h->prm.dim,
+                                 L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
+  else if (h->red)
+    stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, L.waves,
+                                 h->tbc, h->prm.dim,
+                                 L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
+  else if (h->tb && f32)
+    stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r,
+                                L.y.p);
+  else if (h->tb)
+    stgmg::k_patch_apply_tb_f64(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv64.p, r,
+                                L.y.p);
+  else if (f32)
+    stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r, L.y.p);
+  else
+    stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv64.p, r, L.y.p);
+}
+
+// Autotuning (stgmg_params.autotune): on every smoothed level the candidate launch shapes are timed
+// with HIP events (one warm-up and three timed launches each, on zero vectors) and the fastest is
+// kept: the waves per patch of the tiled patch kernel (1 or 4, unless waves_per_patch fixes it)
+// and, on every level, the lanes per node of the operator kernel (2, 4, 8 or 16).
+void autotune(stgmg_handle* h) {
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto time3 = [&](auto&& launch) {
+    float ms = 0.f;
+    for (int rep = 0; rep < 4; ++rep) {
+      if (rep == 1) HIPCHK(hipEventRecord(e0, h->st));
+      launch();
+    }
+    HIPCHK(hipEventRecord(e1, h->st));
+    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return ms;
+  };
+  for (int l = 0; l <= h->L; ++l) {
+    LevelDev& L = h->lv[l];
+    stgmg::k_fill_zero(h->st, L.r.p, L.n);
+    stgmg::k_fill_zero(h->st, L.d.p, L.n);
+    stgmg::k_fill_zero(h->st, L.b.p, L.n);
+    if (L.sym && L.npatch > 0 && h->prm.waves_per_patch == 0) {
+      float best = 0.f;
+      int best_w = 1;
+      for (int w : {1, 4}) {
+        L.waves = w;
+        const float ms = time3([&] { launch_patch_apply(h, L, L.r.p); });
+        if (w == 1 || ms < best) {
+          best = ms;
+          best_w = w;
+        }
+      }
+      L.waves = best_w;
+    }
+    if (L.node_ok) {
+      float best = 0.f;
+      int best_g = 0;
+      for (int g : {2, 4, 8, 16}) {
+        L.node.lanes = g;
+        const float ms = time3([&] { op_apply(h, l, 1, L.d.p, L.b.p, L.r.p); });
+        if (best_g == 0 || ms < best) {
+          best = ms;
+          best_g = g;
+        }
+      }
+      L.node.lanes = best_g;
+    }
+  }
+  HIPCHK(hipGetLastError());
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool zero_start) {
@@ -376,25 +485,7 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
     }
     {
       ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
-      const bool f32 = h->prm.smoother_prec == STGMG_FP32;
-      if (h->red && f32)
-        stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->prm.waves_per_patch,
-                                     h->tbc, h->prm.dim,
-                                     L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
-      else if (h->red)
-        stgmg::k_patch_apply_red_f64(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, h->prm.waves_per_patch,
-                                     h->tbc, h->prm.dim,
-                                     L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv64.p, r, L.y.p);
-      else if (h->tb && f32)
-        stgmg::k_patch_apply_tb_f32(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r,
-                                    L.y.p);
-      else if (h->tb)
-        stgmg::k_patch_apply_tb_f64(h->st, L.npatch, L.max_np, h->tbc, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv64.p, r,
-                                    L.y.p);
-      else if (f32)
-        stgmg::k_patch_apply_f32(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv32.p, r, L.y.p);
-      else
-        stgmg::k_patch_apply_f64(h->st, L.npatch, L.max_np, L.poff.p, L.pdof.p, L.tpos.p, L.ioff.p, L.inv64.p, r, L.y.p);
+      launch_patch_apply(h, L, r);
     }
     stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.winv.p, L.y.p, d);
   }
@@ -522,6 +613,26 @@ void build(stgmg_handle* h) {
     if (l >= 1 && !h->tb) D.A.upload(H.A, h->st, ctr);  // full-inverse patch extraction reads it
     D.MMs.upload(H.MM, h->st, ctr);
     D.KKs.upload(H.KK, h->st, ctr);
+    D.alg_op_values = double(H.MM.col.size() + H.KK.col.size());
+    {
+      stgmg::NodeOp no;
+      if (stgmg::build_node_op(H, no, nth)) {
+        D.nptr.upload(no.ptr, h->st, ctr);
+        D.ncol.upload(no.col, h->st, ctr);
+        D.nm.upload(no.m, h->st, ctr);
+        D.na.upload(no.a, h->st, ctr);
+        D.ncptr.upload(no.cptr, h->st, ctr);
+        D.nccol.upload(no.ccol, h->st, ctr);
+        D.nc.upload(no.c, h->st, ctr);
+        D.node = {d, no.nQ, 0, D.nptr.p, D.ncol.p, D.nm.p, D.na.p, D.ncptr.p, D.nccol.p, D.nc.p};
+        D.node_ok = true;
+        // pressure rows from the CSRs, velocity rows from the node pairs
+        const int64_t pr0 = 2 * H.nv;
+        D.alg_op_values = double(no.m.size() + no.a.size() + no.c.size()) +
+                          double(H.MM.ptr[H.ns] - H.MM.ptr[pr0] + H.KK.ptr[H.ns] - H.KK.ptr[pr0]);
+        HIPCHK(hipStreamSynchronize(h->st));  // the host arrays of `no` are freed at the end of this block
+      }
+    }
     if (l == L && p.form == STGMG_FORM_DTU) h->cface.upload(H.Cface, h->st, ctr);
     {
       const double avg = H.ns ? double(H.MM.col.size() + H.KK.col.size()) / double(H.ns) : 0.0;
@@ -998,6 +1109,8 @@ void build(stgmg_handle* h) {
   }
   h->tmp_ns.alloc(h->fine_info.ns, ctr, h->st);
   h->src_buf.alloc(h->fine_info.n, ctr, h->st);
+  h->xend.alloc(h->fine_info.ns, ctr, h->st);
+  h->tdev.alloc(p.k + 1, ctr, h->st);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 512 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(h->st));
 }
@@ -1170,6 +1283,49 @@ stgmg_status do_solve(stgmg_handle* h, const Krylov& K, const double* rhs, doubl
   return status;
 }
 
+// Enqueue the slab right-hand side (Problem 3.1 / B.1, Def:LG) for the slab starting at t_start
+// from the previous slab's end values: the source of every Radau time (from tdev[b] on the device
+// when tdev is not NULL, so that a captured graph can be replayed for every slab), the jump term
+// e_b MM x_prev, and their sum into rhs (rhs may be the source buffer itself).
+void enqueue_slab_rhs(stgmg_handle* h, double t_start, const double* tdev, const double* x_prev_end_dev,
+                      double* rhs_dev) {
+  const auto& F = h->fine_info;
+  const int nt = h->T.k + 1;
+  for (int b = 0; b < nt; ++b) {
+    stgmg::SourceArgs a{};
+    a.d = F.d;
+    a.r = F.r;
+    a.N = F.N;
+    a.nq = 1;
+    for (int x = 0; x < F.d; ++x) a.nq *= F.r + 2;
+    a.n1 = F.n1;
+    a.n1p = F.n1p;
+    a.disc = F.disc ? 1 : 0;
+    a.nlp = F.nlp;
+    a.nv = F.nv;
+    a.ns = F.ns;
+    a.h = 1.0 / F.N;
+    a.rho = h->mat.rho;
+    a.lam = h->mat.lambda;
+    a.mu = h->mat.mu;
+    a.alpha = h->mat.alpha;
+    a.c0 = h->mat.c0;
+    a.t = t_start + 0.5 * h->prm.tau * (1.0 + h->T.x[b]);
+    a.tdev = tdev;
+    a.tidx = b;
+    a.scale = h->T.mt[b];
+    stgmg::k_source(h->st, a, h->src_xq.p, h->src_wq.p, h->src_bq.p, h->src_bp.p, h->kfine.p,
+                    h->src_buf.p + int64_t(b) * F.ns);
+  }
+  h->lv[h->L].MMs.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
+  // Problem B.1: the jump carries alpha div u^{n-1} (the volume part of C) and the boundary
+  // value u_D(t_{n-1}) in place of u^{n-1} . n; MM holds all of C, so add the boundary part
+  // back (u_D is zero on the boundary for the built-in solution)
+  if (h->prm.form == STGMG_FORM_DTU)
+    h->cface.apply(h->st, 2, x_prev_end_dev + F.nv, nullptr, h->tmp_ns.p + 2 * F.nv);
+  stgmg::k_slab_rhs(h->st, nt, F.ns, h->e_dev.p, h->tmp_ns.p, h->src_buf.p, rhs_dev);
+}
+
 template <class F>
 stgmg_status guarded(F&& f) {
   try {
@@ -1224,6 +1380,8 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     enter(h.get());
     build(h.get());
     h->prm.K_cells = nullptr;  // copied into the level data, never kept
+    for (auto& L : h->lv) L.waves = params->waves_per_patch;
+    if (params->autotune) autotune(h.get());
     const int64_t nf = h->lv[h->L].n;
     h->use_graph = params->graph == 1 || (params->graph == -1 && nf < (int64_t(1) << 21));
     if (h->use_graph) {
@@ -1360,42 +1518,50 @@ stgmg_status stgmg_slab_rhs(stgmg_handle* h, double t_start, const double* x_pre
     check_dev(x_prev_end_dev, "x_prev_end");
     check_dev(rhs_dev, "rhs");
     enter(h);
-    const auto& F = h->fine_info;
-    const int nt = h->T.k + 1;
-    for (int b = 0; b < nt; ++b) {
-      stgmg::SourceArgs a{};
-      a.d = F.d;
-      a.r = F.r;
-      a.N = F.N;
-      a.nq = 1;
-      for (int x = 0; x < F.d; ++x) a.nq *= F.r + 2;
-      a.n1 = F.n1;
-      a.n1p = F.n1p;
-      a.disc = F.disc ? 1 : 0;
-      a.nlp = F.nlp;
-      a.nv = F.nv;
-      a.ns = F.ns;
-      a.h = 1.0 / F.N;
-      a.rho = h->mat.rho;
-      a.lam = h->mat.lambda;
-      a.mu = h->mat.mu;
-      a.alpha = h->mat.alpha;
-      a.c0 = h->mat.c0;
-      a.t = t_start + 0.5 * h->prm.tau * (1.0 + h->T.x[b]);
-      a.scale = h->T.mt[b];
-      stgmg::k_source(h->st, a, h->src_xq.p, h->src_wq.p, h->src_bq.p, h->src_bp.p, h->kfine.p,
-                      h->src_buf.p + int64_t(b) * F.ns);
-    }
-    h->lv[h->L].MMs.apply(h->st, 0, x_prev_end_dev, nullptr, h->tmp_ns.p);
-    // Problem B.1: the jump carries alpha div u^{n-1} (the volume part of C) and the boundary
-    // value u_D(t_{n-1}) in place of u^{n-1} . n; MM holds all of C, so add the boundary part
-    // back (u_D is zero on the boundary for the built-in solution)
-    if (h->prm.form == STGMG_FORM_DTU)
-      h->cface.apply(h->st, 2, x_prev_end_dev + F.nv, nullptr, h->tmp_ns.p + 2 * F.nv);
-    stgmg::k_slab_rhs(h->st, nt, F.ns, h->e_dev.p, h->tmp_ns.p, h->src_buf.p, rhs_dev);
+    enqueue_slab_rhs(h, t_start, nullptr, x_prev_end_dev, rhs_dev);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(h->st));
     return STGMG_OK;
+  });
+}
+
+stgmg_status stgmg_march(stgmg_handle* h, double t_start, int32_t n_slabs, double* x_end_dev, double* x_dev,
+                         double rtol, int32_t restart, int32_t max_iters, stgmg_info* infos) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    if (n_slabs < 0) throw ApiError(STGMG_ERR_INVALID_ARG, "n_slabs < 0");
+    check_dev(x_end_dev, "x_end");
+    check_solve_args(h->src_buf.p, x_dev, rtol, restart, max_iters);
+    enter(h);
+    const Krylov K = ensure_krylov(h, restart);
+    const auto& F = h->fine_info;
+    const int nt = h->T.k + 1;
+    double* pinned_t = h->hhost + 448;  // the Radau times of one slab (the solve uses [0, 356))
+    HIPCHK(hipMemcpyAsync(h->xend.p, x_end_dev, F.ns * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    stgmg_status worst = STGMG_OK;
+    for (int32_t sl = 0; sl < n_slabs; ++sl) {
+      const double ts = t_start + double(sl) * h->prm.tau;
+      if (h->rhs_exec && !h->prof) {
+        // the solve of the previous slab synchronised the stream: the pinned times are free
+        for (int b = 0; b < nt; ++b) pinned_t[b] = ts + 0.5 * h->prm.tau * (1.0 + h->T.x[b]);
+        HIPCHK(hipMemcpyAsync(h->tdev.p, pinned_t, nt * sizeof(double), hipMemcpyHostToDevice, h->st));
+        HIPCHK(hipGraphLaunch(h->rhs_exec, h->st));
+      } else {
+        enqueue_slab_rhs(h, ts, nullptr, h->xend.p, h->src_buf.p);
+      }
+      stgmg::k_fill_zero(h->st, x_dev, F.n);
+      stgmg_info inf{};
+      const stgmg_status st = do_solve(h, K, h->src_buf.p, x_dev, rtol, restart, max_iters, &inf);
+      if (infos) infos[sl] = inf;
+      if (st != STGMG_OK && worst == STGMG_OK) worst = st;
+      // the end values at t_n: the last time-node block (right Radau node t_{n,k+1} = t_n)
+      HIPCHK(hipMemcpyAsync(h->xend.p, x_dev + int64_t(h->T.k) * F.ns, F.ns * sizeof(double),
+                            hipMemcpyDeviceToDevice, h->st));
+    }
+    HIPCHK(hipMemcpyAsync(x_end_dev, h->xend.p, F.ns * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->st));
+    return worst;
   });
 }
 
@@ -1553,6 +1719,11 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       const int64_t n = S.n;
       // factored operator: spatial MM and KK; vectors b, d, r
       res += 2 * (S.ns + 1) * 8 + (S.nnzMM + S.nnzKK) * 12 + 3 * n * 8;
+      {  // the velocity rows by node pairs (ptr, col, rhoM, A; cptr, ccol, C^T)
+        int64_t nQ = 1;
+        for (int a = 0; a < d; ++a) nQ *= int64_t(p.r) * (int64_t(p.coarse_cells) << l) + 1;
+        res += 2 * (nQ + 1) * 8 + S.nodeQQ * (4 + 8 + 8 * d * d) + S.nodeQP * (4 + 8 * d);
+      }
       if (l == L && p.form == STGMG_FORM_DTU) res += (S.nP + 1) * 8 + S.nnzCface * 12;  // boundary part of C
       if (l == 0) {
         res += n * stgmg::inv_ld(int(n)) * 8 + int64_t(stgmg::dense_gemv_chunks(int(n))) * n * 8;
@@ -1598,6 +1769,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       }
       if (l == L) {
         res += (p.k + 1) * 8 + S.ns * 8 + n * 8;  // e, MM x_prev, source
+        res += S.ns * 8 + (p.k + 1) * 8;             // time marching: slab start values, Radau times
         int64_t nq = 1, nls = 1, nlp = 1, ncell = 1;
         for (int a = 0; a < d; ++a) {
           nq *= p.r + 2;
@@ -1653,7 +1825,7 @@ stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches,
       const double sum_np = F.npatch ? double(F.poff_h[F.npatch]) : 0.0;
       bytes = w * F.alg_inv_entries + 16.0 * sum_np;
     } else {
-      bytes = 8.0 * double(F.MMs.nnz + F.KKs.nnz) + 24.0 * double(F.n);
+      bytes = 8.0 * F.alg_op_values + 24.0 * double(F.n);
     }
     if (launches) *launches = int64_t(h->ev_used[what]);
     if (total_ms) *total_ms = ms;

@@ -9,6 +9,7 @@
 namespace {
 stgmg::LevelHost g_level;
 stgmg::Csr g_P;
+stgmg::NodeOp g_node;
 std::vector<double> g_vec;
 bool g_disc = false;  // pressure pair of the following builds
 bool g_dtu = false;   // Problem B.1 instead of Problem 3.1 in the following builds
@@ -151,6 +152,25 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[13] = S.nnzCface;
   out[14] = S.sum_tiles;
   out[15] = S.sum_tiles2;
+  out[16] = S.nodeQQ;
+  out[17] = S.nodeQP;
+}
+
+// Node-pair form of the velocity rows of the last built level (NodeOp): returns the number of
+// node pairs, or -1 if the matrices do not have the structure; then the arrays.
+long long stgmg_host_node_build(void) {
+  if (!stgmg::build_node_op(g_level, g_node, 4)) return -1;
+  return (long long)g_node.col.size();
+}
+long long stgmg_host_node_cnnz(void) { return (long long)g_node.ccol.size(); }
+void stgmg_host_node_arrays(long long* ptr, int* col, double* m, double* a, long long* cptr, int* ccol, double* c) {
+  for (size_t i = 0; i < g_node.ptr.size(); ++i) ptr[i] = g_node.ptr[i];
+  for (size_t i = 0; i < g_node.cptr.size(); ++i) cptr[i] = g_node.cptr[i];
+  std::memcpy(col, g_node.col.data(), g_node.col.size() * sizeof(int));
+  std::memcpy(m, g_node.m.data(), g_node.m.size() * sizeof(double));
+  std::memcpy(a, g_node.a.data(), g_node.a.size() * sizeof(double));
+  std::memcpy(ccol, g_node.ccol.data(), g_node.ccol.size() * sizeof(int));
+  std::memcpy(c, g_node.c.data(), g_node.c.size() * sizeof(double));
 }
 
 // position of X[row][col], row >= col, in one plane of the symmetric tiled storage with P tiles

@@ -1181,6 +1181,136 @@ void build_level(const BuildOptions& o, const Material& m, const std::vector<dou
   }
 }
 
+// ------------------------------------------------------------- node-pair form of the velocity rows
+bool build_node_op(const LevelHost& L, NodeOp& out, int nthreads) {
+  const int d = L.d;
+  const int64_t nQ = L.nQ, nv = L.nv, np = L.nP;
+  const Csr &MM = L.MM, &KK = L.KK;
+  out = NodeOp();
+  if (MM.nrows != L.ns || KK.nrows != L.ns || nv != int64_t(d) * nQ) return false;
+  using NodeList = std::vector<std::pair<int32_t, double>>;
+  // the sorted node list (j, rhoM_ij) from MM's u-row of component 0 and the union of the
+  // pressure columns of KK's v-rows of node i
+  auto node_list = [&](int64_t i, NodeList& nodes, std::vector<int32_t>& pcols) -> bool {
+    nodes.clear();
+    pcols.clear();
+    const int64_t r0 = int64_t(d) * i;
+    for (int64_t p = MM.ptr[r0]; p < MM.ptr[r0 + 1]; ++p) {
+      const int64_t c = MM.col[p];
+      if (c >= nv && c < 2 * nv && (c - nv) % d == 0)
+        nodes.emplace_back(int32_t((c - nv) / d), MM.val[p]);
+      else if (MM.val[p] != 0.0)
+        return false;
+    }
+    std::sort(nodes.begin(), nodes.end());
+    for (int c = 0; c < d; ++c) {
+      const int64_t rv = nv + int64_t(d) * i + c;
+      for (int64_t p = KK.ptr[rv]; p < KK.ptr[rv + 1]; ++p)
+        if (KK.col[p] >= 2 * nv) pcols.push_back(int32_t(KK.col[p] - 2 * nv));
+    }
+    std::sort(pcols.begin(), pcols.end());
+    pcols.erase(std::unique(pcols.begin(), pcols.end()), pcols.end());
+    return true;
+  };
+  auto find = [](const NodeList& v, int32_t j) -> int64_t {
+    auto it = std::lower_bound(v.begin(), v.end(), j,
+                               [](const std::pair<int32_t, double>& e, int32_t k) { return e.first < k; });
+    return (it != v.end() && it->first == j) ? int64_t(it - v.begin()) : -1;
+  };
+  std::vector<int64_t> cnt(nQ + 1, 0), ccnt(nQ + 1, 0);
+  std::vector<char> bad(nQ, 0);
+  parallel_for(nQ, nthreads, [&](int64_t i0, int64_t i1) {
+    NodeList nodes;
+    std::vector<int32_t> pcols;
+    for (int64_t i = i0; i < i1; ++i) {
+      if (!node_list(i, nodes, pcols)) {
+        bad[i] = 1;
+        continue;
+      }
+      cnt[i + 1] = int64_t(nodes.size());
+      ccnt[i + 1] = int64_t(pcols.size());
+    }
+  });
+  for (int64_t i = 0; i < nQ; ++i)
+    if (bad[i]) return false;
+  for (int64_t i = 0; i < nQ; ++i) {
+    cnt[i + 1] += cnt[i];
+    ccnt[i + 1] += ccnt[i];
+  }
+  NodeOp o;
+  o.d = d;
+  o.nQ = nQ;
+  o.ptr = cnt;
+  o.cptr = ccnt;
+  o.col.resize(size_t(cnt[nQ]));
+  o.m.resize(size_t(cnt[nQ]));
+  o.a.assign(size_t(cnt[nQ]) * d * d, 0.0);
+  o.ccol.resize(size_t(ccnt[nQ]));
+  o.c.assign(size_t(ccnt[nQ]) * d, 0.0);
+  // fill, checking every velocity row against the structure
+  parallel_for(nQ, nthreads, [&](int64_t i0, int64_t i1) {
+    NodeList nodes;
+    std::vector<int32_t> pcols;
+    for (int64_t i = i0; i < i1; ++i) {
+      node_list(i, nodes, pcols);
+      const int64_t e0 = o.ptr[i], c0 = o.cptr[i];
+      const int64_t nn = int64_t(nodes.size());
+      for (int64_t t = 0; t < nn; ++t) {
+        o.col[size_t(e0 + t)] = nodes[size_t(t)].first;
+        o.m[size_t(e0 + t)] = nodes[size_t(t)].second;
+      }
+      for (size_t t = 0; t < pcols.size(); ++t) o.ccol[size_t(c0) + t] = pcols[t];
+      // the rows of one kind (which CSR, which row block) must hold sign * rhoM_ij at the
+      // column (col_block + d j + c) for every listed node j and nothing else
+      auto mass_rows = [&](const Csr& A, int64_t row, int64_t col0, double sign) {
+        int64_t seen = 0;
+        for (int64_t p = A.ptr[row]; p < A.ptr[row + 1]; ++p) {
+          const int64_t cl = A.col[p] - col0;
+          const double v = A.val[p];
+          if (cl >= 0 && cl < nv && cl % d == (row % d)) {
+            const int64_t t = find(nodes, int32_t(cl / d));
+            if (t < 0 || nodes[size_t(t)].second != sign * v) return false;
+            ++seen;
+          } else if (v != 0.0) {
+            return false;
+          }
+        }
+        return seen == nn;
+      };
+      for (int c = 0; c < d && !bad[i]; ++c) {
+        const int64_t ru = int64_t(d) * i + c, rv = nv + ru;
+        // nv is a multiple of d, so row % d is the component in both row blocks
+        if (!mass_rows(MM, ru, nv, 1.0) || !mass_rows(KK, ru, 0, -1.0) || !mass_rows(MM, rv, 0, 1.0)) {
+          bad[i] = 1;
+          break;
+        }
+        // KK v-row: A on U (the listed nodes), C^T on P, nothing on V
+        for (int64_t p = KK.ptr[rv]; p < KK.ptr[rv + 1] && !bad[i]; ++p) {
+          const int64_t cl = KK.col[p];
+          const double v = KK.val[p];
+          if (cl >= nv && cl < 2 * nv) {
+            const int64_t t = find(nodes, int32_t((cl - nv) / d));
+            if (t < 0) {
+              if (v != 0.0) bad[i] = 1;
+              continue;
+            }
+            o.a[size_t(e0 + t) * d * d + size_t(c) * d + size_t((cl - nv) % d)] = v;
+          } else if (cl >= 2 * nv && cl < 2 * nv + np) {
+            const auto it = std::lower_bound(pcols.begin(), pcols.end(), int32_t(cl - 2 * nv));
+            o.c[size_t(c0 + (it - pcols.begin())) * d + c] = v;
+          } else if (v != 0.0) {
+            bad[i] = 1;
+          }
+        }
+      }
+    }
+  });
+  for (int64_t i = 0; i < nQ; ++i)
+    if (bad[i]) return false;
+  out = std::move(o);
+  return true;
+}
+
 // ------------------------------------------------------------- transfers
 namespace {
 // 1D interpolation weights of the coarse Q_p basis at fine lattice point g.
@@ -1432,6 +1562,8 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bo
   S.ns = 2 * d * nQ + nP;
   S.n = kt * S.ns;
   S.nP = nP;
+  S.nodeQQ = QQ;
+  S.nodeQP = QP;
   if (dtu) {
     // boundary part of C: a pressure row couples the velocity nodes of its adjacent boundary
     // cells; the union of their node boxes is counted by inclusion-exclusion

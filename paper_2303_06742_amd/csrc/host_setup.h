@@ -111,6 +111,28 @@ struct BuildOptions {
 void build_level(const BuildOptions& o, const Material& m, const std::vector<double>& Kcell, LevelHost& L,
                  int nthreads);
 
+// The velocity rows of a level's spatial matrices by pairs of Q_r nodes.  In the rows of one
+// time-node block, ordered (u-equation, v-equation, p-equation) against the columns (V, U, P),
+// Problem 3.1 and Problem B.1 both have
+//   MM = [[0, rhoM (x) I_d, 0], [rhoM (x) I_d, 0, 0], [...]],  KK = [[-rhoM (x) I_d, 0, 0], [0, A, C^T], [...]],
+// so the velocity rows need, per pair of nodes (i, j) that share a cell, the scalar rhoM_ij and
+// the d x d block A_ij, and per pair (node i, pressure dof q) the d values C^T_{(i,c), q}.
+struct NodeOp {
+  int d = 0;
+  int64_t nQ = 0;
+  std::vector<int64_t> ptr;   // nQ + 1: node pairs of node i
+  std::vector<int32_t> col;   // node j
+  std::vector<double> m;      // rhoM_ij
+  std::vector<double> a;      // A_ij, row-major d x d (row = component of i)
+  std::vector<int64_t> cptr;  // nQ + 1: pressure dofs coupled to node i
+  std::vector<int32_t> ccol;  // pressure dof q
+  std::vector<double> c;      // C^T_{(i,c), q}, d values per pair
+};
+// Extract the node-pair form from the spatial MM and KK of a level (rows sorted by column or
+// not).  Returns false, leaving `out` empty, if the matrices do not have the block structure
+// above exactly (the equal rhoM blocks included).
+bool build_node_op(const LevelHost& L, NodeOp& out, int nthreads);
+
 // Space-time prolongation from the coarse level to the next finer one.
 Csr build_prolongation(const LevelHost& coarse, const LevelHost& fine, int nthreads = 1);
 Csr transpose(const Csr& a, int64_t ncols_out);
@@ -136,6 +158,8 @@ struct LevelSizes {
   int max_nr = 0, max_nn = 0;
   int64_t nP = 0;
   int64_t nnzCface = 0;  // Problem B.1: nonzeros of the boundary part of C (LevelHost::Cface)
+  int64_t nodeQQ = 0;    // NodeOp pairs of Q_r nodes sharing a cell
+  int64_t nodeQP = 0;    // NodeOp pairs (Q_r node, pressure dof) sharing a cell
 };
 LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc = false, bool dtu = false);
 

@@ -27,6 +27,23 @@ struct TimeOp {
 void k_kron_spmv(hipStream_t st, int mode, const TimeOp& top, int64_t ns, const int64_t* mptr, const int32_t* mcol,
                  const double* mval, const int64_t* kptr, const int32_t* kcol, const double* kval, const double* x,
                  const double* b, double* y, int lanes);
+// The same operator with the velocity rows in node-pair form (host_setup.h NodeOp, uploaded):
+// d = 2 or 3, nQ Q_r nodes; the pressure rows [2 d nQ, ns) from the spatial CSRs as above.
+struct NodeOpDev {
+  int d = 0;
+  int64_t nQ = 0;
+  int lanes = 0;  // lanes per node, 2, 4, 8 or 16 (0: 4 in 2D, 8 in 3D)
+  const int64_t* ptr = nullptr;
+  const int32_t* col = nullptr;
+  const double* m = nullptr;
+  const double* a = nullptr;
+  const int64_t* cptr = nullptr;
+  const int32_t* ccol = nullptr;
+  const double* c = nullptr;
+};
+void k_node_op(hipStream_t st, int mode, const TimeOp& top, const NodeOpDev& o, int64_t ns, const int64_t* mptr,
+               const int32_t* mcol, const double* mval, const int64_t* kptr, const int32_t* kcol, const double* kval,
+               const double* x, const double* b, double* y);
 void k_patch_extract_t(hipStream_t st, int64_t p0, int64_t count, int max_np, const int64_t* poff,
                        const int32_t* pdof, const int64_t* ptr, const int32_t* col, const double* val,
                        const int64_t* woff, double* W);
@@ -148,6 +165,8 @@ struct SourceArgs {
   int d, r, N, nq, disc, nlp;
   int64_t n1, n1p, nv, ns;
   double h, rho, lam, mu, alpha, c0, t, scale;
+  const double* tdev;  // if not NULL the time is tdev[tidx] (device memory, read at run time)
+  int tidx;
 };
 void k_source(hipStream_t st, const SourceArgs& a, const double* xq, const double* wq, const double* bq,
               const double* bp, const double* Kcell, double* out);

@@ -88,17 +88,11 @@ static void launch_csr(hipStream_t st, int64_t nrows, const int64_t* ptr, const 
 // and accumulate u_a = MM[i,:] x_a, v_a = KK[i,:] x_a for every time node a; then
 // (A x)_b[i] = sum_a D[b][a] u_a + mt[b] v_b.
 template <int G, int MODE, int NT>
-__global__ void __launch_bounds__(256) kron_spmv_kernel(TimeOp top, int64_t ns, const int64_t* __restrict__ mptr,
-                                                        const int32_t* __restrict__ mcol,
-                                                        const double* __restrict__ mval,
-                                                        const int64_t* __restrict__ kptr,
-                                                        const int32_t* __restrict__ kcol,
-                                                        const double* __restrict__ kval,
-                                                        const double* __restrict__ x, const double* __restrict__ b,
-                                                        double* __restrict__ y) {
-  const int lane = threadIdx.x % G;
-  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
-  if (row >= ns) return;
+__device__ inline void kron_row(const TimeOp& top, int64_t ns, int64_t row, int lane, const int64_t* __restrict__ mptr,
+                                const int32_t* __restrict__ mcol, const double* __restrict__ mval,
+                                const int64_t* __restrict__ kptr, const int32_t* __restrict__ kcol,
+                                const double* __restrict__ kval, const double* __restrict__ x,
+                                const double* __restrict__ b, double* __restrict__ y) {
   double u[NT], v[NT];
 #pragma unroll
   for (int a = 0; a < NT; ++a) u[a] = v[a] = 0.0;
@@ -132,6 +126,149 @@ __global__ void __launch_bounds__(256) kron_spmv_kernel(TimeOp top, int64_t ns, 
     if (MODE == 0) y[o] = acc;
     if (MODE == 1) y[o] = b[o] - acc;
   }
+}
+
+template <int G, int MODE, int NT>
+__global__ void __launch_bounds__(256) kron_spmv_kernel(TimeOp top, int64_t ns, const int64_t* __restrict__ mptr,
+                                                        const int32_t* __restrict__ mcol,
+                                                        const double* __restrict__ mval,
+                                                        const int64_t* __restrict__ kptr,
+                                                        const int32_t* __restrict__ kcol,
+                                                        const double* __restrict__ kval,
+                                                        const double* __restrict__ x, const double* __restrict__ b,
+                                                        double* __restrict__ y) {
+  const int lane = threadIdx.x % G;
+  const int64_t row = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+  if (row >= ns) return;
+  kron_row<G, MODE, NT>(top, ns, row, lane, mptr, mcol, mval, kptr, kcol, kval, x, b, y);
+}
+
+// Level operator with the velocity rows in node-pair form (NodeOp on the host): blocks
+// [0, nb_node) give G lanes to each Q_r node i and produce its 2 d rows (u- and v-equation) at
+// every time node from
+//   su[a][c] = sum_j rhoM_ij U_a[j][c],  sv[a][c] = sum_j rhoM_ij V_a[j][c],
+//   tk[b][c] = sum_j (A_ij U_b[j])[c] + sum_q C^T_{(i,c),q} P_b[q]:
+//   (A x)_u,b = sum_a D[b][a] su[a] - mt[b] sv[b],  (A x)_v,b = sum_a D[b][a] sv[a] + mt[b] tk[b];
+// the remaining blocks give GP lanes to each pressure row and apply its MM and KK rows as the
+// CSR kernel above.  Every value of x at a node is read once per node pair (D consecutive
+// values per field and time node), and rhoM, A and C^T are stored once per pair.
+template <int G, int MODE, int NT, int D>
+__device__ inline void node_rows(const TimeOp& top, int64_t i, int lane, int64_t nv, int64_t ns,
+                                 const int64_t* __restrict__ nptr, const int32_t* __restrict__ ncol,
+                                 const double* __restrict__ nm, const double* __restrict__ na,
+                                 const int64_t* __restrict__ cptr, const int32_t* __restrict__ ccol,
+                                 const double* __restrict__ cval, const double* __restrict__ x,
+                                 const double* __restrict__ b, double* __restrict__ y) {
+  double su[NT][D], sv[NT][D], tk[NT][D];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < D; ++c) su[t][c] = sv[t][c] = tk[t][c] = 0.0;
+  const double* xv = x;
+  const double* xu = x + nv;
+  // the node pairs of node i, G lanes apart, two per lane and round (their loads in flight together)
+  auto pair_load = [&](int64_t p, double* A, double (*u)[D], double (*v)[D], double& m) {
+    const int64_t j = int64_t(ncol[p]) * D;
+    m = nm[p];
+#pragma unroll
+    for (int e = 0; e < D * D; ++e) A[e] = na[p * (D * D) + e];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        u[t][c] = xu[t * ns + j + c];
+        v[t][c] = xv[t * ns + j + c];
+      }
+  };
+  auto pair_add = [&](const double* A, const double (*u)[D], const double (*v)[D], double m) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        su[t][c] += m * u[t][c];
+        sv[t][c] += m * v[t][c];
+        double s = tk[t][c];
+#pragma unroll
+        for (int e = 0; e < D; ++e) s += A[c * D + e] * u[t][e];
+        tk[t][c] = s;
+      }
+  };
+  const int64_t pe = nptr[i + 1];
+  int64_t p = nptr[i] + lane;
+  for (; p + G < pe; p += 2 * G) {
+    double A0[D * D], A1[D * D], u0[NT][D], v0[NT][D], u1[NT][D], v1[NT][D], m0, m1;
+    pair_load(p, A0, u0, v0, m0);
+    pair_load(p + G, A1, u1, v1, m1);
+    pair_add(A0, u0, v0, m0);
+    pair_add(A1, u1, v1, m1);
+  }
+  if (p < pe) {
+    double A0[D * D], u0[NT][D], v0[NT][D], m0;
+    pair_load(p, A0, u0, v0, m0);
+    pair_add(A0, u0, v0, m0);
+  }
+  const double* xp = x + 2 * nv;
+  for (int64_t p = cptr[i] + lane; p < cptr[i + 1]; p += G) {
+    const int64_t q = ccol[p];
+    double cv[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) cv[c] = cval[p * D + c];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double pq = xp[t * ns + q];
+#pragma unroll
+      for (int c = 0; c < D; ++c) tk[t][c] += cv[c] * pq;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      su[t][c] = group_sum<G>(su[t][c]);
+      sv[t][c] = group_sum<G>(sv[t][c]);
+      tk[t][c] = group_sum<G>(tk[t][c]);
+    }
+  // every lane holds the sums; the 2 NT D outputs are spread over the lanes
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const int k = 2 * (t * D + c);
+      const int64_t ou = int64_t(t) * ns + D * i + c, ov = ou + nv;
+      if (lane == k % G) {
+        double yu = -top.mt[t] * sv[t][c];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) yu += top.D[t * NT + a] * su[a][c];
+        if (MODE == 0) y[ou] = yu;
+        if (MODE == 1) y[ou] = b[ou] - yu;
+      }
+      if (lane == (k + 1) % G) {
+        double yv = top.mt[t] * tk[t][c];
+#pragma unroll
+        for (int a = 0; a < NT; ++a) yv += top.D[t * NT + a] * sv[a][c];
+        if (MODE == 0) y[ov] = yv;
+        if (MODE == 1) y[ov] = b[ov] - yv;
+      }
+    }
+}
+
+template <int G, int GP, int MODE, int NT, int D>
+__global__ void __launch_bounds__(256) node_op_kernel(
+    TimeOp top, int64_t nQ, int64_t nv, int64_t ns, int64_t nb_node, const int64_t* __restrict__ nptr,
+    const int32_t* __restrict__ ncol, const double* __restrict__ nm, const double* __restrict__ na,
+    const int64_t* __restrict__ cptr, const int32_t* __restrict__ ccol, const double* __restrict__ cval,
+    const int64_t* __restrict__ mptr, const int32_t* __restrict__ mcol, const double* __restrict__ mval,
+    const int64_t* __restrict__ kptr, const int32_t* __restrict__ kcol, const double* __restrict__ kval,
+    const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ y) {
+  if (int64_t(blockIdx.x) < nb_node) {
+    const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    if (i >= nQ) return;
+    node_rows<G, MODE, NT, D>(top, i, int(threadIdx.x % G), nv, ns, nptr, ncol, nm, na, cptr, ccol, cval, x, b, y);
+    return;
+  }
+  const int64_t row = 2 * nv + ((int64_t(blockIdx.x) - nb_node) * blockDim.x + threadIdx.x) / GP;
+  if (row >= ns) return;
+  kron_row<GP, MODE, NT>(top, ns, row, int(threadIdx.x % GP), mptr, mcol, mval, kptr, kcol, kval, x, b, y);
 }
 
 template <int G, int MODE>
@@ -1759,8 +1896,9 @@ __global__ void axpby_kernel(double a, const double* __restrict__ x, double b, c
 }
 
 // rhs[b*ns + i] = e_b * mmx[i] + src[b*ns + i]
+// rhs may be src itself (each thread reads its entry before writing it)
 __global__ void slab_rhs_kernel(int nt, int64_t ns, const double* __restrict__ e, const double* __restrict__ mmx,
-                                const double* __restrict__ src, double* __restrict__ rhs) {
+                                const double* src, double* rhs) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= int64_t(nt) * ns) return;
   const int b = int(i / ns);
@@ -1810,6 +1948,58 @@ void k_kron_spmv(hipStream_t st, int mode, const TimeOp& top, int64_t ns, const 
     STGMG_KRON(32)
   }
 #undef STGMG_KRON
+}
+
+template <int G, int MODE, int NT, int D>
+static void launch_node_op(hipStream_t st, const TimeOp& top, const NodeOpDev& o, int64_t ns, const int64_t* mptr,
+                           const int32_t* mcol, const double* mval, const int64_t* kptr, const int32_t* kcol,
+                           const double* kval, const double* x, const double* b, double* y) {
+  // lanes per pressure row as for the CSR kernel
+  constexpr int GP = D == 2 ? 16 : 32;
+  const int64_t nv = int64_t(D) * o.nQ, np = ns - 2 * nv;
+  const int64_t nb_node = (o.nQ * G + 255) / 256, nb_p = (np * GP + 255) / 256;
+  hipLaunchKernelGGL((dev::node_op_kernel<G, GP, MODE, NT, D>), dim3(nb_node + nb_p), dim3(256), 0, st, top, o.nQ, nv,
+                     ns, nb_node, o.ptr, o.col, o.m, o.a, o.cptr, o.ccol, o.c, mptr, mcol, mval, kptr, kcol, kval, x, b,
+                     y);
+}
+
+template <int MODE, int D>
+static void node_op_nt(hipStream_t st, const TimeOp& top, const NodeOpDev& o, int64_t ns, const int64_t* mptr,
+                       const int32_t* mcol, const double* mval, const int64_t* kptr, const int32_t* kcol,
+                       const double* kval, const double* x, const double* b, double* y) {
+  // lanes per node (a power of two): by default 4 for the ~16 node pairs of a 2D Q2 node, 8 for
+  // the ~64 of a 3D one
+  const int lanes = o.lanes > 0 ? o.lanes : (D == 2 ? 4 : 8);
+#define STGMG_NODE(G)                                                                                    \
+  switch (top.nt) {                                                                                      \
+    case 1: launch_node_op<G, MODE, 1, D>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y); break; \
+    case 2: launch_node_op<G, MODE, 2, D>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y); break; \
+    case 3: launch_node_op<G, MODE, 3, D>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y); break; \
+    default: launch_node_op<G, MODE, 4, D>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y); break; \
+  }
+  if (lanes <= 2) {
+    STGMG_NODE(2)
+  } else if (lanes <= 4) {
+    STGMG_NODE(4)
+  } else if (lanes <= 8) {
+    STGMG_NODE(8)
+  } else {
+    STGMG_NODE(16)
+  }
+#undef STGMG_NODE
+}
+
+void k_node_op(hipStream_t st, int mode, const TimeOp& top, const NodeOpDev& o, int64_t ns, const int64_t* mptr,
+               const int32_t* mcol, const double* mval, const int64_t* kptr, const int32_t* kcol, const double* kval,
+               const double* x, const double* b, double* y) {
+  if (ns == 0) return;
+  if (o.d == 2) {
+    if (mode == 0) node_op_nt<0, 2>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y);
+    else node_op_nt<1, 2>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y);
+  } else {
+    if (mode == 0) node_op_nt<0, 3>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y);
+    else node_op_nt<1, 3>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y);
+  }
 }
 
 void k_fill_zero(hipStream_t st, double* a, int64_t n) {

@@ -49,6 +49,7 @@ __device__ inline void builtin_fg(const SourceArgs& a, const double* x, double K
 __global__ void source_kernel(SourceArgs a, const double* __restrict__ xq, const double* __restrict__ wq,
                               const double* __restrict__ bq, const double* __restrict__ bp,
                               const double* __restrict__ Kcell, double* __restrict__ out) {
+  if (a.tdev) a.t = a.tdev[a.tidx];  // a time set on the device (replays of a captured graph)
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t nQ = a.nv / a.d, nP = a.ns - 2 * a.nv;
   if (t >= nQ + nP) return;

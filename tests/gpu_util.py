@@ -35,7 +35,7 @@ def oracle_direct_solve(cfg, F):
     return prob.direct_solve(F), prob.A
 
 
-@functools.lru_cache(maxsize=8)
+@functools.lru_cache(maxsize=64)
 def oracle_hierarchy(cfg_key):
     from oracle import gmg
     # the storage of the patch solves does not change the operator

@@ -47,8 +47,25 @@ def csr(lib, which, nrows):
 
 
 def sizes(lib, d, r, k, N, kind):
-    out = np.zeros(16, dtype=np.int64)
+    out = np.zeros(18, dtype=np.int64)
     lib.stgmg_host_sizes.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p]
     lib.stgmg_host_sizes(d, r, k, N, kind, ptr(out))
     return dict(zip(['n', 'nnzA', 'nnzMM', 'nnzP', 'npatch', 'sum_np', 'sum_np_ld', 'max_np', 'nnzKK',
-                    'sum_red_fixed', 'sum_nr_ldr', 'max_nr', 'max_nn', 'nnzCface', 'sum_tiles', 'sum_tiles2'], out.tolist()))
+                    'sum_red_fixed', 'sum_nr_ldr', 'max_nr', 'max_nn', 'nnzCface', 'sum_tiles', 'sum_tiles2',
+                    'nodeQQ', 'nodeQP'], out.tolist()))
+
+
+def node_op(lib, nQ, d):
+    """The node-pair form of the velocity rows of the last built level, or None."""
+    lib.stgmg_host_node_build.restype = ctypes.c_longlong
+    lib.stgmg_host_node_cnnz.restype = ctypes.c_longlong
+    lib.stgmg_host_node_arrays.argtypes = [ctypes.c_void_p] * 7
+    nnz = lib.stgmg_host_node_build()
+    if nnz < 0:
+        return None
+    cnnz = lib.stgmg_host_node_cnnz()
+    out = dict(ptr=np.zeros(nQ + 1, dtype=np.int64), col=np.zeros(nnz, dtype=np.int32), m=np.zeros(nnz),
+               a=np.zeros(nnz * d * d), cptr=np.zeros(nQ + 1, dtype=np.int64), ccol=np.zeros(cnnz, dtype=np.int32),
+               c=np.zeros(cnnz * d))
+    lib.stgmg_host_node_arrays(*[ptr(out[k]) for k in ('ptr', 'col', 'm', 'a', 'cptr', 'ccol', 'c')])
+    return out

@@ -93,36 +93,51 @@ def test_patch_inverses_sampled(ctx):
 
 def test_one_sweep_sampled_dofs(ctx):
     """Algorithm 4.1, one sweep from a random iterate: at sampled dofs mu the GPU's new iterate
-    equals d0 + omega / p(mu) sum_{P contains mu} (A_P^{-1} R_P (b - A d0))[mu]."""
+    equals d0 + omega / p(mu) sum_{P contains mu} (A_P^{-1} R_P (b - A d0))[mu].  Sampled: every
+    velocity component of V and U at sampled Q_r nodes and the pressure at sampled Q_{r-1}
+    nodes, at every time node (the rows of the tiled kernel's 4x16 last block row and of its
+    pressure scaling included), with the finest level on one wave per patch."""
     S = ctx['S']
     b = W.random_vector(S.n, 911)
     d0 = W.random_vector(S.n, 912)
     d1 = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 1))
-    ns = ctx['b'].ns
+    blk = ctx['b']
+    ns, nv, nt, dim = blk.ns, blk.nv, CFG.k + 1, CFG.dim
     cells = ctx['cells']
-    # the vertex patches that contain a Q_r node: those of the grid vertices of its adjacent cells
     N, r = CFG.fine_cells, CFG.r
     rng = np.random.default_rng(913)
-    n1 = r * N + 1
-    for node in list(rng.integers(0, n1 * n1, 6)) + [0, n1 * n1 - 1]:
-        gx, gy = node % n1, node // n1
-        cxs = sorted({min(max((gx - 1) // r, 0), N - 1), min(gx // r, N - 1)})
-        cys = sorted({min(max((gy - 1) // r, 0), N - 1), min(gy // r, N - 1)})
-        verts = {vx + (N + 1) * vy for cx in cxs for cy in cys for vx in (cx, cx + 1) for vy in (cy, cy + 1)}
-        mu = ns + ctx['b'].nv + CFG.dim * node  # time node 1, U component 0 of this node (nt >= 2)
-        acc, cnt = 0.0, 0
+
+    def adjacent(g, p):
+        """cells along one axis touching lattice point g of a degree-p lattice"""
+        return sorted({min(max((g - 1) // p, 0), N - 1), min(g // p, N - 1)})
+
+    def check(gx, gy, p, mus):
+        # the vertex patches that contain a node: those of the grid vertices of its adjacent cells
+        verts = {vx + (N + 1) * vy for cx in adjacent(gx, p) for cy in adjacent(gy, p)
+                 for vx in (cx, cx + 1) for vy in (cy, cy + 1)}
+        acc = np.zeros(len(mus))
+        cnt = np.zeros(len(mus))
         for v in sorted(verts):
             Z = patch_dofs_of(ctx, cells[v])
-            pos = np.searchsorted(Z, mu)
-            if pos >= len(Z) or Z[pos] != mu:
+            pos = np.searchsorted(Z, mus)
+            inside = (pos < len(Z)) & (Z[np.minimum(pos, len(Z) - 1)] == mus)
+            if not inside.any():
                 continue
             rP = b[Z] - apply_rows(ctx, d0, Z)
             y = np.linalg.solve(patch_matrix(ctx, Z), rP)
-            acc += y[pos]
-            cnt += 1
-        assert cnt >= 1
-        ref = d0[mu] + CFG.omega * acc / cnt
-        assert abs(d1[mu] - ref) <= 1e-10 * max(1.0, abs(ref)), (node, d1[mu], ref)
+            acc[inside] += y[pos[inside]]
+            cnt[inside] += 1
+        assert np.all(cnt >= 1)
+        ref = d0[mus] + CFG.omega * acc / cnt
+        assert np.all(np.abs(d1[mus] - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), (gx, gy, d1[mus] - ref)
+
+    n1, n1p = r * N + 1, (r - 1) * N + 1
+    for node in list(rng.integers(0, n1 * n1, 5)) + [0, n1 * n1 - 1, n1 * (n1 // 2) + 1]:
+        mus = np.array([t * ns + f * nv + dim * node + c for t in range(nt) for f in (0, 1) for c in range(dim)])
+        check(node % n1, node // n1, r, mus)
+    for q in list(rng.integers(0, n1p * n1p, 4)) + [0, n1p * n1p - 1]:
+        mus = np.array([t * ns + 2 * nv + q for t in range(nt)])
+        check(q % n1p, q // n1p, r - 1, mus)
 
 
 def test_solve_true_residual_through_the_oracle_operator(ctx):

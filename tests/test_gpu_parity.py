@@ -142,10 +142,13 @@ def test_solve_against_oracle(key, waves):
     xs = to_host(x)
     assert info['converged'] == 1
     assert np.linalg.norm(F - A @ xs) <= 1e-8 * np.linalg.norm(F) * (1 + 1e-6)
-    xo, oi = fgmres.fgmres(A, F, H.precondition, rtol=1e-8)
-    assert abs(info['iters'] - oi['iters']) <= 1, (info['iters'], oi['iters'])
-    # equal iteration counts: the two iterates agree to the rounding of the V-cycle
-    xg, _ = fgmres.fgmres(A, F, H.precondition, rtol=0.0, fixed_iters=info['iters'])
+    # the oracle's FGMRES-GMG run for the same number of iterations: its own residual estimate
+    # crosses the tolerance at the same iteration (one earlier at most: the test sits on a
+    # rounding edge), and the two iterates agree to the rounding of the V-cycle
+    xg, oi = fgmres.fgmres(A, F, H.precondition, rtol=0.0, fixed_iters=info['iters'])
+    hist = np.array(oi['resid_history'])
+    assert hist[-1] <= 1e-8 * hist[0] * 1.01, (info['iters'], hist / hist[0])
+    assert info['iters'] <= 1 or hist[-3] > 1e-8 * hist[0], (info['iters'], hist / hist[0])
     e = rel_err(xs, xg)
     print(f"[iterate] {key} waves={waves} iters={info['iters']} rel_err={e:.2e}", flush=True)
     assert e < 1e-10, e
@@ -177,13 +180,19 @@ def test_fp32_solve_against_oracle(key, waves):
     """The mixed path (FP32 patch solves inside FP64 FGMRES) against the oracle's FP64 sparse
     direct solve: stopped at rtol 1e-10, the true relative residual is <= 1e-10 (so <= 1e-8) and
     the solution is within 1e-7 of the oracle's (relative, max norm)."""
+    from oracle import fgmres
     from tests.gpu_util import oracle_direct_solve
     S = solver(key, 'fp32', waves=waves)
     cfg = CONFIGS[key]
     F = workloads.random_vector(S.n, 53)
     x = S.empty()
     info = S.solve(to_dev(F), x, rtol=1e-10)
-    ref, A = oracle_direct_solve(cfg, F)
+    if cfg.dim == 2:
+        ref, A = oracle_direct_solve(cfg, F)
+    else:  # the sparse LU of a 3D Q2 operator fills in too much: the oracle's FGMRES-GMG to 1e-11
+        H = oracle_hierarchy(key)
+        A = H.levels[-1].A
+        ref, _ = fgmres.fgmres(A, F, H.precondition, rtol=1e-11)
     xs = to_host(x)
     assert info['converged'] == 1
     assert np.linalg.norm(F - A @ xs) <= 1e-10 * np.linalg.norm(F) * (1 + 1e-6)
@@ -314,3 +323,31 @@ def test_c2_64_automatic_waves(precision):
         e = rel_err(to_host(x), ref)
         print(f"[c2_64 fp32] iters={info['iters']} err_vs_oracle={e:.2e}", flush=True)
         assert info['converged'] == 1 and e < 1e-7
+
+
+@pytest.mark.parametrize("key", ['c2s', 'c2_64', 'c3s'])
+def test_autotuned_launch_shapes(key):
+    """autotune = 1: the setup times the tiled kernel with one and four waves per patch and the
+    operator kernel with 2, 4, 8 and 16 lanes per node on every level and keeps the fastest; the
+    operator and the smoother still match the oracle (1e-13 of |A||x|, 1e-10) and the solve the
+    default handle's to 1e-10."""
+    from oracle import gmg
+    require_gpu()
+    from paper_2303_06742_amd import capi
+    S = capi.Solver(CONFIGS[key], autotune=1)
+    H = oracle_hierarchy(key)
+    for l in range(S.levels):
+        A = H.levels[l].A
+        xv = workloads.random_vector(A.shape[0], 110 + l)
+        yv = to_host(S.apply_operator(to_dev(xv), level=l))
+        assert np.all(np.abs(yv - A @ xv) <= 1e-13 * (abs(A) @ abs(xv)) + 1e-300), (key, l)
+    lev = H.levels[-1]
+    b = workloads.random_vector(lev.n, 17)
+    d0 = workloads.random_vector(lev.n, 18)
+    d = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 2))
+    assert rel_err(d, gmg.vanka_smooth(lev, b, d0, 2, H.omega)) < 1e-10
+    F = to_dev(workloads.random_vector(S.n, 33))
+    x, x0 = S.empty(), S.empty()
+    i1 = S.solve(F, x, rtol=1e-8)
+    i0 = solver(key).solve(F, x0, rtol=1e-8)
+    assert i1['iters'] == i0['iters'] and rel_err(to_host(x), to_host(x0)) < 1e-10
