@@ -331,7 +331,7 @@ def main():
     ap.add_argument('--slots', type=int, default=8)
     ap.add_argument('--seed', type=int, default=0)
     ap.add_argument('--hbm-budget-gb', type=float, default=200.0)
-    ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32'])
+    ap.add_argument('--precision', default='fp64', choices=['fp64', 'fp32', 'bf16'])
     ap.add_argument('--form', default='v', choices=['v', 'dtu'],
                     help="third equation: 'v' Problem 3.1, 'dtu' Problem B.1")
     ap.add_argument('--graph', type=int, default=-1, choices=[-1, 0, 1],
@@ -436,7 +436,7 @@ def main():
         'higher_is_better': True,
         'scaling': 'weak',
         'vs_baseline': None,
-        'dtype': 'f64' if args.precision == 'fp64' else 'f64+f32-smoother',
+        'dtype': 'f64' if args.precision == 'fp64' else f'f64+{"f32" if args.precision == "fp32" else "bf16"}-smoother',
         'data': 'synthetic',
         'config': {'workload': cfg.name, 'dim': cfg.dim, 'cells': f"{cfg.fine_cells}^{cfg.dim}",
                    'levels': cfg.levels, 'r': cfg.r, 'k': cfg.k, 'patch': cfg.patch, 'pressure': cfg.pressure, 'form': cfg.form, 'smoother': args.precision,
@@ -451,6 +451,7 @@ def main():
         'setup_s': setup_s,
         'hbm_bytes_resident': q['bytes'],
         'roofline': {'bound': 'hbm', 'kernel': (PATCH_KERNEL_FP32_SYM if args.precision == 'fp32' and cfg.time_blocks == 3
+                                                else PATCH_KERNEL[3] + ' BF16' if args.precision == 'bf16'
                                                 else PATCH_KERNEL[cfg.time_blocks]) + ' (finest level)',
                      'achieved': achieved,
                      'peak': HBM_PEAK_GBS, 'unit': 'GB/s', 'frac': achieved / HBM_PEAK_GBS,
@@ -461,8 +462,8 @@ def main():
                      # w * sum n_P^2 + 32 n) would have to move this many bytes; the rate is the
                      # equivalent throughput of the reformulated patch solve, not HBM traffic
                      'dense_inverse_equivalent': {
-                         'bytes_per_launch': dense_inverse_bytes(cfg, 8 if args.precision == 'fp64' else 4),
-                         'GBs': dense_inverse_bytes(cfg, 8 if args.precision == 'fp64' else 4) /
+                         'bytes_per_launch': dense_inverse_bytes(cfg, {'fp64': 8, 'fp32': 4, 'bf16': 2}[args.precision]),
+                         'GBs': dense_inverse_bytes(cfg, {'fp64': 8, 'fp32': 4, 'bf16': 2}[args.precision]) /
                          (avg_pa_ms * 1e-3) / 1e9 if pa['launches'] else 0.0}},
         'residual_spmv': {'kernel': 'node_op_kernel (finest level)', 'avg_launch_ms': avg_rs_ms,
                           'launches': rs['launches'], 'bytes_per_launch': rs['bytes_per_launch'],

@@ -60,6 +60,9 @@ typedef int32_t stgmg_status;
 
 #define STGMG_FP64 0 /* patch inverses stored and applied in FP64 */
 #define STGMG_FP32 1 /* patch inverses computed in FP64, stored and applied in FP32 */
+#define STGMG_BF16 2 /* patch inverses computed in FP64, stored in BF16 (time_blocks = 3 only: the
+                        symmetric tiles, four tiles per 8-byte unit, and the small reduced factors),
+                        applied with FP64 sums */
 
 /* pressure space Q_h of Def:VhQh / Eq:DefVhQh */
 #define STGMG_PRESSURE_CONT 0 /* continuous Q_{r-1} (Taylor-Hood), B_gamma with Nitsche terms (Def:B, first option) */
@@ -82,7 +85,7 @@ typedef struct {
   int32_t r;             /* displacement degree (Q_r^d); pressure degree r-1 (see pressure); 2 <= r <= 4 */
   int32_t k;             /* dG(k) in time, 0 <= k <= 3 */
   int32_t patch;         /* STGMG_PATCH_CELL or STGMG_PATCH_VERTEX */
-  int32_t smoother_prec; /* STGMG_FP64 or STGMG_FP32 */
+  int32_t smoother_prec; /* STGMG_FP64, STGMG_FP32 or STGMG_BF16 */
   int32_t n_smooth;      /* J_max pre- and post-smoothing sweeps (paper: 4) */
   double omega;          /* Vanka under-relaxation (paper: 0.7) */
   double tau;            /* slab length */

@@ -31,7 +31,7 @@ STGMG_ERR_BAD_POINTER = -7
 PATCH = {'cell': 0, 'vertex': 1}
 PROF_PATCH_APPLY = 0
 PROF_RESIDUAL = 1
-PREC = {'fp64': 0, 'fp32': 1}
+PREC = {'fp64': 0, 'fp32': 1, 'bf16': 2}
 PRESSURE = {'cont': 0, 'disc': 1}  # Q_{r-1} (Taylor-Hood) or P_{r-1}^disc with the interior penalty form
 FORM = {'v': 0, 'dtu': 1}  # Problem 3.1 or Problem B.1
 

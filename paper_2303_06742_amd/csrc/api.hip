@@ -135,6 +135,7 @@ struct LevelDev {
   int waves = 0;     // waves per patch of the tiled patch kernel on this level (0: by patch count)
   DArr<double> inv64, winv, y;
   DArr<float> inv32;
+  DArr<__bf16> inv16;  // BF16 storage (symmetric tiles and the small reduced factors)
   DevCsr P, R;  // prolongation from level-1 and its transpose
   DevCsr MMs, KKs;  // spatial MM and KK: the level operator A = D^t (x) MM + M^t (x) KK
   // the velocity rows of the same operator by node pairs (rhoM_ij, A_ij, C^T), used by the
@@ -279,8 +280,10 @@ void check_params(const stgmg_params* p) {
   if (p->k < 0 || p->k > 3) throw ApiError(STGMG_ERR_UNSUPPORTED, "k must be in 0..3");
   if (p->patch != STGMG_PATCH_CELL && p->patch != STGMG_PATCH_VERTEX)
     throw ApiError(STGMG_ERR_INVALID_ARG, "unknown patch kind");
-  if (p->smoother_prec != STGMG_FP64 && p->smoother_prec != STGMG_FP32)
+  if (p->smoother_prec != STGMG_FP64 && p->smoother_prec != STGMG_FP32 && p->smoother_prec != STGMG_BF16)
     throw ApiError(STGMG_ERR_INVALID_ARG, "unknown smoother precision");
+  if (p->smoother_prec == STGMG_BF16 && p->time_blocks != 3)
+    throw ApiError(STGMG_ERR_UNSUPPORTED, "BF16 storage needs the symmetric tiles (time_blocks = 3)");
   if (p->n_smooth < 0 || p->n_smooth > 64) throw ApiError(STGMG_ERR_INVALID_ARG, "n_smooth out of range");
   if (!(p->tau > 0) || !(p->rho > 0) || !(p->mu > 0) || !(p->c0 > 0) || !(p->alpha >= 0) ||
       !(p->lambda >= 0) || !(p->omega > 0))
@@ -350,7 +353,10 @@ bool red_sym_possible(const stgmg::TimeBlockConsts& tb) {
 }
 
 // stored 64-value tiles of the lower triangle of an nr x nr matrix (FP32: tiles paired)
-int64_t red_sym_tiles(int nr, bool f32) { return stgmg::sym_slots(nr, f32 ? 2 : 1); }
+// tiles interleaved per 8-byte unit of the stored values: 1 (FP64), 2 (FP32), 4 (BF16)
+int tiles_per_unit(int32_t prec) { return prec == STGMG_BF16 ? 4 : prec == STGMG_FP32 ? 2 : 1; }
+int64_t red_sym_tiles(int nr, int32_t prec) { return stgmg::sym_slots(nr, tiles_per_unit(prec)); }
+size_t value_bytes(int32_t prec) { return prec == STGMG_BF16 ? 2 : prec == STGMG_FP32 ? 4 : 8; }
 
 // FP32 storage takes the tiles up to this many Schur rows and the square layout beyond: one
 // wave streams a patch's tiles, and with 4-byte values it keeps half the bytes of FP64 in
@@ -360,6 +366,7 @@ int64_t red_sym_tiles(int nr, bool f32) { return stgmg::sym_slots(nr, f32 ? 2 : 
 constexpr int FP32_SYM_MAX_NR = 96;
 bool red_sym_used(const stgmg_params& p, bool sym_possible, int max_nr) {
   return p.time_blocks == 3 && sym_possible && (p.smoother_prec != STGMG_FP32 || max_nr <= FP32_SYM_MAX_NR);
+  // (BF16 storage exists only as tiles: check_level_storage rejects a level without them)
 }
 
 // Event pair around one launch of kernel class `what` on the finest level.
@@ -398,7 +405,10 @@ void op_apply(stgmg_handle* h, int l, int mode, const double* x, const double* b
 // The patch solves y_P = A_P^{-1} R_P r of one level, in the level's storage mode.
 void launch_patch_apply(stgmg_handle* h, LevelDev& L, const double* r) {
   const bool f32 = h->prm.smoother_prec == STGMG_FP32;
-  if (h->red && f32)
+  if (h->red && h->prm.smoother_prec == STGMG_BF16)
+    stgmg::k_patch_apply_red_bf16(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, L.waves, h->tbc, h->prm.dim,
+                                  L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv16.p, r, L.y.p);
+  else if (h->red && f32)
     stgmg::k_patch_apply_red_f32(h->st, L.npatch, L.max_np, L.max_nu, L.max_nr, L.sym, L.waves,
                                  h->tbc, h->prm.dim,
                                  L.poff.p, L.pdof.p, L.tpos.p, L.pnu.p, L.ioff.p, L.inv32.p, r, L.y.p);
@@ -746,7 +756,7 @@ void build(stgmg_handle* h) {
           for (int a = 0; a < h->tbc.nblk; ++a) {
             const int64_t planes = h->tbc.cplx[a] ? 2 : 1;
             if (D.sym) {
-              sz += planes * red_sym_tiles(int(nr), p.smoother_prec == STGMG_FP32) * 64;
+              sz += planes * red_sym_tiles(int(nr), p.smoother_prec) * 64;
               D.alg_inv_entries += double(planes * nr * (nr + 1) / 2);
             } else {
               sz += planes * nr * stgmg::inv_ld(int(nr));
@@ -778,7 +788,11 @@ void build(stgmg_handle* h) {
       D.winv.upload(H.winv, h->st, ctr);
       D.y.alloc(int64_t(H.pdof.size()), ctr, h->st);
       const int64_t tot = D.ioff_h[H.npatch];
-      if (p.smoother_prec == STGMG_FP32)
+      if (p.smoother_prec == STGMG_BF16 && !D.sym)
+        throw ApiError(STGMG_ERR_UNSUPPORTED, "BF16 storage needs the symmetric tiles (positive real eigenvalues)");
+      if (p.smoother_prec == STGMG_BF16)
+        D.inv16.alloc(tot, ctr, h->st);
+      else if (p.smoother_prec == STGMG_FP32)
         D.inv32.alloc(tot, ctr, h->st);
       else
         D.inv64.alloc(tot, ctr, h->st);
@@ -890,7 +904,7 @@ void build(stgmg_handle* h) {
                 soff[i * nblk + a] = so;
                 toff[i * nblk + a] = oo;
                 so += int64_t(nr) * (c ? 2 * ldr : ldr);
-                oo += (c ? 2 : 1) * red_sym_tiles(nr, p.smoother_prec == STGMG_FP32) * 64;
+                oo += (c ? 2 : 1) * red_sym_tiles(nr, p.smoother_prec) * 64;
               } else {
                 oo += int64_t(nr) * (c ? 2 * ldr : ldr);
               }
@@ -941,7 +955,24 @@ void build(stgmg_handle* h) {
           stgmg::k_fill_zero(h->st, wkk.p, cnt * sq);
           stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
                                            D.MMs.val.p, D.KKs.ptr.p, D.KKs.col.p, D.KKs.val.p, wmm.p, wkk.p);
-          if (p.smoother_prec == STGMG_FP32) {
+          if (p.smoother_prec == STGMG_BF16) {  // symmetric tiles only
+            stgmg::k_form_reduced_blocks_bf16(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
+                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv16.p);
+            if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
+              stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch, int64_t(max_nn) * max_nn);
+            if (in_lds) {
+              stgmg::k_gj_lds_bf16(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv16.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
+              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+            } else {
+              stgmg::k_gj_invert_bf16(h->st, nb, n_mass, max_n, dgrp, Wb.p, D.inv16.p, stat.p);
+              stgmg::k_gj_invert_f64(h->st, nb, n_real + n_cplx, max_n, dgrp + n_mass, Wb.p, Sq.p, stat.p);
+            }
+            stgmg::k_pack_red_sym_bf16(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
+                                       dtoff.back().p, Sq.p, D.inv16.p);
+            stgmg::k_fold_reduced_bf16(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, dper, nblk + 1,
+                                       D.inv16.p);
+          } else if (p.smoother_prec == STGMG_FP32) {
             stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv32.p);
             if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
@@ -1591,7 +1622,18 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
     if (!out_host) return STGMG_OK;
     const int64_t cnt = D.ioff_h[patch + 1] - D.ioff_h[patch];
     std::vector<double> st(cnt);
-    if (h->prm.smoother_prec == STGMG_FP32) {
+    if (h->prm.smoother_prec == STGMG_BF16) {
+      std::vector<uint16_t> f(st.size());
+      HIPCHK(hipMemcpyAsync(f.data(), D.inv16.p + D.ioff_h[patch], f.size() * sizeof(uint16_t), hipMemcpyDeviceToHost,
+                            h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      for (size_t i = 0; i < f.size(); ++i) {  // a BF16 value is the upper half of an FP32 one
+        const uint32_t bits = uint32_t(f[i]) << 16;
+        float v;
+        std::memcpy(&v, &bits, sizeof(v));
+        st[i] = v;
+      }
+    } else if (h->prm.smoother_prec == STGMG_FP32) {
       std::vector<float> f(st.size());
       HIPCHK(hipMemcpyAsync(f.data(), D.inv32.p + D.ioff_h[patch], f.size() * sizeof(float), hipMemcpyDeviceToHost,
                             h->st));
@@ -1635,11 +1677,11 @@ stgmg_status stgmg_get_patch_inverse(stgmg_handle* h, int32_t level, int64_t pat
           const std::complex<double> lam(tb.lam[2 * a], tb.lam[2 * a + 1]);
           // S(lam)^{-1}(i, q): square column-major, or D2 X D1 from the symmetric tiles
           const std::complex<double> mu2 = std::sqrt(lam), mu1 = -1.0 / mu2;
-          const bool f32 = h->prm.smoother_prec == STGMG_FP32;
-          const int64_t ntl = red_sym_tiles(nr, f32);
+          const int tpu = tiles_per_unit(h->prm.smoother_prec);
+          const int64_t ntl = red_sym_tiles(nr, h->prm.smoother_prec);
           auto sinv = [&](int i, int q) -> std::complex<double> {
             if (!D.sym) return {st[off + size_t(q) * ldc + i], c ? st[off + size_t(q) * ldc + ldr + i] : 0.0};
-            const int64_t e = stgmg::sym_slot_elem(nr, f32 ? 2 : 1, std::max(i, q), std::min(i, q));
+            const int64_t e = stgmg::sym_slot_elem(nr, tpu, std::max(i, q), std::min(i, q));
             std::complex<double> x(st[off + e], c ? st[off + ntl * 64 + e] : 0.0);
             if (i >= nU) x *= mu2;
             if (q >= nU) x *= mu1;
@@ -1702,7 +1744,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
     if (restart < 1 || restart > 100) throw ApiError(STGMG_ERR_INVALID_ARG, "restart out of range");
     const stgmg_params& p = *params;
     const int L = p.levels - 1, d = p.dim;
-    const int64_t w = p.smoother_prec == STGMG_FP32 ? 4 : 8;
+    const int64_t w = int64_t(value_bytes(p.smoother_prec));
     int64_t res = 0, temp_peak = 0, n_prev = 0, n_fine = 0;
     int nreal = 0, ncplx = 0;
     bool sym_ok = true;  // real kept eigenvalues > 0
@@ -1745,7 +1787,9 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
           const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
                               stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
           const bool sym = red_sym_used(p, sym_ok, int(S.max_nr));
-          const int64_t tiles = p.smoother_prec == STGMG_FP32 ? S.sum_tiles2 : S.sum_tiles;
+          const int64_t tiles = p.smoother_prec == STGMG_BF16   ? S.sum_tiles4
+                                : p.smoother_prec == STGMG_FP32 ? S.sum_tiles2
+                                                                : S.sum_tiles;
           res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
                                     (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
@@ -1821,7 +1865,7 @@ stgmg_status stgmg_profile_get(stgmg_handle* h, int32_t what, int64_t* launches,
     const LevelDev& F = h->lv[h->L];
     double bytes = 0.0;
     if (what == STGMG_PROF_PATCH_APPLY) {
-      const double w = h->prm.smoother_prec == STGMG_FP32 ? 4.0 : 8.0;
+      const double w = double(value_bytes(h->prm.smoother_prec));
       const double sum_np = F.npatch ? double(F.poff_h[F.npatch]) : 0.0;
       bytes = w * F.alg_inv_entries + 16.0 * sum_np;
     } else {

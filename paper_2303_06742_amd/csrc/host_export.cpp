@@ -154,6 +154,7 @@ void stgmg_host_sizes(int d, int r, int k, int N, int patch_kind, long long* out
   out[15] = S.sum_tiles2;
   out[16] = S.nodeQQ;
   out[17] = S.nodeQP;
+  out[18] = S.sum_tiles4;
 }
 
 // Node-pair form of the velocity rows of the last built level (NodeOp): returns the number of

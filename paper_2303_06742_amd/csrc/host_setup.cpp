@@ -1702,6 +1702,7 @@ LevelSizes level_sizes(int d, int r, int k, int N, int patch_kind, bool disc, bo
     S.sum_nr2 += mult * nr * nr;
     S.sum_tiles += mult * sym_tiles(int(nr));
     S.sum_tiles2 += mult * sym_slots(int(nr), 2);
+    S.sum_tiles4 += mult * sym_slots(int(nr), 4);
     S.max_nr = std::max<int>(S.max_nr, int(nr));
     S.max_nn = std::max<int>(S.max_nn, int(q));
   }

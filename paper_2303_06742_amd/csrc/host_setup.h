@@ -155,6 +155,7 @@ struct LevelSizes {
   int64_t sum_nr2 = 0;        // sum of nr^2
   int64_t sum_tiles = 0;      // sum of sym_tiles(nr): 64-value tiles of the symmetric storage (FP64)
   int64_t sum_tiles2 = 0;     // sum of sym_slots(nr, 2): the same with the FP32 pairing
+  int64_t sum_tiles4 = 0;     // sum of sym_slots(nr, 4): the same with four BF16 tiles per unit
   int max_nr = 0, max_nn = 0;
   int64_t nP = 0;
   int64_t nnzCface = 0;  // Problem B.1: nonzeros of the boundary part of C (LevelHost::Cface)

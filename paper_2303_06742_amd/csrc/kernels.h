@@ -130,6 +130,23 @@ void k_pack_red_sym_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb
                         const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, double* out);
 void k_pack_red_sym_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
                         const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, float* out);
+// BF16 storage (__bf16 values; the reduced solves with symmetric tiles only, four tiles per 8-byte
+// unit): the same kernels as the FP32 variants above.
+void k_gj_invert_bf16(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, __bf16* out,
+                      int32_t* status);
+void k_gj_lds_bf16(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                   __bf16* out, int32_t* status);
+void k_form_reduced_blocks_bf16(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes,
+                                int max_ns, int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
+                                const double* wkk, const GjDesc* desc, double* W, __bf16* out);
+void k_fold_reduced_bf16(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
+                         const int32_t* nu_of, const GjDesc* desc, int dstride, __bf16* out);
+void k_pack_red_sym_bf16(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
+                         const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, __bf16* out);
+void k_patch_apply_red_bf16(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
+                            int waves, const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                            const int32_t* tpos, const int32_t* pnu, const int64_t* ioff, const __bf16* inv,
+                            const double* r, double* y);
 // Block size used by the patch GEMV for patches of at most max_np rows.
 int patch_apply_threads(int max_np, bool fp32);
 void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,

@@ -1029,7 +1029,7 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
   const int nU = nu_of[i], nr = nr_of[i], ldr = inv_ld(nr);
   const bool cp = tb.cplx[a] != 0;
   const int ldc = cp ? 2 * ldr : ldr;
-  constexpr int P = sizeof(T) == 4 ? 2 : 1;  // tiles interleaved per unit (tile_layout.h)
+  constexpr int P = 8 / int(sizeof(T));  // tiles interleaved per unit (tile_layout.h)
   const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr), ntf2 = sym_full_slots(nr, P);
   const int nsl = sym_slots(nr, P), Ilast = sym_nbk(nr) - 1;
   double m1r, m1i, m2r, m2i;
@@ -1088,8 +1088,10 @@ template <typename T, bool NTL>
 __device__ inline T bld1(__amdgpu_buffer_rsrc_t rs, int voff) {
   if constexpr (sizeof(T) == 8)
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, NTL ? 2 : 0));
-  else
+  else if constexpr (sizeof(T) == 4)
     return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, 0, NTL ? 2 : 0));
+  else
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(rs, voff, 0, NTL ? 2 : 0));
 }
 
 template <typename V, bool NTL>
@@ -1139,11 +1141,18 @@ template <typename T, bool NTL>
 __device__ inline void bld_unit(__amdgpu_buffer_rsrc_t rs, int voff, T* out) {
   if constexpr (sizeof(T) == 8) {
     out[0] = bld1<T, NTL>(rs, voff);
-  } else {
+  } else if constexpr (sizeof(T) == 4) {
     typedef float F2 __attribute__((ext_vector_type(2)));
     const F2 v = __builtin_bit_cast(F2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, NTL ? 2 : 0));
     out[0] = v.x;
     out[1] = v.y;
+  } else {
+    typedef __bf16 B4 __attribute__((ext_vector_type(4)));
+    const B4 v = __builtin_bit_cast(B4, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, 0, NTL ? 2 : 0));
+    out[0] = v.x;
+    out[1] = v.y;
+    out[2] = v.z;
+    out[3] = v.w;
   }
 }
 
@@ -1160,7 +1169,7 @@ __device__ inline void bld_unit(__amdgpu_buffer_rsrc_t rs, int voff, T* out) {
 template <typename T, bool NTL, bool CP>
 __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int nh, const double* zt, int ldt,
                                        double* y, int w, int nw) {
-  constexpr int P = sizeof(T) == 4 ? 2 : 1;  // tiles per unit: one 8-byte load per lane
+  constexpr int P = 8 / int(sizeof(T));  // tiles per unit: one 8-byte load per lane
   constexpr int UB = 8 / P;                  // units per batch of 8 tiles
   const int lane = threadIdx.x & 63, rr = lane & 7, cc = lane >> 3;
   const double* zr = zt;
@@ -1416,7 +1425,7 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
     // W waves: wave w's products at tv + w * 2 nblk LDT ([a][re, im][LDT], the partial images
     // the back-transform sums), then D1 z shared by all waves
     const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr);
-    const int nsl = sym_slots(nr, sizeof(T) == 4 ? 2 : 1);  // stored tiles per plane
+    const int nsl = sym_slots(nr, 8 / int(sizeof(T)));  // stored tiles per plane
     const int wv_i = threadIdx.x >> 6;
     double* tt = tv;
     double* zt = tv + int64_t(W) * 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
@@ -2055,6 +2064,10 @@ void k_gj_invert_f32(hipStream_t st, int nb, int64_t count, int max_n, const GjD
                      int32_t* status) {
   if (count) gj_launch<float>(st, nb, count, max_n, desc, W, out, status);
 }
+void k_gj_invert_bf16(hipStream_t st, int nb, int64_t count, int max_n, const GjDesc* desc, double* W, __bf16* out,
+                      int32_t* status) {
+  if (count) gj_launch<__bf16>(st, nb, count, max_n, desc, W, out, status);
+}
 
 int patch_apply_threads(int max_np, bool fp32) {
   const int rpt = fp32 ? 4 : 2;
@@ -2238,15 +2251,19 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
 #undef STGMG_SYM
     return;
   }
-  if constexpr (sizeof(T) == 4) {
-    if (rr == 4) {
-      if (ntl) STGMG_RED(4, true);
-      else STGMG_RED(4, false);
-      return;
+  if constexpr (sizeof(T) == 2) {
+    return;  // BF16 storage uses the symmetric tiles only (the setup makes sure of it)
+  } else {
+    if constexpr (sizeof(T) == 4) {
+      if (rr == 4) {
+        if (ntl) STGMG_RED(4, true);
+        else STGMG_RED(4, false);
+        return;
+      }
     }
+    if (ntl) STGMG_RED(2, true);
+    else STGMG_RED(2, false);
   }
-  if (ntl) STGMG_RED(2, true);
-  else STGMG_RED(2, false);
 #undef STGMG_RED
 }
 
@@ -2262,6 +2279,12 @@ void k_patch_apply_red_f32(hipStream_t st, int64_t npatch, int max_np, int max_n
                            const double* r, double* y) {
   launch_red<float>(st, npatch, max_np, max_nu, max_nr, sym, waves, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
 }
+void k_patch_apply_red_bf16(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym,
+                            int waves, const TimeBlockConsts& tb, int d, const int64_t* poff, const int32_t* pdof,
+                            const int32_t* tpos, const int32_t* pnu, const int64_t* ioff, const __bf16* inv,
+                            const double* r, double* y) {
+  launch_red<__bf16>(st, npatch, max_np, max_nu, max_nr, sym, waves, tb, d, poff, pdof, tpos, pnu, ioff, inv, r, y);
+}
 
 void k_pack_red_sym_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
                         const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, double* out) {
@@ -2273,6 +2296,12 @@ void k_pack_red_sym_f32(hipStream_t st, int64_t count, const TimeBlockConsts& tb
                         const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, float* out) {
   if (count == 0) return;
   hipLaunchKernelGGL(dev::pack_red_sym_kernel<float>, dim3(count * tb.nblk), dim3(256), 0, st, tb, nu_of, nr_of, soff,
+                     toff, sq, out);
+}
+void k_pack_red_sym_bf16(hipStream_t st, int64_t count, const TimeBlockConsts& tb, const int32_t* nu_of,
+                         const int32_t* nr_of, const int64_t* soff, const int64_t* toff, const double* sq, __bf16* out) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(dev::pack_red_sym_kernel<__bf16>, dim3(count * tb.nblk), dim3(256), 0, st, tb, nu_of, nr_of, soff,
                      toff, sq, out);
 }
 
@@ -2291,6 +2320,10 @@ void k_fold_reduced_f64(hipStream_t st, int64_t count, int d, int max_nu, int ma
 void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
                         const int32_t* nu_of, const GjDesc* desc, int dstride, float* out) {
   launch_fold<float>(st, count, d, max_nu, max_npr, ns_of, nu_of, desc, dstride, out);
+}
+void k_fold_reduced_bf16(hipStream_t st, int64_t count, int d, int max_nu, int max_npr, const int32_t* ns_of,
+                         const int32_t* nu_of, const GjDesc* desc, int dstride, __bf16* out) {
+  launch_fold<__bf16>(st, count, d, max_nu, max_npr, ns_of, nu_of, desc, dstride, out);
 }
 
 size_t gj_lds_kernel_bytes(int max_n, bool cplx) {
@@ -2321,6 +2354,10 @@ void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjD
                   float* out, int32_t* status) {
   gj_lds_launch<float>(st, cplx, count, max_n, desc, W, out, status);
 }
+void k_gj_lds_bf16(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
+                   __bf16* out, int32_t* status) {
+  gj_lds_launch<__bf16>(st, cplx, count, max_n, desc, W, out, status);
+}
 
 void k_form_reduced_blocks_f64(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes, int max_ns,
                                int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
@@ -2337,6 +2374,14 @@ void k_form_reduced_blocks_f32(hipStream_t st, int64_t count, const TimeBlockCon
   const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (4 * int64_t(max_nr) * max_nr + 255) / 256));
   hipLaunchKernelGGL(dev::form_reduced_blocks_kernel<float>, dim3(count * (tb.nblk + 2), gx), dim3(256), 0, st, tb, d,
                      cplanes, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
+}
+void k_form_reduced_blocks_bf16(hipStream_t st, int64_t count, const TimeBlockConsts& tb, int d, int cplanes,
+                                int max_ns, int max_nr, const int32_t* ns_of, const int32_t* nu_of, const double* wmm,
+                                const double* wkk, const GjDesc* desc, double* W, __bf16* out) {
+  if (count == 0) return;
+  const int64_t gx = std::max<int64_t>(1, std::min<int64_t>(16, (4 * int64_t(max_nr) * max_nr + 255) / 256));
+  hipLaunchKernelGGL(dev::form_reduced_blocks_kernel<__bf16>, dim3(count * (tb.nblk + 2), gx), dim3(256), 0, st, tb,
+                     d, cplanes, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
 }
 
 void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d) {

@@ -47,12 +47,12 @@ def csr(lib, which, nrows):
 
 
 def sizes(lib, d, r, k, N, kind):
-    out = np.zeros(18, dtype=np.int64)
+    out = np.zeros(19, dtype=np.int64)
     lib.stgmg_host_sizes.argtypes = [ctypes.c_int] * 5 + [ctypes.c_void_p]
     lib.stgmg_host_sizes(d, r, k, N, kind, ptr(out))
     return dict(zip(['n', 'nnzA', 'nnzMM', 'nnzP', 'npatch', 'sum_np', 'sum_np_ld', 'max_np', 'nnzKK',
                     'sum_red_fixed', 'sum_nr_ldr', 'max_nr', 'max_nn', 'nnzCface', 'sum_tiles', 'sum_tiles2',
-                    'nodeQQ', 'nodeQP'], out.tolist()))
+                    'nodeQQ', 'nodeQP', 'sum_tiles4'], out.tolist()))
 
 
 def node_op(lib, nQ, d):

@@ -123,7 +123,7 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
     MM, KK, poff, pdof, nv, ns = build(d, N, k, kind)
     S = hostlib.sizes(LIB, d, r, k, N, 1 if kind == 'vertex' else 0)
     ld4 = lambda v: (v + 3) // 4 * 4
-    fixed = nrl = max_nr = max_nn = tiles = tiles2 = 0
+    fixed = nrl = max_nr = max_nn = tiles = tiles2 = tiles4 = 0
     for p in range(len(poff) - 1):
         nsp = (poff[p + 1] - poff[p]) // (k + 1)
         nU = int(np.sum(pdof[poff[p]:poff[p] + nsp] < nv))
@@ -133,9 +133,10 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
         nrl += nr * ld4(nr)
         tiles += len(tile_blocks(nr))
         tiles2 += len(pair_tiles(np.zeros(64 * len(tile_blocks(nr))), nr, 2)) // 64
+        tiles4 += len(pair_tiles(np.zeros(64 * len(tile_blocks(nr))), nr, 4)) // 64
         max_nr, max_nn = max(max_nr, nr), max(max_nn, nn)
     assert (S['sum_red_fixed'], S['sum_nr_ldr'], S['max_nr'], S['max_nn']) == (fixed, nrl, max_nr, max_nn)
-    assert S['sum_tiles'] == tiles and S['sum_tiles2'] == tiles2
+    assert S['sum_tiles'] == tiles and S['sum_tiles2'] == tiles2 and S['sum_tiles4'] == tiles4
 
 
 def sym_factors(lam):
@@ -167,7 +168,7 @@ def pack_tiles(X, nr):
 
 
 def pair_tiles(tiles, nr, P):
-    """The storage order with P tiles interleaved per unit (P = 2 for FP32 values): the 8x8 and
+    """The storage order with P tiles interleaved per unit (P = 2 for FP32, 4 for BF16 values): the 8x8 and
     the 4x16 tile counts each padded with zero tiles to a multiple of P, then entry e of slot t
     at (t // P * 64 + e) * P + t % P."""
     blocks = tile_blocks(nr)
@@ -192,11 +193,11 @@ def tile_apply(tiles, nr, zt):
     return y
 
 
-@pytest.mark.parametrize("P", [1, 2])
+@pytest.mark.parametrize("P", [1, 2, 4])
 @pytest.mark.parametrize("nr", [1, 5, 8, 9, 12, 13, 16, 18, 20, 21, 27, 29, 36, 40, 59, 60, 61, 64, 84, 89, 100])
 def test_tile_layout_positions(nr, P):
     """The kernels' and the readback's position of X[row][col] (tile_layout.h) is the position
-    of that entry in pack_tiles (P = 1) and in its FP32 pairing (P = 2); every stored tile is 64
+    of that entry in pack_tiles (P = 1) and in its FP32 and BF16 interleavings (P = 2, 4); every stored tile is 64
     values, and the 4x16 tiles are used exactly when the last block row holds at most 4 rows and
     the block rows are even."""
     X = np.arange(nr * nr, dtype=float).reshape(nr, nr)
