@@ -497,7 +497,8 @@ void smooth(stgmg_handle* h, int l, const double* b, double* d, int sweeps, bool
       ProfScope ps(h, STGMG_PROF_PATCH_APPLY, l);
       launch_patch_apply(h, L, r);
     }
-    stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.winv.p, L.y.p, d);
+    // a sweep from d = 0 writes d instead of adding to it (0 + x = x: the same values)
+    stgmg::k_vanka_update(h->st, L.n, L.tptr.p, L.winv.p, L.y.p, d, j == 0 && zero_start);
   }
 }
 
@@ -509,7 +510,7 @@ void vcycle(stgmg_handle* h, int l, const double* b, double* d) {
   LevelDev& L = h->lv[l];
   LevelDev& C = h->lv[l - 1];
   const int J = h->prm.n_smooth;
-  stgmg::k_fill_zero(h->st, d, L.n);
+  if (J == 0) stgmg::k_fill_zero(h->st, d, L.n);  // else the first sweep writes d
   smooth(h, l, b, d, J, true);
   op_apply(h, l, 1, d, b, L.r.p);
   L.R.apply(h->st, 0, L.r.p, nullptr, C.b.p);

@@ -154,7 +154,9 @@ void k_patch_apply_f64(hipStream_t st, int64_t npatch, int max_np, const int64_t
 void k_patch_apply_f32(hipStream_t st, int64_t npatch, int max_np, const int64_t* poff, const int32_t* pdof, const int32_t* tpos,
                        const int64_t* ioff, const float* inv, const double* r, double* y);
 // patch images y stored dof-major (slots [tptr[mu], tptr[mu + 1]) of dof mu): d += winv (sum of the slots)
-void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d);
+// assign: d = winv (sum of the slots) instead (the first sweep from d = 0, which needs no zero fill)
+void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d,
+                    bool assign = false);
 // y = X b for a dense inverse in the padded column layout; part holds dense_gemv_chunks(n) * n doubles
 int dense_gemv_chunks(int n);
 void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, double* part, double* y);

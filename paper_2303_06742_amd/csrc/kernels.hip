@@ -1656,13 +1656,17 @@ __global__ void __launch_bounds__(256) fold_reduced_kernel(int d, const int32_t*
 // d[mu] += winv[mu] * sum of the patch images of mu, stored dof-major: the patch kernels write
 // the image of patch entry (p, l) at tpos[poff[p] + l], and the slots of mu are
 // [tptr[mu], tptr[mu + 1]) in patch order.
+template <bool ASSIGN>  // ASSIGN: d = winv (sum of the slots), for a sweep from d = 0
 __global__ void vanka_update_kernel(int64_t n, const int64_t* __restrict__ tptr, const double* __restrict__ winv,
                                     const double* __restrict__ y, double* __restrict__ d) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
   for (int64_t t = tptr[i]; t < tptr[i + 1]; ++t) s += y[t];
-  d[i] += winv[i] * s;
+  if (ASSIGN)
+    d[i] = winv[i] * s;
+  else
+    d[i] += winv[i] * s;
 }
 
 // ---------------------------------------------------------------- dense coarse solve
@@ -2384,9 +2388,14 @@ void k_form_reduced_blocks_bf16(hipStream_t st, int64_t count, const TimeBlockCo
                      d, cplanes, max_ns, ns_of, nu_of, wmm, wkk, desc, W, out);
 }
 
-void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d) {
+void k_vanka_update(hipStream_t st, int64_t n, const int64_t* tptr, const double* winv, const double* y, double* d,
+                    bool assign) {
   if (n == 0) return;
-  hipLaunchKernelGGL(dev::vanka_update_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tptr, winv, y, d);
+  if (assign)
+    hipLaunchKernelGGL(dev::vanka_update_kernel<true>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tptr, winv, y, d);
+  else
+    hipLaunchKernelGGL(dev::vanka_update_kernel<false>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, tptr, winv, y,
+                       d);
 }
 
 int dense_gemv_chunks(int n) { return (n + dev::GEMV_COLS - 1) / dev::GEMV_COLS; }
