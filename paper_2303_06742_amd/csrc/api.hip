@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -537,9 +538,23 @@ int64_t test_zero_patch() {
   return e ? std::atoll(e) : -1;
 }
 
+// Wall time of the setup phases (host assembly, node-pair extraction, coarse inverse, transfers,
+// patch solves), printed to stderr when STGMG_SETUP_TIMES is set.
+struct SetupClock {
+  using C = std::chrono::steady_clock;
+  C::time_point t = C::now();
+  double sec[5] = {0, 0, 0, 0, 0};  // assembly, node pairs, coarse, transfers, patch solves
+  void lap(int phase) {
+    const C::time_point u = C::now();
+    sec[phase] += std::chrono::duration<double>(u - t).count();
+    t = u;
+  }
+};
+
 void build(stgmg_handle* h) {
   const stgmg_params& p = h->prm;
   const int64_t zero_patch = test_zero_patch();
+  SetupClock clk;
   const int d = p.dim, L = p.levels - 1;
   h->L = L;
   h->mat = {p.rho, p.lambda, p.mu, p.alpha, p.c0};
@@ -617,6 +632,7 @@ void build(stgmg_handle* h) {
                           l == 0 || !h->tb, p.pressure == STGMG_PRESSURE_DISC, p.form == STGMG_FORM_DTU,
                           p.form == STGMG_FORM_DTU && l == L};
     stgmg::build_level(o, h->mat, Kl[l], H, nth);
+    clk.lap(0);
     LevelDev& D = h->lv[l];
     D.N = H.N;
     D.n = H.n;
@@ -643,6 +659,7 @@ void build(stgmg_handle* h) {
                           double(H.MM.ptr[H.ns] - H.MM.ptr[pr0] + H.KK.ptr[H.ns] - H.KK.ptr[pr0]);
         HIPCHK(hipStreamSynchronize(h->st));  // the host arrays of `no` are freed at the end of this block
       }
+      clk.lap(1);
     }
     if (l == L && p.form == STGMG_FORM_DTU) h->cface.upload(H.Cface, h->st, ctr);
     {
@@ -707,6 +724,7 @@ void build(stgmg_handle* h) {
       HIPCHK(hipMemcpyAsync(&s, stat.p, sizeof(int32_t), hipMemcpyDeviceToHost, h->st));
       HIPCHK(hipStreamSynchronize(h->st));
       if (s) throw ApiError(STGMG_ERR_SINGULAR_PATCH, "coarse operator is singular");
+      clk.lap(2);
     }
     if (l >= 1) {
       stgmg::Csr P = stgmg::build_prolongation(prev, H, nth);
@@ -722,6 +740,8 @@ void build(stgmg_handle* h) {
           }
         D.R.upload(stgmg::transpose_block_diag(P, H.n, rb, cb, nth), h->st, ctr);
       }
+      HIPCHK(hipStreamSynchronize(h->st));
+      clk.lap(3);
       // patches
       D.npatch = H.npatch;
       D.poff_h = H.poff;
@@ -1099,6 +1119,7 @@ void build(stgmg_handle* h) {
         if (st_h[q])
           throw ApiError(STGMG_ERR_SINGULAR_PATCH,
                          "patch " + std::to_string(q) + " of level " + std::to_string(l) + " is singular");
+      clk.lap(4);
     }
     if (l == L) {
       h->fine_info = H;
@@ -1145,6 +1166,12 @@ void build(stgmg_handle* h) {
   h->tdev.alloc(p.k + 1, ctr, h->st);
   HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&h->hhost), 512 * sizeof(double), hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(h->st));
+  clk.lap(0);
+  if (std::getenv("STGMG_SETUP_TIMES"))
+    std::fprintf(stderr,
+                 "[stgmg setup] assembly and uploads %.3f s, node pairs %.3f s, coarse inverse %.3f s, transfers "
+                 "%.3f s, patch solves %.3f s\n",
+                 clk.sec[0], clk.sec[1], clk.sec[2], clk.sec[3], clk.sec[4]);
 }
 
 // FGMRES workspace of restart length m on n unknowns: the bases V (m+1 vectors) and Z (m), the

@@ -1247,10 +1247,13 @@ bool build_node_op(const LevelHost& L, NodeOp& out, int nthreads) {
   o.a.assign(size_t(cnt[nQ]) * d * d, 0.0);
   o.ccol.resize(size_t(ccnt[nQ]));
   o.c.assign(size_t(ccnt[nQ]) * d, 0.0);
-  // fill, checking every velocity row against the structure
+  // fill, checking every velocity row against the structure; the position of a neighbour node
+  // (pressure dof) in the node's list is looked up in a per-thread table, reset after each node
   parallel_for(nQ, nthreads, [&](int64_t i0, int64_t i1) {
     NodeList nodes;
     std::vector<int32_t> pcols;
+    std::vector<int32_t> at(size_t(nQ), -1), atp(size_t(np), -1);
+    auto find = [&](const NodeList&, int32_t j) -> int64_t { return (j >= 0 && j < nQ) ? at[size_t(j)] : -1; };
     for (int64_t i = i0; i < i1; ++i) {
       node_list(i, nodes, pcols);
       const int64_t e0 = o.ptr[i], c0 = o.cptr[i];
@@ -1258,8 +1261,12 @@ bool build_node_op(const LevelHost& L, NodeOp& out, int nthreads) {
       for (int64_t t = 0; t < nn; ++t) {
         o.col[size_t(e0 + t)] = nodes[size_t(t)].first;
         o.m[size_t(e0 + t)] = nodes[size_t(t)].second;
+        at[size_t(nodes[size_t(t)].first)] = int32_t(t);
       }
-      for (size_t t = 0; t < pcols.size(); ++t) o.ccol[size_t(c0) + t] = pcols[t];
+      for (size_t t = 0; t < pcols.size(); ++t) {
+        o.ccol[size_t(c0) + t] = pcols[t];
+        atp[size_t(pcols[t])] = int32_t(t);
+      }
       // the rows of one kind (which CSR, which row block) must hold sign * rhoM_ij at the
       // column (col_block + d j + c) for every listed node j and nothing else
       auto mass_rows = [&](const Csr& A, int64_t row, int64_t col0, double sign) {
@@ -1296,13 +1303,14 @@ bool build_node_op(const LevelHost& L, NodeOp& out, int nthreads) {
             }
             o.a[size_t(e0 + t) * d * d + size_t(c) * d + size_t((cl - nv) % d)] = v;
           } else if (cl >= 2 * nv && cl < 2 * nv + np) {
-            const auto it = std::lower_bound(pcols.begin(), pcols.end(), int32_t(cl - 2 * nv));
-            o.c[size_t(c0 + (it - pcols.begin())) * d + c] = v;
+            o.c[size_t(c0 + atp[size_t(cl - 2 * nv)]) * d + c] = v;
           } else if (v != 0.0) {
             bad[i] = 1;
           }
         }
       }
+      for (int64_t t = 0; t < nn; ++t) at[size_t(nodes[size_t(t)].first)] = -1;
+      for (size_t t = 0; t < pcols.size(); ++t) atp[size_t(pcols[t])] = -1;
     }
   });
   for (int64_t i = 0; i < nQ; ++i)

@@ -86,6 +86,10 @@ CONFIGS = {
     'c1_b1_tb': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-tb', form='dtu', time_blocks=1),
     'c1_b1_full': W.scaled(W.C1, 2, name='2d-8x8-dg1-cell-b1-full', form='dtu', time_blocks=0),
     'c3s_disc_b1': W.scaled(W.C3, 2, name='3d-8cube-q2p1disc-dg1-cell-lognormal-b1', pressure='disc', form='dtu'),
+    # the elements of Table C.1 (Q4^2/Q3) and Table 5.2 (Q4^2/P3^disc) with dG(3), 4x4 cells
+    # (2 levels from 2x2), cell patches; two complex eigenvalue pairs in time
+    'r4': W.scaled(W.C1, 2, name='2d-4x4-q4q3-dg3-cell', coarse_cells=2, r=4, k=3),
+    'r4_disc': W.scaled(W.C1, 2, name='2d-4x4-q4p3disc-dg3-cell', coarse_cells=2, r=4, k=3, pressure='disc'),
     # the benchmark's physics on 64^2 (5 levels): 4,225 finest patches, where the tiled patch solve
     # picks one wave per patch by itself (four on the coarser levels)
     'c2_64': W.scaled(W.C2, 5, name='2d-64x64-dg2-vertex'),

@@ -28,7 +28,7 @@ def rel_err(a, b, scale=None):
 
 KEYS = ['c1', 'c2s', 'c2s_cell', 'c3s', 'k0', 'k3', 'c3v', 'c1_full', 'c2s_full', 'c3s_full', 'c1_tb', 'c2s_tb',
         'c3s_tb', 'k0_tb', 'c1_disc', 'c2d', 'c3s_disc', 'c2d_full', 'c2s_b1', 'c1_b1_tb', 'c1_b1_full',
-        'c3s_disc_b1', 'c2s_red', 'c3s_red', 'k3_red', 'c3v_red', 'c2d_red', 'c2s_b1_red']
+        'c3s_disc_b1', 'c2s_red', 'c3s_red', 'k3_red', 'c3v_red', 'c2d_red', 'c2s_b1_red', 'r4', 'r4_disc']
 # configs whose patch solves use the symmetric tiles (time_blocks = 3): the tile kernel runs with one
 # wave per patch on large levels and four on small ones; both variants are compared with the oracle
 TILED = [k for k in KEYS if CONFIGS[k].time_blocks == 3]
