@@ -19,6 +19,7 @@ DEVICE = ['-Xclang', '-target-feature', '-Xclang', '-packed-fp32-ops']
 SOURCES = [
     ('host_setup.cpp', False),
     ('kernels.hip', True),
+    ('gj_mfma.hip', True),
     ('source.hip', True),
     ('api.hip', True),
     ('server.cpp', True),

@@ -339,11 +339,26 @@ size_t lds_per_block() {
 void vcycle(stgmg_handle* h, int l, const double* b, double* d);
 
 // reduced solves: all blocks of a level inverted by the kernel that holds a matrix in LDS
-bool red_blocks_in_lds(const stgmg::TimeBlockConsts& tb, int max_nr, int max_nn) {
+// Kernel that inverts the reduced blocks (the node mass block and the Schur complements):
+// RED_INV_LDS  the whole matrix in LDS (workgroup kernel, complex blocks in complex arithmetic),
+// RED_INV_MFMA the matrix in global memory, trailing updates on MFMA (complex arithmetic),
+// RED_INV_PANEL the panel kernel on the 2x2-block real form of complex blocks (used when neither
+//               fits, or through STGMG_GJ_KERNEL=panel for comparisons).
+enum { RED_INV_LDS = 0, RED_INV_MFMA = 1, RED_INV_PANEL = 2 };
+int red_inv_kernel(bool any_c, int max_nr, int max_nn) {
+  if (stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
+      stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block())
+    return RED_INV_LDS;
+  const char* e = std::getenv("STGMG_GJ_KERNEL");
+  if (e && std::string(e) == "panel") return RED_INV_PANEL;
+  if (stgmg::gj_mfma_bytes(max_nr, any_c) <= lds_per_block() && stgmg::gj_mfma_bytes(max_nn, false) <= lds_per_block())
+    return RED_INV_MFMA;
+  return RED_INV_PANEL;
+}
+int red_inv_kernel(const stgmg::TimeBlockConsts& tb, int max_nr, int max_nn) {
   bool any_c = false;
   for (int a = 0; a < tb.nblk; ++a) any_c = any_c || tb.cplx[a];
-  return stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
-         stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block();
+  return red_inv_kernel(any_c, max_nr, max_nn);
 }
 
 // symmetric tiles need real kept eigenvalues > 0 (real square roots); true for dG(k)
@@ -700,15 +715,17 @@ void build(stgmg_handle* h) {
       } else {
         // panels over many workgroups
         const int n0 = int(H.n), pnb = 32;
-        DArr<double> scl, Wb;
+        DArr<double> scl, Wb, P0, P1;
         DArr<int> perm, src;
         scl.alloc(n0, nullptr, h->st);
         Wb.alloc(int64_t(pnb) * n0, nullptr, h->st);
+        P0.alloc(int64_t(pnb) * n0, nullptr, h->st);
+        P1.alloc(int64_t(pnb) * n0, nullptr, h->st);
         perm.alloc(n0, nullptr, h->st);
         src.alloc(n0, nullptr, h->st);
         stgmg::k_gj_large_rowscale(h->st, n0, Wd.p, scl.p);
         for (int k0 = 0; k0 < n0; k0 += pnb)
-          stgmg::k_gj_large_step(h->st, n0, k0, std::min(pnb, n0 - k0), Wd.p, perm.p, Wb.p, stat.p);
+          stgmg::k_gj_large_step(h->st, n0, k0, std::min(pnb, n0 - k0), Wd.p, perm.p, P0.p, P1.p, Wb.p, stat.p);
         HIPCHK(hipGetLastError());
         std::vector<int> perm_h(n0), src_h(n0);
         HIPCHK(hipMemcpyAsync(perm_h.data(), perm.p, n0 * sizeof(int), hipMemcpyDeviceToHost, h->st));
@@ -748,7 +765,7 @@ void build(stgmg_handle* h) {
       D.pdof_h = H.pdof;
       D.ioff_h.assign(H.npatch + 1, 0);
       int max_np = 0;
-      bool red_in_lds = false;
+      int red_kernel = RED_INV_LDS;
       if (h->red) {
         D.pnu_h.assign(H.npatch, 0);
         for (int64_t q = 0; q < H.npatch; ++q) {
@@ -763,7 +780,7 @@ void build(stgmg_handle* h) {
           D.max_nr = std::max<int>(D.max_nr, int(nr));
           D.max_npr = std::max<int>(D.max_npr, int(nP));
         }
-        red_in_lds = red_blocks_in_lds(h->tbc, D.max_nr, D.max_nu / d);
+        red_kernel = red_inv_kernel(h->tbc, D.max_nr, D.max_nu / d);
         D.sym = red_sym_used(p, red_sym_possible(h->tbc), D.max_nr);
       }
       for (int64_t q = 0; q < H.npatch; ++q) {
@@ -865,19 +882,20 @@ void build(stgmg_handle* h) {
         const int max_ns = max_np / nt, max_nr = D.max_nr, max_nn = D.max_nu / d;
         bool any_c = false;
         for (int a = 0; a < nblk; ++a) any_c = any_c || h->tbc.cplx[a];
-        // blocks held entirely in LDS when they fit in one workgroup's LDS (complex blocks then
-        // inverted in complex arithmetic), else the panel kernel on the 2x2-block real form
-        const bool in_lds = red_in_lds;
+        // blocks held entirely in LDS when they fit in one workgroup's LDS, else in global memory
+        // with MFMA updates (both in complex arithmetic for complex blocks: real and imaginary
+        // planes), else the panel kernel on the 2x2-block real form
+        const bool in_lds = red_kernel == RED_INV_LDS, planes = red_kernel != RED_INV_PANEL;
         (void)any_c;
         int64_t per_patch = int64_t(max_nn) * max_nn;
         std::vector<int64_t> blk_woff(nblk);
         for (int a = 0; a < nblk; ++a) {
           blk_woff[a] = per_patch;
           const bool c = h->tbc.cplx[a] != 0;
-          per_patch += in_lds ? (c ? 2 : 1) * int64_t(max_nr) * max_nr : (c ? 4 : 1) * int64_t(max_nr) * max_nr;
+          per_patch += planes ? (c ? 2 : 1) * int64_t(max_nr) * max_nr : (c ? 4 : 1) * int64_t(max_nr) * max_nr;
         }
         const int max_n = std::max(any_c ? 2 * max_nr : max_nr, max_nn);
-        const int nb = in_lds ? 32 : stgmg::gj_panel_width(max_n, lds_limit());
+        const int nb = planes ? 32 : stgmg::gj_panel_width(max_n, lds_limit());
         if (nb == 0) throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the inversion kernel");
         if (stgmg::patch_apply_red_threads(max_nr, p.smoother_prec == STGMG_FP32) > 512 || D.max_nu > 64 * 32)
           throw ApiError(STGMG_ERR_UNSUPPORTED, "patch too large for the reduced patch solve");
@@ -918,7 +936,7 @@ void build(stgmg_handle* h) {
             int64_t so = i * sq_item;
             for (int a = 0; a < nblk; ++a) {
               const bool c = h->tbc.cplx[a] != 0;
-              const int n_in = c && !in_lds ? 2 * nr : nr;  // LDS kernel: complex n x n
+              const int n_in = c && !planes ? 2 * nr : nr;  // LDS and MFMA kernels: complex n x n
               dd[i * (nblk + 1) + 1 + a] = {n_in, nr, c ? 2 * ldr : ldr, c ? nr : 0, ldr,
                                             int32_t(p0 + i), i * per_patch + blk_woff[a], D.sym ? so : oo};
               if (D.sym) {
@@ -936,7 +954,7 @@ void build(stgmg_handle* h) {
           // blocks, real blocks, complex blocks
           std::vector<stgmg::GjDesc> grp;
           int64_t n_mass = 0, n_real = 0;
-          if (in_lds || D.sym) {
+          if (planes || D.sym) {
             for (int g = 0; g < 3; ++g)
               for (int64_t i = 0; i < cnt; ++i)
                 for (int sl = 0; sl <= nblk; ++sl) {
@@ -954,7 +972,7 @@ void build(stgmg_handle* h) {
           ddesc.emplace_back();
           ddesc.back().upload(descs[descs.size() - 2], h->st, nullptr);
           ddesc.emplace_back();
-          if (in_lds || D.sym) ddesc.back().upload(descs.back(), h->st, nullptr);
+          if (planes || D.sym) ddesc.back().upload(descs.back(), h->st, nullptr);
           const stgmg::GjDesc* dper = ddesc[ddesc.size() - 2].p;
           const stgmg::GjDesc* dgrp = ddesc.back().p;
           dns.emplace_back();
@@ -976,15 +994,34 @@ void build(stgmg_handle* h) {
           stgmg::k_fill_zero(h->st, wkk.p, cnt * sq);
           stgmg::k_patch_extract_spatial_t(h->st, p0, cnt, nt, max_ns, D.poff.p, D.pdof.p, D.MMs.ptr.p, D.MMs.col.p,
                                            D.MMs.val.p, D.KKs.ptr.p, D.KKs.col.p, D.KKs.val.p, wmm.p, wkk.p);
+          // the batched inversion of the planar layout: LDS or MFMA kernel
+          auto gj64 = [&](bool c, int64_t m, int mx, const stgmg::GjDesc* dsc, double* o) {
+            if (in_lds)
+              stgmg::k_gj_lds_f64(h->st, c, m, mx, dsc, Wb.p, o, stat.p);
+            else
+              stgmg::k_gj_mfma_f64(h->st, c, m, mx, dsc, Wb.p, o, stat.p);
+          };
+          auto gj32 = [&](bool c, int64_t m, int mx, const stgmg::GjDesc* dsc, float* o) {
+            if (in_lds)
+              stgmg::k_gj_lds_f32(h->st, c, m, mx, dsc, Wb.p, o, stat.p);
+            else
+              stgmg::k_gj_mfma_f32(h->st, c, m, mx, dsc, Wb.p, o, stat.p);
+          };
+          auto gj16 = [&](bool c, int64_t m, int mx, const stgmg::GjDesc* dsc, __bf16* o) {
+            if (in_lds)
+              stgmg::k_gj_lds_bf16(h->st, c, m, mx, dsc, Wb.p, o, stat.p);
+            else
+              stgmg::k_gj_mfma_bf16(h->st, c, m, mx, dsc, Wb.p, o, stat.p);
+          };
           if (p.smoother_prec == STGMG_BF16) {  // symmetric tiles only
-            stgmg::k_form_reduced_blocks_bf16(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
+            stgmg::k_form_reduced_blocks_bf16(h->st, cnt, h->tbc, d, planes ? 1 : 0, max_ns, max_nr, dns.back().p,
                                               dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv16.p);
             if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
               stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch, int64_t(max_nn) * max_nn);
-            if (in_lds) {
-              stgmg::k_gj_lds_bf16(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv16.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+            if (planes) {
+              gj16(false, n_mass, max_nn, dgrp, D.inv16.p);
+              gj64(false, n_real, max_nr, dgrp + n_mass, Sq.p);
+              gj64(true, n_cplx, max_nr, dgrp + n_mass + n_real, Sq.p);
             } else {
               stgmg::k_gj_invert_bf16(h->st, nb, n_mass, max_n, dgrp, Wb.p, D.inv16.p, stat.p);
               stgmg::k_gj_invert_f64(h->st, nb, n_real + n_cplx, max_n, dgrp + n_mass, Wb.p, Sq.p, stat.p);
@@ -994,14 +1031,14 @@ void build(stgmg_handle* h) {
             stgmg::k_fold_reduced_bf16(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, dper, nblk + 1,
                                        D.inv16.p);
           } else if (p.smoother_prec == STGMG_FP32) {
-            stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
+            stgmg::k_form_reduced_blocks_f32(h->st, cnt, h->tbc, d, planes ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv32.p);
             if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
               stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch, int64_t(max_nn) * max_nn);
-            if (in_lds && D.sym) {
-              stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+            if (planes && D.sym) {
+              gj32(false, n_mass, max_nn, dgrp, D.inv32.p);
+              gj64(false, n_real, max_nr, dgrp + n_mass, Sq.p);
+              gj64(true, n_cplx, max_nr, dgrp + n_mass + n_real, Sq.p);
               stgmg::k_pack_red_sym_f32(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
                                         dtoff.back().p, Sq.p, D.inv32.p);
             } else if (D.sym) {
@@ -1009,30 +1046,30 @@ void build(stgmg_handle* h) {
               stgmg::k_gj_invert_f64(h->st, nb, n_real + n_cplx, max_n, dgrp + n_mass, Wb.p, Sq.p, stat.p);
               stgmg::k_pack_red_sym_f32(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
                                         dtoff.back().p, Sq.p, D.inv32.p);
-            } else if (in_lds) {
-              stgmg::k_gj_lds_f32(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv32.p, stat.p);
-              stgmg::k_gj_lds_f32(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv32.p, stat.p);
-              stgmg::k_gj_lds_f32(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv32.p, stat.p);
+            } else if (planes) {
+              gj32(false, n_mass, max_nn, dgrp, D.inv32.p);
+              gj32(false, n_real, max_nr, dgrp + n_mass, D.inv32.p);
+              gj32(true, n_cplx, max_nr, dgrp + n_mass + n_real, D.inv32.p);
             } else {
               stgmg::k_gj_invert_f32(h->st, nb, cnt * (nblk + 1), max_n, dper, Wb.p, D.inv32.p, stat.p);
             }
             stgmg::k_fold_reduced_f32(h->st, cnt, d, D.max_nu, D.max_npr, dns.back().p, dnu.back().p, dper, nblk + 1,
                                       D.inv32.p);
           } else {
-            stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, in_lds ? 1 : 0, max_ns, max_nr, dns.back().p,
+            stgmg::k_form_reduced_blocks_f64(h->st, cnt, h->tbc, d, planes ? 1 : 0, max_ns, max_nr, dns.back().p,
                                              dnu.back().p, wmm.p, wkk.p, dper, Wb.p, D.inv64.p);
             if (l == L && zero_patch >= p0 && zero_patch < p0 + cnt)
               stgmg::k_fill_zero(h->st, Wb.p + (zero_patch - p0) * per_patch, int64_t(max_nn) * max_nn);
-            if (in_lds && D.sym) {
-              stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, Sq.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, Sq.p, stat.p);
+            if (planes && D.sym) {
+              gj64(false, n_mass, max_nn, dgrp, D.inv64.p);
+              gj64(false, n_real, max_nr, dgrp + n_mass, Sq.p);
+              gj64(true, n_cplx, max_nr, dgrp + n_mass + n_real, Sq.p);
               stgmg::k_pack_red_sym_f64(h->st, cnt, h->tbc, dnu.back().p, dnr.back().p, dsoff.back().p,
                                         dtoff.back().p, Sq.p, D.inv64.p);
-            } else if (in_lds) {
-              stgmg::k_gj_lds_f64(h->st, false, n_mass, max_nn, dgrp, Wb.p, D.inv64.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, false, n_real, max_nr, dgrp + n_mass, Wb.p, D.inv64.p, stat.p);
-              stgmg::k_gj_lds_f64(h->st, true, n_cplx, max_nr, dgrp + n_mass + n_real, Wb.p, D.inv64.p, stat.p);
+            } else if (planes) {
+              gj64(false, n_mass, max_nn, dgrp, D.inv64.p);
+              gj64(false, n_real, max_nr, dgrp + n_mass, D.inv64.p);
+              gj64(true, n_cplx, max_nr, dgrp + n_mass + n_real, D.inv64.p);
             } else if (D.sym) {
               stgmg::k_gj_invert_f64(h->st, nb, n_mass, max_n, dgrp, Wb.p, D.inv64.p, stat.p);
               stgmg::k_gj_invert_f64(h->st, nb, n_real + n_cplx, max_n, dgrp + n_mass, Wb.p, Sq.p, stat.p);
@@ -1797,7 +1834,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
       if (l == L && p.form == STGMG_FORM_DTU) res += (S.nP + 1) * 8 + S.nnzCface * 12;  // boundary part of C
       if (l == 0) {
         res += n * stgmg::inv_ld(int(n)) * 8 + int64_t(stgmg::dense_gemv_chunks(int(n))) * n * 8;
-        temp_peak = std::max(temp_peak, n * n * 8 + 32 * n * 8 + 3 * n * 8 + 64);
+        temp_peak = std::max(temp_peak, n * n * 8 + 3 * 32 * n * 8 + 3 * n * 8 + 64);  // W, Wb, two panels, scl, perm, src
       } else {
         res += (n + 1) * 8 + S.nnzP * 12 + (n_prev + 1) * 8 + S.nnzP * 12;
         // poff, ioff; pdof, tpos; tptr; winv; y
@@ -1812,15 +1849,14 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
                                               S.npatch * 4);
         } else if (p.time_blocks >= 2) {
           const int64_t max_ns = S.max_np / (p.k + 1), sq = max_ns * max_ns;
-          const bool in_lds = stgmg::gj_lds_kernel_bytes(S.max_nr, ncplx > 0) <= lds_per_block() &&
-                              stgmg::gj_lds_kernel_bytes(S.max_nn, false) <= lds_per_block();
+          const bool planes = red_inv_kernel(ncplx > 0, int(S.max_nr), int(S.max_nn)) != RED_INV_PANEL;
           const bool sym = red_sym_used(p, sym_ok, int(S.max_nr));
           const int64_t tiles = p.smoother_prec == STGMG_BF16   ? S.sum_tiles4
                                 : p.smoother_prec == STGMG_FP32 ? S.sum_tiles2
                                                                 : S.sum_tiles;
           res += (S.sum_red_fixed + (nreal + 2 * ncplx) * (sym ? tiles * 64 : S.sum_nr_ldr)) * w + S.npatch * 4;
           const int64_t per_patch = int64_t(S.max_nn) * S.max_nn +
-                                    (nreal + (in_lds ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
+                                    (nreal + (planes ? 2 : 4) * ncplx) * int64_t(S.max_nr) * S.max_nr;
           const int64_t sq_item = sym ? (nreal + 2 * ncplx) * int64_t(S.max_nr) * stgmg::inv_ld(S.max_nr) : 0;
           const int64_t batch = std::max<int64_t>(
               1, std::min<int64_t>(S.npatch, (int64_t(3) << 30) / ((per_patch + 2 * sq + sq_item) * 8)));

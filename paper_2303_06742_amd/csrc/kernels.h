@@ -104,6 +104,16 @@ void k_fold_reduced_f32(hipStream_t st, int64_t count, int d, int max_nu, int ma
 // k_gj_invert_*; cplx: input = real plane then imaginary plane of an n x n complex matrix,
 // output Re at column position j and Im at ldh + j).  LDS bytes per workgroup for size max_n:
 size_t gj_lds_kernel_bytes(int max_n, bool cplx);
+// Batched Gauss-Jordan of matrices in global memory (W, modified in place), one workgroup per
+// descriptor, trailing updates on MFMA; same input planes and output conventions as k_gj_lds_*.
+// gj_mfma_bytes: its LDS per workgroup.
+size_t gj_mfma_bytes(int max_n, bool cplx);
+void k_gj_mfma_f64(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, double* W, double* out,
+                   int32_t* status);
+void k_gj_mfma_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, double* W, float* out,
+                   int32_t* status);
+void k_gj_mfma_bf16(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, double* W, __bf16* out,
+                    int32_t* status);
 void k_gj_lds_f64(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
                   double* out, int32_t* status);
 void k_gj_lds_f32(hipStream_t st, bool cplx, int64_t count, int max_n, const GjDesc* desc, const double* W,
@@ -163,7 +173,9 @@ void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, do
 // Multi-workgroup Gauss-Jordan of one row-major n x n matrix (panels of nb <= 32 columns):
 // rowscale once, one step per panel, then the un-permuted, re-scaled output.
 void k_gj_large_rowscale(hipStream_t st, int n, double* M, double* scl);
-void k_gj_large_step(hipStream_t st, int n, int k0, int nb, double* M, int* perm, double* Wb, int32_t* status);
+// one panel of nb <= 32 columns at k0; P0 and P1: nb x n scratch (the panel, column-major), Wb: nb x n
+void k_gj_large_step(hipStream_t st, int n, int k0, int nb, double* M, int* perm, double* P0, double* P1,
+                     double* Wb, int32_t* status);
 void k_gj_large_output(hipStream_t st, int n, const double* M, const int* src, const double* scl, double* out);
 int dot_blocks(int64_t n);
 // out[v] (+)= V_v . w for v < m (V rows of length n, leading dimension ldv); partials >= m * dot_blocks(n)

@@ -1721,76 +1721,93 @@ __global__ void __launch_bounds__(1024) gj_large_rowscale_kernel(int n, double* 
   if (lane == 0) scl[i] = s;
 }
 
-__global__ void __launch_bounds__(1024) gj_large_panel_kernel(int n, int k0, int nb, double* __restrict__ M,
-                                                              int* __restrict__ perm, int32_t* __restrict__ status) {
-  __shared__ double rv[1024 / WAVE];
-  __shared__ int ri[1024 / WAVE];
+// One pivot column of the panel, over many workgroups.  The panel is held column-major
+// (P[c * n + i] = M[i][k0 + c]) in two buffers: every workgroup reads Pin only and writes its own
+// rows of Pout, so no workgroup can see a half-updated column.  Each workgroup repeats the pivot
+// search of column c over rows k..n-1 (the same rows and tie rule in every workgroup: the largest
+// scaled entry, ties to the lowest row), forms the new pivot row (the old row p divided by the
+// pivot, with 1/pivot in column c) and writes, for its rows i != k, the old row (row k's values
+// for i = p, the row swap) minus its column-c entry times the new pivot row (column c: 0 minus
+// it).  These are the same operations, in the same order per element, as one step of the
+// workgroup Gauss-Jordan kernels.
+__global__ void __launch_bounds__(256) gj_large_column_kernel(int n, int k0, int c, int nb,
+                                                              const double* __restrict__ Pin,
+                                                              double* __restrict__ Pout, int* __restrict__ perm,
+                                                              int32_t* __restrict__ status) {
+  __shared__ double rv[256 / WAVE];
+  __shared__ int ri[256 / WAVE];
+  __shared__ double prow[32];
   __shared__ int s_piv;
-  const int tid = threadIdx.x, bs = blockDim.x, wave = tid / WAVE, lane = tid % WAVE, nw = bs / WAVE;
-  for (int c = 0; c < nb; ++c) {
-    const int k = k0 + c;
-    double bv = -1.0;
-    int bi = n;
-    for (int i = k + tid; i < n; i += bs) {
-      const double v = fabs(M[int64_t(i) * n + k]);
-      if (v > bv) {
-        bv = v;
-        bi = i;
-      }
+  const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE, nw = blockDim.x / WAVE;
+  const int k = k0 + c;
+  const double* col = Pin + int64_t(c) * n;
+  double bv = -1.0;
+  int bi = n;
+  for (int i = k + tid; i < n; i += blockDim.x) {
+    const double v = fabs(col[i]);
+    if (v > bv) {
+      bv = v;
+      bi = i;
     }
-    for (int off = WAVE / 2; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      rv[wave] = bv;
-      ri[wave] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double v = rv[0];
-      int ii = ri[0];
-      for (int w = 1; w < nw; ++w)
-        if (rv[w] > v || (rv[w] == v && ri[w] < ii)) {
-          v = rv[w];
-          ii = ri[w];
-        }
-      if (!(v > 0.0) || !isfinite(v) || ii >= n) {
-        status[0] = 1;
-        ii = k;
-      }
-      perm[k] = ii;
-      s_piv = ii;
-    }
-    __syncthreads();
-    const int q = s_piv;
-    if (q != k && tid < nb) {
-      const double t = M[int64_t(k) * n + k0 + tid];
-      M[int64_t(k) * n + k0 + tid] = M[int64_t(q) * n + k0 + tid];
-      M[int64_t(q) * n + k0 + tid] = t;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double piv = M[int64_t(k) * n + k];
-      if (piv == 0.0 || !isfinite(piv)) piv = 1.0;
-      const double rp = 1.0 / piv;
-      M[int64_t(k) * n + k] = 1.0;
-      for (int cc = 0; cc < nb; ++cc) M[int64_t(k) * n + k0 + cc] *= rp;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += bs) {
-      if (i == k) continue;
-      double* row = M + int64_t(i) * n + k0;
-      const double f = row[c];
-      row[c] = 0.0;
-      for (int cc = 0; cc < nb; ++cc) row[cc] -= f * M[int64_t(k) * n + k0 + cc];
-    }
-    __syncthreads();
   }
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  if (lane == 0) {
+    rv[wave] = bv;
+    ri[wave] = bi;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double v = rv[0];
+    int ii = ri[0];
+    for (int w = 1; w < nw; ++w)
+      if (rv[w] > v || (rv[w] == v && ri[w] < ii)) {
+        v = rv[w];
+        ii = ri[w];
+      }
+    const bool bad = !(v > 0.0) || !isfinite(v) || ii >= n;
+    if (bad) ii = k;
+    if (blockIdx.x == 0) {
+      perm[k] = ii;
+      if (bad) status[0] = 1;
+    }
+    s_piv = ii;
+  }
+  __syncthreads();
+  const int p = s_piv;
+  double piv = col[p];
+  if (piv == 0.0 || !isfinite(piv)) piv = 1.0;
+  const double rp = 1.0 / piv;
+  if (tid < nb) prow[tid] = (tid == c ? 1.0 : Pin[int64_t(tid) * n + p]) * rp;
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + tid;
+  if (i >= n) return;
+  if (i == k) {
+    for (int cc = 0; cc < nb; ++cc) Pout[int64_t(cc) * n + i] = prow[cc];
+    return;
+  }
+  const int s = i == p ? k : i;
+  const double f = Pin[int64_t(c) * n + s];
+  for (int cc = 0; cc < nb; ++cc)
+    Pout[int64_t(cc) * n + i] = (cc == c ? 0.0 : Pin[int64_t(cc) * n + s]) - f * prow[cc];
+}
+
+// P[c * n + i] = M[i][k0 + c] (to_panel) or back
+__global__ void gj_large_panel_copy_kernel(int n, int k0, int nb, double* __restrict__ M, double* __restrict__ P,
+                                           int to_panel) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= nb) return;
+  if (to_panel)
+    P[int64_t(c) * n + i] = M[int64_t(i) * n + k0 + c];
+  else
+    M[int64_t(i) * n + k0 + c] = P[int64_t(c) * n + i];
 }
 
 // columns outside the panel: apply the row swaps of this panel, copy the pivot rows to Wb[c][j]
@@ -1809,16 +1826,17 @@ __global__ void gj_large_swap_kernel(int n, int k0, int nb, double* __restrict__
   for (int c = 0; c < nb; ++c) Wb[int64_t(c) * n + j] = M[int64_t(k0 + c) * n + j];
 }
 
-// M[i][j] = [i not in panel rows] M[i][j] + sum_c M[i][k0+c] Wb[c][j], j outside the panel
+// M[i][j] = [i not in panel rows] M[i][j] + sum_c P[c][i] Wb[c][j], j outside the panel
 constexpr int GJL_ROWS = 128;
 __global__ void __launch_bounds__(256) gj_large_update_kernel(int n, int k0, int nb, double* __restrict__ M,
+                                                              const double* __restrict__ P,
                                                               const double* __restrict__ Wb) {
   __shared__ double pn[GJL_ROWS * 32];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i0 = blockIdx.y * GJL_ROWS, i1 = min(n, i0 + GJL_ROWS);
   for (int t = threadIdx.x; t < (i1 - i0) * nb; t += blockDim.x) {
-    const int i = t / nb, c = t % nb;
-    pn[i * 32 + c] = M[int64_t(i0 + i) * n + k0 + c];
+    const int c = t / (i1 - i0), i = t % (i1 - i0);
+    pn[i * 32 + c] = P[int64_t(c) * n + i0 + i];
   }
   __syncthreads();
   if (j >= n || (j >= k0 && j < k0 + nb)) return;
@@ -2409,11 +2427,21 @@ void k_dense_gemv_t(hipStream_t st, int n, const double* Xt, const double* b, do
 void k_gj_large_rowscale(hipStream_t st, int n, double* M, double* scl) {
   hipLaunchKernelGGL(dev::gj_large_rowscale_kernel, dim3(blocks_for(n, 16)), dim3(1024), 0, st, n, M, scl);
 }
-void k_gj_large_step(hipStream_t st, int n, int k0, int nb, double* M, int* perm, double* Wb, int32_t* status) {
-  hipLaunchKernelGGL(dev::gj_large_panel_kernel, dim3(1), dim3(1024), 0, st, n, k0, nb, M, perm, status);
+void k_gj_large_step(hipStream_t st, int n, int k0, int nb, double* M, int* perm, double* P0, double* P1,
+                     double* Wb, int32_t* status) {
+  const dim3 cgrid(blocks_for(n, 256), nb);
+  hipLaunchKernelGGL(dev::gj_large_panel_copy_kernel, cgrid, dim3(256), 0, st, n, k0, nb, M, P0, 1);
+  double* pin = P0;
+  double* pout = P1;
+  for (int c = 0; c < nb; ++c) {
+    hipLaunchKernelGGL(dev::gj_large_column_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, k0, c, nb, pin,
+                       pout, perm, status);
+    std::swap(pin, pout);
+  }
   hipLaunchKernelGGL(dev::gj_large_swap_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, k0, nb, M, perm, Wb);
   hipLaunchKernelGGL(dev::gj_large_update_kernel, dim3(blocks_for(n, 256), blocks_for(n, dev::GJL_ROWS)), dim3(256),
-                     0, st, n, k0, nb, M, Wb);
+                     0, st, n, k0, nb, M, pin, Wb);
+  hipLaunchKernelGGL(dev::gj_large_panel_copy_kernel, cgrid, dim3(256), 0, st, n, k0, nb, M, pin, 0);
 }
 void k_gj_large_output(hipStream_t st, int n, const double* M, const int* src, const double* scl, double* out) {
   hipLaunchKernelGGL(dev::gj_large_output_kernel, dim3(blocks_for(inv_ld(n), 256), n), dim3(256), 0, st, n, M, src,

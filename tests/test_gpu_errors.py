@@ -114,7 +114,7 @@ def test_invalid_waves_rejected():
     assert b"waves_per_patch" in c.stgmg_last_error()
 
 
-@pytest.mark.parametrize("key", ['c2s', 'c1_full', 'c1_tb'])
+@pytest.mark.parametrize("key", ['c2s', 'c1_full', 'c1_tb', 'c2d', 'c3v'])
 def test_singular_patch_reported(key, monkeypatch):
     """A patch block with a zero pivot (zeroed on the device by the setup's test hook) makes
     stgmg_setup return SINGULAR_PATCH naming the patch; the inversion kernel flags the pivot and

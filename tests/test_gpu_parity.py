@@ -86,6 +86,30 @@ def test_patch_inverses(key):
         assert rel_err(X @ y, ref @ y) < 1e-9
 
 
+@pytest.mark.parametrize("key", ['c2d', 'c3v'])
+def test_inversion_kernels_agree(key, monkeypatch):
+    """Blocks too large for LDS (the complex Schur blocks of 122 rows, c2d, and of 402 rows, c3v)
+    are inverted in global memory with the trailing updates on MFMA; the panel kernel on the
+    2x2-block real form (STGMG_GJ_KERNEL=panel) stores the same inverses to rounding (1e-10 of the
+    largest entry), and the oracle's A_P times either is the identity to 1e-9."""
+    from paper_2303_06742_amd import capi
+    S = solver(key)
+    monkeypatch.setenv('STGMG_GJ_KERNEL', 'panel')
+    Sp = capi.Solver(CONFIGS[key])
+    monkeypatch.delenv('STGMG_GJ_KERNEL')
+    lev = oracle_hierarchy(key).levels[-1]
+    npatch = len(lev.patches)
+    for q in sorted(set([0, 1, npatch // 3, npatch // 2, npatch - 1])):
+        X, dofs = S.patch_inverse(-1, q)
+        Xp, dofs_p = Sp.patch_inverse(-1, q)
+        assert np.array_equal(dofs, dofs_p)
+        assert rel_err(X, Xp) < 1e-10, (q, rel_err(X, Xp))
+        Ap = lev.A[lev.patches[q]][:, lev.patches[q]].toarray()
+        for Y in (X, Xp):
+            assert np.abs(Ap @ Y - np.eye(len(dofs))).max() < 1e-9
+    Sp.close()
+
+
 @pytest.mark.parametrize("key", ['c2s', 'k3', 'c3v', 'c2d'])
 def test_fp32_tile_readback(key):
     """FP32 storage (paired tiles up to 96 Schur rows: c2s, k3; the square layout beyond: c3v,
