@@ -449,6 +449,7 @@ def main():
         'rel_res_true_max': max(i['rel_res_true'] for i in infos),
         'nodal_err_vs_exact': nodal_err,
         'setup_s': setup_s,
+        'launch_shapes': [dict(level=l, **S.query_launch(l)) for l in range(S.levels)],
         'hbm_bytes_resident': q['bytes'],
         'roofline': {'bound': 'hbm', 'kernel': (PATCH_KERNEL_FP32_SYM if args.precision == 'fp32' and cfg.time_blocks == 3
                                                 else PATCH_KERNEL[3] + ' BF16' if args.precision == 'bf16'

@@ -159,6 +159,14 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
 stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, int64_t* n_patches,
                          int64_t* nnz, int64_t* hbm_bytes);
 
+/* Launch shapes that level `level` (as in stgmg_query) uses, after the setup's autotuning when
+ * stgmg_params.autotune = 1: the wavefronts that apply one patch's symmetric tiles (1 or 4; 0 where
+ * the level has no tiled patch solve) and the lanes per Q_r node of the level-operator kernel
+ * (2, 4, 8 or 16; 0 where the level applies its operator from the CSR matrices).  Either output
+ * pointer may be NULL. */
+stgmg_status stgmg_query_launch(const stgmg_handle* h, int32_t level, int32_t* waves_per_patch,
+                                int32_t* node_lanes);
+
 /* Solve A_n x = rhs (Problem 4.1, Eq:ALS_In) on the finest level with FGMRES
  * (right preconditioning, restart length `restart`, at most `max_iters`
  * iterations), one V-cycle per iteration (Sec. 4).  x: in = x0, out = solution.

@@ -72,6 +72,7 @@ def _decl(name, args, res=_S):
 stgmg_setup = _decl('stgmg_setup', [ctypes.POINTER(Params), _P, ctypes.POINTER(_H)])
 stgmg_query = _decl('stgmg_query', [_H, _I32, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                                     ctypes.POINTER(_I64)])
+stgmg_query_launch = _decl('stgmg_query_launch', [_H, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32)])
 stgmg_solve = _decl('stgmg_solve', [_H, _P, _P, _D, _I32, _I32, ctypes.POINTER(Info)])
 stgmg_solve_noalloc = _decl('stgmg_solve_noalloc', [_H, _P, _P, _D, _I32, _I32, ctypes.POINTER(Info)])
 stgmg_apply_operator = _decl('stgmg_apply_operator', [_H, _I32, _P, _P])
@@ -100,7 +101,7 @@ stgmg_destroy = _decl('stgmg_destroy', [_H])
 stgmg_status_string = _decl('stgmg_status_string', [_S], ctypes.c_char_p)
 stgmg_last_error = _decl('stgmg_last_error', [], ctypes.c_char_p)
 
-EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_solve', 'stgmg_solve_noalloc', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
+EXPORTED = ['stgmg_setup', 'stgmg_query', 'stgmg_query_launch', 'stgmg_solve', 'stgmg_solve_noalloc', 'stgmg_apply_operator', 'stgmg_apply_vcycle',
             'stgmg_smooth', 'stgmg_prolongate_add', 'stgmg_restrict', 'stgmg_slab_rhs', 'stgmg_march',
             'stgmg_interpolate_solution', 'stgmg_get_patch_inverse', 'stgmg_profile_enable', 'stgmg_profile_get',
             'stgmg_destroy', 'stgmg_status_string', 'stgmg_last_error', 'stgmg_footprint', 'stgmg_solve_batch',
@@ -242,6 +243,11 @@ class Solver:
         check(stgmg_query(self.h, level, ctypes.byref(n), ctypes.byref(npch), ctypes.byref(nnz), ctypes.byref(b)),
               'stgmg_query')
         return {'n': n.value, 'patches': npch.value, 'nnz': nnz.value, 'bytes': b.value}
+
+    def query_launch(self, level=-1):
+        w, g = _I32(), _I32()
+        check(stgmg_query_launch(self.h, level, ctypes.byref(w), ctypes.byref(g)), 'stgmg_query_launch')
+        return {'waves_per_patch': w.value, 'node_lanes': g.value}
 
     def empty(self, n=None):
         return self._torch.zeros(self.n if n is None else n, dtype=self._torch.float64, device='cuda')

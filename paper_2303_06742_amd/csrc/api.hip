@@ -1504,6 +1504,18 @@ stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, 
   });
 }
 
+stgmg_status stgmg_query_launch(const stgmg_handle* h, int32_t level, int32_t* waves_per_patch,
+                                int32_t* node_lanes) {
+  return guarded([&] {
+    if (!h) throw ApiError(STGMG_ERR_INVALID_ARG, "NULL handle");
+    const int l = level_index(h, level);
+    const LevelDev& L = h->lv[l];
+    if (waves_per_patch) *waves_per_patch = L.sym && L.npatch > 0 ? stgmg::red_sym_waves(L.waves, L.npatch, L.max_nr) : 0;
+    if (node_lanes) *node_lanes = L.node_ok ? stgmg::node_op_lanes(L.node) : 0;
+    return STGMG_OK;
+  });
+}
+
 stgmg_status stgmg_solve(stgmg_handle* h, const double* rhs_dev, double* x_dev, double rtol, int32_t restart,
                          int32_t max_iters, stgmg_info* info) {
   return guarded([&] {

@@ -2000,7 +2000,7 @@ static void node_op_nt(hipStream_t st, const TimeOp& top, const NodeOpDev& o, in
                        const double* kval, const double* x, const double* b, double* y) {
   // lanes per node (a power of two): by default 4 for the ~16 node pairs of a 2D Q2 node, 8 for
   // the ~64 of a 3D one
-  const int lanes = o.lanes > 0 ? o.lanes : (D == 2 ? 4 : 8);
+  const int lanes = node_op_lanes(o);
 #define STGMG_NODE(G)                                                                                    \
   switch (top.nt) {                                                                                      \
     case 1: launch_node_op<G, MODE, 1, D>(st, top, o, ns, mptr, mcol, mval, kptr, kcol, kval, x, b, y); break; \
@@ -2230,6 +2230,15 @@ int patch_apply_red_threads(int max_nr, bool fp32) {
 constexpr int64_t SYM_MULTI_BELOW = 4096;
 constexpr int SYM_LARGE_NR = 96;
 
+int red_sym_waves(int waves, int64_t npatch, int max_nr) {
+  if (waves == 1 || waves == 4) return waves;
+  int64_t multi = max_nr > SYM_LARGE_NR ? 2 * SYM_MULTI_BELOW : SYM_MULTI_BELOW;
+  if (const char* e = std::getenv("STGMG_SYM_MULTI_BELOW")) multi = std::atoll(e);  // tuning
+  return npatch < multi ? 4 : 1;
+}
+
+int node_op_lanes(const NodeOpDev& o) { return o.lanes > 0 ? o.lanes : (o.d == 2 ? 4 : 8); }
+
 // tuning: STGMG_RED_NT (0: ordinary loads instead of streaming loads), STGMG_XCD_CHUNK
 template <typename T>
 static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, int max_nr, bool sym, int waves,
@@ -2241,9 +2250,7 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   red_layout(max_nr, rr, &th, &W);
   size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
   if (sym) {  // W waves per patch; region B holds W partial products and D1 z at stride 8 ceil(nr / 8)
-    int64_t multi = max_nr > SYM_LARGE_NR ? 2 * SYM_MULTI_BELOW : SYM_MULTI_BELOW;
-    if (const char* e = std::getenv("STGMG_SYM_MULTI_BELOW")) multi = std::atoll(e);  // tuning
-    W = waves == 1 || waves == 4 ? waves : npatch < multi ? 4 : 1;
+    W = red_sym_waves(waves, npatch, max_nr);
     th = 64 * W;
     const size_t ldr = inv_ld(max_nr), ns = max_np / tb.nt, ldt = 8 * ((max_nr + 7) / 8);
     const size_t a = std::max<size_t>(max_np, 2 * size_t(tb.nblk) * (max_nu + ldr));

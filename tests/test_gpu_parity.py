@@ -366,6 +366,9 @@ def test_autotuned_launch_shapes(key):
     require_gpu()
     from paper_2303_06742_amd import capi
     S = capi.Solver(CONFIGS[key], autotune=1)
+    for l in range(S.levels):
+        q = S.query_launch(l)
+        assert q['waves_per_patch'] in ((0,) if l == 0 else (1, 4)) and q['node_lanes'] in (0, 2, 4, 8, 16), (l, q)
     H = oracle_hierarchy(key)
     for l in range(S.levels):
         A = H.levels[l].A
