@@ -1313,47 +1313,56 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int n
   }
 }
 
-template <typename T, int R, bool NTL, bool SYM>
-__device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, int W, int xc,
-                                                     const int64_t* __restrict__ poff, const int32_t* __restrict__ pdof,
-                                                     const int32_t* __restrict__ tpos, const int32_t* __restrict__ pnu,
-                                                     const int64_t* __restrict__ ioff, const T* __restrict__ inv,
-                                                     const double* __restrict__ r, double* __restrict__ y) {
-  typedef T V __attribute__((ext_vector_type(R)));
-  extern __shared__ double sm[];
-  const int64_t p = xcd_chunk(blockIdx.x, gridDim.x, xc);
-  const int64_t o = poff[p];
-  const int n = int(poff[p + 1] - o);
-  const int nt = tb.nt, nblk = tb.nblk;
-  const int ns = n / nt, nU = pnu[p], nP = ns - 2 * nU, nn = nU / d, nr = nU + nP;
-  const int ldn = inv_ld(nn), ldp = inv_ld(nP), ldr = inv_ld(nr);
-  // region A: r_P, later w [a][re, im][nU] and z [a][re, im][ldr];
-  // region B: transformed right-hand sides [a][re, im][ns], later W partial images [w][a][re, im][ldr]
-  const int szA = max(n, 2 * nblk * (nU + ldr));
-  double* rl = sm;
-  double* wv = sm;
-  double* z = sm + 2 * nblk * nU;
-  double* sv = sm + szA;
-  double* tv = sm + szA;
-  const int64_t base = ioff[p];
-  const int64_t nsmall = int64_t(nn) * ldn + int64_t(nU) * ldp;  // (rho M)^{-1} and G
+// The sizes and offsets of one patch's reduced solve.
+struct RedPatch {
+  int64_t o, base, nsmall;
+  int n, ns, nU, nP, nn, nr, ldn, ldp, ldr;
+};
+__device__ inline RedPatch red_patch(const TimeBlockConsts& tb, int d, int64_t p, const int64_t* __restrict__ poff,
+                                     const int32_t* __restrict__ pnu, const int64_t* __restrict__ ioff) {
+  RedPatch P;
+  P.o = poff[p];
+  P.n = int(poff[p + 1] - P.o);
+  P.ns = P.n / tb.nt;
+  P.nU = pnu[p];
+  P.nP = P.ns - 2 * P.nU;
+  P.nn = P.nU / d;
+  P.nr = P.nU + P.nP;
+  P.ldn = inv_ld(P.nn);
+  P.ldp = inv_ld(P.nP);
+  P.ldr = inv_ld(P.nr);
+  P.base = ioff[p];
+  P.nsmall = int64_t(P.nn) * P.ldn + int64_t(P.nU) * P.ldp;  // (rho M)^{-1} and G
+  return P;
+}
+
+// Front of the reduced solve, threads t0, t0 + nth, ... of the patch's thread set, sync() between
+// phases: r_P gathered into rl (n), transformed to the eigenvalue blocks in sv ([a][re, im][ns]),
+// then w = (rho M)^{-1} r_u per component into wv ([a][re, im][nU]) and z = [r_v + lam r_u;
+// r_p + G r_u] into z ([a][re, im][ldr]).  rl may share memory with wv and z (it is dead once sv
+// is formed); the caller synchronises after the last phase.
+template <typename T, bool NTL, typename Sync>
+__device__ inline void red_front(const TimeBlockConsts& tb, int d, const RedPatch& P, const int32_t* __restrict__ pdof,
+                                 const T* __restrict__ inv, const double* __restrict__ r, double* rl, double* sv,
+                                 double* wv, double* z, int t0, int nth, Sync sync) {
+  const int nt = tb.nt, nblk = tb.nblk, n = P.n, ns = P.ns, nU = P.nU, nn = P.nn, nr = P.nr, ldr = P.ldr;
   // gather r_P: batches of independent index and value loads
-  for (int ib = threadIdx.x; ib < n; ib += 8 * blockDim.x) {
+  for (int ib = t0; ib < n; ib += 8 * nth) {
     int32_t g[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = ib + u * blockDim.x;
-      g[u] = i < n ? pdof[o + i] : 0;
+      const int i = ib + u * nth;
+      g[u] = i < n ? pdof[P.o + i] : 0;
     }
     double v[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ib + u * blockDim.x < n ? r[g[u]] : 0.0;
+    for (int u = 0; u < 8; ++u) v[u] = ib + u * nth < n ? r[g[u]] : 0.0;
 #pragma unroll
     for (int u = 0; u < 8; ++u)
-      if (ib + u * blockDim.x < n) rl[ib + u * blockDim.x] = v[u];
+      if (ib + u * nth < n) rl[ib + u * nth] = v[u];
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < ns; i += blockDim.x)
+  sync();
+  for (int i = t0; i < ns; i += nth)
     for (int a = 0; a < nblk; ++a) {
       double sr = 0.0, si = 0.0;
       for (int b = 0; b < nt; ++b) {
@@ -1364,120 +1373,207 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
       sv[(2 * a) * ns + i] = sr;
       sv[(2 * a + 1) * ns + i] = si;
     }
-  __syncthreads();
+  sync();
   // items [0, nU): w = (rho M)^{-1} r_u per component and z_U = r_v + lam r_u;
   // items [nU, nr): z_P = r_p + G r_u
-  {
-    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + base, nsmall);
-    for (int it = threadIdx.x; it < nr; it += blockDim.x) {
-      double ar[RED_MAXB] = {0, 0}, ai[RED_MAXB] = {0, 0};
-      const bool vel = it < nU;
-      // element j of the row: byte offset e0 + j * es (column-major: adjacent lanes read
-      // adjacent entries)
-      const int e0 = int(sizeof(T)) * (vel ? it / d : nn * ldn + (it - nU));
-      const int es = int(sizeof(T)) * (vel ? ldn : ldp);
-      const int m = vel ? nn : nU;
-      const int sstep = vel ? d : 1, s0 = vel ? it % d : 0;  // r_u entries: j * d + c (mass) or j (G)
-      int j = 0;
-      for (; j + 7 < m; j += 8) {
-        T mv[8];
+  const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + P.base, P.nsmall);
+  for (int it = t0; it < nr; it += nth) {
+    double ar[RED_MAXB] = {0, 0}, ai[RED_MAXB] = {0, 0};
+    const bool vel = it < nU;
+    // element j of the row: byte offset e0 + j * es (column-major: adjacent lanes read
+    // adjacent entries)
+    const int e0 = int(sizeof(T)) * (vel ? it / d : nn * P.ldn + (it - nU));
+    const int es = int(sizeof(T)) * (vel ? P.ldn : P.ldp);
+    const int m = vel ? nn : nU;
+    const int sstep = vel ? d : 1, s0 = vel ? it % d : 0;  // r_u entries: j * d + c (mass) or j (G)
+    int j = 0;
+    for (; j + 7 < m; j += 8) {
+      T mv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) mv[u] = bld1<T, NTL>(rs, e0 + (j + u) * es);
+      for (int u = 0; u < 8; ++u) mv[u] = bld1<T, NTL>(rs, e0 + (j + u) * es);
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int a = 0; a < RED_MAXB; ++a)
-            if (a < nblk) {
-              ar[a] += double(mv[u]) * sv[(2 * a) * ns + (j + u) * sstep + s0];
-              ai[a] += double(mv[u]) * sv[(2 * a + 1) * ns + (j + u) * sstep + s0];
-            }
-      }
-      for (; j < m; ++j) {
-        const double mv = double(bld1<T, NTL>(rs, e0 + j * es));
+      for (int u = 0; u < 8; ++u)
 #pragma unroll
         for (int a = 0; a < RED_MAXB; ++a)
           if (a < nblk) {
-            ar[a] += mv * sv[(2 * a) * ns + j * sstep + s0];
-            ai[a] += mv * sv[(2 * a + 1) * ns + j * sstep + s0];
+            ar[a] += double(mv[u]) * sv[(2 * a) * ns + (j + u) * sstep + s0];
+            ai[a] += double(mv[u]) * sv[(2 * a + 1) * ns + (j + u) * sstep + s0];
           }
-      }
+    }
+    for (; j < m; ++j) {
+      const double mv = double(bld1<T, NTL>(rs, e0 + j * es));
 #pragma unroll
       for (int a = 0; a < RED_MAXB; ++a)
         if (a < nblk) {
-          if (vel) {
-            const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
-            const double ur = sv[(2 * a) * ns + it], ui = sv[(2 * a + 1) * ns + it];
-            wv[(2 * a) * nU + it] = ar[a];
-            wv[(2 * a + 1) * nU + it] = ai[a];
-            z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + al * ur - be * ui;
-            z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + al * ui + be * ur;
-          } else {
-            z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + ar[a];
-            z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + ai[a];
-          }
+          ar[a] += mv * sv[(2 * a) * ns + j * sstep + s0];
+          ai[a] += mv * sv[(2 * a + 1) * ns + j * sstep + s0];
         }
     }
+#pragma unroll
+    for (int a = 0; a < RED_MAXB; ++a)
+      if (a < nblk) {
+        if (vel) {
+          const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+          const double ur = sv[(2 * a) * ns + it], ui = sv[(2 * a + 1) * ns + it];
+          wv[(2 * a) * nU + it] = ar[a];
+          wv[(2 * a + 1) * nU + it] = ai[a];
+          z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + al * ur - be * ui;
+          z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + al * ui + be * ur;
+        } else {
+          z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + ar[a];
+          z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + ai[a];
+        }
+      }
   }
+}
+
+// Symmetric tiles: zt = D1 z ([a][re, im][LDT], zero padded beyond nr).
+__device__ inline void sym_scale_z(const TimeBlockConsts& tb, const RedPatch& P, int LDT, const double* z, double* zt,
+                                   int t0, int nth) {
+  const int nblk = tb.nblk, nr = P.nr, nU = P.nU, ldr = P.ldr;
+  for (int x = t0; x < LDT; x += nth)
+#pragma unroll
+    for (int a = 0; a < RED_MAXB; ++a)
+      if (a < nblk) {
+        double m1r, m1i, m2r, m2i;
+        sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
+        double vr = x < nr ? z[(2 * a) * ldr + x] : 0.0, vi = x < nr ? z[(2 * a + 1) * ldr + x] : 0.0;
+        if (x >= nU) {
+          const double ur = vr * m1r - vi * m1i, ui = vr * m1i + vi * m1r;
+          vr = ur;
+          vi = ui;
+        }
+        zt[(2 * a) * LDT + x] = vr;
+        zt[(2 * a + 1) * LDT + x] = vi;
+      }
+}
+
+// Symmetric tiles: wave w of W adds X D1 z of every kept eigenvalue into its own partial
+// products tt + w * 2 nblk LDT ([a][re, im][LDT], zeroed by the caller).
+template <typename T, bool NTL>
+__device__ inline void sym_apply_blocks(const TimeBlockConsts& tb, const RedPatch& P, int LDT,
+                                        const T* __restrict__ inv, const double* zt, double* tt, int w, int W) {
+  const int nblk = tb.nblk, nr = P.nr;
+  const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr);
+  const int nsl = sym_slots(nr, 8 / int(sizeof(T)));  // stored tiles per plane
+  int64_t off = P.base + P.nsmall;
+  for (int a = 0; a < nblk; ++a) {
+    const bool cp = tb.cplx[a] != 0;
+    const int64_t cnt = int64_t(cp ? 2 : 1) * nsl * 64;
+    const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
+    double* yw = tt + (int64_t(w) * nblk + a) * 2 * LDT;
+    if (cp)
+      sym_tiles_apply<T, NTL, true>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, w, W);
+    else
+      sym_tiles_apply<T, NTL, false>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, w, W);
+    off += cnt;
+  }
+}
+
+// Symmetric tiles: t_P = mu2 (X D1 z)_P in each of the W partial products.
+__device__ inline void sym_scale_t(const TimeBlockConsts& tb, const RedPatch& P, int LDT, int W, double* tt, int t0,
+                                   int nth) {
+  const int nblk = tb.nblk, nU = P.nU, nP = P.nP;
+  for (int q = t0; q < W * nP; q += nth)
+#pragma unroll
+    for (int a = 0; a < RED_MAXB; ++a)
+      if (a < nblk) {
+        const int ww = q / nP, x = nU + q % nP;
+        double m1r, m1i, m2r, m2i;
+        sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
+        double* yb = tt + (int64_t(ww) * nblk + a) * 2 * LDT;
+        const double vr = yb[x], vi = yb[LDT + x];
+        yb[x] = vr * m2r - vi * m2i;
+        yb[LDT + x] = vr * m2i + vi * m2r;
+      }
+}
+
+// Back of the reduced solve: the spatial images [lam U - w; U; P] (the sum of the W partial
+// products at stride LDT, and w) transformed back to the time nodes and written to the image
+// slots y[tpos[o + l]].
+__device__ inline void red_back(const TimeBlockConsts& tb, const RedPatch& P, int LDT, int W, const double* tv,
+                                const double* wv, const int32_t* __restrict__ tpos, double* __restrict__ y, int t0,
+                                int nth) {
+  const int nt = tb.nt, nblk = tb.nblk, ns = P.ns, nU = P.nU;
+  for (int i = t0; i < ns; i += nth) {
+    const int ii = i < nU ? i : i - nU;
+    double hr[RED_MAXB], hi[RED_MAXB];
+#pragma unroll
+    for (int a = 0; a < RED_MAXB; ++a)
+      if (a < nblk) {
+        double t_r = 0.0, t_i = 0.0;
+        for (int ww = 0; ww < W; ++ww) {
+          t_r += tv[(int64_t(ww) * nblk + a) * 2 * LDT + ii];
+          t_i += tv[(int64_t(ww) * nblk + a) * 2 * LDT + LDT + ii];
+        }
+        if (i < nU) {
+          const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+          hr[a] = al * t_r - be * t_i - wv[(2 * a) * nU + i];
+          hi[a] = al * t_i + be * t_r - wv[(2 * a + 1) * nU + i];
+        } else {
+          hr[a] = t_r;
+          hi[a] = t_i;
+        }
+      }
+    for (int b = 0; b < nt; ++b) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < RED_MAXB; ++a)
+        if (a < nblk) {
+          const double qr = tb.qout[2 * (b * nblk + a)], qi = tb.qout[2 * (b * nblk + a) + 1];
+          acc += tb.cplx[a] ? 2.0 * (qr * hr[a] - qi * hi[a]) : qr * hr[a];
+        }
+      y[tpos[P.o + b * ns + i]] = acc;
+    }
+  }
+}
+
+struct BlockSync {
+  __device__ void operator()() const { __syncthreads(); }
+};
+
+template <typename T, int R, bool NTL, bool SYM>
+__device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, int W, int xc,
+                                                     const int64_t* __restrict__ poff, const int32_t* __restrict__ pdof,
+                                                     const int32_t* __restrict__ tpos, const int32_t* __restrict__ pnu,
+                                                     const int64_t* __restrict__ ioff, const T* __restrict__ inv,
+                                                     const double* __restrict__ r, double* __restrict__ y) {
+  typedef T V __attribute__((ext_vector_type(R)));
+  extern __shared__ double sm[];
+  const int64_t p = xcd_chunk(blockIdx.x, gridDim.x, xc);
+  const RedPatch P = red_patch(tb, d, p, poff, pnu, ioff);
+  const int nblk = tb.nblk;
+  const int n = P.n, ns = P.ns, nU = P.nU, nr = P.nr, ldr = P.ldr;
+  // region A: r_P, later w [a][re, im][nU] and z [a][re, im][ldr];
+  // region B: transformed right-hand sides [a][re, im][ns], later W partial images [w][a][re, im][ldr]
+  const int szA = max(n, 2 * nblk * (nU + ldr));
+  double* rl = sm;
+  double* wv = sm;
+  double* z = sm + 2 * nblk * nU;
+  double* sv = sm + szA;
+  double* tv = sm + szA;
+  red_front<T, NTL>(tb, d, P, pdof, inv, r, rl, sv, wv, z, int(threadIdx.x), int(blockDim.x), BlockSync());
   __syncthreads();
   // symmetric tiles (one wave): t = D2 X D1 z per kept eigenvalue into region B, stride LDT
   const int LDT = SYM ? 8 * ((nr + 7) >> 3) : ldr;
   if constexpr (SYM) {
     // W waves: wave w's products at tv + w * 2 nblk LDT ([a][re, im][LDT], the partial images
     // the back-transform sums), then D1 z shared by all waves
-    const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr);
-    const int nsl = sym_slots(nr, 8 / int(sizeof(T)));  // stored tiles per plane
-    const int wv_i = threadIdx.x >> 6;
     double* tt = tv;
     double* zt = tv + int64_t(W) * 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
     for (int x = threadIdx.x; x < int64_t(W) * 2 * nblk * LDT; x += blockDim.x) tt[x] = 0.0;
-    for (int x = threadIdx.x; x < LDT; x += blockDim.x)
-#pragma unroll
-      for (int a = 0; a < RED_MAXB; ++a)
-        if (a < nblk) {
-          double m1r, m1i, m2r, m2i;
-          sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
-          double vr = x < nr ? z[(2 * a) * ldr + x] : 0.0, vi = x < nr ? z[(2 * a + 1) * ldr + x] : 0.0;
-          if (x >= nU) {
-            const double ur = vr * m1r - vi * m1i, ui = vr * m1i + vi * m1r;
-            vr = ur;
-            vi = ui;
-          }
-          zt[(2 * a) * LDT + x] = vr;
-          zt[(2 * a + 1) * LDT + x] = vi;
-        }
+    sym_scale_z(tb, P, LDT, z, zt, int(threadIdx.x), int(blockDim.x));
     __syncthreads();
-    int64_t off = base + nsmall;
-    for (int a = 0; a < nblk; ++a) {
-      const bool cp = tb.cplx[a] != 0;
-      const int64_t cnt = int64_t(cp ? 2 : 1) * nsl * 64;
-      const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
-      double* yw = tt + (int64_t(wv_i) * nblk + a) * 2 * LDT;
-      if (cp)
-        sym_tiles_apply<T, NTL, true>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
-      else
-        sym_tiles_apply<T, NTL, false>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, wv_i, W);
-      off += cnt;
-    }
+    sym_apply_blocks<T, NTL>(tb, P, LDT, inv, zt, tt, int(threadIdx.x >> 6), W);
     __syncthreads();
-    for (int q = threadIdx.x; q < W * nP; q += blockDim.x)  // t_P = mu2 (X D1 z)_P, every wave's part
-#pragma unroll
-      for (int a = 0; a < RED_MAXB; ++a)
-        if (a < nblk) {
-          const int ww = q / nP, x = nU + q % nP;
-          double m1r, m1i, m2r, m2i;
-          sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
-          double* yb = tt + (int64_t(ww) * nblk + a) * 2 * LDT;
-          const double vr = yb[x], vi = yb[LDT + x];
-          yb[x] = vr * m2r - vi * m2i;
-          yb[LDT + x] = vr * m2i + vi * m2r;
-        }
+    sym_scale_t(tb, P, LDT, W, tt, int(threadIdx.x), int(blockDim.x));  // every wave's part
   } else {
     const int per_w = blockDim.x / W;
     const int w = threadIdx.x / per_w, tl = threadIdx.x % per_w;
     const int i0 = R * tl;
     const int jc = (nr + W - 1) / W, j0 = w * jc, j1 = min(nr, j0 + jc);
     const int voff = i0 * int(sizeof(T));
-    int64_t off = base + nsmall;
+    int64_t off = P.base + P.nsmall;
     for (int a = 0; a < nblk; ++a) {
       const double* zr = z + (2 * a) * ldr;
       const double* zi = z + (2 * a + 1) * ldr;
@@ -1565,37 +1661,7 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
   __syncthreads();
   // spatial images [lam U - w; U; P], transformed back to the time nodes (products at stride
   // LDT: the square path's W partial images, or the tiled path's single result)
-  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
-    const int ii = i < nU ? i : i - nU;
-    double hr[RED_MAXB], hi[RED_MAXB];
-#pragma unroll
-    for (int a = 0; a < RED_MAXB; ++a)
-      if (a < nblk) {
-        double t_r = 0.0, t_i = 0.0;
-        for (int ww = 0; ww < W; ++ww) {
-          t_r += tv[(int64_t(ww) * nblk + a) * 2 * LDT + ii];
-          t_i += tv[(int64_t(ww) * nblk + a) * 2 * LDT + LDT + ii];
-        }
-        if (i < nU) {
-          const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
-          hr[a] = al * t_r - be * t_i - wv[(2 * a) * nU + i];
-          hi[a] = al * t_i + be * t_r - wv[(2 * a + 1) * nU + i];
-        } else {
-          hr[a] = t_r;
-          hi[a] = t_i;
-        }
-      }
-    for (int b = 0; b < nt; ++b) {
-      double acc = 0.0;
-#pragma unroll
-      for (int a = 0; a < RED_MAXB; ++a)
-        if (a < nblk) {
-          const double qr = tb.qout[2 * (b * nblk + a)], qi = tb.qout[2 * (b * nblk + a) + 1];
-          acc += tb.cplx[a] ? 2.0 * (qr * hr[a] - qi * hi[a]) : qr * hr[a];
-        }
-      y[tpos[o + b * ns + i]] = acc;
-    }
-  }
+  red_back(tb, P, LDT, W, tv, wv, tpos, y, int(threadIdx.x), int(blockDim.x));
 }
 
 // Square Schur inverses: W column ranges per block of up to 512 threads.
