@@ -35,9 +35,10 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, precision):
-    """HBM bytes per launch of the finest-level patch GEMV from the rocprofv3 counter runs
-    recorded in profiles/hbm_traffic.json, if they were taken on the current kernel source."""
+def measured_traffic(workload, precision, role='patch'):
+    """HBM bytes per launch of the finest-level patch kernel (role 'patch') or operator kernel
+    (role 'operator') from the rocprofv3 counter runs recorded in profiles/hbm_traffic.json, if
+    they were taken on the current kernel source."""
     path = os.path.join(ROOT, 'profiles', 'hbm_traffic.json')
     if not os.path.exists(path):
         return None
@@ -45,7 +46,8 @@ def measured_traffic(workload, precision):
         entries = json.load(f).get('entries', [])
     h = kernel_source_hash()
     for e in entries:
-        if e.get('workload') == workload and e.get('precision') == precision and e.get('kernels_hip_sha256') == h:
+        if (e.get('workload') == workload and e.get('precision') == precision and e.get('kernels_hip_sha256') == h
+                and e.get('role', 'patch') == role):
             return e['bytes_per_launch']
     return None
 
@@ -468,7 +470,8 @@ def main():
                          (avg_pa_ms * 1e-3) / 1e9 if pa['launches'] else 0.0}},
         'residual_spmv': {'kernel': 'node_op_kernel (finest level)', 'avg_launch_ms': avg_rs_ms,
                           'launches': rs['launches'], 'bytes_per_launch': rs['bytes_per_launch'],
-                          'achieved_GBs': rs['bytes_per_launch'] / (avg_rs_ms * 1e-3) / 1e9 if rs['launches'] else 0},
+                          'achieved_GBs': rs['bytes_per_launch'] / (avg_rs_ms * 1e-3) / 1e9 if rs['launches'] else 0,
+                          'traffic': measured_traffic(cfg.name, args.precision, 'operator')},
     }
     S.close()
     if kept:
