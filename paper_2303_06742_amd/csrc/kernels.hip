@@ -259,9 +259,10 @@ __global__ void __launch_bounds__(256) node_op_kernel(
     const int64_t* __restrict__ cptr, const int32_t* __restrict__ ccol, const double* __restrict__ cval,
     const int64_t* __restrict__ mptr, const int32_t* __restrict__ mcol, const double* __restrict__ mval,
     const int64_t* __restrict__ kptr, const int32_t* __restrict__ kcol, const double* __restrict__ kval,
-    const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ y) {
+    const double* __restrict__ x, const double* __restrict__ b, double* __restrict__ y, int64_t xc) {
   if (int64_t(blockIdx.x) < nb_node) {
-    const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) / G;
+    const int64_t blk = xcd_chunk(blockIdx.x, nb_node, xc);
+    const int64_t i = (blk * blockDim.x + threadIdx.x) / G;
     if (i >= nQ) return;
     node_rows<G, MODE, NT, D>(top, i, int(threadIdx.x % G), nv, ns, nptr, ncol, nm, na, cptr, ccol, cval, x, b, y);
     return;
@@ -2055,9 +2056,16 @@ static void launch_node_op(hipStream_t st, const TimeOp& top, const NodeOpDev& o
   constexpr int GP = D == 2 ? 16 : 32;
   const int64_t nv = int64_t(D) * o.nQ, np = ns - 2 * nv;
   const int64_t nb_node = (o.nQ * G + 255) / 256, nb_p = (np * GP + 255) / 256;
+  // each XCD takes chunks of xc consecutive node blocks, so that the x values of neighbouring
+  // nodes are fetched into one XCD's L2 rather than into all eight: measured best of round-robin /
+  // 16 / 64 / 256 / one range per XCD (256^2 dG(2): 0.136 -> 0.124 ms at 64; 32^3 dG(1):
+  // 0.576 -> 0.532 ms at 16).  Tuning: STGMG_OP_XCD_CHUNK (0 round-robin, -1 one range per XCD).
+  int64_t xc = D == 2 ? 64 : 16;
+  if (const char* e = std::getenv("STGMG_OP_XCD_CHUNK")) xc = std::atoll(e);
+  if (xc < 0) xc = std::max<int64_t>(1, nb_node / 8);
   hipLaunchKernelGGL((dev::node_op_kernel<G, GP, MODE, NT, D>), dim3(nb_node + nb_p), dim3(256), 0, st, top, o.nQ, nv,
                      ns, nb_node, o.ptr, o.col, o.m, o.a, o.cptr, o.ccol, o.c, mptr, mcol, mval, kptr, kcol, kval, x, b,
-                     y);
+                     y, xc);
 }
 
 template <int MODE, int D>
