@@ -9,6 +9,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch brings its own HIP and HSA runtime libraries.  It is loaded before libstgmg.so so that the
+# process holds the runtime torch uses when the library is loaded: with the library loaded first, a
+# process that then initialised torch found no device in the library's HIP calls.
+import torch  # noqa: F401  (device memory and streams)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, 'libstgmg.so')

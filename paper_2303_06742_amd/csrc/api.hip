@@ -343,17 +343,24 @@ void vcycle(stgmg_handle* h, int l, const double* b, double* d);
 // RED_INV_LDS  the whole matrix in LDS (workgroup kernel, complex blocks in complex arithmetic),
 // RED_INV_MFMA the matrix in global memory, trailing updates on MFMA (complex arithmetic),
 // RED_INV_PANEL the panel kernel on the 2x2-block real form of complex blocks (used when neither
-//               fits, or through STGMG_GJ_KERNEL=panel for comparisons).
+//               of the others fits).
+// STGMG_GJ_KERNEL = lds, mfma or panel selects a kernel where its blocks fit (comparisons).
 enum { RED_INV_LDS = 0, RED_INV_MFMA = 1, RED_INV_PANEL = 2 };
+constexpr int RED_INV_MFMA_ROWS = 64;
 int red_inv_kernel(bool any_c, int max_nr, int max_nn) {
-  if (stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
-      stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block())
-    return RED_INV_LDS;
-  const char* e = std::getenv("STGMG_GJ_KERNEL");
-  if (e && std::string(e) == "panel") return RED_INV_PANEL;
-  if (stgmg::gj_mfma_bytes(max_nr, any_c) <= lds_per_block() && stgmg::gj_mfma_bytes(max_nn, false) <= lds_per_block())
-    return RED_INV_MFMA;
-  return RED_INV_PANEL;
+  const std::string e = std::getenv("STGMG_GJ_KERNEL") ? std::getenv("STGMG_GJ_KERNEL") : "";
+  const bool mfma_fits = stgmg::gj_mfma_bytes(max_nr, any_c) <= lds_per_block() &&
+                         stgmg::gj_mfma_bytes(max_nn, false) <= lds_per_block();
+  const bool lds_fits = stgmg::gj_lds_kernel_bytes(max_nr, any_c) <= lds_per_block() &&
+                        stgmg::gj_lds_kernel_bytes(max_nn, false) <= lds_per_block();
+  if (e == "lds" && lds_fits) return RED_INV_LDS;
+  if (e == "mfma" && mfma_fits) return RED_INV_MFMA;
+  if (e == "panel") return RED_INV_PANEL;
+  // Schur blocks above RED_INV_MFMA_ROWS rows go to the MFMA kernel even where they fit in LDS
+  // (patch-solve setup phase, 32^3 dG(1) cell patches, 89 rows: 0.151 s in LDS, 0.125 s on MFMA;
+  // 256^2 dG(2) vertex patches, 59 rows: 0.141 s in LDS, 0.234 s on MFMA)
+  if (lds_fits && !(max_nr > RED_INV_MFMA_ROWS && mfma_fits)) return RED_INV_LDS;
+  return mfma_fits ? RED_INV_MFMA : RED_INV_PANEL;
 }
 int red_inv_kernel(const stgmg::TimeBlockConsts& tb, int max_nr, int max_nn) {
   bool any_c = false;

@@ -86,15 +86,18 @@ def test_patch_inverses(key):
         assert rel_err(X @ y, ref @ y) < 1e-9
 
 
-@pytest.mark.parametrize("key", ['c2d', 'c3v'])
-def test_inversion_kernels_agree(key, monkeypatch):
-    """Blocks too large for LDS (the complex Schur blocks of 122 rows, c2d, and of 402 rows, c3v)
-    are inverted in global memory with the trailing updates on MFMA; the panel kernel on the
-    2x2-block real form (STGMG_GJ_KERNEL=panel) stores the same inverses to rounding (1e-10 of the
-    largest entry), and the oracle's A_P times either is the identity to 1e-9."""
+@pytest.mark.parametrize("key,other", [('c2d', 'panel'), ('c3v', 'panel'), ('c2s', 'mfma'), ('c3s', 'lds'),
+                                       ('c3s', 'panel'), ('k3', 'mfma')])
+def test_inversion_kernels_agree(key, other, monkeypatch):
+    """The patch blocks are inverted in LDS up to 64 Schur rows where they fit (c2s: 59, k3) and
+    in global memory with the trailing updates on MFMA above (c3s: 89 rows; the complex Schur
+    blocks of 122 rows, c2d, and of 402 rows, c3v).  Another kernel for the same blocks
+    (STGMG_GJ_KERNEL: LDS, MFMA, or the panel kernel on the 2x2-block real form) stores the same
+    inverses to rounding (1e-10 of the largest entry), and the oracle's A_P times either is the
+    identity to 1e-9."""
     from paper_2303_06742_amd import capi
     S = solver(key)
-    monkeypatch.setenv('STGMG_GJ_KERNEL', 'panel')
+    monkeypatch.setenv('STGMG_GJ_KERNEL', other)
     Sp = capi.Solver(CONFIGS[key])
     monkeypatch.delenv('STGMG_GJ_KERNEL')
     lev = oracle_hierarchy(key).levels[-1]
