@@ -91,53 +91,63 @@ def test_patch_inverses_sampled(ctx):
         assert res < max(1e-9, 100 * res_ref), (q, res, res_ref)
 
 
-def test_one_sweep_sampled_dofs(ctx):
-    """Algorithm 4.1, one sweep from a random iterate: at sampled dofs mu the GPU's new iterate
-    equals d0 + omega / p(mu) sum_{P contains mu} (A_P^{-1} R_P (b - A d0))[mu].  Sampled: every
+def sampled_sweep(c, b, d0, seed):
+    """Algorithm 4.1, one sweep from d0, computed by the oracle one dof at a time: at sampled dofs
+    mu, d0 + omega / p(mu) sum_{P contains mu} (A_P^{-1} R_P (b - A d0))[mu].  Sampled: every
     velocity component of V and U at sampled Q_r nodes and the pressure at sampled Q_{r-1}
-    nodes, at every time node (the rows of the tiled kernel's 4x16 last block row and of its
-    pressure scaling included), with the finest level on one wave per patch."""
-    S = ctx['S']
-    b = W.random_vector(S.n, 911)
-    d0 = W.random_vector(S.n, 912)
-    d1 = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 1))
-    blk = ctx['b']
+    nodes, at every time node.  Returns (dofs, values)."""
+    blk = c['b']
     ns, nv, nt, dim = blk.ns, blk.nv, CFG.k + 1, CFG.dim
-    cells = ctx['cells']
+    cells = c['cells']
     N, r = CFG.fine_cells, CFG.r
-    rng = np.random.default_rng(913)
+    rng = np.random.default_rng(seed)
 
     def adjacent(g, p):
         """cells along one axis touching lattice point g of a degree-p lattice"""
         return sorted({min(max((g - 1) // p, 0), N - 1), min(g // p, N - 1)})
 
-    def check(gx, gy, p, mus):
+    def one(gx, gy, p, mus):
         # the vertex patches that contain a node: those of the grid vertices of its adjacent cells
         verts = {vx + (N + 1) * vy for cx in adjacent(gx, p) for cy in adjacent(gy, p)
                  for vx in (cx, cx + 1) for vy in (cy, cy + 1)}
         acc = np.zeros(len(mus))
         cnt = np.zeros(len(mus))
         for v in sorted(verts):
-            Z = patch_dofs_of(ctx, cells[v])
+            Z = patch_dofs_of(c, cells[v])
             pos = np.searchsorted(Z, mus)
             inside = (pos < len(Z)) & (Z[np.minimum(pos, len(Z) - 1)] == mus)
             if not inside.any():
                 continue
-            rP = b[Z] - apply_rows(ctx, d0, Z)
-            y = np.linalg.solve(patch_matrix(ctx, Z), rP)
+            rP = b[Z] - apply_rows(c, d0, Z)
+            y = np.linalg.solve(patch_matrix(c, Z), rP)
             acc[inside] += y[pos[inside]]
             cnt[inside] += 1
         assert np.all(cnt >= 1)
-        ref = d0[mus] + CFG.omega * acc / cnt
-        assert np.all(np.abs(d1[mus] - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), (gx, gy, d1[mus] - ref)
+        return d0[mus] + CFG.omega * acc / cnt
 
+    dofs, vals = [], []
     n1, n1p = r * N + 1, (r - 1) * N + 1
     for node in list(rng.integers(0, n1 * n1, 5)) + [0, n1 * n1 - 1, n1 * (n1 // 2) + 1]:
-        mus = np.array([t * ns + f * nv + dim * node + c for t in range(nt) for f in (0, 1) for c in range(dim)])
-        check(node % n1, node // n1, r, mus)
+        mus = np.array([t * ns + f * nv + dim * node + k for t in range(nt) for f in (0, 1) for k in range(dim)])
+        dofs.append(mus)
+        vals.append(one(node % n1, node // n1, r, mus))
     for q in list(rng.integers(0, n1p * n1p, 4)) + [0, n1p * n1p - 1]:
         mus = np.array([t * ns + 2 * nv + q for t in range(nt)])
-        check(q % n1p, q // n1p, r - 1, mus)
+        dofs.append(mus)
+        vals.append(one(q % n1p, q // n1p, r - 1, mus))
+    return np.concatenate(dofs), np.concatenate(vals)
+
+
+def test_one_sweep_sampled_dofs(ctx):
+    """One sweep from a random iterate against the oracle's sweep at sampled dofs of every field
+    and time node (the rows of the tiled kernel's 4x16 last block row and of its pressure scaling
+    included), with the finest level on one wave per patch."""
+    S = ctx['S']
+    b = W.random_vector(S.n, 911)
+    d0 = W.random_vector(S.n, 912)
+    d1 = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 1))
+    mus, ref = sampled_sweep(ctx, b, d0, 913)
+    assert np.all(np.abs(d1[mus] - ref) <= 1e-10 * np.maximum(1.0, np.abs(ref))), d1[mus] - ref
 
 
 def test_solve_true_residual_through_the_oracle_operator(ctx):
@@ -147,4 +157,46 @@ def test_solve_true_residual_through_the_oracle_operator(ctx):
     info = S.solve(to_dev(F), x, rtol=1e-8)
     assert info['converged'] == 1
     res = np.linalg.norm(F - apply_rows(ctx, to_host(x)))
+    assert res <= 1e-8 * np.linalg.norm(F) * (1 + 1e-6), (res, info)
+
+
+SWEEP_TOL = {'fp32': 1e-5, 'bf16': 5e-2}  # one sweep, relative to the largest sampled entry
+
+
+@pytest.fixture(scope='module', params=['fp32', 'bf16'])
+def ctx_mixed(ctx, request):
+    """The same workload with FP32 or BF16 storage of the patch solves (FP64 sums, FP64 FGMRES)."""
+    from paper_2303_06742_amd import capi
+    print(f"[setup] {CFG.name} {request.param} (full size)", flush=True)
+    S = capi.Solver(CFG, precision=request.param)
+    yield dict(ctx, S=S, precision=request.param)
+    S.close()
+
+
+def test_mixed_sweep_sampled_dofs(ctx_mixed):
+    """One sweep with the stored patch solves rounded to FP32 or BF16 against the oracle's FP64
+    sweep at the sampled dofs of test_one_sweep_sampled_dofs, to the storage precision's per-sweep
+    tolerance (relative to the largest sampled entry)."""
+    c = ctx_mixed
+    S = c['S']
+    b = W.random_vector(S.n, 931)
+    d0 = W.random_vector(S.n, 932)
+    d1 = to_host(S.smooth(S.levels - 1, to_dev(b), to_dev(d0), 1))
+    mus, ref = sampled_sweep(c, b, d0, 933)
+    e = np.abs(d1[mus] - ref).max() / np.abs(ref).max()
+    print(f"[full size {c['precision']} sweep] rel_err={e:.2e}", flush=True)
+    assert e < SWEEP_TOL[c['precision']], e
+
+
+def test_mixed_solve_true_residual(ctx_mixed):
+    """FP64 FGMRES with the FP32 or BF16 patch solves reaches the FP64 path's stopping test on the
+    true residual, computed through the oracle's operator."""
+    S = ctx_mixed['S']
+    F = W.random_vector(S.n, 941)
+    x = S.empty()
+    info = S.solve(to_dev(F), x, rtol=1e-8)
+    assert info['converged'] == 1
+    res = np.linalg.norm(F - apply_rows(ctx_mixed, to_host(x)))
+    print(f"[full size {ctx_mixed['precision']} solve] iters={info['iters']} rel_res={res / np.linalg.norm(F):.2e}",
+          flush=True)
     assert res <= 1e-8 * np.linalg.norm(F) * (1 + 1e-6), (res, info)
