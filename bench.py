@@ -292,10 +292,14 @@ def run_serve(args):
                 time.sleep(float(rng.exponential(1.0 / rate)))
             tickets.append(srv.submit(cfg, rhs[j], key=key + 1000 * hash(tag) % 1000000))
         lat, ok = [], 0
-        for t in tickets:
-            st, _, inf, l = srv.wait(t)
+        for k, t in enumerate(tickets):
+            # a request the server never finishes ends the run with an error instead of polling on
+            st, _, inf, l = srv.wait(t, timeout_s=600.0)
             ok += int(st == capi.STGMG_OK and inf['converged'] == 1)
             lat.append(l)
+            if (k + 1) % 40 == 0:
+                print(f"[bench] serve {tag}: {k + 1}/{len(tickets)} done after {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
         el = time.perf_counter() - t0
         srv.close()
         print(f"[bench] serve {tag}: {len(mix) / el:.2f} solves/s p50 {np.percentile(lat, 50):.0f} ms", file=sys.stderr,

@@ -206,12 +206,16 @@ class Server:
         """Error text of a finished request that failed ('' otherwise)."""
         return stgmg_server_message(self.s, ticket).decode(errors='replace')
 
-    def wait(self, ticket, poll_s=0.0005):
+    def wait(self, ticket, poll_s=0.0005, timeout_s=None):
+        """Poll until the request is done; TimeoutError after timeout_s seconds (None: no limit)."""
         import time
+        t0 = time.perf_counter()
         while True:
             r = self.poll(ticket)
             if r is not None:
                 return r
+            if timeout_s is not None and time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"server request {ticket} not done after {timeout_s} s")
             time.sleep(poll_s)
 
     def close(self):

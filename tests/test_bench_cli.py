@@ -1,0 +1,15 @@
+"""bench.py's command line without a GPU: a run on more than one GPU is refused with a message
+(the library has no multi-GPU path) and exit status 2."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, 'bench.py'), '--gpus', '2', '--steps', '1'],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert 'one GPU' in r.stderr
+    assert r.stdout.strip() == ''
