@@ -342,8 +342,8 @@ def main():
                     help="third equation: 'v' Problem 3.1, 'dtu' Problem B.1")
     ap.add_argument('--graph', type=int, default=-1, choices=[-1, 0, 1],
                     help='V-cycle as a captured HIP graph: -1 automatic (below 2^21 unknowns), 0 never, 1 always')
-    ap.add_argument('--waves', type=int, default=0, choices=[0, 1, 4],
-                    help='waves per patch of the tiled patch kernel: 0 by patch count or autotuned, 1 or 4')
+    ap.add_argument('--waves', type=int, default=0, choices=[0, 1, 2, 4],
+                    help='waves per patch of the tiled patch kernel: 0 by patch count or autotuned, 1, 2 or 4')
     ap.add_argument('--autotune', type=int, default=1, choices=[0, 1],
                     help='time the launch shapes of the patch and operator kernels at setup (default 1)')
     ap.add_argument('--no-cpu-baseline', action='store_true')

@@ -122,11 +122,11 @@ typedef struct {
   int32_t waves_per_patch; /* time_blocks = 3 only: wavefronts that apply one patch's tiles: 0 by the
                               patch count (4 on levels of fewer than 4,096 patches -- 8,192 for Schur
                               blocks of more than 96 rows -- and 1 on larger levels; see autotune), or
-                              1 or 4 on every level.  The same operator either way, up to the order of
-                              the sums. */
+                              1, 2 or 4 on every level.  The same operator either way, up to the order
+                              of the sums. */
   int32_t autotune;      /* 1: stgmg_setup times the candidate launch shapes on every level and keeps
-                            the fastest -- the waves per patch of the tiled patch solve (1 or 4, when
-                            waves_per_patch is 0) and the lanes per node of the level operator
+                            the fastest -- the waves per patch of the tiled patch solve (1, 2 or 4,
+                            when waves_per_patch is 0) and the lanes per node of the level operator
                             (2, 4, 8 or 16) -- adding a few milliseconds per level.  The results then
                             depend on the timing in their last bits (the order of sums), so two
                             handles of one problem may differ by rounding.  0: fixed rules. */
@@ -160,7 +160,7 @@ stgmg_status stgmg_query(const stgmg_handle* h, int32_t level, int64_t* n_dofs, 
                          int64_t* nnz, int64_t* hbm_bytes);
 
 /* Launch shapes that level `level` (as in stgmg_query) uses, after the setup's autotuning when
- * stgmg_params.autotune = 1: the wavefronts that apply one patch's symmetric tiles (1 or 4; 0 where
+ * stgmg_params.autotune = 1: the wavefronts that apply one patch's symmetric tiles (1, 2 or 4; 0 where
  * the level has no tiled patch solve) and the lanes per Q_r node of the level-operator kernel
  * (2, 4, 8 or 16; 0 where the level applies its operator from the CSR matrices).  Either output
  * pointer may be NULL. */

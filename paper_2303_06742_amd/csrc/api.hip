@@ -296,8 +296,8 @@ void check_params(const stgmg_params* p) {
   if (p->pressure != STGMG_PRESSURE_CONT && p->pressure != STGMG_PRESSURE_DISC)
     throw ApiError(STGMG_ERR_INVALID_ARG, "unknown pressure space");
   if (p->form != STGMG_FORM_V && p->form != STGMG_FORM_DTU) throw ApiError(STGMG_ERR_INVALID_ARG, "unknown formulation");
-  if (p->waves_per_patch != 0 && p->waves_per_patch != 1 && p->waves_per_patch != 4)
-    throw ApiError(STGMG_ERR_INVALID_ARG, "waves_per_patch must be 0, 1 or 4");
+  if (p->waves_per_patch != 0 && p->waves_per_patch != 1 && p->waves_per_patch != 2 && p->waves_per_patch != 4)
+    throw ApiError(STGMG_ERR_INVALID_ARG, "waves_per_patch must be 0, 1, 2 or 4");
   if (p->autotune != 0 && p->autotune != 1) throw ApiError(STGMG_ERR_INVALID_ARG, "autotune must be 0 or 1");
 }
 
@@ -453,7 +453,7 @@ void launch_patch_apply(stgmg_handle* h, LevelDev& L, const double* r) {
 
 // Autotuning (stgmg_params.autotune): on every smoothed level the candidate launch shapes are timed
 // with HIP events (one warm-up and three timed launches each, on zero vectors) and the fastest is
-// kept: the waves per patch of the tiled patch kernel (1 or 4, unless waves_per_patch fixes it)
+// kept: the waves per patch of the tiled patch kernel (1, 2 or 4, unless waves_per_patch fixes it)
 // and, on every level, the lanes per node of the operator kernel (2, 4, 8 or 16).
 void autotune(stgmg_handle* h) {
   hipEvent_t e0, e1;
@@ -478,7 +478,7 @@ void autotune(stgmg_handle* h) {
     if (L.sym && L.npatch > 0 && h->prm.waves_per_patch == 0) {
       float best = 0.f;
       int best_w = 1;
-      for (int w : {1, 4}) {
+      for (int w : {1, 2, 4}) {
         L.waves = w;
         const float ms = time3([&] { launch_patch_apply(h, L, L.r.p); });
         if (w == 1 || ms < best) {

@@ -41,7 +41,7 @@ struct NodeOpDev {
   const int32_t* ccol = nullptr;
   const double* c = nullptr;
 };
-// Launch shapes in effect: waves per patch of the tiled patch kernel (waves = 1 or 4 fixes it,
+// Launch shapes in effect: waves per patch of the tiled patch kernel (waves = 1, 2 or 4 fixes it,
 // else by patch count: four below 4,096 patches, 8,192 above 96 Schur rows) and lanes per node of
 // the operator kernel (o.lanes, else 4 in 2D and 8 in 3D).
 int red_sym_waves(int waves, int64_t npatch, int max_nr);

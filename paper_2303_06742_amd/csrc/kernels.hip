@@ -2305,7 +2305,7 @@ constexpr int64_t SYM_MULTI_BELOW = 4096;
 constexpr int SYM_LARGE_NR = 96;
 
 int red_sym_waves(int waves, int64_t npatch, int max_nr) {
-  if (waves == 1 || waves == 4) return waves;
+  if (waves == 1 || waves == 2 || waves == 4) return waves;
   int64_t multi = max_nr > SYM_LARGE_NR ? 2 * SYM_MULTI_BELOW : SYM_MULTI_BELOW;
   if (const char* e = std::getenv("STGMG_SYM_MULTI_BELOW")) multi = std::atoll(e);  // tuning
   return npatch < multi ? 4 : 1;
@@ -2347,6 +2347,9 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
     if (W == 4) {
       if (ntl) STGMG_SYM(true, 4);
       else STGMG_SYM(false, 4);
+    } else if (W == 2) {
+      if (ntl) STGMG_SYM(true, 2);
+      else STGMG_SYM(false, 2);
     } else {
       if (ntl) STGMG_SYM(true, 1);
       else STGMG_SYM(false, 1);

@@ -108,7 +108,7 @@ def test_bad_pointers_rejected_before_launch():
 
 def test_invalid_waves_rejected():
     c = capi()
-    p, _K = c.make_params(CONFIGS['c1'], waves=2)
+    p, _K = c.make_params(CONFIGS['c1'], waves=3)
     h = ctypes.c_void_p()
     assert c.stgmg_setup(ctypes.byref(p), None, ctypes.byref(h)) == c.STGMG_ERR_INVALID_ARG
     assert b"waves_per_patch" in c.stgmg_last_error()
