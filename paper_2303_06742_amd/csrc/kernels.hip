@@ -1771,10 +1771,12 @@ __global__ void dense_gemv_reduce_kernel(int n, int nchunk, const double* __rest
 
 // ---------------------------------------------------------------- large Gauss-Jordan
 // The same blocked Gauss-Jordan as gj_invert_kernel for one matrix too large
-// for a workgroup: per panel of nb columns, gj_large_panel factors the n x nb
-// panel in place (one workgroup), gj_large_swap applies the panel's row swaps to
-// the other columns and copies the pivot rows to Wb, gj_large_update performs
-// the rank-nb update over 2D tiles.  M is row-major n x n.
+// for a workgroup (M row-major n x n).  Per panel of nb columns: the panel is
+// copied column-major into a scratch buffer, gj_large_column eliminates it one
+// pivot column per launch over as many workgroups as the rows need (two
+// ping-pong buffers), gj_large_swap applies the panel's row swaps to the other
+// columns and copies the pivot rows to Wb, gj_large_update performs the rank-nb
+// update over 2D tiles, and the eliminated panel is copied back.
 __global__ void __launch_bounds__(1024) gj_large_rowscale_kernel(int n, double* __restrict__ M,
                                                                  double* __restrict__ scl) {
   const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
