@@ -1,5 +1,6 @@
-// Batched Gauss-Jordan inversion of the patch blocks that do not fit in LDS, with the
-// rank-16 updates of the trailing matrix on the matrix cores (v_mfma_f64_16x16x4f64).
+// Batched Gauss-Jordan inversion of the larger patch blocks (above 64 Schur rows, in particular
+// those that do not fit in LDS), with the rank-16 updates of the trailing matrix on the matrix
+// cores (v_mfma_f64_16x16x4f64).
 //
 // The operation is the exact inverse of each local block (the patch solve of Def. 4.2 and the
 // local operator of Alg. 4.1, inverted once at setup).  One workgroup inverts one matrix, held in
