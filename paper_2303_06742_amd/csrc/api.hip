@@ -338,7 +338,6 @@ size_t lds_per_block() {
 
 void vcycle(stgmg_handle* h, int l, const double* b, double* d);
 
-// reduced solves: all blocks of a level inverted by the kernel that holds a matrix in LDS
 // Kernel that inverts the reduced blocks (the node mass block and the Schur complements):
 // RED_INV_LDS  the whole matrix in LDS (workgroup kernel, complex blocks in complex arithmetic),
 // RED_INV_MFMA the matrix in global memory, trailing updates on MFMA (complex arithmetic),
