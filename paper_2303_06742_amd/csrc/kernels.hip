@@ -1013,8 +1013,9 @@ __device__ inline void sym_factors(double al, double be, double* m1r, double* m1
 }
 
 // Symmetric tiled storage of the Schur inverses: X = (D1 S D2)^{-1} = D2^{-1} S^{-1} D1^{-1} is
-// symmetric; its lower triangle is stored in the tiles of tile_layout.h (8x8 tiles I-major, the
-// last block row possibly as 4x16 tiles); a complex X as the Re tiles followed by the Im tiles.  One block per (batch item, kept eigenvalue); S^{-1} is read
+// symmetric; its lower triangle is stored in the tiles of tile_layout.h (off-diagonal 8x8 tiles
+// I-major, the diagonal blocks as triangles paired two to a tile, the last block row possibly as
+// 4x16 tiles); a complex X as the Re tiles followed by the Im tiles.  One block per (batch item, kept eigenvalue); S^{-1} is read
 // from the square scratch (column j of Re at soff + j * ldc, Im rows after ldr) and
 // symmetrised as (X + X^T) / 2.
 template <typename T>
@@ -1031,8 +1032,10 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
   const bool cp = tb.cplx[a] != 0;
   const int ldc = cp ? 2 * ldr : ldr;
   constexpr int P = 8 / int(sizeof(T));  // tiles interleaved per unit (tile_layout.h)
-  const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr), ntf2 = sym_full_slots(nr, P);
+  const int nh = sym_half_tiles(nr), ntf2 = sym_full_slots(nr, P);
   const int nsl = sym_slots(nr, P), Ilast = sym_nbk(nr) - 1;
+  const int nd = sym_nd(nr), noff = sym_off_tiles(nr), npair = sym_pair_tiles(nr), nof2 = sym_off_slots(nr, P);
+  const int ndl = sym_dlist(nr), ndp = sym_dlist_in_pair(nr), npd = npair + sym_diag_tiles(nr);
   double m1r, m1i, m2r, m2i;
   sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
   // 1/mu2 and 1/mu1 = -mu2
@@ -1058,19 +1061,37 @@ __global__ void __launch_bounds__(256) pack_red_sym_kernel(TimeBlockConsts tb, c
   for (int q = threadIdx.x; q < nsl * 64; q += blockDim.x) {
     const int t = q / (64 * P) * P + q % P, e = q % (64 * P) / P;  // slot and entry of position q
     int row = nr, col = nr;  // zero slots
+    const int r = e & 7, c = e >> 3;
+    int s = ndl;  // entry of the odd blocks' diagonal list held here, if below ndl
     if (t >= ntf2) {  // 4x16 tile of the last block row
       if (t - ntf2 < nh) {
         row = 8 * Ilast + (e & 3);
         col = 16 * (t - ntf2) + (e >> 2);
       }
-    } else if (t < ntf) {
-      int I = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while (I * (I + 1) / 2 > t) --I;
-      while ((I + 1) * (I + 2) / 2 <= t) ++I;
-      const int J = t - I * (I + 1) / 2;
-      row = 8 * I + (e & 7);
-      col = 8 * J + (e >> 3);
+    } else if (t < nof2) {  // off-diagonal tile (I, J), J < I
+      if (t < noff) {
+        int I = int((sqrt(8.0 * t + 1.0) + 1.0) * 0.5);
+        while (I * (I - 1) / 2 > t) --I;
+        while ((I + 1) * I / 2 <= t) ++I;
+        const int J = t - I * (I - 1) / 2;
+        row = 8 * I + r;
+        col = 8 * J + c;
+      }
+    } else if (t < nof2 + npair) {  // pair tile: block A at r >= c, block B transposed at r < c
+      const int A = 2 * (t - nof2), B = A + 1;
+      if (r >= c) {
+        row = 8 * A + r;
+        col = 8 * A + c;
+      } else if (B < nd) {
+        row = 8 * B + c;
+        col = 8 * B + r;
+      } else {
+        s = c * (c - 1) / 2 + r;
+      }
+    } else if (t < nof2 + npd) {  // diagonal tile
+      s = ndp + 64 * (t - nof2 - npair) + e;
     }
+    if (s < ndl) row = col = 16 * (s >> 3) + 8 + (s & 7);
     double vr = 0.0, vi = 0.0;
     if (row < nr && col < nr) {
       double ar, ai, br, bi;
@@ -1137,6 +1158,11 @@ __device__ inline double dpp_sum8(double v) { return dpp_sum_step(dpp_sum_step(d
 // The same over the 4 lanes of each quad.
 __device__ inline double dpp_sum4(double v) { return dpp_sum_step(dpp_sum_step(v, 0), 1); }
 
+// *p += v in LDS as one atomic add (ds_add_f64), for lanes of a wave that share an address.
+__device__ inline void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // P values of one unit of tiles (tile_layout.h) at byte offset voff: one 8-byte load per lane.
 template <typename T, bool NTL>
 __device__ inline void bld_unit(__amdgpu_buffer_rsrc_t rs, int voff, T* out) {
@@ -1157,19 +1183,21 @@ __device__ inline void bld_unit(__amdgpu_buffer_rsrc_t rs, int voff, T* out) {
   }
 }
 
-// y += X zt for one plane of symmetric tiles (ntf 8x8 tiles, then nh 4x16 tiles of the last
-// block row; layout and the FP32 pairing of tiles in tile_layout.h), by wave w of nw: it takes
-// the units (P tiles each) w, w + nw, ... of the 8x8 tiles and of the 4x16 tiles.  Lane
-// (r, c) = (lane % 8, lane / 8) of 8x8 tile (I, J) adds X[8I+r][8J+c] zt[8J+c] to its row
-// partial (summed over c when the wave leaves block row I) and, below the diagonal,
-// X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  Lane (r, c) =
-// (lane % 4, lane / 4) of 4x16 tile q does the same for row 8I+r, column 16q+c of the last block
-// row I, the transposed entry only left of the diagonal block (which the 4x16 tiles hold in
-// full).  zt and y are LDS vectors (re at [0, ldt), im at [ldt, 2 ldt), ldt >= 16 nh); y is this
-// wave's own buffer and must start at zero.
+// y += X zt for one plane of symmetric tiles (layout and the interleaving of P tiles per unit in
+// tile_layout.h), by wave w of nw: it takes the units w, w + nw, ... of each of the three
+// sections.  Lane (r, c) = (lane % 8, lane / 8) of the off-diagonal tile (I, J) adds
+// X[8I+r][8J+c] zt[8J+c] to its row partial (summed over c when the wave leaves block row I) and
+// X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  A pair tile's lanes do the same
+// for the triangle of their own diagonal block, with one row sum and one column sum per block; the
+// lanes that hold the diagonal list add x_ii zt_i to row i alone.  Lane (r, c) = (lane % 4,
+// lane / 4) of 4x16 tile q adds row 8I+r, column 16q+c of the last block row I, the transposed
+// entry only left of the diagonal block (which the 4x16 tiles hold in full).  The pair and
+// diagonal tiles have a loop of their own after the off-diagonal stream, so that the stream keeps
+// its registers.  zt and y are LDS vectors (re at [0, ldt), im at [ldt, 2 ldt), ldt =
+// 8 ceil(nr / 8)); y is this wave's own buffer and must start at zero.
 template <typename T, bool NTL, bool CP>
-__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int nh, const double* zt, int ldt,
-                                       double* y, int w, int nw) {
+__device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int nr, const double* zt, int ldt, double* y, int w,
+                                       int nw) {
   constexpr int P = 8 / int(sizeof(T));  // tiles per unit: one 8-byte load per lane
   constexpr int UB = 8 / P;                  // units per batch of 8 tiles
   const int lane = threadIdx.x & 63, rr = lane & 7, cc = lane >> 3;
@@ -1177,11 +1205,15 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int n
   const double* zi = zt + ldt;
   double* yr = y;
   double* yi = y + ldt;
-  const int ntf2 = (ntf + P - 1) / P * P, nh2 = (nh + P - 1) / P * P;
-  const int im = (ntf2 + nh2) * 64 * int(sizeof(T));
-  int I = 0, J = w * P;  // the wave's first tile I(I+1)/2 + J, J <= I
-  while (J > I) {
-    J -= I + 1;
+  const int nd = sym_nd(nr), noff = sym_off_tiles(nr), npair = sym_pair_tiles(nr);
+  const int npd = npair + sym_diag_tiles(nr), ndl = sym_dlist(nr), ndp = sym_dlist_in_pair(nr);
+  const int nh = sym_half_tiles(nr);
+  const int nof2 = sym_off_slots(nr, P), ntf2 = sym_full_slots(nr, P);
+  const int im = sym_slots(nr, P) * 64 * int(sizeof(T));
+  // off-diagonal tiles
+  int I = 1, J = w * P;  // the wave's first tile I(I-1)/2 + J, J < I
+  while (J >= I) {
+    J -= I;
     ++I;
   }
   int curI = I;
@@ -1198,13 +1230,13 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int n
     }
     rowr = rowi = 0.0;
   };
-  for (int u0 = w; u0 * P < ntf; u0 += UB * nw) {
+  for (int u0 = w; u0 * P < noff; u0 += UB * nw) {
     T xr[8], xi[8];
 #pragma unroll
     for (int b = 0; b < UB; ++b) {
       const int u = u0 + b * nw;
       const int e = (u * 64 + lane) * P * int(sizeof(T));
-      if (u * P < ntf) {
+      if (u * P < noff) {
         bld_unit<T, NTL>(rs, e, xr + b * P);
         if constexpr (CP) bld_unit<T, NTL>(rs, e + im, xi + b * P);
       } else {
@@ -1214,43 +1246,90 @@ __device__ inline void sym_tiles_apply(__amdgpu_buffer_rsrc_t rs, int ntf, int n
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      if ((u0 + (k / P) * nw) * P + k % P >= ntf) break;
+      if ((u0 + (k / P) * nw) * P + k % P >= noff) break;
       if (I != curI) {
         flush(curI);
         curI = I;
       }
       const double ar = double(xr[k]);
-      const double ai = CP ? double(xi[k]) : 0.0;
       const double zjr = zr[8 * J + cc];
+      const double zir = zr[8 * I + rr];
       if constexpr (CP) {
-        const double zji = zi[8 * J + cc];
+        const double ai = double(xi[k]);
+        const double zji = zi[8 * J + cc], zii = zi[8 * I + rr];
         rowr += ar * zjr - ai * zji;
         rowi += ar * zji + ai * zjr;
+        const double cr = dpp_sum8(ar * zir - ai * zii), ci = dpp_sum8(ar * zii + ai * zir);
+        if (rr == 0) {
+          yr[8 * J + cc] += cr;
+          yi[8 * J + cc] += ci;
+        }
       } else {
         rowr += ar * zjr;
-      }
-      if (J < I) {  // the transposed entry: column 8J + c of row 8I + r, summed over r
-        const double zir = zr[8 * I + rr];
-        if constexpr (CP) {
-          const double zii = zi[8 * I + rr];
-          const double cr = dpp_sum8(ar * zir - ai * zii), ci = dpp_sum8(ar * zii + ai * zir);
-          if (rr == 0) {
-            yr[8 * J + cc] += cr;
-            yi[8 * J + cc] += ci;
-          }
-        } else {
-          const double cr = dpp_sum8(ar * zir);
-          if (rr == 0) yr[8 * J + cc] += cr;
-        }
+        const double cr = dpp_sum8(ar * zir);
+        if (rr == 0) yr[8 * J + cc] += cr;
       }
       J += k % P == P - 1 ? P * nw - (P - 1) : 1;  // the next tile of this wave
-      while (J > I) {
-        J -= I + 1;
+      while (J >= I) {
+        J -= I;
         ++I;
       }
     }
   }
-  if (w * P < ntf) flush(curI);
+  if (w * P < noff) flush(curI);
+  // pair and diagonal tiles (units after the nof2 / P units of the off-diagonal section)
+  auto diag_entry = [&](int s, double ar, double ai) {  // x_ii of the list (s < ndl): y_i += x_ii zt_i
+    if (s < ndl) {
+      const int x = 16 * (s >> 3) + 8 + (s & 7);
+      if constexpr (CP) {
+        const double vr = zr[x], vi = zi[x];
+        yr[x] += ar * vr - ai * vi;
+        yi[x] += ar * vi + ai * vr;
+      } else {
+        yr[x] += ar * zr[x];
+      }
+    }
+  };
+  for (int u0 = w; u0 * P < npd; u0 += nw) {
+    T xr[P], xi[P];
+    const int e = ((nof2 / P + u0) * 64 + lane) * P * int(sizeof(T));
+    bld_unit<T, NTL>(rs, e, xr);
+    if constexpr (CP) bld_unit<T, NTL>(rs, e + im, xi);
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+      const int t = u0 * P + k;
+      if (t >= npd) break;
+      const double ar = double(xr[k]);
+      const double ai = CP ? double(xi[k]) : 0.0;
+      if (t < npair) {  // pair tile: block A at r >= c, block B transposed at r < c
+        const int A = 2 * t, B = A + 1;
+        const bool lo = rr >= cc;
+        if (lo || B < nd) {
+          // the entry couples i = base + r and j = base + c of the lane's block (block B's is
+          // stored transposed, which the symmetric coupling does not see): y_i += v zt_j and, off
+          // the diagonal, y_j += v zt_i, as LDS atomic adds (several lanes share each row)
+          const int base = lo ? 8 * A : 8 * B, i = base + rr, j = base + cc;
+          if constexpr (CP) {
+            const double zjr = zr[j], zji = zi[j];
+            lds_add(yr + i, ar * zjr - ai * zji);
+            lds_add(yi + i, ar * zji + ai * zjr);
+            if (rr != cc) {
+              const double zir = zr[i], zii = zi[i];
+              lds_add(yr + j, ar * zir - ai * zii);
+              lds_add(yi + j, ar * zii + ai * zir);
+            }
+          } else {
+            lds_add(yr + i, ar * zr[j]);
+            if (rr != cc) lds_add(yr + j, ar * zr[i]);
+          }
+        } else {  // no block B: the lanes r < c hold the diagonal list
+          diag_entry(cc * (cc - 1) / 2 + rr, ar, ai);
+        }
+      } else {  // diagonal tile
+        diag_entry(ndp + 64 * (t - npair) + lane, ar, ai);
+      }
+    }
+  }
   if (w * P >= nh) return;
   // 4x16 tiles of the last block row Ih = 2 nh - 1 (units after the ntf2 / P units of 8x8 tiles)
   constexpr int UH = 4 / P;  // units per batch of 4 tiles
@@ -1455,7 +1534,6 @@ template <typename T, bool NTL>
 __device__ inline void sym_apply_blocks(const TimeBlockConsts& tb, const RedPatch& P, int LDT,
                                         const T* __restrict__ inv, const double* zt, double* tt, int w, int W) {
   const int nblk = tb.nblk, nr = P.nr;
-  const int ntf = sym_full_tiles(nr), nh = sym_half_tiles(nr);
   const int nsl = sym_slots(nr, 8 / int(sizeof(T)));  // stored tiles per plane
   int64_t off = P.base + P.nsmall;
   for (int a = 0; a < nblk; ++a) {
@@ -1464,9 +1542,9 @@ __device__ inline void sym_apply_blocks(const TimeBlockConsts& tb, const RedPatc
     const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
     double* yw = tt + (int64_t(w) * nblk + a) * 2 * LDT;
     if (cp)
-      sym_tiles_apply<T, NTL, true>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, w, W);
+      sym_tiles_apply<T, NTL, true>(rs, nr, zt + (2 * a) * LDT, LDT, yw, w, W);
     else
-      sym_tiles_apply<T, NTL, false>(rs, ntf, nh, zt + (2 * a) * LDT, LDT, yw, w, W);
+      sym_tiles_apply<T, NTL, false>(rs, nr, zt + (2 * a) * LDT, LDT, yw, w, W);
     off += cnt;
   }
 }
@@ -1679,14 +1757,15 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
 }
 
 // Symmetric tiles: NW waves per patch (one on large levels, several where the level has too
-// few patches to fill the chip and a patch's serial chain sets the time); the register budget
-// is held to STGMG_SYM_WAVES waves per
-// SIMD (the kernel is bound by HBM streams, which want many waves in flight).
-#ifndef STGMG_SYM_WAVES
-#define STGMG_SYM_WAVES 6
-#endif
+// few patches to fill the chip and a patch's serial chain sets the time).  The register budget
+// is held to 6 waves per SIMD (80 VGPRs) for the one-wave FP64 and BF16 kernels: the kernel is
+// bound by HBM streams, which want many waves in flight.  The FP32 kernels and the several-wave
+// ones do not fit in 80 VGPRs without spilling; they get 5 waves (96 VGPRs), which the LDS of a
+// 59-row patch (7.6 KB, 21 waves per CU) nearly imposes anyway.
+template <typename T, int NW>
+constexpr int sym_waves_per_eu() { return NW == 1 && sizeof(T) != 4 ? 6 : 5; }
 template <typename T, bool NTL, int NW>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(STGMG_SYM_WAVES)))
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sym_waves_per_eu<T, NW>())))
 patch_apply_red_sym_kernel(TimeBlockConsts tb, int d, int xc, const int64_t* __restrict__ poff,
                            const int32_t* __restrict__ pdof, const int32_t* __restrict__ tpos,
                            const int32_t* __restrict__ pnu, const int64_t* __restrict__ ioff,

@@ -131,9 +131,10 @@ def test_reduced_storage_sizes_closed_form(d, r, k, N, kind):
         nr = nU + nP
         fixed += nn * ld4(nn) + nU * ld4(nP)
         nrl += nr * ld4(nr)
-        tiles += len(tile_blocks(nr))
-        tiles2 += len(pair_tiles(np.zeros(64 * len(tile_blocks(nr))), nr, 2)) // 64
-        tiles4 += len(pair_tiles(np.zeros(64 * len(tile_blocks(nr))), nr, 4)) // 64
+        ntl = len(tile_entries(nr)[0])
+        tiles += ntl
+        tiles2 += len(pair_tiles(np.zeros(64 * ntl), nr, 2)) // 64
+        tiles4 += len(pair_tiles(np.zeros(64 * ntl), nr, 4)) // 64
         max_nr, max_nn = max(max_nr, nr), max(max_nn, nn)
     assert (S['sum_red_fixed'], S['sum_nr_ldr'], S['max_nr'], S['max_nn']) == (fixed, nrl, max_nr, max_nn)
     assert S['sum_tiles'] == tiles and S['sum_tiles2'] == tiles2 and S['sum_tiles4'] == tiles4
@@ -146,50 +147,77 @@ def sym_factors(lam):
     return -1.0 / mu2, mu2
 
 
-def tile_blocks(nr):
-    """(row0, col0, rows, cols) of the stored tiles in order: 8x8 tiles (I, J), J <= I, I-major;
-    when the last block row holds at most 4 rows and the number nb of block rows is even, that
-    row as nb/2 tiles of 4x16 instead (the diagonal block in full)."""
+def tile_entries(nr):
+    """(row, col) of the 64 entries of each stored tile in order, (-1, -1) where the tile holds a
+    zero, the number of off-diagonal tiles and the number of 8x8 tiles.  Block rows of 8, nb of them; when the last one holds at
+    most 4 rows and nb is even it is stored last, as nb/2 tiles of 4x16 (entry (r, c) at 4c + r,
+    its diagonal block in full), and nd = nb - 1 block rows remain, else nd = nb.  Those are
+    stored as 8x8 tiles, entry (r, c) at 8c + r: the off-diagonal tiles (I, J), J < I, I-major;
+    then the pair tiles, pair k holding the lower triangle of diagonal block 2k at r >= c and
+    the strict lower triangle of block 2k+1 transposed at r < c; then the diagonal tiles.  The
+    diagonal entries of the odd blocks form one list, entry s being row 16(s // 8) + 8 + s % 8;
+    when nd is odd the last pair has no block 2k+1 and its lanes r < c hold the list's first 28
+    entries (s = c(c-1)/2 + r); the rest fill the diagonal tiles 64 to a tile."""
     nb = (nr + 7) // 8
     half = nb >= 2 and nb % 2 == 0 and nr - 8 * (nb - 1) <= 4
-    out = [(8 * I, 8 * J, 8, 8) for I in range(nb - 1 if half else nb) for J in range(I + 1)]
+    nd = nb - 1 if half else nb
+    ndl = 8 * (nd // 2)
+    ent = lambda row, col: (row, col) if row < nr and col < nr else (-1, -1)
+    lst = lambda s: ent(16 * (s // 8) + 8 + s % 8, 16 * (s // 8) + 8 + s % 8) if s < ndl else (-1, -1)
+    tiles = [[ent(8 * I + e % 8, 8 * J + e // 8) for e in range(64)] for I in range(nd) for J in range(I)]
+    for k in range((nd + 1) // 2):
+        A, B = 2 * k, 2 * k + 1
+        tile = []
+        for e in range(64):
+            r, c = e % 8, e // 8
+            if r >= c:
+                tile.append(ent(8 * A + r, 8 * A + c))
+            elif B < nd:
+                tile.append(ent(8 * B + c, 8 * B + r))
+            else:
+                tile.append(lst(c * (c - 1) // 2 + r))
+        tiles.append(tile)
+    s0 = 28 if nd % 2 else 0
+    tiles += [[lst(s0 + 64 * m + e) for e in range(64)] for m in range(-(-max(ndl - s0, 0) // 64))]
+    nfull = len(tiles)
     if half:
-        out += [(8 * (nb - 1), 16 * q, 4, 16) for q in range(nb // 2)]
-    return out
+        tiles += [[ent(8 * (nb - 1) + e % 4, 16 * q + e // 4) for e in range(64)] for q in range(nb // 2)]
+    return tiles, nd * (nd - 1) // 2, nfull
 
 
 def pack_tiles(X, nr):
-    """The tiles of tile_blocks(nr) of the symmetric X, each column-major (entry (r, c) at
-    rows * c + r); entries beyond nr are zero; X is symmetrised as (X + X^T)/2."""
-    nb = (nr + 7) // 8
-    Xs = np.zeros((8 * nb, 8 * nb), dtype=complex)
-    Xs[:nr, :nr] = 0.5 * (X + X.T)
-    return np.concatenate([Xs[r0:r0 + h, c0:c0 + w].reshape(-1, order='F') for r0, c0, h, w in tile_blocks(nr)])
+    """The stored tiles of tile_entries(nr) of the symmetric X, concatenated; X is symmetrised as
+    (X + X^T)/2."""
+    Xs = 0.5 * (X + X.T)
+    return np.array([Xs[row, col] if row >= 0 else 0.0 for tile in tile_entries(nr)[0] for row, col in tile])
 
 
 def pair_tiles(tiles, nr, P):
-    """The storage order with P tiles interleaved per unit (P = 2 for FP32, 4 for BF16 values): the 8x8 and
-    the 4x16 tile counts each padded with zero tiles to a multiple of P, then entry e of slot t
-    at (t // P * 64 + e) * P + t % P."""
-    blocks = tile_blocks(nr)
-    nf = sum(1 for b in blocks if b[2] == 8)
+    """The storage order with P tiles interleaved per unit (P = 2 for FP32, 4 for BF16 values): the
+    off-diagonal, the pair and diagonal, and the 4x16 tile counts each padded with zero tiles to a
+    multiple of P, then entry e of slot t at (t // P * 64 + e) * P + t % P."""
+    _, no, nf = tile_entries(nr)
     T = tiles.reshape(-1, 64)
     pad = lambda A: np.concatenate([A, np.zeros((-len(A) % P, 64), dtype=A.dtype)])
-    S = np.concatenate([pad(T[:nf]), pad(T[nf:])])
+    S = np.concatenate([pad(T[:no]), pad(T[no:nf]), pad(T[nf:])])
     return S.reshape(-1, P, 64).transpose(0, 2, 1).reshape(-1)
 
 
 def tile_apply(tiles, nr, zt):
-    """y = X zt from the stored tiles the way a wave does it: lane (r, c) of a tile adds
-    X[row][col] zt[col] to the row and, for columns left of the tile row's diagonal block,
-    X[row][col] zt[row] to the column."""
+    """y = X zt from the stored tiles the way the waves do it: every entry X[row][col] adds
+    X[row][col] zt[col] to the row and, off the diagonal and outside the diagonal block that the
+    4x16 tiles hold in full, X[row][col] zt[row] to the column."""
     nb = (nr + 7) // 8
     y = np.zeros(8 * nb, dtype=complex)
-    for t, (r0, c0, h, w) in enumerate(tile_blocks(nr)):
-        T = tiles[64 * t:64 * t + 64].reshape(h, w, order='F')
-        y[r0:r0 + h] += T @ zt[c0:c0 + w]
-        below = np.arange(c0, c0 + w) < r0 // 8 * 8
-        y[c0:c0 + w] += np.where(below, T.T @ zt[r0:r0 + h], 0.0)
+    entries, _, nfull = tile_entries(nr)
+    for t, tile in enumerate(entries):
+        for e, (row, col) in enumerate(tile):
+            if row < 0:
+                continue
+            v = tiles[64 * t + e]
+            y[row] += v * zt[col]
+            if row != col and (t < nfull or col < 8 * (nb - 1)):
+                y[col] += v * zt[row]
     return y
 
 
@@ -205,14 +233,27 @@ def test_tile_layout_positions(nr, P):
     tiles = pack_tiles(X, nr).real
     stored = pair_tiles(tiles, nr, P)
     assert np.count_nonzero(stored) == np.count_nonzero(tiles)
+    seen = set()
     for row in range(nr):
         for col in range(row + 1):
             e = LIB.stgmg_host_sym_slot_elem(nr, P, row, col)
             assert stored[e] == 0.5 * (X[row, col] + X[col, row]), (row, col, e)
+            seen.add(e)
+    assert len(seen) == nr * (nr + 1) // 2
     nb = (nr + 7) // 8
-    half = any(h == 4 for _, _, h, _ in tile_blocks(nr))
-    assert half == (nb % 2 == 0 and nr - 8 * (nb - 1) <= 4)
-    assert len(tiles) == 64 * (nb * (nb - 1) // 2 + nb // 2 if half else nb * (nb + 1) // 2)
+    entries, noff, nfull = tile_entries(nr)
+    half = len(entries) > nfull
+    assert half == (nb >= 2 and nb % 2 == 0 and nr - 8 * (nb - 1) <= 4)
+    # every lower entry is held once, except the upper triangle of the diagonal block in 4x16 tiles
+    held = [(r, c) for tile in entries for r, c in tile if r >= 0]
+    assert len(held) == len(set(held))
+    assert {(r, c) for r, c in held if r >= c} == {(r, c) for r in range(nr) for c in range(r + 1)}
+    assert all(r // 8 == nb - 1 and c // 8 == nb - 1 for r, c in held if r < c)
+    # the stored 8x8 tiles: the triangles of nd diagonal blocks take ceil(nd/2) pair tiles plus
+    # the diagonal list of the odd blocks beyond what a last, half-empty pair holds
+    nd = nb - 1 if half else nb
+    ndiag = -(-max(8 * (nd // 2) - (28 if nd % 2 else 0), 0) // 64)
+    assert noff == nd * (nd - 1) // 2 and nfull == noff + (nd + 1) // 2 + ndiag
 
 
 @pytest.mark.parametrize("d,N,k,kind", [(2, 4, 2, 'vertex'), (3, 2, 1, 'cell'), (2, 2, 1, 'vertex')])
@@ -240,7 +281,7 @@ def test_symmetric_tiles_reproduce_the_schur_inverse(d, N, k, kind):
             assert np.abs(Ssym - Ssym.T).max() <= 1e-13 * np.abs(Ssym).max()
             X = np.linalg.inv(Ssym)
             tiles = pack_tiles(X, nr)
-            assert len(tiles) == 64 * len(tile_blocks(nr))
+            assert len(tiles) == 64 * len(tile_entries(nr)[0])
             z = rng.standard_normal(nr) + 1j * rng.standard_normal(nr)
             zt = np.zeros(8 * ((nr + 7) // 8), dtype=complex)
             zt[:nr] = np.diag(D1) * z
