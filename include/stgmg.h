@@ -112,8 +112,9 @@ typedef struct {
                             3: as 2, with each Schur inverse stored through its symmetric form:
                                X = (D1 S D2)^{-1}, D1 = diag(I, -lam^{-1/2}), D2 = diag(I, lam^{1/2})
                                on the (U, P) rows, is symmetric, and its lower triangle is kept in
-                               8x8 tiles (a last block row of at most 4 rows in 4x16 tiles; about
-                               0.58x the values of 2 at 59 rows; FP32 storage pairs the tiles
+                               64-value tiles: off-diagonal 8x8 tiles, the diagonal 8x8 blocks as
+                               triangles two to a tile, a last block row of at most 4 rows in 4x16
+                               tiles (about 0.52x the values of 2 at 59 rows; FP32 storage pairs the tiles
                                so that a lane loads 8 bytes, and keeps 2 for Schur blocks of
                                more than 96 rows, where the square layout measured faster).
                             Default of the Python workloads: 3. */

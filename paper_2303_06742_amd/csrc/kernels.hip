@@ -997,6 +997,14 @@ __global__ void __launch_bounds__(512) patch_apply_tb_kernel(TimeBlockConsts tb,
 // Thread layout of the S^{-1} product: W column ranges of blockDim / W threads, R consecutive
 // rows per thread (one 16-byte load per column).
 constexpr int RED_MAXB = 2;
+// LDS planes of the kept eigenvalues in the reduced solve: Re of block a at plane red_pl(tb, a),
+// its Im in the next plane if the eigenvalue is complex (a real one has none); red_npl in all.
+__host__ __device__ inline int red_pl(const TimeBlockConsts& tb, int a) {
+  int p = 0;
+  for (int b = 0; b < a; ++b) p += tb.cplx[b] ? 2 : 1;
+  return p;
+}
+__host__ __device__ inline int red_npl(const TimeBlockConsts& tb) { return red_pl(tb, tb.nblk); }
 
 // Balanced symmetrising factors of a Schur complement S(lam) = [[lam^2 rho M + A, C^T],
 // [-lam C, lam c0 M_p + B]]: with mu2 = sqrt(lam) (principal root) and mu1 = -1/mu2,
@@ -1418,8 +1426,8 @@ __device__ inline RedPatch red_patch(const TimeBlockConsts& tb, int d, int64_t p
 
 // Front of the reduced solve, threads t0, t0 + nth, ... of the patch's thread set, sync() between
 // phases: r_P gathered into rl (n), transformed to the eigenvalue blocks in sv ([a][re, im][ns]),
-// then w = (rho M)^{-1} r_u per component into wv ([a][re, im][nU]) and z = [r_v + lam r_u;
-// r_p + G r_u] into z ([a][re, im][ldr]).  rl may share memory with wv and z (it is dead once sv
+// then w = (rho M)^{-1} r_u per component into wv (planes of nU, red_pl) and z = [r_v + lam r_u;
+// r_p + G r_u] into z (planes of ldr).  rl may share memory with wv and z (it is dead once sv
 // is formed); the caller synchronises after the last phase.
 template <typename T, bool NTL, typename Sync>
 __device__ inline void red_front(const TimeBlockConsts& tb, int d, const RedPatch& P, const int32_t* __restrict__ pdof,
@@ -1457,6 +1465,9 @@ __device__ inline void red_front(const TimeBlockConsts& tb, int d, const RedPatc
   // items [0, nU): w = (rho M)^{-1} r_u per component and z_U = r_v + lam r_u;
   // items [nU, nr): z_P = r_p + G r_u
   const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + P.base, P.nsmall);
+  int pl[RED_MAXB];
+#pragma unroll
+  for (int a = 0; a < RED_MAXB; ++a) pl[a] = red_pl(tb, a);
   for (int it = t0; it < nr; it += nth) {
     double ar[RED_MAXB] = {0, 0}, ai[RED_MAXB] = {0, 0};
     const bool vel = it < nU;
@@ -1494,20 +1505,23 @@ __device__ inline void red_front(const TimeBlockConsts& tb, int d, const RedPatc
       if (a < nblk) {
         if (vel) {
           const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
+          const bool c = tb.cplx[a] != 0;
           const double ur = sv[(2 * a) * ns + it], ui = sv[(2 * a + 1) * ns + it];
-          wv[(2 * a) * nU + it] = ar[a];
-          wv[(2 * a + 1) * nU + it] = ai[a];
-          z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + al * ur - be * ui;
-          z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + al * ui + be * ur;
+          wv[pl[a] * nU + it] = ar[a];
+          z[pl[a] * ldr + it] = sv[(2 * a) * ns + nU + it] + al * ur - be * ui;
+          if (c) {
+            wv[(pl[a] + 1) * nU + it] = ai[a];
+            z[(pl[a] + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + al * ui + be * ur;
+          }
         } else {
-          z[(2 * a) * ldr + it] = sv[(2 * a) * ns + nU + it] + ar[a];
-          z[(2 * a + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + ai[a];
+          z[pl[a] * ldr + it] = sv[(2 * a) * ns + nU + it] + ar[a];
+          if (tb.cplx[a]) z[(pl[a] + 1) * ldr + it] = sv[(2 * a + 1) * ns + nU + it] + ai[a];
         }
       }
   }
 }
 
-// Symmetric tiles: zt = D1 z ([a][re, im][LDT], zero padded beyond nr).
+// Symmetric tiles: zt = D1 z (planes of LDT, zero padded beyond nr).
 __device__ inline void sym_scale_z(const TimeBlockConsts& tb, const RedPatch& P, int LDT, const double* z, double* zt,
                                    int t0, int nth) {
   const int nblk = tb.nblk, nr = P.nr, nU = P.nU, ldr = P.ldr;
@@ -1517,19 +1531,21 @@ __device__ inline void sym_scale_z(const TimeBlockConsts& tb, const RedPatch& P,
       if (a < nblk) {
         double m1r, m1i, m2r, m2i;
         sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
-        double vr = x < nr ? z[(2 * a) * ldr + x] : 0.0, vi = x < nr ? z[(2 * a + 1) * ldr + x] : 0.0;
+        const int pa = red_pl(tb, a);
+        const bool c = tb.cplx[a] != 0;
+        double vr = x < nr ? z[pa * ldr + x] : 0.0, vi = x < nr && c ? z[(pa + 1) * ldr + x] : 0.0;
         if (x >= nU) {
           const double ur = vr * m1r - vi * m1i, ui = vr * m1i + vi * m1r;
           vr = ur;
           vi = ui;
         }
-        zt[(2 * a) * LDT + x] = vr;
-        zt[(2 * a + 1) * LDT + x] = vi;
+        zt[pa * LDT + x] = vr;
+        if (c) zt[(pa + 1) * LDT + x] = vi;
       }
 }
 
 // Symmetric tiles: wave w of W adds X D1 z of every kept eigenvalue into its own partial
-// products tt + w * 2 nblk LDT ([a][re, im][LDT], zeroed by the caller).
+// products tt + w * npl LDT (planes of LDT, zeroed by the caller).
 template <typename T, bool NTL>
 __device__ inline void sym_apply_blocks(const TimeBlockConsts& tb, const RedPatch& P, int LDT,
                                         const T* __restrict__ inv, const double* zt, double* tt, int w, int W) {
@@ -1540,11 +1556,12 @@ __device__ inline void sym_apply_blocks(const TimeBlockConsts& tb, const RedPatc
     const bool cp = tb.cplx[a] != 0;
     const int64_t cnt = int64_t(cp ? 2 : 1) * nsl * 64;
     const __amdgpu_buffer_rsrc_t rs = patch_rsrc(inv + off, cnt);
-    double* yw = tt + (int64_t(w) * nblk + a) * 2 * LDT;
+    const int pa = red_pl(tb, a);
+    double* yw = tt + (int64_t(w) * red_npl(tb) + pa) * LDT;
     if (cp)
-      sym_tiles_apply<T, NTL, true>(rs, nr, zt + (2 * a) * LDT, LDT, yw, w, W);
+      sym_tiles_apply<T, NTL, true>(rs, nr, zt + pa * LDT, LDT, yw, w, W);
     else
-      sym_tiles_apply<T, NTL, false>(rs, nr, zt + (2 * a) * LDT, LDT, yw, w, W);
+      sym_tiles_apply<T, NTL, false>(rs, nr, zt + pa * LDT, LDT, yw, w, W);
     off += cnt;
   }
 }
@@ -1560,10 +1577,11 @@ __device__ inline void sym_scale_t(const TimeBlockConsts& tb, const RedPatch& P,
         const int ww = q / nP, x = nU + q % nP;
         double m1r, m1i, m2r, m2i;
         sym_factors(tb.lam[2 * a], tb.lam[2 * a + 1], &m1r, &m1i, &m2r, &m2i);
-        double* yb = tt + (int64_t(ww) * nblk + a) * 2 * LDT;
-        const double vr = yb[x], vi = yb[LDT + x];
+        const bool c = tb.cplx[a] != 0;
+        double* yb = tt + (int64_t(ww) * red_npl(tb) + red_pl(tb, a)) * LDT;
+        const double vr = yb[x], vi = c ? yb[LDT + x] : 0.0;
         yb[x] = vr * m2r - vi * m2i;
-        yb[LDT + x] = vr * m2i + vi * m2r;
+        if (c) yb[LDT + x] = vr * m2i + vi * m2r;
       }
 }
 
@@ -1580,15 +1598,17 @@ __device__ inline void red_back(const TimeBlockConsts& tb, const RedPatch& P, in
 #pragma unroll
     for (int a = 0; a < RED_MAXB; ++a)
       if (a < nblk) {
+        const bool c = tb.cplx[a] != 0;
+        const int pa = red_pl(tb, a), npl = red_npl(tb);
         double t_r = 0.0, t_i = 0.0;
         for (int ww = 0; ww < W; ++ww) {
-          t_r += tv[(int64_t(ww) * nblk + a) * 2 * LDT + ii];
-          t_i += tv[(int64_t(ww) * nblk + a) * 2 * LDT + LDT + ii];
+          t_r += tv[(int64_t(ww) * npl + pa) * LDT + ii];
+          if (c) t_i += tv[(int64_t(ww) * npl + pa + 1) * LDT + ii];
         }
         if (i < nU) {
           const double al = tb.lam[2 * a], be = tb.lam[2 * a + 1];
-          hr[a] = al * t_r - be * t_i - wv[(2 * a) * nU + i];
-          hi[a] = al * t_i + be * t_r - wv[(2 * a + 1) * nU + i];
+          hr[a] = al * t_r - be * t_i - wv[pa * nU + i];
+          hi[a] = c ? al * t_i + be * t_r - wv[(pa + 1) * nU + i] : 0.0;
         } else {
           hr[a] = t_r;
           hi[a] = t_i;
@@ -1623,12 +1643,13 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
   const RedPatch P = red_patch(tb, d, p, poff, pnu, ioff);
   const int nblk = tb.nblk;
   const int n = P.n, ns = P.ns, nU = P.nU, nr = P.nr, ldr = P.ldr;
-  // region A: r_P, later w [a][re, im][nU] and z [a][re, im][ldr];
-  // region B: transformed right-hand sides [a][re, im][ns], later W partial images [w][a][re, im][ldr]
-  const int szA = max(n, 2 * nblk * (nU + ldr));
+  // region A: r_P, later w (npl planes of nU) and z (npl planes of ldr);
+  // region B: transformed right-hand sides [a][re, im][ns], later W partial images (W npl planes)
+  const int npl = red_npl(tb);
+  const int szA = max(n, npl * (nU + ldr));
   double* rl = sm;
   double* wv = sm;
-  double* z = sm + 2 * nblk * nU;
+  double* z = sm + npl * nU;
   double* sv = sm + szA;
   double* tv = sm + szA;
   red_front<T, NTL>(tb, d, P, pdof, inv, r, rl, sv, wv, z, int(threadIdx.x), int(blockDim.x), BlockSync());
@@ -1636,11 +1657,11 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
   // symmetric tiles (one wave): t = D2 X D1 z per kept eigenvalue into region B, stride LDT
   const int LDT = SYM ? 8 * ((nr + 7) >> 3) : ldr;
   if constexpr (SYM) {
-    // W waves: wave w's products at tv + w * 2 nblk LDT ([a][re, im][LDT], the partial images
-    // the back-transform sums), then D1 z shared by all waves
+    // W waves: wave w's products at tv + w * npl LDT (planes of LDT, the partial images the
+    // back-transform sums), then D1 z shared by all waves
     double* tt = tv;
-    double* zt = tv + int64_t(W) * 2 * nblk * LDT;  // [a][re, im][LDT]: D1 z, zero padded
-    for (int x = threadIdx.x; x < int64_t(W) * 2 * nblk * LDT; x += blockDim.x) tt[x] = 0.0;
+    double* zt = tv + int64_t(W) * npl * LDT;  // planes of LDT: D1 z, zero padded
+    for (int x = threadIdx.x; x < int64_t(W) * npl * LDT; x += blockDim.x) tt[x] = 0.0;
     sym_scale_z(tb, P, LDT, z, zt, int(threadIdx.x), int(blockDim.x));
     __syncthreads();
     sym_apply_blocks<T, NTL>(tb, P, LDT, inv, zt, tt, int(threadIdx.x >> 6), W);
@@ -1654,10 +1675,10 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
     const int voff = i0 * int(sizeof(T));
     int64_t off = P.base + P.nsmall;
     for (int a = 0; a < nblk; ++a) {
-      const double* zr = z + (2 * a) * ldr;
-      const double* zi = z + (2 * a + 1) * ldr;
-      double* twr = tv + (int64_t(w) * nblk + a) * 2 * ldr;
-      double* twi = twr + ldr;
+      const double* zr = z + red_pl(tb, a) * ldr;
+      const double* zi = zr + ldr;  // complex blocks only
+      double* twr = tv + (int64_t(w) * npl + red_pl(tb, a)) * ldr;
+      double* twi = twr + ldr;  // complex blocks only
       const bool cp = tb.cplx[a] != 0;
       const int64_t cnt = int64_t(nr) * (cp ? 2 * ldr : ldr);
       if (w < W && i0 < ldr) {
@@ -1694,10 +1715,7 @@ __device__ __forceinline__ void patch_apply_red_body(TimeBlockConsts tb, int d, 
             for (int q = 0; q < R; ++q) accr[q] += double(v0[q]) * zr[jt + t];
           }
 #pragma unroll
-          for (int q = 0; q < R; ++q) {
-            twr[i0 + q] = accr[q] + acci[q];
-            twi[i0 + q] = 0.0;
-          }
+          for (int q = 0; q < R; ++q) twr[i0 + q] = accr[q] + acci[q];
         } else {
           const int cb = 2 * ldr * int(sizeof(T)), ib = ldr * int(sizeof(T));  // column, Im offset
           const int vo = voff + j0 * cb;
@@ -1758,12 +1776,12 @@ __global__ void __launch_bounds__(512) patch_apply_red_kernel(TimeBlockConsts tb
 
 // Symmetric tiles: NW waves per patch (one on large levels, several where the level has too
 // few patches to fill the chip and a patch's serial chain sets the time).  The register budget
-// is held to 6 waves per SIMD (80 VGPRs) for the one-wave FP64 and BF16 kernels: the kernel is
-// bound by HBM streams, which want many waves in flight.  The FP32 kernels and the several-wave
-// ones do not fit in 80 VGPRs without spilling; they get 5 waves (96 VGPRs), which the LDS of a
-// 59-row patch (7.6 KB, 21 waves per CU) nearly imposes anyway.
+// is held to 6 waves per SIMD (80 VGPRs) for the one-wave kernels: the kernel is bound by the
+// HBM loads in flight, and the LDS of a 59-row dG(2) patch (6.1 KB) allows 26 waves per CU.
+// The several-wave kernels of the small levels do not fit in 80 VGPRs without spilling; they
+// get 5 waves (96 VGPRs).
 template <typename T, int NW>
-constexpr int sym_waves_per_eu() { return NW == 1 && sizeof(T) != 4 ? 6 : 5; }
+constexpr int sym_waves_per_eu() { return NW == 1 ? 6 : 5; }
 template <typename T, bool NTL, int NW>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(sym_waves_per_eu<T, NW>())))
 patch_apply_red_sym_kernel(TimeBlockConsts tb, int d, int xc, const int64_t* __restrict__ poff,
@@ -2333,10 +2351,10 @@ void k_patch_apply_tb_f32(hipStream_t st, int64_t npatch, int max_np, const Time
 
 // Reduced time-block solves: LDS regions A = max(n_P, 2 nblk (nU + ldr)) and
 // B = max(2 nblk ns, W 2 nblk ldr) doubles (bounds from the maxima over the patches).
-static size_t red_lds(int max_np, int max_nu, int max_nr, int nt, int nblk, int W) {
+static size_t red_lds(int max_np, int max_nu, int max_nr, int nt, int nblk, int npl, int W) {
   const size_t ldr = inv_ld(max_nr), ns = max_np / nt;
-  const size_t a = std::max<size_t>(max_np, 2 * size_t(nblk) * (max_nu + ldr));
-  const size_t b = std::max<size_t>(2 * size_t(nblk) * ns, size_t(W) * 2 * nblk * ldr);
+  const size_t a = std::max<size_t>(max_np, size_t(npl) * (max_nu + ldr));
+  const size_t b = std::max<size_t>(2 * size_t(nblk) * ns, size_t(W) * npl * ldr);
   return (a + b) * sizeof(double);
 }
 
@@ -2403,13 +2421,14 @@ static void launch_red(hipStream_t st, int64_t npatch, int max_np, int max_nu, i
   const int rr = red_rows(sizeof(T) == 4, max_nr);
   int th, W;
   red_layout(max_nr, rr, &th, &W);
-  size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, W);
+  const int npl = dev::red_npl(tb);
+  size_t lds = red_lds(max_np, max_nu, max_nr, tb.nt, tb.nblk, npl, W);
   if (sym) {  // W waves per patch; region B holds W partial products and D1 z at stride 8 ceil(nr / 8)
     W = red_sym_waves(waves, npatch, max_nr);
     th = 64 * W;
     const size_t ldr = inv_ld(max_nr), ns = max_np / tb.nt, ldt = 8 * ((max_nr + 7) / 8);
-    const size_t a = std::max<size_t>(max_np, 2 * size_t(tb.nblk) * (max_nu + ldr));
-    const size_t b = std::max<size_t>(2 * size_t(tb.nblk) * ns, size_t(W + 1) * 2 * size_t(tb.nblk) * ldt);
+    const size_t a = std::max<size_t>(max_np, size_t(npl) * (max_nu + ldr));
+    const size_t b = std::max<size_t>(2 * size_t(tb.nblk) * ns, size_t(W + 1) * npl * ldt);
     lds = (a + b) * sizeof(double);
   }
   bool ntl = true;
