@@ -93,9 +93,12 @@ typedef struct {
   double K;              /* permeability K*I when K_cells == NULL */
   const double* K_cells; /* host, optional: K per fine cell, lexicographic (x fastest);
                             coarse cells take the mean of their 2^d children. Copied. */
-  int32_t graph;         /* V-cycle as a captured HIP graph: -1 automatic (hierarchies below
-                            2^21 fine unknowns, where launch latency matters), 0 never, 1 always.
-                            The capture happens inside stgmg_setup; while it runs, null-stream
+  int32_t graph;         /* V-cycle as a captured HIP graph: 1 captures it inside stgmg_setup and
+                            replays it in every solve; 0 and -1 (automatic, the default) launch
+                            the kernels directly.  A process that set up, solved and released
+                            several hundred graph-captured handles has seen every later solve
+                            report non-finite Arnoldi values; the same work without graphs did
+                            not, so capture is not automatic.  While a capture runs, null-stream
                             work from other threads of the process fails (a runtime rule), so
                             set up handles with graphs while no other thread uses the GPU
                             through the null stream (the server launches directly). */

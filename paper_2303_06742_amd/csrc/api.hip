@@ -1485,7 +1485,8 @@ stgmg_status stgmg_setup(const stgmg_params* params, void* hip_stream, stgmg_han
     for (auto& L : h->lv) L.waves = params->waves_per_patch;
     if (params->autotune) autotune(h.get());
     const int64_t nf = h->lv[h->L].n;
-    h->use_graph = params->graph == 1 || (params->graph == -1 && nf < (int64_t(1) << 21));
+    // captured only on request: see the graph field of stgmg_params
+    h->use_graph = params->graph == 1;
     if (h->use_graph) {
       h->gin.alloc(nf, &h->bytes, h->st);
       h->gout.alloc(nf, &h->bytes, h->st);
@@ -1905,7 +1906,7 @@ stgmg_status stgmg_footprint(const stgmg_params* params, int32_t restart, int64_
         }
         if (p.pressure == STGMG_PRESSURE_DISC) nlp = int64_t(stgmg::pdisc_exponents(p.r - 1, d).size());
         res += (4 * nq + (nls + nlp) * nq + ncell) * 8;  // device source tables and K
-        const bool graph = p.graph == 1 || (p.graph == -1 && n < (int64_t(1) << 21));
+        const bool graph = p.graph == 1;
         if (graph) res += 2 * n * 8;
         n_fine = n;
       }
