@@ -30,9 +30,17 @@ METRIC = "GMRES-GMG solves/s and V-cycle DoF/s at 1e-8 rel. residual; p50/p99 la
 
 
 def kernel_source_hash():
+    """sha256 prefix of the code of kernels.hip: comments (from // to the end of the line) and
+    blank lines dropped, so that a counter record stays tied to the code it was measured on
+    through edits of comments alone (the file holds no // inside string literals)."""
     import hashlib
-    with open(os.path.join(ROOT, 'paper_2303_06742_amd', 'csrc', 'kernels.hip'), 'rb') as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    code = []
+    with open(os.path.join(ROOT, 'paper_2303_06742_amd', 'csrc', 'kernels.hip')) as f:
+        for line in f:
+            c = line.split('//', 1)[0].rstrip()
+            if c:
+                code.append(c)
+    return hashlib.sha256('\n'.join(code).encode()).hexdigest()[:16]
 
 
 def measured_traffic(workload, precision, role='patch'):

@@ -1195,9 +1195,10 @@ __device__ inline void bld_unit(__amdgpu_buffer_rsrc_t rs, int voff, T* out) {
 // tile_layout.h), by wave w of nw: it takes the units w, w + nw, ... of each of the three
 // sections.  Lane (r, c) = (lane % 8, lane / 8) of the off-diagonal tile (I, J) adds
 // X[8I+r][8J+c] zt[8J+c] to its row partial (summed over c when the wave leaves block row I) and
-// X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  A pair tile's lanes do the same
-// for the triangle of their own diagonal block, with one row sum and one column sum per block; the
-// lanes that hold the diagonal list add x_ii zt_i to row i alone.  Lane (r, c) = (lane % 4,
+// X[8I+r][8J+c] zt[8I+r] to column 8J+c (summed over r at once).  A pair tile's lanes add the
+// same two terms for the entry of their own diagonal block with LDS atomic adds (lanes of one row
+// or column share an address); the lanes that hold the diagonal list add x_ii zt_i to row i
+// alone.  Lane (r, c) = (lane % 4,
 // lane / 4) of 4x16 tile q adds row 8I+r, column 16q+c of the last block row I, the transposed
 // entry only left of the diagonal block (which the 4x16 tiles hold in full).  The pair and
 // diagonal tiles have a loop of their own after the off-diagonal stream, so that the stream keeps
